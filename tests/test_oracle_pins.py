@@ -1,0 +1,496 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself:
+exactness of quadrature, closed-form energies, null spaces, symmetry and
+definiteness of SIPG (Sec. 4.1 calls both forms symmetric interior penalty),
+reproduction of discrete solutions (Galerkin consistency), the patch test on
+curved cells, the relation between the viscous and the Poisson form for
+constant viscosity, the optimal order k+1 (Sec. 6.1), a brute-force
+recomputation of matrix entries, and published values of the random
+generator.  All CPU only.
+"""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+import sympy as sy
+
+import workloads as W
+from oracle import solvers
+from oracle.basis import gauss_points, lagrange_values, lagrange_derivatives
+from oracle.forms import (Problem, apply, assemble, diagonal, interpolate, l2_error,
+                          load_vector, cell_sizes)
+from oracle.laws import viscosity, shear_rate_of_modes
+from oracle.mesh import Mesh
+
+pytestmark = pytest.mark.filterwarnings("ignore::scipy.sparse.SparseEfficiencyWarning")
+
+
+def jittered_vertices(n, amp, seed=7):
+    """Unit-cube vertices with interior vertices moved randomly by up to amp*h."""
+    t = np.linspace(0, 1, n + 1)
+    Z, Y, X = np.meshgrid(t, t, t, indexing="ij")
+    V = np.stack([X, Y, Z], -1)
+    rng = np.random.default_rng(seed)
+    d = rng.uniform(-amp / n, amp / n, size=V.shape)
+    inner = np.zeros(V.shape[:3], bool)
+    inner[1:-1, 1:-1, 1:-1] = True
+    V[inner] += d[inner]
+    return V.reshape(-1, 3)
+
+
+# ---------------------------------------------------------------- basis ---
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6])
+def test_gauss_rule_exact_to_degree_2n_minus_1(n):
+    x, w = gauss_points(n)
+    for m in range(2 * n):
+        assert abs(w @ x ** m - 1.0 / (m + 1)) < 1e-14
+    assert abs(w @ x ** (2 * n) - 1.0 / (2 * n + 1)) > 1e-8
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 6])
+def test_lagrange_cardinal_and_derivative_vs_polyfit(n):
+    x, _ = gauss_points(n)
+    assert np.allclose(lagrange_values(x, x), np.eye(n), atol=1e-14)
+    t = np.linspace(-0.3, 1.2, 17)
+    D = lagrange_derivatives(x, t)
+    V = lagrange_values(x, t)
+    for j in range(n):
+        e = np.zeros(n); e[j] = 1.0
+        c = np.polyfit(x, e, n - 1)
+        assert np.allclose(V[:, j], np.polyval(c, t), atol=1e-10)
+        assert np.allclose(D[:, j], np.polyval(np.polyder(c), t), atol=1e-9)
+
+
+# ------------------------------------------------- structural properties ---
+
+def _problems():
+    return [
+        Problem(Mesh(3, 3, 3, W.box_vertices(3, 3, 3, 0.1)), 2, "viscous", 10.0, 1.0, W.logfield_law(2, 1e3)),
+        Problem(Mesh(3, 3, 2, None, ("D", "N", "D", "D", "N", "D")),
+                3, "viscous", 0.0, 1.0, W.sine_law()),
+        Problem(Mesh(3, 3, 3, jittered_vertices(3, 0.25)), 2, "viscous", 1.0, 1.0, W.carreau_law(3)),
+        Problem(Mesh(3, 3, 3, jittered_vertices(3, 0.25)), 3, "poisson", 0.0, 1.0),
+        Problem(Mesh(2, 3, 2, None, ("N",) * 6), 4, "poisson", 0.0, 1.0),
+    ]
+
+
+@pytest.mark.parametrize("i", range(5))
+def test_symmetric(i):
+    pb = _problems()[i]
+    A = assemble(pb)
+    assert abs(A - A.T).max() <= 1e-14 * abs(A).max()
+    rng = np.random.default_rng(i)
+    u, v = rng.standard_normal(pb.ndof), rng.standard_normal(pb.ndof)
+    assert abs(v @ apply(pb, u) - u @ apply(pb, v)) <= 1e-12 * np.linalg.norm(u) * np.linalg.norm(v) * abs(A).max()
+
+
+@pytest.mark.parametrize("op,deg,alpha", [("viscous", 2, 0.0), ("viscous", 3, 5.0), ("poisson", 2, 0.0), ("poisson", 3, 0.0)])
+def test_dirichlet_operator_is_positive_definite(op, deg, alpha):
+    pb = Problem(Mesh(2, 2, 2, jittered_vertices(2, 0.0)), deg, op, alpha, 1.0, W.logfield_law(4, 1e2))
+    ev = np.linalg.eigvalsh(assemble(pb).toarray())
+    assert ev[0] > 1e-8 * ev[-1]
+
+
+def test_neumann_poisson_annihilates_constants_on_curved_mesh():
+    pb = Problem(Mesh(3, 3, 3, jittered_vertices(3, 0.25), ("N",) * 6), 3, "poisson", 0.0, 1.0)
+    A = assemble(pb)
+    assert np.abs(A @ np.ones(pb.ndof)).max() <= 1e-13 * abs(A).max()
+    assert np.abs(apply(pb, np.ones(pb.ndof))).max() <= 1e-13 * abs(A).max()
+
+
+def test_neumann_viscous_annihilates_rigid_motions_on_curved_mesh():
+    """eps(u) = 0 and [u] = 0 for translations and rotations w x x, which lie in
+    the mapped Q_k space because physical linear functions are trilinear in xi."""
+    pb = Problem(Mesh(3, 3, 3, jittered_vertices(3, 0.25), ("N",) * 6), 2, "viscous", 0.0, 1.0,
+                 W.logfield_law(1, 1e3))
+    A = assemble(pb)
+    scale = abs(A).max()
+    modes = [lambda x, c=c: np.eye(3)[c][None, :].repeat(len(x), 0) for c in range(3)]
+    for w in np.eye(3):
+        modes.append(lambda x, w=w: np.cross(w[None, :], x))
+    for m in modes:
+        r = interpolate(pb, m)
+        assert np.abs(A @ r).max() <= 1e-12 * scale * np.abs(r).max()
+    # a stretching mode is not in the null space: a(u,u) = int 2 mu eps:eps = 2 mu |Omega| for u = (x,0,0)
+    pbc = Problem(pb.mesh, 2, "viscous", 0.0, 1.0, W.const_law(0.7))
+    u = interpolate(pbc, lambda x: np.stack([x[:, 0], 0 * x[:, 0], 0 * x[:, 0]], 1))
+    assert abs(u @ apply(pbc, u) - 2 * 0.7) < 1e-12
+
+
+def test_poisson_energy_of_linear_function_is_exact():
+    pb = Problem(Mesh(3, 3, 3, jittered_vertices(3, 0.25), ("N",) * 6), 2, "poisson", 0.0, 1.0)
+    p = interpolate(pb, lambda x: 2.0 * x[:, 1] - x[:, 2])
+    assert abs(p @ apply(pb, p) - 5.0) < 1e-12    # int |(0, 2, -1)|^2 over the unit cube
+
+
+def test_zero_viscosity_leaves_diagonal_mass_of_domain_volume():
+    """mu = 0 => tau = 0 and A = alpha M; collocation at Gauss points makes M
+    diagonal, and the entries of one component sum to alpha |Omega| = alpha."""
+    pb = Problem(Mesh(3, 3, 3, jittered_vertices(3, 0.25)), 3, "viscous", 4.0, 1.0, W.const_law(0.0))
+    A = assemble(pb).toarray()
+    off = A - np.diag(np.diag(A))
+    assert np.abs(off).max() <= 1e-14 * np.abs(A).max()
+    d = np.diag(A).reshape(pb.mesh.ncells, 3, -1)
+    for c in range(3):
+        assert abs(d[:, c].sum() - 4.0) < 1e-12
+
+
+@pytest.mark.parametrize("deg", [2, 3])
+def test_penalty_energy_of_cell_indicator(deg):
+    """Piecewise constant on the corner cell of an affine 3^3 mesh: only the
+    penalty survives.  Poisson: 3 interior faces (tau) + 3 Dirichlet faces (2 tau),
+    tau = (k+1)^2 / h, area h^2.  Viscous component c: tau (1 + n_c^2) inside,
+    2 tau (1 + n_c^2) on the boundary, tau = (k+1)^2 mu / h."""
+    N, h = 3, 1.0 / 3
+    pbp = Problem(Mesh(N, N, N), deg, "poisson", 0.0, 1.0)
+    u = np.zeros(pbp.ndof); u[: (deg + 1) ** 3] = 1.0
+    assert abs(u @ apply(pbp, u) - 9 * (deg + 1) ** 2 * h) < 1e-12
+    mu = 0.3
+    pbv = Problem(Mesh(N, N, N), deg, "viscous", 0.0, 1.0, W.const_law(mu))
+    n3 = (deg + 1) ** 3
+    for c in range(3):
+        u = np.zeros(pbv.ndof); u[c * n3:(c + 1) * n3] = 1.0
+        assert abs(u @ apply(pbv, u) - 12 * (deg + 1) ** 2 * mu * h) < 1e-12
+
+
+def test_constant_viscosity_reduces_to_laplacian():
+    """Affine mesh, x/y sides Dirichlet, z sides Neumann, constant mu: for
+    u = f e_3 and v = g e_3 with f, g independent of z,
+    a(v, u) = mu a_p(g, f) + alpha (g, f)  (2 eps(f e3):eps(g e3) = grad f.grad g)."""
+    N, deg, mu, alpha = 3, 2, 0.6, 3.0
+    bc = ("D", "D", "D", "D", "N", "N")
+    n = deg + 1
+    pbv = Problem(Mesh(N, N, N, None, bc), deg, "viscous", alpha, 1.0, W.const_law(mu))
+    pbp = Problem(Mesh(N, N, N, None, bc), deg, "poisson", alpha / mu, 1.0)
+    rng = np.random.default_rng(3)
+
+    def zindep():
+        base = rng.standard_normal((N, N, n, n))          # (ey, ex, i2, i1)
+        F = np.zeros((N, N, N, n, n, n))                  # (ez, ey, ex, i3, i2, i1)
+        F[:] = base[None, :, :, None, :, :]
+        return F.reshape(N ** 3, n ** 3)
+
+    f, g = zindep(), zindep()
+    uf = np.zeros((N ** 3, 3, n ** 3)); uf[:, 2] = f
+    ug = np.zeros((N ** 3, 3, n ** 3)); ug[:, 2] = g
+    lhs = ug.ravel() @ apply(pbv, uf.ravel())
+    rhs = mu * (g.ravel() @ apply(pbp, f.ravel()))
+    assert abs(lhs - rhs) <= 1e-12 * abs(rhs)
+
+
+# --------------------------------------------------- consistency pins ---
+
+X = sy.symbols("x y z")
+
+
+def _visc_rhs(u, mu, alpha):
+    """f = alpha u - div(2 mu eps(u)) symbolically."""
+    G = sy.Matrix(3, 3, lambda i, j: sy.diff(u[i], X[j]))
+    S = mu * (G + G.T)
+    return [sy.simplify(alpha * u[i] - sum(sy.diff(S[i, j], X[j]) for j in range(3))) for i in range(3)]
+
+
+def _vec_fn(exprs):
+    fs = [sy.lambdify(X, e, "numpy") for e in exprs]
+    return lambda P: np.stack([np.broadcast_to(f(P[:, 0], P[:, 1], P[:, 2]), (len(P),)) for f in fs], 1)
+
+
+def _scal_fn(expr):
+    f = sy.lambdify(X, expr, "numpy")
+    return lambda P: np.broadcast_to(f(P[:, 0], P[:, 1], P[:, 2]), (len(P),)).copy()
+
+
+@pytest.mark.parametrize("mu_expr", ["const", "multilinear"])
+@pytest.mark.parametrize("deg", [2, 3])
+def test_viscous_reproduces_polynomial_solution(mu_expr, deg):
+    """u* in [Q_2]^3 vanishing on the boundary; with mu constant or multilinear
+    every integrand is of degree <= 2k+1 per direction, so the discrete
+    solution equals the interpolant of u* (Galerkin consistency)."""
+    x, y, z = X
+    b0 = x * (1 - x) * y * (1 - y) * z * (1 - z)
+    u = [b0, 2 * b0, 3 * b0]
+    mu = sy.Float(0.8) if mu_expr == "const" else 1 + x / 2 + y / 3 + z / 4 + x * y * z / 5
+    alpha = 2.0
+    f = _visc_rhs(u, mu, alpha)
+    pb = Problem(Mesh(3, 2, 2), deg, "viscous", alpha, 1.0, _scal_fn(mu + 0 * x))
+    A = assemble(pb)
+    b = load_vector(pb, _vec_fn(f))
+    sol = spla.spsolve(A.tocsc(), b)
+    ref = interpolate(pb, _vec_fn(u))
+    assert np.abs(sol - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("deg", [2, 3])
+def test_poisson_reproduces_polynomial_solution(deg):
+    x, y, z = X
+    p = x * (1 - x) * y * (1 - y) * z * (1 - z)
+    f = -(sy.diff(p, x, 2) + sy.diff(p, y, 2) + sy.diff(p, z, 2))
+    pb = Problem(Mesh(2, 3, 2), deg, "poisson", 0.0, 1.0)
+    sol = spla.spsolve(assemble(pb).tocsc(), load_vector(pb, _scal_fn(f)))
+    ref = interpolate(pb, _scal_fn(p))
+    assert np.abs(sol - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
+def test_neumann_poisson_reproduces_polynomial_solution():
+    """p* = q(x)q(y)q(z), q = 3t^2 - 2t^3 has zero normal derivative on the
+    box; with alpha = 1 the Neumann problem is regular."""
+    x, y, z = X
+    q = lambda t: 3 * t ** 2 - 2 * t ** 3
+    p = q(x) * q(y) * q(z)
+    f = p - (sy.diff(p, x, 2) + sy.diff(p, y, 2) + sy.diff(p, z, 2))
+    pb = Problem(Mesh(2, 2, 3, None, ("N",) * 6), 3, "poisson", 1.0, 1.0)
+    sol = spla.spsolve(assemble(pb).tocsc(), load_vector(pb, _scal_fn(f)))
+    ref = interpolate(pb, _scal_fn(p))
+    assert np.abs(sol - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("deg", [2, 3])
+def test_viscous_patch_test_on_curved_cells(deg):
+    """Linear u* with inhomogeneous Dirichlet data on four sides and the exact
+    traction 2 mu eps(u*) n on two; on trilinear cells every integrand stays of
+    degree <= k+2 per direction, so the solution reproduces u* exactly."""
+    Amat = np.array([[0.3, -0.2, 0.5], [0.1, 0.4, -0.3], [-0.6, 0.2, 0.1]])
+    c0 = np.array([0.2, -0.1, 0.4])
+    ustar = lambda P: P @ Amat.T + c0
+    mu, alpha = 1.7, 3.0
+    eps = 0.5 * (Amat + Amat.T)
+    bc = ("D", "D", "N", "D", "D", "N")
+    pb = Problem(Mesh(3, 3, 3, jittered_vertices(3, 0.25), bc), deg, "viscous", alpha, 1.0, W.const_law(mu))
+
+    def traction(P, nrm):
+        return 2 * mu * nrm @ eps.T
+
+    b = load_vector(pb, lambda P: alpha * ustar(P), g=ustar, hN=traction)
+    sol = spla.spsolve(assemble(pb).tocsc(), b)
+    ref = interpolate(pb, ustar)
+    assert np.abs(sol - ref).max() <= 1e-10
+
+
+def test_poisson_patch_test_on_curved_cells():
+    gvec = np.array([0.4, -1.1, 0.7])
+    pstar = lambda P: P @ gvec + 0.3
+    bc = ("D", "N", "D", "D", "N", "D")
+    pb = Problem(Mesh(3, 3, 3, jittered_vertices(3, 0.25), bc), 2, "poisson", 0.0, 1.0)
+    b = load_vector(pb, lambda P: 0.0 * P[:, 0], g=pstar, hN=lambda P, nrm: nrm @ gvec)
+    sol = spla.spsolve(assemble(pb).tocsc(), b)
+    assert np.abs(sol - interpolate(pb, pstar)).max() <= 1e-10
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("deg,Ns,curved", [(2, (2, 3, 4), False), (3, (2, 3), False), (2, (3, 4), True)])
+def test_viscous_converges_at_order_k_plus_1(deg, Ns, curved):
+    """Sec. 6.1 reports optimal k+1 L2 convergence; here for the viscous
+    operator alone with the smooth viscosity 1 + 0.5 sin sin sin."""
+    x, y, z = X
+    s = sy.sin
+    pi = sy.pi
+    u = [s(pi * x) * s(pi * y) * s(pi * z), s(2 * pi * x) * s(pi * y) * s(pi * z),
+         s(pi * x) * s(2 * pi * y) * s(pi * z)]
+    mu = 1 + sy.Rational(1, 2) * s(2 * pi * x) * s(2 * pi * y) * s(2 * pi * z)
+    alpha = 10.0
+    f = _visc_rhs(u, mu, alpha)
+    errs = []
+    for N in Ns:
+        V = W.box_vertices(N, N, N, 0.1) if curved else None
+        pb = Problem(Mesh(N, N, N, V), deg, "viscous", alpha, 1.0, W.sine_law(1.0, 0.5))
+        sol = spla.spsolve(assemble(pb).tocsc(), load_vector(pb, _vec_fn(f)))
+        e, r = l2_error(pb, sol, _vec_fn(u))
+        errs.append(e / r)
+    rates = [np.log(errs[i] / errs[i + 1]) / np.log(Ns[i + 1] / Ns[i]) for i in range(len(Ns) - 1)]
+    assert abs(rates[-1] - (deg + 1)) < 0.6, rates
+
+
+def test_bruteforce_entries_affine_two_cells():
+    """Recompute entries of the Poisson and viscous matrices on two affine cells
+    with an independent construction: 1D basis from numpy's polynomial fit
+    through the Legendre roots, physical coordinates directly (J = h I), a
+    (k+3)-point rule (integrands are polynomials, both rules are exact), and
+    faces enumerated by hand."""
+    deg, hx = 2, 0.5
+    n = deg + 1
+    mu = 1.3
+    roots = (np.polynomial.legendre.legroots([0] * n + [1]) + 1) / 2
+    polys = [np.polynomial.Polynomial.fit(roots, np.eye(n)[j], n - 1).convert() for j in range(n)]
+    dpolys = [p.deriv() for p in polys]
+    gq, gw = np.polynomial.legendre.leggauss(n + 3)
+    gq, gw = (gq + 1) / 2, gw / 2
+    # two cells [0,.5]x[0,1]^2 and [.5,1]x[0,1]^2 (nx=2, ny=nz=1), all Dirichlet
+    cells = [(0.0, 0.0, 0.0), (0.5, 0.0, 0.0)]
+    size = np.array([0.5, 1.0, 1.0])
+
+    def phi(cell, i, P):      # value and physical gradient of node i=(i1,i2,i3) of cell at points P
+        xi = (P - np.array(cells[cell])) / size
+        inside = np.all((xi >= -1e-12) & (xi <= 1 + 1e-12), axis=1)
+        v = [polys[i[d]](xi[:, d]) for d in range(3)]
+        dv = [dpolys[i[d]](xi[:, d]) / size[d] for d in range(3)]
+        val = v[0] * v[1] * v[2] * inside
+        grad = np.stack([dv[0] * v[1] * v[2], v[0] * dv[1] * v[2], v[0] * v[1] * dv[2]], 1) * inside[:, None]
+        return val, grad
+
+    def vol_pts(cell):
+        T = np.array(np.meshgrid(gq, gq, gq, indexing="ij")).reshape(3, -1).T
+        Wt = np.prod(np.array(np.meshgrid(gw, gw, gw, indexing="ij")).reshape(3, -1).T, 1)
+        return np.array(cells[cell]) + T * size, Wt * np.prod(size)
+
+    def face_pts(x0, d, lo, hi):   # plane x_d = x0 over the rectangle lo..hi in the other two dims
+        t = [k for k in range(3) if k != d]
+        A, B = np.meshgrid(gq, gq, indexing="ij")
+        P = np.zeros((A.size, 3)); P[:, d] = x0
+        P[:, t[0]] = lo[0] + A.ravel() * (hi[0] - lo[0]); P[:, t[1]] = lo[1] + B.ravel() * (hi[1] - lo[1])
+        Wt = np.outer(gw, gw).ravel() * (hi[0] - lo[0]) * (hi[1] - lo[1])
+        return P, Wt
+
+    def side(P, cell, d, s):       # trace from inside `cell`, nudged towards its interior
+        Q = P.copy(); Q[:, d] += (-1e-13 if s == 1 else 1e-13)
+        return Q
+
+    h_e = (0.5 * 1 * 1) ** (1 / 3)
+    tau_p = (deg + 1) ** 2 / h_e
+    # face list: (plane coordinate, direction, normal sign for the owning cell, owner, neighbour or None)
+    faces = [(0.0, 0, -1, 0, None), (0.5, 0, +1, 0, 1), (1.0, 0, +1, 1, None)]
+    for cell in (0, 1):
+        for d in (1, 2):
+            for s in (0, 1):
+                faces.append((float(s), d, 2 * s - 1, cell, None))
+
+    def poisson_entry(I, J):
+        ci, ni = I; cj, nj = J
+        val = 0.0
+        for cell in (0, 1):
+            P, Wt = vol_pts(cell)
+            vi, gi = phi(ci, ni, P); vj, gj = phi(cj, nj, P)
+            val += Wt @ np.einsum("pi,pi->p", gi, gj)
+        for x0, d, sgn, own, nb in faces:
+            o = np.array(cells[own])
+            lo = [o[k] for k in range(3) if k != d]; hi = [o[k] + size[k] for k in range(3) if k != d]
+            P, Wt = face_pts(x0, d, lo, hi)
+            nrm = np.zeros(3); nrm[d] = sgn
+            sm = 1 if sgn > 0 else 0
+            qm, gqm = phi(ci, ni, side(P, own, d, sm)) if ci == own else (0 * Wt, 0 * P)
+            pm, gpm = phi(cj, nj, side(P, own, d, sm)) if cj == own else (0 * Wt, 0 * P)
+            if nb is None:
+                val += Wt @ (-(gqm @ nrm) * pm - (gpm @ nrm) * qm + 2 * tau_p * qm * pm)
+            else:
+                qp, gqp = phi(ci, ni, side(P, nb, d, 1 - sm)) if ci == nb else (0 * Wt, 0 * P)
+                pp, gpp = phi(cj, nj, side(P, nb, d, 1 - sm)) if cj == nb else (0 * Wt, 0 * P)
+                jq, jp = qm - qp, pm - pp
+                val += Wt @ (-0.5 * ((gqm + gqp) @ nrm) * jp - 0.5 * ((gpm + gpp) @ nrm) * jq + tau_p * jq * jp)
+        return val
+
+    pb = Problem(Mesh(2, 1, 1), deg, "poisson", 0.0, 1.0)
+    A = assemble(pb).toarray()
+    rng = np.random.default_rng(0)
+    idx = lambda cell, i: cell * n ** 3 + i[2] * n * n + i[1] * n + i[0]
+    for _ in range(25):
+        I = (int(rng.integers(2)), tuple(int(v) for v in rng.integers(0, n, 3)))
+        J = (int(rng.integers(2)), tuple(int(v) for v in rng.integers(0, n, 3)))
+        ref = poisson_entry(I, J)
+        # the 1e-13 nudge that picks a side of a face costs ~1e-12 in the traces
+        assert abs(A[idx(*I), idx(*J)] - ref) <= 1e-10 * np.abs(A).max(), (I, J)
+
+
+def test_oracle_modes_agree():
+    """The assembled matrix (O2) and the direct quadrature apply (O3)."""
+    for pb in _problems():
+        A = assemble(pb)
+        x = np.random.default_rng(1).uniform(-1, 1, pb.ndof)
+        y2, y3 = A @ x, apply(pb, x)
+        assert np.abs(y2 - y3).max() <= 1e-13 * np.abs(y2).max()
+        for parts in (("cell",), ("interior",), ("boundary",)):
+            Ap = assemble(pb, parts)
+            assert np.abs(Ap @ x - apply(pb, x, parts)).max() <= 1e-13 * np.abs(y2).max()
+        assert np.abs(diagonal(pb) - A.diagonal()).max() <= 1e-13 * np.abs(A.diagonal()).max()
+
+
+# --------------------------------------------------------------- laws ---
+
+def test_sine_law_values():
+    law = W.sine_law(2.0, 0.5)
+    P = np.array([[0.25, 0.25, 0.25], [0.75, 0.25, 0.25], [0.5, 0.3, 0.9]])
+    assert np.allclose(viscosity(law, P), [3.0, 1.0, 2.0], atol=1e-14)
+
+
+def test_logfield_range_and_contrast():
+    law = W.logfield_law(2, 1e3)
+    P = np.random.default_rng(0).uniform(0, 1, (20000, 3))
+    mu = viscosity(law, P)
+    assert mu.min() >= 1.0 - 1e-14 and mu.max() <= 1e3 * (1 + 1e-14)
+    assert mu.max() / mu.min() > 1e2
+
+
+def test_generalized_newtonian_special_cases():
+    base = W.carreau_law(3)
+    P = np.random.default_rng(1).uniform(0, 1, (50, 3))
+    gd = shear_rate_of_modes(base, P)
+    newt = dict(base, mu0=0.7, mu_inf=0.7)
+    assert np.allclose(viscosity(newt, P), 0.7)
+    power = dict(base, kappa=0.0, mu_inf=0.0, a_exp=2.0, n_exp=0.4, lam=2.0, mu0=1.5)
+    assert np.allclose(viscosity(power, P), 1.5 * (2.0 * gd) ** (0.4 - 1.0), rtol=1e-12)
+    car = viscosity(base, P)   # Carreau: mu_inf + (mu0 - mu_inf)(1 + (lam g)^2)^((n-1)/2)
+    assert np.allclose(car, 1e-4 + (1 - 1e-4) * (1 + gd ** 2) ** (-0.25), rtol=1e-12)
+
+
+def test_shear_rate_matches_finite_differences_and_field_is_solenoidal():
+    law = W.carreau_law(3)
+    k, v, phi = law["k"].astype(float), law["v"], law["phi"]
+    w = lambda P: np.cos(2 * np.pi * P @ k.T + phi) @ v
+    P = np.random.default_rng(2).uniform(0, 1, (30, 3))
+    hh = 1e-6
+    G = np.stack([(w(P + hh * e) - w(P - hh * e)) / (2 * hh) for e in np.eye(3)], 2)  # G[p,i,j]=dw_i/dx_j
+    eps = 0.5 * (G + G.transpose(0, 2, 1))
+    gd = np.sqrt(2 * np.einsum("pij,pij->p", eps, eps))
+    assert np.allclose(shear_rate_of_modes(law, P), gd, rtol=1e-6)
+    assert np.abs(np.trace(G, axis1=1, axis2=2)).max() < 1e-6 * np.abs(G).max()
+
+
+# ------------------------------------------------------------ solvers ---
+
+def test_splitmix64_published_outputs():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "splitmix64_seed0.txt")
+    ref = [int(l, 16) for l in open(path) if l.strip() and not l.startswith("#")]
+    u = solvers.splitmix64_uniform(0, 3)
+    bits = ((u + 1.0) / 2.0 * 2.0 ** 53).astype(np.uint64)
+    assert [int(b) for b in bits] == [r >> 11 for r in ref]
+
+
+def test_chebyshev_matches_closed_form_polynomial():
+    """For diagonal A and D = I, the error after the Chebyshev iteration from
+    0 is the scaled Chebyshev polynomial T_d((theta - l)/delta) / T_d(theta/delta)."""
+    lam = np.linspace(0.05, 2.0, 40)
+    A = lambda v: lam * v
+    r = np.ones_like(lam)
+    lo, hi, deg = 0.1, 2.1, 5
+    z = solvers.chebyshev_jacobi(A, np.ones_like(lam), r, deg, hi, lo)
+    theta, delta = (hi + lo) / 2, (hi - lo) / 2
+    T = np.polynomial.chebyshev.Chebyshev.basis(deg)
+    resid = 1 - lam * z                       # error polynomial at each eigenvalue
+    assert np.allclose(resid, T((theta - lam) / delta) / T(theta / delta), atol=1e-13)
+
+
+def test_lanczos_recovers_largest_eigenvalue():
+    rng = np.random.default_rng(0)
+    Q, _ = np.linalg.qr(rng.standard_normal((12, 12)))
+    M = Q @ np.diag(np.linspace(1, 9, 12)) @ Q.T
+    d = np.diag(M)
+    est = solvers.lanczos_max(lambda v: M @ v, 1 / d, steps=12)
+    S = M / np.sqrt(np.outer(d, d))
+    assert abs(est - np.linalg.eigvalsh(S)[-1]) < 1e-9
+
+
+def test_flexible_cg_solves_and_reports():
+    pb = Problem(Mesh(3, 3, 3, jittered_vertices(3, 0.2)), 2, "viscous", 10.0, 1.0, W.sine_law())
+    A = assemble(pb).tocsc()
+    b = W.uniform_vector(1, pb.ndof)
+    x, info = solvers.solve(lambda v: A @ v, A.diagonal(), b, tol=1e-10)
+    assert info["status"] == "ok" and info["rel_residual"] <= 1e-10
+    assert np.abs(x - spla.spsolve(A, b)).max() <= 1e-7 * np.abs(x).max()
+
+
+def test_neumann_poisson_solve_is_mean_zero():
+    pb = Problem(Mesh(3, 3, 3, None, ("N",) * 6), 3, "poisson", 0.0, 1.0)
+    A = assemble(pb).tocsr()
+    b = W.uniform_vector(4, pb.ndof)
+    x, info = solvers.solve(lambda v: A @ v, A.diagonal(), b, tol=1e-8, mean_zero=True)
+    assert info["status"] == "ok" and abs(x.mean()) < 1e-14
+    bz = b - b.mean()
+    assert np.linalg.norm(bz - A @ x) <= 1e-8 * np.linalg.norm(bz)

@@ -1,0 +1,210 @@
+"""Seeded synthetic inputs shared by the oracle, the tests and the bench.
+
+This module only *draws* inputs: mesh vertices, the random modes that define a
+viscosity field or a background velocity, right-hand sides and request
+streams.  It holds none of the discretisation's arithmetic (no basis, no
+quadrature, no geometry factors, no viscosity-law evaluation at quadrature
+points); both the oracle and the HIP library evaluate the fields defined here
+on their own.
+
+The workloads stand in for the paper's cavity and backward-facing-step runs
+(Sec. 6.2 and 6.3): hexahedral meshes of a cube, polynomial degrees 2-5,
+viscosity contrasts 1 to 1e4 and about 1e6-1e7 unknowns.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = [
+    "box_vertices",
+    "logfield_law",
+    "carreau_law",
+    "sine_law",
+    "const_law",
+    "uniform_vector",
+    "CONFIGS",
+    "config",
+    "serving_requests",
+]
+
+# Side order used for boundary conditions everywhere: -x, +x, -y, +y, -z, +z.
+ALL_DIRICHLET = ("D",) * 6
+ALL_NEUMANN = ("N",) * 6
+
+
+def box_vertices(nx: int, ny: int, nz: int, perturb: float = 0.0) -> np.ndarray | None:
+    """Vertices of a structured nx*ny*nz hex mesh of the unit cube.
+
+    Returns an array of shape ((nz+1)*(ny+1)*(nx+1), 3), vertex
+    (ix, iy, iz) at row (iz*(ny+1) + iy)*(nx+1) + ix.  With perturb != 0 every
+    coordinate of every vertex is moved by perturb*h*sin(2 pi x)sin(2 pi y)
+    sin(2 pi z) of the unperturbed position, h = 1/max(nx, ny, nz); boundary
+    vertices stay on the boundary because the product vanishes there.
+    Returns None for the unperturbed (affine) box, which the library and the
+    oracle both accept as "unit box with straight cells".
+    """
+    if perturb == 0.0:
+        return None
+    x = np.linspace(0.0, 1.0, nx + 1)
+    y = np.linspace(0.0, 1.0, ny + 1)
+    z = np.linspace(0.0, 1.0, nz + 1)
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    h = 1.0 / max(nx, ny, nz)
+    s = np.sin(2 * np.pi * X) * np.sin(2 * np.pi * Y) * np.sin(2 * np.pi * Z)
+    # the product vanishes on the boundary; make that exact (sin(2 pi) != 0 in fp64)
+    on_bdry = np.zeros_like(s, dtype=bool)
+    on_bdry[0], on_bdry[-1] = True, True
+    on_bdry[:, 0], on_bdry[:, -1] = True, True
+    on_bdry[:, :, 0], on_bdry[:, :, -1] = True, True
+    d = np.where(on_bdry, 0.0, perturb * h * s)
+    V = np.stack([X + d, Y + d, Z + d], axis=-1)
+    return np.ascontiguousarray(V.reshape(-1, 3))
+
+
+def _wave_vectors(rng: np.random.Generator, n_modes: int, kmax: int) -> np.ndarray:
+    """n_modes integer wave vectors drawn uniformly from {-kmax..kmax}^3 minus 0."""
+    out = []
+    while len(out) < n_modes:
+        k = rng.integers(-kmax, kmax + 1, size=3)
+        if np.any(k != 0):
+            out.append(k)
+    return np.array(out, dtype=np.int64)
+
+
+def const_law(mu: float = 1.0) -> dict:
+    return {"kind": "const", "mu": float(mu)}
+
+
+def sine_law(mu: float = 1.0, amp: float = 0.5) -> dict:
+    """mu(x) = mu * (1 + amp sin(2 pi x) sin(2 pi y) sin(2 pi z))."""
+    return {"kind": "sine", "mu": float(mu), "amp": float(amp)}
+
+
+def logfield_law(seed: int, contrast: float, n_modes: int = 8, kmax: int = 2) -> dict:
+    """Smooth random log-viscosity field mu(x) = contrast ** s(x).
+
+    s(x) = clip((r(x) - rmin) / (rmax - rmin), 0, 1) with
+    r(x) = sum_m a_m cos(2 pi k_m . x + phi_m); the modes are drawn here and
+    rmin / rmax are the extremes of r over a fixed 65^3 lattice of the unit
+    cube, so the field does not depend on the mesh it is sampled on.
+    """
+    rng = np.random.default_rng(seed)
+    k = _wave_vectors(rng, n_modes, kmax)
+    a = rng.uniform(0.0, 1.0, size=n_modes)
+    phi = rng.uniform(0.0, 2 * np.pi, size=n_modes)
+    t = np.linspace(0.0, 1.0, 65)
+    Z, Y, X = np.meshgrid(t, t, t, indexing="ij")
+    P = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+    r = np.cos(2 * np.pi * (P @ k.T.astype(np.float64)) + phi) @ a
+    return {
+        "kind": "logfield",
+        "contrast": float(contrast),
+        "k": k,
+        "a": a,
+        "phi": phi,
+        "rmin": float(r.min()),
+        "rmax": float(r.max()),
+    }
+
+
+def carreau_law(seed: int, mu0: float = 1.0, mu_inf: float = 1e-4, lam: float = 1.0,
+                n_exp: float = 0.5, kappa: float = 1.0, a_exp: float = 2.0,
+                n_modes: int = 8, kmax: int = 2) -> dict:
+    """Generalised-Newtonian viscosity of a prescribed background velocity.
+
+    mu = mu_inf + (mu0 - mu_inf) [kappa + (lam * gdot)^a]^((b-1)/a), b = n_exp,
+    with gdot the shear rate of w(x) = sum_m v_m cos(2 pi k_m . x + phi_m),
+    v_m = c_m x k_m, c_m ~ N(0, I): each mode is orthogonal to its wave vector,
+    so w is divergence-free.  The cross product only builds the input field.
+    """
+    rng = np.random.default_rng(seed)
+    k = _wave_vectors(rng, n_modes, kmax)
+    c = rng.normal(0.0, 1.0, size=(n_modes, 3))
+    phi = rng.uniform(0.0, 2 * np.pi, size=n_modes)
+    v = np.cross(c, k.astype(np.float64))
+    return {
+        "kind": "carreau",
+        "mu0": float(mu0), "mu_inf": float(mu_inf), "lam": float(lam),
+        "n_exp": float(n_exp), "kappa": float(kappa), "a_exp": float(a_exp),
+        "k": k, "v": v, "phi": phi,
+    }
+
+
+def uniform_vector(seed: int, n: int) -> np.ndarray:
+    """n values ~ U(-1, 1) from numpy's default generator."""
+    return np.random.default_rng(seed).uniform(-1.0, 1.0, size=n)
+
+
+def _cfg(name, n, degree, op, law, alpha, bc, perturb, **extra):
+    d = {
+        "name": name, "nx": n, "ny": n, "nz": n, "degree": degree, "op": op,
+        "law": law, "alpha": float(alpha), "penalty": 1.0, "bc": tuple(bc),
+        "perturb": float(perturb),
+    }
+    d.update(extra)
+    return d
+
+
+def config(name: str, n: int | None = None) -> dict:
+    """The five workloads, optionally on a smaller n^3 mesh of the same kind.
+
+    c1  4^3 affine, k=2, viscous, sine viscosity, alpha/dt = 10, Dirichlet.
+    c2  32^3 perturbed (0.1 h), k=3, viscous, mu = 10^(3 s(x)), seed 2.
+    c3  24^3 perturbed, k=4, viscous, Carreau of a seeded velocity, seed 3.
+    c4p 20^3 affine, k=5, Poisson, all Neumann (singular, mean-zero data).
+    c4v 20^3 affine, k=5, viscous, sine viscosity, Dirichlet.
+    """
+    if name == "c1":
+        return _cfg("c1", n or 4, 2, "viscous", sine_law(1.0, 0.5), 10.0, ALL_DIRICHLET, 0.0,
+                    x_seed=1, tol=1e-10)
+    if name == "c2":
+        return _cfg("c2", n or 32, 3, "viscous", logfield_law(2, 1e3), 10.0, ALL_DIRICHLET, 0.1,
+                    x_seed=2)
+    if name == "c3":
+        return _cfg("c3", n or 24, 4, "viscous", carreau_law(3), 10.0, ALL_DIRICHLET, 0.1,
+                    x_seed=3, tol=1e-8)
+    if name == "c4p":
+        return _cfg("c4p", n or 20, 5, "poisson", const_law(1.0), 0.0, ALL_NEUMANN, 0.0,
+                    x_seed=4, tol=1e-8)
+    if name == "c4v":
+        return _cfg("c4v", n or 20, 5, "viscous", sine_law(1.0, 0.5), 10.0, ALL_DIRICHLET, 0.0,
+                    x_seed=4, tol=1e-8)
+    raise KeyError(name)
+
+
+CONFIGS = ("c1", "c2", "c3", "c4p", "c4v")
+
+
+def ndofs(cfg: dict) -> int:
+    n = cfg["degree"] + 1
+    comps = 3 if cfg["op"] == "viscous" else 1
+    return cfg["nx"] * cfg["ny"] * cfg["nz"] * comps * n ** 3
+
+
+def serving_requests(seed: int = 5, count: int = 256, rate: float = 20.0,
+                     nmin: int = 4, nmax: int = 24) -> list[dict]:
+    """Viscous-step solve requests with Poisson arrivals.
+
+    Edge count N ~ U{nmin..nmax}, degree ~ U{2,3,4,5}, viscosity contrast
+    ~ U{1, 1e2, 1e4} (mu = contrast^s(x), per-request field seed),
+    alpha/dt ~ U[1, 100], all-Dirichlet, affine cube, right-hand side
+    ~ U(-1, 1) with a per-request seed; arrival gaps ~ Exp(1/rate).
+    """
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for i in range(count):
+        t += rng.exponential(1.0 / rate)
+        n = int(rng.integers(nmin, nmax + 1))
+        k = int(rng.integers(2, 6))
+        contrast = float([1.0, 1e2, 1e4][rng.integers(0, 3)])
+        alpha = float(rng.uniform(1.0, 100.0))
+        fseed = int(rng.integers(0, 2**31 - 1))
+        bseed = int(rng.integers(0, 2**31 - 1))
+        law = const_law(1.0) if contrast == 1.0 else logfield_law(fseed, contrast)
+        out.append({
+            "id": i, "arrival": t,
+            "cfg": _cfg(f"req{i}", n, k, "viscous", law, alpha, ALL_DIRICHLET, 0.0,
+                        x_seed=bseed, tol=1e-8),
+        })
+    return out
