@@ -1,0 +1,216 @@
+/*
+ * sipg.h -- C ABI of the MI355X (gfx950) library for the matrix-free SIPG
+ * operators of Schussnig, Fehn, Pacheco and Kronbichler, "Higher-Order
+ * Discontinuous Galerkin Splitting Schemes for Fluids with Variable Viscosity"
+ * (arXiv 2506.14424).
+ *
+ * Operators (Sec. 4.1):
+ *   viscous  a(v,u) = (alpha v, u) + v_h^e(v, u; mu): the viscous-step operator
+ *            (gamma_0/dt) M - div(2 mu eps(u)), SIPG fluxes u = {{u}},
+ *            tau_1 = {{mu grad u}} - tau [[u]], tau_2 = tau_1^T ("Viscous Step");
+ *   poisson  the SIPG Laplacian of the pressure step ("Pressure Step"), with
+ *            the coercive penalty sign and an optional mass term alpha.
+ * Boundary conditions are homogeneous and imposed by the mirror principle
+ * (Sec. 4).  Penalty: tau = P (k+1)^2 mu(x) / h_F, h_F = min(h^-, h^+),
+ * h_e = |cell|^(1/3) (the paper defers the formula to Hillewaert 2013).
+ *
+ * Discretisation: structured nx*ny*nz hexahedral mesh of a box, cells
+ * trilinear in their vertices (straight unit box when no vertices are given),
+ * tensor-product Lagrange basis of degree k on the k+1 Gauss-Legendre points,
+ * the same points as quadrature rule (Sec. 4: Q_k spaces; Sec. 4.1: as many
+ * integration as support points).  The viscosity is evaluated once, at
+ * quadrature points (Sec. 4.1 stores it pointwise), from one of the laws below.
+ *
+ * Vector layout (all device vectors): cell-major,
+ *   index = ((e*C + c)*n + i3)*n*n + i2*n + i1,   n = k+1,
+ *   e = (ez*ny + ey)*nx + ex, C = 3 (viscous) or 1 (poisson),
+ *   node (i1, i2, i3) at reference point (g[i1], g[i2], g[i3]) of cell e.
+ *
+ * Ownership: the caller owns every device buffer (vectors and the workspace);
+ * the library never calls hipMalloc.  A plan owns host metadata and a small
+ * block of pinned host memory for solver status read-back.
+ *
+ * Errors: every call returns a sipg_status; SIPG_OK is 0, errors are
+ * negative; sipg_last_error() returns a message for the calling thread.
+ * Nothing is thrown across the ABI.
+ *
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = default
+ * stream).  apply, diagonal, solve_begin and solve_advance only enqueue work;
+ * sipg_solve blocks; sipg_solve_poll never blocks.
+ */
+#ifndef SIPG_H
+#define SIPG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SIPG_OK = 0,
+    SIPG_ERR_INVALID = -1,        /* bad argument or inconsistent plan */
+    SIPG_ERR_OOM = -2,            /* workspace smaller than sipg_plan_workspace_bytes */
+    SIPG_ERR_HIP = -3,            /* a HIP runtime call failed */
+    SIPG_ERR_NOT_CONVERGED = -4,  /* solve hit max_iter */
+    SIPG_ERR_BREAKDOWN = -5,      /* p.Ap <= 0 or non-finite value in CG */
+    SIPG_ERR_UNSUPPORTED = -6,    /* valid request this build does not handle */
+    SIPG_ERR_STATE = -7           /* call out of order (e.g. apply before bind) */
+} sipg_status;
+
+typedef enum { SIPG_F64 = 0, SIPG_F32 = 1 } sipg_precision;
+typedef enum { SIPG_VISCOUS = 0, SIPG_POISSON = 1 } sipg_operator;
+typedef enum { SIPG_BC_DIRICHLET = 0, SIPG_BC_NEUMANN = 1 } sipg_bc;
+
+/* Viscosity laws, evaluated at physical quadrature points x:
+ *  CONST     mu = mu
+ *  SINE      mu = mu (1 + amp sin(2 pi x) sin(2 pi y) sin(2 pi z))
+ *  LOGFIELD  mu = contrast^s, s = clamp((r - rmin)/(rmax - rmin), 0, 1),
+ *            r(x) = sum_m a_m cos(2 pi k_m.x + phi_m)
+ *  CARREAU   the generalised Newtonian law of Sec. 2,
+ *            mu = mu_inf + (mu0 - mu_inf)[kappa + (lam gdot)^a]^((b-1)/a),
+ *            gdot = sqrt(2 eps(w):eps(w)) of the prescribed velocity
+ *            w(x) = sum_m v_m cos(2 pi k_m.x + phi_m).
+ * The poisson operator ignores the law (mu = 1). */
+typedef enum {
+    SIPG_LAW_CONST = 0, SIPG_LAW_SINE = 1, SIPG_LAW_LOGFIELD = 2, SIPG_LAW_CARREAU = 3
+} sipg_law_kind;
+
+#define SIPG_MAX_MODES 16
+
+/* Apply-part mask (sipg_apply_parts): the three sums of the bilinear form. */
+enum { SIPG_PART_CELL = 1, SIPG_PART_INTERIOR = 2, SIPG_PART_BOUNDARY = 4, SIPG_PART_ALL = 7 };
+
+typedef struct {
+    int32_t nx, ny, nz;        /* cells per direction, each >= 1 */
+    const double* vertices;    /* host, [(nz+1)(ny+1)(nx+1)][3], vertex (ix,iy,iz) at
+                                  row (iz*(ny+1)+iy)*(nx+1)+ix; NULL = straight unit box.
+                                  Copied by sipg_plan_create. */
+    int32_t bc[6];             /* sipg_bc for the sides -x,+x,-y,+y,-z,+z */
+} sipg_mesh;
+
+typedef struct {
+    int32_t kind;              /* sipg_law_kind */
+    double mu, amp;            /* CONST, SINE */
+    double contrast, rmin, rmax;                      /* LOGFIELD */
+    double mu0, mu_inf, lam, n_exp, kappa, a_exp;     /* CARREAU: b = n_exp, a = a_exp */
+    int32_t n_modes;           /* <= SIPG_MAX_MODES */
+    const int32_t* k;          /* host [n_modes][3] integer wave vectors */
+    const double* a;           /* LOGFIELD host [n_modes] amplitudes */
+    const double* v;           /* CARREAU host [n_modes][3] velocity amplitudes */
+    const double* phi;         /* host [n_modes] phases */
+} sipg_viscosity;
+
+typedef struct {
+    int32_t op;                /* sipg_operator */
+    int32_t degree;            /* k, 1..5 */
+    double alpha;              /* gamma_0/dt in front of the mass term, >= 0 */
+    double penalty;            /* P > 0 */
+} sipg_params;
+
+typedef struct {
+    double rel_tol;            /* stop when ||b - A x|| <= rel_tol ||b|| */
+    int32_t max_iter;          /* CG iterations (operator applications of A p) */
+    int32_t precond_precision; /* sipg_precision of the Chebyshev-Jacobi preconditioner */
+    int32_t cheb_degree;       /* >= 1; degree d uses d-1 operator applications */
+    double cheb_ratio;         /* lambda_lo = lambda_hi / cheb_ratio */
+    double cheb_safety;        /* lambda_hi = cheb_safety * Lanczos estimate */
+    int32_t lanczos_steps;     /* 1..64 */
+    int32_t check_every;       /* sipg_solve: iterations between host read-backs */
+    int32_t max_restarts;      /* defect-correction restarts */
+} sipg_solve_opts;
+
+typedef struct {
+    int32_t iterations;
+    int32_t restarts;
+    double rel_residual;       /* true ||b - A x|| / ||b||, computed in FP64 */
+    double lambda_max;         /* Lanczos estimate of lambda_max(D^-1 A) */
+    int32_t status;            /* sipg_status of the solve */
+} sipg_solve_info;
+
+typedef struct sipg_plan sipg_plan;
+
+/* Version of this ABI (increments on any change of a struct or signature). */
+int32_t sipg_abi_version(void);
+
+/* Thread-local message of the last error, "" if none. */
+const char* sipg_last_error(void);
+
+/* Validates and copies mesh, law and parameters into a new host-side plan
+ * (Sec. 4: mesh, degree, viscosity; Sec. 4.1: penalty, alpha = gamma_0/dt).
+ * Rejects degree outside 1..5, non-positive cells (det J <= 0 at a corner),
+ * bad bc values, a law needing more than SIPG_MAX_MODES modes.
+ * No device work. *out is NULL on error. */
+sipg_status sipg_plan_create(const sipg_mesh* mesh, const sipg_viscosity* law,
+                             const sipg_params* params, sipg_plan** out);
+
+void sipg_plan_destroy(sipg_plan* plan);
+
+/* Number of unknowns C*(k+1)^3*nx*ny*nz. */
+int64_t sipg_dof_count(const sipg_plan* plan);
+
+/* Device bytes the plan needs: operator data (geometry, viscosity at cell and
+ * face quadrature points in FP64 and FP32, diagonal and inverse diagonal),
+ * plus solver vectors when with_solver != 0.  Used for admission control. */
+sipg_status sipg_plan_workspace_bytes(const sipg_plan* plan, int32_t with_solver, size_t* bytes);
+
+/* Carves `workspace` (device, 256-byte aligned, at least the size above for
+ * with_solver) and enqueues the setup on `stream`: geometry factors, the
+ * viscosity at quadrature points (Sec. 4.1 evaluates it pointwise) and the
+ * matrix diagonal with its inverse (Sec. 5.3 precomputes it).  The workspace
+ * must stay valid and untouched until the plan is destroyed or re-bound. */
+sipg_status sipg_plan_bind(sipg_plan* plan, void* workspace, size_t bytes, int32_t with_solver,
+                           void* stream);
+
+/* y = A x in the given precision (x, y: device, ndof elements of double or
+ * float, no aliasing).  The matrix-free action of the operator above. */
+sipg_status sipg_apply(sipg_plan* plan, int32_t precision, const void* x, void* y, void* stream);
+
+/* Same, restricted to the sums selected by `parts` (SIPG_PART_*). */
+sipg_status sipg_apply_parts(sipg_plan* plan, int32_t precision, int32_t parts,
+                             const void* x, void* y, void* stream);
+
+/* out = diag(A) (inverse == 0) or 1/diag(A) (inverse != 0), device, ndof
+ * elements of the given precision (Sec. 5.3, Jacobi-type smoothing). */
+sipg_status sipg_diagonal(sipg_plan* plan, int32_t precision, int32_t inverse, void* out,
+                          void* stream);
+
+/* Copies the viscosity the plan evaluated at quadrature points: mu_cell
+ * [ncells][n^3] (node layout of a cell) and mu_face [nfaces][n^2] in FP64
+ * (device; either may be NULL).  Faces are numbered x-faces first,
+ * ((ez*ny + ey)*(nx+1) + fx), then y-faces ((ez*(ny+1) + fy)*nx + ex), then
+ * z-faces ((fz*ny + ey)*nx + ex); face point (a, b) at index b*n + a with a
+ * along the lower tangential axis. */
+sipg_status sipg_viscosity_values(sipg_plan* plan, double* mu_cell, double* mu_face, void* stream);
+
+int64_t sipg_face_count(const sipg_plan* plan);
+
+void sipg_solve_opts_default(sipg_solve_opts* opts);
+
+/* Solves A x = b (b, x: device FP64, ndof) with flexible CG in FP64,
+ * preconditioned by Chebyshev-accelerated Jacobi in opts->precond_precision
+ * (Sec. 5.3: double-precision Krylov, single-precision preconditioner,
+ * Chebyshev-Jacobi on the inverse diagonal), followed by an FP64 true-residual
+ * check with restarts.  Pure-Neumann Poisson with alpha = 0 is solved in the
+ * mean-zero subspace (Sec. 3.2).  Needs a plan bound with_solver.  Blocks
+ * until done; info may be NULL.  Returns the solve's status. */
+sipg_status sipg_solve(sipg_plan* plan, const double* b, double* x, const sipg_solve_opts* opts,
+                       sipg_solve_info* info, void* stream);
+
+/* Asynchronous form of sipg_solve for interleaving many solves:
+ * begin enqueues the eigenvalue estimate and the CG start on `stream` (the
+ * solve stays bound to it); advance enqueues up to `iters` more iterations
+ * (iterations after convergence are skipped on the device); poll returns
+ * immediately with *done = 1 once the solve has finished and `info` filled,
+ * enqueueing the true-residual check and restarts itself when needed.
+ * b and x must stay valid until done. */
+sipg_status sipg_solve_begin(sipg_plan* plan, const double* b, double* x,
+                             const sipg_solve_opts* opts, void* stream);
+sipg_status sipg_solve_advance(sipg_plan* plan, int32_t iters);
+sipg_status sipg_solve_poll(sipg_plan* plan, int32_t* done, sipg_solve_info* info);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SIPG_H */

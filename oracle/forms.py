@@ -296,18 +296,27 @@ def _test_project(V, G, Jinv, a, B, w):
             + np.einsum("pjd,ep,epcd->ecj", G, w, Bref, optimize=True))
 
 
-def apply(pb: Problem, x: np.ndarray, parts=PARTS_ALL, batch: int = 4096) -> np.ndarray:
-    """y = A x evaluated directly from the quadrature sums (no global matrix)."""
+def apply(pb: Problem, x: np.ndarray, parts=PARTS_ALL, batch: int = 4096, cells=None) -> np.ndarray:
+    """y = A x evaluated directly from the quadrature sums (no global matrix).
+
+    With `cells` given, only the rows of those cells are evaluated (the other
+    rows are returned as zero), so single entries of large problems can be
+    checked without evaluating the whole operator."""
     mesh, n, C = pb.mesh, pb.n, pb.C
     X = np.asarray(x, dtype=np.float64).reshape(mesh.ncells, C, n ** 3)
     Y = np.zeros_like(X)
     h = cell_sizes(pb)
+    sel = np.ones(mesh.ncells, dtype=bool)
+    if cells is not None:
+        sel[:] = False
+        sel[np.asarray(cells)] = True
+    own = np.nonzero(sel)[0]
 
     if "cell" in parts:
         pts, _ = cell_points(n)
         V, G = tensor_tables(n, pts)
-        for s in range(0, mesh.ncells, batch):
-            cells = np.arange(s, min(s + batch, mesh.ncells))
+        for s in range(0, len(own), batch):
+            cells = own[s:s + batch]
             xq, Jinv, JxW = _cell_geo(pb, cells)
             mu = _mu(pb, xq)
             Xc = X[cells]
@@ -322,6 +331,8 @@ def apply(pb: Problem, x: np.ndarray, parts=PARTS_ALL, batch: int = 4096) -> np.
     if "interior" in parts:
         for d in range(3):
             em_all, ep_all = mesh.interior_faces(d)
+            keep = sel[em_all] | sel[ep_all]
+            em_all, ep_all = em_all[keep], ep_all[keep]
             ptm, _ = face_points(n, d, 1)
             ptp, _ = face_points(n, d, 0)
             Vm, Gm = tensor_tables(n, ptm)
@@ -356,6 +367,9 @@ def apply(pb: Problem, x: np.ndarray, parts=PARTS_ALL, batch: int = 4096) -> np.
                 pts, _ = face_points(n, d, side)
                 Vf, Gf = tensor_tables(n, pts)
                 cells = mesh.boundary_cells(d, side)
+                cells = cells[sel[cells]]
+                if len(cells) == 0:
+                    continue
                 _, xq, Ji, nrm, ds = _face_geo(pb, cells, d, side)
                 mu = _mu(pb, xq)
                 tau = _tau(pb, mu, h[cells])
@@ -370,6 +384,7 @@ def apply(pb: Problem, x: np.ndarray, parts=PARTS_ALL, batch: int = 4096) -> np.
                     B = -u[..., :, None] * nrm[..., None, :]
                 Y[cells] += _test_project(Vf, Gf, Ji, a, B, ds)
 
+    Y[~sel] = 0.0
     return Y.reshape(-1)
 
 

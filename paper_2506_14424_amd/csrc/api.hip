@@ -1,0 +1,692 @@
+// Host side of libsipg: plans, workspace layout, the C ABI of include/sipg.h.
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "sipg_internal.h"
+#include "solver_kernels.h"
+
+using namespace sipg;
+
+namespace {
+
+thread_local std::string g_err;
+
+sipg_status fail(sipg_status code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIP_TRY(call)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess) return fail(SIPG_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// ------------------------------------------------------------ 1D tables
+// Gauss-Legendre points of [-1, 1] by Newton's method on P_n (three-term
+// recurrence), mapped to [0, 1]; derivative matrix from barycentric weights.
+void gauss_legendre01(int n, double* x, double* w) {
+    for (int i = 0; i < n; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+        double dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            if (n == 1) { p1 = z; p0 = 1.0; }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+            const double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-17) break;
+        }
+        double p0 = 1.0, p1 = z;
+        for (int k = 2; k <= n; ++k) {
+            const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+            p0 = p1;
+            p1 = p2;
+        }
+        if (n == 1) p0 = 1.0;
+        dp = n == 1 ? 1.0 : n * (z * p1 - p0) / (z * z - 1.0);
+        // z_i descending in i; store ascending on [0, 1]
+        x[n - 1 - i] = 0.5 * (1.0 + z);
+        w[n - 1 - i] = 1.0 / ((1.0 - z * z) * dp * dp);  // 2/((1-z^2)P'^2) halved for [0,1]
+    }
+}
+
+template <typename T>
+void fill_tables(int n, Tables<T>& tb) {
+    double x[kMaxN], w[kMaxN], lam[kMaxN];
+    gauss_legendre01(n, x, w);
+    std::memset(&tb, 0, sizeof(tb));
+    for (int j = 0; j < n; ++j) {
+        double p = 1.0;
+        for (int m = 0; m < n; ++m)
+            if (m != j) p *= x[j] - x[m];
+        lam[j] = 1.0 / p;
+    }
+    for (int q = 0; q < n; ++q) {
+        double diag = 0.0;
+        for (int j = 0; j < n; ++j)
+            if (j != q) {
+                const double v = lam[j] / lam[q] / (x[q] - x[j]);
+                tb.D[q][j] = T(v);
+                diag -= v;
+            }
+        tb.D[q][q] = T(diag);
+        tb.w[q] = T(w[q]);
+        tb.x[q] = T(x[q]);
+    }
+    for (int s = 0; s < 2; ++s) {
+        const double t = s;
+        for (int j = 0; j < n; ++j) {
+            double val = 1.0, der = 0.0;
+            for (int m = 0; m < n; ++m) {
+                if (m == j) continue;
+                // product rule: d/dt prod (t - x_m)/(x_j - x_m)
+                der = der * (t - x[m]) / (x[j] - x[m]) + val / (x[j] - x[m]);
+                val *= (t - x[m]) / (x[j] - x[m]);
+            }
+            tb.S[s][j] = T(val);
+            tb.G[s][j] = T(der);
+        }
+    }
+}
+
+inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+enum Phase { PH_IDLE = 0, PH_RUNNING, PH_CHECKING, PH_DONE };
+
+}  // namespace
+
+struct sipg_plan {
+    int nx, ny, nz, bc[6];
+    int op, degree, n, C;
+    double alpha, penalty;
+    bool curved;
+    std::vector<double> verts;
+    std::vector<float> verts32;
+    LawDev law;
+    long long ncell, ndof, nface, nvert;
+    Tables<double> tab64;
+    Tables<float> tab32;
+
+    // device workspace
+    bool bound = false, with_solver = false;
+    char* ws = nullptr;
+    double *verts64_d = nullptr, *hcell = nullptr, *tfac64 = nullptr, *mu_cell64 = nullptr, *mu_face64 = nullptr;
+    float *verts32_d = nullptr, *tfac32 = nullptr, *mu_cell32 = nullptr, *mu_face32 = nullptr;
+    double *diag64 = nullptr, *dinv64 = nullptr;
+    float* dinv32 = nullptr;
+    double *r = nullptr, *p = nullptr, *q = nullptr, *z = nullptr, *zo = nullptr;
+    void *cr = nullptr, *cd = nullptr, *cz0 = nullptr, *cz1 = nullptr;
+    double* partials = nullptr;
+    SolveState* st = nullptr;
+
+    // solve session
+    SolveState* mirror = nullptr;  // pinned host copy of *st
+    hipEvent_t ev = nullptr;
+    hipStream_t sstream = nullptr;
+    const double* b = nullptr;
+    double* x = nullptr;
+    sipg_solve_opts opts;
+    int phase = PH_IDLE;
+    int restarts = 0;
+    bool mean_zero = false;
+    bool lz_valid = false;
+    int lz_steps = 0;
+    sipg_solve_info info;
+
+    template <typename T>
+    OpData<T> opdata() const;
+};
+
+template <typename T>
+OpData<T> sipg_plan::opdata() const {
+    OpData<T> o;
+    std::memset(&o, 0, sizeof(o));
+    o.nx = nx; o.ny = ny; o.nz = nz;
+    o.ncell = (int)ncell;
+    o.nfx = (nx + 1) * ny * nz;
+    o.nfy = nx * (ny + 1) * nz;
+    for (int i = 0; i < 6; ++i) o.bc[i] = bc[i];
+    o.alpha = T(alpha);
+    o.h[0] = T(1.0 / nx); o.h[1] = T(1.0 / ny); o.h[2] = T(1.0 / nz);
+    if constexpr (sizeof(T) == 8) {
+        o.verts = curved ? verts64_d : nullptr;
+        o.mu_cell = mu_cell64; o.mu_face = mu_face64; o.tfac = tfac64;
+        o.tab = tab64;
+    } else {
+        o.verts = curved ? verts32_d : nullptr;
+        o.mu_cell = mu_cell32; o.mu_face = mu_face32; o.tfac = tfac32;
+        o.tab = tab32;
+    }
+    return o;
+}
+
+namespace {
+
+struct Layout {
+    size_t verts64, verts32, hcell, tfac64, tfac32, mu_cell64, mu_cell32, mu_face64, mu_face32, diag64, dinv64,
+        dinv32;
+    size_t r, p, q, z, zo, cr, cd, cz0, cz1, partials, st;
+    size_t op_end, total;
+};
+
+Layout layout(const sipg_plan* P) {
+    Layout L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
+    const size_t nv = P->curved ? (size_t)P->nvert * 3 : 0;
+    const size_t nqc = P->C == 3 ? (size_t)P->ncell * P->n * P->n * P->n : 0;
+    const size_t nqf = P->C == 3 ? (size_t)P->nface * P->n * P->n : 0;
+    const size_t nd = (size_t)P->ndof;
+    L.verts64 = take(nv * 8); L.verts32 = take(nv * 4);
+    L.hcell = take((size_t)P->ncell * 8);
+    L.tfac64 = take((size_t)P->nface * 8); L.tfac32 = take((size_t)P->nface * 4);
+    L.mu_cell64 = take(nqc * 8); L.mu_cell32 = take(nqc * 4);
+    L.mu_face64 = take(nqf * 8); L.mu_face32 = take(nqf * 4);
+    L.diag64 = take(nd * 8); L.dinv64 = take(nd * 8); L.dinv32 = take(nd * 4);
+    L.op_end = off;
+    L.r = take(nd * 8); L.p = take(nd * 8); L.q = take(nd * 8); L.z = take(nd * 8); L.zo = take(nd * 8);
+    L.cr = take(nd * 8); L.cd = take(nd * 8); L.cz0 = take(nd * 8); L.cz1 = take(nd * 8);
+    L.partials = take(2 * kRedBlocks * 8);
+    L.st = take(sizeof(SolveState));
+    L.total = off;
+    return L;
+}
+
+bool valid_plan(const sipg_plan* P) { return P != nullptr; }
+
+double cell_corner_det_min(const sipg_plan* P) {
+    // det J of a trilinear cell at its 8 corners; positive everywhere iff the cell is valid enough
+    double mn = 1e300;
+    const int nx = P->nx, ny = P->ny, nz = P->nz;
+    auto V = [&](int ix, int iy, int iz, int i) { return P->verts[(((size_t)iz * (ny + 1) + iy) * (nx + 1) + ix) * 3 + i]; };
+    for (int ez = 0; ez < nz; ++ez)
+        for (int ey = 0; ey < ny; ++ey)
+            for (int ex = 0; ex < nx; ++ex)
+                for (int c = 0; c < 8; ++c) {
+                    const int a = c & 1, b = (c >> 1) & 1, d = (c >> 2) & 1;
+                    double J[3][3];
+                    for (int i = 0; i < 3; ++i) {
+                        // edges leaving corner (a,b,d) along each axis, pointing in +xi
+                        J[i][0] = V(ex + 1, ey + b, ez + d, i) - V(ex, ey + b, ez + d, i);
+                        J[i][1] = V(ex + a, ey + 1, ez + d, i) - V(ex + a, ey, ez + d, i);
+                        J[i][2] = V(ex + a, ey + b, ez + 1, i) - V(ex + a, ey + b, ez, i);
+                    }
+                    const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                                       J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                                       J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+                    mn = std::min(mn, det);
+                }
+    return mn;
+}
+
+template <typename T>
+sipg_status do_apply(sipg_plan* P, int parts, const void* x, void* y, hipStream_t s) {
+    ApplyIO<T> io;
+    std::memset(&io, 0, sizeof(io));
+    io.x = static_cast<const T*>(x);
+    io.y = static_cast<T*>(y);
+    io.parts = parts;
+    HIP_TRY(launch_apply<T>(P->n, P->C, P->curved, P->opdata<T>(), io, MODE_APPLY, s));
+    return SIPG_OK;
+}
+
+// z_out = Chebyshev-Jacobi(r) in precision T (skips when the solve is done)
+template <typename T>
+sipg_status precondition(sipg_plan* P, const double* r, double* zout, hipStream_t s) {
+    const long long n = P->ndof;
+    T* rT = static_cast<T*>(P->cr);
+    T* d = static_cast<T*>(P->cd);
+    T* za = static_cast<T*>(P->cz0);
+    T* zb = static_cast<T*>(P->cz1);
+    const T* dinv;
+    if constexpr (sizeof(T) == 8) dinv = P->dinv64; else dinv = P->dinv32;
+    sk_cheb_start<T>(r, rT, za, d, dinv, n, P->st, s);
+    const OpData<T> od = P->opdata<T>();
+    for (int j = 1; j < P->opts.cheb_degree; ++j) {
+        ApplyIO<T> io;
+        io.x = za; io.y = zb; io.parts = SIPG_PART_ALL;
+        io.r = rT; io.dinv = dinv; io.d = d;
+        io.coef = &P->st->cheb[j][0];
+        io.skip = &P->st->skip;
+        HIP_TRY(launch_apply<T>(P->n, P->C, P->curved, od, io, MODE_CHEB, s));
+        std::swap(za, zb);
+    }
+    sk_cheb_end<T>(za, zout, n, P->st, P->partials, P->mean_zero ? 1 : 0, s);
+    if (P->mean_zero) {
+        sk_scalar(P->st, P->partials, 1, SC_MEAN, n, s, 1);
+        sk_sub_mean(zout, n, P->st, P->st, s);
+    }
+    return SIPG_OK;
+}
+
+sipg_status precond(sipg_plan* P, const double* r, double* z, hipStream_t s) {
+    return P->opts.precond_precision == SIPG_F32 ? precondition<float>(P, r, z, s) : precondition<double>(P, r, z, s);
+}
+
+sipg_status run_lanczos(sipg_plan* P, hipStream_t s) {
+    const long long n = P->ndof;
+    double *v = P->z, *vprev = P->zo, *w = P->q, *t = P->p;
+    sk_lz_start(v, n, 12345ull, P->partials, s);
+    sk_scalar(P->st, P->partials, 1, SC_LZ_NORM, n, s);
+    sk_lz_normalize(v, vprev, n, P->st, s);
+    for (int j = 0; j < P->opts.lanczos_steps; ++j) {
+        sk_lz_pre(t, v, P->dinv64, n, s);
+        sipg_status rc = do_apply<double>(P, SIPG_PART_ALL, t, w, s);
+        if (rc != SIPG_OK) return rc;
+        sk_lz_post(w, v, P->dinv64, n, P->partials, s);
+        sk_scalar(P->st, P->partials, 1, SC_LZ_ALPHA, n, s);
+        sk_lz_orth(w, v, vprev, n, P->st, P->partials, s);
+        sk_scalar(P->st, P->partials, 1, SC_LZ_BETA, n, s);
+        sk_lz_next(vprev, w, n, P->st, s);   // vprev <- w / beta
+        std::swap(v, vprev);                 // (vprev, v) <- (v, w/beta)
+    }
+    HIP_TRY(hipGetLastError());
+    P->lz_valid = true;
+    P->lz_steps = P->opts.lanczos_steps;
+    return SIPG_OK;
+}
+
+sipg_status enqueue_readback(sipg_plan* P) {
+    HIP_TRY(hipMemcpyAsync(P->mirror, P->st, sizeof(SolveState), hipMemcpyDeviceToHost, P->sstream));
+    HIP_TRY(hipEventRecord(P->ev, P->sstream));
+    return SIPG_OK;
+}
+
+// restart CG from the current x with r already holding b - A x
+sipg_status cg_start_from_residual(sipg_plan* P) {
+    hipStream_t s = P->sstream;
+    const long long n = P->ndof;
+    sipg_status rc = precond(P, P->r, P->z, s);
+    if (rc != SIPG_OK) return rc;
+    sk_dot2(P->r, P->z, nullptr, n, P->partials, P->st, s);
+    sk_scalar(P->st, P->partials, 1, SC_RZ, n, s, 1);
+    sk_pcg_direction(P->p, P->z, n, 1, P->st, s);
+    HIP_TRY(hipGetLastError());
+    return SIPG_OK;
+}
+
+sipg_status enqueue_true_residual(sipg_plan* P) {
+    hipStream_t s = P->sstream;
+    const long long n = P->ndof;
+    if (P->mean_zero) {
+        sk_sum(P->x, n, P->partials, nullptr, s);
+        sk_scalar(P->st, P->partials, 1, SC_MEAN, n, s);
+        sk_sub_mean(P->x, n, P->st, nullptr, s);
+    }
+    sipg_status rc = do_apply<double>(P, SIPG_PART_ALL, P->x, P->q, s);
+    if (rc != SIPG_OK) return rc;
+    if (P->mean_zero) {
+        sk_sum(P->b, n, P->partials, nullptr, s);
+        sk_scalar(P->st, P->partials, 1, SC_MEAN, n, s);
+    }
+    sk_residual(P->b, P->q, P->r, n, P->mean_zero ? 1 : 0, P->st, P->partials, s);
+    sk_scalar(P->st, P->partials, 1, SC_TRUE, n, s);
+    HIP_TRY(hipGetLastError());
+    return enqueue_readback(P);
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t sipg_abi_version(void) { return 1; }
+
+const char* sipg_last_error(void) { return g_err.c_str(); }
+
+sipg_status sipg_plan_create(const sipg_mesh* mesh, const sipg_viscosity* law, const sipg_params* params,
+                             sipg_plan** out) {
+    if (out) *out = nullptr;
+    if (!mesh || !params || !out) return fail(SIPG_ERR_INVALID, "null argument");
+    if (mesh->nx < 1 || mesh->ny < 1 || mesh->nz < 1) return fail(SIPG_ERR_INVALID, "mesh needs >= 1 cell per direction");
+    if (params->degree < 1 || params->degree > 5) return fail(SIPG_ERR_INVALID, "degree must be 1..5");
+    if (params->op != SIPG_VISCOUS && params->op != SIPG_POISSON) return fail(SIPG_ERR_INVALID, "unknown operator");
+    if (!(params->alpha >= 0.0) || !std::isfinite(params->alpha)) return fail(SIPG_ERR_INVALID, "alpha must be >= 0");
+    if (!(params->penalty > 0.0) || !std::isfinite(params->penalty)) return fail(SIPG_ERR_INVALID, "penalty must be > 0");
+    for (int i = 0; i < 6; ++i)
+        if (mesh->bc[i] != SIPG_BC_DIRICHLET && mesh->bc[i] != SIPG_BC_NEUMANN) return fail(SIPG_ERR_INVALID, "bad bc value");
+    const long long ncell = (long long)mesh->nx * mesh->ny * mesh->nz;
+    const int n = params->degree + 1, C = params->op == SIPG_VISCOUS ? 3 : 1;
+    const long long ndof = ncell * C * n * n * n;
+    if (ndof > (1ll << 31) - 1 || ncell * n * n * n > (1ll << 31) - 1)
+        return fail(SIPG_ERR_UNSUPPORTED, "problem too large for 32-bit cell indexing");
+
+    sipg_plan* P = new (std::nothrow) sipg_plan();
+    if (!P) return fail(SIPG_ERR_OOM, "host allocation failed");
+    P->nx = mesh->nx; P->ny = mesh->ny; P->nz = mesh->nz;
+    for (int i = 0; i < 6; ++i) P->bc[i] = mesh->bc[i];
+    P->op = params->op; P->degree = params->degree; P->n = n; P->C = C;
+    P->alpha = params->alpha; P->penalty = params->penalty;
+    P->ncell = ncell; P->ndof = ndof;
+    P->nface = (long long)(mesh->nx + 1) * mesh->ny * mesh->nz + (long long)mesh->nx * (mesh->ny + 1) * mesh->nz +
+               (long long)mesh->nx * mesh->ny * (mesh->nz + 1);
+    P->nvert = (long long)(mesh->nx + 1) * (mesh->ny + 1) * (mesh->nz + 1);
+    P->curved = mesh->vertices != nullptr;
+    if (P->curved) {
+        P->verts.assign(mesh->vertices, mesh->vertices + P->nvert * 3);
+        for (double v : P->verts)
+            if (!std::isfinite(v)) { delete P; return fail(SIPG_ERR_INVALID, "non-finite vertex"); }
+        if (cell_corner_det_min(P) <= 0.0) { delete P; return fail(SIPG_ERR_INVALID, "a cell has det J <= 0 at a corner"); }
+        P->verts32.assign(P->verts.begin(), P->verts.end());
+    }
+    std::memset(&P->law, 0, sizeof(P->law));
+    if (C == 3) {
+        if (!law) { delete P; return fail(SIPG_ERR_INVALID, "viscous operator needs a viscosity law"); }
+        LawDev& L = P->law;
+        L.kind = law->kind;
+        L.mu = law->mu; L.amp = law->amp; L.contrast = law->contrast; L.rmin = law->rmin; L.rmax = law->rmax;
+        L.mu0 = law->mu0; L.mu_inf = law->mu_inf; L.lam = law->lam; L.n_exp = law->n_exp; L.kappa = law->kappa;
+        L.a_exp = law->a_exp;
+        switch (law->kind) {
+            case SIPG_LAW_CONST:
+                if (!(law->mu >= 0.0)) { delete P; return fail(SIPG_ERR_INVALID, "CONST law needs mu >= 0"); }
+                break;
+            case SIPG_LAW_SINE:
+                if (!(law->mu > 0.0) || !(std::fabs(law->amp) < 1.0)) {
+                    delete P; return fail(SIPG_ERR_INVALID, "SINE law needs mu > 0 and |amp| < 1");
+                }
+                break;
+            case SIPG_LAW_LOGFIELD:
+            case SIPG_LAW_CARREAU: {
+                if (law->n_modes < 0 || law->n_modes > SIPG_MAX_MODES || (law->n_modes > 0 && (!law->k || !law->phi))) {
+                    delete P; return fail(SIPG_ERR_INVALID, "law modes missing or more than SIPG_MAX_MODES");
+                }
+                L.n_modes = law->n_modes;
+                for (int m = 0; m < law->n_modes; ++m) {
+                    for (int i = 0; i < 3; ++i) L.k[m][i] = law->k[3 * m + i];
+                    L.phi[m] = law->phi[m];
+                }
+                if (law->kind == SIPG_LAW_LOGFIELD) {
+                    if (law->n_modes > 0 && !law->a) { delete P; return fail(SIPG_ERR_INVALID, "LOGFIELD needs amplitudes"); }
+                    if (!(law->contrast > 0.0) || !(law->rmax > law->rmin)) {
+                        delete P; return fail(SIPG_ERR_INVALID, "LOGFIELD needs contrast > 0 and rmax > rmin");
+                    }
+                    for (int m = 0; m < law->n_modes; ++m) L.a[m] = law->a[m];
+                } else {
+                    if (law->n_modes > 0 && !law->v) { delete P; return fail(SIPG_ERR_INVALID, "CARREAU needs velocity modes"); }
+                    if (!(law->mu_inf >= 0.0) || !(law->mu0 > 0.0) || !(law->a_exp > 0.0)) {
+                        delete P; return fail(SIPG_ERR_INVALID, "CARREAU needs mu0 > 0, mu_inf >= 0, a > 0");
+                    }
+                    for (int m = 0; m < law->n_modes; ++m)
+                        for (int i = 0; i < 3; ++i) L.v[m][i] = law->v[3 * m + i];
+                }
+                break;
+            }
+            default:
+                delete P;
+                return fail(SIPG_ERR_INVALID, "unknown viscosity law");
+        }
+    }
+    fill_tables<double>(n, P->tab64);
+    fill_tables<float>(n, P->tab32);
+    std::memset(&P->info, 0, sizeof(P->info));
+    sipg_solve_opts_default(&P->opts);
+    *out = P;
+    g_err.clear();
+    return SIPG_OK;
+}
+
+void sipg_plan_destroy(sipg_plan* P) {
+    if (!P) return;
+    if (P->mirror) (void)hipHostFree(P->mirror);
+    if (P->ev) (void)hipEventDestroy(P->ev);
+    delete P;
+}
+
+int64_t sipg_dof_count(const sipg_plan* P) { return P ? P->ndof : -1; }
+int64_t sipg_face_count(const sipg_plan* P) { return P ? P->nface : -1; }
+
+sipg_status sipg_plan_workspace_bytes(const sipg_plan* P, int32_t with_solver, size_t* bytes) {
+    if (!valid_plan(P) || !bytes) return fail(SIPG_ERR_INVALID, "null argument");
+    const Layout L = layout(P);
+    *bytes = with_solver ? L.total : L.op_end;
+    return SIPG_OK;
+}
+
+sipg_status sipg_plan_bind(sipg_plan* P, void* workspace, size_t bytes, int32_t with_solver, void* stream) {
+    if (!valid_plan(P)) return fail(SIPG_ERR_INVALID, "null plan");
+    if (!workspace) return fail(SIPG_ERR_INVALID, "null workspace");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(SIPG_ERR_INVALID, "workspace must be 256-byte aligned");
+    const Layout L = layout(P);
+    const size_t need = with_solver ? L.total : L.op_end;
+    if (bytes < need) return fail(SIPG_ERR_OOM, "workspace too small: need " + std::to_string(need) + " bytes");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* w = static_cast<char*>(workspace);
+    P->ws = w;
+    P->verts64_d = P->curved ? reinterpret_cast<double*>(w + L.verts64) : nullptr;
+    P->verts32_d = P->curved ? reinterpret_cast<float*>(w + L.verts32) : nullptr;
+    P->hcell = reinterpret_cast<double*>(w + L.hcell);
+    P->tfac64 = reinterpret_cast<double*>(w + L.tfac64);
+    P->tfac32 = reinterpret_cast<float*>(w + L.tfac32);
+    if (P->C == 3) {
+        P->mu_cell64 = reinterpret_cast<double*>(w + L.mu_cell64);
+        P->mu_cell32 = reinterpret_cast<float*>(w + L.mu_cell32);
+        P->mu_face64 = reinterpret_cast<double*>(w + L.mu_face64);
+        P->mu_face32 = reinterpret_cast<float*>(w + L.mu_face32);
+    }
+    P->diag64 = reinterpret_cast<double*>(w + L.diag64);
+    P->dinv64 = reinterpret_cast<double*>(w + L.dinv64);
+    P->dinv32 = reinterpret_cast<float*>(w + L.dinv32);
+    P->with_solver = with_solver != 0;
+    if (P->with_solver) {
+        P->r = reinterpret_cast<double*>(w + L.r);
+        P->p = reinterpret_cast<double*>(w + L.p);
+        P->q = reinterpret_cast<double*>(w + L.q);
+        P->z = reinterpret_cast<double*>(w + L.z);
+        P->zo = reinterpret_cast<double*>(w + L.zo);
+        P->cr = w + L.cr; P->cd = w + L.cd; P->cz0 = w + L.cz0; P->cz1 = w + L.cz1;
+        P->partials = reinterpret_cast<double*>(w + L.partials);
+        P->st = reinterpret_cast<SolveState*>(w + L.st);
+        if (!P->mirror) HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&P->mirror), sizeof(SolveState), hipHostMallocDefault));
+        if (!P->ev) HIP_TRY(hipEventCreateWithFlags(&P->ev, hipEventDisableTiming));
+        HIP_TRY(hipMemsetAsync(P->st, 0, sizeof(SolveState), s));
+    }
+    P->lz_valid = false;
+    P->phase = PH_IDLE;
+    if (P->curved) {
+        HIP_TRY(hipMemcpyAsync(P->verts64_d, P->verts.data(), P->verts.size() * 8, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(P->verts32_d, P->verts32.data(), P->verts32.size() * 4, hipMemcpyHostToDevice, s));
+    }
+    const OpData<double> od = P->opdata<double>();
+    HIP_TRY(launch_setup(P->n, P->C, P->curved, od, P->law, P->penalty, P->hcell, P->tfac64, P->tfac32, P->mu_cell64,
+                         P->mu_cell32, P->mu_face64, P->mu_face32, (int)P->nface, s));
+    const OpData<double> od2 = P->opdata<double>();
+    HIP_TRY(launch_diagonal(P->n, P->C, P->curved, od2, P->diag64, P->dinv64, P->dinv32, s));
+    P->bound = true;
+    g_err.clear();
+    return SIPG_OK;
+}
+
+sipg_status sipg_apply_parts(sipg_plan* P, int32_t precision, int32_t parts, const void* x, void* y, void* stream) {
+    if (!valid_plan(P) || !x || !y) return fail(SIPG_ERR_INVALID, "null argument");
+    if (!P->bound) return fail(SIPG_ERR_STATE, "plan not bound");
+    if (x == y) return fail(SIPG_ERR_INVALID, "x and y must not alias");
+    if (parts & ~SIPG_PART_ALL) return fail(SIPG_ERR_INVALID, "bad parts mask");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (precision == SIPG_F64) return do_apply<double>(P, parts, x, y, s);
+    if (precision == SIPG_F32) return do_apply<float>(P, parts, x, y, s);
+    return fail(SIPG_ERR_INVALID, "bad precision");
+}
+
+sipg_status sipg_apply(sipg_plan* P, int32_t precision, const void* x, void* y, void* stream) {
+    return sipg_apply_parts(P, precision, SIPG_PART_ALL, x, y, stream);
+}
+
+sipg_status sipg_diagonal(sipg_plan* P, int32_t precision, int32_t inverse, void* out, void* stream) {
+    if (!valid_plan(P) || !out) return fail(SIPG_ERR_INVALID, "null argument");
+    if (!P->bound) return fail(SIPG_ERR_STATE, "plan not bound");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const long long n = P->ndof;
+    if (precision == SIPG_F64) {
+        HIP_TRY(hipMemcpyAsync(out, inverse ? P->dinv64 : P->diag64, n * 8, hipMemcpyDeviceToDevice, s));
+    } else if (precision == SIPG_F32) {
+        if (inverse) HIP_TRY(hipMemcpyAsync(out, P->dinv32, n * 4, hipMemcpyDeviceToDevice, s));
+        else sk_cast(static_cast<float*>(out), P->diag64, n, s);
+    } else {
+        return fail(SIPG_ERR_INVALID, "bad precision");
+    }
+    HIP_TRY(hipGetLastError());
+    return SIPG_OK;
+}
+
+sipg_status sipg_viscosity_values(sipg_plan* P, double* mu_cell, double* mu_face, void* stream) {
+    if (!valid_plan(P)) return fail(SIPG_ERR_INVALID, "null plan");
+    if (!P->bound) return fail(SIPG_ERR_STATE, "plan not bound");
+    if (P->C != 3) return fail(SIPG_ERR_INVALID, "the poisson operator has no viscosity");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t nn = (size_t)P->n * P->n;
+    if (mu_cell) HIP_TRY(hipMemcpyAsync(mu_cell, P->mu_cell64, P->ncell * nn * P->n * 8, hipMemcpyDeviceToDevice, s));
+    if (mu_face) HIP_TRY(hipMemcpyAsync(mu_face, P->mu_face64, P->nface * nn * 8, hipMemcpyDeviceToDevice, s));
+    return SIPG_OK;
+}
+
+void sipg_solve_opts_default(sipg_solve_opts* o) {
+    if (!o) return;
+    o->rel_tol = 1e-8;
+    o->max_iter = 5000;
+    o->precond_precision = SIPG_F32;
+    o->cheb_degree = 5;
+    o->cheb_ratio = 20.0;
+    o->cheb_safety = 1.2;
+    o->lanczos_steps = 20;
+    o->check_every = 10;
+    o->max_restarts = 3;
+}
+
+sipg_status sipg_solve_begin(sipg_plan* P, const double* b, double* x, const sipg_solve_opts* opts, void* stream) {
+    if (!valid_plan(P) || !b || !x) return fail(SIPG_ERR_INVALID, "null argument");
+    if (!P->bound || !P->with_solver) return fail(SIPG_ERR_STATE, "plan not bound with solver workspace");
+    if (P->phase == PH_RUNNING || P->phase == PH_CHECKING) return fail(SIPG_ERR_STATE, "a solve is in progress on this plan");
+    sipg_solve_opts o;
+    if (opts) o = *opts; else sipg_solve_opts_default(&o);
+    if (!(o.rel_tol > 0.0) || o.max_iter < 1 || o.cheb_degree < 1 || o.cheb_degree > 63 || !(o.cheb_ratio > 1.0) ||
+        !(o.cheb_safety > 0.0) || o.lanczos_steps < 1 || o.lanczos_steps > 64 || o.check_every < 1 ||
+        o.max_restarts < 0 || (o.precond_precision != SIPG_F32 && o.precond_precision != SIPG_F64))
+        return fail(SIPG_ERR_INVALID, "bad solve options");
+    const bool all_neumann = std::all_of(P->bc, P->bc + 6, [](int v) { return v == SIPG_BC_NEUMANN; });
+    if (P->C == 3 && all_neumann && P->alpha == 0.0)
+        return fail(SIPG_ERR_UNSUPPORTED, "pure-Neumann viscous operator with alpha = 0 is singular (rigid motions)");
+    P->mean_zero = P->C == 1 && all_neumann && P->alpha == 0.0;
+    P->sstream = static_cast<hipStream_t>(stream);
+    P->b = b;
+    P->x = x;
+    P->opts = o;
+    P->restarts = 0;
+    std::memset(&P->info, 0, sizeof(P->info));
+    hipStream_t s = P->sstream;
+    const long long n = P->ndof;
+    sk_state_init(P->st, o.rel_tol * o.rel_tol, o.max_iter, s);
+    if (!P->lz_valid || P->lz_steps != o.lanczos_steps) {
+        sipg_status rc = run_lanczos(P, s);
+        if (rc != SIPG_OK) return rc;
+    }
+    sk_lz_finish(P->st, o.cheb_safety, o.cheb_ratio, o.cheb_degree, s);
+    if (P->mean_zero) {
+        sk_sum(b, n, P->partials, nullptr, s);
+        sk_scalar(P->st, P->partials, 1, SC_MEAN, n, s);
+    }
+    sk_pcg_start(b, P->r, x, n, P->mean_zero ? 1 : 0, P->st, P->partials, s);
+    sk_scalar(P->st, P->partials, 1, SC_PCG_INIT, n, s);
+    sipg_status rc = cg_start_from_residual(P);
+    if (rc != SIPG_OK) return rc;
+    P->phase = PH_RUNNING;
+    return enqueue_readback(P);
+}
+
+sipg_status sipg_solve_advance(sipg_plan* P, int32_t iters) {
+    if (!valid_plan(P)) return fail(SIPG_ERR_INVALID, "null plan");
+    if (P->phase == PH_IDLE) return fail(SIPG_ERR_STATE, "no solve in progress");
+    if (P->phase == PH_DONE || iters <= 0) return SIPG_OK;
+    hipStream_t s = P->sstream;
+    const long long n = P->ndof;
+    for (int it = 0; it < iters; ++it) {
+        ApplyIO<double> io;
+        std::memset(&io, 0, sizeof(io));
+        io.x = P->p; io.y = P->q; io.parts = SIPG_PART_ALL; io.skip = &P->st->skip;
+        HIP_TRY(launch_apply<double>(P->n, P->C, P->curved, P->opdata<double>(), io, MODE_APPLY, s));
+        sk_dot2(P->p, P->q, nullptr, n, P->partials, P->st, s);
+        sk_scalar(P->st, P->partials, 1, SC_ALPHA, n, s, 1);
+        sk_pcg_update(P->x, P->r, P->p, P->q, n, P->st, P->partials, s);
+        sk_scalar(P->st, P->partials, 1, SC_RESID, n, s, 1);
+        sipg_status rc = precond(P, P->r, P->zo, s);   // zo <- z_new
+        if (rc != SIPG_OK) return rc;
+        sk_dot2(P->r, P->zo, P->z, n, P->partials, P->st, s);
+        sk_scalar(P->st, P->partials, 2, SC_BETA, n, s, 1);
+        sk_pcg_direction(P->p, P->zo, n, 0, P->st, s);
+        std::swap(P->z, P->zo);
+    }
+    HIP_TRY(hipGetLastError());
+    return enqueue_readback(P);
+}
+
+sipg_status sipg_solve_poll(sipg_plan* P, int32_t* done, sipg_solve_info* info) {
+    if (!valid_plan(P) || !done) return fail(SIPG_ERR_INVALID, "null argument");
+    *done = 0;
+    if (P->phase == PH_IDLE) return fail(SIPG_ERR_STATE, "no solve in progress");
+    if (P->phase == PH_DONE) {
+        *done = 1;
+        if (info) *info = P->info;
+        return SIPG_OK;
+    }
+    const hipError_t q = hipEventQuery(P->ev);
+    if (q == hipErrorNotReady) return SIPG_OK;
+    if (q != hipSuccess) return fail(SIPG_ERR_HIP, std::string("hipEventQuery: ") + hipGetErrorString(q));
+    const SolveState& m = *P->mirror;
+    if (P->phase == PH_RUNNING) {
+        if (m.done == 0) return SIPG_OK;  // caller should advance further
+        P->phase = PH_CHECKING;
+        return enqueue_true_residual(P);
+    }
+    // PH_CHECKING: the true residual has arrived
+    const double rel = m.bnorm2 > 0.0 ? std::sqrt(m.rr_true / m.bnorm2) : 0.0;
+    const bool ok = rel <= P->opts.rel_tol;
+    if (ok || m.done == 2 || m.iter >= P->opts.max_iter || P->restarts >= P->opts.max_restarts) {
+        P->phase = PH_DONE;
+        P->info.iterations = m.iter;
+        P->info.restarts = P->restarts;
+        P->info.rel_residual = rel;
+        P->info.lambda_max = m.lam_max;
+        P->info.status = ok ? SIPG_OK : (m.done == 2 ? SIPG_ERR_BREAKDOWN : SIPG_ERR_NOT_CONVERGED);
+        *done = 1;
+        if (info) *info = P->info;
+        return SIPG_OK;
+    }
+    // restart from x: r = b - A x is already in place
+    P->restarts += 1;
+    sk_state_resume(P->st, P->opts.max_iter, P->sstream);
+    sipg_status rc = cg_start_from_residual(P);
+    if (rc != SIPG_OK) return rc;
+    P->phase = PH_RUNNING;
+    return enqueue_readback(P);
+}
+
+sipg_status sipg_solve(sipg_plan* P, const double* b, double* x, const sipg_solve_opts* opts, sipg_solve_info* info,
+                       void* stream) {
+    sipg_status rc = sipg_solve_begin(P, b, x, opts, stream);
+    if (rc != SIPG_OK) return rc;
+    for (;;) {
+        int32_t done = 0;
+        if (P->phase == PH_RUNNING) {
+            rc = sipg_solve_advance(P, P->opts.check_every);
+            if (rc != SIPG_OK) return rc;
+        }
+        HIP_TRY(hipEventSynchronize(P->ev));
+        rc = sipg_solve_poll(P, &done, info);
+        if (rc != SIPG_OK) return rc;
+        if (done) break;
+    }
+    return P->info.status == SIPG_OK ? SIPG_OK
+                                     : fail((sipg_status)P->info.status, "solve did not reach the tolerance");
+}
+
+}  // extern "C"

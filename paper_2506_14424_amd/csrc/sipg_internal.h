@@ -1,0 +1,106 @@
+// Internal declarations shared by the host code and the HIP kernels of libsipg.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/sipg.h"
+
+namespace sipg {
+
+constexpr int kMaxN = 6;  // n = k + 1 <= 6
+
+// One-dimensional tables on the n Gauss-Legendre points g_q of [0, 1] with
+// the Lagrange basis l_j through the same points.
+template <typename T>
+struct Tables {
+    T D[kMaxN][kMaxN];  // D[q][j] = l_j'(g_q)
+    T S[2][kMaxN];      // S[s][j] = l_j(s), s = 0, 1 (face values)
+    T G[2][kMaxN];      // G[s][j] = l_j'(s)     (face normal derivatives)
+    T w[kMaxN];         // quadrature weights, sum 1
+    T x[kMaxN];         // quadrature points
+};
+
+// Geometry, viscosity and penalty data of one operator in precision T.
+template <typename T>
+struct OpData {
+    int nx, ny, nz, ncell;
+    int nfx, nfy;            // number of x-faces, y-faces (face id offsets)
+    int bc[6];               // 0 = Dirichlet, 1 = Neumann, sides -x,+x,-y,+y,-z,+z
+    T alpha;                 // mass factor gamma_0/dt
+    T h[3];                  // straight cells: edge lengths
+    const T* verts;          // curved cells: vertex coordinates, else nullptr
+    const T* mu_cell;        // [ncell][n^3]
+    const T* mu_face;        // [nface][n^2]
+    const T* tfac;           // [nface] P (k+1)^2 / h_F
+    Tables<T> tab;
+};
+
+// Device law parameters (copied by value into kernels).
+struct LawDev {
+    int kind;
+    int n_modes;
+    double mu, amp, contrast, rmin, rmax;
+    double mu0, mu_inf, lam, n_exp, kappa, a_exp;
+    int k[SIPG_MAX_MODES][3];
+    double a[SIPG_MAX_MODES];
+    double v[SIPG_MAX_MODES][3];
+    double phi[SIPG_MAX_MODES];
+};
+
+enum ApplyMode { MODE_APPLY = 0, MODE_CHEB = 1 };
+
+// Vector arguments of one operator application.
+template <typename T>
+struct ApplyIO {
+    const T* x;      // input (MODE_CHEB: current iterate z_j)
+    T* y;            // output (MODE_CHEB: next iterate z_{j+1})
+    int parts;       // SIPG_PART_* mask
+    // MODE_CHEB: d <- c1 d + c2 Dinv (r - A z); z_{j+1} = z_j + d
+    const T* r;
+    const T* dinv;
+    T* d;
+    const double* coef;  // device {c1, c2}
+    const int* skip;     // device flag: nonzero => kernel returns at once (may be null)
+};
+
+// Device-side state of one CG solve (lives in the workspace).
+struct SolveState {
+    double bnorm2, rz, alpha, beta;
+    double tol2;             // rel_tol^2
+    double rr;               // last recursive residual norm^2
+    double rr_true;          // last true residual norm^2
+    double mean;             // scratch for mean-zero projections
+    double scale;            // scratch
+    double lam_max;
+    double theta_inv;
+    double cheb[64][2];      // per Chebyshev step (c1, c2), step 1..degree-1
+    double lz_alpha[64], lz_beta[65];
+    int lz_m;                // Lanczos steps taken
+    int done;                // 0 running, 1 converged (recursive), 2 breakdown, 3 max_iter
+    int iter;
+    int max_iter;
+    int skip;                // nonzero while done != 0 (read by apply kernels)
+    int pad[3];
+};
+
+constexpr int kRedBlocks = 512;   // blocks of the deterministic reductions
+constexpr int kRedThreads = 256;
+
+// ---------------------------------------------------------------- launchers
+// (defined in the .hip files; return hipError_t of the launch)
+
+template <typename T>
+hipError_t launch_apply(int n, int C, bool curved, const OpData<T>& op, const ApplyIO<T>& io,
+                        int mode, hipStream_t s);
+
+hipError_t launch_setup(int n, int C, bool curved, const OpData<double>& op, const LawDev& law,
+                        double penalty, double* hcell, double* tfac64, float* tfac32,
+                        double* mu_cell64, float* mu_cell32, double* mu_face64, float* mu_face32,
+                        int nface, hipStream_t s);
+
+hipError_t launch_diagonal(int n, int C, bool curved, const OpData<double>& op, double* diag,
+                           double* dinv, float* dinv32, hipStream_t s);
+
+}  // namespace sipg
