@@ -1,0 +1,278 @@
+"""Benchmark of the matrix-free SIPG viscous operator on one MI355X.
+
+One step = one FP64 application y = A x of the viscous operator on the
+headline workload (32^3 trilinear cells with perturbed vertices, k = 3,
+mu = 10^(3 s(x)), 6,291,456 unknowns); inputs resident in device memory,
+(x, y) rotated over enough buffers that they do not stay in the 256 MB
+last-level cache.  Besides the headline DoF/s the line reports the FP32
+(preconditioner precision) apply, the setup including the inverse diagonal,
+FP64- vs FP32-preconditioned solves of the 24^3 k = 4 Carreau workload to
+1e-8, the continuous-batching request loop (solves/s, p50/p99), the
+roofline of the apply kernel and the CPU oracle timed on this host.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+                       [--no-solve] [--no-serve] [--copy-probe]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, published
+METRIC = "operator DoF/s FP64 vs mixed; solves/s and p50/p99 latency at 1e-8 rel. res."
+KERNEL_SRC = os.path.join(ROOT, "paper_2506_14424_amd", "csrc", "apply.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_apply_c2.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(cfg, elem: int) -> dict:
+    """Bytes an apply must move at least: x in, y out, the viscosity at cell
+    and face quadrature points (stored pointwise), the mesh vertices."""
+    n = cfg["degree"] + 1
+    nx, ny, nz = cfg["nx"], cfg["ny"], cfg["nz"]
+    ncell = nx * ny * nz
+    C = 3 if cfg["op"] == "viscous" else 1
+    ndof = ncell * C * n ** 3
+    nface = (nx + 1) * ny * nz + nx * (ny + 1) * nz + nx * ny * (nz + 1)
+    vec = 2 * ndof * elem
+    mu = (ncell * n ** 3 + nface * n * n) * elem if C == 3 else 0
+    verts = (nx + 1) * (ny + 1) * (nz + 1) * 3 * elem if cfg["perturb"] else 0
+    return {"vectors": vec, "viscosity": mu, "vertices": verts, "total": vec + mu + verts,
+            "per_dof": (vec + mu + verts) / ndof}
+
+
+def kernel_hash() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def time_applies(op, dtype, steps, warmup, rotate_bytes=640e6):
+    import torch
+    import workloads as W
+    npairs = max(1, math.ceil(rotate_bytes / (2 * op.ndof * (8 if dtype == torch.float64 else 4))))
+    base = torch.from_numpy(W.uniform_vector(2, op.ndof)).cuda().to(dtype)
+    xs = [base.roll(i * 7919) for i in range(npairs)]
+    ys = [torch.empty_like(base) for _ in range(npairs)]
+    for i in range(warmup):
+        op.apply(xs[i % npairs], ys[i % npairs])
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for i in range(steps):
+        op.apply(xs[i % npairs], ys[i % npairs])
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = e0.elapsed_time(e1)
+    # cache-resident ("hot") rate for reference: the same pair over and over
+    e2, e3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e2.record()
+    for i in range(steps):
+        op.apply(xs[0], ys[0])
+    e3.record()
+    torch.cuda.synchronize()
+    hot_ms = e2.elapsed_time(e3)
+    del xs, ys
+    return {"wall_s": wall, "event_ms": ev_ms, "hot_event_ms": hot_ms, "pairs": npairs}
+
+
+def copy_probe(nbytes=1 << 30, reps=5):
+    """A plain device copy of known size, for scaling HBM counters."""
+    import torch
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    return {"bytes_read": nbytes, "bytes_written": nbytes, "reps": reps}
+
+
+def cpu_baseline(cfg, V):
+    """The oracle's direct quadrature apply of the whole workload, once."""
+    import numpy as np
+    import workloads as W
+    from oracle.forms import Problem, apply as oracle_apply
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    pb = Problem.from_config(cfg, V)
+    x = W.uniform_vector(cfg["x_seed"], pb.ndof)
+    t0 = time.perf_counter()
+    oracle_apply(pb, x)
+    dt = time.perf_counter() - t0
+    return {"value": pb.ndof / dt, "unit": "DoF/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"one full FP64 apply of the same workload by the oracle's direct quadrature "
+                      f"evaluation ({pb.ndof} unknowns, {dt:.1f} s, numpy/BLAS threads={threads})"}
+
+
+def solve_compare(tol=1e-8):
+    import torch
+    import workloads as W
+    from paper_2506_14424_amd import Operator, SolveOptions
+    cfg = W.config("c3")
+    V = W.box_vertices(cfg["nx"], cfg["ny"], cfg["nz"], cfg["perturb"])
+    op = Operator.from_config(cfg, V).bind(with_solver=True)
+    b = torch.from_numpy(W.uniform_vector(cfg["x_seed"], op.ndof)).cuda()
+    out = {"workload": "c3: viscous k=4, 24^3 perturbed, Carreau of a seeded velocity, "
+                       f"{op.ndof} DoFs, rel. tol {tol:g}"}
+    sols = {}
+    for prec in ("f64", "f32"):
+        opts = SolveOptions(rel_tol=tol, precond_precision=prec, check_every=25)
+        op.solve(b, opts=opts)                       # warm (Lanczos cached after the first)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, info = op.solve(b, opts=opts)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        sols[prec] = x
+        out[prec + "_precond"] = {"seconds": dt, "iterations": info["iterations"],
+                                  "rel_residual": info["rel_residual"], "status": info["status"]}
+    out["speedup_mixed_over_fp64"] = out["f64_precond"]["seconds"] / out["f32_precond"]["seconds"]
+    out["rel_diff_solutions"] = float((sols["f32"] - sols["f64"]).norm() / sols["f64"].norm())
+    fp32_err = None
+    try:
+        x64 = b.clone()
+        y64 = op.apply(x64)
+        y32 = op.apply(x64.float()).double()
+        ref32 = op.apply(x64.float().double())
+        fp32_err = float((y32 - ref32).abs().max() / ref32.abs().max())
+    except Exception:
+        pass
+    out["fp32_apply_rel_err_vs_fp64_apply"] = fp32_err
+    return out
+
+
+def serving(count=256, rate=20.0, budget=8 << 30):
+    """c5: the seeded request stream through the continuous-batching loop."""
+    import workloads as W
+    from paper_2506_14424_amd.serve import GpuExecutor, Request, Server
+    reqs = []
+    for r in W.serving_requests(5, count, rate):
+        cfg = r["cfg"]
+        rhs = (lambda s=cfg["x_seed"], n=W.ndofs(cfg): W.uniform_vector(s, n))
+        reqs.append(Request(r["id"], r["arrival"], cfg, rhs, None, cfg["tol"]))
+    out = Server(GpuExecutor(), hbm_budget=budget).run(reqs)
+    out["workload"] = (f"c5: {count} viscous-step solves, Poisson arrivals {rate:g}/s, N~U{{4..24}}, "
+                       "k~U{2..5}, contrast~U{1,1e2,1e4}, alpha/dt~U[1,100], FP32-preconditioned "
+                       "FP64 CG to 1e-8, HBM budget %d GiB" % (budget >> 30))
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true", help="also run a plain copy of known size")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the operator path has no "
+                                   "multi-GPU mode (see the sharding note in DESIGN.md)",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    import workloads as W
+    from paper_2506_14424_amd import Operator
+
+    cfg = W.config("c2")
+    V = W.box_vertices(cfg["nx"], cfg["ny"], cfg["nz"], cfg["perturb"])
+    op = Operator.from_config(cfg, V)
+    s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ws = torch.empty(op.workspace_bytes(False) + 256, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    s0.record()
+    op.bind(with_solver=False, workspace=ws)
+    s1.record()
+    torch.cuda.synchronize()
+    setup_ms = s0.elapsed_time(s1)
+    log(f"c2 bound: {op.ndof} DoFs, setup {setup_ms:.2f} ms")
+
+    r64 = time_applies(op, torch.float64, args.steps, args.warmup)
+    r32 = time_applies(op, torch.float32, args.steps, args.warmup)
+    k = args.steps
+    ms64 = r64["event_ms"] / k
+    value = op.ndof * k / r64["wall_s"]
+    b64 = algorithmic_bytes(cfg, 8)
+    b32 = algorithmic_bytes(cfg, 4)
+    achieved = b64["total"] / (ms64 * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        tr = json.load(open(TRAFFIC_FILE))
+        if tr.get("kernel_hash") == kernel_hash():
+            traffic = tr.get("bytes_per_launch")
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "DoF/s",
+        "n_gpus": 1,
+        "steps": k,
+        "warmup": args.warmup,
+        "ms_per_step": r64["wall_s"] * 1e3 / k,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "c2: SIPG viscous operator (alpha/dt) M - div(2 mu eps(u)), k=3, "
+                               "32^3 hex cells with vertices perturbed by 0.1h sin sin sin (trilinear), "
+                               "mu = 10^(3 s(x)) seeded smooth field, all-Dirichlet, "
+                               f"{op.ndof} DoFs, FP64 apply y = A x",
+                   "ndof": op.ndof, "degree": 3, "cells": 32 ** 3, "rotating_buffer_pairs": r64["pairs"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_apply<n=4,C=3,double,curved>",
+                     "algorithmic_bytes_per_launch": b64["total"],
+                     "algorithmic_bytes_per_dof": b64["per_dof"],
+                     "avg_launch_ms": ms64},
+        "hot_cache": {"dof_per_s": op.ndof * k / (r64["hot_event_ms"] * 1e-3),
+                      "note": "same (x, y) pair every step: inputs served from the 256 MB last-level cache"},
+        "fp32_apply": {"dof_per_s": op.ndof * k / (r32["event_ms"] * 1e-3),
+                       "avg_launch_ms": r32["event_ms"] / k,
+                       "achieved_GBs": b32["total"] / (r32["event_ms"] / k * 1e-3) / 1e9,
+                       "algorithmic_bytes_per_launch": b32["total"],
+                       "speedup_over_fp64": r64["event_ms"] / r32["event_ms"]},
+        "setup_ms": setup_ms,
+        "setup_note": "plan bind: cell sizes, penalty factors, viscosity at all quadrature points, "
+                      "diagonal and inverse diagonal (FP64 + FP32)",
+    }
+    log(f"apply f64: {ms64:.3f} ms/launch, {value:.3e} DoF/s, {achieved:.0f} GB/s algorithmic; "
+        f"f32 {r32['event_ms'] / k:.3f} ms")
+    if args.copy_probe:
+        line["copy_probe"] = copy_probe()
+    del op, ws
+    torch.cuda.empty_cache()
+
+    if not args.no_solve:
+        log("solve comparison (c3) ...")
+        line["solve"] = solve_compare()
+        log(json.dumps(line["solve"]))
+    if not args.no_serve:
+        log("serving loop (c5) ...")
+        line["serving"] = serving()
+        log(json.dumps(line["serving"]))
+    if not args.no_cpu:
+        log("cpu baseline (oracle) ...")
+        line["cpu_baseline"] = cpu_baseline(cfg, V)
+        log(json.dumps(line["cpu_baseline"]))
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

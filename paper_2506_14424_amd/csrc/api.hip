@@ -648,7 +648,7 @@ sipg_status sipg_solve_poll(sipg_plan* P, int32_t* done, sipg_solve_info* info) 
         return enqueue_true_residual(P);
     }
     // PH_CHECKING: the true residual has arrived
-    const double rel = m.bnorm2 > 0.0 ? std::sqrt(m.rr_true / m.bnorm2) : 0.0;
+    const double rel = m.bnorm2 == 0.0 ? 0.0 : std::sqrt(m.rr_true / m.bnorm2);  // NaN if b is not finite
     const bool ok = rel <= P->opts.rel_tol;
     if (ok || m.done == 2 || m.iter >= P->opts.max_iter || P->restarts >= P->opts.max_restarts) {
         P->phase = PH_DONE;

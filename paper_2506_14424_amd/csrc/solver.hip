@@ -187,8 +187,8 @@ __global__ void k_scalar(SolveState* st, const double* partials, int nslots, int
         case SC_PCG_INIT:
             st->bnorm2 = s0;
             st->iter = 0;
-            st->done = s0 > 0.0 ? 0 : 1;
-            st->skip = st->done;
+            st->done = !isfinite(s0) ? 2 : (s0 > 0.0 ? 0 : 1);   // NaN/Inf in b: breakdown
+            st->skip = st->done != 0;
             st->rr = s0;
             break;
         case SC_RZ:

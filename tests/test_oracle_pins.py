@@ -494,3 +494,21 @@ def test_neumann_poisson_solve_is_mean_zero():
     assert info["status"] == "ok" and abs(x.mean()) < 1e-14
     bz = b - b.mean()
     assert np.linalg.norm(bz - A @ x) <= 1e-8 * np.linalg.norm(bz)
+
+
+@pytest.mark.slow
+def test_pointwise_viscosity_can_make_the_operator_indefinite():
+    """Sec. 4.1 notes that the pointwise viscosity update does not by itself
+    guarantee a positive operator.  With the penalty tau = (k+1)^2 mu(x)/h at
+    each face point, a 3^3 mesh with a viscosity contrast of 1e4 across the
+    unit cube has negative eigenvalues, while the same mesh with contrast 10
+    stays positive definite."""
+    cfg = W.serving_requests(seed=11, count=12, rate=200.0, nmin=2, nmax=6)[3]["cfg"]
+    assert (cfg["nx"], cfg["degree"], cfg["law"]["contrast"]) == (3, 3, 1e4)
+
+    def lam_min(contrast):
+        law = dict(cfg["law"], contrast=contrast)
+        pb = Problem(Mesh(3, 3, 3), 3, "viscous", cfg["alpha"], 1.0, law)
+        return np.linalg.eigvalsh(assemble(pb).toarray())[0]
+    assert lam_min(1e4) < 0.0
+    assert lam_min(10.0) > 0.0
