@@ -1,21 +1,24 @@
 // Matrix-free SIPG operator application (viscous and Poisson) for gfx950.
 //
-// One workgroup handles CPB cells; each cell gets n*n threads, thread (i1, i2)
-// owning the line of nodes (i1, i2, 0..n-1) along xi_3.  Everything a cell
-// needs is computed by its own threads ("cell-centric"): the cell integral
-// and all six face integrals for the cell's own test functions.  A face is
-// therefore evaluated once from each side, but every output entry is written
-// exactly once, with no atomics and no second pass over the output.  The
-// neighbour's trace on a shared face is interpolated from the neighbour's
-// nodal values, which the XCD-aware block order keeps in the L2.
+// One workgroup handles CPB cells; each cell gets n*n threads.  Everything a
+// cell needs is computed by its own threads ("cell-centric"): the cell
+// integral and all six face integrals for the cell's own test functions.  A
+// face is therefore evaluated once from each side, but every output entry is
+// written exactly once, with no atomics and no second pass over the output.
+// The neighbour's trace on a shared face is interpolated from the
+// neighbour's nodal values, which the XCD-aware block order keeps in the L2.
 //
 // Sum factorisation (Sec. 5.3): with nodes at the Gauss points, values at
-// quadrature points are the nodal values; reference derivatives are 1D
-// contractions with D[q][j] = l_j'(g_q) along one axis.  Derivatives along
-// xi_3 stay in registers; along xi_1 and xi_2 they go through LDS.
+// quadrature points are the nodal values, and reference derivatives are 1D
+// contractions with D[q][j] = l_j'(g_q) along one axis.  For every 1D sweep a
+// thread owns a whole line of n values (the n*n threads of a cell own the
+// n*n lines of each direction), so all sweep coefficients are the same for
+// the whole wavefront and stay in scalar registers; lines are exchanged
+// through LDS between sweeps.  The thread (i1, i2) owns the xi_3 line
+// (i1, i2, 0..n-1) of quadrature points and outputs.
 //
-// Forms (Sec. 4.1), per quadrature point, written for the test functions of
-// the cell that owns the thread (outward unit normal n, [u] = u_own - u_nbr):
+// Forms (Sec. 4.1), per quadrature point, for the test functions of the cell
+// that owns the thread (outward unit normal n, [u] = u_own - u_nbr):
 //   cell      viscous: sigma = 2 mu eps(u) JxW, mass alpha u JxW
 //             poisson: sigma = grad u JxW,      mass alpha u JxW
 //   face      viscous: a = -2 {{mu eps(u)}} n + tau([u] + n([u].n)),
@@ -31,52 +34,463 @@ namespace sipg {
 
 template <int N, int C, bool DBL>
 struct Shape {
-    // cells per workgroup: about 64-256 threads, LDS well under 64 KB
+    // cells per workgroup: one wavefront for n <= 4, LDS well under 64 KB
     static constexpr int CPB = N == 2 ? 16 : N == 3 ? 7 : N == 4 ? 4 : N == 5 ? 5 : (DBL && C == 3 ? 3 : 7);
     static constexpr int THREADS = CPB * N * N;
+    static constexpr int NNN = N * N * N, NN = N * N;
+    // per-cell LDS: nodal values and a work space for the cell sweeps and the
+    // face stages; +1 staggers consecutive cells over the LDS banks
+    static constexpr int U = C * NNN + 1;
+    static constexpr int W = (2 * C * NNN > 8 * C * NN ? 2 * C * NNN : 8 * C * NN) + 1;
 };
+
+// Barrier between LDS stages.  A workgroup of one wavefront only needs the
+// wavefront's own (in-order) LDS accesses fenced against compiler reordering.
+template <int THREADS>
+__device__ __forceinline__ void stage_sync() {
+    if constexpr (THREADS <= 64) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
+// Reciprocal: hardware estimate refined by Newton steps to full precision.
+template <typename T>
+__device__ __forceinline__ T recip(T d) {
+    if constexpr (sizeof(T) == 8) {
+        double r = __builtin_amdgcn_rcp(d);
+        double e = __builtin_fma(-d, r, 1.0);
+        r = __builtin_fma(r, e, r);
+        e = __builtin_fma(-d, r, 1.0);
+        return __builtin_fma(r, e, r);
+    } else {
+        float r = __builtin_amdgcn_rcpf(d);
+        const float e = __builtin_fmaf(-d, r, 1.0f);
+        return __builtin_fmaf(r, e, r);
+    }
+}
+
+// Columns a_d = d x / d xi_d of the Jacobian of a trilinear cell at xi.
+template <typename T>
+__device__ __forceinline__ void jac_columns(const T (*g)[3], const T xi[3], T a[3][3]) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        a[0][i] = g[1][i] + g[4][i] * xi[1] + g[5][i] * xi[2] + g[7][i] * (xi[1] * xi[2]);
+        a[1][i] = g[2][i] + g[4][i] * xi[0] + g[6][i] * xi[2] + g[7][i] * (xi[0] * xi[2]);
+        a[2][i] = g[3][i] + g[5][i] * xi[0] + g[6][i] * xi[1] + g[7][i] * (xi[0] * xi[1]);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void cross3(const T u[3], const T v[3], T w[3]) {
+    w[0] = u[1] * v[2] - u[2] * v[1];
+    w[1] = u[2] * v[0] - u[0] * v[2];
+    w[2] = u[0] * v[1] - u[1] * v[0];
+}
+
+// Rows of J^-1 from the columns: row d = (a_{d+1} x a_{d+2}) / det.
+template <typename T>
+__device__ __forceinline__ void inverse_from_columns(const T a[3][3], T Ji[3][3], T& det) {
+    T c0[3], c1[3], c2[3];
+    cross3(a[1], a[2], c0);
+    cross3(a[2], a[0], c1);
+    cross3(a[0], a[1], c2);
+    det = a[0][0] * c0[0] + a[0][1] * c0[1] + a[0][2] * c0[2];
+    const T inv = recip(det);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        Ji[0][i] = c0[i] * inv;
+        Ji[1][i] = c1[i] * inv;
+        Ji[2][i] = c2[i] * inv;
+    }
+}
+
+struct CellIdx {
+    int lc, t, i1, i2, ec, ex, ey, ez;
+    bool active;
+};
+
+// Small per-lane tables kept in LDS: points, weights, face values/derivatives.
+template <typename T, int N>
+struct LaneTab {
+    T x[N], w[N], S[2][N], G[2][N];
+};
+
+// ---------------------------------------------------------------- faces
+//
+// One face of the cell (direction D, side s), in stages separated by LDS
+// barriers:
+//   A  traces of both sides at face point (a, b) = (i1, i2): values into LDS,
+//      d/dxi_D in registers;
+//   B1 tangential derivatives of both traces, one line per task;
+//   B2 geometry and flux at the face point;
+//   C1 transposed tangential sweeps of the flux, one line per task;
+//   C2 projection onto the cell's nodes (accumulated in y).
+template <int N, int C, typename T, bool CURVED, int D, int THREADS>
+__device__ __forceinline__ void face_pass(const OpData<T>& op, const ApplyIO<T>& io, const CellIdx& ci, int s,
+                                          T (&y)[C][N], const T* su, T* sw, T (*geo)[8][3],
+                                          const LaneTab<T, N>& lt) {
+    constexpr int NN = N * N, NNN = N * N * N;
+    constexpr int t1 = D == 0 ? 1 : 0, t2 = D == 2 ? 1 : 2;
+    const auto& tb = op.tab;
+    const int i1 = ci.i1, i2 = ci.i2, t = ci.t;
+    const int pos = D == 0 ? ci.ex : D == 1 ? ci.ey : ci.ez;
+    const int lim = D == 0 ? op.nx : D == 1 ? op.ny : op.nz;
+    const bool has_nb = s == 1 ? pos + 1 < lim : pos > 0;
+    const int stride = D == 0 ? 1 : D == 1 ? op.nx : op.nx * op.ny;
+    const int en = has_nb ? ci.ec + (s == 1 ? stride : -stride) : ci.ec;
+    const bool dir = !has_nb && op.bc[2 * D + s] == 0;
+    const bool live = ci.active && (has_nb ? (io.parts & SIPG_PART_INTERIOR) != 0
+                                           : (dir && (io.parts & SIPG_PART_BOUNDARY) != 0));
+    int fid;
+    if (D == 0) fid = (ci.ez * op.ny + ci.ey) * (op.nx + 1) + ci.ex + s;
+    else if (D == 1) fid = op.nfx + (ci.ez * (op.ny + 1) + ci.ey + s) * op.nx + ci.ex;
+    else fid = op.nfx + op.nfy + ((ci.ez + s) * op.ny + ci.ey) * op.nx + ci.ex;
+    // LDS regions of the work space, each [.][C][NN]
+    T* FT = sw;               // [2] trace values (own, neighbour)          A  -> B1
+    T* TD = sw + 2 * C * NN;  // [2][2] tangential derivatives (side, dir)  B1 -> B2
+    T* BT = sw;               // [2] flux components along t1, t2           B2 -> C1
+    T* VT = sw + 2 * C * NN;  // [2] transposed sweeps                      C1 -> C2
+    T* VV = sw + 6 * C * NN;  // [2] value / normal coefficients (D < 2)    C2
+
+    // ---- A: traces
+    T uo[C], uno[C], un[C], unn[C];
+    {
+        const T* xn = io.x + (size_t)en * (C * NNN);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            T v0 = 0, v1 = 0, w0 = 0, w1 = 0;
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                T own;
+                if (D == 2) own = su[c * NNN + j * NN + i2 * N + i1];
+                else if (D == 0) own = su[c * NNN + i2 * NN + i1 * N + j];
+                else own = su[c * NNN + i2 * NN + j * N + i1];
+                v0 += tb.S[s][j] * own;
+                v1 += tb.G[s][j] * own;
+                T nb = 0;
+                if (live && has_nb) {
+                    if (D == 2) nb = xn[(c * N + j) * NN + i2 * N + i1];
+                    else if (D == 0) nb = xn[(c * N + i2) * NN + i1 * N + j];
+                    else nb = xn[(c * N + i2) * NN + j * N + i1];
+                }
+                w0 += tb.S[1 - s][j] * nb;
+                w1 += tb.G[1 - s][j] * nb;
+            }
+            uo[c] = v0; uno[c] = v1; un[c] = w0; unn[c] = w1;
+            FT[c * NN + t] = v0;
+            FT[(C + c) * NN + t] = w0;
+        }
+    }
+    if constexpr (CURVED) {
+        if (t < 3 && has_nb && ci.active) {
+            const int nex = en % op.nx, ney = (en / op.nx) % op.ny, nez = en / (op.nx * op.ny);
+            T g[8];
+            trilinear_coeffs(op.verts, op.nx, op.ny, nex, ney, nez, t, g);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) geo[1][k][t] = g[k];
+        }
+    }
+    stage_sync<THREADS>();
+
+    // ---- B1: tangential derivatives; task k = ((side*2 + dir)*C + c)*N + line
+#pragma unroll
+    for (int k0 = 0; k0 < 4 * C * N; k0 += NN) {
+        const int k = k0 + t;
+        if (k < 4 * C * N) {
+            const int line = k % N, c = (k / N) % C, dirn = (k / (N * C)) % 2, side = k / (2 * N * C);
+            const T* in = FT + (side * C + c) * NN;
+            T* out = TD + ((side * 2 + dirn) * C + c) * NN;
+            const int base = dirn == 0 ? line * N : line;
+            const int step = dirn == 0 ? 1 : N;
+            T v[N];
+#pragma unroll
+            for (int j = 0; j < N; ++j) v[j] = in[base + j * step];
+#pragma unroll
+            for (int q = 0; q < N; ++q) {
+                T a = 0;
+#pragma unroll
+                for (int j = 0; j < N; ++j) a += tb.D[q][j] * v[j];
+                out[base + q * step] = a;
+            }
+        }
+    }
+    stage_sync<THREADS>();
+
+    // ---- B2: geometry and flux at the face point
+    T xi[3];
+    xi[t1] = lt.x[i1];
+    xi[t2] = lt.x[i2];
+    xi[D] = T(s);
+    T Jo[3][3], nrm[3], ds;
+    T acol[3][3];  // Jacobian columns; the tangential ones are shared with the neighbour
+    const T sgn = s == 1 ? T(1) : T(-1);
+    if constexpr (CURVED) {
+        jac_columns(geo[0], xi, acol);
+        T det;
+        inverse_from_columns(acol, Jo, det);
+        // row D of J^-1 is (a_t1 x a_t2) / det: n = sign row/|row|, ds = det |row| w_a w_b
+        const T v0 = Jo[D][0], v1 = Jo[D][1], v2 = Jo[D][2];
+        const T nv2 = v0 * v0 + v1 * v1 + v2 * v2;
+        const T rinv = T(1) / sqrt(nv2);
+        nrm[0] = sgn * v0 * rinv; nrm[1] = sgn * v1 * rinv; nrm[2] = sgn * v2 * rinv;
+        ds = det * (nv2 * rinv) * (lt.w[i1] * lt.w[i2]);
+    } else {
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) Jo[a][b] = a == b ? T(1) / op.h[a] : T(0);
+        nrm[0] = nrm[1] = nrm[2] = T(0);
+        nrm[D] = sgn;
+        ds = op.h[t1] * op.h[t2] * (lt.w[i1] * lt.w[i2]);
+    }
+    T mo[3];  // m = J^-1 n:  (grad u) n = gr . m for the reference gradient gr
+#pragma unroll
+    for (int d = 0; d < 3; ++d) mo[d] = Jo[d][0] * nrm[0] + Jo[d][1] * nrm[1] + Jo[d][2] * nrm[2];
+    T en_[C];  // viscous: (G + G^T) n summed over both sides; poisson: (G- + G+) . n
+    {
+        T gr[C][3];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            gr[c][t1] = TD[(0 * C + c) * NN + t];
+            gr[c][t2] = TD[(1 * C + c) * NN + t];
+            gr[c][D] = uno[c];
+        }
+        if constexpr (C == 3) {
+            T w[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) w[d] = nrm[0] * gr[0][d] + nrm[1] * gr[1][d] + nrm[2] * gr[2][d];
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                en_[c] = gr[c][0] * mo[0] + gr[c][1] * mo[1] + gr[c][2] * mo[2] +
+                         Jo[0][c] * w[0] + Jo[1][c] * w[1] + Jo[2][c] * w[2];
+        } else {
+            en_[0] = gr[0][0] * mo[0] + gr[0][1] * mo[1] + gr[0][2] * mo[2];
+        }
+    }
+    if (has_nb) {
+        T Jn[3][3];
+        if constexpr (CURVED) {
+            // the neighbour shares the tangential columns; only its xi_D column differs
+            T xin[3] = {xi[0], xi[1], xi[2]};
+            xin[D] = T(1 - s);
+            T an[3][3];
+            jac_columns(geo[1], xin, an);
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                an[t1][i] = acol[t1][i];
+                an[t2][i] = acol[t2][i];
+            }
+            T detn;
+            inverse_from_columns(an, Jn, detn);
+        } else {
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) Jn[a][b] = Jo[a][b];
+        }
+        T mn[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) mn[d] = Jn[d][0] * nrm[0] + Jn[d][1] * nrm[1] + Jn[d][2] * nrm[2];
+        T gr[C][3];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            gr[c][t1] = TD[(2 * C + c) * NN + t];
+            gr[c][t2] = TD[(3 * C + c) * NN + t];
+            gr[c][D] = unn[c];
+        }
+        if constexpr (C == 3) {
+            T w[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) w[d] = nrm[0] * gr[0][d] + nrm[1] * gr[1][d] + nrm[2] * gr[2][d];
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                en_[c] += gr[c][0] * mn[0] + gr[c][1] * mn[1] + gr[c][2] * mn[2] +
+                          Jn[0][c] * w[0] + Jn[1][c] * w[1] + Jn[2][c] * w[2];
+        } else {
+            en_[0] += gr[0][0] * mn[0] + gr[0][1] * mn[1] + gr[0][2] * mn[2];
+        }
+    } else {
+        // mirror principle on a Dirichlet face: u+ = -u-, grad u+ = grad u-
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            en_[c] *= T(2);
+            un[c] = -uo[c];
+        }
+    }
+    const T mu = (C == 3 && live) ? op.mu_face[(size_t)fid * NN + t] : T(1);
+    const T tau = live ? op.tfac[fid] * mu : T(0);
+    const T lf = live ? T(1) : T(0);
+    T ju[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) ju[c] = uo[c] - un[c];
+    T av[C], Bh[C][3];
+    if constexpr (C == 3) {
+        // a = -2 {{mu eps(u)}} n + tau ([u] + n([u].n)),  B = -mu sym([u] (x) n),
+        // B^ = J^-1 B:  B^[c][d] = -mu/2 (ju_c m_d + n_c p_d),  p = J^-1 ju
+        const T jn = ju[0] * nrm[0] + ju[1] * nrm[1] + ju[2] * nrm[2];
+        T p[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) p[d] = Jo[d][0] * ju[0] + Jo[d][1] * ju[1] + Jo[d][2] * ju[2];
+        const T dl = ds * lf;
+        const T hm = -T(0.5) * mu * dl;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            av[c] = dl * (-T(0.5) * mu * en_[c] + tau * (ju[c] + nrm[c] * jn));
+#pragma unroll
+            for (int d = 0; d < 3; ++d) Bh[c][d] = hm * (ju[c] * mo[d] + nrm[c] * p[d]);
+        }
+    } else {
+        // a = -{{grad u}}.n + tau [u],  B = -[u] n / 2,  B^ = -[u] m / 2
+        const T dl = ds * lf;
+        av[0] = dl * (-T(0.5) * en_[0] + tau * ju[0]);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) Bh[0][d] = -T(0.5) * dl * ju[0] * mo[d];
+    }
+    stage_sync<THREADS>();  // TD reads done before BT/VT overwrite the space
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        BT[c * NN + t] = Bh[c][t1];
+        BT[(C + c) * NN + t] = Bh[c][t2];
+    }
+    stage_sync<THREADS>();
+
+    // ---- C1: transposed tangential sweeps; task k = (dir*C + c)*N + line
+#pragma unroll
+    for (int k0 = 0; k0 < 2 * C * N; k0 += NN) {
+        const int k = k0 + t;
+        if (k < 2 * C * N) {
+            const int line = k % N, c = (k / N) % C, dirn = k / (N * C);
+            const T* in = BT + (dirn * C + c) * NN;
+            T* out = VT + (dirn * C + c) * NN;
+            const int base = dirn == 0 ? line * N : line;
+            const int step = dirn == 0 ? 1 : N;
+            T v[N];
+#pragma unroll
+            for (int q = 0; q < N; ++q) v[q] = in[base + q * step];
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+                T acc = 0;
+#pragma unroll
+                for (int q = 0; q < N; ++q) acc += tb.D[q][a] * v[q];
+                out[base + a * step] = acc;
+            }
+        }
+    }
+    stage_sync<THREADS>();
+
+    // ---- C2: projection onto the nodes
+    T vv[C], vn[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        vv[c] = av[c] + VT[c * NN + t] + VT[(C + c) * NN + t];
+        vn[c] = Bh[c][D];
+    }
+    if (D == 2) {
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int i3 = 0; i3 < N; ++i3) y[c][i3] += tb.S[s][i3] * vv[c] + tb.G[s][i3] * vn[c];
+    } else {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            VV[c * NN + t] = vv[c];
+            VV[(C + c) * NN + t] = vn[c];
+        }
+        stage_sync<THREADS>();
+        // node (i1, i2, i3): D = 0 -> face point (i2, i3), normal index i1
+        //                    D = 1 -> face point (i1, i3), normal index i2
+        const int ni = D == 0 ? i1 : i2;
+        const T sv = lt.S[s][ni], gv = lt.G[s][ni];
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int i3 = 0; i3 < N; ++i3) {
+                const int fp = D == 0 ? i3 * N + i2 : i3 * N + i1;
+                y[c][i3] += sv * VV[c * NN + fp] + gv * VV[(C + c) * NN + fp];
+            }
+    }
+    stage_sync<THREADS>();
+}
+
+// ---------------------------------------------------------------- kernel
 
 template <int N, int C, typename T, bool CURVED, int MODE>
 __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS))
     k_apply(const OpData<T> op, const ApplyIO<T> io) {
+    using Sh = Shape<N, C, sizeof(T) == 8>;
     constexpr int NN = N * N, NNN = N * N * N;
-    constexpr int CPB = Shape<N, C, sizeof(T) == 8>::CPB;
+    constexpr int CPB = Sh::CPB, THREADS = Sh::THREADS;
 
     if (io.skip != nullptr && *io.skip) return;  // uniform over the grid
 
-    __shared__ T s_u[CPB][C * NNN];      // the cell's nodal values
-    __shared__ T s_w[CPB][2 * C * NNN];  // work space of the cell and face passes
-    __shared__ T s_geo[CPB][2][8][3];    // own / neighbour trilinear coefficients
+    __shared__ T s_u[CPB][Sh::U];      // the cell's nodal values
+    __shared__ T s_w[CPB][Sh::W];      // work space of the cell and face passes
+    __shared__ T s_geo[CPB][2][8][3];  // own / neighbour trilinear coefficients
+    __shared__ LaneTab<T, N> s_lt;
 
-    const int lc = threadIdx.x / NN;
-    const int t = threadIdx.x - lc * NN;
-    const int i1 = t % N, i2 = t / N;
-    const int e = xcd_block(blockIdx.x, gridDim.x) * CPB + lc;
-    const bool active = e < op.ncell;
-    const int ec = active ? e : 0;
-    const int ex = ec % op.nx, ey = (ec / op.nx) % op.ny, ez = ec / (op.nx * op.ny);
+    CellIdx ci;
+    ci.lc = threadIdx.x / NN;
+    ci.t = threadIdx.x - ci.lc * NN;
+    ci.i1 = ci.t % N;
+    ci.i2 = ci.t / N;
+    const int e = xcd_block(blockIdx.x, gridDim.x) * CPB + ci.lc;
+    ci.active = e < op.ncell;
+    ci.ec = ci.active ? e : 0;
+    ci.ex = ci.ec % op.nx;
+    ci.ey = (ci.ec / op.nx) % op.ny;
+    ci.ez = ci.ec / (op.nx * op.ny);
+    const int lc = ci.lc, t = ci.t, i1 = ci.i1, i2 = ci.i2;
     const auto& tb = op.tab;
-    const int parts = io.parts;
+    T* su = s_u[lc];
+    T* sw = s_w[lc];
+    // thread t as a line: (la, lb) = (i2, i3) for xi_1 sweeps, (i1, i3) for xi_2 sweeps
+    const int la = t % N, lb = t / N;
 
-    // ------------------------------------------------------------ load
-    const T* xe = io.x + (size_t)ec * (C * NNN);
-    T ucol[C][N];
+    if (threadIdx.x < N) {
+        const int j = threadIdx.x;
+        s_lt.x[j] = tb.x[j];
+        s_lt.w[j] = tb.w[j];
+        s_lt.S[0][j] = tb.S[0][j];
+        s_lt.S[1][j] = tb.S[1][j];
+        s_lt.G[0][j] = tb.G[0][j];
+        s_lt.G[1][j] = tb.G[1][j];
+    }
+
+    // ------------------------------------------------------------ load; xi_3 derivative of the own line
+    T g3[C][N];
+    {
+        const T* xe = io.x + (size_t)ci.ec * (C * NNN);
 #pragma unroll
-    for (int c = 0; c < C; ++c)
+        for (int c = 0; c < C; ++c) {
+            T col[N];
 #pragma unroll
-        for (int j = 0; j < N; ++j) {
-            ucol[c][j] = active ? xe[(c * N + j) * NN + t] : T(0);
-            s_u[lc][c * NNN + j * NN + t] = ucol[c][j];
+            for (int j = 0; j < N; ++j) {
+                col[j] = ci.active ? xe[(c * N + j) * NN + t] : T(0);
+                su[c * NNN + j * NN + t] = col[j];
+            }
+#pragma unroll
+            for (int q = 0; q < N; ++q) {
+                T a = 0;
+#pragma unroll
+                for (int j = 0; j < N; ++j) a += tb.D[q][j] * col[j];
+                g3[c][q] = a;
+            }
         }
+    }
     if constexpr (CURVED) {
         if (t < 3) {
             T g[8];
-            trilinear_coeffs(op.verts, op.nx, op.ny, ex, ey, ez, t, g);
+            trilinear_coeffs(op.verts, op.nx, op.ny, ci.ex, ci.ey, ci.ez, t, g);
 #pragma unroll
             for (int k = 0; k < 8; ++k) s_geo[lc][0][k][t] = g[k];
         }
     }
     __syncthreads();
+    const LaneTab<T, N>& lt = s_lt;
 
     T y[C][N];
 #pragma unroll
@@ -85,44 +499,58 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS))
         for (int j = 0; j < N; ++j) y[c][j] = T(0);
 
     // ------------------------------------------------------------ cell
-    if (parts & SIPG_PART_CELL) {
-        T f3[C][N];
+    if (io.parts & SIPG_PART_CELL) {
+        T* W1 = sw;            // [C][NNN] d/dxi_1, then B^_1
+        T* W2 = sw + C * NNN;  // [C][NNN] d/dxi_2, then B^_2
+        // forward sweeps along xi_1 and xi_2
 #pragma unroll
-        for (int q3 = 0; q3 < N; ++q3) {
-            T gr[C][3];
+        for (int c = 0; c < C; ++c) {
+            T v[N], w[N];
 #pragma unroll
-            for (int c = 0; c < C; ++c) {
-                T g1 = 0, g2 = 0, g3 = 0;
+            for (int j = 0; j < N; ++j) {
+                v[j] = su[c * NNN + lb * NN + la * N + j];
+                w[j] = su[c * NNN + lb * NN + j * N + la];
+            }
+#pragma unroll
+            for (int q = 0; q < N; ++q) {
+                T a = 0, b = 0;
 #pragma unroll
                 for (int j = 0; j < N; ++j) {
-                    g1 += tb.D[i1][j] * s_u[lc][c * NNN + q3 * NN + i2 * N + j];
-                    g2 += tb.D[i2][j] * s_u[lc][c * NNN + q3 * NN + j * N + i1];
-                    g3 += tb.D[q3][j] * ucol[c][j];
+                    a += tb.D[q][j] * v[j];
+                    b += tb.D[q][j] * w[j];
                 }
-                gr[c][0] = g1; gr[c][1] = g2; gr[c][2] = g3;
+                W1[c * NNN + lb * NN + la * N + q] = a;
+                W2[c * NNN + lb * NN + q * N + la] = b;
             }
+        }
+        stage_sync<THREADS>();
+        // pointwise, on the own xi_3 line of quadrature points
+#pragma unroll
+        for (int q3 = 0; q3 < N; ++q3) {
             T Ji[3][3], JxW;
             if constexpr (CURVED) {
-                T det;
-                jacobian_inverse(s_geo[lc][0], tb.x[i1], tb.x[i2], tb.x[q3], Ji, det);
-                JxW = det * (tb.w[i1] * tb.w[i2] * tb.w[q3]);
+                const T xi[3] = {lt.x[i1], lt.x[i2], tb.x[q3]};
+                T a[3][3], det;
+                jac_columns(s_geo[lc][0], xi, a);
+                inverse_from_columns(a, Ji, det);
+                JxW = det * (lt.w[i1] * lt.w[i2] * tb.w[q3]);
             } else {
 #pragma unroll
                 for (int a = 0; a < 3; ++a)
 #pragma unroll
                     for (int b = 0; b < 3; ++b) Ji[a][b] = a == b ? T(1) / op.h[a] : T(0);
-                JxW = op.h[0] * op.h[1] * op.h[2] * (tb.w[i1] * tb.w[i2] * tb.w[q3]);
+                JxW = op.h[0] * op.h[1] * op.h[2] * (lt.w[i1] * lt.w[i2] * tb.w[q3]);
             }
-            // physical gradient G[c][i] = sum_d gr[c][d] Ji[d][i]
             T G[C][3];
 #pragma unroll
-            for (int c = 0; c < C; ++c)
+            for (int c = 0; c < C; ++c) {
+                const T g1 = W1[c * NNN + q3 * NN + t], g2 = W2[c * NNN + q3 * NN + t], gg3 = g3[c][q3];
 #pragma unroll
-                for (int i = 0; i < 3; ++i)
-                    G[c][i] = gr[c][0] * Ji[0][i] + gr[c][1] * Ji[1][i] + gr[c][2] * Ji[2][i];
+                for (int i = 0; i < 3; ++i) G[c][i] = g1 * Ji[0][i] + g2 * Ji[1][i] + gg3 * Ji[2][i];
+            }
             T S[C][3];
             if constexpr (C == 3) {
-                const T mu = active ? op.mu_cell[(size_t)ec * NNN + q3 * NN + t] : T(0);
+                const T mu = ci.active ? op.mu_cell[(size_t)ci.ec * NNN + q3 * NN + t] : T(0);
                 const T f = mu * JxW;  // 2 mu eps = mu (G + G^T)
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
@@ -132,252 +560,68 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS))
 #pragma unroll
                 for (int i = 0; i < 3; ++i) S[0][i] = JxW * G[0][i];
             }
+            const T mass = op.alpha * JxW;
 #pragma unroll
             for (int c = 0; c < C; ++c) {
-                T Bh[3];
-#pragma unroll
-                for (int d = 0; d < 3; ++d)
-                    Bh[d] = Ji[d][0] * S[c][0] + Ji[d][1] * S[c][1] + Ji[d][2] * S[c][2];
-                s_w[lc][(2 * c) * NNN + q3 * NN + t] = Bh[0];
-                s_w[lc][(2 * c + 1) * NNN + q3 * NN + t] = Bh[1];
-                f3[c][q3] = Bh[2];
-                y[c][q3] = op.alpha * JxW * ucol[c][q3];
+                W1[c * NNN + q3 * NN + t] = Ji[0][0] * S[c][0] + Ji[0][1] * S[c][1] + Ji[0][2] * S[c][2];
+                W2[c * NNN + q3 * NN + t] = Ji[1][0] * S[c][0] + Ji[1][1] * S[c][1] + Ji[1][2] * S[c][2];
+                g3[c][q3] = Ji[2][0] * S[c][0] + Ji[2][1] * S[c][1] + Ji[2][2] * S[c][2];
+                y[c][q3] = mass * su[c * NNN + q3 * NN + t];
             }
         }
-        __syncthreads();
+        stage_sync<THREADS>();
+        // transposed sweeps, in place on the lines (each line is read and written by one thread)
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            T v[N], w[N];
+#pragma unroll
+            for (int q = 0; q < N; ++q) {
+                v[q] = W1[c * NNN + lb * NN + la * N + q];
+                w[q] = W2[c * NNN + lb * NN + q * N + la];
+            }
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                T a = 0, b = 0;
+#pragma unroll
+                for (int q = 0; q < N; ++q) {
+                    a += tb.D[q][j] * v[q];
+                    b += tb.D[q][j] * w[q];
+                }
+                W1[c * NNN + lb * NN + la * N + j] = a;
+                W2[c * NNN + lb * NN + j * N + la] = b;
+            }
+        }
 #pragma unroll
         for (int c = 0; c < C; ++c)
 #pragma unroll
             for (int i3 = 0; i3 < N; ++i3) {
                 T acc = y[c][i3];
 #pragma unroll
-                for (int q = 0; q < N; ++q) {
-                    acc += tb.D[q][i1] * s_w[lc][(2 * c) * NNN + i3 * NN + i2 * N + q];
-                    acc += tb.D[q][i2] * s_w[lc][(2 * c + 1) * NNN + i3 * NN + q * N + i1];
-                    acc += tb.D[q][i3] * f3[c][q];
-                }
+                for (int q = 0; q < N; ++q) acc += tb.D[q][i3] * g3[c][q];
                 y[c][i3] = acc;
             }
-        __syncthreads();
+        stage_sync<THREADS>();
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int i3 = 0; i3 < N; ++i3) y[c][i3] += W1[c * NNN + i3 * NN + t] + W2[c * NNN + i3 * NN + t];
+        stage_sync<THREADS>();
     }
 
     // ------------------------------------------------------------ faces
-    if (parts & (SIPG_PART_INTERIOR | SIPG_PART_BOUNDARY)) {
-        T* FO = &s_w[lc][0];          // own trace values      [C][NN]
-        T* FN = &s_w[lc][C * NN];     // neighbour trace values [C][NN]
-        T* VV = &s_w[lc][2 * C * NN]; // value coefficients     [C][NN]
-        T* VN = &s_w[lc][3 * C * NN]; // normal coefficients    [C][NN]
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-#pragma unroll
-            for (int s = 0; s < 2; ++s) {
-                const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
-                const int pos = d == 0 ? ex : d == 1 ? ey : ez;
-                const int lim = d == 0 ? op.nx : d == 1 ? op.ny : op.nz;
-                const bool has_nb = s == 1 ? pos + 1 < lim : pos > 0;
-                const int en = ec + (s == 1 ? 1 : -1) * (d == 0 ? 1 : d == 1 ? op.nx : op.nx * op.ny);
-                const bool dir = !has_nb && op.bc[2 * d + s] == 0;
-                const bool live = active && (has_nb ? (parts & SIPG_PART_INTERIOR) != 0
-                                                    : (dir && (parts & SIPG_PART_BOUNDARY) != 0));
-                int fid;
-                if (d == 0) fid = (ez * op.ny + ey) * (op.nx + 1) + ex + s;
-                else if (d == 1) fid = op.nfx + (ez * (op.ny + 1) + ey + s) * op.nx + ex;
-                else fid = op.nfx + op.nfy + ((ez + s) * op.ny + ey) * op.nx + ex;
-
-                // traces at face point (a, b) = (i1, i2): value and d/dxi_d
-                T uo[C], uno[C], un[C], unn[C];
-                const T* xn = io.x + (size_t)(has_nb ? en : ec) * (C * NNN);
-#pragma unroll
-                for (int c = 0; c < C; ++c) {
-                    T v0 = 0, v1 = 0, w0 = 0, w1 = 0;
-#pragma unroll
-                    for (int j = 0; j < N; ++j) {
-                        T own;
-                        if (d == 2) own = ucol[c][j];
-                        else if (d == 0) own = s_u[lc][c * NNN + i2 * NN + i1 * N + j];
-                        else own = s_u[lc][c * NNN + i2 * NN + j * N + i1];
-                        v0 += tb.S[s][j] * own;
-                        v1 += tb.G[s][j] * own;
-                        if (live && has_nb) {
-                            T nb;
-                            if (d == 2) nb = xn[(c * N + j) * NN + i2 * N + i1];
-                            else if (d == 0) nb = xn[(c * N + i2) * NN + i1 * N + j];
-                            else nb = xn[(c * N + i2) * NN + j * N + i1];
-                            w0 += tb.S[1 - s][j] * nb;
-                            w1 += tb.G[1 - s][j] * nb;
-                        }
-                    }
-                    uo[c] = v0; uno[c] = v1; un[c] = w0; unn[c] = w1;
-                    FO[c * NN + t] = v0;
-                    FN[c * NN + t] = w0;
-                }
-                if constexpr (CURVED) {
-                    if (t < 3 && has_nb && active) {
-                        const int nex = en % op.nx, ney = (en / op.nx) % op.ny, nez = en / (op.nx * op.ny);
-                        T g[8];
-                        trilinear_coeffs(op.verts, op.nx, op.ny, nex, ney, nez, t, g);
-#pragma unroll
-                        for (int k = 0; k < 8; ++k) s_geo[lc][1][k][t] = g[k];
-                    }
-                }
-                __syncthreads();
-
-                // reference gradients (order xi_1, xi_2, xi_3)
-                T gro[C][3], grn[C][3];
-#pragma unroll
-                for (int c = 0; c < C; ++c) {
-                    T ta = 0, tbv = 0, na = 0, nbv = 0;
-#pragma unroll
-                    for (int j = 0; j < N; ++j) {
-                        ta += tb.D[i1][j] * FO[c * NN + i2 * N + j];
-                        tbv += tb.D[i2][j] * FO[c * NN + j * N + i1];
-                        na += tb.D[i1][j] * FN[c * NN + i2 * N + j];
-                        nbv += tb.D[i2][j] * FN[c * NN + j * N + i1];
-                    }
-                    gro[c][t1] = ta; gro[c][t2] = tbv; gro[c][d] = uno[c];
-                    grn[c][t1] = na; grn[c][t2] = nbv; grn[c][d] = unn[c];
-                }
-                // geometry on the face
-                T xi[3];
-                xi[t1] = tb.x[i1]; xi[t2] = tb.x[i2]; xi[d] = T(s);
-                T Jo[3][3], Jn[3][3], nrm[3], ds;
-                const T sgn = s == 1 ? T(1) : T(-1);
-                if constexpr (CURVED) {
-                    T deto, detn;
-                    jacobian_inverse(s_geo[lc][0], xi[0], xi[1], xi[2], Jo, deto);
-                    T xin[3] = {xi[0], xi[1], xi[2]};
-                    xin[d] = T(1 - s);
-                    if (has_nb) jacobian_inverse(s_geo[lc][1], xin[0], xin[1], xin[2], Jn, detn);
-                    else {
-#pragma unroll
-                        for (int a = 0; a < 3; ++a)
-#pragma unroll
-                            for (int b = 0; b < 3; ++b) Jn[a][b] = Jo[a][b];
-                    }
-                    const T v0 = Jo[d][0], v1 = Jo[d][1], v2 = Jo[d][2];
-                    const T nv = sqrt(v0 * v0 + v1 * v1 + v2 * v2);
-                    nrm[0] = sgn * v0 / nv; nrm[1] = sgn * v1 / nv; nrm[2] = sgn * v2 / nv;
-                    ds = deto * nv * (tb.w[i1] * tb.w[i2]);
-                } else {
-#pragma unroll
-                    for (int a = 0; a < 3; ++a)
-#pragma unroll
-                        for (int b = 0; b < 3; ++b) {
-                            Jo[a][b] = a == b ? T(1) / op.h[a] : T(0);
-                            Jn[a][b] = Jo[a][b];
-                        }
-                    nrm[0] = nrm[1] = nrm[2] = T(0);
-                    nrm[d] = sgn;
-                    ds = op.h[t1] * op.h[t2] * (tb.w[i1] * tb.w[i2]);
-                }
-                T Go[C][3], Gn[C][3];
-#pragma unroll
-                for (int c = 0; c < C; ++c)
-#pragma unroll
-                    for (int i = 0; i < 3; ++i) {
-                        Go[c][i] = gro[c][0] * Jo[0][i] + gro[c][1] * Jo[1][i] + gro[c][2] * Jo[2][i];
-                        Gn[c][i] = grn[c][0] * Jn[0][i] + grn[c][1] * Jn[1][i] + grn[c][2] * Jn[2][i];
-                    }
-                if (!has_nb) {  // mirror principle, Dirichlet: u+ = -u-, grad u+ = grad u-
-#pragma unroll
-                    for (int c = 0; c < C; ++c) {
-                        un[c] = -uo[c];
-#pragma unroll
-                        for (int i = 0; i < 3; ++i) Gn[c][i] = Go[c][i];
-                    }
-                }
-                const T mu = (C == 3 && live) ? op.mu_face[(size_t)fid * NN + t] : T(1);
-                const T tau = live ? op.tfac[fid] * mu : T(0);
-                T av[C], Bh[C][3];
-                T ju[C];
-#pragma unroll
-                for (int c = 0; c < C; ++c) ju[c] = uo[c] - un[c];
-                if constexpr (C == 3) {
-                    const T jn = ju[0] * nrm[0] + ju[1] * nrm[1] + ju[2] * nrm[2];
-                    T B[3][3];
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        T en_ = 0;  // (eps(u-) + eps(u+)) n, times 1/2 twice folded below
-#pragma unroll
-                        for (int i = 0; i < 3; ++i)
-                            en_ += (Go[c][i] + Go[i][c] + Gn[c][i] + Gn[i][c]) * nrm[i];
-                        // -2 {{mu eps}} n = -2 * mu/2 * (eps- + eps+) n = -mu/2 * (G + G^T)- + ...) n
-                        av[c] = -T(0.5) * mu * en_ + tau * (ju[c] + nrm[c] * jn);
-#pragma unroll
-                        for (int i = 0; i < 3; ++i) B[c][i] = -T(0.5) * mu * (ju[c] * nrm[i] + nrm[c] * ju[i]);
-                    }
-#pragma unroll
-                    for (int c = 0; c < 3; ++c)
-#pragma unroll
-                        for (int dd = 0; dd < 3; ++dd)
-                            Bh[c][dd] = ds * (Jo[dd][0] * B[c][0] + Jo[dd][1] * B[c][1] + Jo[dd][2] * B[c][2]);
-                } else {
-                    const T gn = (Go[0][0] + Gn[0][0]) * nrm[0] + (Go[0][1] + Gn[0][1]) * nrm[1] +
-                                 (Go[0][2] + Gn[0][2]) * nrm[2];
-                    av[0] = -T(0.5) * gn + tau * ju[0];
-                    T B[3];
-#pragma unroll
-                    for (int i = 0; i < 3; ++i) B[i] = -T(0.5) * ju[0] * nrm[i];
-#pragma unroll
-                    for (int dd = 0; dd < 3; ++dd)
-                        Bh[0][dd] = ds * (Jo[dd][0] * B[0] + Jo[dd][1] * B[1] + Jo[dd][2] * B[2]);
-                }
-#pragma unroll
-                for (int c = 0; c < C; ++c) {
-                    av[c] = live ? av[c] * ds : T(0);
-#pragma unroll
-                    for (int dd = 0; dd < 3; ++dd) Bh[c][dd] = live ? Bh[c][dd] : T(0);
-                }
-                __syncthreads();  // all reads of FO/FN done
-#pragma unroll
-                for (int c = 0; c < C; ++c) {
-                    FO[c * NN + t] = Bh[c][t1];
-                    FN[c * NN + t] = Bh[c][t2];
-                }
-                __syncthreads();
-                T vv[C], vn[C];
-#pragma unroll
-                for (int c = 0; c < C; ++c) {
-                    T acc = av[c];
-#pragma unroll
-                    for (int q = 0; q < N; ++q) {
-                        acc += tb.D[q][i1] * FO[c * NN + i2 * N + q];
-                        acc += tb.D[q][i2] * FN[c * NN + q * N + i1];
-                    }
-                    vv[c] = acc;
-                    vn[c] = Bh[c][d];
-                }
-                if (d == 2) {
-#pragma unroll
-                    for (int c = 0; c < C; ++c)
-#pragma unroll
-                        for (int i3 = 0; i3 < N; ++i3) y[c][i3] += tb.S[s][i3] * vv[c] + tb.G[s][i3] * vn[c];
-                } else {
-#pragma unroll
-                    for (int c = 0; c < C; ++c) {
-                        VV[c * NN + t] = vv[c];
-                        VN[c * NN + t] = vn[c];
-                    }
-                    __syncthreads();
-#pragma unroll
-                    for (int c = 0; c < C; ++c)
-#pragma unroll
-                        for (int i3 = 0; i3 < N; ++i3) {
-                            // node (i1, i2, i3): d == 0 -> face point (i2, i3), normal index i1
-                            //                    d == 1 -> face point (i1, i3), normal index i2
-                            const int fp = d == 0 ? i3 * N + i2 : i3 * N + i1;
-                            const int ni = d == 0 ? i1 : i2;
-                            y[c][i3] += tb.S[s][ni] * VV[c * NN + fp] + tb.G[s][ni] * VN[c * NN + fp];
-                        }
-                }
-                __syncthreads();
-            }
+    if (io.parts & (SIPG_PART_INTERIOR | SIPG_PART_BOUNDARY)) {
+#pragma unroll 1
+        for (int f = 0; f < 6; ++f) {
+            const int s = f & 1;
+            if (f < 2) face_pass<N, C, T, CURVED, 0, THREADS>(op, io, ci, s, y, su, sw, s_geo[lc], lt);
+            else if (f < 4) face_pass<N, C, T, CURVED, 1, THREADS>(op, io, ci, s, y, su, sw, s_geo[lc], lt);
+            else face_pass<N, C, T, CURVED, 2, THREADS>(op, io, ci, s, y, su, sw, s_geo[lc], lt);
         }
     }
 
     // ------------------------------------------------------------ store
-    if (!active) return;
-    const size_t base = (size_t)ec * (C * NNN);
+    if (!ci.active) return;
+    const size_t base = (size_t)ci.ec * (C * NNN);
     if constexpr (MODE == MODE_APPLY) {
 #pragma unroll
         for (int c = 0; c < C; ++c)
@@ -392,7 +636,7 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS))
                 const size_t idx = base + (c * N + j) * NN + t;
                 const T dn = c1 * io.d[idx] + c2 * io.dinv[idx] * (io.r[idx] - y[c][j]);
                 io.d[idx] = dn;
-                io.y[idx] = ucol[c][j] + dn;
+                io.y[idx] = su[c * NNN + j * NN + t] + dn;
             }
     }
 }
