@@ -159,6 +159,7 @@ OpData<T> sipg_plan::opdata() const {
     for (int i = 0; i < 6; ++i) o.bc[i] = bc[i];
     o.alpha = T(alpha);
     o.h[0] = T(1.0 / nx); o.h[1] = T(1.0 / ny); o.h[2] = T(1.0 / nz);
+    o.hinv[0] = T(nx); o.hinv[1] = T(ny); o.hinv[2] = T(nz);
     if constexpr (sizeof(T) == 8) {
         o.verts = curved ? verts64_d : nullptr;
         o.mu_cell = mu_cell64; o.mu_face = mu_face64; o.tfac = tfac64;

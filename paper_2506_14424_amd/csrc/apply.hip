@@ -73,6 +73,21 @@ __device__ __forceinline__ T recip(T d) {
     }
 }
 
+// 1/sqrt(v): hardware estimate refined by Newton steps to full precision.
+template <typename T>
+__device__ __forceinline__ T rsqrt_nr(T v) {
+    if constexpr (sizeof(T) == 8) {
+        double r = __builtin_amdgcn_rsq(v);
+        double h = 0.5 * v;
+        r = r * __builtin_fma(-h * r, r, 1.5);
+        r = r * __builtin_fma(-h * r, r, 1.5);
+        return r;
+    } else {
+        float r = __builtin_amdgcn_rsqf(v);
+        return r * __builtin_fmaf(-0.5f * v * r, r, 1.5f);
+    }
+}
+
 // Columns a_d = d x / d xi_d of the Jacobian of a trilinear cell at xi.
 template <typename T>
 __device__ __forceinline__ void jac_columns(const T (*g)[3], const T xi[3], T a[3][3]) {
@@ -119,6 +134,41 @@ struct LaneTab {
     T x[N], w[N], S[2][N], G[2][N];
 };
 
+// The neighbour's line of nodal values through face point (i1, i2) of face
+// (D, s), and the face viscosity and penalty factor at that point.
+template <int N, int C, typename T, int D>
+__device__ __forceinline__ void face_prefetch(const OpData<T>& op, const ApplyIO<T>& io, const CellIdx& ci, int s,
+                                              T (&nb)[C][N], T& mu, T& tf) {
+    constexpr int NN = N * N, NNN = N * N * N;
+    const int i1 = ci.i1, i2 = ci.i2;
+    const int pos = D == 0 ? ci.ex : D == 1 ? ci.ey : ci.ez;
+    const int lim = D == 0 ? op.nx : D == 1 ? op.ny : op.nz;
+    const bool has_nb = s == 1 ? pos + 1 < lim : pos > 0;
+    const int stride = D == 0 ? 1 : D == 1 ? op.nx : op.nx * op.ny;
+    const int en = has_nb ? ci.ec + (s == 1 ? stride : -stride) : ci.ec;
+    const bool dir = !has_nb && op.bc[2 * D + s] == 0;
+    const bool live = ci.active && (has_nb ? (io.parts & SIPG_PART_INTERIOR) != 0
+                                           : (dir && (io.parts & SIPG_PART_BOUNDARY) != 0));
+    int fid;
+    if (D == 0) fid = (ci.ez * op.ny + ci.ey) * (op.nx + 1) + ci.ex + s;
+    else if (D == 1) fid = op.nfx + (ci.ez * (op.ny + 1) + ci.ey + s) * op.nx + ci.ex;
+    else fid = op.nfx + op.nfy + ((ci.ez + s) * op.ny + ci.ey) * op.nx + ci.ex;
+    const T* xn = io.x + (size_t)en * (C * NNN);
+    const bool ld = live && has_nb;
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            int off;
+            if (D == 2) off = (c * N + j) * NN + i2 * N + i1;
+            else if (D == 0) off = (c * N + i2) * NN + i1 * N + j;
+            else off = (c * N + i2) * NN + j * N + i1;
+            nb[c][j] = ld ? xn[off] : T(0);
+        }
+    mu = (C == 3 && live) ? op.mu_face[(size_t)fid * NN + ci.t] : T(1);
+    tf = live ? op.tfac[fid] : T(0);
+}
+
 // ---------------------------------------------------------------- faces
 //
 // One face of the cell (direction D, side s), in stages separated by LDS
@@ -133,6 +183,8 @@ template <int N, int C, typename T, bool CURVED, int D, int THREADS>
 __device__ __forceinline__ void face_pass(const OpData<T>& op, const ApplyIO<T>& io, const CellIdx& ci, int s,
                                           T (&y)[C][N], const T* su, T* sw, T (*geo)[8][3],
                                           const LaneTab<T, N>& lt) {
+    T nbl[C][N], mu_pre, tf_pre;
+    face_prefetch<N, C, T, D>(op, io, ci, s, nbl, mu_pre, tf_pre);
     constexpr int NN = N * N, NNN = N * N * N;
     constexpr int t1 = D == 0 ? 1 : 0, t2 = D == 2 ? 1 : 2;
     const auto& tb = op.tab;
@@ -157,33 +209,26 @@ __device__ __forceinline__ void face_pass(const OpData<T>& op, const ApplyIO<T>&
     T* VV = sw + 6 * C * NN;  // [2] value / normal coefficients (D < 2)    C2
 
     // ---- A: traces
-    T uo[C], uno[C], un[C], unn[C];
-    {
-        const T* xn = io.x + (size_t)en * (C * NNN);
+    T ju[C], uno[C], unn[C];  // jump u_own - u_nbr (mirror state on Dirichlet faces), normal derivatives
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-            T v0 = 0, v1 = 0, w0 = 0, w1 = 0;
+    for (int c = 0; c < C; ++c) {
+        T v0 = 0, v1 = 0, w0 = 0, w1 = 0;
 #pragma unroll
-            for (int j = 0; j < N; ++j) {
-                T own;
-                if (D == 2) own = su[c * NNN + j * NN + i2 * N + i1];
-                else if (D == 0) own = su[c * NNN + i2 * NN + i1 * N + j];
-                else own = su[c * NNN + i2 * NN + j * N + i1];
-                v0 += tb.S[s][j] * own;
-                v1 += tb.G[s][j] * own;
-                T nb = 0;
-                if (live && has_nb) {
-                    if (D == 2) nb = xn[(c * N + j) * NN + i2 * N + i1];
-                    else if (D == 0) nb = xn[(c * N + i2) * NN + i1 * N + j];
-                    else nb = xn[(c * N + i2) * NN + j * N + i1];
-                }
-                w0 += tb.S[1 - s][j] * nb;
-                w1 += tb.G[1 - s][j] * nb;
-            }
-            uo[c] = v0; uno[c] = v1; un[c] = w0; unn[c] = w1;
-            FT[c * NN + t] = v0;
-            FT[(C + c) * NN + t] = w0;
+        for (int j = 0; j < N; ++j) {
+            T own;
+            if (D == 2) own = su[c * NNN + j * NN + i2 * N + i1];
+            else if (D == 0) own = su[c * NNN + i2 * NN + i1 * N + j];
+            else own = su[c * NNN + i2 * NN + j * N + i1];
+            v0 += tb.S[s][j] * own;
+            v1 += tb.G[s][j] * own;
+            w0 += tb.S[1 - s][j] * nbl[c][j];
+            w1 += tb.G[1 - s][j] * nbl[c][j];
         }
+        ju[c] = has_nb ? v0 - w0 : T(2) * v0;
+        uno[c] = v1;
+        unn[c] = w1;
+        FT[c * NN + t] = v0;
+        FT[(C + c) * NN + t] = w0;
     }
     if constexpr (CURVED) {
         if (t < 3 && has_nb && ci.active) {
@@ -225,33 +270,41 @@ __device__ __forceinline__ void face_pass(const OpData<T>& op, const ApplyIO<T>&
     xi[t1] = lt.x[i1];
     xi[t2] = lt.x[i2];
     xi[D] = T(s);
-    T Jo[3][3], nrm[3], ds;
-    T acol[3][3];  // Jacobian columns; the tangential ones are shared with the neighbour
     const T sgn = s == 1 ? T(1) : T(-1);
-    if constexpr (CURVED) {
-        jac_columns(geo[0], xi, acol);
-        T det;
-        inverse_from_columns(acol, Jo, det);
-        // row D of J^-1 is (a_t1 x a_t2) / det: n = sign row/|row|, ds = det |row| w_a w_b
-        const T v0 = Jo[D][0], v1 = Jo[D][1], v2 = Jo[D][2];
-        const T nv2 = v0 * v0 + v1 * v1 + v2 * v2;
-        const T rinv = T(1) / sqrt(nv2);
-        nrm[0] = sgn * v0 * rinv; nrm[1] = sgn * v1 * rinv; nrm[2] = sgn * v2 * rinv;
-        ds = det * (nv2 * rinv) * (lt.w[i1] * lt.w[i2]);
-    } else {
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int b = 0; b < 3; ++b) Jo[a][b] = a == b ? T(1) / op.h[a] : T(0);
-        nrm[0] = nrm[1] = nrm[2] = T(0);
-        nrm[D] = sgn;
-        ds = op.h[t1] * op.h[t2] * (lt.w[i1] * lt.w[i2]);
-    }
-    T mo[3];  // m = J^-1 n:  (grad u) n = gr . m for the reference gradient gr
-#pragma unroll
-    for (int d = 0; d < 3; ++d) mo[d] = Jo[d][0] * nrm[0] + Jo[d][1] * nrm[1] + Jo[d][2] * nrm[2];
-    T en_[C];  // viscous: (G + G^T) n summed over both sides; poisson: (G- + G+) . n
+    T nrm[3], ds, mo[3], p[3], en_[C];
+    T at1[3], at2[3];  // tangential Jacobian columns, shared with the neighbour
     {
+        T Jo[3][3];
+        if constexpr (CURVED) {
+            T a[3][3], det;
+            jac_columns(geo[0], xi, a);
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                at1[i] = a[t1][i];
+                at2[i] = a[t2][i];
+            }
+            inverse_from_columns(a, Jo, det);
+            // row D of J^-1 is (a_t1 x a_t2)/det: n = sign row/|row|, ds = det |row| w_a w_b
+            const T v0 = Jo[D][0], v1 = Jo[D][1], v2 = Jo[D][2];
+            const T nv2 = v0 * v0 + v1 * v1 + v2 * v2;
+            const T rinv = rsqrt_nr(nv2);
+            nrm[0] = sgn * v0 * rinv; nrm[1] = sgn * v1 * rinv; nrm[2] = sgn * v2 * rinv;
+            ds = det * (nv2 * rinv) * (lt.w[i1] * lt.w[i2]);
+        } else {
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) Jo[a][b] = a == b ? op.hinv[a] : T(0);
+            nrm[0] = nrm[1] = nrm[2] = T(0);
+            nrm[D] = sgn;
+            ds = op.h[t1] * op.h[t2] * (lt.w[i1] * lt.w[i2]);
+        }
+        // m = J^-1 n:  (grad u) n = gr . m for the reference gradient gr;  p = J^-1 [u]
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            mo[d] = Jo[d][0] * nrm[0] + Jo[d][1] * nrm[1] + Jo[d][2] * nrm[2];
+            if constexpr (C == 3) p[d] = Jo[d][0] * ju[0] + Jo[d][1] * ju[1] + Jo[d][2] * ju[2];
+        }
         T gr[C][3];
 #pragma unroll
         for (int c = 0; c < C; ++c) {
@@ -259,6 +312,8 @@ __device__ __forceinline__ void face_pass(const OpData<T>& op, const ApplyIO<T>&
             gr[c][t2] = TD[(1 * C + c) * NN + t];
             gr[c][D] = uno[c];
         }
+        // viscous: (G + G^T) n with G n = gr.m and (G^T n)_c = sum_d J^-1[d][c] (n . gr[:, d]);
+        // poisson: G . n
         if constexpr (C == 3) {
             T w[3];
 #pragma unroll
@@ -274,23 +329,26 @@ __device__ __forceinline__ void face_pass(const OpData<T>& op, const ApplyIO<T>&
     if (has_nb) {
         T Jn[3][3];
         if constexpr (CURVED) {
-            // the neighbour shares the tangential columns; only its xi_D column differs
+            // the neighbour's Jacobian differs from the own one only in the xi_D column
             T xin[3] = {xi[0], xi[1], xi[2]};
             xin[D] = T(1 - s);
-            T an[3][3];
-            jac_columns(geo[1], xin, an);
+            const T(*g)[3] = geo[1];
+            T a[3][3];
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                an[t1][i] = acol[t1][i];
-                an[t2][i] = acol[t2][i];
+                a[t1][i] = at1[i];
+                a[t2][i] = at2[i];
+                if (D == 0) a[0][i] = g[1][i] + g[4][i] * xin[1] + g[5][i] * xin[2] + g[7][i] * (xin[1] * xin[2]);
+                if (D == 1) a[1][i] = g[2][i] + g[4][i] * xin[0] + g[6][i] * xin[2] + g[7][i] * (xin[0] * xin[2]);
+                if (D == 2) a[2][i] = g[3][i] + g[5][i] * xin[0] + g[6][i] * xin[1] + g[7][i] * (xin[0] * xin[1]);
             }
             T detn;
-            inverse_from_columns(an, Jn, detn);
+            inverse_from_columns(a, Jn, detn);
         } else {
 #pragma unroll
             for (int a = 0; a < 3; ++a)
 #pragma unroll
-                for (int b = 0; b < 3; ++b) Jn[a][b] = Jo[a][b];
+                for (int b = 0; b < 3; ++b) Jn[a][b] = a == b ? op.hinv[a] : T(0);
         }
         T mn[3];
 #pragma unroll
@@ -314,27 +372,19 @@ __device__ __forceinline__ void face_pass(const OpData<T>& op, const ApplyIO<T>&
             en_[0] += gr[0][0] * mn[0] + gr[0][1] * mn[1] + gr[0][2] * mn[2];
         }
     } else {
-        // mirror principle on a Dirichlet face: u+ = -u-, grad u+ = grad u-
+        // mirror principle on a Dirichlet face: grad u+ = grad u- (u+ = -u- is in ju)
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-            en_[c] *= T(2);
-            un[c] = -uo[c];
-        }
+        for (int c = 0; c < C; ++c) en_[c] *= T(2);
     }
-    const T mu = (C == 3 && live) ? op.mu_face[(size_t)fid * NN + t] : T(1);
-    const T tau = live ? op.tfac[fid] * mu : T(0);
+    const T mu = (C == 3 && live) ? mu_pre : T(1);
+    const T tau = live ? tf_pre * mu : T(0);
     const T lf = live ? T(1) : T(0);
-    T ju[C];
-#pragma unroll
-    for (int c = 0; c < C; ++c) ju[c] = uo[c] - un[c];
+    (void)fid;
     T av[C], Bh[C][3];
     if constexpr (C == 3) {
         // a = -2 {{mu eps(u)}} n + tau ([u] + n([u].n)),  B = -mu sym([u] (x) n),
-        // B^ = J^-1 B:  B^[c][d] = -mu/2 (ju_c m_d + n_c p_d),  p = J^-1 ju
+        // B^ = J^-1 B:  B^[c][d] = -mu/2 (ju_c m_d + n_c p_d)
         const T jn = ju[0] * nrm[0] + ju[1] * nrm[1] + ju[2] * nrm[2];
-        T p[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) p[d] = Jo[d][0] * ju[0] + Jo[d][1] * ju[1] + Jo[d][2] * ju[2];
         const T dl = ds * lf;
         const T hm = -T(0.5) * mu * dl;
 #pragma unroll
@@ -419,7 +469,7 @@ __device__ __forceinline__ void face_pass(const OpData<T>& op, const ApplyIO<T>&
 // ---------------------------------------------------------------- kernel
 
 template <int N, int C, typename T, bool CURVED, int MODE>
-__global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS))
+__global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attribute__((amdgpu_waves_per_eu(2)))
     k_apply(const OpData<T> op, const ApplyIO<T> io) {
     using Sh = Shape<N, C, sizeof(T) == 8>;
     constexpr int NN = N * N, NNN = N * N * N;
@@ -524,21 +574,41 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS))
             }
         }
         stage_sync<THREADS>();
-        // pointwise, on the own xi_3 line of quadrature points
+        // pointwise, on the own xi_3 line of quadrature points.  Along that
+        // line the Jacobian columns of a trilinear cell are a_0 = A0 + B0 xi_3,
+        // a_1 = A1 + B1 xi_3 and a_2 constant.
+        T A0[3], B0[3], A1[3], B1[3], a2c[3];
+        if constexpr (CURVED) {
+            const T(*g)[3] = s_geo[lc][0];
+            const T x1 = lt.x[i1], x2 = lt.x[i2];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                A0[i] = g[1][i] + g[4][i] * x2;
+                B0[i] = g[5][i] + g[7][i] * x2;
+                A1[i] = g[2][i] + g[4][i] * x1;
+                B1[i] = g[6][i] + g[7][i] * x1;
+                a2c[i] = g[3][i] + g[5][i] * x1 + g[6][i] * x2 + g[7][i] * (x1 * x2);
+            }
+        }
 #pragma unroll
         for (int q3 = 0; q3 < N; ++q3) {
             T Ji[3][3], JxW;
             if constexpr (CURVED) {
-                const T xi[3] = {lt.x[i1], lt.x[i2], tb.x[q3]};
+                const T x3 = tb.x[q3];
                 T a[3][3], det;
-                jac_columns(s_geo[lc][0], xi, a);
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    a[0][i] = A0[i] + B0[i] * x3;
+                    a[1][i] = A1[i] + B1[i] * x3;
+                    a[2][i] = a2c[i];
+                }
                 inverse_from_columns(a, Ji, det);
                 JxW = det * (lt.w[i1] * lt.w[i2] * tb.w[q3]);
             } else {
 #pragma unroll
                 for (int a = 0; a < 3; ++a)
 #pragma unroll
-                    for (int b = 0; b < 3; ++b) Ji[a][b] = a == b ? T(1) / op.h[a] : T(0);
+                    for (int b = 0; b < 3; ++b) Ji[a][b] = a == b ? op.hinv[a] : T(0);
                 JxW = op.h[0] * op.h[1] * op.h[2] * (lt.w[i1] * lt.w[i2] * tb.w[q3]);
             }
             T G[C][3];

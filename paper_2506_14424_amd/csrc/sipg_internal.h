@@ -30,6 +30,7 @@ struct OpData {
     int bc[6];               // 0 = Dirichlet, 1 = Neumann, sides -x,+x,-y,+y,-z,+z
     T alpha;                 // mass factor gamma_0/dt
     T h[3];                  // straight cells: edge lengths
+    T hinv[3];               // and their inverses
     const T* verts;          // curved cells: vertex coordinates, else nullptr
     const T* mu_cell;        // [ncell][n^3]
     const T* mu_face;        // [nface][n^2]
