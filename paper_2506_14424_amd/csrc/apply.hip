@@ -38,10 +38,17 @@ struct Shape {
     static constexpr int CPB = N == 2 ? 16 : N == 3 ? 7 : N == 4 ? 4 : N == 5 ? 5 : (DBL && C == 3 ? 3 : 7);
     static constexpr int THREADS = CPB * N * N;
     static constexpr int NNN = N * N * N, NN = N * N;
+    // LDS layout of a cell's volume arrays: node (i1, i2, i3) of component c at
+    // c*CS + i3*S3 + i2*N + i1.  In FP32 the padded xi_3 stride S3 spreads the
+    // column, xi_1-line and xi_2-line access patterns of a cell's n*n lanes
+    // over the LDS banks (n = 4: at most 2-way conflicts instead of 4-way);
+    // in FP64 the extra LDS would cost a resident wavefront per SIMD.
+    static constexpr int S3 = DBL ? NN : (N == 3 ? 12 : N == 4 ? 19 : NN);
+    static constexpr int CS = N * S3;
     // per-cell LDS: nodal values and a work space for the cell sweeps and the
     // face stages; +1 staggers consecutive cells over the LDS banks
-    static constexpr int U = C * NNN + 1;
-    static constexpr int W = (2 * C * NNN > 8 * C * NN ? 2 * C * NNN : 8 * C * NN) + 1;
+    static constexpr int U = C * CS + 1;
+    static constexpr int W = (2 * C * CS > 8 * C * NN ? 2 * C * CS : 8 * C * NN) + 1;
 };
 
 // Barrier between LDS stages.  A workgroup of one wavefront only needs the
@@ -186,6 +193,7 @@ __device__ __forceinline__ void face_pass(const OpData<T>& op, const ApplyIO<T>&
     T nbl[C][N], mu_pre, tf_pre;
     face_prefetch<N, C, T, D>(op, io, ci, s, nbl, mu_pre, tf_pre);
     constexpr int NN = N * N, NNN = N * N * N;
+    constexpr int S3 = Shape<N, C, sizeof(T) == 8>::S3, CS = Shape<N, C, sizeof(T) == 8>::CS;
     constexpr int t1 = D == 0 ? 1 : 0, t2 = D == 2 ? 1 : 2;
     const auto& tb = op.tab;
     const int i1 = ci.i1, i2 = ci.i2, t = ci.t;
@@ -216,9 +224,9 @@ __device__ __forceinline__ void face_pass(const OpData<T>& op, const ApplyIO<T>&
 #pragma unroll
         for (int j = 0; j < N; ++j) {
             T own;
-            if (D == 2) own = su[c * NNN + j * NN + i2 * N + i1];
-            else if (D == 0) own = su[c * NNN + i2 * NN + i1 * N + j];
-            else own = su[c * NNN + i2 * NN + j * N + i1];
+            if (D == 2) own = su[c * CS + j * S3 + i2 * N + i1];
+            else if (D == 0) own = su[c * CS + i2 * S3 + i1 * N + j];
+            else own = su[c * CS + i2 * S3 + j * N + i1];
             v0 += tb.S[s][j] * own;
             v1 += tb.G[s][j] * own;
             w0 += tb.S[1 - s][j] * nbl[c][j];
@@ -474,6 +482,7 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
     using Sh = Shape<N, C, sizeof(T) == 8>;
     constexpr int NN = N * N, NNN = N * N * N;
     constexpr int CPB = Sh::CPB, THREADS = Sh::THREADS;
+    constexpr int S3 = Sh::S3, CS = Sh::CS;
 
     if (io.skip != nullptr && *io.skip) return;  // uniform over the grid
 
@@ -520,7 +529,7 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
 #pragma unroll
             for (int j = 0; j < N; ++j) {
                 col[j] = ci.active ? xe[(c * N + j) * NN + t] : T(0);
-                su[c * NNN + j * NN + t] = col[j];
+                su[c * CS + j * S3 + t] = col[j];
             }
 #pragma unroll
             for (int q = 0; q < N; ++q) {
@@ -551,15 +560,15 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
     // ------------------------------------------------------------ cell
     if (io.parts & SIPG_PART_CELL) {
         T* W1 = sw;            // [C][NNN] d/dxi_1, then B^_1
-        T* W2 = sw + C * NNN;  // [C][NNN] d/dxi_2, then B^_2
+        T* W2 = sw + C * CS;  // [C][NNN] d/dxi_2, then B^_2
         // forward sweeps along xi_1 and xi_2
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             T v[N], w[N];
 #pragma unroll
             for (int j = 0; j < N; ++j) {
-                v[j] = su[c * NNN + lb * NN + la * N + j];
-                w[j] = su[c * NNN + lb * NN + j * N + la];
+                v[j] = su[c * CS + lb * S3 + la * N + j];
+                w[j] = su[c * CS + lb * S3 + j * N + la];
             }
 #pragma unroll
             for (int q = 0; q < N; ++q) {
@@ -569,8 +578,8 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
                     a += tb.D[q][j] * v[j];
                     b += tb.D[q][j] * w[j];
                 }
-                W1[c * NNN + lb * NN + la * N + q] = a;
-                W2[c * NNN + lb * NN + q * N + la] = b;
+                W1[c * CS + lb * S3 + la * N + q] = a;
+                W2[c * CS + lb * S3 + q * N + la] = b;
             }
         }
         stage_sync<THREADS>();
@@ -614,7 +623,7 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
             T G[C][3];
 #pragma unroll
             for (int c = 0; c < C; ++c) {
-                const T g1 = W1[c * NNN + q3 * NN + t], g2 = W2[c * NNN + q3 * NN + t], gg3 = g3[c][q3];
+                const T g1 = W1[c * CS + q3 * S3 + t], g2 = W2[c * CS + q3 * S3 + t], gg3 = g3[c][q3];
 #pragma unroll
                 for (int i = 0; i < 3; ++i) G[c][i] = g1 * Ji[0][i] + g2 * Ji[1][i] + gg3 * Ji[2][i];
             }
@@ -633,10 +642,10 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
             const T mass = op.alpha * JxW;
 #pragma unroll
             for (int c = 0; c < C; ++c) {
-                W1[c * NNN + q3 * NN + t] = Ji[0][0] * S[c][0] + Ji[0][1] * S[c][1] + Ji[0][2] * S[c][2];
-                W2[c * NNN + q3 * NN + t] = Ji[1][0] * S[c][0] + Ji[1][1] * S[c][1] + Ji[1][2] * S[c][2];
+                W1[c * CS + q3 * S3 + t] = Ji[0][0] * S[c][0] + Ji[0][1] * S[c][1] + Ji[0][2] * S[c][2];
+                W2[c * CS + q3 * S3 + t] = Ji[1][0] * S[c][0] + Ji[1][1] * S[c][1] + Ji[1][2] * S[c][2];
                 g3[c][q3] = Ji[2][0] * S[c][0] + Ji[2][1] * S[c][1] + Ji[2][2] * S[c][2];
-                y[c][q3] = mass * su[c * NNN + q3 * NN + t];
+                y[c][q3] = mass * su[c * CS + q3 * S3 + t];
             }
         }
         stage_sync<THREADS>();
@@ -646,8 +655,8 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
             T v[N], w[N];
 #pragma unroll
             for (int q = 0; q < N; ++q) {
-                v[q] = W1[c * NNN + lb * NN + la * N + q];
-                w[q] = W2[c * NNN + lb * NN + q * N + la];
+                v[q] = W1[c * CS + lb * S3 + la * N + q];
+                w[q] = W2[c * CS + lb * S3 + q * N + la];
             }
 #pragma unroll
             for (int j = 0; j < N; ++j) {
@@ -657,8 +666,8 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
                     a += tb.D[q][j] * v[q];
                     b += tb.D[q][j] * w[q];
                 }
-                W1[c * NNN + lb * NN + la * N + j] = a;
-                W2[c * NNN + lb * NN + j * N + la] = b;
+                W1[c * CS + lb * S3 + la * N + j] = a;
+                W2[c * CS + lb * S3 + j * N + la] = b;
             }
         }
 #pragma unroll
@@ -674,7 +683,7 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
 #pragma unroll
         for (int c = 0; c < C; ++c)
 #pragma unroll
-            for (int i3 = 0; i3 < N; ++i3) y[c][i3] += W1[c * NNN + i3 * NN + t] + W2[c * NNN + i3 * NN + t];
+            for (int i3 = 0; i3 < N; ++i3) y[c][i3] += W1[c * CS + i3 * S3 + t] + W2[c * CS + i3 * S3 + t];
         stage_sync<THREADS>();
     }
 
@@ -706,7 +715,7 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
                 const size_t idx = base + (c * N + j) * NN + t;
                 const T dn = c1 * io.d[idx] + c2 * io.dinv[idx] * (io.r[idx] - y[c][j]);
                 io.d[idx] = dn;
-                io.y[idx] = su[c * NNN + j * NN + t] + dn;
+                io.y[idx] = su[c * CS + j * S3 + t] + dn;
             }
     }
 }
