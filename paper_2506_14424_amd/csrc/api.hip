@@ -198,7 +198,7 @@ Layout layout(const sipg_plan* P) {
     L.op_end = off;
     L.r = take(nd * 8); L.p = take(nd * 8); L.q = take(nd * 8); L.z = take(nd * 8); L.zo = take(nd * 8);
     L.cr = take(nd * 8); L.cd = take(nd * 8); L.cz0 = take(nd * 8); L.cz1 = take(nd * 8);
-    L.partials = take(2 * kRedBlocks * 8);
+    L.partials = take(kRedSlots * kRedBlocks * 8);
     L.st = take(sizeof(SolveState));
     L.total = off;
     return L;
@@ -242,20 +242,21 @@ sipg_status do_apply(sipg_plan* P, int parts, const void* x, void* y, hipStream_
     return SIPG_OK;
 }
 
-// z_out = Chebyshev-Jacobi(r) in precision T (skips when the solve is done)
+// Chebyshev-Jacobi steps 1..degree-1 (Sec. 5.3) in precision T, from the
+// start z_1 = theta^-1 D^-1 r already in cz0 (written by the fused CG update
+// or by k_cheb_start); *zlast receives the buffer holding the last iterate.
 template <typename T>
-sipg_status precondition(sipg_plan* P, const double* r, double* zout, hipStream_t s) {
-    const long long n = P->ndof;
+sipg_status cheb_steps(sipg_plan* P, const T** zlast, hipStream_t s) {
     T* rT = static_cast<T*>(P->cr);
     T* d = static_cast<T*>(P->cd);
     T* za = static_cast<T*>(P->cz0);
     T* zb = static_cast<T*>(P->cz1);
     const T* dinv;
     if constexpr (sizeof(T) == 8) dinv = P->dinv64; else dinv = P->dinv32;
-    sk_cheb_start<T>(r, rT, za, d, dinv, n, P->st, s);
     const OpData<T> od = P->opdata<T>();
     for (int j = 1; j < P->opts.cheb_degree; ++j) {
         ApplyIO<T> io;
+        std::memset(&io, 0, sizeof(io));
         io.x = za; io.y = zb; io.parts = SIPG_PART_ALL;
         io.r = rT; io.dinv = dinv; io.d = d;
         io.coef = &P->st->cheb[j][0];
@@ -263,16 +264,58 @@ sipg_status precondition(sipg_plan* P, const double* r, double* zout, hipStream_
         HIP_TRY(launch_apply<T>(P->n, P->C, P->curved, od, io, MODE_CHEB, s));
         std::swap(za, zb);
     }
-    sk_cheb_end<T>(za, zout, n, P->st, P->partials, P->mean_zero ? 1 : 0, s);
-    if (P->mean_zero) {
-        sk_scalar(P->st, P->partials, 1, SC_MEAN, n, s, 1);
-        sk_sub_mean(zout, n, P->st, P->st, s);
-    }
+    *zlast = za;
     return SIPG_OK;
 }
 
-sipg_status precond(sipg_plan* P, const double* r, double* z, hipStream_t s) {
-    return P->opts.precond_precision == SIPG_F32 ? precondition<float>(P, r, z, s) : precondition<double>(P, r, z, s);
+template <typename T>
+const T* dinv_of(const sipg_plan* P) {
+    if constexpr (sizeof(T) == 8) return P->dinv64; else return P->dinv32;
+}
+
+// (Re)start of the flexible CG from r = b - A x: z = M r, rz = r.z, p = z.
+template <typename T>
+sipg_status cg_start(sipg_plan* P) {
+    hipStream_t s = P->sstream;
+    const long long n = P->ndof;
+    const int mz = P->mean_zero ? 1 : 0;
+    sk_cheb_start<T>(P->r, static_cast<T*>(P->cr), static_cast<T*>(P->cz0), static_cast<T*>(P->cd), dinv_of<T>(P),
+                     n, P->st, s);
+    const T* zl = nullptr;
+    sipg_status rc = cheb_steps<T>(P, &zl, s);
+    if (rc != SIPG_OK) return rc;
+    sk_cg_beta<T>(zl, P->z, P->r, nullptr, n, mz, 1, P->st, P->partials, s);
+    sk_cg_direction(P->p, P->z, n, mz, 1, P->st, s);
+    HIP_TRY(hipGetLastError());
+    return SIPG_OK;
+}
+
+// `iters` flexible-CG iterations (Sec. 5.3: FP64 CG, preconditioner in T):
+// q = A p; alpha; x, r update with the convergence test and the first
+// Chebyshev step; the remaining Chebyshev steps; beta; p = z + beta p.
+template <typename T>
+sipg_status cg_iterations(sipg_plan* P, int iters) {
+    hipStream_t s = P->sstream;
+    const long long n = P->ndof;
+    const int mz = P->mean_zero ? 1 : 0;
+    const OpData<double> od = P->opdata<double>();
+    for (int it = 0; it < iters; ++it) {
+        ApplyIO<double> io;
+        std::memset(&io, 0, sizeof(io));
+        io.x = P->p; io.y = P->q; io.parts = SIPG_PART_ALL; io.skip = &P->st->skip;
+        HIP_TRY(launch_apply<double>(P->n, P->C, P->curved, od, io, MODE_APPLY, s));
+        sk_cg_alpha(P->p, P->q, n, P->st, P->partials, s);
+        sk_cg_update<T>(P->x, P->r, P->p, P->q, static_cast<T*>(P->cr), static_cast<T*>(P->cz0),
+                        static_cast<T*>(P->cd), dinv_of<T>(P), n, P->st, P->partials, s);
+        const T* zl = nullptr;
+        sipg_status rc = cheb_steps<T>(P, &zl, s);
+        if (rc != SIPG_OK) return rc;
+        sk_cg_beta<T>(zl, P->zo, P->r, P->z, n, mz, 0, P->st, P->partials, s);
+        sk_cg_direction(P->p, P->zo, n, mz, 0, P->st, s);
+        std::swap(P->z, P->zo);
+    }
+    HIP_TRY(hipGetLastError());
+    return SIPG_OK;
 }
 
 sipg_status run_lanczos(sipg_plan* P, hipStream_t s) {
@@ -306,15 +349,7 @@ sipg_status enqueue_readback(sipg_plan* P) {
 
 // restart CG from the current x with r already holding b - A x
 sipg_status cg_start_from_residual(sipg_plan* P) {
-    hipStream_t s = P->sstream;
-    const long long n = P->ndof;
-    sipg_status rc = precond(P, P->r, P->z, s);
-    if (rc != SIPG_OK) return rc;
-    sk_dot2(P->r, P->z, nullptr, n, P->partials, P->st, s);
-    sk_scalar(P->st, P->partials, 1, SC_RZ, n, s, 1);
-    sk_pcg_direction(P->p, P->z, n, 1, P->st, s);
-    HIP_TRY(hipGetLastError());
-    return SIPG_OK;
+    return P->opts.precond_precision == SIPG_F32 ? cg_start<float>(P) : cg_start<double>(P);
 }
 
 sipg_status enqueue_true_residual(sipg_plan* P) {
@@ -332,7 +367,6 @@ sipg_status enqueue_true_residual(sipg_plan* P) {
         sk_scalar(P->st, P->partials, 1, SC_MEAN, n, s);
     }
     sk_residual(P->b, P->q, P->r, n, P->mean_zero ? 1 : 0, P->st, P->partials, s);
-    sk_scalar(P->st, P->partials, 1, SC_TRUE, n, s);
     HIP_TRY(hipGetLastError());
     return enqueue_readback(P);
 }
@@ -597,7 +631,6 @@ sipg_status sipg_solve_begin(sipg_plan* P, const double* b, double* x, const sip
         sk_scalar(P->st, P->partials, 1, SC_MEAN, n, s);
     }
     sk_pcg_start(b, P->r, x, n, P->mean_zero ? 1 : 0, P->st, P->partials, s);
-    sk_scalar(P->st, P->partials, 1, SC_PCG_INIT, n, s);
     sipg_status rc = cg_start_from_residual(P);
     if (rc != SIPG_OK) return rc;
     P->phase = PH_RUNNING;
@@ -608,25 +641,9 @@ sipg_status sipg_solve_advance(sipg_plan* P, int32_t iters) {
     if (!valid_plan(P)) return fail(SIPG_ERR_INVALID, "null plan");
     if (P->phase == PH_IDLE) return fail(SIPG_ERR_STATE, "no solve in progress");
     if (P->phase == PH_DONE || iters <= 0) return SIPG_OK;
-    hipStream_t s = P->sstream;
-    const long long n = P->ndof;
-    for (int it = 0; it < iters; ++it) {
-        ApplyIO<double> io;
-        std::memset(&io, 0, sizeof(io));
-        io.x = P->p; io.y = P->q; io.parts = SIPG_PART_ALL; io.skip = &P->st->skip;
-        HIP_TRY(launch_apply<double>(P->n, P->C, P->curved, P->opdata<double>(), io, MODE_APPLY, s));
-        sk_dot2(P->p, P->q, nullptr, n, P->partials, P->st, s);
-        sk_scalar(P->st, P->partials, 1, SC_ALPHA, n, s, 1);
-        sk_pcg_update(P->x, P->r, P->p, P->q, n, P->st, P->partials, s);
-        sk_scalar(P->st, P->partials, 1, SC_RESID, n, s, 1);
-        sipg_status rc = precond(P, P->r, P->zo, s);   // zo <- z_new
-        if (rc != SIPG_OK) return rc;
-        sk_dot2(P->r, P->zo, P->z, n, P->partials, P->st, s);
-        sk_scalar(P->st, P->partials, 2, SC_BETA, n, s, 1);
-        sk_pcg_direction(P->p, P->zo, n, 0, P->st, s);
-        std::swap(P->z, P->zo);
-    }
-    HIP_TRY(hipGetLastError());
+    const sipg_status rc = P->opts.precond_precision == SIPG_F32 ? cg_iterations<float>(P, iters)
+                                                                 : cg_iterations<double>(P, iters);
+    if (rc != SIPG_OK) return rc;
     return enqueue_readback(P);
 }
 

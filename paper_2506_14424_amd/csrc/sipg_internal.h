@@ -83,11 +83,13 @@ struct SolveState {
     int iter;
     int max_iter;
     int skip;                // nonzero while done != 0 (read by apply kernels)
-    int pad[3];
+    unsigned arrive;         // blocks of the running fused reduction that have finished (0 between kernels)
+    int pad[2];
 };
 
 constexpr int kRedBlocks = 512;   // blocks of the deterministic reductions
 constexpr int kRedThreads = 256;
+constexpr int kRedSlots = 4;      // partial sums per block
 
 // ---------------------------------------------------------------- launchers
 // (defined in the .hip files; return hipError_t of the launch)

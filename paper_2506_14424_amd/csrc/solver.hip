@@ -2,11 +2,16 @@
 // in FP32 or FP64, and the Lanczos eigenvalue estimate (Sec. 5.3).
 //
 // Reductions are deterministic: each of kRedBlocks blocks reduces a fixed
-// grid-stride subset with a fixed tree and writes one partial; a one-block
-// "scalar" kernel sums the partials in a fixed order and updates the solve
-// state (alpha, beta, convergence flags) on the device, so iterations can be
-// enqueued without host round trips.  Every kernel of an iteration returns at
-// once when the state's skip flag is set (the solve has finished).
+// grid-stride subset with a fixed tree and writes one partial; the partials
+// are then summed in a fixed order, either by a one-block "scalar" kernel or,
+// in the CG iteration, by the last block of the same kernel to finish, which
+// also updates the solve state (alpha, beta, convergence flags) on the
+// device, so iterations are enqueued without host round trips.  Every kernel
+// of an iteration returns at once when the state's skip flag is set (the
+// solve has finished).
+//
+// One CG iteration is: A p (FP64 apply), alpha, update + first Chebyshev
+// step, degree-1 Chebyshev applies, beta, direction.
 
 #include "device_common.h"
 #include "solver_kernels.h"
@@ -150,27 +155,8 @@ __global__ void k_lz_finish(SolveState* st, double safety, double ratio, int deg
     }
 }
 
-// One-block reduction of the partials in a fixed order, then the scalar step.
-__global__ void k_scalar(SolveState* st, const double* partials, int nslots, int op, long long n,
-                         int respect_skip) {
-    if (respect_skip && st->skip) return;
-    __shared__ double sh[2][kRedThreads];
-    for (int k = 0; k < 2; ++k) {
-        double s = 0.0;
-        if (k < nslots)
-            for (int i = threadIdx.x; i < kRedBlocks; i += kRedThreads) s += partials[k * kRedBlocks + i];
-        sh[k][threadIdx.x] = s;
-    }
-    __syncthreads();
-    for (int w = kRedThreads / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) {
-            sh[0][threadIdx.x] += sh[0][threadIdx.x + w];
-            sh[1][threadIdx.x] += sh[1][threadIdx.x + w];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x != 0) return;
-    const double s0 = sh[0][0], s1 = sh[1][0];
+// The scalar step that follows a reduction (s0, s1: the first two sums).
+__device__ void scalar_step(SolveState* st, int op, double s0, double s1, long long n) {
     switch (op) {
         case SC_LZ_NORM:
             st->scale = s0 > 0.0 ? 1.0 / sqrt(s0) : 0.0;
@@ -223,6 +209,66 @@ __global__ void k_scalar(SolveState* st, const double* partials, int nslots, int
     }
 }
 
+// One-block reduction of the partials in a fixed order, then the scalar step.
+__global__ void k_scalar(SolveState* st, const double* partials, int nslots, int op, long long n,
+                         int respect_skip) {
+    if (respect_skip && st->skip) return;
+    __shared__ double sh[2][kRedThreads];
+    for (int k = 0; k < 2; ++k) {
+        double s = 0.0;
+        if (k < nslots)
+            for (int i = threadIdx.x; i < kRedBlocks; i += kRedThreads) s += partials[k * kRedBlocks + i];
+        sh[k][threadIdx.x] = s;
+    }
+    __syncthreads();
+    for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + w];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    scalar_step(st, op, sh[0][0], sh[1][0], n);
+}
+
+// Fused reduction: every block stores its NS partial sums; the last block to
+// arrive (device-scope counter in the state) adds the partials of all blocks
+// in the same fixed order as k_scalar, so the totals do not depend on which
+// block finishes last.  Returns true in (all threads of) the last block, with
+// the totals in tot for thread 0; that block also clears the counter for the
+// next fused kernel on the stream.
+template <int NS>
+__device__ bool reduce_last(double (&v)[NS], double* partials, SolveState* st, double (&tot)[NS]) {
+    block_reduce_store<NS>(v, partials);
+    __shared__ int s_last;
+    if (threadIdx.x == 0) {
+        const unsigned prev = __hip_atomic_fetch_add(&st->arrive, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        s_last = prev == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!s_last) return false;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    __shared__ double sh[NS][kRedThreads];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        double s = 0.0;
+        for (int i = threadIdx.x; i < (int)gridDim.x; i += kRedThreads) s += partials[k * kRedBlocks + i];
+        sh[k][threadIdx.x] = s;
+    }
+    __syncthreads();
+    for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+#pragma unroll
+            for (int k = 0; k < NS; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + w];
+        __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < NS; ++k) tot[k] = sh[k][0];
+    if (threadIdx.x == 0) __hip_atomic_store(&st->arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return true;
+}
+
 __device__ __forceinline__ bool skipped(const SolveState* st) { return st != nullptr && st->skip; }
 
 // partial sums of x (slot 0)
@@ -240,68 +286,65 @@ __global__ void k_sub_mean(double* x, long long n, const SolveState* st, const S
     GRID_STRIDE(i, n) x[i] -= m;
 }
 
-// partials a.b (slot 0) and a.c (slot 1, if c)
-__global__ void k_dot2(const double* a, const double* b, const double* c, long long n, double* partials,
-                       const SolveState* st) {
-    if (skipped(st)) return;
-    double acc[2] = {0.0, 0.0};
-    GRID_STRIDE(i, n) {
-        acc[0] += a[i] * b[i];
-        if (c) acc[1] += a[i] * c[i];
-    }
-    block_reduce_store<2>(acc, partials);
-}
-
-// r = b - mean, x = 0, partial r.r   (mean from state when mean_zero)
-__global__ void k_pcg_start(const double* b, double* r, double* x, long long n, int mean_zero,
-                            const SolveState* st, double* partials) {
+// r = b - mean, x = 0; |r|^2 -> bnorm2 and the start flags (mean from state when mean_zero)
+__global__ void k_pcg_start(const double* b, double* r, double* x, long long n, int mean_zero, SolveState* st,
+                            double* partials) {
     const double m = mean_zero ? st->mean : 0.0;
-    double acc[1] = {0.0};
+    double acc[1] = {0.0}, tot[1];
     GRID_STRIDE(i, n) {
         const double v = b[i] - m;
         r[i] = v;
         x[i] = 0.0;
         acc[0] += v * v;
     }
-    block_reduce_store<1>(acc, partials);
+    if (reduce_last<1>(acc, partials, st, tot) && threadIdx.x == 0) scalar_step(st, SC_PCG_INIT, tot[0], 0.0, n);
 }
 
-// r = b - Ax (q holds Ax); partial r.r  (restart / true residual)
-__global__ void k_residual(const double* b, const double* q, double* r, long long n, int mean_zero,
-                           const SolveState* st, double* partials) {
+// r = b - Ax (q holds Ax); |r|^2 -> rr_true  (restart / final defect check)
+__global__ void k_residual(const double* b, const double* q, double* r, long long n, int mean_zero, SolveState* st,
+                           double* partials) {
     const double m = mean_zero ? st->mean : 0.0;
-    double acc[1] = {0.0};
+    double acc[1] = {0.0}, tot[1];
     GRID_STRIDE(i, n) {
         const double v = (b[i] - m) - q[i];
         r[i] = v;
         acc[0] += v * v;
     }
-    block_reduce_store<1>(acc, partials);
+    if (reduce_last<1>(acc, partials, st, tot) && threadIdx.x == 0) scalar_step(st, SC_TRUE, tot[0], 0.0, n);
 }
 
-// x += alpha p, r -= alpha q; partial r.r
-__global__ void k_pcg_update(double* x, double* r, const double* p, const double* q, long long n,
-                             const SolveState* st, double* partials) {
+// alpha = (r.z) / (p.Ap), breakdown when p.Ap is not positive
+__global__ void k_cg_alpha(const double* p, const double* q, long long n, SolveState* st, double* partials) {
+    if (skipped(st)) return;
+    double acc[1] = {0.0}, tot[1];
+    GRID_STRIDE(i, n) acc[0] += p[i] * q[i];
+    if (reduce_last<1>(acc, partials, st, tot) && threadIdx.x == 0) scalar_step(st, SC_ALPHA, tot[0], 0.0, n);
+}
+
+// x += alpha p, r -= alpha q, convergence test on |r|^2, and the first
+// Chebyshev step from the new residual: rT = (T) r, z = theta^-1 dinv rT, d = z.
+template <typename T>
+__global__ void k_cg_update(double* x, double* r, const double* p, const double* q, T* rT, T* z, T* d,
+                            const T* dinv, long long n, SolveState* st, double* partials) {
     if (skipped(st)) return;
     const double a = st->alpha;
-    double acc[1] = {0.0};
+    const T ti = T(st->theta_inv);
+    double acc[1] = {0.0}, tot[1];
     GRID_STRIDE(i, n) {
         x[i] += a * p[i];
         const double v = r[i] - a * q[i];
         r[i] = v;
         acc[0] += v * v;
+        const T rv = T(v);
+        rT[i] = rv;
+        const T zv = ti * dinv[i] * rv;
+        z[i] = zv;
+        d[i] = zv;
     }
-    block_reduce_store<1>(acc, partials);
+    if (reduce_last<1>(acc, partials, st, tot) && threadIdx.x == 0) scalar_step(st, SC_RESID, tot[0], 0.0, n);
 }
 
-// p = z + beta p (beta from state, or 0 when first)
-__global__ void k_pcg_direction(double* p, const double* z, long long n, int first, const SolveState* st) {
-    if (skipped(st)) return;
-    const double b = first ? 0.0 : st->beta;
-    GRID_STRIDE(i, n) p[i] = first ? z[i] : z[i] + b * p[i];
-}
-
-// Chebyshev start: rT = (T) r, z = theta^-1 dinv rT, d = z
+// Chebyshev start from r without a CG update (first iteration, restarts)
 template <typename T>
 __global__ void k_cheb_start(const double* r, T* rT, T* z, T* d, const T* dinv, long long n, const SolveState* st) {
     if (skipped(st)) return;
@@ -315,18 +358,46 @@ __global__ void k_cheb_start(const double* r, T* rT, T* z, T* d, const T* dinv, 
     }
 }
 
-// Chebyshev end: z64 = (double) zT; partial sum(z64) when mean_zero
+// End of the preconditioner and the flexible-CG beta:
+//   z = (double) zT;  with mean_zero the mean of z is removed (the
+//   subtraction itself happens in k_cg_direction; r.(z - m 1) = r.z - m sum r);
+//   first: rz = r.z;  else beta = (r.z - r.zold) / rz, rz = r.z.
 template <typename T>
-__global__ void k_cheb_end(const T* zT, double* z, long long n, const SolveState* st, double* partials,
-                           int want_sum) {
+__global__ void k_cg_beta(const T* zT, double* z, const double* r, const double* zold, long long n, int mean_zero,
+                          int first, SolveState* st, double* partials) {
     if (skipped(st)) return;
-    double acc[1] = {0.0};
+    double acc[4] = {0.0, 0.0, 0.0, 0.0}, tot[4];
     GRID_STRIDE(i, n) {
         const double v = (double)zT[i];
+        const double ri = r[i];
         z[i] = v;
-        acc[0] += v;
+        acc[0] += ri * v;
+        if (!first) acc[1] += ri * zold[i];
+        acc[2] += v;
+        acc[3] += ri;
     }
-    if (want_sum) block_reduce_store<1>(acc, partials);
+    if (reduce_last<4>(acc, partials, st, tot) && threadIdx.x == 0) {
+        const double m = mean_zero ? tot[2] / (double)n : 0.0;
+        const double rzn = mean_zero ? tot[0] - m * tot[3] : tot[0];
+        st->mean = m;
+        if (!first) st->beta = (rzn - tot[1]) / st->rz;
+        st->rz = rzn;
+    }
+}
+
+// z -= mean (mean_zero), p = z + beta p  (p = z when first)
+__global__ void k_cg_direction(double* p, double* z, long long n, int mean_zero, int first, const SolveState* st) {
+    if (skipped(st)) return;
+    const double b = first ? 0.0 : st->beta;
+    const double m = st->mean;
+    GRID_STRIDE(i, n) {
+        double zz = z[i];
+        if (mean_zero) {
+            zz -= m;
+            z[i] = zz;
+        }
+        p[i] = first ? zz : zz + b * p[i];
+    }
 }
 
 __global__ void k_copy(double* dst, const double* src, long long n) { GRID_STRIDE(i, n) dst[i] = src[i]; }
@@ -341,6 +412,7 @@ __global__ void k_state_init(SolveState* st, double tol2, int max_iter) {
     st->done = 0;
     st->skip = 0;
     st->iter = 0;
+    st->arrive = 0;
 }
 __global__ void k_state_resume(SolveState* st, int max_iter) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -386,24 +458,21 @@ void sk_sum(const double* x, long long n, double* partials, const SolveState* st
 void sk_sub_mean(double* x, long long n, const SolveState* st, const SolveState* skip_st, hipStream_t s) {
     L(k_sub_mean, x, n, st, skip_st);
 }
-void sk_dot2(const double* a, const double* b, const double* c, long long n, double* partials, const SolveState* st,
-             hipStream_t s) {
-    L(k_dot2, a, b, c, n, partials, st);
-}
-void sk_pcg_start(const double* b, double* r, double* x, long long n, int mean_zero, const SolveState* st,
+void sk_pcg_start(const double* b, double* r, double* x, long long n, int mean_zero, SolveState* st,
                   double* partials, hipStream_t s) {
     L(k_pcg_start, b, r, x, n, mean_zero, st, partials);
 }
-void sk_residual(const double* b, const double* q, double* r, long long n, int mean_zero, const SolveState* st,
+void sk_residual(const double* b, const double* q, double* r, long long n, int mean_zero, SolveState* st,
                  double* partials, hipStream_t s) {
     L(k_residual, b, q, r, n, mean_zero, st, partials);
 }
-void sk_pcg_update(double* x, double* r, const double* p, const double* q, long long n, const SolveState* st,
-                   double* partials, hipStream_t s) {
-    L(k_pcg_update, x, r, p, q, n, st, partials);
+void sk_cg_alpha(const double* p, const double* q, long long n, SolveState* st, double* partials, hipStream_t s) {
+    L(k_cg_alpha, p, q, n, st, partials);
 }
-void sk_pcg_direction(double* p, const double* z, long long n, int first, const SolveState* st, hipStream_t s) {
-    L(k_pcg_direction, p, z, n, first, st);
+template <typename T>
+void sk_cg_update(double* x, double* r, const double* p, const double* q, T* rT, T* z, T* d, const T* dinv,
+                  long long n, SolveState* st, double* partials, hipStream_t s) {
+    L(k_cg_update<T>, x, r, p, q, rT, z, d, dinv, n, st, partials);
 }
 template <typename T>
 void sk_cheb_start(const double* r, T* rT, T* z, T* d, const T* dinv, long long n, const SolveState* st,
@@ -411,16 +480,24 @@ void sk_cheb_start(const double* r, T* rT, T* z, T* d, const T* dinv, long long 
     L(k_cheb_start<T>, r, rT, z, d, dinv, n, st);
 }
 template <typename T>
-void sk_cheb_end(const T* zT, double* z, long long n, const SolveState* st, double* partials, int want_sum,
-                 hipStream_t s) {
-    L(k_cheb_end<T>, zT, z, n, st, partials, want_sum);
+void sk_cg_beta(const T* zT, double* z, const double* r, const double* zold, long long n, int mean_zero, int first,
+                SolveState* st, double* partials, hipStream_t s) {
+    L(k_cg_beta<T>, zT, z, r, zold, n, mean_zero, first, st, partials);
 }
-template void sk_cheb_start<double>(const double*, double*, double*, double*, const double*, long long,
-                                    const SolveState*, hipStream_t);
-template void sk_cheb_start<float>(const double*, float*, float*, float*, const float*, long long, const SolveState*,
-                                   hipStream_t);
-template void sk_cheb_end<double>(const double*, double*, long long, const SolveState*, double*, int, hipStream_t);
-template void sk_cheb_end<float>(const float*, double*, long long, const SolveState*, double*, int, hipStream_t);
+void sk_cg_direction(double* p, double* z, long long n, int mean_zero, int first, const SolveState* st,
+                     hipStream_t s) {
+    L(k_cg_direction, p, z, n, mean_zero, first, st);
+}
+#define INST(T)                                                                                             \
+    template void sk_cg_update<T>(double*, double*, const double*, const double*, T*, T*, T*, const T*,       \
+                                  long long, SolveState*, double*, hipStream_t);                            \
+    template void sk_cheb_start<T>(const double*, T*, T*, T*, const T*, long long, const SolveState*,         \
+                                   hipStream_t);                                                             \
+    template void sk_cg_beta<T>(const T*, double*, const double*, const double*, long long, int, int,         \
+                                SolveState*, double*, hipStream_t);
+INST(double)
+INST(float)
+#undef INST
 
 void sk_copy(double* dst, const double* src, long long n, hipStream_t s) { L(k_copy, dst, src, n); }
 void sk_cast(float* dst, const double* src, long long n, hipStream_t s) { L(k_cast, dst, src, n); }

@@ -21,21 +21,22 @@ void sk_scalar(SolveState* st, const double* partials, int nslots, int op, long 
                int respect_skip = 0);
 void sk_sum(const double* x, long long n, double* partials, const SolveState* st, hipStream_t s);
 void sk_sub_mean(double* x, long long n, const SolveState* st, const SolveState* skip_st, hipStream_t s);
-void sk_dot2(const double* a, const double* b, const double* c, long long n, double* partials, const SolveState* st,
-             hipStream_t s);
-void sk_pcg_start(const double* b, double* r, double* x, long long n, int mean_zero, const SolveState* st,
+void sk_pcg_start(const double* b, double* r, double* x, long long n, int mean_zero, SolveState* st,
                   double* partials, hipStream_t s);
-void sk_residual(const double* b, const double* q, double* r, long long n, int mean_zero, const SolveState* st,
+void sk_residual(const double* b, const double* q, double* r, long long n, int mean_zero, SolveState* st,
                  double* partials, hipStream_t s);
-void sk_pcg_update(double* x, double* r, const double* p, const double* q, long long n, const SolveState* st,
-                   double* partials, hipStream_t s);
-void sk_pcg_direction(double* p, const double* z, long long n, int first, const SolveState* st, hipStream_t s);
+void sk_cg_alpha(const double* p, const double* q, long long n, SolveState* st, double* partials, hipStream_t s);
+template <typename T>
+void sk_cg_update(double* x, double* r, const double* p, const double* q, T* rT, T* z, T* d, const T* dinv,
+                  long long n, SolveState* st, double* partials, hipStream_t s);
 template <typename T>
 void sk_cheb_start(const double* r, T* rT, T* z, T* d, const T* dinv, long long n, const SolveState* st,
                    hipStream_t s);
 template <typename T>
-void sk_cheb_end(const T* zT, double* z, long long n, const SolveState* st, double* partials, int want_sum,
-                 hipStream_t s);
+void sk_cg_beta(const T* zT, double* z, const double* r, const double* zold, long long n, int mean_zero, int first,
+                SolveState* st, double* partials, hipStream_t s);
+void sk_cg_direction(double* p, double* z, long long n, int mean_zero, int first, const SolveState* st,
+                     hipStream_t s);
 void sk_copy(double* dst, const double* src, long long n, hipStream_t s);
 void sk_cast(float* dst, const double* src, long long n, hipStream_t s);
 void sk_fill(double* dst, double v, long long n, hipStream_t s);
