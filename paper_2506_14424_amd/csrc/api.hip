@@ -390,6 +390,8 @@ sipg_status sipg_plan_create(const sipg_mesh* mesh, const sipg_viscosity* law, c
     if (!(params->penalty > 0.0) || !std::isfinite(params->penalty)) return fail(SIPG_ERR_INVALID, "penalty must be > 0");
     for (int i = 0; i < 6; ++i)
         if (mesh->bc[i] != SIPG_BC_DIRICHLET && mesh->bc[i] != SIPG_BC_NEUMANN) return fail(SIPG_ERR_INVALID, "bad bc value");
+    if ((long long)(mesh->nx + 1) * (mesh->ny + 1) * (mesh->nz + 1) * 3 >= (1ll << 31))
+        return fail(SIPG_ERR_INVALID, "mesh too large: 2^31 or more vertex coordinates");
     const long long ncell = (long long)mesh->nx * mesh->ny * mesh->nz;
     const int n = params->degree + 1, C = params->op == SIPG_VISCOUS ? 3 : 1;
     const long long ndof = ncell * C * n * n * n;

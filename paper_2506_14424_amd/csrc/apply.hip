@@ -39,16 +39,21 @@ struct Shape {
     static constexpr int THREADS = CPB * N * N;
     static constexpr int NNN = N * N * N, NN = N * N;
     // LDS layout of a cell's volume arrays: node (i1, i2, i3) of component c at
-    // c*CS + i3*S3 + i2*N + i1.  In FP32 the padded xi_3 stride S3 spreads the
-    // column, xi_1-line and xi_2-line access patterns of a cell's n*n lanes
-    // over the LDS banks (n = 4: at most 2-way conflicts instead of 4-way);
-    // in FP64 the extra LDS would cost a resident wavefront per SIMD.
+    //   plain:  c*CS + i3*S3 + i2*N + i1,
+    //   skewed: c*CS + (i3 ^ x)*S3 + ((i2 + i3) % N)*N + (i1 + i3) % N, x = cell % 4.
+    // The skew (FP64, n = 4) makes the xi_1-line, xi_2-line and xi_3-column
+    // patterns of a cell's 16 lanes hit 16 different bank pairs, and the
+    // plane swap x moves the four cells of a wavefront onto different
+    // quarters of the banks without padding.  In FP32 the padded xi_3
+    // stride S3 spreads the three patterns instead (n = 3, 4); there the
+    // padding costs no occupancy.
+    static constexpr bool SKEW = DBL && N == 4;
     static constexpr int S3 = DBL ? NN : (N == 3 ? 12 : N == 4 ? 19 : NN);
     static constexpr int CS = N * S3;
     // per-cell LDS: nodal values and a work space for the cell sweeps and the
-    // face stages; +1 staggers consecutive cells over the LDS banks
-    static constexpr int U = C * CS + 1;
-    static constexpr int W = (2 * C * CS > 8 * C * NN ? 2 * C * CS : 8 * C * NN) + 1;
+    // face stages; +1 staggers consecutive cells over the LDS banks (plain layout)
+    static constexpr int U = C * CS + (SKEW ? 0 : 1);
+    static constexpr int W = (2 * C * CS > 8 * C * NN ? 2 * C * CS : 8 * C * NN) + (SKEW ? 0 : 1);
 };
 
 // Barrier between LDS stages.  A workgroup of one wavefront only needs the
@@ -135,6 +140,38 @@ struct CellIdx {
     bool active;
 };
 
+// Per-lane LDS offsets of the three line patterns of a cell's volume arrays
+// (lane (la, lb) = (t % n, t / n)): oz[j] = node (la, lb, j), the lane's
+// xi_3 column; ox[j] = node (j, la, lb), a xi_1 line; oy[j] = node (la, j, lb),
+// a xi_2 line.
+template <int N>
+struct VolOff {
+    int oz[N], ox[N], oy[N];
+};
+
+template <int N, int S3, bool SKEW>
+__device__ __forceinline__ int vol_pos(int i1, int i2, int i3, int px) {
+    if constexpr (!SKEW) {
+        return i3 * S3 + i2 * N + i1;
+    } else {
+        int a = i2 + i3, b = i1 + i3;
+        a = a >= N ? a - N : a;
+        b = b >= N ? b - N : b;
+        return (i3 ^ px) * S3 + a * N + b;
+    }
+}
+
+template <int N, int S3, bool SKEW>
+__device__ __forceinline__ void vol_offsets(int la, int lb, int lc, VolOff<N>& o) {
+    const int px = lc & 3;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        o.oz[j] = vol_pos<N, S3, SKEW>(la, lb, j, px);
+        o.ox[j] = vol_pos<N, S3, SKEW>(j, la, lb, px);
+        o.oy[j] = vol_pos<N, S3, SKEW>(la, j, lb, px);
+    }
+}
+
 // Small per-lane tables kept in LDS: points, weights, face values/derivatives.
 template <typename T, int N>
 struct LaneTab {
@@ -143,9 +180,9 @@ struct LaneTab {
 
 // The neighbour's line of nodal values through face point (i1, i2) of face
 // (D, s), and the face viscosity and penalty factor at that point.
-template <int N, int C, typename T, int D>
+template <int N, int C, typename T, bool CURVED, int D>
 __device__ __forceinline__ void face_prefetch(const OpData<T>& op, const ApplyIO<T>& io, const CellIdx& ci, int s,
-                                              T (&nb)[C][N], T& mu, T& tf) {
+                                              T (&nb)[C][N], T& mu, T& tf, T (&gn)[8]) {
     constexpr int NN = N * N, NNN = N * N * N;
     const int i1 = ci.i1, i2 = ci.i2;
     const int pos = D == 0 ? ci.ex : D == 1 ? ci.ey : ci.ez;
@@ -160,6 +197,11 @@ __device__ __forceinline__ void face_prefetch(const OpData<T>& op, const ApplyIO
     if (D == 0) fid = (ci.ez * op.ny + ci.ey) * (op.nx + 1) + ci.ex + s;
     else if (D == 1) fid = op.nfx + (ci.ez * (op.ny + 1) + ci.ey + s) * op.nx + ci.ex;
     else fid = op.nfx + op.nfy + ((ci.ez + s) * op.ny + ci.ey) * op.nx + ci.ex;
+    if constexpr (CURVED) {
+        const int dn = has_nb ? (s == 1 ? 1 : -1) : 0;  // the neighbour is one cell away along xi_D
+        trilinear_coeffs(op.verts, op.nx, op.ny, ci.ex + (D == 0 ? dn : 0), ci.ey + (D == 1 ? dn : 0),
+                         ci.ez + (D == 2 ? dn : 0), ci.t % 3, gn);
+    }
     const T* xn = io.x + (size_t)en * (C * NNN);
     const bool ld = live && has_nb;
 #pragma unroll
@@ -170,10 +212,13 @@ __device__ __forceinline__ void face_prefetch(const OpData<T>& op, const ApplyIO
             if (D == 2) off = (c * N + j) * NN + i2 * N + i1;
             else if (D == 0) off = (c * N + i2) * NN + i1 * N + j;
             else off = (c * N + i2) * NN + j * N + i1;
-            nb[c][j] = ld ? xn[off] : T(0);
+            const T v = xn[off];  // en and fid are valid for every lane: load unconditionally
+            nb[c][j] = ld ? v : T(0);
         }
-    mu = (C == 3 && live) ? op.mu_face[(size_t)fid * NN + ci.t] : T(1);
-    tf = live ? op.tfac[fid] : T(0);
+    const T muf = C == 3 ? op.mu_face[(size_t)fid * NN + ci.t] : T(1);
+    const T tff = op.tfac[fid];
+    mu = live ? muf : T(1);
+    tf = live ? tff : T(0);
 }
 
 // ---------------------------------------------------------------- faces
@@ -189,11 +234,11 @@ __device__ __forceinline__ void face_prefetch(const OpData<T>& op, const ApplyIO
 template <int N, int C, typename T, bool CURVED, int D, int THREADS>
 __device__ __forceinline__ void face_pass(const OpData<T>& op, const ApplyIO<T>& io, const CellIdx& ci, int s,
                                           T (&y)[C][N], const T* su, T* sw, T (*geo)[8][3],
-                                          const LaneTab<T, N>& lt) {
-    T nbl[C][N], mu_pre, tf_pre;
-    face_prefetch<N, C, T, D>(op, io, ci, s, nbl, mu_pre, tf_pre);
+                                          const LaneTab<T, N>& lt, const VolOff<N>& vo) {
+    T nbl[C][N], mu_pre, tf_pre, gnb[8];
+    face_prefetch<N, C, T, CURVED, D>(op, io, ci, s, nbl, mu_pre, tf_pre, gnb);
     constexpr int NN = N * N, NNN = N * N * N;
-    constexpr int S3 = Shape<N, C, sizeof(T) == 8>::S3, CS = Shape<N, C, sizeof(T) == 8>::CS;
+    constexpr int CS = Shape<N, C, sizeof(T) == 8>::CS;
     constexpr int t1 = D == 0 ? 1 : 0, t2 = D == 2 ? 1 : 2;
     const auto& tb = op.tab;
     const int i1 = ci.i1, i2 = ci.i2, t = ci.t;
@@ -224,9 +269,9 @@ __device__ __forceinline__ void face_pass(const OpData<T>& op, const ApplyIO<T>&
 #pragma unroll
         for (int j = 0; j < N; ++j) {
             T own;
-            if (D == 2) own = su[c * CS + j * S3 + i2 * N + i1];
-            else if (D == 0) own = su[c * CS + i2 * S3 + i1 * N + j];
-            else own = su[c * CS + i2 * S3 + j * N + i1];
+            if (D == 2) own = su[c * CS + vo.oz[j]];
+            else if (D == 0) own = su[c * CS + vo.ox[j]];
+            else own = su[c * CS + vo.oy[j]];
             v0 += tb.S[s][j] * own;
             v1 += tb.G[s][j] * own;
             w0 += tb.S[1 - s][j] * nbl[c][j];
@@ -239,13 +284,9 @@ __device__ __forceinline__ void face_pass(const OpData<T>& op, const ApplyIO<T>&
         FT[(C + c) * NN + t] = w0;
     }
     if constexpr (CURVED) {
-        if (t < 3 && has_nb && ci.active) {
-            const int nex = en % op.nx, ney = (en / op.nx) % op.ny, nez = en / (op.nx * op.ny);
-            T g[8];
-            trilinear_coeffs(op.verts, op.nx, op.ny, nex, ney, nez, t, g);
+        if (t < 3)
 #pragma unroll
-            for (int k = 0; k < 8; ++k) geo[1][k][t] = g[k];
-        }
+            for (int k = 0; k < 8; ++k) geo[1][k][t] = gnb[k];
     }
     stage_sync<THREADS>();
 
@@ -483,12 +524,14 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
     constexpr int NN = N * N, NNN = N * N * N;
     constexpr int CPB = Sh::CPB, THREADS = Sh::THREADS;
     constexpr int S3 = Sh::S3, CS = Sh::CS;
+    constexpr bool SKEW = Sh::SKEW;
 
     if (io.skip != nullptr && *io.skip) return;  // uniform over the grid
 
     __shared__ T s_u[CPB][Sh::U];      // the cell's nodal values
     __shared__ T s_w[CPB][Sh::W];      // work space of the cell and face passes
     __shared__ T s_geo[CPB][2][8][3];  // own / neighbour trilinear coefficients
+    __shared__ T s_sink[8];             // target of the geometry stores of lanes t >= 3
     __shared__ LaneTab<T, N> s_lt;
 
     CellIdx ci;
@@ -508,6 +551,8 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
     T* sw = s_w[lc];
     // thread t as a line: (la, lb) = (i2, i3) for xi_1 sweeps, (i1, i3) for xi_2 sweeps
     const int la = t % N, lb = t / N;
+    VolOff<N> vo;
+    vol_offsets<N, S3, SKEW>(la, lb, lc, vo);
 
     if (threadIdx.x < N) {
         const int j = threadIdx.x;
@@ -520,6 +565,12 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
     }
 
     // ------------------------------------------------------------ load; xi_3 derivative of the own line
+    T gown[8];
+    if constexpr (CURVED) trilinear_coeffs(op.verts, op.nx, op.ny, ci.ex, ci.ey, ci.ez, t % 3, gown);
+    T muq[N];  // viscosity on the own xi_3 line of quadrature points, loaded with the nodal values
+    if constexpr (C == 3)
+#pragma unroll
+        for (int q3 = 0; q3 < N; ++q3) muq[q3] = op.mu_cell[(size_t)ci.ec * NNN + q3 * NN + t];
     T g3[C][N];
     {
         const T* xe = io.x + (size_t)ci.ec * (C * NNN);
@@ -528,8 +579,9 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
             T col[N];
 #pragma unroll
             for (int j = 0; j < N; ++j) {
-                col[j] = ci.active ? xe[(c * N + j) * NN + t] : T(0);
-                su[c * CS + j * S3 + t] = col[j];
+                const T v = xe[(c * N + j) * NN + t];  // ec = 0 on inactive lanes: in bounds
+                col[j] = ci.active ? v : T(0);
+                su[c * CS + vo.oz[j]] = col[j];
             }
 #pragma unroll
             for (int q = 0; q < N; ++q) {
@@ -541,12 +593,9 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
         }
     }
     if constexpr (CURVED) {
-        if (t < 3) {
-            T g[8];
-            trilinear_coeffs(op.verts, op.nx, op.ny, ci.ex, ci.ey, ci.ez, t, g);
+        // unconditional stores (lanes t >= 3 write a sink) keep the loads at the top
 #pragma unroll
-            for (int k = 0; k < 8; ++k) s_geo[lc][0][k][t] = g[k];
-        }
+        for (int k = 0; k < 8; ++k) *(t < 3 ? &s_geo[lc][0][k][t] : &s_sink[k]) = gown[k];
     }
     __syncthreads();
     const LaneTab<T, N>& lt = s_lt;
@@ -567,8 +616,8 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
             T v[N], w[N];
 #pragma unroll
             for (int j = 0; j < N; ++j) {
-                v[j] = su[c * CS + lb * S3 + la * N + j];
-                w[j] = su[c * CS + lb * S3 + j * N + la];
+                v[j] = su[c * CS + vo.ox[j]];
+                w[j] = su[c * CS + vo.oy[j]];
             }
 #pragma unroll
             for (int q = 0; q < N; ++q) {
@@ -578,8 +627,8 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
                     a += tb.D[q][j] * v[j];
                     b += tb.D[q][j] * w[j];
                 }
-                W1[c * CS + lb * S3 + la * N + q] = a;
-                W2[c * CS + lb * S3 + q * N + la] = b;
+                W1[c * CS + vo.ox[q]] = a;
+                W2[c * CS + vo.oy[q]] = b;
             }
         }
         stage_sync<THREADS>();
@@ -623,14 +672,13 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
             T G[C][3];
 #pragma unroll
             for (int c = 0; c < C; ++c) {
-                const T g1 = W1[c * CS + q3 * S3 + t], g2 = W2[c * CS + q3 * S3 + t], gg3 = g3[c][q3];
+                const T g1 = W1[c * CS + vo.oz[q3]], g2 = W2[c * CS + vo.oz[q3]], gg3 = g3[c][q3];
 #pragma unroll
                 for (int i = 0; i < 3; ++i) G[c][i] = g1 * Ji[0][i] + g2 * Ji[1][i] + gg3 * Ji[2][i];
             }
             T S[C][3];
             if constexpr (C == 3) {
-                const T mu = ci.active ? op.mu_cell[(size_t)ci.ec * NNN + q3 * NN + t] : T(0);
-                const T f = mu * JxW;  // 2 mu eps = mu (G + G^T)
+                const T f = muq[q3] * JxW;  // 2 mu eps = mu (G + G^T)
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -642,10 +690,10 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
             const T mass = op.alpha * JxW;
 #pragma unroll
             for (int c = 0; c < C; ++c) {
-                W1[c * CS + q3 * S3 + t] = Ji[0][0] * S[c][0] + Ji[0][1] * S[c][1] + Ji[0][2] * S[c][2];
-                W2[c * CS + q3 * S3 + t] = Ji[1][0] * S[c][0] + Ji[1][1] * S[c][1] + Ji[1][2] * S[c][2];
+                W1[c * CS + vo.oz[q3]] = Ji[0][0] * S[c][0] + Ji[0][1] * S[c][1] + Ji[0][2] * S[c][2];
+                W2[c * CS + vo.oz[q3]] = Ji[1][0] * S[c][0] + Ji[1][1] * S[c][1] + Ji[1][2] * S[c][2];
                 g3[c][q3] = Ji[2][0] * S[c][0] + Ji[2][1] * S[c][1] + Ji[2][2] * S[c][2];
-                y[c][q3] = mass * su[c * CS + q3 * S3 + t];
+                y[c][q3] = mass * su[c * CS + vo.oz[q3]];
             }
         }
         stage_sync<THREADS>();
@@ -655,8 +703,8 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
             T v[N], w[N];
 #pragma unroll
             for (int q = 0; q < N; ++q) {
-                v[q] = W1[c * CS + lb * S3 + la * N + q];
-                w[q] = W2[c * CS + lb * S3 + q * N + la];
+                v[q] = W1[c * CS + vo.ox[q]];
+                w[q] = W2[c * CS + vo.oy[q]];
             }
 #pragma unroll
             for (int j = 0; j < N; ++j) {
@@ -666,8 +714,8 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
                     a += tb.D[q][j] * v[q];
                     b += tb.D[q][j] * w[q];
                 }
-                W1[c * CS + lb * S3 + la * N + j] = a;
-                W2[c * CS + lb * S3 + j * N + la] = b;
+                W1[c * CS + vo.ox[j]] = a;
+                W2[c * CS + vo.oy[j]] = b;
             }
         }
 #pragma unroll
@@ -683,7 +731,7 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
 #pragma unroll
         for (int c = 0; c < C; ++c)
 #pragma unroll
-            for (int i3 = 0; i3 < N; ++i3) y[c][i3] += W1[c * CS + i3 * S3 + t] + W2[c * CS + i3 * S3 + t];
+            for (int i3 = 0; i3 < N; ++i3) y[c][i3] += W1[c * CS + vo.oz[i3]] + W2[c * CS + vo.oz[i3]];
         stage_sync<THREADS>();
     }
 
@@ -692,9 +740,9 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
 #pragma unroll 1
         for (int f = 0; f < 6; ++f) {
             const int s = f & 1;
-            if (f < 2) face_pass<N, C, T, CURVED, 0, THREADS>(op, io, ci, s, y, su, sw, s_geo[lc], lt);
-            else if (f < 4) face_pass<N, C, T, CURVED, 1, THREADS>(op, io, ci, s, y, su, sw, s_geo[lc], lt);
-            else face_pass<N, C, T, CURVED, 2, THREADS>(op, io, ci, s, y, su, sw, s_geo[lc], lt);
+            if (f < 2) face_pass<N, C, T, CURVED, 0, THREADS>(op, io, ci, s, y, su, sw, s_geo[lc], lt, vo);
+            else if (f < 4) face_pass<N, C, T, CURVED, 1, THREADS>(op, io, ci, s, y, su, sw, s_geo[lc], lt, vo);
+            else face_pass<N, C, T, CURVED, 2, THREADS>(op, io, ci, s, y, su, sw, s_geo[lc], lt, vo);
         }
     }
 
@@ -715,7 +763,7 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
                 const size_t idx = base + (c * N + j) * NN + t;
                 const T dn = c1 * io.d[idx] + c2 * io.dinv[idx] * (io.r[idx] - y[c][j]);
                 io.d[idx] = dn;
-                io.y[idx] = su[c * CS + j * S3 + t] + dn;
+                io.y[idx] = su[c * CS + vo.oz[j]] + dn;
             }
     }
 }

@@ -9,12 +9,13 @@ namespace sipg {
 //   x_i(xi) = g0 + g1 xi1 + g2 xi2 + g3 xi3 + g4 xi1 xi2 + g5 xi1 xi3
 //           + g6 xi2 xi3 + g7 xi1 xi2 xi3,
 // from the 8 vertex coordinates X_abc (a along xi1, b along xi2, c along xi3).
+// 32-bit offsets: the plan rejects meshes with 2^31 or more vertex coordinates.
 template <typename T>
 __device__ __forceinline__ void trilinear_coeffs(const T* verts, int nx, int ny, int ex, int ey,
                                                  int ez, int i, T g[8]) {
-    auto X = [&](int a, int b, int c) {
-        return verts[(((size_t)(ez + c) * (ny + 1) + (ey + b)) * (nx + 1) + (ex + a)) * 3 + i];
-    };
+    const int sy = 3 * (nx + 1), sz = sy * (ny + 1);
+    const int base = ez * sz + ey * sy + ex * 3 + i;
+    auto X = [&](int a, int b, int c) { return verts[base + c * sz + b * sy + a * 3]; };
     const T x000 = X(0, 0, 0), x100 = X(1, 0, 0), x010 = X(0, 1, 0), x001 = X(0, 0, 1);
     const T x110 = X(1, 1, 0), x101 = X(1, 0, 1), x011 = X(0, 1, 1), x111 = X(1, 1, 1);
     g[0] = x000;
