@@ -315,115 +315,105 @@ __device__ __forceinline__ void face_pass(const OpData<T>& op, const ApplyIO<T>&
     stage_sync<THREADS>();
 
     // ---- B2: geometry and flux at the face point
+    //
+    // Own side: columns a_d = dx/dxi_d, adjugate rows c_d (c_0 = a_1 x a_2 and
+    // cyclic), J^-1 = rows c_d / det.  The neighbour's Jacobian J' differs only
+    // in column D, and its adjugate row D equals c_D, so with M = J'^-1 J
+    // (identity except column D, v = J'^-1 a_D: v_D = det / det',
+    // v_d = -(a'_D . c_d) / det' for d != D, det' = a'_D . c_D) the sum of the
+    // two physical gradients is (gr + gr' M) J^-1: one transformation with the
+    // own J^-1 for both sides.  The unit normal is sign * c_D / |c_D| and
+    // ds = |c_D| w_a w_b.  On straight cells J^-1 = diag(1/h) and M = I.
     T xi[3];
     xi[t1] = lt.x[i1];
     xi[t2] = lt.x[i2];
     xi[D] = T(s);
     const T sgn = s == 1 ? T(1) : T(-1);
-    T nrm[3], ds, mo[3], p[3], en_[C];
-    T at1[3], at2[3];  // tangential Jacobian columns, shared with the neighbour
-    {
-        T Jo[3][3];
-        if constexpr (CURVED) {
-            T a[3][3], det;
-            jac_columns(geo[0], xi, a);
-#pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                at1[i] = a[t1][i];
-                at2[i] = a[t2][i];
-            }
-            inverse_from_columns(a, Jo, det);
-            // row D of J^-1 is (a_t1 x a_t2)/det: n = sign row/|row|, ds = det |row| w_a w_b
-            const T v0 = Jo[D][0], v1 = Jo[D][1], v2 = Jo[D][2];
-            const T nv2 = v0 * v0 + v1 * v1 + v2 * v2;
-            const T rinv = rsqrt_nr(nv2);
-            nrm[0] = sgn * v0 * rinv; nrm[1] = sgn * v1 * rinv; nrm[2] = sgn * v2 * rinv;
-            ds = det * (nv2 * rinv) * (lt.w[i1] * lt.w[i2]);
-        } else {
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-#pragma unroll
-                for (int b = 0; b < 3; ++b) Jo[a][b] = a == b ? op.hinv[a] : T(0);
-            nrm[0] = nrm[1] = nrm[2] = T(0);
-            nrm[D] = sgn;
-            ds = op.h[t1] * op.h[t2] * (lt.w[i1] * lt.w[i2]);
-        }
-        // m = J^-1 n:  (grad u) n = gr . m for the reference gradient gr;  p = J^-1 [u]
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            mo[d] = Jo[d][0] * nrm[0] + Jo[d][1] * nrm[1] + Jo[d][2] * nrm[2];
-            if constexpr (C == 3) p[d] = Jo[d][0] * ju[0] + Jo[d][1] * ju[1] + Jo[d][2] * ju[2];
-        }
-        T gr[C][3];
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            gr[c][t1] = TD[(0 * C + c) * NN + t];
-            gr[c][t2] = TD[(1 * C + c) * NN + t];
-            gr[c][D] = uno[c];
-        }
-        // viscous: (G + G^T) n with G n = gr.m and (G^T n)_c = sum_d J^-1[d][c] (n . gr[:, d]);
-        // poisson: G . n
-        if constexpr (C == 3) {
-            T w[3];
-#pragma unroll
-            for (int d = 0; d < 3; ++d) w[d] = nrm[0] * gr[0][d] + nrm[1] * gr[1][d] + nrm[2] * gr[2][d];
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-                en_[c] = gr[c][0] * mo[0] + gr[c][1] * mo[1] + gr[c][2] * mo[2] +
-                         Jo[0][c] * w[0] + Jo[1][c] * w[1] + Jo[2][c] * w[2];
-        } else {
-            en_[0] = gr[0][0] * mo[0] + gr[0][1] * mo[1] + gr[0][2] * mo[2];
-        }
-    }
-    if (has_nb) {
-        T Jn[3][3];
-        if constexpr (CURVED) {
-            // the neighbour's Jacobian differs from the own one only in the xi_D column
+    T Cr[3][3], idet;  // rows c_d (curved: adjugate, 1/det; straight: J^-1, 1)
+    T nrm[3], ds;
+    T v[3];            // curved: column D of M
+    if constexpr (CURVED) {
+        T a[3][3];
+        jac_columns(geo[0], xi, a);
+        cross3(a[1], a[2], Cr[0]);
+        cross3(a[2], a[0], Cr[1]);
+        cross3(a[0], a[1], Cr[2]);
+        const T det = a[0][0] * Cr[0][0] + a[0][1] * Cr[0][1] + a[0][2] * Cr[0][2];
+        idet = recip(det);
+        const T nv2 = Cr[D][0] * Cr[D][0] + Cr[D][1] * Cr[D][1] + Cr[D][2] * Cr[D][2];
+        const T rinv = rsqrt_nr(nv2);
+        const T sr = sgn * rinv;
+        nrm[0] = Cr[D][0] * sr; nrm[1] = Cr[D][1] * sr; nrm[2] = Cr[D][2] * sr;
+        ds = (nv2 * rinv) * (lt.w[i1] * lt.w[i2]);
+        if (has_nb) {
+            // the neighbour's xi_D column at the same face point
             T xin[3] = {xi[0], xi[1], xi[2]};
             xin[D] = T(1 - s);
             const T(*g)[3] = geo[1];
-            T a[3][3];
+            T an[3];
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                a[t1][i] = at1[i];
-                a[t2][i] = at2[i];
-                if (D == 0) a[0][i] = g[1][i] + g[4][i] * xin[1] + g[5][i] * xin[2] + g[7][i] * (xin[1] * xin[2]);
-                if (D == 1) a[1][i] = g[2][i] + g[4][i] * xin[0] + g[6][i] * xin[2] + g[7][i] * (xin[0] * xin[2]);
-                if (D == 2) a[2][i] = g[3][i] + g[5][i] * xin[0] + g[6][i] * xin[1] + g[7][i] * (xin[0] * xin[1]);
+                if (D == 0) an[i] = g[1][i] + g[4][i] * xin[1] + g[5][i] * xin[2] + g[7][i] * (xin[1] * xin[2]);
+                if (D == 1) an[i] = g[2][i] + g[4][i] * xin[0] + g[6][i] * xin[2] + g[7][i] * (xin[0] * xin[2]);
+                if (D == 2) an[i] = g[3][i] + g[5][i] * xin[0] + g[6][i] * xin[1] + g[7][i] * (xin[0] * xin[1]);
             }
-            T detn;
-            inverse_from_columns(a, Jn, detn);
-        } else {
+            const T rdn = recip(an[0] * Cr[D][0] + an[1] * Cr[D][1] + an[2] * Cr[D][2]);
 #pragma unroll
-            for (int a = 0; a < 3; ++a)
-#pragma unroll
-                for (int b = 0; b < 3; ++b) Jn[a][b] = a == b ? op.hinv[a] : T(0);
-        }
-        T mn[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) mn[d] = Jn[d][0] * nrm[0] + Jn[d][1] * nrm[1] + Jn[d][2] * nrm[2];
-        T gr[C][3];
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            gr[c][t1] = TD[(2 * C + c) * NN + t];
-            gr[c][t2] = TD[(3 * C + c) * NN + t];
-            gr[c][D] = unn[c];
-        }
-        if constexpr (C == 3) {
-            T w[3];
-#pragma unroll
-            for (int d = 0; d < 3; ++d) w[d] = nrm[0] * gr[0][d] + nrm[1] * gr[1][d] + nrm[2] * gr[2][d];
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-                en_[c] += gr[c][0] * mn[0] + gr[c][1] * mn[1] + gr[c][2] * mn[2] +
-                          Jn[0][c] * w[0] + Jn[1][c] * w[1] + Jn[2][c] * w[2];
-        } else {
-            en_[0] += gr[0][0] * mn[0] + gr[0][1] * mn[1] + gr[0][2] * mn[2];
+            for (int d = 0; d < 3; ++d)
+                v[d] = d == D ? det * rdn : -(an[0] * Cr[d][0] + an[1] * Cr[d][1] + an[2] * Cr[d][2]) * rdn;
         }
     } else {
-        // mirror principle on a Dirichlet face: grad u+ = grad u- (u+ = -u- is in ju)
 #pragma unroll
-        for (int c = 0; c < C; ++c) en_[c] *= T(2);
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) Cr[a][b] = a == b ? op.hinv[a] : T(0);
+        idet = T(1);
+        nrm[0] = nrm[1] = nrm[2] = T(0);
+        nrm[D] = sgn;
+        ds = op.h[t1] * op.h[t2] * (lt.w[i1] * lt.w[i2]);
+    }
+    // gs = gr + gr' M: reference gradient of both sides in the own frame
+    // (Dirichlet mirror: grad u+ = grad u-, so gs = 2 gr)
+    T gs[C][3];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const T o1 = TD[(0 * C + c) * NN + t], o2 = TD[(1 * C + c) * NN + t];
+        if (has_nb) {
+            const T n1 = TD[(2 * C + c) * NN + t], n2 = TD[(3 * C + c) * NN + t];
+            gs[c][t1] = o1 + n1;
+            gs[c][t2] = o2 + n2;
+            if constexpr (CURVED) {
+                T nr[3];
+                nr[t1] = n1; nr[t2] = n2; nr[D] = unn[c];
+                gs[c][D] = uno[c] + (nr[0] * v[0] + nr[1] * v[1] + nr[2] * v[2]);
+            } else {
+                gs[c][D] = uno[c] + unn[c];
+            }
+        } else {
+            gs[c][t1] = T(2) * o1;
+            gs[c][t2] = T(2) * o2;
+            gs[c][D] = T(2) * uno[c];
+        }
+    }
+    // m' = adj n (J^-1 n = m' / det), p' = adj [u]
+    T mo[3], p[3], en_[C];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        mo[d] = Cr[d][0] * nrm[0] + Cr[d][1] * nrm[1] + Cr[d][2] * nrm[2];
+        if constexpr (C == 3) p[d] = Cr[d][0] * ju[0] + Cr[d][1] * ju[1] + Cr[d][2] * ju[2];
+    }
+    // viscous: (G + G^T) n of the summed gradient G = gs J^-1, with G n = gs m
+    // and (G^T n)_c = sum_d J^-1[d][c] (n . gs[:, d]);  poisson: G . n
+    if constexpr (C == 3) {
+        T w[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) w[d] = nrm[0] * gs[0][d] + nrm[1] * gs[1][d] + nrm[2] * gs[2][d];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            en_[c] = (gs[c][0] * mo[0] + gs[c][1] * mo[1] + gs[c][2] * mo[2] +
+                      Cr[0][c] * w[0] + Cr[1][c] * w[1] + Cr[2][c] * w[2]) * idet;
+    } else {
+        en_[0] = (gs[0][0] * mo[0] + gs[0][1] * mo[1] + gs[0][2] * mo[2]) * idet;
     }
     const T mu = (C == 3 && live) ? mu_pre : T(1);
     const T tau = live ? tf_pre * mu : T(0);
@@ -432,10 +422,10 @@ __device__ __forceinline__ void face_pass(const OpData<T>& op, const ApplyIO<T>&
     T av[C], Bh[C][3];
     if constexpr (C == 3) {
         // a = -2 {{mu eps(u)}} n + tau ([u] + n([u].n)),  B = -mu sym([u] (x) n),
-        // B^ = J^-1 B:  B^[c][d] = -mu/2 (ju_c m_d + n_c p_d)
+        // B^ = J^-1 B:  B^[c][d] = -mu/2 (ju_c m_d + n_c p_d) / det
         const T jn = ju[0] * nrm[0] + ju[1] * nrm[1] + ju[2] * nrm[2];
         const T dl = ds * lf;
-        const T hm = -T(0.5) * mu * dl;
+        const T hm = -T(0.5) * mu * dl * idet;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             av[c] = dl * (-T(0.5) * mu * en_[c] + tau * (ju[c] + nrm[c] * jn));
@@ -446,8 +436,9 @@ __device__ __forceinline__ void face_pass(const OpData<T>& op, const ApplyIO<T>&
         // a = -{{grad u}}.n + tau [u],  B = -[u] n / 2,  B^ = -[u] m / 2
         const T dl = ds * lf;
         av[0] = dl * (-T(0.5) * en_[0] + tau * ju[0]);
+        const T hb = -T(0.5) * dl * ju[0] * idet;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) Bh[0][d] = -T(0.5) * dl * ju[0] * mo[d];
+        for (int d = 0; d < 3; ++d) Bh[0][d] = hb * mo[d];
     }
     stage_sync<THREADS>();  // TD reads done before BT/VT overwrite the space
 #pragma unroll
