@@ -27,6 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, published
+FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 vector, published
 METRIC = "operator DoF/s FP64 vs mixed; solves/s and p50/p99 latency at 1e-8 rel. res."
 KERNEL_SRC = os.path.join(ROOT, "paper_2506_14424_amd", "csrc", "apply.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_apply_c2.json")
@@ -110,12 +111,15 @@ def cpu_baseline(cfg, V):
         threads = os.cpu_count() or 1
     pb = Problem.from_config(cfg, V)
     x = W.uniform_vector(cfg["x_seed"], pb.ndof)
-    t0 = time.perf_counter()
-    oracle_apply(pb, x)
-    dt = time.perf_counter() - t0
-    return {"value": pb.ndof / dt, "unit": "DoF/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"one full FP64 apply of the same workload by the oracle's direct quadrature "
-                      f"evaluation ({pb.ndof} unknowns, {dt:.1f} s, numpy/BLAS threads={threads})"}
+    reps, dt = 0, 0.0
+    while reps < 3 and (reps == 0 or dt < 10.0):   # bounded: about 10-20 s of CPU work
+        t0 = time.perf_counter()
+        oracle_apply(pb, x)
+        dt += time.perf_counter() - t0
+        reps += 1
+    return {"value": reps * pb.ndof / dt, "unit": "DoF/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{reps} full FP64 applies of the same workload by the oracle's direct quadrature "
+                      f"evaluation ({pb.ndof} unknowns each, {dt:.1f} s in total, numpy/BLAS threads={threads})"}
 
 
 def solve_compare(tol=1e-8):
@@ -212,11 +216,15 @@ def main():
     b64 = algorithmic_bytes(cfg, 8)
     b32 = algorithmic_bytes(cfg, 4)
     achieved = b64["total"] / (ms64 * 1e-3) / 1e9
-    traffic = None
+    # HBM bytes and FP64 operations per launch measured with rocprofv3 counters
+    # (FETCH_SIZE, WRITE_SIZE scaled by a plain copy of known size; SQ FP64
+    # instruction counts); only used while the kernel source is unchanged
+    traffic, counters = None, None
     if os.path.exists(TRAFFIC_FILE):
         tr = json.load(open(TRAFFIC_FILE))
         if tr.get("kernel_hash") == kernel_hash():
-            traffic = tr.get("bytes_per_launch")
+            counters = tr
+            traffic = tr["fetch_bytes_per_launch"] + tr["write_bytes_per_launch"]
     line = {
         "metric": METRIC,
         "value": value,
@@ -240,7 +248,21 @@ def main():
                      "kernel": "k_apply<n=4,C=3,double,curved>",
                      "algorithmic_bytes_per_launch": b64["total"],
                      "algorithmic_bytes_per_dof": b64["per_dof"],
-                     "avg_launch_ms": ms64},
+                     "avg_launch_ms": ms64,
+                     "traffic_detail": None if counters is None else {
+                         "fetch_bytes": counters["fetch_bytes_per_launch"],
+                         "write_bytes": counters["write_bytes_per_launch"],
+                         "fetch_over_algorithmic_reads": counters["fetch_bytes_per_launch"] / (b64["total"] - b64["vectors"] / 2),
+                         "source": os.path.relpath(TRAFFIC_FILE, ROOT)},
+                     "fp64_alu": None if counters is None else {
+                         "flops_per_launch": counters["fp64_flops_per_launch"],
+                         "flops_per_dof": counters["fp64_flops_per_launch"] / op.ndof,
+                         "achieved_tflops": counters["fp64_flops_per_launch"] / (ms64 * 1e-3) / 1e12,
+                         "peak_tflops": FP64_PEAK_TFLOPS,
+                         "frac": counters["fp64_flops_per_launch"] / (ms64 * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+                         "note": "executed FP64 operations (FMA counted twice) from SQ counters: the "
+                                 "kernel's arithmetic intensity is above the FP64 ridge, so the vector "
+                                 "ALU, not HBM, is the binding roof"}},
         "hot_cache": {"dof_per_s": op.ndof * k / (r64["hot_event_ms"] * 1e-3),
                       "note": "same (x, y) pair every step: inputs served from the 256 MB last-level cache"},
         "fp32_apply": {"dof_per_s": op.ndof * k / (r32["event_ms"] * 1e-3),

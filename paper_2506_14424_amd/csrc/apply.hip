@@ -53,7 +53,10 @@ struct Shape {
     // per-cell LDS: nodal values and a work space for the cell sweeps and the
     // face stages; +1 staggers consecutive cells over the LDS banks (plain layout)
     static constexpr int U = C * CS + (SKEW ? 0 : 1);
-    static constexpr int W = (2 * C * CS > 8 * C * NN ? 2 * C * CS : 8 * C * NN) + (SKEW ? 0 : 1);
+    // work-space stride: skewed layout +8 (the four cells of a wavefront at
+    // offsets 0, 8, 16, 24 mod 32 doubles: line tasks and lane-per-point
+    // accesses of the face stages spread over all bank pairs), else +1
+    static constexpr int W = (2 * C * CS > 8 * C * NN ? 2 * C * CS : 8 * C * NN) + (SKEW ? 8 : 1);
 };
 
 // Barrier between LDS stages.  A workgroup of one wavefront only needs the
@@ -521,8 +524,11 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
 
     __shared__ T s_u[CPB][Sh::U];      // the cell's nodal values
     __shared__ T s_w[CPB][Sh::W];      // work space of the cell and face passes
-    __shared__ T s_geo[CPB][2][8][3];  // own / neighbour trilinear coefficients
-    __shared__ T s_sink[8];             // target of the geometry stores of lanes t >= 3
+    // own / neighbour trilinear coefficients, [2][8][3] per cell; the odd cell
+    // stride puts the four cells of a wavefront on different banks (their
+    // reads are per-cell broadcasts)
+    constexpr int GS = 2 * 8 * 3 + 1;
+    __shared__ T s_geo_all[CPB * GS];
     __shared__ LaneTab<T, N> s_lt;
 
     CellIdx ci;
@@ -537,6 +543,7 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
     ci.ey = (ci.ec / op.nx) % op.ny;
     ci.ez = ci.ec / (op.nx * op.ny);
     const int lc = ci.lc, t = ci.t, i1 = ci.i1, i2 = ci.i2;
+    T(*geo)[8][3] = reinterpret_cast<T(*)[8][3]>(s_geo_all + lc * GS);
     const auto& tb = op.tab;
     T* su = s_u[lc];
     T* sw = s_w[lc];
@@ -584,9 +591,10 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
         }
     }
     if constexpr (CURVED) {
-        // unconditional stores (lanes t >= 3 write a sink) keep the loads at the top
+        // unconditional stores keep the loads at the top (lanes t >= 3 write into the
+        // neighbour slot, which every face stage rewrites before reading it)
 #pragma unroll
-        for (int k = 0; k < 8; ++k) *(t < 3 ? &s_geo[lc][0][k][t] : &s_sink[k]) = gown[k];
+        for (int k = 0; k < 8; ++k) *(t < 3 ? &geo[0][k][t] : &geo[1][k][0]) = gown[k];
     }
     __syncthreads();
     const LaneTab<T, N>& lt = s_lt;
@@ -628,7 +636,7 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
         // a_1 = A1 + B1 xi_3 and a_2 constant.
         T A0[3], B0[3], A1[3], B1[3], a2c[3];
         if constexpr (CURVED) {
-            const T(*g)[3] = s_geo[lc][0];
+            const T(*g)[3] = geo[0];
             const T x1 = lt.x[i1], x2 = lt.x[i2];
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
@@ -731,9 +739,9 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
 #pragma unroll 1
         for (int f = 0; f < 6; ++f) {
             const int s = f & 1;
-            if (f < 2) face_pass<N, C, T, CURVED, 0, THREADS>(op, io, ci, s, y, su, sw, s_geo[lc], lt, vo);
-            else if (f < 4) face_pass<N, C, T, CURVED, 1, THREADS>(op, io, ci, s, y, su, sw, s_geo[lc], lt, vo);
-            else face_pass<N, C, T, CURVED, 2, THREADS>(op, io, ci, s, y, su, sw, s_geo[lc], lt, vo);
+            if (f < 2) face_pass<N, C, T, CURVED, 0, THREADS>(op, io, ci, s, y, su, sw, geo, lt, vo);
+            else if (f < 4) face_pass<N, C, T, CURVED, 1, THREADS>(op, io, ci, s, y, su, sw, geo, lt, vo);
+            else face_pass<N, C, T, CURVED, 2, THREADS>(op, io, ci, s, y, su, sw, geo, lt, vo);
         }
     }
 
