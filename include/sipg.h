@@ -201,7 +201,9 @@ sipg_status sipg_solve(sipg_plan* plan, const double* b, double* x, const sipg_s
 /* Asynchronous form of sipg_solve for interleaving many solves:
  * begin enqueues the eigenvalue estimate and the CG start on `stream` (the
  * solve stays bound to it); advance enqueues up to `iters` more iterations
- * (iterations after convergence are skipped on the device); poll returns
+ * (iterations after convergence are skipped on the device; nothing is
+ * enqueued while poll's true-residual check is pending or after the solve
+ * has finished); poll returns
  * immediately with *done = 1 once the solve has finished and `info` filled,
  * enqueueing the true-residual check and restarts itself when needed.
  * b and x must stay valid until done. */

@@ -61,6 +61,11 @@ def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2506_14424_amd.build` "
                           "(there is no CPU fallback)")
+    # torch ships its own HIP runtime; importing it first makes the library
+    # bind to that runtime (by soname) instead of loading a second HIP and HSA
+    # runtime into the process, which cannot share streams or device pointers
+    # with torch's and crashes the process
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     P = C.c_void_p
     st = C.c_int32

@@ -642,7 +642,7 @@ sipg_status sipg_solve_begin(sipg_plan* P, const double* b, double* x, const sip
 sipg_status sipg_solve_advance(sipg_plan* P, int32_t iters) {
     if (!valid_plan(P)) return fail(SIPG_ERR_INVALID, "null plan");
     if (P->phase == PH_IDLE) return fail(SIPG_ERR_STATE, "no solve in progress");
-    if (P->phase == PH_DONE || iters <= 0) return SIPG_OK;
+    if (P->phase != PH_RUNNING || iters <= 0) return SIPG_OK;  // checking, done: nothing to enqueue
     const sipg_status rc = P->opts.precond_precision == SIPG_F32 ? cg_iterations<float>(P, iters)
                                                                  : cg_iterations<double>(P, iters);
     if (rc != SIPG_OK) return rc;

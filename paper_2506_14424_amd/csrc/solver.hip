@@ -210,14 +210,14 @@ __device__ void scalar_step(SolveState* st, int op, double s0, double s1, long l
 }
 
 // One-block reduction of the partials in a fixed order, then the scalar step.
-__global__ void k_scalar(SolveState* st, const double* partials, int nslots, int op, long long n,
+__global__ void k_scalar(SolveState* st, const double* partials, int nslots, int nblocks, int op, long long n,
                          int respect_skip) {
     if (respect_skip && st->skip) return;
     __shared__ double sh[2][kRedThreads];
     for (int k = 0; k < 2; ++k) {
         double s = 0.0;
         if (k < nslots)
-            for (int i = threadIdx.x; i < kRedBlocks; i += kRedThreads) s += partials[k * kRedBlocks + i];
+            for (int i = threadIdx.x; i < nblocks; i += kRedThreads) s += partials[k * kRedBlocks + i];
         sh[k][threadIdx.x] = s;
     }
     __syncthreads();
@@ -423,10 +423,16 @@ __global__ void k_state_resume(SolveState* st, int max_iter) {
 
 // ---------------------------------------------------------------- launchers
 
-static inline dim3 red_grid() { return dim3(kRedBlocks); }
+// Reduction grids shrink with the vector (at least 4 elements per thread) so
+// that small solves do not pay for hundreds of idle blocks per kernel.
+static inline int red_blocks(long long n) {
+    const long long b = (n + 4 * kRedThreads - 1) / (4 * kRedThreads);
+    return (int)(b < 1 ? 1 : b > kRedBlocks ? kRedBlocks : b);
+}
+static inline dim3 red_grid(long long n) { return dim3(red_blocks(n)); }
 static inline dim3 red_block() { return dim3(kRedThreads); }
 
-#define L(kern, ...) hipLaunchKernelGGL(kern, red_grid(), red_block(), 0, s, __VA_ARGS__)
+#define L(kern, ...) hipLaunchKernelGGL(kern, red_grid(n), red_block(), 0, s, __VA_ARGS__)
 
 void sk_lz_start(double* v, long long n, unsigned long long seed, double* partials, hipStream_t s) {
     L(k_lz_start, v, n, seed, partials);
@@ -450,7 +456,8 @@ void sk_lz_finish(SolveState* st, double safety, double ratio, int degree, hipSt
 }
 void sk_scalar(SolveState* st, const double* partials, int nslots, int op, long long n, hipStream_t s,
                int respect_skip) {
-    hipLaunchKernelGGL(k_scalar, dim3(1), dim3(kRedThreads), 0, s, st, partials, nslots, op, n, respect_skip);
+    hipLaunchKernelGGL(k_scalar, dim3(1), dim3(kRedThreads), 0, s, st, partials, nslots, red_blocks(n), op, n,
+                       respect_skip);
 }
 void sk_sum(const double* x, long long n, double* partials, const SolveState* st, hipStream_t s) {
     L(k_sum, x, n, partials, st);

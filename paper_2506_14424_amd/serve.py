@@ -43,11 +43,13 @@ class Request:
 class GpuExecutor:
     """Runs each request as one libsipg plan on a pool of HIP streams."""
 
-    def __init__(self, n_streams: int = 8, precond: str = "f32", keep_solutions: bool = False):
+    def __init__(self, n_streams: int = 8, precond: str = "f32", keep_solutions: bool = False,
+                 depth: int = 2):
         import torch
         self.streams = [torch.cuda.Stream() for _ in range(n_streams)]   # default priority
         self.precond = precond
         self.keep = keep_solutions
+        self.depth = depth
         self._rr = 0
 
     def prepare(self, req: Request):
@@ -67,10 +69,24 @@ class GpuExecutor:
             op.bind(with_solver=True, stream=stream)
             op.solve_begin(b, x, SolveOptions(rel_tol=req.tol, precond_precision=self.precond),
                            stream=stream)
-        return (op, b, x, stream)
+        return (op, b, x, stream, [])
 
     def advance(self, handle, iters: int):
+        """Enqueue `iters` more iterations, keeping at most `depth` rounds in
+        flight per request: a request whose earlier rounds are still queued
+        on its stream gets no new work this round, so a solve that has
+        converged on the device is seen by poll() after at most that many
+        rounds instead of after an ever-growing queue of skipped kernels."""
+        import torch
+        inflight = handle[4]
+        while inflight and inflight[0].query():
+            inflight.pop(0)
+        if len(inflight) >= self.depth:
+            return
         handle[0].solve_advance(iters)
+        ev = torch.cuda.Event()
+        ev.record(handle[3])
+        inflight.append(ev)
 
     def poll(self, handle):
         return handle[0].solve_poll()

@@ -88,3 +88,18 @@ def test_package_has_no_cpu_fallback():
     import paper_2506_14424_amd.operator as opmod
     src = open(opmod.__file__).read()
     assert "oracle" not in src and "numpy.linalg" not in src
+
+
+def test_package_import_loads_a_single_hip_runtime():
+    """Importing the binding before torch must not load a second HIP runtime
+    next to torch's (two runtimes in one process cannot share streams or
+    device pointers): the package imports torch before opening the library."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "import paper_2506_14424_amd\n"
+            "libs = set(l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l)\n"
+            "print(len(libs))\n") % ROOT
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr[-2000:]
+    assert out.stdout.strip().splitlines()[-1] == "1"
