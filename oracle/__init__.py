@@ -24,7 +24,10 @@ What it computes, and from which passage:
 * the viscosity laws of Sec. 2 (generalised Newtonian law) and smooth
   prescribed fields, evaluated pointwise at quadrature points (Sec. 4.1);
 * the matrix diagonal, a Chebyshev-accelerated Jacobi preconditioner and a
-  flexible CG with FP64 outer iteration (Sec. 5.3).
+  flexible CG with FP64 outer iteration (Sec. 5.3);
+* the hp-multigrid V-cycle preconditioner of Sec. 5.3 (degree lowered from
+  k to 1, then mesh coarsening, Chebyshev-Jacobi smoothing on every level),
+  in ``multigrid``.
 
 Two evaluation modes: ``assemble`` builds the global sparse matrix cell by
 cell and face by face (small meshes); ``apply`` evaluates the same quadrature

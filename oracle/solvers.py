@@ -121,12 +121,14 @@ def flexible_cg(apply, b, precond, tol, max_iter, x0=None, bnorm=None, project=N
 def solve(apply, diag: np.ndarray, b: np.ndarray, tol: float = 1e-8, max_iter: int = 2000,
           cheb_degree: int = 5, cheb_ratio: float = 20.0, safety: float = 1.2,
           lanczos_steps: int = 20, seed: int = 12345, mean_zero: bool = False,
-          max_restarts: int = 3, precond_apply=None):
+          max_restarts: int = 3, precond_apply=None, precond=None):
     """Solve A x = b to ||b - A x|| <= tol ||b||; returns (x, info dict).
 
     precond_apply (default: apply) is the operator used inside the
     Chebyshev-Jacobi preconditioner, so a lower-precision action can be
-    substituted there while the outer iteration stays in FP64."""
+    substituted there while the outer iteration stays in FP64; `precond`
+    (r -> z) replaces the Chebyshev-Jacobi preconditioner altogether (the
+    multigrid V-cycle of ``oracle.multigrid``)."""
     precond_apply = precond_apply or apply
     dinv = 1.0 / diag
     b = np.asarray(b, dtype=np.float64)
@@ -136,7 +138,7 @@ def solve(apply, diag: np.ndarray, b: np.ndarray, tol: float = 1e-8, max_iter: i
     lam = lanczos_max(apply, dinv, lanczos_steps, seed)
     lam_hi = safety * lam
     lam_lo = lam_hi / cheb_ratio
-    M = lambda r: chebyshev_jacobi(precond_apply, dinv, r, cheb_degree, lam_hi, lam_lo)
+    M = precond or (lambda r: chebyshev_jacobi(precond_apply, dinv, r, cheb_degree, lam_hi, lam_lo))
     bnorm = float(np.linalg.norm(b))
     x, its, status = flexible_cg(apply, b, M, tol, max_iter, bnorm=bnorm, project=project)
     total, restarts = its, 0
