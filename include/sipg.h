@@ -119,7 +119,30 @@ typedef struct {
     int32_t lanczos_steps;     /* 1..64 */
     int32_t check_every;       /* sipg_solve: iterations between host read-backs */
     int32_t max_restarts;      /* defect-correction restarts */
+    int32_t precond_kind;      /* sipg_precond_kind; MULTIGRID needs sipg_plan_set_multigrid */
 } sipg_solve_opts;
+
+/* Preconditioner of the FP64 CG (Sec. 5.3): Chebyshev-accelerated Jacobi on
+ * the operator itself, or V-cycles of the hp-multigrid hierarchy with the
+ * same Chebyshev-Jacobi smoother on every level. */
+typedef enum { SIPG_PRECOND_CHEBYSHEV = 0, SIPG_PRECOND_MULTIGRID = 1 } sipg_precond_kind;
+
+/* hp-multigrid hierarchy (Sec. 5.3): the polynomial degree is lowered from
+ * k to k-1 down to 1 on the plan's mesh, then the mesh is coarsened by two
+ * in every direction (every other vertex) while all cell counts are even and
+ * at least min_cells.  Levels stay discontinuous; transfers embed the coarse
+ * polynomial of a cell in the fine space (restriction is the transpose);
+ * every level evaluates the viscosity law at its own quadrature points and
+ * has its own inverse diagonal and eigenvalue estimate.  Smoothing:
+ * opts->cheb_degree Chebyshev-Jacobi steps before and after the coarse
+ * correction; the coarsest level gets one Chebyshev-Jacobi polynomial of
+ * degree coarse_degree (in place of the paper's AMG cycles). */
+typedef struct {
+    int32_t coarse_degree;     /* 1..63 */
+    int32_t min_cells;         /* >= 1 */
+    int32_t max_levels;        /* >= 1, including the finest */
+    int32_t h_coarsen;         /* 0: degree lowering only */
+} sipg_mg_opts;
 
 typedef struct {
     int32_t iterations;
@@ -197,6 +220,34 @@ void sipg_solve_opts_default(sipg_solve_opts* opts);
  * until done; info may be NULL.  Returns the solve's status. */
 sipg_status sipg_solve(sipg_plan* plan, const double* b, double* x, const sipg_solve_opts* opts,
                        sipg_solve_info* info, void* stream);
+
+void sipg_mg_opts_default(sipg_mg_opts* opts);   /* 12, 2, 16, 1 */
+
+/* Builds the multigrid hierarchy of a plan (host only).  Must be called
+ * before sipg_plan_workspace_bytes / sipg_plan_bind: the coarse levels' data
+ * (viscosity, diagonals, vectors) then live in the same caller-owned
+ * workspace, and binding sets up every level.  Errors: INVALID options,
+ * STATE if the plan is already bound. */
+sipg_status sipg_plan_set_multigrid(sipg_plan* plan, const sipg_mg_opts* opts);
+
+/* Number of levels (1 without a hierarchy); with non-NULL arrays of `cap`
+ * entries (3*cap for cells), the degree and cells per direction of each
+ * level, finest first. */
+int32_t sipg_multigrid_levels(const sipg_plan* plan, int32_t* degrees, int32_t* cells, int32_t cap);
+
+/* Transfer between multigrid level `level` and level+1 (0 = finest) in
+ * precision (sipg_precision), device vectors of the two levels' sizes:
+ * restrict != 0: out(level+1) = P^T in(level); else out(level) += P in(level+1).
+ * Needs a bound plan with a hierarchy; stream-ordered. */
+sipg_status sipg_multigrid_transfer(sipg_plan* plan, int32_t level, int32_t restrict_, int32_t precision,
+                                    const void* in, void* out, void* stream);
+
+/* One application z = M r of the preconditioner selected by opts
+ * (r, z: device FP64, ndof; may alias) in opts->precond_precision, after
+ * the eigenvalue estimates it needs (cached per plan).  Needs a plan bound
+ * with_solver and no solve in progress; stream-ordered. */
+sipg_status sipg_precondition(sipg_plan* plan, const double* r, double* z, const sipg_solve_opts* opts,
+                              void* stream);
 
 /* Asynchronous form of sipg_solve for interleaving many solves:
  * begin enqueues the eigenvalue estimate and the CG start on `stream` (the

@@ -8,6 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsipg.so")
 
 PART_CELL, PART_INTERIOR, PART_BOUNDARY, PART_ALL = 1, 2, 4, 7
+PRECOND = {"chebyshev": 0, "multigrid": 1}
 F64, F32 = 0, 1
 VISCOUS, POISSON = 0, 1
 BC = {"D": 0, "N": 1}
@@ -49,7 +50,13 @@ class Params(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("rel_tol", C.c_double), ("max_iter", C.c_int32), ("precond_precision", C.c_int32),
                 ("cheb_degree", C.c_int32), ("cheb_ratio", C.c_double), ("cheb_safety", C.c_double),
-                ("lanczos_steps", C.c_int32), ("check_every", C.c_int32), ("max_restarts", C.c_int32)]
+                ("lanczos_steps", C.c_int32), ("check_every", C.c_int32), ("max_restarts", C.c_int32),
+                ("precond_kind", C.c_int32)]
+
+
+class MgOpts(C.Structure):
+    _fields_ = [("coarse_degree", C.c_int32), ("min_cells", C.c_int32), ("max_levels", C.c_int32),
+                ("h_coarsen", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -87,6 +94,11 @@ def _load():
         "sipg_solve_begin": (st, [P, P, P, C.POINTER(SolveOpts), P]),
         "sipg_solve_advance": (st, [P, C.c_int32]),
         "sipg_solve_poll": (st, [P, C.POINTER(C.c_int32), C.POINTER(SolveInfo)]),
+        "sipg_mg_opts_default": (None, [C.POINTER(MgOpts)]),
+        "sipg_plan_set_multigrid": (st, [P, C.POINTER(MgOpts)]),
+        "sipg_multigrid_levels": (C.c_int32, [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int32]),
+        "sipg_precondition": (st, [P, P, P, C.POINTER(SolveOpts), P]),
+        "sipg_multigrid_transfer": (st, [P, C.c_int32, C.c_int32, C.c_int32, P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

@@ -144,6 +144,15 @@ struct sipg_plan {
     int lz_steps = 0;
     sipg_solve_info info;
 
+    // multigrid hierarchy: this plan is the finest level, mg[i] is level i+1
+    bool mg_on = false;
+    sipg_mg_opts mg_opts;
+    std::vector<sipg_plan*> mg;
+    bool mesh_step = false;          // (coarse level) transfer from the finer level is a mesh step
+    MgTab<double> tr64;              // (coarse level) 1D tables of that transfer
+    MgTab<float> tr32;
+    void *mgz = nullptr, *mgt = nullptr;  // (finest level) V-cycle correction and residual
+
     template <typename T>
     OpData<T> opdata() const;
 };
@@ -174,10 +183,15 @@ OpData<T> sipg_plan::opdata() const {
 
 namespace {
 
+struct Layout;
+Layout layout(const sipg_plan* P);
+
 struct Layout {
     size_t verts64, verts32, hcell, tfac64, tfac32, mu_cell64, mu_cell32, mu_face64, mu_face32, diag64, dinv64,
         dinv32;
     size_t r, p, q, z, zo, cr, cd, cz0, cz1, partials, st;
+    size_t mgz = 0, mgt = 0;          // multigrid: finest-level vectors
+    std::vector<size_t> level, level_bytes;   // multigrid: workspaces of the coarser levels
     size_t op_end, total;
 };
 
@@ -200,6 +214,15 @@ Layout layout(const sipg_plan* P) {
     L.cr = take(nd * 8); L.cd = take(nd * 8); L.cz0 = take(nd * 8); L.cz1 = take(nd * 8);
     L.partials = take(kRedSlots * kRedBlocks * 8);
     L.st = take(sizeof(SolveState));
+    if (P->mg_on) {
+        L.mgz = take(nd * 8);
+        L.mgt = take(nd * 8);
+        for (const sipg_plan* c : P->mg) {
+            const size_t b = layout(c).total;
+            L.level.push_back(take(b));
+            L.level_bytes.push_back(b);
+        }
+    }
     L.total = off;
     return L;
 }
@@ -242,35 +265,97 @@ sipg_status do_apply(sipg_plan* P, int parts, const void* x, void* y, hipStream_
     return SIPG_OK;
 }
 
-// Chebyshev-Jacobi steps 1..degree-1 (Sec. 5.3) in precision T, from the
-// start z_1 = theta^-1 D^-1 r already in cz0 (written by the fused CG update
-// or by k_cheb_start); *zlast receives the buffer holding the last iterate.
 template <typename T>
-sipg_status cheb_steps(sipg_plan* P, const T** zlast, hipStream_t s) {
-    T* rT = static_cast<T*>(P->cr);
-    T* d = static_cast<T*>(P->cd);
-    T* za = static_cast<T*>(P->cz0);
-    T* zb = static_cast<T*>(P->cz1);
-    const T* dinv;
-    if constexpr (sizeof(T) == 8) dinv = P->dinv64; else dinv = P->dinv32;
-    const OpData<T> od = P->opdata<T>();
-    for (int j = 1; j < P->opts.cheb_degree; ++j) {
+const T* dinv_of(const sipg_plan* P) {
+    if constexpr (sizeof(T) == 8) return P->dinv64; else return P->dinv32;
+}
+
+template <typename T>
+const MgTab<T>& tab_of(const sipg_plan* P) {
+    if constexpr (sizeof(T) == 8) return P->tr64; else return P->tr32;
+}
+
+// Chebyshev-Jacobi steps 1..degree-1 (Sec. 5.3) of level L in precision T for
+// the right-hand side rhs, from the start z_1 = theta^-1 D^-1 rhs already in
+// L's cz0 (d = z_1 in cd); *zlast receives the buffer holding the last iterate.
+template <typename T>
+sipg_status cheb_steps(sipg_plan* L, int degree, const T* rhs, const int* skip, const T** zlast, hipStream_t s) {
+    T* d = static_cast<T*>(L->cd);
+    T* za = static_cast<T*>(L->cz0);
+    T* zb = static_cast<T*>(L->cz1);
+    const OpData<T> od = L->opdata<T>();
+    for (int j = 1; j < degree; ++j) {
         ApplyIO<T> io;
         std::memset(&io, 0, sizeof(io));
         io.x = za; io.y = zb; io.parts = SIPG_PART_ALL;
-        io.r = rT; io.dinv = dinv; io.d = d;
-        io.coef = &P->st->cheb[j][0];
-        io.skip = &P->st->skip;
-        HIP_TRY(launch_apply<T>(P->n, P->C, P->curved, od, io, MODE_CHEB, s));
+        io.r = rhs; io.dinv = dinv_of<T>(L); io.d = d;
+        io.coef = &L->st->cheb[j][0];
+        io.skip = skip;
+        HIP_TRY(launch_apply<T>(L->n, L->C, L->curved, od, io, MODE_CHEB, s));
         std::swap(za, zb);
     }
     *zlast = za;
     return SIPG_OK;
 }
 
+int mg_levels(const sipg_plan* P) { return P->mg_on ? 1 + (int)P->mg.size() : 1; }
+sipg_plan* mg_level(sipg_plan* P, int l) { return l == 0 ? P : P->mg[l - 1]; }
+
+// One V-cycle from zero on level l of the finest plan `top` (Sec. 5.3):
+// right-hand side in the level's cr (precision T), result in *out.  Level 0's
+// first Chebyshev step has been written by the CG kernels; every kernel
+// follows the finest plan's skip flag.
 template <typename T>
-const T* dinv_of(const sipg_plan* P) {
-    if constexpr (sizeof(T) == 8) return P->dinv64; else return P->dinv32;
+sipg_status vcycle(sipg_plan* top, int l, const T** out, hipStream_t s) {
+    sipg_plan* L = mg_level(top, l);
+    const int* skip = &top->st->skip;
+    const long long n = L->ndof;
+    const T* R = static_cast<const T*>(L->cr);
+    const bool last = l == mg_levels(top) - 1;
+    const int deg = last ? top->mg_opts.coarse_degree : top->opts.cheb_degree;
+    if (l > 0) HIP_TRY(launch_cheb_start_t<T>(R, static_cast<T*>(L->cz0), static_cast<T*>(L->cd), dinv_of<T>(L), n,
+                                              L->st, skip, s));
+    const T* zs = nullptr;
+    sipg_status rc = cheb_steps<T>(L, deg, R, skip, &zs, s);                     // pre-smoothing
+    if (rc != SIPG_OK || last) {
+        *out = zs;
+        return rc;
+    }
+    T* Z = static_cast<T*>(l == 0 ? top->mgz : static_cast<void*>(L->p));
+    T* Tm = static_cast<T*>(l == 0 ? top->mgt : static_cast<void*>(L->q));
+    const OpData<T> od = L->opdata<T>();
+    auto residual = [&]() -> sipg_status {                                       // Tm = R - A Z
+        ApplyIO<T> io;
+        std::memset(&io, 0, sizeof(io));
+        io.x = Z; io.y = Tm; io.parts = SIPG_PART_ALL; io.r = R; io.skip = skip;
+        HIP_TRY(launch_apply<T>(L->n, L->C, L->curved, od, io, MODE_RESID, s));
+        return SIPG_OK;
+    };
+    HIP_TRY(launch_copy_t<T>(Z, zs, n, skip, s));
+    if ((rc = residual()) != SIPG_OK) return rc;
+    sipg_plan* Cc = top->mg[l];
+    HIP_TRY(launch_restrict<T>(Cc->mesh_step, L->C, L->n, Cc->n, L->nx, L->ny, L->nz, tab_of<T>(Cc), Tm,
+                               static_cast<T*>(Cc->cr), skip, s));
+    const T* zc = nullptr;
+    if ((rc = vcycle<T>(top, l + 1, &zc, s)) != SIPG_OK) return rc;               // coarse correction
+    HIP_TRY(launch_prolong_add<T>(Cc->mesh_step, L->C, L->n, Cc->n, L->nx, L->ny, L->nz, tab_of<T>(Cc), zc, Z,
+                                  skip, s));
+    if ((rc = residual()) != SIPG_OK) return rc;
+    HIP_TRY(launch_cheb_start_t<T>(Tm, static_cast<T*>(L->cz0), static_cast<T*>(L->cd), dinv_of<T>(L), n, L->st,
+                                   skip, s));
+    if ((rc = cheb_steps<T>(L, deg, Tm, skip, &zs, s)) != SIPG_OK) return rc;    // post-smoothing
+    HIP_TRY(launch_add_t<T>(Z, zs, n, skip, s));
+    *out = Z;
+    return SIPG_OK;
+}
+
+// The preconditioner after its first Chebyshev step (written by the CG
+// kernels into the finest level's cr, cz0, cd): the rest of the one-level
+// Chebyshev-Jacobi polynomial, or a V-cycle.
+template <typename T>
+sipg_status precond_body(sipg_plan* P, const T** zl, hipStream_t s) {
+    if (P->opts.precond_kind == SIPG_PRECOND_MULTIGRID) return vcycle<T>(P, 0, zl, s);
+    return cheb_steps<T>(P, P->opts.cheb_degree, static_cast<const T*>(P->cr), &P->st->skip, zl, s);
 }
 
 // (Re)start of the flexible CG from r = b - A x: z = M r, rz = r.z, p = z.
@@ -282,7 +367,7 @@ sipg_status cg_start(sipg_plan* P) {
     sk_cheb_start<T>(P->r, static_cast<T*>(P->cr), static_cast<T*>(P->cz0), static_cast<T*>(P->cd), dinv_of<T>(P),
                      n, P->st, s);
     const T* zl = nullptr;
-    sipg_status rc = cheb_steps<T>(P, &zl, s);
+    sipg_status rc = precond_body<T>(P, &zl, s);
     if (rc != SIPG_OK) return rc;
     sk_cg_beta<T>(zl, P->z, P->r, nullptr, n, mz, 1, P->st, P->partials, s);
     sk_cg_direction(P->p, P->z, n, mz, 1, P->st, s);
@@ -308,7 +393,7 @@ sipg_status cg_iterations(sipg_plan* P, int iters) {
         sk_cg_update<T>(P->x, P->r, P->p, P->q, static_cast<T*>(P->cr), static_cast<T*>(P->cz0),
                         static_cast<T*>(P->cd), dinv_of<T>(P), n, P->st, P->partials, s);
         const T* zl = nullptr;
-        sipg_status rc = cheb_steps<T>(P, &zl, s);
+        sipg_status rc = precond_body<T>(P, &zl, s);
         if (rc != SIPG_OK) return rc;
         sk_cg_beta<T>(zl, P->zo, P->r, P->z, n, mz, 0, P->st, P->partials, s);
         sk_cg_direction(P->p, P->zo, n, mz, 0, P->st, s);
@@ -369,6 +454,66 @@ sipg_status enqueue_true_residual(sipg_plan* P) {
     sk_residual(P->b, P->q, P->r, n, P->mean_zero ? 1 : 0, P->st, P->partials, s);
     HIP_TRY(hipGetLastError());
     return enqueue_readback(P);
+}
+
+sipg_status check_opts(const sipg_plan* P, const sipg_solve_opts& o) {
+    if (!(o.rel_tol > 0.0) || o.max_iter < 1 || o.cheb_degree < 1 || o.cheb_degree > 63 || !(o.cheb_ratio > 1.0) ||
+        !(o.cheb_safety > 0.0) || o.lanczos_steps < 1 || o.lanczos_steps > 64 || o.check_every < 1 ||
+        o.max_restarts < 0 || (o.precond_precision != SIPG_F32 && o.precond_precision != SIPG_F64) ||
+        (o.precond_kind != SIPG_PRECOND_CHEBYSHEV && o.precond_kind != SIPG_PRECOND_MULTIGRID))
+        return fail(SIPG_ERR_INVALID, "bad solve options");
+    if (o.precond_kind == SIPG_PRECOND_MULTIGRID && !P->mg_on)
+        return fail(SIPG_ERR_STATE, "multigrid preconditioner requested but no hierarchy was set before binding");
+    return SIPG_OK;
+}
+
+// Eigenvalue estimates (cached per level) and Chebyshev coefficients of the
+// preconditioner in P->opts: the finest level's polynomial, and with
+// multigrid every coarser level's (coarse_degree on the coarsest).
+sipg_status prepare_precond(sipg_plan* P, hipStream_t s) {
+    const sipg_solve_opts& o = P->opts;
+    const bool mg = o.precond_kind == SIPG_PRECOND_MULTIGRID;
+    const int nl = mg ? mg_levels(P) : 1;
+    for (int l = 0; l < nl; ++l) {
+        sipg_plan* L = mg_level(P, l);
+        if (l > 0) L->opts = o;
+        if (!L->lz_valid || L->lz_steps != o.lanczos_steps) {
+            const sipg_status rc = run_lanczos(L, s);
+            if (rc != SIPG_OK) return rc;
+        }
+        const int deg = (mg && l == nl - 1) ? P->mg_opts.coarse_degree : o.cheb_degree;
+        sk_lz_finish(L->st, o.cheb_safety, o.cheb_ratio, deg, s);
+    }
+    HIP_TRY(hipGetLastError());
+    return SIPG_OK;
+}
+
+// Lagrange basis of the n Gauss points of [0, 1] at x.
+void lagrange_at(int n, double x, double* out) {
+    double g[kMaxN], w[kMaxN];
+    gauss_legendre01(n, g, w);
+    for (int j = 0; j < n; ++j) {
+        double v = 1.0;
+        for (int m = 0; m < n; ++m)
+            if (m != j) v *= (x - g[m]) / (g[j] - g[m]);
+        out[j] = v;
+    }
+}
+
+// Transfer tables from a level with nf nodes per direction to one with nc.
+void fill_transfer(sipg_plan* Cc, int nf, int nc) {
+    double xf[kMaxN], wf[kMaxN], row[kMaxN];
+    gauss_legendre01(nf, xf, wf);
+    std::memset(&Cc->tr64, 0, sizeof(Cc->tr64));
+    std::memset(&Cc->tr32, 0, sizeof(Cc->tr32));
+    for (int i = 0; i < nf; ++i) {
+        lagrange_at(nc, xf[i], row);                       // degree step: coarse basis at fine nodes
+        for (int j = 0; j < nc; ++j) { Cc->tr64.P[i][j] = row[j]; Cc->tr32.P[i][j] = float(row[j]); }
+        for (int b = 0; b < 2; ++b) {                      // mesh step: parent basis at child b's nodes
+            lagrange_at(nc, 0.5 * (b + xf[i]), row);
+            for (int j = 0; j < nc; ++j) { Cc->tr64.H[b][i][j] = row[j]; Cc->tr32.H[b][i][j] = float(row[j]); }
+        }
+    }
 }
 
 }  // namespace
@@ -475,6 +620,7 @@ sipg_status sipg_plan_create(const sipg_mesh* mesh, const sipg_viscosity* law, c
 
 void sipg_plan_destroy(sipg_plan* P) {
     if (!P) return;
+    for (sipg_plan* c : P->mg) sipg_plan_destroy(c);
     if (P->mirror) (void)hipHostFree(P->mirror);
     if (P->ev) (void)hipEventDestroy(P->ev);
     delete P;
@@ -539,6 +685,14 @@ sipg_status sipg_plan_bind(sipg_plan* P, void* workspace, size_t bytes, int32_t 
                          P->mu_cell32, P->mu_face64, P->mu_face32, (int)P->nface, s));
     const OpData<double> od2 = P->opdata<double>();
     HIP_TRY(launch_diagonal(P->n, P->C, P->curved, od2, P->diag64, P->dinv64, P->dinv32, s));
+    if (P->mg_on && P->with_solver) {
+        P->mgz = w + L.mgz;
+        P->mgt = w + L.mgt;
+        for (size_t i = 0; i < P->mg.size(); ++i) {
+            const sipg_status rc = sipg_plan_bind(P->mg[i], w + L.level[i], L.level_bytes[i], 1, stream);
+            if (rc != SIPG_OK) return rc;
+        }
+    }
     P->bound = true;
     g_err.clear();
     return SIPG_OK;
@@ -598,6 +752,152 @@ void sipg_solve_opts_default(sipg_solve_opts* o) {
     o->lanczos_steps = 20;
     o->check_every = 10;
     o->max_restarts = 3;
+    o->precond_kind = SIPG_PRECOND_CHEBYSHEV;
+}
+
+void sipg_mg_opts_default(sipg_mg_opts* o) {
+    if (!o) return;
+    o->coarse_degree = 12;
+    o->min_cells = 2;
+    o->max_levels = 16;
+    o->h_coarsen = 1;
+}
+
+sipg_status sipg_plan_set_multigrid(sipg_plan* P, const sipg_mg_opts* opts) {
+    if (!valid_plan(P)) return fail(SIPG_ERR_INVALID, "null plan");
+    if (P->bound) return fail(SIPG_ERR_STATE, "set the multigrid hierarchy before binding the plan");
+    sipg_mg_opts o;
+    if (opts) o = *opts; else sipg_mg_opts_default(&o);
+    if (o.coarse_degree < 1 || o.coarse_degree > 63 || o.min_cells < 1 || o.max_levels < 1)
+        return fail(SIPG_ERR_INVALID, "bad multigrid options");
+    for (sipg_plan* c : P->mg) sipg_plan_destroy(c);
+    P->mg.clear();
+    // levels: degree k-1 .. 1 on the plan's mesh, then the mesh halved while possible
+    int deg = P->degree, nx = P->nx, ny = P->ny, nz = P->nz;
+    std::vector<double> verts = P->verts;
+    int nlev = 1, n_prev = P->n;
+    auto add_level = [&](bool mesh_step) -> sipg_status {
+        sipg_mesh m;
+        std::memset(&m, 0, sizeof(m));
+        m.nx = nx; m.ny = ny; m.nz = nz;
+        m.vertices = P->curved ? verts.data() : nullptr;
+        for (int i = 0; i < 6; ++i) m.bc[i] = P->bc[i];
+        sipg_viscosity law;
+        std::memset(&law, 0, sizeof(law));
+        law.kind = SIPG_LAW_CONST;
+        law.mu = 1.0;                                   // replaced by the plan's law below
+        sipg_params par;
+        par.op = P->op; par.degree = deg; par.alpha = P->alpha; par.penalty = P->penalty;
+        sipg_plan* c = nullptr;
+        const sipg_status rc = sipg_plan_create(&m, &law, &par, &c);
+        if (rc != SIPG_OK) return rc;
+        c->law = P->law;
+        c->mesh_step = mesh_step;
+        fill_transfer(c, n_prev, c->n);
+        n_prev = c->n;
+        P->mg.push_back(c);
+        ++nlev;
+        return SIPG_OK;
+    };
+    sipg_status rc = SIPG_OK;
+    while (rc == SIPG_OK && deg > 1 && nlev < o.max_levels) {
+        --deg;
+        rc = add_level(false);
+    }
+    auto halvable = [&](int c) { return c % 2 == 0 && c / 2 >= o.min_cells; };
+    while (rc == SIPG_OK && o.h_coarsen && nlev < o.max_levels && halvable(nx) && halvable(ny) && halvable(nz)) {
+        if (P->curved) {                                 // every other vertex of the finer mesh
+            std::vector<double> cv;
+            cv.reserve((size_t)(nx / 2 + 1) * (ny / 2 + 1) * (nz / 2 + 1) * 3);
+            for (int k = 0; k <= nz; k += 2)
+                for (int j = 0; j <= ny; j += 2)
+                    for (int i = 0; i <= nx; i += 2)
+                        for (int d = 0; d < 3; ++d)
+                            cv.push_back(verts[(((size_t)k * (ny + 1) + j) * (nx + 1) + i) * 3 + d]);
+            verts.swap(cv);
+        }
+        nx /= 2; ny /= 2; nz /= 2;
+        rc = add_level(true);
+    }
+    if (rc != SIPG_OK) {
+        for (sipg_plan* c : P->mg) sipg_plan_destroy(c);
+        P->mg.clear();
+        P->mg_on = false;
+        return rc;
+    }
+    P->mg_opts = o;
+    P->mg_on = true;
+    g_err.clear();
+    return SIPG_OK;
+}
+
+int32_t sipg_multigrid_levels(const sipg_plan* P, int32_t* degrees, int32_t* cells, int32_t cap) {
+    if (!P) return 0;
+    const int nl = P->mg_on ? 1 + (int)P->mg.size() : 1;
+    for (int l = 0; l < nl && l < cap; ++l) {
+        const sipg_plan* L = l == 0 ? P : P->mg[l - 1];
+        if (degrees) degrees[l] = L->degree;
+        if (cells) { cells[3 * l] = L->nx; cells[3 * l + 1] = L->ny; cells[3 * l + 2] = L->nz; }
+    }
+    return nl;
+}
+
+sipg_status sipg_multigrid_transfer(sipg_plan* P, int32_t level, int32_t restrict_, int32_t precision,
+                                    const void* in, void* out, void* stream) {
+    if (!valid_plan(P) || !in || !out) return fail(SIPG_ERR_INVALID, "null argument");
+    if (!P->bound) return fail(SIPG_ERR_STATE, "plan not bound");
+    if (!P->mg_on || level < 0 || level + 1 >= mg_levels(P)) return fail(SIPG_ERR_INVALID, "no such level pair");
+    if (precision != SIPG_F64 && precision != SIPG_F32) return fail(SIPG_ERR_INVALID, "bad precision");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const sipg_plan* F = mg_level(P, level);
+    const sipg_plan* Cc = P->mg[level];
+    if (precision == SIPG_F64) {
+        if (restrict_)
+            HIP_TRY(launch_restrict<double>(Cc->mesh_step, F->C, F->n, Cc->n, F->nx, F->ny, F->nz, Cc->tr64,
+                                            static_cast<const double*>(in), static_cast<double*>(out), nullptr, s));
+        else
+            HIP_TRY(launch_prolong_add<double>(Cc->mesh_step, F->C, F->n, Cc->n, F->nx, F->ny, F->nz, Cc->tr64,
+                                               static_cast<const double*>(in), static_cast<double*>(out), nullptr, s));
+    } else {
+        if (restrict_)
+            HIP_TRY(launch_restrict<float>(Cc->mesh_step, F->C, F->n, Cc->n, F->nx, F->ny, F->nz, Cc->tr32,
+                                           static_cast<const float*>(in), static_cast<float*>(out), nullptr, s));
+        else
+            HIP_TRY(launch_prolong_add<float>(Cc->mesh_step, F->C, F->n, Cc->n, F->nx, F->ny, F->nz, Cc->tr32,
+                                              static_cast<const float*>(in), static_cast<float*>(out), nullptr, s));
+    }
+    return SIPG_OK;
+}
+
+sipg_status sipg_precondition(sipg_plan* P, const double* r, double* z, const sipg_solve_opts* opts, void* stream) {
+    if (!valid_plan(P) || !r || !z) return fail(SIPG_ERR_INVALID, "null argument");
+    if (!P->bound || !P->with_solver) return fail(SIPG_ERR_STATE, "plan not bound with solver workspace");
+    if (P->phase == PH_RUNNING || P->phase == PH_CHECKING) return fail(SIPG_ERR_STATE, "a solve is in progress on this plan");
+    sipg_solve_opts o;
+    if (opts) o = *opts; else sipg_solve_opts_default(&o);
+    sipg_status rc = check_opts(P, o);
+    if (rc != SIPG_OK) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    P->opts = o;
+    const long long n = P->ndof;
+    sk_state_init(P->st, 0.0, 1, s);                    // clears the skip flag
+    if ((rc = prepare_precond(P, s)) != SIPG_OK) return rc;
+    sk_copy(P->r, r, n, s);
+    if (o.precond_precision == SIPG_F32) {
+        sk_cheb_start<float>(P->r, static_cast<float*>(P->cr), static_cast<float*>(P->cz0), static_cast<float*>(P->cd),
+                             P->dinv32, n, P->st, s);
+        const float* zl = nullptr;
+        if ((rc = precond_body<float>(P, &zl, s)) != SIPG_OK) return rc;
+        HIP_TRY(launch_to_f64<float>(z, zl, n, s));
+    } else {
+        sk_cheb_start<double>(P->r, static_cast<double*>(P->cr), static_cast<double*>(P->cz0),
+                              static_cast<double*>(P->cd), P->dinv64, n, P->st, s);
+        const double* zl = nullptr;
+        if ((rc = precond_body<double>(P, &zl, s)) != SIPG_OK) return rc;
+        HIP_TRY(launch_to_f64<double>(z, zl, n, s));
+    }
+    P->phase = PH_IDLE;
+    return SIPG_OK;
 }
 
 sipg_status sipg_solve_begin(sipg_plan* P, const double* b, double* x, const sipg_solve_opts* opts, void* stream) {
@@ -606,10 +906,8 @@ sipg_status sipg_solve_begin(sipg_plan* P, const double* b, double* x, const sip
     if (P->phase == PH_RUNNING || P->phase == PH_CHECKING) return fail(SIPG_ERR_STATE, "a solve is in progress on this plan");
     sipg_solve_opts o;
     if (opts) o = *opts; else sipg_solve_opts_default(&o);
-    if (!(o.rel_tol > 0.0) || o.max_iter < 1 || o.cheb_degree < 1 || o.cheb_degree > 63 || !(o.cheb_ratio > 1.0) ||
-        !(o.cheb_safety > 0.0) || o.lanczos_steps < 1 || o.lanczos_steps > 64 || o.check_every < 1 ||
-        o.max_restarts < 0 || (o.precond_precision != SIPG_F32 && o.precond_precision != SIPG_F64))
-        return fail(SIPG_ERR_INVALID, "bad solve options");
+    sipg_status vrc = check_opts(P, o);
+    if (vrc != SIPG_OK) return vrc;
     const bool all_neumann = std::all_of(P->bc, P->bc + 6, [](int v) { return v == SIPG_BC_NEUMANN; });
     if (P->C == 3 && all_neumann && P->alpha == 0.0)
         return fail(SIPG_ERR_UNSUPPORTED, "pure-Neumann viscous operator with alpha = 0 is singular (rigid motions)");
@@ -623,11 +921,8 @@ sipg_status sipg_solve_begin(sipg_plan* P, const double* b, double* x, const sip
     hipStream_t s = P->sstream;
     const long long n = P->ndof;
     sk_state_init(P->st, o.rel_tol * o.rel_tol, o.max_iter, s);
-    if (!P->lz_valid || P->lz_steps != o.lanczos_steps) {
-        sipg_status rc = run_lanczos(P, s);
-        if (rc != SIPG_OK) return rc;
-    }
-    sk_lz_finish(P->st, o.cheb_safety, o.cheb_ratio, o.cheb_degree, s);
+    vrc = prepare_precond(P, s);
+    if (vrc != SIPG_OK) return vrc;
     if (P->mean_zero) {
         sk_sum(b, n, P->partials, nullptr, s);
         sk_scalar(P->st, P->partials, 1, SC_MEAN, n, s);

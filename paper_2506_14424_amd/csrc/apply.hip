@@ -753,6 +753,14 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
         for (int c = 0; c < C; ++c)
 #pragma unroll
             for (int j = 0; j < N; ++j) io.y[base + (c * N + j) * NN + t] = y[c][j];
+    } else if constexpr (MODE == MODE_RESID) {
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                const size_t idx = base + (c * N + j) * NN + t;
+                io.y[idx] = io.r[idx] - y[c][j];
+            }
     } else {
         const T c1 = T(io.coef[0]), c2 = T(io.coef[1]);
 #pragma unroll
@@ -773,6 +781,8 @@ static hipError_t launch_nc(const OpData<T>& op, const ApplyIO<T>& io, int mode,
     const int blocks = (op.ncell + Sh::CPB - 1) / Sh::CPB;
     if (mode == MODE_APPLY)
         hipLaunchKernelGGL((k_apply<N, C, T, CURVED, MODE_APPLY>), dim3(blocks), dim3(Sh::THREADS), 0, s, op, io);
+    else if (mode == MODE_RESID)
+        hipLaunchKernelGGL((k_apply<N, C, T, CURVED, MODE_RESID>), dim3(blocks), dim3(Sh::THREADS), 0, s, op, io);
     else
         hipLaunchKernelGGL((k_apply<N, C, T, CURVED, MODE_CHEB>), dim3(blocks), dim3(Sh::THREADS), 0, s, op, io);
     return hipGetLastError();

@@ -50,7 +50,8 @@ struct LawDev {
     double phi[SIPG_MAX_MODES];
 };
 
-enum ApplyMode { MODE_APPLY = 0, MODE_CHEB = 1 };
+// MODE_APPLY: y = A x;  MODE_CHEB: Chebyshev step (below);  MODE_RESID: y = r - A x
+enum ApplyMode { MODE_APPLY = 0, MODE_CHEB = 1, MODE_RESID = 2 };
 
 // Vector arguments of one operator application.
 template <typename T>
@@ -58,7 +59,7 @@ struct ApplyIO {
     const T* x;      // input (MODE_CHEB: current iterate z_j)
     T* y;            // output (MODE_CHEB: next iterate z_{j+1})
     int parts;       // SIPG_PART_* mask
-    // MODE_CHEB: d <- c1 d + c2 Dinv (r - A z); z_{j+1} = z_j + d
+    // MODE_CHEB: d <- c1 d + c2 Dinv (r - A z); z_{j+1} = z_j + d;  MODE_RESID: y = r - A x
     const T* r;
     const T* dinv;
     T* d;
@@ -91,6 +92,15 @@ constexpr int kRedBlocks = 512;   // blocks of the deterministic reductions
 constexpr int kRedThreads = 256;
 constexpr int kRedSlots = 4;      // partial sums per block
 
+// 1D multigrid transfer tables: P[i][j] = l^coarse_j(x^fine_i) between
+// degrees (nf x nc); H[c][i][j] = l_j((c + x_i) / 2) from an interval to its
+// half c (n x n).
+template <typename T>
+struct MgTab {
+    T P[kMaxN][kMaxN];
+    T H[2][kMaxN][kMaxN];
+};
+
 // ---------------------------------------------------------------- launchers
 // (defined in the .hip files; return hipError_t of the launch)
 
@@ -105,5 +115,28 @@ hipError_t launch_setup(int n, int C, bool curved, const OpData<double>& op, con
 
 hipError_t launch_diagonal(int n, int C, bool curved, const OpData<double>& op, double* diag,
                            double* dinv, float* dinv32, hipStream_t s);
+
+// Multigrid transfers between a fine level (nf nodes per direction, fine
+// mesh fx*fy*fz cells) and the next coarser one (nc; same mesh for a degree
+// step, half the cells per direction for a mesh step).  restrict: rc = P^T tf;
+// prolong: zf += P zc.  Every kernel returns at once when *skip != 0.
+template <typename T>
+hipError_t launch_restrict(bool mesh_step, int C, int nf, int nc, int fx, int fy, int fz, const MgTab<T>& tab,
+                           const T* tf, T* rc, const int* skip, hipStream_t s);
+template <typename T>
+hipError_t launch_prolong_add(bool mesh_step, int C, int nf, int nc, int fx, int fy, int fz, const MgTab<T>& tab,
+                              const T* zc, T* zf, const int* skip, hipStream_t s);
+// Level vector kernels in the preconditioner precision T (all skip-aware):
+// Chebyshev start z = theta^-1 dinv r, d = z (theta from the level's state);
+// y = x; y += x; z64 = (double) zT.
+template <typename T>
+hipError_t launch_cheb_start_t(const T* r, T* z, T* d, const T* dinv, long long n, const SolveState* st,
+                               const int* skip, hipStream_t s);
+template <typename T>
+hipError_t launch_copy_t(T* y, const T* x, long long n, const int* skip, hipStream_t s);
+template <typename T>
+hipError_t launch_add_t(T* y, const T* x, long long n, const int* skip, hipStream_t s);
+template <typename T>
+hipError_t launch_to_f64(double* y, const T* x, long long n, hipStream_t s);
 
 }  // namespace sipg

@@ -21,6 +21,7 @@ class SolveOptions:
     lanczos_steps: int = 20
     check_every: int = 10
     max_restarts: int = 3
+    precond: str = "chebyshev"       # or "multigrid" (after Operator.set_multigrid)
 
     def to_c(self) -> F.SolveOpts:
         o = F.SolveOpts()
@@ -33,6 +34,7 @@ class SolveOptions:
         o.lanczos_steps = self.lanczos_steps
         o.check_every = self.check_every
         o.max_restarts = self.max_restarts
+        o.precond_kind = F.PRECOND[self.precond]
         return o
 
 
@@ -121,6 +123,32 @@ class Operator:
             self._h = None
 
     # ------------------------------------------------------------- setup
+    def set_multigrid(self, coarse_degree: int = 12, min_cells: int = 2, max_levels: int = 16,
+                      h_coarsen: bool = True):
+        """Build the hp-multigrid hierarchy (before bind); see sipg_plan_set_multigrid."""
+        o = F.MgOpts()
+        o.coarse_degree, o.min_cells, o.max_levels, o.h_coarsen = coarse_degree, min_cells, max_levels, int(h_coarsen)
+        check(lib.sipg_plan_set_multigrid(self._h, C.byref(o)))
+        return self
+
+    def multigrid_levels(self) -> list[tuple[int, int, int, int]]:
+        """(degree, nx, ny, nz) of every level, finest first."""
+        nl = int(lib.sipg_multigrid_levels(self._h, None, None, 0))
+        deg = (C.c_int32 * nl)()
+        cells = (C.c_int32 * (3 * nl))()
+        lib.sipg_multigrid_levels(self._h, deg, cells, nl)
+        return [(deg[l], cells[3 * l], cells[3 * l + 1], cells[3 * l + 2]) for l in range(nl)]
+
+    def multigrid_transfer(self, level: int, x, restrict: bool, out=None, stream=None):
+        """restrict: P^T x from level to level+1; else out += P x from level+1 to level."""
+        import torch
+        if out is None:
+            raise ValueError("pass the output vector (prolongation adds into it)")
+        prec = self._prec(x)
+        check(lib.sipg_multigrid_transfer(self._h, int(level), int(restrict), prec, C.c_void_p(x.data_ptr()),
+                                          C.c_void_p(out.data_ptr()), C.c_void_p(_stream_handle(stream))))
+        return out
+
     def workspace_bytes(self, with_solver: bool = True) -> int:
         b = C.c_size_t()
         check(lib.sipg_plan_workspace_bytes(self._h, int(with_solver), C.byref(b)))
@@ -203,6 +231,19 @@ class Operator:
         if rc != 0 and (raise_on_error or rc not in (-4, -5)):
             check(rc)
         return x, self._info(info)
+
+    def precondition(self, r, z=None, opts: SolveOptions | None = None, stream=None):
+        """One application z = M r of the solve's preconditioner (FP64 vectors)."""
+        import torch
+        self._check_vec(r)
+        if r.dtype != torch.float64:
+            raise TypeError("precondition takes FP64 vectors")
+        if z is None:
+            z = torch.empty_like(r)
+        o = (opts or SolveOptions()).to_c()
+        check(lib.sipg_precondition(self._h, C.c_void_p(r.data_ptr()), C.c_void_p(z.data_ptr()), C.byref(o),
+                                    C.c_void_p(_stream_handle(stream))))
+        return z
 
     def solve_begin(self, b, x, opts: SolveOptions | None = None, stream=None):
         o = (opts or SolveOptions()).to_c()
