@@ -6,8 +6,9 @@ mu = 10^(3 s(x)), 6,291,456 unknowns); inputs resident in device memory,
 (x, y) rotated over enough buffers that they do not stay in the 256 MB
 last-level cache.  Besides the headline DoF/s the line reports the FP32
 (preconditioner precision) apply, the setup including the inverse diagonal,
-FP64- vs FP32-preconditioned solves of the 24^3 k = 4 Carreau workload to
-1e-8, the continuous-batching request loop (solves/s, p50/p99), the
+FP64- vs FP32-preconditioned solves (one-level Chebyshev-Jacobi and
+hp-multigrid) of the 24^3 k = 4 Carreau workload to 1e-8, the
+continuous-batching request loop (solves/s, p50/p99), the
 roofline of the apply kernel and the CPU oracle timed on this host.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
@@ -123,33 +124,42 @@ def cpu_baseline(cfg, V):
 
 
 def solve_compare(tol=1e-8):
+    """c3 solved to `tol` four ways: one-level Chebyshev-Jacobi (degree 5) and
+    hp-multigrid V-cycles (Chebyshev-Jacobi degree 4 on every level), each
+    with the preconditioner in FP64 and in FP32 (outer CG always FP64)."""
     import torch
     import workloads as W
     from paper_2506_14424_amd import Operator, SolveOptions
     cfg = W.config("c3")
     V = W.box_vertices(cfg["nx"], cfg["ny"], cfg["nz"], cfg["perturb"])
-    op = Operator.from_config(cfg, V).bind(with_solver=True)
+    op = Operator.from_config(cfg, V).set_multigrid().bind(with_solver=True)
     b = torch.from_numpy(W.uniform_vector(cfg["x_seed"], op.ndof)).cuda()
     out = {"workload": "c3: viscous k=4, 24^3 perturbed, Carreau of a seeded velocity, "
-                       f"{op.ndof} DoFs, rel. tol {tol:g}"}
+                       f"{op.ndof} DoFs, rel. tol {tol:g}",
+           "multigrid_levels": op.multigrid_levels()}
     sols = {}
-    for prec in ("f64", "f32"):
-        opts = SolveOptions(rel_tol=tol, precond_precision=prec, check_every=25)
-        op.solve(b, opts=opts)                       # warm (Lanczos cached after the first)
+    for key, prec, kind, deg in (("f64_precond", "f64", "chebyshev", 5), ("f32_precond", "f32", "chebyshev", 5),
+                                 ("mg_f64_precond", "f64", "multigrid", 4), ("mg_f32_precond", "f32", "multigrid", 4)):
+        opts = SolveOptions(rel_tol=tol, precond_precision=prec, precond=kind, cheb_degree=deg,
+                            check_every=25 if kind == "chebyshev" else 5)
+        op.solve(b, opts=opts)                       # warm (eigenvalue estimates cached after the first)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         x, info = op.solve(b, opts=opts)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        sols[prec] = x
-        out[prec + "_precond"] = {"seconds": dt, "iterations": info["iterations"],
-                                  "rel_residual": info["rel_residual"], "status": info["status"]}
+        sols[key] = x
+        out[key] = {"seconds": dt, "iterations": info["iterations"], "rel_residual": info["rel_residual"],
+                    "status": info["status"], "preconditioner": kind, "degree": deg}
     out["speedup_mixed_over_fp64"] = out["f64_precond"]["seconds"] / out["f32_precond"]["seconds"]
-    out["rel_diff_solutions"] = float((sols["f32"] - sols["f64"]).norm() / sols["f64"].norm())
+    out["speedup_mg_mixed_over_mg_fp64"] = out["mg_f64_precond"]["seconds"] / out["mg_f32_precond"]["seconds"]
+    out["speedup_mg_mixed_over_chebyshev_mixed"] = out["f32_precond"]["seconds"] / out["mg_f32_precond"]["seconds"]
+    out["rel_diff_solutions"] = float((sols["f32_precond"] - sols["f64_precond"]).norm() / sols["f64_precond"].norm())
+    out["rel_diff_solutions_mg"] = float((sols["mg_f32_precond"] - sols["f64_precond"]).norm()
+                                         / sols["f64_precond"].norm())
     fp32_err = None
     try:
         x64 = b.clone()
-        y64 = op.apply(x64)
         y32 = op.apply(x64.float()).double()
         ref32 = op.apply(x64.float().double())
         fp32_err = float((y32 - ref32).abs().max() / ref32.abs().max())
@@ -170,8 +180,8 @@ def serving(count=256, rate=20.0, budget=8 << 30):
         reqs.append(Request(r["id"], r["arrival"], cfg, rhs, None, cfg["tol"]))
     out = Server(GpuExecutor(), hbm_budget=budget).run(reqs)
     out["workload"] = (f"c5: {count} viscous-step solves, Poisson arrivals {rate:g}/s, N~U{{4..24}}, "
-                       "k~U{2..5}, contrast~U{1,1e2,1e4}, alpha/dt~U[1,100], FP32-preconditioned "
-                       "FP64 CG to 1e-8, HBM budget %d GiB" % (budget >> 30))
+                       "k~U{2..5}, contrast~U{1,1e2,1e4}, alpha/dt~U[1,100], FP64 CG with FP32 hp-multigrid "
+                       "V-cycles to 1e-8, HBM budget %d GiB" % (budget >> 30))
     return out
 
 

@@ -41,20 +41,25 @@ class Request:
 
 
 class GpuExecutor:
-    """Runs each request as one libsipg plan on a pool of HIP streams."""
+    """Runs each request as one libsipg plan on a pool of HIP streams, by
+    default preconditioned by FP32 hp-multigrid V-cycles."""
 
     def __init__(self, n_streams: int = 8, precond: str = "f32", keep_solutions: bool = False,
-                 depth: int = 2):
+                 depth: int = 2, multigrid: bool = True, smooth_degree: int = 4):
         import torch
         self.streams = [torch.cuda.Stream() for _ in range(n_streams)]   # default priority
         self.precond = precond
         self.keep = keep_solutions
         self.depth = depth
+        self.multigrid = multigrid
+        self.smooth_degree = smooth_degree
         self._rr = 0
 
     def prepare(self, req: Request):
         from .operator import Operator
         op = Operator.from_config(req.cfg, req.vertices)
+        if self.multigrid:
+            op.set_multigrid()
         return op, op.workspace_bytes(True) + 256 + 2 * 8 * op.ndof
 
     def start(self, req: Request, op):
@@ -67,8 +72,10 @@ class GpuExecutor:
             b = torch.from_numpy(np.ascontiguousarray(rhs, dtype=np.float64)).to("cuda")
             x = torch.empty_like(b)
             op.bind(with_solver=True, stream=stream)
-            op.solve_begin(b, x, SolveOptions(rel_tol=req.tol, precond_precision=self.precond),
-                           stream=stream)
+            opts = (SolveOptions(rel_tol=req.tol, precond_precision=self.precond, precond="multigrid",
+                                 cheb_degree=self.smooth_degree) if self.multigrid
+                    else SolveOptions(rel_tol=req.tol, precond_precision=self.precond))
+            op.solve_begin(b, x, opts, stream=stream)
         return (op, b, x, stream, [])
 
     def advance(self, handle, iters: int):

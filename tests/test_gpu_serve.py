@@ -1,6 +1,8 @@
 """Continuous batching on the GPU: every result of a mixed batch equals the
 same request solved alone (the kernels are deterministic and each solve only
-touches its own buffers), and every solve reaches its tolerance."""
+touches its own buffers), and every solve reaches its tolerance.  The
+executor's default preconditioner is the FP32 hp-multigrid V-cycle; one test
+also runs the one-level Chebyshev-Jacobi variant."""
 import sys
 
 import numpy as np
@@ -35,9 +37,10 @@ def test_mixed_batch_equals_solo_solves():
     assert out["requests"] == 12
     assert out["peak_reserved"] <= 256 << 20
     for r in reqs:
-        op = Operator.from_config(r.cfg).bind()
+        op = Operator.from_config(r.cfg).set_multigrid().bind()
         b = torch.from_numpy(r.rhs).cuda()
-        x, info = op.solve(b, opts=SolveOptions(rel_tol=1e-8), raise_on_error=False)
+        x, info = op.solve(b, opts=SolveOptions(rel_tol=1e-8, precond="multigrid", cheb_degree=4),
+                           raise_on_error=False)
         assert info["status"] == r.info["status"] and info["iterations"] == r.info["iterations"], r.id
         assert torch.equal(x, r.x), r.id
         if info["status"] == "SIPG_OK":
@@ -45,3 +48,17 @@ def test_mixed_batch_equals_solo_solves():
     # requests on coarse meshes with contrast 1e4 can give an indefinite SIPG
     # matrix (pointwise face viscosity); those stop with a breakdown, alone and in the mix
     assert out["converged"] >= 10
+
+
+def test_mixed_batch_with_chebyshev_preconditioner():
+    stream = W.serving_requests(seed=12, count=6, rate=200.0, nmin=2, nmax=6)
+    reqs = [Request(r["id"], r["arrival"], r["cfg"], W.uniform_vector(r["cfg"]["x_seed"], W.ndofs(r["cfg"])),
+                    None, 1e-8) for r in stream]
+    out = Server(GpuExecutor(keep_solutions=True, multigrid=False), hbm_budget=256 << 20, max_active=4,
+                 iters_per_round=3).run(reqs)
+    print(f"   {out}", flush=True)
+    for r in reqs:
+        op = Operator.from_config(r.cfg).bind()
+        x, info = op.solve(torch.from_numpy(r.rhs).cuda(), opts=SolveOptions(rel_tol=1e-8), raise_on_error=False)
+        assert info["status"] == r.info["status"] and info["iterations"] == r.info["iterations"], r.id
+        assert torch.equal(x, r.x), r.id
