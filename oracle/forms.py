@@ -24,7 +24,19 @@ Poisson operator (Sec. 4.1, paragraph "Pressure Step"), coercive SIPG sign:
             + sum_interior int -{{grad q}}.n [p] - {{grad p}}.n [q] + tau_p [q][p]
             + sum_Dirichlet int -(grad q . n) p - (grad p . n) q + 2 tau_p q p
 
-Penalty (the paper defers to Hillewaert 2013 and omits the formula):
+Penalty step (Sec. 3, "Consistent Stabilization", eq. penalty_step): per cell
+(v, u) + (div v, tau_div^e div u) + (v.n, tau_cont^e [[u]].n) on the cell
+boundary.  Summed over cells with the face factor taken as the mean of the
+two cells' tau_cont (a reading: it keeps the form symmetric) and the
+oriented jump u - g on Dirichlet faces (no mirror doubling):
+
+  a_pen(v, u) = sum_cells int alpha v.u + tau_div div v div u
+              + sum_interior int tau_F ([v].n)([u].n)
+              + sum_Dirichlet int tau_e (v.n)(u.n)
+
+with alpha = 1 for the paper's form; the factors come per cell as inputs.
+
+Penalty of the SIPG forms (the paper defers to Hillewaert 2013 and omits the formula):
 tau = P (k+1)^2 mu(x) / h_F with h_F = min(h^-, h^+), h_e = |cell|^(1/3),
 h_F = h^- on the boundary, and mu = 1 for the Poisson operator.
 
@@ -47,10 +59,12 @@ from .mesh import Mesh
 class Problem:
     mesh: Mesh
     degree: int
-    op: str = "viscous"          # "viscous" (3 components) or "poisson" (1)
-    alpha: float = 0.0           # gamma_0 / dt in front of the mass term
+    op: str = "viscous"          # "viscous" (3 components), "poisson" (1) or "penalty" (3)
+    alpha: float = 0.0           # gamma_0 / dt in front of the mass term (1 for the penalty step)
     penalty: float = 1.0         # P in tau = P (k+1)^2 mu / h_F
     law: object = field(default_factory=lambda: {"kind": "const", "mu": 1.0})
+    tau_div: object = None       # penalty step: tau_div per cell
+    tau_cont: object = None      # penalty step: tau_cont per cell
 
     @property
     def n(self) -> int:
@@ -58,7 +72,7 @@ class Problem:
 
     @property
     def C(self) -> int:
-        return 3 if self.op == "viscous" else 1
+        return 1 if self.op == "poisson" else 3
 
     @property
     def nloc(self) -> int:
@@ -72,7 +86,8 @@ class Problem:
     def from_config(cfg: dict, vertices=None) -> "Problem":
         """Build from a ``workloads.config`` dictionary (vertices drawn there)."""
         mesh = Mesh(cfg["nx"], cfg["ny"], cfg["nz"], vertices, cfg["bc"])
-        return Problem(mesh, cfg["degree"], cfg["op"], cfg["alpha"], cfg["penalty"], cfg["law"])
+        return Problem(mesh, cfg["degree"], cfg["op"], cfg["alpha"], cfg["penalty"], cfg["law"],
+                       cfg.get("tau_div"), cfg.get("tau_cont"))
 
 
 # ---------------------------------------------------------------------------
@@ -113,7 +128,7 @@ def _face_geo(pb: Problem, cells, d, side):
 
 
 def _mu(pb: Problem, x):
-    if pb.op == "poisson":
+    if pb.op != "viscous":
         return np.ones(x.shape[:-1])
     return viscosity(pb.law, x)
 
@@ -156,6 +171,29 @@ def poisson_face_form(qm, qp, Gqm, Gqp, pm, pp, Gpm, Gpp, tau, n):
     aq = 0.5 * (Gqm + Gqp) @ n
     ap = 0.5 * (Gpm + Gpp) @ n
     return -np.outer(aq, jp) - np.outer(jq, ap) + tau * np.outer(jq, jp)
+
+
+def penalty_face_form(vm, vp, um, up, tau, n):
+    """Continuity penalty of the penalty step on an interior face:
+    tau ([v].n)([u].n) for (I, 3) test and (J, 3) trial traces."""
+    return tau * np.outer((vm - vp) @ n, (um - up) @ n)
+
+
+def penalty_dirichlet_form(v, u, tau, n):
+    """tau (v.n)(u.n): the oriented jump on a Dirichlet face is u - g."""
+    return tau * np.outer(v @ n, u @ n)
+
+
+def _div(g):
+    """Divergence of vector basis functions from their gradients (..., C, 3)."""
+    return np.einsum("...cc->...", g)
+
+
+def _tau_face(pb: Problem, a, b=None):
+    """Penalty step: face value of tau_cont, the mean of the two cells'
+    values inside and the cell's own value on the boundary."""
+    t = np.asarray(pb.tau_cont, dtype=np.float64)
+    return t[a] if b is None else 0.5 * (t[a] + t[b])
 
 
 def poisson_dirichlet_form(q, Gq, p, Gp, tau, n):
@@ -212,6 +250,9 @@ def assemble(pb: Problem, parts=PARTS_ALL) -> sp.csr_matrix:
                 if pb.op == "viscous":
                     E = _sym(g[q]).reshape(nloc, 9)
                     K += JxW[0, q] * (pb.alpha * v[q] @ v[q].T + 2.0 * mu[q] * E @ E.T)
+                elif pb.op == "penalty":
+                    dv = _div(g[q])
+                    K += JxW[0, q] * (pb.alpha * v[q] @ v[q].T + pb.tau_div[e] * np.outer(dv, dv))
                 else:
                     gg = g[q][:, 0, :]
                     K += JxW[0, q] * (pb.alpha * v[q] @ v[q].T + gg @ gg.T)
@@ -241,6 +282,8 @@ def assemble(pb: Problem, parts=PARTS_ALL) -> sp.csr_matrix:
                         blk = viscous_face_form(Vminus, Vplus, Gminus, Gplus,
                                                 Vminus, Vplus, Gminus, Gplus,
                                                 mu[f], tau[f], nrm[0, f])
+                    elif pb.op == "penalty":
+                        blk = penalty_face_form(Vminus, Vplus, Vminus, Vplus, _tau_face(pb, a, b), nrm[0, f])
                     else:
                         blk = poisson_face_form(Vminus[:, 0], Vplus[:, 0], Gminus[:, 0], Gplus[:, 0],
                                                 Vminus[:, 0], Vplus[:, 0], Gminus[:, 0], Gplus[:, 0],
@@ -265,6 +308,8 @@ def assemble(pb: Problem, parts=PARTS_ALL) -> sp.csr_matrix:
                     for f in range(len(ds[0])):
                         if pb.op == "viscous":
                             blk = viscous_dirichlet_form(v[f], g[f], v[f], g[f], mu[f], tau[f], nrm[0, f])
+                        elif pb.op == "penalty":
+                            blk = penalty_dirichlet_form(v[f], v[f], _tau_face(pb, e), nrm[0, f])
                         else:
                             blk = poisson_dirichlet_form(v[f][:, 0], g[f][:, 0], v[f][:, 0], g[f][:, 0],
                                                          tau[f], nrm[0, f])
@@ -324,6 +369,9 @@ def apply(pb: Problem, x: np.ndarray, parts=PARTS_ALL, batch: int = 4096, cells=
             gu = _phys_grad(Xc, G, Jinv)
             if pb.op == "viscous":
                 B = 2.0 * mu[..., None, None] * _sym(gu)
+            elif pb.op == "penalty":
+                td = np.asarray(pb.tau_div, dtype=np.float64)[cells]
+                B = (td[:, None] * _div(gu))[..., None, None] * np.eye(3)
             else:
                 B = gu
             Y[cells] += _test_project(V, G, Jinv, pb.alpha * u, B, JxW)
@@ -345,7 +393,12 @@ def apply(pb: Problem, x: np.ndarray, parts=PARTS_ALL, batch: int = 4096, cells=
                 tau = _tau(pb, mu, np.minimum(h[em], h[ep]))
                 um = np.einsum("pj,ecj->epc", Vm, X[em]); up = np.einsum("pj,ecj->epc", Vp, X[ep])
                 gm = _phys_grad(X[em], Gm, Jim); gp = _phys_grad(X[ep], Gp, Jip)
-                if pb.op == "viscous":
+                if pb.op == "penalty":
+                    ju = um - up
+                    tf = _tau_face(pb, em, ep)[:, None]
+                    a_m = tf[..., None] * nrm * np.einsum("epc,epc->ep", ju, nrm)[..., None]
+                    B = np.zeros(ju.shape + (3,))
+                elif pb.op == "viscous":
                     ju = um - up
                     avg = 0.5 * mu[..., None, None] * (_sym(gm) + _sym(gp))
                     a_m = (-2.0 * np.einsum("epci,epi->epc", avg, nrm)
@@ -375,7 +428,11 @@ def apply(pb: Problem, x: np.ndarray, parts=PARTS_ALL, batch: int = 4096, cells=
                 tau = _tau(pb, mu, h[cells])
                 u = np.einsum("pj,ecj->epc", Vf, X[cells])
                 gu = _phys_grad(X[cells], Gf, Ji)
-                if pb.op == "viscous":
+                if pb.op == "penalty":
+                    tf = _tau_face(pb, cells)[:, None]
+                    a = tf[..., None] * nrm * np.einsum("epc,epc->ep", u, nrm)[..., None]
+                    B = np.zeros(u.shape + (3,))
+                elif pb.op == "viscous":
                     a = (-2.0 * mu[..., None] * np.einsum("epci,epi->epc", _sym(gu), nrm)
                          + 2.0 * tau[..., None] * (u + nrm * np.einsum("epc,epc->ep", u, nrm)[..., None]))
                     B = -2.0 * mu[..., None, None] * _sym(u[..., :, None] * nrm[..., None, :])
@@ -411,11 +468,15 @@ def diagonal(pb: Problem, batch: int = 1024) -> np.ndarray:
             if pb.op == "viscous":
                 # 2 mu eps(phi e_c):eps(phi e_c) = mu (|grad phi|^2 + (d_c phi)^2)
                 dens = pb.alpha * V[None] ** 2 + mu[..., None] * (g2 + grad[..., c] ** 2)
+            elif pb.op == "penalty":
+                # div(phi e_c) = d_c phi
+                td = np.asarray(pb.tau_div, dtype=np.float64)[cells]
+                dens = pb.alpha * V[None] ** 2 + td[:, None, None] * grad[..., c] ** 2
             else:
                 dens = pb.alpha * V[None] ** 2 + g2
             D[cells, c * n ** 3:(c + 1) * n ** 3] += np.einsum("ep,epj->ej", JxW, dens)
 
-    def face_self(cells, d, side, hF, dirichlet):
+    def face_self(cells, d, side, hF, dirichlet, tau_p=None):
         pts, _ = face_points(n, d, side)
         Vf, Gf = tensor_tables(n, pts)
         _, xq, Ji, nrm, ds = _face_geo(pb, cells, d, side)
@@ -425,7 +486,10 @@ def diagonal(pb: Problem, batch: int = 1024) -> np.ndarray:
         for ii, e in enumerate(cells):
             v, g = _basis_traces(pb, Vf, Gf, Ji[ii])
             for f in range(len(pts)):
-                if pb.op == "viscous":
+                if pb.op == "penalty":
+                    # tau ((phi e_c).n)^2 on interior and Dirichlet faces alike
+                    m = penalty_dirichlet_form(v[f], v[f], tau_p[ii], nrm[ii, f])
+                elif pb.op == "viscous":
                     if dirichlet:
                         m = viscous_dirichlet_form(v[f], g[f], v[f], g[f], mu[ii, f], tau[ii, f], nrm[ii, f])
                     else:
@@ -450,16 +514,18 @@ def diagonal(pb: Problem, batch: int = 1024) -> np.ndarray:
                 out[ii] += ds[ii, f] * np.diag(m)
         return out
 
+    pen = pb.op == "penalty"
     for d in range(3):
         em, ep = mesh.interior_faces(d)
         if len(em):
             hF = np.minimum(h[em], h[ep])
-            D[em] += face_self(em, d, 1, hF, False)
-            D[ep] += face_self(ep, d, 0, hF, False)
+            tp = _tau_face(pb, em, ep) if pen else None
+            D[em] += face_self(em, d, 1, hF, False, tp)
+            D[ep] += face_self(ep, d, 0, hF, False, tp)
         for side in (0, 1):
             if mesh.bc[2 * d + side] == "D":
                 cells = mesh.boundary_cells(d, side)
-                D[cells] += face_self(cells, d, side, h[cells], True)
+                D[cells] += face_self(cells, d, side, h[cells], True, _tau_face(pb, cells) if pen else None)
     return D.reshape(-1)
 
 

@@ -20,7 +20,9 @@ AMG cycles or a direct solver):
   the fine nodes (p: same cell; h: the child cell's nodes mapped into the
   parent's reference cell, xi_parent = (child + xi_child) / 2 per direction),
   restriction is the transpose;
-* every level evaluates the viscosity law at its own quadrature points;
+* every level evaluates the viscosity law at its own quadrature points; for
+  the penalty step a coarse cell takes the mean of its children's penalty
+  factors;
 * smoothing: the same Chebyshev-Jacobi polynomial as the one-level
   preconditioner (interval [lam/20, lam], lam = 1.2 x the largest Ritz value
   of 20 Lanczos steps) of degree ``smooth_degree`` before and after the
@@ -45,13 +47,17 @@ def level_problems(pb: Problem, h_coarsen: bool = True, min_cells: int = 2,
     k = pb.degree
     while k > 1 and len(levels) < max_levels:
         k -= 1
-        levels.append(Problem(pb.mesh, k, pb.op, pb.alpha, pb.penalty, pb.law))
+        levels.append(Problem(pb.mesh, k, pb.op, pb.alpha, pb.penalty, pb.law, pb.tau_div, pb.tau_cont))
     m = levels[-1].mesh
+    td, tc = pb.tau_div, pb.tau_cont
     while (h_coarsen and len(levels) < max_levels
            and all(c % 2 == 0 and c // 2 >= min_cells for c in (m.nx, m.ny, m.nz))):
+        if td is not None:     # penalty step: a coarse cell takes the mean of its 8 children's factors
+            td, tc = (np.asarray(t, float).reshape(m.nz // 2, 2, m.ny // 2, 2, m.nx // 2, 2)
+                      .mean(axis=(1, 3, 5)).reshape(-1) for t in (td, tc))
         verts = m.vertices[::2, ::2, ::2].reshape(-1, 3)
         m = Mesh(m.nx // 2, m.ny // 2, m.nz // 2, verts, m.bc)
-        levels.append(Problem(m, levels[-1].degree, pb.op, pb.alpha, pb.penalty, pb.law))
+        levels.append(Problem(m, levels[-1].degree, pb.op, pb.alpha, pb.penalty, pb.law, td, tc))
     return levels
 
 

@@ -130,6 +130,32 @@ def carreau_law(seed: int, mu0: float = 1.0, mu_inf: float = 1e-4, lam: float = 
     }
 
 
+def penalty_parameters(nx: int, ny: int, nz: int, degree: int, vertices, seed: int,
+                       cfl: float = 0.4, zeta: float = 1.0) -> tuple[np.ndarray, np.ndarray]:
+    """Per-cell divergence and continuity penalty factors of the penalty step.
+
+    The paper takes them from Fehn et al. (2018); the reading used here is
+    tau_div = zeta |u_e| h dt / (k+1) and tau_cont = zeta |u_e| dt, with u_e
+    the seeded divergence-free velocity of ``carreau_law(seed)`` at the cell
+    centre (mean of the 8 vertices), h = 1/N per direction (geometric mean)
+    and dt = cfl * h / max_e |u_e|.
+    """
+    law = carreau_law(seed)
+    if vertices is None:
+        Z, Y, X = np.meshgrid(np.linspace(0, 1, nz + 1), np.linspace(0, 1, ny + 1), np.linspace(0, 1, nx + 1),
+                              indexing="ij")
+        vertices = np.stack([X, Y, Z], axis=-1)
+    V = np.asarray(vertices, dtype=np.float64).reshape(nz + 1, ny + 1, nx + 1, 3)
+    centre = 0.125 * sum(V[c:nz + c, b:ny + b, a:nx + a] for a in (0, 1) for b in (0, 1) for c in (0, 1))
+    x = centre.reshape(-1, 3)
+    arg = 2 * np.pi * x @ law["k"].T.astype(np.float64) + law["phi"]
+    w = np.cos(arg) @ law["v"]
+    speed = np.linalg.norm(w, axis=1)
+    h = (1.0 / nx / ny / nz) ** (1.0 / 3.0)
+    dt = cfl * h / speed.max()
+    return zeta * speed * h * dt / (degree + 1), zeta * speed * dt
+
+
 def uniform_vector(seed: int, n: int) -> np.ndarray:
     """n values ~ U(-1, 1) from numpy's default generator."""
     return np.random.default_rng(seed).uniform(-1.0, 1.0, size=n)
@@ -153,6 +179,8 @@ def config(name: str, n: int | None = None) -> dict:
     c3  24^3 perturbed, k=4, viscous, Carreau of a seeded velocity, seed 3.
     c4p 20^3 affine, k=5, Poisson, all Neumann (singular, mean-zero data).
     c4v 20^3 affine, k=5, viscous, sine viscosity, Dirichlet.
+    c6  16^3 perturbed, k=3, penalty step (mass + divergence and continuity
+        penalties, per-cell factors from ``penalty_parameters``, seed 6).
     """
     if name == "c1":
         return _cfg("c1", n or 4, 2, "viscous", sine_law(1.0, 0.5), 10.0, ALL_DIRICHLET, 0.0,
@@ -169,6 +197,11 @@ def config(name: str, n: int | None = None) -> dict:
     if name == "c4v":
         return _cfg("c4v", n or 20, 5, "viscous", sine_law(1.0, 0.5), 10.0, ALL_DIRICHLET, 0.0,
                     x_seed=4, tol=1e-8)
+    if name == "c6":
+        m = n or 16
+        td, tc = penalty_parameters(m, m, m, 3, box_vertices(m, m, m, 0.1), 6)
+        return _cfg("c6", m, 3, "penalty", None, 1.0, ALL_DIRICHLET, 0.1, x_seed=6, tol=1e-8,
+                    tau_div=td, tau_cont=tc)
     raise KeyError(name)
 
 
@@ -177,7 +210,7 @@ CONFIGS = ("c1", "c2", "c3", "c4p", "c4v")
 
 def ndofs(cfg: dict) -> int:
     n = cfg["degree"] + 1
-    comps = 3 if cfg["op"] == "viscous" else 1
+    comps = 1 if cfg["op"] == "poisson" else 3
     return cfg["nx"] * cfg["ny"] * cfg["nz"] * comps * n ** 3
 
 
