@@ -30,7 +30,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, published
 FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 vector, published
 METRIC = "operator DoF/s FP64 vs mixed; solves/s and p50/p99 latency at 1e-8 rel. res."
-KERNEL_SRC = os.path.join(ROOT, "paper_2506_14424_amd", "csrc", "apply.hip")
+KERNEL_SRC = [os.path.join(ROOT, "paper_2506_14424_amd", "csrc", f) for f in ("apply_kernel.h", "apply.hip")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_apply_c2.json")
 
 
@@ -55,7 +55,7 @@ def algorithmic_bytes(cfg, elem: int) -> dict:
 
 
 def kernel_hash() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    return hashlib.sha256(b"".join(open(f, "rb").read() for f in KERNEL_SRC)).hexdigest()[:16]
 
 
 def time_applies(op, dtype, steps, warmup, rotate_bytes=640e6):

@@ -9,7 +9,13 @@
  *            (gamma_0/dt) M - div(2 mu eps(u)), SIPG fluxes u = {{u}},
  *            tau_1 = {{mu grad u}} - tau [[u]], tau_2 = tau_1^T ("Viscous Step");
  *   poisson  the SIPG Laplacian of the pressure step ("Pressure Step"), with
- *            the coercive penalty sign and an optional mass term alpha.
+ *            the coercive penalty sign and an optional mass term alpha;
+ *   penalty  the operator of the penalty step (Sec. 3, "Consistent
+ *            Stabilization", eq. penalty_step): (alpha v, u) +
+ *            (div v, tau_div^e div u)_e + (v.n, tau_cont [[u]].n) on faces, with
+ *            per-cell factors given by the caller, the face factor the mean of
+ *            the two cells' tau_cont, and the oriented jump u - g on Dirichlet
+ *            faces (no mirror doubling); alpha = 1 is the paper's form.
  * Boundary conditions are homogeneous and imposed by the mirror principle
  * (Sec. 4).  Penalty: tau = P (k+1)^2 mu(x) / h_F, h_F = min(h^-, h^+),
  * h_e = |cell|^(1/3) (the paper defers the formula to Hillewaert 2013).
@@ -23,7 +29,7 @@
  *
  * Vector layout (all device vectors): cell-major,
  *   index = ((e*C + c)*n + i3)*n*n + i2*n + i1,   n = k+1,
- *   e = (ez*ny + ey)*nx + ex, C = 3 (viscous) or 1 (poisson),
+ *   e = (ez*ny + ey)*nx + ex, C = 3 (viscous, penalty) or 1 (poisson),
  *   node (i1, i2, i3) at reference point (g[i1], g[i2], g[i3]) of cell e.
  *
  * Ownership: the caller owns every device buffer (vectors and the workspace);
@@ -60,7 +66,7 @@ typedef enum {
 } sipg_status;
 
 typedef enum { SIPG_F64 = 0, SIPG_F32 = 1 } sipg_precision;
-typedef enum { SIPG_VISCOUS = 0, SIPG_POISSON = 1 } sipg_operator;
+typedef enum { SIPG_VISCOUS = 0, SIPG_POISSON = 1, SIPG_PENALTY = 2 } sipg_operator;
 typedef enum { SIPG_BC_DIRICHLET = 0, SIPG_BC_NEUMANN = 1 } sipg_bc;
 
 /* Viscosity laws, evaluated at physical quadrature points x:
@@ -106,7 +112,9 @@ typedef struct {
     int32_t op;                /* sipg_operator */
     int32_t degree;            /* k, 1..5 */
     double alpha;              /* gamma_0/dt in front of the mass term, >= 0 */
-    double penalty;            /* P > 0 */
+    double penalty;            /* P > 0 (SIPG operators) */
+    const double* tau_div;     /* SIPG_PENALTY: host [ncells] divergence factors >= 0, else ignored */
+    const double* tau_cont;    /* SIPG_PENALTY: host [ncells] continuity factors >= 0, else ignored */
 } sipg_params;
 
 typedef struct {
@@ -216,8 +224,10 @@ void sipg_solve_opts_default(sipg_solve_opts* opts);
  * (Sec. 5.3: double-precision Krylov, single-precision preconditioner,
  * Chebyshev-Jacobi on the inverse diagonal), followed by an FP64 true-residual
  * check with restarts.  Pure-Neumann Poisson with alpha = 0 is solved in the
- * mean-zero subspace (Sec. 3.2).  Needs a plan bound with_solver.  Blocks
- * until done; info may be NULL.  Returns the solve's status. */
+ * mean-zero subspace (Sec. 3.2).  SIPG_ERR_UNSUPPORTED for the singular
+ * cases left: pure-Neumann viscous and penalty operators with alpha = 0.
+ * Needs a plan bound with_solver.  Blocks until done; info may be NULL.
+ * Returns the solve's status. */
 sipg_status sipg_solve(sipg_plan* plan, const double* b, double* x, const sipg_solve_opts* opts,
                        sipg_solve_info* info, void* stream);
 

@@ -10,7 +10,8 @@ LIB_PATH = os.path.join(HERE, "libsipg.so")
 PART_CELL, PART_INTERIOR, PART_BOUNDARY, PART_ALL = 1, 2, 4, 7
 PRECOND = {"chebyshev": 0, "multigrid": 1}
 F64, F32 = 0, 1
-VISCOUS, POISSON = 0, 1
+VISCOUS, POISSON, PENALTY = 0, 1, 2
+OPS = {"viscous": VISCOUS, "poisson": POISSON, "penalty": PENALTY}
 BC = {"D": 0, "N": 1}
 LAW = {"const": 0, "sine": 1, "logfield": 2, "carreau": 3}
 MAX_MODES = 16
@@ -44,7 +45,8 @@ class Viscosity(C.Structure):
 
 class Params(C.Structure):
     _fields_ = [("op", C.c_int32), ("degree", C.c_int32), ("alpha", C.c_double),
-                ("penalty", C.c_double)]
+                ("penalty", C.c_double), ("tau_div", C.POINTER(C.c_double)),
+                ("tau_cont", C.POINTER(C.c_double))]
 
 
 class SolveOpts(C.Structure):

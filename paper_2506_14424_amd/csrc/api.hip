@@ -113,6 +113,9 @@ struct sipg_plan {
     bool curved;
     std::vector<double> verts;
     std::vector<float> verts32;
+    bool pen = false;                    // penalty-step operator
+    std::vector<double> tau_div, tau_cont;   // its per-cell factors (host)
+    double *tau_div_d = nullptr, *tau_cont_d = nullptr;
     LawDev law;
     long long ncell, ndof, nface, nvert;
     Tables<double> tab64;
@@ -166,6 +169,7 @@ OpData<T> sipg_plan::opdata() const {
     o.nfx = (nx + 1) * ny * nz;
     o.nfy = nx * (ny + 1) * nz;
     for (int i = 0; i < 6; ++i) o.bc[i] = bc[i];
+    o.pen = pen ? 1 : 0;
     o.alpha = T(alpha);
     o.h[0] = T(1.0 / nx); o.h[1] = T(1.0 / ny); o.h[2] = T(1.0 / nz);
     o.hinv[0] = T(nx); o.hinv[1] = T(ny); o.hinv[2] = T(nz);
@@ -190,6 +194,7 @@ struct Layout {
     size_t verts64, verts32, hcell, tfac64, tfac32, mu_cell64, mu_cell32, mu_face64, mu_face32, diag64, dinv64,
         dinv32;
     size_t r, p, q, z, zo, cr, cd, cz0, cz1, partials, st;
+    size_t tdiv = 0, tcont = 0;       // penalty step: per-cell factors
     size_t mgz = 0, mgt = 0;          // multigrid: finest-level vectors
     std::vector<size_t> level, level_bytes;   // multigrid: workspaces of the coarser levels
     size_t op_end, total;
@@ -201,7 +206,8 @@ Layout layout(const sipg_plan* P) {
     auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
     const size_t nv = P->curved ? (size_t)P->nvert * 3 : 0;
     const size_t nqc = P->C == 3 ? (size_t)P->ncell * P->n * P->n * P->n : 0;
-    const size_t nqf = P->C == 3 ? (size_t)P->nface * P->n * P->n : 0;
+    const size_t nqf = (P->C == 3 && !P->pen) ? (size_t)P->nface * P->n * P->n : 0;
+    const size_t ntau = P->pen ? (size_t)P->ncell : 0;
     const size_t nd = (size_t)P->ndof;
     L.verts64 = take(nv * 8); L.verts32 = take(nv * 4);
     L.hcell = take((size_t)P->ncell * 8);
@@ -209,6 +215,7 @@ Layout layout(const sipg_plan* P) {
     L.mu_cell64 = take(nqc * 8); L.mu_cell32 = take(nqc * 4);
     L.mu_face64 = take(nqf * 8); L.mu_face32 = take(nqf * 4);
     L.diag64 = take(nd * 8); L.dinv64 = take(nd * 8); L.dinv32 = take(nd * 4);
+    L.tdiv = take(ntau * 8); L.tcont = take(ntau * 8);
     L.op_end = off;
     L.r = take(nd * 8); L.p = take(nd * 8); L.q = take(nd * 8); L.z = take(nd * 8); L.zo = take(nd * 8);
     L.cr = take(nd * 8); L.cd = take(nd * 8); L.cz0 = take(nd * 8); L.cz1 = take(nd * 8);
@@ -530,7 +537,10 @@ sipg_status sipg_plan_create(const sipg_mesh* mesh, const sipg_viscosity* law, c
     if (!mesh || !params || !out) return fail(SIPG_ERR_INVALID, "null argument");
     if (mesh->nx < 1 || mesh->ny < 1 || mesh->nz < 1) return fail(SIPG_ERR_INVALID, "mesh needs >= 1 cell per direction");
     if (params->degree < 1 || params->degree > 5) return fail(SIPG_ERR_INVALID, "degree must be 1..5");
-    if (params->op != SIPG_VISCOUS && params->op != SIPG_POISSON) return fail(SIPG_ERR_INVALID, "unknown operator");
+    if (params->op != SIPG_VISCOUS && params->op != SIPG_POISSON && params->op != SIPG_PENALTY)
+        return fail(SIPG_ERR_INVALID, "unknown operator");
+    if (params->op == SIPG_PENALTY && (!params->tau_div || !params->tau_cont))
+        return fail(SIPG_ERR_INVALID, "penalty operator needs tau_div and tau_cont per cell");
     if (!(params->alpha >= 0.0) || !std::isfinite(params->alpha)) return fail(SIPG_ERR_INVALID, "alpha must be >= 0");
     if (!(params->penalty > 0.0) || !std::isfinite(params->penalty)) return fail(SIPG_ERR_INVALID, "penalty must be > 0");
     for (int i = 0; i < 6; ++i)
@@ -538,7 +548,7 @@ sipg_status sipg_plan_create(const sipg_mesh* mesh, const sipg_viscosity* law, c
     if ((long long)(mesh->nx + 1) * (mesh->ny + 1) * (mesh->nz + 1) * 3 >= (1ll << 31))
         return fail(SIPG_ERR_INVALID, "mesh too large: 2^31 or more vertex coordinates");
     const long long ncell = (long long)mesh->nx * mesh->ny * mesh->nz;
-    const int n = params->degree + 1, C = params->op == SIPG_VISCOUS ? 3 : 1;
+    const int n = params->degree + 1, C = params->op == SIPG_POISSON ? 1 : 3;
     const long long ndof = ncell * C * n * n * n;
     if (ndof > (1ll << 31) - 1 || ncell * n * n * n > (1ll << 31) - 1)
         return fail(SIPG_ERR_UNSUPPORTED, "problem too large for 32-bit cell indexing");
@@ -562,7 +572,17 @@ sipg_status sipg_plan_create(const sipg_mesh* mesh, const sipg_viscosity* law, c
         P->verts32.assign(P->verts.begin(), P->verts.end());
     }
     std::memset(&P->law, 0, sizeof(P->law));
-    if (C == 3) {
+    if (params->op == SIPG_PENALTY) {
+        P->pen = true;
+        P->tau_div.assign(params->tau_div, params->tau_div + ncell);
+        P->tau_cont.assign(params->tau_cont, params->tau_cont + ncell);
+        for (long long e = 0; e < ncell; ++e)
+            if (!(P->tau_div[e] >= 0.0) || !(P->tau_cont[e] >= 0.0) || !std::isfinite(P->tau_div[e]) ||
+                !std::isfinite(P->tau_cont[e])) {
+                delete P;
+                return fail(SIPG_ERR_INVALID, "penalty factors must be finite and >= 0");
+            }
+    } else if (C == 3) {
         if (!law) { delete P; return fail(SIPG_ERR_INVALID, "viscous operator needs a viscosity law"); }
         LawDev& L = P->law;
         L.kind = law->kind;
@@ -654,8 +674,14 @@ sipg_status sipg_plan_bind(sipg_plan* P, void* workspace, size_t bytes, int32_t 
     if (P->C == 3) {
         P->mu_cell64 = reinterpret_cast<double*>(w + L.mu_cell64);
         P->mu_cell32 = reinterpret_cast<float*>(w + L.mu_cell32);
-        P->mu_face64 = reinterpret_cast<double*>(w + L.mu_face64);
-        P->mu_face32 = reinterpret_cast<float*>(w + L.mu_face32);
+        if (!P->pen) {
+            P->mu_face64 = reinterpret_cast<double*>(w + L.mu_face64);
+            P->mu_face32 = reinterpret_cast<float*>(w + L.mu_face32);
+        }
+    }
+    if (P->pen) {
+        P->tau_div_d = reinterpret_cast<double*>(w + L.tdiv);
+        P->tau_cont_d = reinterpret_cast<double*>(w + L.tcont);
     }
     P->diag64 = reinterpret_cast<double*>(w + L.diag64);
     P->dinv64 = reinterpret_cast<double*>(w + L.dinv64);
@@ -680,9 +706,13 @@ sipg_status sipg_plan_bind(sipg_plan* P, void* workspace, size_t bytes, int32_t 
         HIP_TRY(hipMemcpyAsync(P->verts64_d, P->verts.data(), P->verts.size() * 8, hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemcpyAsync(P->verts32_d, P->verts32.data(), P->verts32.size() * 4, hipMemcpyHostToDevice, s));
     }
+    if (P->pen) {
+        HIP_TRY(hipMemcpyAsync(P->tau_div_d, P->tau_div.data(), P->ncell * 8, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(P->tau_cont_d, P->tau_cont.data(), P->ncell * 8, hipMemcpyHostToDevice, s));
+    }
     const OpData<double> od = P->opdata<double>();
     HIP_TRY(launch_setup(P->n, P->C, P->curved, od, P->law, P->penalty, P->hcell, P->tfac64, P->tfac32, P->mu_cell64,
-                         P->mu_cell32, P->mu_face64, P->mu_face32, (int)P->nface, s));
+                         P->mu_cell32, P->mu_face64, P->mu_face32, (int)P->nface, P->tau_div_d, P->tau_cont_d, s));
     const OpData<double> od2 = P->opdata<double>();
     HIP_TRY(launch_diagonal(P->n, P->C, P->curved, od2, P->diag64, P->dinv64, P->dinv32, s));
     if (P->mg_on && P->with_solver) {
@@ -733,7 +763,7 @@ sipg_status sipg_diagonal(sipg_plan* P, int32_t precision, int32_t inverse, void
 sipg_status sipg_viscosity_values(sipg_plan* P, double* mu_cell, double* mu_face, void* stream) {
     if (!valid_plan(P)) return fail(SIPG_ERR_INVALID, "null plan");
     if (!P->bound) return fail(SIPG_ERR_STATE, "plan not bound");
-    if (P->C != 3) return fail(SIPG_ERR_INVALID, "the poisson operator has no viscosity");
+    if (P->op != SIPG_VISCOUS) return fail(SIPG_ERR_INVALID, "only the viscous operator has a viscosity");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const size_t nn = (size_t)P->n * P->n;
     if (mu_cell) HIP_TRY(hipMemcpyAsync(mu_cell, P->mu_cell64, P->ncell * nn * P->n * 8, hipMemcpyDeviceToDevice, s));
@@ -775,6 +805,7 @@ sipg_status sipg_plan_set_multigrid(sipg_plan* P, const sipg_mg_opts* opts) {
     // levels: degree k-1 .. 1 on the plan's mesh, then the mesh halved while possible
     int deg = P->degree, nx = P->nx, ny = P->ny, nz = P->nz;
     std::vector<double> verts = P->verts;
+    std::vector<double> td = P->tau_div, tc = P->tau_cont;   // penalty step: factors of the level's cells
     int nlev = 1, n_prev = P->n;
     auto add_level = [&](bool mesh_step) -> sipg_status {
         sipg_mesh m;
@@ -787,7 +818,10 @@ sipg_status sipg_plan_set_multigrid(sipg_plan* P, const sipg_mg_opts* opts) {
         law.kind = SIPG_LAW_CONST;
         law.mu = 1.0;                                   // replaced by the plan's law below
         sipg_params par;
+        std::memset(&par, 0, sizeof(par));
         par.op = P->op; par.degree = deg; par.alpha = P->alpha; par.penalty = P->penalty;
+        par.tau_div = td.empty() ? nullptr : td.data();
+        par.tau_cont = tc.empty() ? nullptr : tc.data();
         sipg_plan* c = nullptr;
         const sipg_status rc = sipg_plan_create(&m, &law, &par, &c);
         if (rc != SIPG_OK) return rc;
@@ -815,6 +849,25 @@ sipg_status sipg_plan_set_multigrid(sipg_plan* P, const sipg_mg_opts* opts) {
                         for (int d = 0; d < 3; ++d)
                             cv.push_back(verts[(((size_t)k * (ny + 1) + j) * (nx + 1) + i) * 3 + d]);
             verts.swap(cv);
+        }
+        if (P->pen) {                                    // a coarse cell takes the mean of its 8 children
+            std::vector<double> ctd((size_t)(nx / 2) * (ny / 2) * (nz / 2)), ctc(ctd.size());
+            for (int k = 0; k < nz / 2; ++k)
+                for (int j = 0; j < ny / 2; ++j)
+                    for (int i = 0; i < nx / 2; ++i) {
+                        double a = 0.0, b = 0.0;
+                        for (int c = 0; c < 8; ++c) {
+                            const size_t f = ((size_t)(2 * k + (c >> 2)) * ny + 2 * j + ((c >> 1) & 1)) * nx +
+                                             2 * i + (c & 1);
+                            a += td[f];
+                            b += tc[f];
+                        }
+                        const size_t e = ((size_t)k * (ny / 2) + j) * (nx / 2) + i;
+                        ctd[e] = a / 8.0;
+                        ctc[e] = b / 8.0;
+                    }
+            td.swap(ctd);
+            tc.swap(ctc);
         }
         nx /= 2; ny /= 2; nz /= 2;
         rc = add_level(true);
@@ -909,6 +962,8 @@ sipg_status sipg_solve_begin(sipg_plan* P, const double* b, double* x, const sip
     sipg_status vrc = check_opts(P, o);
     if (vrc != SIPG_OK) return vrc;
     const bool all_neumann = std::all_of(P->bc, P->bc + 6, [](int v) { return v == SIPG_BC_NEUMANN; });
+    if (P->pen && P->alpha == 0.0)
+        return fail(SIPG_ERR_UNSUPPORTED, "penalty operator with alpha = 0 is singular (continuous divergence-free fields)");
     if (P->C == 3 && all_neumann && P->alpha == 0.0)
         return fail(SIPG_ERR_UNSUPPORTED, "pure-Neumann viscous operator with alpha = 0 is singular (rigid motions)");
     P->mean_zero = P->C == 1 && all_neumann && P->alpha == 0.0;

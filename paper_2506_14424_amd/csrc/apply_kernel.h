@@ -1,0 +1,898 @@
+// Matrix-free operator application (SIPG viscous and Poisson, penalty step) for gfx950:
+// the kernel template, instantiated by apply.hip and apply_penalty.hip.
+//
+// One workgroup handles CPB cells; each cell gets n*n threads.  Everything a
+// cell needs is computed by its own threads ("cell-centric"): the cell
+// integral and all six face integrals for the cell's own test functions.  A
+// face is therefore evaluated once from each side, but every output entry is
+// written exactly once, with no atomics and no second pass over the output.
+// The neighbour's trace on a shared face is interpolated from the
+// neighbour's nodal values, which the XCD-aware block order keeps in the L2.
+//
+// Sum factorisation (Sec. 5.3): with nodes at the Gauss points, values at
+// quadrature points are the nodal values, and reference derivatives are 1D
+// contractions with D[q][j] = l_j'(g_q) along one axis.  For every 1D sweep a
+// thread owns a whole line of n values (the n*n threads of a cell own the
+// n*n lines of each direction), so all sweep coefficients are the same for
+// the whole wavefront and stay in scalar registers; lines are exchanged
+// through LDS between sweeps.  The thread (i1, i2) owns the xi_3 line
+// (i1, i2, 0..n-1) of quadrature points and outputs.
+//
+// Forms (Sec. 4.1), per quadrature point, for the test functions of the cell
+// that owns the thread (outward unit normal n, [u] = u_own - u_nbr):
+//   cell      viscous: sigma = 2 mu eps(u) JxW, mass alpha u JxW
+//             poisson: sigma = grad u JxW,      mass alpha u JxW
+//   face      viscous: a = -2 {{mu eps(u)}} n + tau([u] + n([u].n)),
+//                      B = -mu sym([u] (x) n)
+//             poisson: a = -{{grad u}}.n + tau [u],  B = -[u] n / 2
+//   and the test integration y_i += sum ds (phi_i a + grad phi_i : B).
+// Dirichlet faces use the mirror state u_nbr = -u_own, grad u_nbr = grad u_own;
+// Neumann faces contribute nothing.
+
+#pragma once
+
+#include "device_common.h"
+
+namespace sipg {
+
+template <int N, int C, bool DBL>
+struct Shape {
+    // cells per workgroup: one wavefront for n <= 4, LDS well under 64 KB
+    static constexpr int CPB = N == 2 ? 16 : N == 3 ? 7 : N == 4 ? 4 : N == 5 ? 5 : (DBL && C == 3 ? 3 : 7);
+    static constexpr int THREADS = CPB * N * N;
+    static constexpr int NNN = N * N * N, NN = N * N;
+    // LDS layout of a cell's volume arrays: node (i1, i2, i3) of component c at
+    //   plain:  c*CS + i3*S3 + i2*N + i1,
+    //   skewed: c*CS + (i3 ^ x)*S3 + ((i2 + i3) % N)*N + (i1 + i3) % N, x = cell % 4.
+    // The skew (FP64, n = 4) makes the xi_1-line, xi_2-line and xi_3-column
+    // patterns of a cell's 16 lanes hit 16 different bank pairs, and the
+    // plane swap x moves the four cells of a wavefront onto different
+    // quarters of the banks without padding.  In FP32 the padded xi_3
+    // stride S3 spreads the three patterns instead (n = 3, 4); there the
+    // padding costs no occupancy.
+    static constexpr bool SKEW = DBL && N == 4;
+    static constexpr int S3 = DBL ? NN : (N == 3 ? 12 : N == 4 ? 19 : NN);
+    static constexpr int CS = N * S3;
+    // per-cell LDS: nodal values and a work space for the cell sweeps and the
+    // face stages; +1 staggers consecutive cells over the LDS banks (plain layout)
+    static constexpr int U = C * CS + (SKEW ? 0 : 1);
+    // work-space stride: skewed layout +8 (the four cells of a wavefront at
+    // offsets 0, 8, 16, 24 mod 32 doubles: line tasks and lane-per-point
+    // accesses of the face stages spread over all bank pairs), else +1
+    static constexpr int W = (2 * C * CS > 8 * C * NN ? 2 * C * CS : 8 * C * NN) + (SKEW ? 8 : 1);
+};
+
+// Barrier between LDS stages.  A workgroup of one wavefront only needs the
+// wavefront's own (in-order) LDS accesses fenced against compiler reordering.
+template <int THREADS>
+__device__ __forceinline__ void stage_sync() {
+    if constexpr (THREADS <= 64) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
+// Reciprocal: hardware estimate refined by Newton steps to full precision.
+template <typename T>
+__device__ __forceinline__ T recip(T d) {
+    if constexpr (sizeof(T) == 8) {
+        double r = __builtin_amdgcn_rcp(d);
+        double e = __builtin_fma(-d, r, 1.0);
+        r = __builtin_fma(r, e, r);
+        e = __builtin_fma(-d, r, 1.0);
+        return __builtin_fma(r, e, r);
+    } else {
+        float r = __builtin_amdgcn_rcpf(d);
+        const float e = __builtin_fmaf(-d, r, 1.0f);
+        return __builtin_fmaf(r, e, r);
+    }
+}
+
+// 1/sqrt(v): hardware estimate refined by Newton steps to full precision.
+template <typename T>
+__device__ __forceinline__ T rsqrt_nr(T v) {
+    if constexpr (sizeof(T) == 8) {
+        double r = __builtin_amdgcn_rsq(v);
+        double h = 0.5 * v;
+        r = r * __builtin_fma(-h * r, r, 1.5);
+        r = r * __builtin_fma(-h * r, r, 1.5);
+        return r;
+    } else {
+        float r = __builtin_amdgcn_rsqf(v);
+        return r * __builtin_fmaf(-0.5f * v * r, r, 1.5f);
+    }
+}
+
+// Columns a_d = d x / d xi_d of the Jacobian of a trilinear cell at xi.
+template <typename T>
+__device__ __forceinline__ void jac_columns(const T (*g)[3], const T xi[3], T a[3][3]) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        a[0][i] = g[1][i] + g[4][i] * xi[1] + g[5][i] * xi[2] + g[7][i] * (xi[1] * xi[2]);
+        a[1][i] = g[2][i] + g[4][i] * xi[0] + g[6][i] * xi[2] + g[7][i] * (xi[0] * xi[2]);
+        a[2][i] = g[3][i] + g[5][i] * xi[0] + g[6][i] * xi[1] + g[7][i] * (xi[0] * xi[1]);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void cross3(const T u[3], const T v[3], T w[3]) {
+    w[0] = u[1] * v[2] - u[2] * v[1];
+    w[1] = u[2] * v[0] - u[0] * v[2];
+    w[2] = u[0] * v[1] - u[1] * v[0];
+}
+
+// Rows of J^-1 from the columns: row d = (a_{d+1} x a_{d+2}) / det.
+template <typename T>
+__device__ __forceinline__ void inverse_from_columns(const T a[3][3], T Ji[3][3], T& det) {
+    T c0[3], c1[3], c2[3];
+    cross3(a[1], a[2], c0);
+    cross3(a[2], a[0], c1);
+    cross3(a[0], a[1], c2);
+    det = a[0][0] * c0[0] + a[0][1] * c0[1] + a[0][2] * c0[2];
+    const T inv = recip(det);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        Ji[0][i] = c0[i] * inv;
+        Ji[1][i] = c1[i] * inv;
+        Ji[2][i] = c2[i] * inv;
+    }
+}
+
+struct CellIdx {
+    int lc, t, i1, i2, ec, ex, ey, ez;
+    bool active;
+};
+
+// Per-lane LDS offsets of the three line patterns of a cell's volume arrays
+// (lane (la, lb) = (t % n, t / n)): oz[j] = node (la, lb, j), the lane's
+// xi_3 column; ox[j] = node (j, la, lb), a xi_1 line; oy[j] = node (la, j, lb),
+// a xi_2 line.
+template <int N>
+struct VolOff {
+    int oz[N], ox[N], oy[N];
+};
+
+template <int N, int S3, bool SKEW>
+__device__ __forceinline__ int vol_pos(int i1, int i2, int i3, int px) {
+    if constexpr (!SKEW) {
+        return i3 * S3 + i2 * N + i1;
+    } else {
+        int a = i2 + i3, b = i1 + i3;
+        a = a >= N ? a - N : a;
+        b = b >= N ? b - N : b;
+        return (i3 ^ px) * S3 + a * N + b;
+    }
+}
+
+template <int N, int S3, bool SKEW>
+__device__ __forceinline__ void vol_offsets(int la, int lb, int lc, VolOff<N>& o) {
+    const int px = lc & 3;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        o.oz[j] = vol_pos<N, S3, SKEW>(la, lb, j, px);
+        o.ox[j] = vol_pos<N, S3, SKEW>(j, la, lb, px);
+        o.oy[j] = vol_pos<N, S3, SKEW>(la, j, lb, px);
+    }
+}
+
+// Small per-lane tables kept in LDS: points, weights, face values/derivatives.
+template <typename T, int N>
+struct LaneTab {
+    T x[N], w[N], S[2][N], G[2][N];
+};
+
+// The neighbour's line of nodal values through face point (i1, i2) of face
+// (D, s), and the face viscosity and penalty factor at that point.
+template <int N, int C, typename T, bool CURVED, int D>
+__device__ __forceinline__ void face_prefetch(const OpData<T>& op, const ApplyIO<T>& io, const CellIdx& ci, int s,
+                                              T (&nb)[C][N], T& mu, T& tf, T (&gn)[8]) {
+    constexpr int NN = N * N, NNN = N * N * N;
+    const int i1 = ci.i1, i2 = ci.i2;
+    const int pos = D == 0 ? ci.ex : D == 1 ? ci.ey : ci.ez;
+    const int lim = D == 0 ? op.nx : D == 1 ? op.ny : op.nz;
+    const bool has_nb = s == 1 ? pos + 1 < lim : pos > 0;
+    const int stride = D == 0 ? 1 : D == 1 ? op.nx : op.nx * op.ny;
+    const int en = has_nb ? ci.ec + (s == 1 ? stride : -stride) : ci.ec;
+    const bool dir = !has_nb && op.bc[2 * D + s] == 0;
+    const bool live = ci.active && (has_nb ? (io.parts & SIPG_PART_INTERIOR) != 0
+                                           : (dir && (io.parts & SIPG_PART_BOUNDARY) != 0));
+    int fid;
+    if (D == 0) fid = (ci.ez * op.ny + ci.ey) * (op.nx + 1) + ci.ex + s;
+    else if (D == 1) fid = op.nfx + (ci.ez * (op.ny + 1) + ci.ey + s) * op.nx + ci.ex;
+    else fid = op.nfx + op.nfy + ((ci.ez + s) * op.ny + ci.ey) * op.nx + ci.ex;
+    if constexpr (CURVED) {
+        const int dn = has_nb ? (s == 1 ? 1 : -1) : 0;  // the neighbour is one cell away along xi_D
+        trilinear_coeffs(op.verts, op.nx, op.ny, ci.ex + (D == 0 ? dn : 0), ci.ey + (D == 1 ? dn : 0),
+                         ci.ez + (D == 2 ? dn : 0), ci.t % 3, gn);
+    }
+    const T* xn = io.x + (size_t)en * (C * NNN);
+    const bool ld = live && has_nb;
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            int off;
+            if (D == 2) off = (c * N + j) * NN + i2 * N + i1;
+            else if (D == 0) off = (c * N + i2) * NN + i1 * N + j;
+            else off = (c * N + i2) * NN + j * N + i1;
+            const T v = xn[off];  // en and fid are valid for every lane: load unconditionally
+            nb[c][j] = ld ? v : T(0);
+        }
+    const T muf = C == 3 ? op.mu_face[(size_t)fid * NN + ci.t] : T(1);
+    const T tff = op.tfac[fid];
+    mu = live ? muf : T(1);
+    tf = live ? tff : T(0);
+}
+
+// ---------------------------------------------------------------- faces
+//
+// One face of the cell (direction D, side s), in stages separated by LDS
+// barriers:
+//   A  traces of both sides at face point (a, b) = (i1, i2): values into LDS,
+//      d/dxi_D in registers;
+//   B1 tangential derivatives of both traces, one line per task;
+//   B2 geometry and flux at the face point;
+//   C1 transposed tangential sweeps of the flux, one line per task;
+//   C2 projection onto the cell's nodes (accumulated in y).
+template <int N, int C, typename T, bool CURVED, int D, int THREADS>
+__device__ __forceinline__ void face_pass(const OpData<T>& op, const ApplyIO<T>& io, const CellIdx& ci, int s,
+                                          T (&y)[C][N], const T* su, T* sw, T (*geo)[8][3],
+                                          const LaneTab<T, N>& lt, const VolOff<N>& vo) {
+    T nbl[C][N], mu_pre, tf_pre, gnb[8];
+    face_prefetch<N, C, T, CURVED, D>(op, io, ci, s, nbl, mu_pre, tf_pre, gnb);
+    constexpr int NN = N * N, NNN = N * N * N;
+    constexpr int CS = Shape<N, C, sizeof(T) == 8>::CS;
+    constexpr int t1 = D == 0 ? 1 : 0, t2 = D == 2 ? 1 : 2;
+    const auto& tb = op.tab;
+    const int i1 = ci.i1, i2 = ci.i2, t = ci.t;
+    const int pos = D == 0 ? ci.ex : D == 1 ? ci.ey : ci.ez;
+    const int lim = D == 0 ? op.nx : D == 1 ? op.ny : op.nz;
+    const bool has_nb = s == 1 ? pos + 1 < lim : pos > 0;
+    const int stride = D == 0 ? 1 : D == 1 ? op.nx : op.nx * op.ny;
+    const int en = has_nb ? ci.ec + (s == 1 ? stride : -stride) : ci.ec;
+    const bool dir = !has_nb && op.bc[2 * D + s] == 0;
+    const bool live = ci.active && (has_nb ? (io.parts & SIPG_PART_INTERIOR) != 0
+                                           : (dir && (io.parts & SIPG_PART_BOUNDARY) != 0));
+    int fid;
+    if (D == 0) fid = (ci.ez * op.ny + ci.ey) * (op.nx + 1) + ci.ex + s;
+    else if (D == 1) fid = op.nfx + (ci.ez * (op.ny + 1) + ci.ey + s) * op.nx + ci.ex;
+    else fid = op.nfx + op.nfy + ((ci.ez + s) * op.ny + ci.ey) * op.nx + ci.ex;
+    // LDS regions of the work space, each [.][C][NN]
+    T* FT = sw;               // [2] trace values (own, neighbour)          A  -> B1
+    T* TD = sw + 2 * C * NN;  // [2][2] tangential derivatives (side, dir)  B1 -> B2
+    T* BT = sw;               // [2] flux components along t1, t2           B2 -> C1
+    T* VT = sw + 2 * C * NN;  // [2] transposed sweeps                      C1 -> C2
+    T* VV = sw + 6 * C * NN;  // [2] value / normal coefficients (D < 2)    C2
+
+    // ---- A: traces
+    T ju[C], uno[C], unn[C];  // jump u_own - u_nbr (mirror state on Dirichlet faces), normal derivatives
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        T v0 = 0, v1 = 0, w0 = 0, w1 = 0;
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            T own;
+            if (D == 2) own = su[c * CS + vo.oz[j]];
+            else if (D == 0) own = su[c * CS + vo.ox[j]];
+            else own = su[c * CS + vo.oy[j]];
+            v0 += tb.S[s][j] * own;
+            v1 += tb.G[s][j] * own;
+            w0 += tb.S[1 - s][j] * nbl[c][j];
+            w1 += tb.G[1 - s][j] * nbl[c][j];
+        }
+        ju[c] = has_nb ? v0 - w0 : T(2) * v0;
+        uno[c] = v1;
+        unn[c] = w1;
+        FT[c * NN + t] = v0;
+        FT[(C + c) * NN + t] = w0;
+    }
+    if constexpr (CURVED) {
+        if (t < 3)
+#pragma unroll
+            for (int k = 0; k < 8; ++k) geo[1][k][t] = gnb[k];
+    }
+    stage_sync<THREADS>();
+
+    // ---- B1: tangential derivatives; task k = ((side*2 + dir)*C + c)*N + line
+#pragma unroll
+    for (int k0 = 0; k0 < 4 * C * N; k0 += NN) {
+        const int k = k0 + t;
+        if (k < 4 * C * N) {
+            const int line = k % N, c = (k / N) % C, dirn = (k / (N * C)) % 2, side = k / (2 * N * C);
+            const T* in = FT + (side * C + c) * NN;
+            T* out = TD + ((side * 2 + dirn) * C + c) * NN;
+            const int base = dirn == 0 ? line * N : line;
+            const int step = dirn == 0 ? 1 : N;
+            T v[N];
+#pragma unroll
+            for (int j = 0; j < N; ++j) v[j] = in[base + j * step];
+#pragma unroll
+            for (int q = 0; q < N; ++q) {
+                T a = 0;
+#pragma unroll
+                for (int j = 0; j < N; ++j) a += tb.D[q][j] * v[j];
+                out[base + q * step] = a;
+            }
+        }
+    }
+    stage_sync<THREADS>();
+
+    // ---- B2: geometry and flux at the face point
+    //
+    // Own side: columns a_d = dx/dxi_d, adjugate rows c_d (c_0 = a_1 x a_2 and
+    // cyclic), J^-1 = rows c_d / det.  The neighbour's Jacobian J' differs only
+    // in column D, and its adjugate row D equals c_D, so with M = J'^-1 J
+    // (identity except column D, v = J'^-1 a_D: v_D = det / det',
+    // v_d = -(a'_D . c_d) / det' for d != D, det' = a'_D . c_D) the sum of the
+    // two physical gradients is (gr + gr' M) J^-1: one transformation with the
+    // own J^-1 for both sides.  The unit normal is sign * c_D / |c_D| and
+    // ds = |c_D| w_a w_b.  On straight cells J^-1 = diag(1/h) and M = I.
+    T xi[3];
+    xi[t1] = lt.x[i1];
+    xi[t2] = lt.x[i2];
+    xi[D] = T(s);
+    const T sgn = s == 1 ? T(1) : T(-1);
+    T Cr[3][3], idet;  // rows c_d (curved: adjugate, 1/det; straight: J^-1, 1)
+    T nrm[3], ds;
+    T v[3];            // curved: column D of M
+    if constexpr (CURVED) {
+        T a[3][3];
+        jac_columns(geo[0], xi, a);
+        cross3(a[1], a[2], Cr[0]);
+        cross3(a[2], a[0], Cr[1]);
+        cross3(a[0], a[1], Cr[2]);
+        const T det = a[0][0] * Cr[0][0] + a[0][1] * Cr[0][1] + a[0][2] * Cr[0][2];
+        idet = recip(det);
+        const T nv2 = Cr[D][0] * Cr[D][0] + Cr[D][1] * Cr[D][1] + Cr[D][2] * Cr[D][2];
+        const T rinv = rsqrt_nr(nv2);
+        const T sr = sgn * rinv;
+        nrm[0] = Cr[D][0] * sr; nrm[1] = Cr[D][1] * sr; nrm[2] = Cr[D][2] * sr;
+        ds = (nv2 * rinv) * (lt.w[i1] * lt.w[i2]);
+        if (has_nb) {
+            // the neighbour's xi_D column at the same face point
+            T xin[3] = {xi[0], xi[1], xi[2]};
+            xin[D] = T(1 - s);
+            const T(*g)[3] = geo[1];
+            T an[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                if (D == 0) an[i] = g[1][i] + g[4][i] * xin[1] + g[5][i] * xin[2] + g[7][i] * (xin[1] * xin[2]);
+                if (D == 1) an[i] = g[2][i] + g[4][i] * xin[0] + g[6][i] * xin[2] + g[7][i] * (xin[0] * xin[2]);
+                if (D == 2) an[i] = g[3][i] + g[5][i] * xin[0] + g[6][i] * xin[1] + g[7][i] * (xin[0] * xin[1]);
+            }
+            const T rdn = recip(an[0] * Cr[D][0] + an[1] * Cr[D][1] + an[2] * Cr[D][2]);
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+                v[d] = d == D ? det * rdn : -(an[0] * Cr[d][0] + an[1] * Cr[d][1] + an[2] * Cr[d][2]) * rdn;
+        }
+    } else {
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) Cr[a][b] = a == b ? op.hinv[a] : T(0);
+        idet = T(1);
+        nrm[0] = nrm[1] = nrm[2] = T(0);
+        nrm[D] = sgn;
+        ds = op.h[t1] * op.h[t2] * (lt.w[i1] * lt.w[i2]);
+    }
+    // gs = gr + gr' M: reference gradient of both sides in the own frame
+    // (Dirichlet mirror: grad u+ = grad u-, so gs = 2 gr)
+    T gs[C][3];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const T o1 = TD[(0 * C + c) * NN + t], o2 = TD[(1 * C + c) * NN + t];
+        if (has_nb) {
+            const T n1 = TD[(2 * C + c) * NN + t], n2 = TD[(3 * C + c) * NN + t];
+            gs[c][t1] = o1 + n1;
+            gs[c][t2] = o2 + n2;
+            if constexpr (CURVED) {
+                T nr[3];
+                nr[t1] = n1; nr[t2] = n2; nr[D] = unn[c];
+                gs[c][D] = uno[c] + (nr[0] * v[0] + nr[1] * v[1] + nr[2] * v[2]);
+            } else {
+                gs[c][D] = uno[c] + unn[c];
+            }
+        } else {
+            gs[c][t1] = T(2) * o1;
+            gs[c][t2] = T(2) * o2;
+            gs[c][D] = T(2) * uno[c];
+        }
+    }
+    // m' = adj n (J^-1 n = m' / det), p' = adj [u]
+    T mo[3], p[3], en_[C];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        mo[d] = Cr[d][0] * nrm[0] + Cr[d][1] * nrm[1] + Cr[d][2] * nrm[2];
+        if constexpr (C == 3) p[d] = Cr[d][0] * ju[0] + Cr[d][1] * ju[1] + Cr[d][2] * ju[2];
+    }
+    // viscous: (G + G^T) n of the summed gradient G = gs J^-1, with G n = gs m
+    // and (G^T n)_c = sum_d J^-1[d][c] (n . gs[:, d]);  poisson: G . n
+    if constexpr (C == 3) {
+        T w[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) w[d] = nrm[0] * gs[0][d] + nrm[1] * gs[1][d] + nrm[2] * gs[2][d];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            en_[c] = (gs[c][0] * mo[0] + gs[c][1] * mo[1] + gs[c][2] * mo[2] +
+                      Cr[0][c] * w[0] + Cr[1][c] * w[1] + Cr[2][c] * w[2]) * idet;
+    } else {
+        en_[0] = (gs[0][0] * mo[0] + gs[0][1] * mo[1] + gs[0][2] * mo[2]) * idet;
+    }
+    const T mu = (C == 3 && live) ? mu_pre : T(1);
+    const T tau = live ? tf_pre * mu : T(0);
+    const T lf = live ? T(1) : T(0);
+    (void)fid;
+    T av[C], Bh[C][3];
+    if constexpr (C == 3) {
+        // a = -2 {{mu eps(u)}} n + tau ([u] + n([u].n)),  B = -mu sym([u] (x) n),
+        // B^ = J^-1 B:  B^[c][d] = -mu/2 (ju_c m_d + n_c p_d) / det
+        const T jn = ju[0] * nrm[0] + ju[1] * nrm[1] + ju[2] * nrm[2];
+        const T dl = ds * lf;
+        const T hm = -T(0.5) * mu * dl * idet;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            av[c] = dl * (-T(0.5) * mu * en_[c] + tau * (ju[c] + nrm[c] * jn));
+#pragma unroll
+            for (int d = 0; d < 3; ++d) Bh[c][d] = hm * (ju[c] * mo[d] + nrm[c] * p[d]);
+        }
+    } else {
+        // a = -{{grad u}}.n + tau [u],  B = -[u] n / 2,  B^ = -[u] m / 2
+        const T dl = ds * lf;
+        av[0] = dl * (-T(0.5) * en_[0] + tau * ju[0]);
+        const T hb = -T(0.5) * dl * ju[0] * idet;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) Bh[0][d] = hb * mo[d];
+    }
+    stage_sync<THREADS>();  // TD reads done before BT/VT overwrite the space
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        BT[c * NN + t] = Bh[c][t1];
+        BT[(C + c) * NN + t] = Bh[c][t2];
+    }
+    stage_sync<THREADS>();
+
+    // ---- C1: transposed tangential sweeps; task k = (dir*C + c)*N + line
+#pragma unroll
+    for (int k0 = 0; k0 < 2 * C * N; k0 += NN) {
+        const int k = k0 + t;
+        if (k < 2 * C * N) {
+            const int line = k % N, c = (k / N) % C, dirn = k / (N * C);
+            const T* in = BT + (dirn * C + c) * NN;
+            T* out = VT + (dirn * C + c) * NN;
+            const int base = dirn == 0 ? line * N : line;
+            const int step = dirn == 0 ? 1 : N;
+            T v[N];
+#pragma unroll
+            for (int q = 0; q < N; ++q) v[q] = in[base + q * step];
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+                T acc = 0;
+#pragma unroll
+                for (int q = 0; q < N; ++q) acc += tb.D[q][a] * v[q];
+                out[base + a * step] = acc;
+            }
+        }
+    }
+    stage_sync<THREADS>();
+
+    // ---- C2: projection onto the nodes
+    T vv[C], vn[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        vv[c] = av[c] + VT[c * NN + t] + VT[(C + c) * NN + t];
+        vn[c] = Bh[c][D];
+    }
+    if (D == 2) {
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int i3 = 0; i3 < N; ++i3) y[c][i3] += tb.S[s][i3] * vv[c] + tb.G[s][i3] * vn[c];
+    } else {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            VV[c * NN + t] = vv[c];
+            VV[(C + c) * NN + t] = vn[c];
+        }
+        stage_sync<THREADS>();
+        // node (i1, i2, i3): D = 0 -> face point (i2, i3), normal index i1
+        //                    D = 1 -> face point (i1, i3), normal index i2
+        const int ni = D == 0 ? i1 : i2;
+        const T sv = lt.S[s][ni], gv = lt.G[s][ni];
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int i3 = 0; i3 < N; ++i3) {
+                const int fp = D == 0 ? i3 * N + i2 : i3 * N + i1;
+                y[c][i3] += sv * VV[c * NN + fp] + gv * VV[(C + c) * NN + fp];
+            }
+    }
+    stage_sync<THREADS>();
+}
+
+// Face of the penalty-step operator (direction D, side s): only the jump of
+// the normal component is penalised, tau_F ([v].n)([u].n), with [u] = u_own -
+// u_nbr inside and u_own on a Dirichlet face (the oriented jump u - g; no
+// mirror doubling).  Needs the traces of both sides, the unit normal and ds:
+// no gradients, no tangential sweeps.
+template <int N, typename T, bool CURVED, int D, int THREADS>
+__device__ __forceinline__ void face_pass_pen(const OpData<T>& op, const ApplyIO<T>& io, const CellIdx& ci, int s,
+                                              T (&y)[3][N], const T* su, T* sw, T (*geo)[8][3],
+                                              const LaneTab<T, N>& lt, const VolOff<N>& vo) {
+    constexpr int C = 3, NN = N * N, NNN = N * N * N;
+    constexpr int CS = Shape<N, C, sizeof(T) == 8>::CS;
+    constexpr int t1 = D == 0 ? 1 : 0, t2 = D == 2 ? 1 : 2;
+    const auto& tb = op.tab;
+    const int i1 = ci.i1, i2 = ci.i2, t = ci.t;
+    const int pos = D == 0 ? ci.ex : D == 1 ? ci.ey : ci.ez;
+    const int lim = D == 0 ? op.nx : D == 1 ? op.ny : op.nz;
+    const bool has_nb = s == 1 ? pos + 1 < lim : pos > 0;
+    const int stride = D == 0 ? 1 : D == 1 ? op.nx : op.nx * op.ny;
+    const int en = has_nb ? ci.ec + (s == 1 ? stride : -stride) : ci.ec;
+    const bool dir = !has_nb && op.bc[2 * D + s] == 0;
+    const bool live = ci.active && (has_nb ? (io.parts & SIPG_PART_INTERIOR) != 0
+                                           : (dir && (io.parts & SIPG_PART_BOUNDARY) != 0));
+    int fid;
+    if (D == 0) fid = (ci.ez * op.ny + ci.ey) * (op.nx + 1) + ci.ex + s;
+    else if (D == 1) fid = op.nfx + (ci.ez * (op.ny + 1) + ci.ey + s) * op.nx + ci.ex;
+    else fid = op.nfx + op.nfy + ((ci.ez + s) * op.ny + ci.ey) * op.nx + ci.ex;
+    // neighbour line and face factor: every index is valid on every lane
+    const T* xn = io.x + (size_t)en * (C * NNN);
+    T nbl[C][N];
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            int off;
+            if (D == 2) off = (c * N + j) * NN + i2 * N + i1;
+            else if (D == 0) off = (c * N + i2) * NN + i1 * N + j;
+            else off = (c * N + i2) * NN + j * N + i1;
+            nbl[c][j] = xn[off];
+        }
+    const T tff = op.tfac[fid];
+    // traces and the jump
+    T ju[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        T v0 = 0, w0 = 0;
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            T own;
+            if (D == 2) own = su[c * CS + vo.oz[j]];
+            else if (D == 0) own = su[c * CS + vo.ox[j]];
+            else own = su[c * CS + vo.oy[j]];
+            v0 += tb.S[s][j] * own;
+            w0 += tb.S[1 - s][j] * nbl[c][j];
+        }
+        ju[c] = has_nb ? v0 - w0 : v0;
+    }
+    // unit normal and surface measure: row D of the adjugate of J is normal to the face
+    const T sgn = s == 1 ? T(1) : T(-1);
+    T nrm[3], ds;
+    if constexpr (CURVED) {
+        T xi[3];
+        xi[t1] = lt.x[i1];
+        xi[t2] = lt.x[i2];
+        xi[D] = T(s);
+        T a[3][3], cD[3];
+        jac_columns(geo[0], xi, a);
+        cross3(a[(D + 1) % 3], a[(D + 2) % 3], cD);
+        const T nv2 = cD[0] * cD[0] + cD[1] * cD[1] + cD[2] * cD[2];
+        const T rinv = rsqrt_nr(nv2);
+        nrm[0] = sgn * cD[0] * rinv; nrm[1] = sgn * cD[1] * rinv; nrm[2] = sgn * cD[2] * rinv;
+        ds = (nv2 * rinv) * (lt.w[i1] * lt.w[i2]);
+    } else {
+        nrm[0] = nrm[1] = nrm[2] = T(0);
+        nrm[D] = sgn;
+        ds = op.h[t1] * op.h[t2] * (lt.w[i1] * lt.w[i2]);
+    }
+    const T jn = ju[0] * nrm[0] + ju[1] * nrm[1] + ju[2] * nrm[2];
+    const T g = live ? ds * tff * jn : T(0);
+    T av[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) av[c] = g * nrm[c];
+    // projection onto the nodes: node (i1, i2, i3) gets S[s][i_D] av at its face point
+    if constexpr (D == 2) {
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int i3 = 0; i3 < N; ++i3) y[c][i3] += tb.S[s][i3] * av[c];
+    } else {
+#pragma unroll
+        for (int c = 0; c < C; ++c) sw[c * NN + t] = av[c];
+        stage_sync<THREADS>();
+        const int ni = D == 0 ? i1 : i2;
+        const T sv = lt.S[s][ni];
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int i3 = 0; i3 < N; ++i3) {
+                const int fp = D == 0 ? i3 * N + i2 : i3 * N + i1;
+                y[c][i3] += sv * sw[c * NN + fp];
+            }
+    }
+    stage_sync<THREADS>();
+}
+
+// ---------------------------------------------------------------- kernel
+
+template <int N, int C, typename T, bool CURVED, int MODE, bool PEN>
+__global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attribute__((amdgpu_waves_per_eu(2)))
+    k_apply(const OpData<T> op, const ApplyIO<T> io) {
+    using Sh = Shape<N, C, sizeof(T) == 8>;
+    constexpr int NN = N * N, NNN = N * N * N;
+    constexpr int CPB = Sh::CPB, THREADS = Sh::THREADS;
+    constexpr int S3 = Sh::S3, CS = Sh::CS;
+    constexpr bool SKEW = Sh::SKEW;
+
+    if (io.skip != nullptr && *io.skip) return;  // uniform over the grid
+
+    __shared__ T s_u[CPB][Sh::U];      // the cell's nodal values
+    __shared__ T s_w[CPB][Sh::W];      // work space of the cell and face passes
+    // own / neighbour trilinear coefficients, [2][8][3] per cell; the odd cell
+    // stride puts the four cells of a wavefront on different banks (their
+    // reads are per-cell broadcasts)
+    constexpr int GS = 2 * 8 * 3 + 1;
+    __shared__ T s_geo_all[CPB * GS];
+    __shared__ LaneTab<T, N> s_lt;
+
+    CellIdx ci;
+    ci.lc = threadIdx.x / NN;
+    ci.t = threadIdx.x - ci.lc * NN;
+    ci.i1 = ci.t % N;
+    ci.i2 = ci.t / N;
+    const int e = xcd_block(blockIdx.x, gridDim.x) * CPB + ci.lc;
+    ci.active = e < op.ncell;
+    ci.ec = ci.active ? e : 0;
+    ci.ex = ci.ec % op.nx;
+    ci.ey = (ci.ec / op.nx) % op.ny;
+    ci.ez = ci.ec / (op.nx * op.ny);
+    const int lc = ci.lc, t = ci.t, i1 = ci.i1, i2 = ci.i2;
+    T(*geo)[8][3] = reinterpret_cast<T(*)[8][3]>(s_geo_all + lc * GS);
+    const auto& tb = op.tab;
+    T* su = s_u[lc];
+    T* sw = s_w[lc];
+    // thread t as a line: (la, lb) = (i2, i3) for xi_1 sweeps, (i1, i3) for xi_2 sweeps
+    const int la = t % N, lb = t / N;
+    VolOff<N> vo;
+    vol_offsets<N, S3, SKEW>(la, lb, lc, vo);
+
+    if (threadIdx.x < N) {
+        const int j = threadIdx.x;
+        s_lt.x[j] = tb.x[j];
+        s_lt.w[j] = tb.w[j];
+        s_lt.S[0][j] = tb.S[0][j];
+        s_lt.S[1][j] = tb.S[1][j];
+        s_lt.G[0][j] = tb.G[0][j];
+        s_lt.G[1][j] = tb.G[1][j];
+    }
+
+    // ------------------------------------------------------------ load; xi_3 derivative of the own line
+    T gown[8];
+    if constexpr (CURVED) trilinear_coeffs(op.verts, op.nx, op.ny, ci.ex, ci.ey, ci.ez, t % 3, gown);
+    T muq[N];  // viscosity on the own xi_3 line of quadrature points, loaded with the nodal values
+    if constexpr (C == 3)
+#pragma unroll
+        for (int q3 = 0; q3 < N; ++q3) muq[q3] = op.mu_cell[(size_t)ci.ec * NNN + q3 * NN + t];
+    T g3[C][N];
+    {
+        const T* xe = io.x + (size_t)ci.ec * (C * NNN);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            T col[N];
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                const T v = xe[(c * N + j) * NN + t];  // ec = 0 on inactive lanes: in bounds
+                col[j] = ci.active ? v : T(0);
+                su[c * CS + vo.oz[j]] = col[j];
+            }
+#pragma unroll
+            for (int q = 0; q < N; ++q) {
+                T a = 0;
+#pragma unroll
+                for (int j = 0; j < N; ++j) a += tb.D[q][j] * col[j];
+                g3[c][q] = a;
+            }
+        }
+    }
+    if constexpr (CURVED) {
+        // unconditional stores keep the loads at the top (lanes t >= 3 write into the
+        // neighbour slot, which every face stage rewrites before reading it)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) *(t < 3 ? &geo[0][k][t] : &geo[1][k][0]) = gown[k];
+    }
+    __syncthreads();
+    const LaneTab<T, N>& lt = s_lt;
+
+    T y[C][N];
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int j = 0; j < N; ++j) y[c][j] = T(0);
+
+    // ------------------------------------------------------------ cell
+    if (io.parts & SIPG_PART_CELL) {
+        T* W1 = sw;            // [C][NNN] d/dxi_1, then B^_1
+        T* W2 = sw + C * CS;  // [C][NNN] d/dxi_2, then B^_2
+        // forward sweeps along xi_1 and xi_2
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            T v[N], w[N];
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                v[j] = su[c * CS + vo.ox[j]];
+                w[j] = su[c * CS + vo.oy[j]];
+            }
+#pragma unroll
+            for (int q = 0; q < N; ++q) {
+                T a = 0, b = 0;
+#pragma unroll
+                for (int j = 0; j < N; ++j) {
+                    a += tb.D[q][j] * v[j];
+                    b += tb.D[q][j] * w[j];
+                }
+                W1[c * CS + vo.ox[q]] = a;
+                W2[c * CS + vo.oy[q]] = b;
+            }
+        }
+        stage_sync<THREADS>();
+        // pointwise, on the own xi_3 line of quadrature points.  Along that
+        // line the Jacobian columns of a trilinear cell are a_0 = A0 + B0 xi_3,
+        // a_1 = A1 + B1 xi_3 and a_2 constant.
+        T A0[3], B0[3], A1[3], B1[3], a2c[3];
+        if constexpr (CURVED) {
+            const T(*g)[3] = geo[0];
+            const T x1 = lt.x[i1], x2 = lt.x[i2];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                A0[i] = g[1][i] + g[4][i] * x2;
+                B0[i] = g[5][i] + g[7][i] * x2;
+                A1[i] = g[2][i] + g[4][i] * x1;
+                B1[i] = g[6][i] + g[7][i] * x1;
+                a2c[i] = g[3][i] + g[5][i] * x1 + g[6][i] * x2 + g[7][i] * (x1 * x2);
+            }
+        }
+#pragma unroll
+        for (int q3 = 0; q3 < N; ++q3) {
+            T Ji[3][3], JxW;
+            if constexpr (CURVED) {
+                const T x3 = tb.x[q3];
+                T a[3][3], det;
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    a[0][i] = A0[i] + B0[i] * x3;
+                    a[1][i] = A1[i] + B1[i] * x3;
+                    a[2][i] = a2c[i];
+                }
+                inverse_from_columns(a, Ji, det);
+                JxW = det * (lt.w[i1] * lt.w[i2] * tb.w[q3]);
+            } else {
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) Ji[a][b] = a == b ? op.hinv[a] : T(0);
+                JxW = op.h[0] * op.h[1] * op.h[2] * (lt.w[i1] * lt.w[i2] * tb.w[q3]);
+            }
+            T G[C][3];
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const T g1 = W1[c * CS + vo.oz[q3]], g2 = W2[c * CS + vo.oz[q3]], gg3 = g3[c][q3];
+#pragma unroll
+                for (int i = 0; i < 3; ++i) G[c][i] = g1 * Ji[0][i] + g2 * Ji[1][i] + gg3 * Ji[2][i];
+            }
+            T S[C][3];
+            if constexpr (PEN) {
+                // penalty step: tau_div div(u) I JxW (muq holds tau_div)
+                const T dv = muq[q3] * JxW * (G[0][0] + G[1][1] + G[2][2]);
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) S[c][i] = c == i ? dv : T(0);
+            } else if constexpr (C == 3) {
+                const T f = muq[q3] * JxW;  // 2 mu eps = mu (G + G^T)
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) S[c][i] = f * (G[c][i] + G[i][c]);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 3; ++i) S[0][i] = JxW * G[0][i];
+            }
+            const T mass = op.alpha * JxW;
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                W1[c * CS + vo.oz[q3]] = Ji[0][0] * S[c][0] + Ji[0][1] * S[c][1] + Ji[0][2] * S[c][2];
+                W2[c * CS + vo.oz[q3]] = Ji[1][0] * S[c][0] + Ji[1][1] * S[c][1] + Ji[1][2] * S[c][2];
+                g3[c][q3] = Ji[2][0] * S[c][0] + Ji[2][1] * S[c][1] + Ji[2][2] * S[c][2];
+                y[c][q3] = mass * su[c * CS + vo.oz[q3]];
+            }
+        }
+        stage_sync<THREADS>();
+        // transposed sweeps, in place on the lines (each line is read and written by one thread)
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            T v[N], w[N];
+#pragma unroll
+            for (int q = 0; q < N; ++q) {
+                v[q] = W1[c * CS + vo.ox[q]];
+                w[q] = W2[c * CS + vo.oy[q]];
+            }
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                T a = 0, b = 0;
+#pragma unroll
+                for (int q = 0; q < N; ++q) {
+                    a += tb.D[q][j] * v[q];
+                    b += tb.D[q][j] * w[q];
+                }
+                W1[c * CS + vo.ox[j]] = a;
+                W2[c * CS + vo.oy[j]] = b;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int i3 = 0; i3 < N; ++i3) {
+                T acc = y[c][i3];
+#pragma unroll
+                for (int q = 0; q < N; ++q) acc += tb.D[q][i3] * g3[c][q];
+                y[c][i3] = acc;
+            }
+        stage_sync<THREADS>();
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int i3 = 0; i3 < N; ++i3) y[c][i3] += W1[c * CS + vo.oz[i3]] + W2[c * CS + vo.oz[i3]];
+        stage_sync<THREADS>();
+    }
+
+    // ------------------------------------------------------------ faces
+    if (io.parts & (SIPG_PART_INTERIOR | SIPG_PART_BOUNDARY)) {
+#pragma unroll 1
+        for (int f = 0; f < 6; ++f) {
+            const int s = f & 1;
+            if constexpr (PEN) {
+                if (f < 2) face_pass_pen<N, T, CURVED, 0, THREADS>(op, io, ci, s, y, su, sw, geo, lt, vo);
+                else if (f < 4) face_pass_pen<N, T, CURVED, 1, THREADS>(op, io, ci, s, y, su, sw, geo, lt, vo);
+                else face_pass_pen<N, T, CURVED, 2, THREADS>(op, io, ci, s, y, su, sw, geo, lt, vo);
+            } else {
+                if (f < 2) face_pass<N, C, T, CURVED, 0, THREADS>(op, io, ci, s, y, su, sw, geo, lt, vo);
+                else if (f < 4) face_pass<N, C, T, CURVED, 1, THREADS>(op, io, ci, s, y, su, sw, geo, lt, vo);
+                else face_pass<N, C, T, CURVED, 2, THREADS>(op, io, ci, s, y, su, sw, geo, lt, vo);
+            }
+        }
+    }
+
+    // ------------------------------------------------------------ store
+    if (!ci.active) return;
+    const size_t base = (size_t)ci.ec * (C * NNN);
+    if constexpr (MODE == MODE_APPLY) {
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int j = 0; j < N; ++j) io.y[base + (c * N + j) * NN + t] = y[c][j];
+    } else if constexpr (MODE == MODE_RESID) {
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                const size_t idx = base + (c * N + j) * NN + t;
+                io.y[idx] = io.r[idx] - y[c][j];
+            }
+    } else {
+        const T c1 = T(io.coef[0]), c2 = T(io.coef[1]);
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                const size_t idx = base + (c * N + j) * NN + t;
+                const T dn = c1 * io.d[idx] + c2 * io.dinv[idx] * (io.r[idx] - y[c][j]);
+                io.d[idx] = dn;
+                io.y[idx] = su[c * CS + vo.oz[j]] + dn;
+            }
+    }
+}
+
+}  // namespace sipg

@@ -126,6 +126,28 @@ __global__ void k_visc_face(const OpData<double> op, int n, int nface, const Law
     mu32[id] = (float)mu;
 }
 
+// penalty step: tau_div of the cell at each of its quadrature points
+__global__ void k_pen_cell(const OpData<double> op, int n, const double* tau_div, double* mu64, float* mu32) {
+    const int nnn = n * n * n;
+    const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= (long long)op.ncell * nnn) return;
+    const double t = tau_div[id / nnn];
+    mu64[id] = t;
+    mu32[id] = (float)t;
+}
+
+// penalty step: face factor = mean of the two cells' tau_cont, the cell's own on the boundary
+__global__ void k_pen_face(const OpData<double> op, int nface, const double* tau_cont, double* tfac64,
+                           float* tfac32) {
+    const int fid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (fid >= nface) return;
+    const FaceInfo f = decode_face(op, fid);
+    const double t = (f.em >= 0 && f.ep >= 0) ? 0.5 * (tau_cont[f.em] + tau_cont[f.ep])
+                                              : tau_cont[f.em >= 0 ? f.em : f.ep];
+    tfac64[fid] = t;
+    tfac32[fid] = (float)t;
+}
+
 // ---------------------------------------------------------------- diagonal
 //
 // d_{(c,i)} = a(phi_i e_c, phi_i e_c).  With nodes at the Gauss points the
@@ -133,10 +155,12 @@ __global__ void k_visc_face(const OpData<double> op, int n, int nface, const Law
 // lines through node i, so the cell part needs 3n-2 points per node:
 //   viscous  alpha JxW_i + sum_q mu JxW (|grad phi_i|^2 + (d_c phi_i)^2)
 //   poisson  alpha JxW_i + sum_q JxW |grad phi_i|^2
+//   penalty  alpha JxW_i + sum_q tau_div JxW (d_c phi_i)^2
 // and each face contributes at the single face point below node i:
 //   viscous  ds [ -mu phi (grad phi.n + n_c d_c phi) + tau phi^2 (1 + n_c^2) ]
 //   poisson  ds [ -phi grad phi.n + tau phi^2 ]
-// (twice that on a Dirichlet face, nothing on a Neumann face).
+// (twice that on a Dirichlet face, nothing on a Neumann face);
+//   penalty  ds tau_F phi^2 n_c^2 on interior and Dirichlet faces alike.
 
 template <int C>
 __global__ void k_diagonal(const OpData<double> op, int n, double* diag, double* dinv, float* dinv32) {
@@ -176,7 +200,10 @@ __global__ void k_diagonal(const OpData<double> op, int n, double* diag, double*
             for (int k = 0; k < 3; ++k) g[k] = gr[0] * Ji[0][k] + gr[1] * Ji[1][k] + gr[2] * Ji[2][k];
             const double g2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
             const int qi = (q[2] * n + q[1]) * n + q[0];
-            if (C == 3) {
+            if (C == 3 && op.pen) {
+                const double td = op.mu_cell[(size_t)e * nnn + qi];
+                for (int c = 0; c < 3; ++c) acc[c] += td * JxW * g[c] * g[c];
+            } else if (C == 3) {
                 const double mu = op.mu_cell[(size_t)e * nnn + qi];
                 for (int c = 0; c < 3; ++c) acc[c] += mu * JxW * (g2 + g[c] * g[c]);
             } else {
@@ -220,7 +247,10 @@ __global__ void k_diagonal(const OpData<double> op, int n, double* diag, double*
             double g[3];
             for (int k = 0; k < 3; ++k) g[k] = gr[0] * Ji[0][k] + gr[1] * Ji[1][k] + gr[2] * Ji[2][k];
             const double gn = g[0] * nrm[0] + g[1] * nrm[1] + g[2] * nrm[2];
-            if (C == 3) {
+            if (C == 3 && op.pen) {
+                const double tau = op.tfac[fid];
+                for (int c = 0; c < 3; ++c) acc[c] += ds * tau * phi * phi * nrm[c] * nrm[c];
+            } else if (C == 3) {
                 const double mu = op.mu_face[(size_t)fid * nn + fp];
                 const double tau = op.tfac[fid] * mu;
                 for (int c = 0; c < 3; ++c)
@@ -242,10 +272,19 @@ __global__ void k_diagonal(const OpData<double> op, int n, double* diag, double*
 
 hipError_t launch_setup(int n, int C, bool curved, const OpData<double>& op, const LawDev& law, double penalty,
                         double* hcell, double* tfac64, float* tfac32, double* mu_cell64, float* mu_cell32,
-                        double* mu_face64, float* mu_face32, int nface, hipStream_t s) {
+                        double* mu_face64, float* mu_face32, int nface, const double* tau_div,
+                        const double* tau_cont, hipStream_t s) {
     (void)curved;
     const int bt = 256;
     hipLaunchKernelGGL(k_cell_size, dim3((op.ncell + bt - 1) / bt), dim3(bt), 0, s, op, n, hcell);
+    if (op.pen) {
+        const long long nc = (long long)op.ncell * n * n * n;
+        hipLaunchKernelGGL(k_pen_cell, dim3((unsigned)((nc + bt - 1) / bt)), dim3(bt), 0, s, op, n, tau_div,
+                           mu_cell64, mu_cell32);
+        hipLaunchKernelGGL(k_pen_face, dim3((nface + bt - 1) / bt), dim3(bt), 0, s, op, nface, tau_cont, tfac64,
+                           tfac32);
+        return hipGetLastError();
+    }
     const double pk2 = penalty * (double)n * (double)n;
     hipLaunchKernelGGL(k_face_penalty, dim3((nface + bt - 1) / bt), dim3(bt), 0, s, op, nface, pk2, hcell, tfac64,
                        tfac32);

@@ -28,6 +28,7 @@ struct OpData {
     int nx, ny, nz, ncell;
     int nfx, nfy;            // number of x-faces, y-faces (face id offsets)
     int bc[6];               // 0 = Dirichlet, 1 = Neumann, sides -x,+x,-y,+y,-z,+z
+    int pen;                 // penalty-step operator (mu_cell holds tau_div, tfac the face tau_cont)
     T alpha;                 // mass factor gamma_0/dt
     T h[3];                  // straight cells: edge lengths
     T hinv[3];               // and their inverses
@@ -107,11 +108,14 @@ struct MgTab {
 template <typename T>
 hipError_t launch_apply(int n, int C, bool curved, const OpData<T>& op, const ApplyIO<T>& io,
                         int mode, hipStream_t s);
+// the penalty-step operator (op.pen), dispatched to by launch_apply
+template <typename T>
+hipError_t launch_apply_pen(int n, bool curved, const OpData<T>& op, const ApplyIO<T>& io, int mode, hipStream_t s);
 
 hipError_t launch_setup(int n, int C, bool curved, const OpData<double>& op, const LawDev& law,
                         double penalty, double* hcell, double* tfac64, float* tfac32,
                         double* mu_cell64, float* mu_cell32, double* mu_face64, float* mu_face32,
-                        int nface, hipStream_t s);
+                        int nface, const double* tau_div, const double* tau_cont, hipStream_t s);
 
 hipError_t launch_diagonal(int n, int C, bool curved, const OpData<double>& op, double* diag,
                            double* dinv, float* dinv32, hipStream_t s);

@@ -80,12 +80,15 @@ def _law_struct(law: dict | None, keep: list) -> F.Viscosity:
 
 
 class Operator:
-    """SIPG viscous ("viscous") or Poisson ("poisson") operator on a structured
-    nx*ny*nz box mesh; see include/sipg.h for the discretisation."""
+    """SIPG viscous ("viscous"), SIPG Poisson ("poisson") or penalty-step
+    ("penalty": mass + divergence and normal-continuity penalties with
+    per-cell factors tau_div, tau_cont) operator on a structured nx*ny*nz box
+    mesh; see include/sipg.h for the discretisation."""
 
     def __init__(self, nx: int, ny: int, nz: int, degree: int, op: str = "viscous",
                  alpha: float = 0.0, penalty: float = 1.0, law: dict | None = None,
-                 vertices: np.ndarray | None = None, bc=("D",) * 6):
+                 vertices: np.ndarray | None = None, bc=("D",) * 6,
+                 tau_div: np.ndarray | None = None, tau_cont: np.ndarray | None = None):
         keep: list = []
         mesh = F.Mesh()
         mesh.nx, mesh.ny, mesh.nz = nx, ny, nz
@@ -96,15 +99,26 @@ class Operator:
         for i, b in enumerate(bc):
             mesh.bc[i] = F.BC[b]
         par = F.Params()
-        par.op = F.VISCOUS if op == "viscous" else F.POISSON
+        if op not in F.OPS:
+            raise ValueError(f"unknown operator {op}")
+        par.op = F.OPS[op]
         par.degree, par.alpha, par.penalty = degree, alpha, penalty
+        if op == "penalty":
+            if tau_div is None or tau_cont is None:
+                raise ValueError("the penalty operator needs tau_div and tau_cont (one value per cell)")
+            for name, t in (("tau_div", tau_div), ("tau_cont", tau_cont)):
+                a = np.ascontiguousarray(t, dtype=np.float64).reshape(-1)
+                if a.size != nx * ny * nz:
+                    raise ValueError(f"{name} needs {nx * ny * nz} values, got {a.size}")
+                keep.append(a)
+                setattr(par, name, a.ctypes.data_as(C.POINTER(C.c_double)))
         lw = _law_struct(law if op == "viscous" else None, keep)
         h = C.c_void_p()
         check(lib.sipg_plan_create(C.byref(mesh), C.byref(lw), C.byref(par), C.byref(h)))
         self._h = h
         self.nx, self.ny, self.nz, self.degree, self.op = nx, ny, nz, degree, op
         self.n = degree + 1
-        self.C = 3 if op == "viscous" else 1
+        self.C = 1 if op == "poisson" else 3
         self.ndof = int(lib.sipg_dof_count(h))
         self.nface = int(lib.sipg_face_count(h))
         self.ncell = nx * ny * nz
@@ -114,7 +128,7 @@ class Operator:
     @classmethod
     def from_config(cls, cfg: dict, vertices=None) -> "Operator":
         return cls(cfg["nx"], cfg["ny"], cfg["nz"], cfg["degree"], cfg["op"], cfg["alpha"],
-                   cfg["penalty"], cfg.get("law"), vertices, cfg["bc"])
+                   cfg["penalty"], cfg.get("law"), vertices, cfg["bc"], cfg.get("tau_div"), cfg.get("tau_cont"))
 
     def __del__(self):
         h = getattr(self, "_h", None)
