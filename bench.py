@@ -7,8 +7,8 @@ mu = 10^(3 s(x)), 6,291,456 unknowns); inputs resident in device memory,
 last-level cache.  Besides the headline DoF/s the line reports the FP32
 (preconditioner precision) apply, the setup including the inverse diagonal,
 FP64- vs FP32-preconditioned solves (one-level Chebyshev-Jacobi and
-hp-multigrid) of the 24^3 k = 4 Carreau workload to 1e-8, the
-continuous-batching request loop (solves/s, p50/p99), the
+hp-multigrid) of the 24^3 k = 4 Carreau workload to 1e-8, the penalty-step
+operator (applies and solves), the continuous-batching request loop (solves/s, p50/p99), the
 roofline of the apply kernel and the CPU oracle timed on this host.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
@@ -40,17 +40,23 @@ def log(*a):
 
 def algorithmic_bytes(cfg, elem: int) -> dict:
     """Bytes an apply must move at least: x in, y out, the viscosity at cell
-    and face quadrature points (stored pointwise), the mesh vertices."""
+    and face quadrature points (stored pointwise; viscous operator) or the two
+    penalty factors per cell (penalty step), the mesh vertices."""
     n = cfg["degree"] + 1
     nx, ny, nz = cfg["nx"], cfg["ny"], cfg["nz"]
     ncell = nx * ny * nz
-    C = 3 if cfg["op"] == "viscous" else 1
+    C = 1 if cfg["op"] == "poisson" else 3
     ndof = ncell * C * n ** 3
     nface = (nx + 1) * ny * nz + nx * (ny + 1) * nz + nx * ny * (nz + 1)
     vec = 2 * ndof * elem
-    mu = (ncell * n ** 3 + nface * n * n) * elem if C == 3 else 0
+    if cfg["op"] == "viscous":
+        mu = (ncell * n ** 3 + nface * n * n) * elem
+    elif cfg["op"] == "penalty":
+        mu = 2 * ncell * elem
+    else:
+        mu = 0
     verts = (nx + 1) * (ny + 1) * (nz + 1) * 3 * elem if cfg["perturb"] else 0
-    return {"vectors": vec, "viscosity": mu, "vertices": verts, "total": vec + mu + verts,
+    return {"vectors": vec, "coefficients": mu, "vertices": verts, "total": vec + mu + verts,
             "per_dof": (vec + mu + verts) / ndof}
 
 
@@ -166,6 +172,42 @@ def solve_compare(tol=1e-8):
     except Exception:
         pass
     out["fp32_apply_rel_err_vs_fp64_apply"] = fp32_err
+    return out
+
+
+def penalty_step(steps, warmup, tol=1e-8):
+    """c6: the penalty-step operator (mass + divergence and normal-continuity
+    penalties), FP64 and FP32 applies, and mixed-precision solves with the
+    one-level Chebyshev-Jacobi and the hp-multigrid preconditioners."""
+    import torch
+    import workloads as W
+    from paper_2506_14424_amd import Operator, SolveOptions
+    cfg = W.config("c6")
+    V = W.box_vertices(cfg["nx"], cfg["ny"], cfg["nz"], cfg["perturb"])
+    op = Operator.from_config(cfg, V).set_multigrid().bind(with_solver=True)
+    r64 = time_applies(op, torch.float64, steps, warmup)
+    r32 = time_applies(op, torch.float32, steps, warmup)
+    ms64, ms32 = r64["event_ms"] / steps, r32["event_ms"] / steps
+    b64, b32 = algorithmic_bytes(cfg, 8), algorithmic_bytes(cfg, 4)
+    out = {"workload": f"c6: penalty step, k=3, 16^3 perturbed, per-cell factors of a seeded velocity, "
+                       f"{op.ndof} DoFs",
+           "apply_f64": {"dof_per_s": op.ndof / (ms64 * 1e-3), "avg_launch_ms": ms64,
+                         "achieved_GBs": b64["total"] / (ms64 * 1e-3) / 1e9,
+                         "hbm_frac": b64["total"] / (ms64 * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                         "algorithmic_bytes_per_dof": b64["per_dof"]},
+           "apply_f32": {"dof_per_s": op.ndof / (ms32 * 1e-3), "avg_launch_ms": ms32,
+                         "achieved_GBs": b32["total"] / (ms32 * 1e-3) / 1e9},
+           "multigrid_levels": op.multigrid_levels()}
+    b = torch.from_numpy(W.uniform_vector(cfg["x_seed"], op.ndof)).cuda()
+    for key, kind, deg in (("chebyshev_f32_precond", "chebyshev", 5), ("mg_f32_precond", "multigrid", 3)):
+        opts = SolveOptions(rel_tol=tol, precond_precision="f32", precond=kind, cheb_degree=deg, check_every=5)
+        op.solve(b, opts=opts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, info = op.solve(b, opts=opts)
+        torch.cuda.synchronize()
+        out[key] = {"seconds": time.perf_counter() - t0, "iterations": info["iterations"],
+                    "rel_residual": info["rel_residual"], "status": info["status"], "degree": deg}
     return out
 
 
@@ -295,6 +337,9 @@ def main():
         log("solve comparison (c3) ...")
         line["solve"] = solve_compare()
         log(json.dumps(line["solve"]))
+        log("penalty step (c6) ...")
+        line["penalty_step"] = penalty_step(args.steps, args.warmup)
+        log(json.dumps(line["penalty_step"]))
     if not args.no_serve:
         log("serving loop (c5) ...")
         line["serving"] = serving()
