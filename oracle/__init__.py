@@ -29,7 +29,11 @@ What it computes, and from which passage:
   flexible CG with FP64 outer iteration (Sec. 5.3);
 * the hp-multigrid V-cycle preconditioner of Sec. 5.3 (degree lowered from
   k to 1, then mesh coarsening, Chebyshev-Jacobi smoothing on every level),
-  in ``multigrid``.
+  in ``multigrid``;
+* the Picard update of the viscosity from the velocity (Sec. 4.1,
+  eq. viscosity_pointwise) on every multigrid level and the Aitken-relaxed
+  fixed-point iteration of the nonlinear viscous step (Sec. 5.1, Alg. 1),
+  in ``picard``.
 
 Two evaluation modes: ``assemble`` builds the global sparse matrix cell by
 cell and face by face (small meshes); ``apply`` evaluates the same quadrature

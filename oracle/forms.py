@@ -65,6 +65,9 @@ class Problem:
     law: object = field(default_factory=lambda: {"kind": "const", "mu": 1.0})
     tau_div: object = None       # penalty step: tau_div per cell
     tau_cont: object = None      # penalty step: tau_cont per cell
+    mu_values: object = None     # viscous: (mu_cell [ncells, n^3], mu_face [nfaces, n^2]) given
+                                 # pointwise (e.g. from a velocity, Sec. 4.1 eq. viscosity_pointwise)
+                                 # in place of the law; faces numbered by Mesh.face_index
 
     @property
     def n(self) -> int:
@@ -131,6 +134,20 @@ def _mu(pb: Problem, x):
     if pb.op != "viscous":
         return np.ones(x.shape[:-1])
     return viscosity(pb.law, x)
+
+
+def _mu_cell(pb: Problem, cells, x):
+    """mu at the cell points x (E, n^3, 3) of `cells`."""
+    if pb.op == "viscous" and pb.mu_values is not None:
+        return np.asarray(pb.mu_values[0], dtype=np.float64)[np.asarray(cells)]
+    return _mu(pb, x)
+
+
+def _mu_face(pb: Problem, d, cells, side, x):
+    """mu at the points x (E, n^2, 3) of the faces xi_d = side of `cells`."""
+    if pb.op == "viscous" and pb.mu_values is not None:
+        return np.asarray(pb.mu_values[1], dtype=np.float64)[pb.mesh.face_index(d, np.asarray(cells), side)]
+    return _mu(pb, x)
 
 
 def _tau(pb: Problem, mu, hF):
@@ -243,7 +260,7 @@ def assemble(pb: Problem, parts=PARTS_ALL) -> sp.csr_matrix:
         V, G = tensor_tables(n, pts)
         for e in range(mesh.ncells):
             xq, Jinv, JxW = _cell_geo(pb, np.array([e]))
-            mu = _mu(pb, xq)[0]
+            mu = _mu_cell(pb, np.array([e]), xq)[0]
             v, g = _basis_traces(pb, V, G, Jinv[0])
             K = np.zeros((nloc, nloc))
             for q in range(len(JxW[0])):
@@ -268,7 +285,7 @@ def assemble(pb: Problem, parts=PARTS_ALL) -> sp.csr_matrix:
             for a, b in zip(em, ep):
                 _, xq, Jim, nrm, ds = _face_geo(pb, np.array([a]), d, 1)
                 _, _, Jip, _, _ = _face_geo(pb, np.array([b]), d, 0)
-                mu = _mu(pb, xq)[0]
+                mu = _mu_face(pb, d, np.array([a]), 1, xq)[0]
                 tau = _tau(pb, mu[None], np.array([min(h[a], h[b])]))[0]
                 vm_, gm_ = _basis_traces(pb, Vm, Gm, Jim[0])
                 vp_, gp_ = _basis_traces(pb, Vp, Gp, Jip[0])
@@ -301,7 +318,7 @@ def assemble(pb: Problem, parts=PARTS_ALL) -> sp.csr_matrix:
                 Vf, Gf = tensor_tables(n, pts)
                 for e in mesh.boundary_cells(d, side):
                     _, xq, Ji, nrm, ds = _face_geo(pb, np.array([e]), d, side)
-                    mu = _mu(pb, xq)[0]
+                    mu = _mu_face(pb, d, np.array([e]), side, xq)[0]
                     tau = _tau(pb, mu[None], np.array([h[e]]))[0]
                     v, g = _basis_traces(pb, Vf, Gf, Ji[0])
                     K = np.zeros((nloc, nloc))
@@ -363,7 +380,7 @@ def apply(pb: Problem, x: np.ndarray, parts=PARTS_ALL, batch: int = 4096, cells=
         for s in range(0, len(own), batch):
             cells = own[s:s + batch]
             xq, Jinv, JxW = _cell_geo(pb, cells)
-            mu = _mu(pb, xq)
+            mu = _mu_cell(pb, cells, xq)
             Xc = X[cells]
             u = np.einsum("pj,ecj->epc", V, Xc)
             gu = _phys_grad(Xc, G, Jinv)
@@ -389,7 +406,7 @@ def apply(pb: Problem, x: np.ndarray, parts=PARTS_ALL, batch: int = 4096, cells=
                 em, ep = em_all[s:s + batch], ep_all[s:s + batch]
                 _, xq, Jim, nrm, ds = _face_geo(pb, em, d, 1)
                 _, _, Jip, _, _ = _face_geo(pb, ep, d, 0)
-                mu = _mu(pb, xq)
+                mu = _mu_face(pb, d, em, 1, xq)
                 tau = _tau(pb, mu, np.minimum(h[em], h[ep]))
                 um = np.einsum("pj,ecj->epc", Vm, X[em]); up = np.einsum("pj,ecj->epc", Vp, X[ep])
                 gm = _phys_grad(X[em], Gm, Jim); gp = _phys_grad(X[ep], Gp, Jip)
@@ -424,7 +441,7 @@ def apply(pb: Problem, x: np.ndarray, parts=PARTS_ALL, batch: int = 4096, cells=
                 if len(cells) == 0:
                     continue
                 _, xq, Ji, nrm, ds = _face_geo(pb, cells, d, side)
-                mu = _mu(pb, xq)
+                mu = _mu_face(pb, d, cells, side, xq)
                 tau = _tau(pb, mu, h[cells])
                 u = np.einsum("pj,ecj->epc", Vf, X[cells])
                 gu = _phys_grad(X[cells], Gf, Ji)
@@ -461,7 +478,7 @@ def diagonal(pb: Problem, batch: int = 1024) -> np.ndarray:
     for s in range(0, mesh.ncells, batch):
         cells = np.arange(s, min(s + batch, mesh.ncells))
         xq, Jinv, JxW = _cell_geo(pb, cells)
-        mu = _mu(pb, xq)
+        mu = _mu_cell(pb, cells, xq)
         grad = np.einsum("pjd,epdi->epji", G, Jinv, optimize=True)   # (E, P, n^3, 3)
         g2 = np.einsum("epji,epji->epj", grad, grad)
         for c in range(C):
@@ -480,7 +497,7 @@ def diagonal(pb: Problem, batch: int = 1024) -> np.ndarray:
         pts, _ = face_points(n, d, side)
         Vf, Gf = tensor_tables(n, pts)
         _, xq, Ji, nrm, ds = _face_geo(pb, cells, d, side)
-        mu = _mu(pb, xq)
+        mu = _mu_face(pb, d, cells, side, xq)
         tau = _tau(pb, mu, hF)
         out = np.zeros((len(cells), nloc))
         for ii, e in enumerate(cells):
@@ -574,7 +591,7 @@ def load_vector(pb: Problem, f, g=None, hN=None) -> np.ndarray:
             _, xq, Ji, nrm, ds = _face_geo(pb, bc_cells, d, side)
             E, P = xq.shape[:2]
             if kind == "D" and g is not None:
-                mu = _mu(pb, xq)
+                mu = _mu_face(pb, d, bc_cells, side, xq)
                 tau = _tau(pb, mu, h[bc_cells])
                 gv = np.asarray(g(xq.reshape(-1, 3))).reshape(E, P, C)
                 if pb.op == "viscous":

@@ -97,3 +97,20 @@ class Mesh:
         pos = (ex, ey, ez)[d]
         keep = pos == (lim - 1 if side == 1 else 0)
         return np.sort((ez[keep] * ny + ey[keep]) * nx + ex[keep])
+
+    @property
+    def nfaces(self) -> int:
+        nx, ny, nz = self.nx, self.ny, self.nz
+        return (nx + 1) * ny * nz + nx * (ny + 1) * nz + nx * ny * (nz + 1)
+
+    def face_index(self, d: int, cells, side: int) -> np.ndarray:
+        """Number of the face xi_d = side of each cell: x-faces first,
+        (ez*ny + ey)*(nx+1) + fx, then y-faces (ez*(ny+1) + fy)*nx + ex,
+        then z-faces (fz*ny + ey)*nx + ex, with f_d = e_d + side."""
+        nx, ny, nz = self.nx, self.ny, self.nz
+        ex, ey, ez = self.cell_ijk(cells)
+        if d == 0:
+            return (ez * ny + ey) * (nx + 1) + ex + side
+        if d == 1:
+            return (nx + 1) * ny * nz + (ez * (ny + 1) + ey + side) * nx + ex
+        return (nx + 1) * ny * nz + nx * (ny + 1) * nz + ((ez + side) * ny + ey) * nx + ex

@@ -114,8 +114,10 @@ class Hierarchy:
     def __init__(self, pb: Problem, smooth_degree: int = 5, coarse_degree: int = 12,
                  h_coarsen: bool = True, min_cells: int = 2, max_levels: int = 16,
                  ratio: float = 20.0, safety: float = 1.2, lanczos_steps: int = 20,
-                 seed: int = 12345):
-        self.levels = level_problems(pb, h_coarsen, min_cells, max_levels)
+                 seed: int = 12345, levels: list[Problem] | None = None):
+        # `levels` replaces the hierarchy of level_problems (e.g. the same
+        # levels with the viscosity updated from a velocity)
+        self.levels = levels if levels is not None else level_problems(pb, h_coarsen, min_cells, max_levels)
         self.smooth_degree, self.coarse_degree = smooth_degree, coarse_degree
         self.ops = [(lambda x, p=p: op_apply(p, x)) for p in self.levels]
         self.dinv = [1.0 / diagonal(p) for p in self.levels]

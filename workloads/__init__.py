@@ -181,6 +181,10 @@ def config(name: str, n: int | None = None) -> dict:
     c4v 20^3 affine, k=5, viscous, sine viscosity, Dirichlet.
     c6  16^3 perturbed, k=3, penalty step (mass + divergence and continuity
         penalties, per-cell factors from ``penalty_parameters``, seed 6).
+    c7  the nonlinear viscous step: c3's mesh, degree and Carreau parameters
+        with the viscosity taken from the velocity (Picard iteration), zero
+        initial velocity, right-hand side ``b_scale`` U(-1, 1) with seed 7,
+        b_scale = 100 alpha / (cells (k+1)^3).
     """
     if name == "c1":
         return _cfg("c1", n or 4, 2, "viscous", sine_law(1.0, 0.5), 10.0, ALL_DIRICHLET, 0.0,
@@ -202,6 +206,10 @@ def config(name: str, n: int | None = None) -> dict:
         td, tc = penalty_parameters(m, m, m, 3, box_vertices(m, m, m, 0.1), 6)
         return _cfg("c6", m, 3, "penalty", None, 1.0, ALL_DIRICHLET, 0.1, x_seed=6, tol=1e-8,
                     tau_div=td, tau_cont=tc)
+    if name == "c7":
+        m = n or 24
+        return _cfg("c7", m, 4, "viscous", carreau_law(3), 10.0, ALL_DIRICHLET, 0.1, x_seed=7, tol=1e-8,
+                    b_scale=100.0 * 10.0 / (m ** 3 * 125), picard=True)
     raise KeyError(name)
 
 
