@@ -273,6 +273,69 @@ sipg_status sipg_solve_begin(sipg_plan* plan, const double* b, double* x,
 sipg_status sipg_solve_advance(sipg_plan* plan, int32_t iters);
 sipg_status sipg_solve_poll(sipg_plan* plan, int32_t* done, sipg_solve_info* info);
 
+/* ---------------------------------------------------------------------
+ * Nonlinear viscous step (Sec. 4.1, paragraph "Viscous Step", eq.
+ * viscosity_pointwise; Sec. 5.1, Alg. 1): the viscosity is updated
+ * pointwise from the velocity, nu = eta(gdot(grad^S u)), and the viscous
+ * step is re-solved (Picard iteration) with Aitken's adaptive relaxation
+ * computed from the full nonlinear residual.  Needs a viscous plan whose
+ * law is SIPG_LAW_CARREAU: its eta parameters (mu0, mu_inf, lam, n_exp,
+ * kappa, a_exp) are used, its prescribed velocity modes are not.
+ */
+
+/* Re-evaluates the viscosity at every cell and face quadrature point from
+ * the velocity u (device FP64, ndof of this plan): gdot = sqrt(2 eps:eps) of
+ * u in the cell, of the mean of the two cells' symmetric gradients at an
+ * interior face point, of the interior trace on the boundary; every
+ * multigrid level evaluates the same velocity at its own quadrature points
+ * (a coarse point lies in one fine cell through the nesting of the
+ * reference cells).  Then recomputes every level's diagonal and inverse
+ * diagonal (FP64 and FP32) and drops the cached eigenvalue estimates, so
+ * the next solve re-estimates them.  Needs a bound plan; stream-ordered;
+ * no solve may be in progress. */
+sipg_status sipg_update_viscosity(sipg_plan* plan, const double* u, void* stream);
+
+typedef struct {
+    double rel_tol;            /* stop when |R_k| <= rel_tol |R_0|, R(u) = b - A(nu(u)) u */
+    double abs_tol;            /* or when |R_k| <= abs_tol (either criterion stops) */
+    int32_t max_iter;          /* Picard iterations (linear solves), >= 0 */
+    int32_t aitken;            /* nonzero: omega_k = -omega_{k-1} R_{k-1}.(R_k - R_{k-1}) / |R_k - R_{k-1}|^2,
+                                  omega_0 = 1; zero: omega = 1 (plain Picard) */
+} sipg_picard_opts;
+
+#define SIPG_PICARD_HISTORY 64
+
+typedef struct {
+    int32_t iterations;        /* linear solves done */
+    int32_t linear_iterations; /* CG iterations summed over them */
+    double residual_initial;   /* |R_0| */
+    double residual_final;     /* |R_k| at the returned iterate */
+    int32_t status;            /* SIPG_OK, SIPG_ERR_NOT_CONVERGED, or a linear solve's error */
+    int32_t recorded;          /* entries of the arrays below (<= SIPG_PICARD_HISTORY) */
+    double residual_norms[SIPG_PICARD_HISTORY];  /* |R_0|, |R_1|, ... */
+    double omegas[SIPG_PICARD_HISTORY];          /* omega used for step 1, 2, ... */
+} sipg_picard_info;
+
+void sipg_picard_opts_default(sipg_picard_opts* opts);
+
+/* Device bytes of the `work` buffer of sipg_picard_solve: 3 vectors of ndof
+ * FP64 values and the reduction partials. */
+size_t sipg_picard_work_bytes(const sipg_plan* plan);
+
+/* Solves the nonlinear viscous step A(nu(x)) x = b (b, x: device FP64,
+ * ndof; x holds the initial iterate on entry, e.g. the extrapolated
+ * velocity, and the result on return).  Each iteration updates the
+ * viscosity from the current x (sipg_update_viscosity), forms
+ * R = b - A x on the device, solves A delta = R with sipg_solve and
+ * lin_opts (its rel_tol is relative to |R|; NULL: defaults) and sets
+ * x += omega delta.  work: device buffer of sipg_picard_work_bytes, 256-byte
+ * aligned, not aliasing b or x.  Needs a plan bound with_solver; blocks;
+ * returns info->status (info may be NULL).  On return the plan's viscosity
+ * is the one of the returned x. */
+sipg_status sipg_picard_solve(sipg_plan* plan, const double* b, double* x, void* work,
+                              const sipg_solve_opts* lin_opts, const sipg_picard_opts* opts,
+                              sipg_picard_info* info, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

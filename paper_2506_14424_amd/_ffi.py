@@ -61,6 +61,19 @@ class MgOpts(C.Structure):
                 ("h_coarsen", C.c_int32)]
 
 
+PICARD_HISTORY = 64
+
+
+class PicardOpts(C.Structure):
+    _fields_ = [("rel_tol", C.c_double), ("abs_tol", C.c_double), ("max_iter", C.c_int32), ("aitken", C.c_int32)]
+
+
+class PicardInfo(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("linear_iterations", C.c_int32), ("residual_initial", C.c_double),
+                ("residual_final", C.c_double), ("status", C.c_int32), ("recorded", C.c_int32),
+                ("residual_norms", C.c_double * PICARD_HISTORY), ("omegas", C.c_double * PICARD_HISTORY)]
+
+
 class SolveInfo(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("restarts", C.c_int32), ("rel_residual", C.c_double),
                 ("lambda_max", C.c_double), ("status", C.c_int32)]
@@ -101,6 +114,10 @@ def _load():
         "sipg_multigrid_levels": (C.c_int32, [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int32]),
         "sipg_precondition": (st, [P, P, P, C.POINTER(SolveOpts), P]),
         "sipg_multigrid_transfer": (st, [P, C.c_int32, C.c_int32, C.c_int32, P, P, P]),
+        "sipg_update_viscosity": (st, [P, P, P]),
+        "sipg_picard_opts_default": (None, [C.POINTER(PicardOpts)]),
+        "sipg_picard_work_bytes": (C.c_size_t, [P]),
+        "sipg_picard_solve": (st, [P, P, P, P, C.POINTER(SolveOpts), C.POINTER(PicardOpts), C.POINTER(PicardInfo), P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

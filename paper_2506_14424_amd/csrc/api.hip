@@ -474,6 +474,42 @@ sipg_status check_opts(const sipg_plan* P, const sipg_solve_opts& o) {
     return SIPG_OK;
 }
 
+// Picard work layout: vectors padded to 32 doubles (256 bytes)
+long long picard_stride(long long n) { return (n + 31) / 32 * 32; }
+
+// Viscosity from the finest level's velocity u on every level, then each
+// level's diagonal; cached eigenvalue estimates are dropped.
+sipg_status update_viscosity(sipg_plan* P, const double* u, hipStream_t s) {
+    FineVelocity F;
+    std::memset(&F, 0, sizeof(F));
+    F.u = u;
+    F.verts = P->curved ? P->verts64_d : nullptr;
+    F.nx = P->nx; F.ny = P->ny; F.nz = P->nz; F.n = P->n;
+    for (int j = 0; j < P->n; ++j) {
+        F.g[j] = P->tab64.x[j];
+        double den = 1.0;
+        for (int m = 0; m < P->n; ++m)
+            if (m != j) den *= P->tab64.x[j] - P->tab64.x[m];
+        F.inv_den[j] = 1.0 / den;
+    }
+    const int nl = mg_levels(P);
+    for (int l = 0; l < nl; ++l) {
+        sipg_plan* L = mg_level(P, l);
+        LevelPoints Lv;
+        std::memset(&Lv, 0, sizeof(Lv));
+        Lv.nx = L->nx; Lv.ny = L->ny; Lv.nz = L->nz; Lv.n = L->n;
+        Lv.r = P->nx / L->nx;
+        if (Lv.r * L->nx != P->nx || Lv.r * L->ny != P->ny || Lv.r * L->nz != P->nz || (Lv.r & (Lv.r - 1)) != 0)
+            return fail(SIPG_ERR_INVALID, "multigrid level is not a power-of-two coarsening of the plan's mesh");
+        for (int j = 0; j < L->n; ++j) Lv.g[j] = L->tab64.x[j];
+        HIP_TRY(launch_picard_viscosity(F, Lv, L->law, L->nface, L->mu_cell64, L->mu_cell32, L->mu_face64,
+                                        L->mu_face32, s));
+        HIP_TRY(launch_diagonal(L->n, L->C, L->curved, L->opdata<double>(), L->diag64, L->dinv64, L->dinv32, s));
+        L->lz_valid = false;
+    }
+    return SIPG_OK;
+}
+
 // Eigenvalue estimates (cached per level) and Chebyshev coefficients of the
 // preconditioner in P->opts: the finest level's polynomial, and with
 // multigrid every coarser level's (coarse_degree on the coarsest).
@@ -1057,6 +1093,121 @@ sipg_status sipg_solve(sipg_plan* P, const double* b, double* x, const sipg_solv
     }
     return P->info.status == SIPG_OK ? SIPG_OK
                                      : fail((sipg_status)P->info.status, "solve did not reach the tolerance");
+}
+
+
+// ------------------------------------------------------------ Picard update
+
+void sipg_picard_opts_default(sipg_picard_opts* o) {
+    if (!o) return;
+    o->rel_tol = 1e-8;
+    o->abs_tol = 0.0;
+    o->max_iter = 50;
+    o->aitken = 1;
+}
+
+size_t sipg_picard_work_bytes(const sipg_plan* P) {
+    if (!valid_plan(P)) return 0;
+    return (size_t)(3 * picard_stride(P->ndof) + 3 * kPicardBlocks + 8) * sizeof(double);
+}
+
+sipg_status sipg_update_viscosity(sipg_plan* P, const double* u, void* stream) {
+    if (!valid_plan(P) || !u) return fail(SIPG_ERR_INVALID, "null argument");
+    if (!P->bound) return fail(SIPG_ERR_STATE, "plan not bound");
+    if (P->op != SIPG_VISCOUS || P->law.kind != SIPG_LAW_CARREAU)
+        return fail(SIPG_ERR_INVALID, "the viscosity update needs a viscous plan with the CARREAU law");
+    if (P->phase == PH_RUNNING || P->phase == PH_CHECKING) return fail(SIPG_ERR_STATE, "a solve is in progress on this plan");
+    return update_viscosity(P, u, static_cast<hipStream_t>(stream));
+}
+
+sipg_status sipg_picard_solve(sipg_plan* P, const double* b, double* x, void* work, const sipg_solve_opts* lin_opts,
+                              const sipg_picard_opts* opts, sipg_picard_info* info, void* stream) {
+    if (!valid_plan(P) || !b || !x || !work) return fail(SIPG_ERR_INVALID, "null argument");
+    if (!P->bound || !P->with_solver) return fail(SIPG_ERR_STATE, "plan not bound with solver workspace");
+    if (P->op != SIPG_VISCOUS || P->law.kind != SIPG_LAW_CARREAU)
+        return fail(SIPG_ERR_INVALID, "the Picard iteration needs a viscous plan with the CARREAU law");
+    if (P->phase == PH_RUNNING || P->phase == PH_CHECKING) return fail(SIPG_ERR_STATE, "a solve is in progress on this plan");
+    if (reinterpret_cast<uintptr_t>(work) % 256 != 0) return fail(SIPG_ERR_INVALID, "work must be 256-byte aligned");
+    if (static_cast<const void*>(b) == static_cast<void*>(x)) return fail(SIPG_ERR_INVALID, "b and x must not alias");
+    sipg_picard_opts o;
+    if (opts) o = *opts; else sipg_picard_opts_default(&o);
+    if (!(o.rel_tol >= 0.0) || !(o.abs_tol >= 0.0) || !std::isfinite(o.rel_tol) || !std::isfinite(o.abs_tol) ||
+        o.max_iter < 0)
+        return fail(SIPG_ERR_INVALID, "Picard options: tolerances must be finite and >= 0, max_iter >= 0");
+    sipg_solve_opts lo;
+    if (lin_opts) lo = *lin_opts; else sipg_solve_opts_default(&lo);
+    const sipg_status vrc = check_opts(P, lo);
+    if (vrc != SIPG_OK) return vrc;
+
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const long long n = P->ndof, stride = picard_stride(n);
+    double* R = static_cast<double*>(work);
+    double* Rp = R + stride;
+    double* dl = Rp + stride;
+    double* partials = dl + stride;
+    double* sums = partials + 3 * kPicardBlocks;
+    const char* wb = static_cast<const char*>(work);
+    const char* we = wb + sipg_picard_work_bytes(P);
+    auto overlaps = [&](const void* v) {
+        const char* a = static_cast<const char*>(v);
+        return a + n * sizeof(double) > wb && a < we;
+    };
+    if (overlaps(b) || overlaps(x)) return fail(SIPG_ERR_INVALID, "work must not alias b or x");
+
+    sipg_picard_info inf;
+    std::memset(&inf, 0, sizeof(inf));
+    double h[3] = {0.0, 0.0, 0.0};
+    // R <- b - A(nu(x)) x with the viscosity updated from x; h <- sums with Rp
+    auto residual = [&](const double* prev) -> sipg_status {
+        sipg_status rc = update_viscosity(P, x, s);
+        if (rc != SIPG_OK) return rc;
+        ApplyIO<double> io;
+        std::memset(&io, 0, sizeof(io));
+        io.x = x; io.y = R; io.parts = SIPG_PART_ALL; io.r = b;
+        HIP_TRY(launch_apply<double>(P->n, P->C, P->curved, P->opdata<double>(), io, MODE_RESID, s));
+        HIP_TRY(launch_picard_sums(R, prev, n, partials, sums, s));
+        HIP_TRY(hipMemcpyAsync(h, sums, sizeof(h), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        return SIPG_OK;
+    };
+    sipg_status rc = residual(nullptr);
+    if (rc != SIPG_OK) return rc;
+    const double r0 = std::sqrt(h[0]);
+    double rn = r0, omega = 1.0;
+    inf.residual_initial = r0;
+    inf.residual_norms[0] = r0;
+    inf.recorded = 1;
+    inf.status = SIPG_ERR_NOT_CONVERGED;
+    for (int k = 0;; ++k) {
+        if (!std::isfinite(rn)) { inf.status = SIPG_ERR_BREAKDOWN; break; }
+        if (rn <= o.rel_tol * r0 || rn <= o.abs_tol) { inf.status = SIPG_OK; break; }
+        if (k >= o.max_iter) break;
+        if (o.aitken && k > 0 && h[2] > 0.0) omega = -omega * h[1] / h[2];
+        sipg_solve_info li;
+        rc = sipg_solve(P, R, dl, &lo, &li, stream);
+        inf.linear_iterations += li.iterations;
+        if (rc != SIPG_OK) { inf.status = rc; break; }
+        HIP_TRY(launch_axpy(x, dl, omega, n, s));
+        std::swap(R, Rp);
+        rc = residual(Rp);
+        if (rc != SIPG_OK) return rc;
+        rn = std::sqrt(h[0]);
+        inf.iterations = k + 1;
+        if (k < SIPG_PICARD_HISTORY) inf.omegas[k] = omega;
+        if (k + 1 < SIPG_PICARD_HISTORY) {
+            inf.residual_norms[k + 1] = rn;
+            inf.recorded = k + 2;
+        }
+    }
+    inf.residual_final = rn;
+    if (info) *info = inf;
+    if (inf.status == SIPG_OK) {
+        g_err.clear();
+        return SIPG_OK;
+    }
+    return fail((sipg_status)inf.status, inf.status == SIPG_ERR_NOT_CONVERGED
+                                             ? "Picard iteration did not reach the tolerance"
+                                             : "Picard iteration stopped: linear solve failed or residual not finite");
 }
 
 }  // extern "C"

@@ -102,6 +102,24 @@ struct MgTab {
     T H[2][kMaxN][kMaxN];
 };
 
+// Picard viscosity update: the finest level's velocity (3 components) and
+// the points of the level whose viscosity is evaluated.
+struct FineVelocity {
+    const double* u;          // [ncell][3][n^3]
+    const double* verts;      // curved cells: vertex coordinates, else nullptr (unit box)
+    int nx, ny, nz, n;
+    double g[kMaxN];          // Gauss points of [0, 1]
+    double inv_den[kMaxN];    // 1 / prod_{m != j} (g_j - g_m)
+};
+
+struct LevelPoints {
+    int nx, ny, nz, n;
+    int r;                    // fine cells per level cell and direction (2^mesh steps)
+    double g[kMaxN];          // the level's Gauss points
+};
+
+constexpr int kPicardBlocks = 512;  // blocks of the residual sums (partials: 3 * kPicardBlocks)
+
 // ---------------------------------------------------------------- launchers
 // (defined in the .hip files; return hipError_t of the launch)
 
@@ -119,6 +137,15 @@ hipError_t launch_setup(int n, int C, bool curved, const OpData<double>& op, con
 
 hipError_t launch_diagonal(int n, int C, bool curved, const OpData<double>& op, double* diag,
                            double* dinv, float* dinv32, hipStream_t s);
+
+// viscosity eta(gdot(u)) at all cell and face points of one level (FP64 + FP32)
+hipError_t launch_picard_viscosity(const FineVelocity& F, const LevelPoints& Lv, const LawDev& law, long long nface,
+                                   double* mu_cell64, float* mu_cell32, double* mu_face64, float* mu_face32,
+                                   hipStream_t s);
+// out[0..2] = |R|^2, Rp.(R - Rp), |R - Rp|^2 (Rp may be null: zeros); deterministic
+hipError_t launch_picard_sums(const double* R, const double* Rp, long long n, double* partials, double* out,
+                              hipStream_t s);
+hipError_t launch_axpy(double* x, const double* d, double omega, long long n, hipStream_t s);
 
 // Multigrid transfers between a fine level (nf nodes per direction, fine
 // mesh fx*fy*fz cells) and the next coarser one (nc; same mesh for a degree

@@ -246,6 +246,51 @@ class Operator:
             check(rc)
         return x, self._info(info)
 
+    # ------------------------------------------------------------- nonlinear viscous step
+    def update_viscosity(self, u, stream=None):
+        """Viscosity at every quadrature point (all multigrid levels) from the
+        velocity u, then the diagonals; see sipg_update_viscosity."""
+        import torch
+        self._check_vec(u)
+        if u.dtype != torch.float64:
+            raise TypeError("update_viscosity takes an FP64 vector")
+        check(lib.sipg_update_viscosity(self._h, C.c_void_p(u.data_ptr()), C.c_void_p(_stream_handle(stream))))
+
+    def picard_solve(self, b, x=None, opts: SolveOptions | None = None, rel_tol: float = 1e-8,
+                     abs_tol: float = 0.0, max_iter: int = 50, aitken: bool = True, work=None, stream=None,
+                     raise_on_error=True):
+        """A(nu(x)) x = b by Picard iterations with Aitken relaxation; x holds
+        the initial iterate (zero if None).  `opts` configures the linear
+        solves (rel_tol relative to the current residual).  Returns (x, info)."""
+        import torch
+        self._check_vec(b)
+        if b.dtype != torch.float64:
+            raise TypeError("picard_solve takes FP64 vectors")
+        x = torch.zeros_like(b) if x is None else x
+        self._check_vec(x)
+        nbytes = int(lib.sipg_picard_work_bytes(self._h))
+        if work is None:
+            work = torch.empty(nbytes + 256, dtype=torch.uint8, device=b.device)
+        ptr = work.data_ptr()
+        off = (-ptr) % 256
+        if work.numel() - off < nbytes:
+            raise ValueError(f"work needs {nbytes} bytes after 256-byte alignment")
+        po = F.PicardOpts()
+        po.rel_tol, po.abs_tol, po.max_iter, po.aitken = rel_tol, abs_tol, max_iter, int(aitken)
+        lo = (opts or SolveOptions(rel_tol=1e-3)).to_c()
+        info = F.PicardInfo()
+        rc = lib.sipg_picard_solve(self._h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()),
+                                   C.c_void_p(ptr + off), C.byref(lo), C.byref(po), C.byref(info),
+                                   C.c_void_p(_stream_handle(stream)))
+        if rc != 0 and raise_on_error:
+            check(rc)
+        k = info.recorded
+        return x, {"iterations": info.iterations, "linear_iterations": info.linear_iterations,
+                   "residual_initial": info.residual_initial, "residual_final": info.residual_final,
+                   "status": F.STATUS.get(info.status, info.status),
+                   "residual_norms": list(info.residual_norms[:k]),
+                   "omegas": list(info.omegas[:max(0, min(info.iterations, F.PICARD_HISTORY))])}
+
     def precondition(self, r, z=None, opts: SolveOptions | None = None, stream=None):
         """One application z = M r of the solve's preconditioner (FP64 vectors)."""
         import torch

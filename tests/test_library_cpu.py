@@ -103,3 +103,24 @@ def test_package_import_loads_a_single_hip_runtime():
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
     assert out.returncode == 0, out.stderr[-2000:]
     assert out.stdout.strip().splitlines()[-1] == "1"
+
+
+def test_picard_entry_points_on_cpu():
+    """Defaults, the work size, and the host-side refusals of the Picard
+    entry points (no GPU call is made before these checks)."""
+    import torch  # noqa: F401
+    from paper_2506_14424_amd import Operator, SipgError, _ffi as F
+    o = F.PicardOpts()
+    F.lib.sipg_picard_opts_default(C.byref(o))
+    assert o.rel_tol == 1e-8 and o.abs_tol == 0.0 and o.max_iter == 50 and o.aitken == 1
+    cfg = W.config("c3", 3)
+    op = Operator.from_config(cfg, W.box_vertices(3, 3, 3, 0.1))
+    wb = int(F.lib.sipg_picard_work_bytes(op._h))
+    assert wb >= 3 * 8 * op.ndof + 3 * 8 * 512
+    dummy = C.c_void_p(256)
+    assert F.lib.sipg_update_viscosity(op._h, dummy, None) == -7            # not bound
+    rc = F.lib.sipg_picard_solve(op._h, dummy, C.c_void_p(512), C.c_void_p(1024), None, None, None, None)
+    assert rc == -7
+    assert F.lib.sipg_update_viscosity(op._h, None, None) == -1
+    sine = Operator.from_config(W.config("c1"))
+    assert F.lib.sipg_update_viscosity(sine._h, dummy, None) == -7
