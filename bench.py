@@ -8,7 +8,8 @@ last-level cache.  Besides the headline DoF/s the line reports the FP32
 (preconditioner precision) apply, the setup including the inverse diagonal,
 FP64- vs FP32-preconditioned solves (one-level Chebyshev-Jacobi and
 hp-multigrid) of the 24^3 k = 4 Carreau workload to 1e-8, the penalty-step
-operator (applies and solves), the continuous-batching request loop (solves/s, p50/p99), the
+operator (applies and solves), the Picard-Aitken nonlinear viscous step, the
+continuous-batching request loop (solves/s, p50/p99), the
 roofline of the apply kernel and the CPU oracle timed on this host.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
@@ -211,6 +212,43 @@ def penalty_step(steps, warmup, tol=1e-8):
     return out
 
 
+def picard_step(tol=1e-8):
+    """c7: the nonlinear viscous step (viscosity from the velocity, Picard
+    iterations) with and without Aitken relaxation, linear solves to 1e-3 with
+    FP32 hp-multigrid; plus the viscosity update alone (all levels and their
+    diagonals)."""
+    import torch
+    import workloads as W
+    from paper_2506_14424_amd import Operator, SolveOptions
+    cfg = W.config("c7")
+    V = W.box_vertices(cfg["nx"], cfg["ny"], cfg["nz"], cfg["perturb"])
+    op = Operator.from_config(cfg, V).set_multigrid().bind(with_solver=True)
+    b = torch.from_numpy(W.uniform_vector(cfg["x_seed"], op.ndof) * cfg["b_scale"]).cuda()
+    lin = SolveOptions(rel_tol=1e-3, precond="multigrid", cheb_degree=4)
+    work = torch.empty(op.picard_work_bytes() + 256, dtype=torch.uint8, device="cuda")
+    out = {"workload": f"c7: nonlinear viscous step, k=4, 24^3 perturbed, Carreau law of the velocity, "
+                       f"{op.ndof} DoFs, x0 = 0, rel. tol {tol:g} of the nonlinear residual"}
+    for key, aitken in (("aitken", True), ("plain", False)):
+        op.picard_solve(b, opts=lin, rel_tol=tol, max_iter=60, aitken=aitken, work=work)   # warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, info = op.picard_solve(b, opts=lin, rel_tol=tol, max_iter=60, aitken=aitken, work=work)
+        torch.cuda.synchronize()
+        out[key] = {"seconds": time.perf_counter() - t0, "picard_iterations": info["iterations"],
+                    "cg_iterations": info["linear_iterations"], "status": info["status"],
+                    "residual_reduction": info["residual_final"] / info["residual_initial"]}
+    s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    s0.record()
+    for _ in range(reps):
+        op.update_viscosity(x)
+    s1.record()
+    torch.cuda.synchronize()
+    out["update_viscosity_ms"] = s0.elapsed_time(s1) / reps
+    out["speedup_aitken"] = out["plain"]["seconds"] / out["aitken"]["seconds"]
+    return out
+
+
 def serving(count=256, rate=20.0, budget=8 << 30):
     """c5: the seeded request stream through the continuous-batching loop."""
     import workloads as W
@@ -340,6 +378,9 @@ def main():
         log("penalty step (c6) ...")
         line["penalty_step"] = penalty_step(args.steps, args.warmup)
         log(json.dumps(line["penalty_step"]))
+        log("nonlinear viscous step (c7) ...")
+        line["picard"] = picard_step()
+        log(json.dumps(line["picard"]))
     if not args.no_serve:
         log("serving loop (c5) ...")
         line["serving"] = serving()

@@ -256,6 +256,9 @@ class Operator:
             raise TypeError("update_viscosity takes an FP64 vector")
         check(lib.sipg_update_viscosity(self._h, C.c_void_p(u.data_ptr()), C.c_void_p(_stream_handle(stream))))
 
+    def picard_work_bytes(self) -> int:
+        return int(lib.sipg_picard_work_bytes(self._h))
+
     def picard_solve(self, b, x=None, opts: SolveOptions | None = None, rel_tol: float = 1e-8,
                      abs_tol: float = 0.0, max_iter: int = 50, aitken: bool = True, work=None, stream=None,
                      raise_on_error=True):
@@ -268,7 +271,7 @@ class Operator:
             raise TypeError("picard_solve takes FP64 vectors")
         x = torch.zeros_like(b) if x is None else x
         self._check_vec(x)
-        nbytes = int(lib.sipg_picard_work_bytes(self._h))
+        nbytes = self.picard_work_bytes()
         if work is None:
             work = torch.empty(nbytes + 256, dtype=torch.uint8, device=b.device)
         ptr = work.data_ptr()
