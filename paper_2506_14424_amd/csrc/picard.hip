@@ -12,7 +12,9 @@
 // interior trace alone on the boundary), so every face point carries one
 // viscosity, as the operator kernel expects.  One thread per point; the
 // fine velocity is evaluated with the 1D Lagrange values and derivatives at
-// the fine reference point (O(n^3) per point, cache-resident cell values).
+// the fine reference point (O(n^3) per point).  On the levels that share
+// the fine mesh (r = 1) a block handles one cell or one face and stages the
+// cells' values in LDS once; coarser levels read them through the caches.
 
 #include "device_common.h"
 
@@ -22,13 +24,15 @@ namespace {
 
 constexpr int kThreads = 256;
 
-// 1D Lagrange basis on the fine level's Gauss points and its derivative at x.
+// 1D Lagrange basis on the fine level's NF Gauss points and its derivative at x.
+template <int NF>
 __device__ __forceinline__ void lagrange_1d(const FineVelocity& F, double x, double* v, double* dv) {
-    const int n = F.n;
-    for (int j = 0; j < n; ++j) {
+#pragma unroll
+    for (int j = 0; j < NF; ++j) {
         double val = F.inv_den[j], der = 0.0;
         // l_j(x) = inv_den_j prod_{m != j} (x - g_m); l_j' by the product rule
-        for (int m = 0; m < n; ++m) {
+#pragma unroll
+        for (int m = 0; m < NF; ++m) {
             if (m == j) continue;
             const double f = x - F.g[m];
             der = der * f + val;
@@ -39,53 +43,89 @@ __device__ __forceinline__ void lagrange_1d(const FineVelocity& F, double x, dou
     }
 }
 
+// l_j(x) and l_j'(x) for one (runtime) j on the NF fine Gauss points.
+template <int NF>
+__device__ __forceinline__ void lagrange_one(const FineVelocity& F, double x, int j, double& v, double& dv) {
+    double val = F.inv_den[j], der = 0.0;
+#pragma unroll
+    for (int m = 0; m < NF; ++m) {
+        const double f = m == j ? 1.0 : x - F.g[m];
+        der = m == j ? der : der * f + val;
+        val *= f;
+    }
+    v = val;
+    dv = der;
+}
+
 // Physical velocity gradient G[c][i] = d u_c / d x_i of fine cell (fx, fy, fz)
-// at fine reference point xi.
-__device__ void velocity_gradient(const FineVelocity& F, int fx, int fy, int fz, const double xi[3],
+// at fine reference point xi; U: that cell's 3 NF^3 values (global memory or
+// a copy in LDS).  The xi_1 and xi_2 contractions are unrolled with their
+// 1D tables in registers; the xi_3 loop computes its factor in place.
+template <int NF>
+__device__ void velocity_gradient(const FineVelocity& F, const double* U, int fx, int fy, int fz, const double xi[3],
                                   double G[3][3]) {
-    double lv[3][kMaxN], ld[3][kMaxN];
-    for (int d = 0; d < 3; ++d) lagrange_1d(F, xi[d], lv[d], ld[d]);
-    const int n = F.n, n3 = n * n * n;
-    const long long cell = ((long long)fz * F.ny + fy) * F.nx + fx;
+    double lv[2][NF], ld[2][NF];
+    lagrange_1d<NF>(F, xi[0], lv[0], ld[0]);
+    lagrange_1d<NF>(F, xi[1], lv[1], ld[1]);
+    constexpr int n3 = NF * NF * NF;
     double gref[3][3];
+#pragma unroll 1
     for (int c = 0; c < 3; ++c) {
-        const double* U = F.u + (cell * 3 + c) * n3;
         double g0 = 0.0, g1 = 0.0, g2 = 0.0;
-        for (int j3 = 0; j3 < n; ++j3)
-            for (int j2 = 0; j2 < n; ++j2) {
-                const double* row = U + (j3 * n + j2) * n;
+#pragma unroll 1
+        for (int j3 = 0; j3 < NF; ++j3) {
+            double v3, d3;
+            lagrange_one<NF>(F, xi[2], j3, v3, d3);
+            const double* slab = U + c * n3 + j3 * NF * NF;
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0;  // sums over (j1, j2) of the slab
+#pragma unroll
+            for (int j2 = 0; j2 < NF; ++j2) {
                 double sd = 0.0, sv = 0.0;
-                for (int j1 = 0; j1 < n; ++j1) {
-                    sd += ld[0][j1] * row[j1];
-                    sv += lv[0][j1] * row[j1];
+#pragma unroll
+                for (int j1 = 0; j1 < NF; ++j1) {
+                    const double u = slab[j2 * NF + j1];
+                    sd += ld[0][j1] * u;
+                    sv += lv[0][j1] * u;
                 }
-                g0 += (lv[1][j2] * lv[2][j3]) * sd;
-                g1 += (ld[1][j2] * lv[2][j3]) * sv;
-                g2 += (lv[1][j2] * ld[2][j3]) * sv;
+                a0 += lv[1][j2] * sd;
+                a1 += ld[1][j2] * sv;
+                a2 += lv[1][j2] * sv;
             }
+            g0 += v3 * a0;
+            g1 += v3 * a1;
+            g2 += d3 * a2;
+        }
         gref[c][0] = g0; gref[c][1] = g1; gref[c][2] = g2;
     }
     double Ji[3][3];
     if (F.verts != nullptr) {
         double geo[8][3], gi[8];
+#pragma unroll
         for (int i = 0; i < 3; ++i) {
             trilinear_coeffs(F.verts, F.nx, F.ny, fx, fy, fz, i, gi);
+#pragma unroll
             for (int k = 0; k < 8; ++k) geo[k][i] = gi[k];
         }
         double det;
         jacobian_inverse<double>(geo, xi[0], xi[1], xi[2], Ji, det);
     } else {
+#pragma unroll
         for (int d = 0; d < 3; ++d)
+#pragma unroll
             for (int i = 0; i < 3; ++i) Ji[d][i] = d == i ? double(d == 0 ? F.nx : d == 1 ? F.ny : F.nz) : 0.0;
     }
+#pragma unroll
     for (int c = 0; c < 3; ++c)
+#pragma unroll
         for (int i = 0; i < 3; ++i) G[c][i] = gref[c][0] * Ji[0][i] + gref[c][1] * Ji[1][i] + gref[c][2] * Ji[2][i];
 }
 
-// eps:eps of the symmetric part of G (times `scale` squared)
+// eps:eps of the symmetric part of G
 __device__ __forceinline__ double sym_square(const double G[3][3]) {
     double ee = 0.0;
+#pragma unroll
     for (int i = 0; i < 3; ++i)
+#pragma unroll
         for (int j = 0; j < 3; ++j) {
             const double e = 0.5 * (G[i][j] + G[j][i]);
             ee += e * e;
@@ -106,7 +146,37 @@ __device__ __forceinline__ void locate(int r, int e, double xi, int& f, double& 
     xf = t - k;
 }
 
-__global__ void k_picard_cell(FineVelocity F, LevelPoints Lv, LawDev law, double* mu64, float* mu32) {
+// Face f of a level: its normal direction (returned) and position, pos[d] =
+// 0..N_d along the normal, the other two the cell indices.
+__device__ __forceinline__ int decode_face(const LevelPoints& Lv, long long f, int pos[3]) {
+    const long long nfx = (long long)(Lv.nx + 1) * Lv.ny * Lv.nz, nfy = (long long)Lv.nx * (Lv.ny + 1) * Lv.nz;
+    if (f < nfx) {
+        pos[0] = (int)(f % (Lv.nx + 1)); pos[1] = (int)((f / (Lv.nx + 1)) % Lv.ny);
+        pos[2] = (int)(f / ((long long)(Lv.nx + 1) * Lv.ny));
+        return 0;
+    }
+    if (f < nfx + nfy) {
+        f -= nfx;
+        pos[0] = (int)(f % Lv.nx); pos[1] = (int)((f / Lv.nx) % (Lv.ny + 1));
+        pos[2] = (int)(f / ((long long)Lv.nx * (Lv.ny + 1)));
+        return 1;
+    }
+    f -= nfx + nfy;
+    pos[0] = (int)(f % Lv.nx); pos[1] = (int)((f / Lv.nx) % Lv.ny);
+    pos[2] = (int)(f / ((long long)Lv.nx * Lv.ny));
+    return 2;
+}
+
+__device__ __forceinline__ void store_mu(double* mu64, float* mu32, long long idx, const LawDev& law, double ee) {
+    const double m = eta(law, sqrt(2.0 * ee));
+    mu64[idx] = m;
+    mu32[idx] = (float)m;
+}
+
+// Any level (fine cells found by locate): one thread per point, the fine
+// cell's values read through the caches.
+template <int NF>
+__global__ void __launch_bounds__(kThreads) k_picard_cell(FineVelocity F, LevelPoints Lv, LawDev law, double* mu64, float* mu32) {
     const int n = Lv.n, n3 = n * n * n;
     const long long total = (long long)Lv.nx * Lv.ny * Lv.nz * n3;
     for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
@@ -114,47 +184,30 @@ __global__ void k_picard_cell(FineVelocity F, LevelPoints Lv, LawDev law, double
         const int q = (int)(idx % n3);
         const int e = (int)(idx / n3);
         const int ex = e % Lv.nx, ey = (e / Lv.nx) % Lv.ny, ez = e / (Lv.nx * Lv.ny);
-        const int q1 = q % n, q2 = (q / n) % n, q3 = q / (n * n);
         int fx, fy, fz;
         double xi[3];
-        locate(Lv.r, ex, Lv.g[q1], fx, xi[0]);
-        locate(Lv.r, ey, Lv.g[q2], fy, xi[1]);
-        locate(Lv.r, ez, Lv.g[q3], fz, xi[2]);
+        locate(Lv.r, ex, Lv.g[q % n], fx, xi[0]);
+        locate(Lv.r, ey, Lv.g[(q / n) % n], fy, xi[1]);
+        locate(Lv.r, ez, Lv.g[q / (n * n)], fz, xi[2]);
         double G[3][3];
-        velocity_gradient(F, fx, fy, fz, xi, G);
-        const double m = eta(law, sqrt(2.0 * sym_square(G)));
-        mu64[idx] = m;
-        mu32[idx] = (float)m;
+        const long long fc = ((long long)fz * F.ny + fy) * F.nx + fx;
+        velocity_gradient<NF>(F, F.u + fc * 3 * NF * NF * NF, fx, fy, fz, xi, G);
+        store_mu(mu64, mu32, idx, law, sym_square(G));
     }
 }
 
-__global__ void k_picard_face(FineVelocity F, LevelPoints Lv, LawDev law, long long nface, double* mu64,
+template <int NF>
+__global__ void __launch_bounds__(kThreads) k_picard_face(FineVelocity F, LevelPoints Lv, LawDev law, long long nface, double* mu64,
                               float* mu32) {
     const int n = Lv.n, n2 = n * n;
     const long long total = nface * n2;
-    const long long nfx = (long long)(Lv.nx + 1) * Lv.ny * Lv.nz, nfy = (long long)Lv.nx * (Lv.ny + 1) * Lv.nz;
+    const int N[3] = {Lv.nx, Lv.ny, Lv.nz};
     for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
          idx += (long long)gridDim.x * blockDim.x) {
         const int p = (int)(idx % n2);
-        long long f = idx / n2;
-        int d, pos[3];  // pos[d] = face position 0..N_d, the others the cell indices
-        if (f < nfx) {
-            d = 0;
-            pos[0] = (int)(f % (Lv.nx + 1)); pos[1] = (int)((f / (Lv.nx + 1)) % Lv.ny);
-            pos[2] = (int)(f / ((long long)(Lv.nx + 1) * Lv.ny));
-        } else if (f < nfx + nfy) {
-            f -= nfx;
-            d = 1;
-            pos[0] = (int)(f % Lv.nx); pos[1] = (int)((f / Lv.nx) % (Lv.ny + 1));
-            pos[2] = (int)(f / ((long long)Lv.nx * (Lv.ny + 1)));
-        } else {
-            f -= nfx + nfy;
-            d = 2;
-            pos[0] = (int)(f % Lv.nx); pos[1] = (int)((f / Lv.nx) % Lv.ny);
-            pos[2] = (int)(f / ((long long)Lv.nx * Lv.ny));
-        }
+        int pos[3];
+        const int d = decode_face(Lv, idx / n2, pos);
         const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
-        const int N[3] = {Lv.nx, Lv.ny, Lv.nz};
         double acc[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
         int sides = 0;
         for (int side = 1; side >= 0; --side) {  // side 1: the lower cell's face xi_d = 1
@@ -167,18 +220,142 @@ __global__ void k_picard_face(FineVelocity F, LevelPoints Lv, LawDev law, long l
             fc[d] = Lv.r * ed + (side == 1 ? Lv.r - 1 : 0);
             xi[d] = (double)side;
             double G[3][3];
-            velocity_gradient(F, fc[0], fc[1], fc[2], xi, G);
+            const long long cid = ((long long)fc[2] * F.ny + fc[1]) * F.nx + fc[0];
+            velocity_gradient<NF>(F, F.u + cid * 3 * NF * NF * NF, fc[0], fc[1], fc[2], xi, G);
+#pragma unroll
             for (int i = 0; i < 3; ++i)
+#pragma unroll
                 for (int j = 0; j < 3; ++j) acc[i][j] += G[i][j];
             ++sides;
         }
-        const double s = 1.0 / sides;
+        const double sc = 1.0 / sides;
+#pragma unroll
         for (int i = 0; i < 3; ++i)
-            for (int j = 0; j < 3; ++j) acc[i][j] *= s;
-        const double m = eta(law, sqrt(2.0 * sym_square(acc)));
-        mu64[idx] = m;
-        mu32[idx] = (float)m;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) acc[i][j] *= sc;
+        store_mu(mu64, mu32, idx, law, sym_square(acc));
     }
+}
+
+// Levels on the fine mesh (r = 1: the finest level and the degree steps):
+// a block of kSame threads takes `per` consecutive cells (or faces), stages
+// their fine values in LDS once and gives each level point one thread.
+constexpr int kSame = 256;
+
+template <int NF>
+__global__ void __launch_bounds__(kSame) k_picard_cell_same(FineVelocity F, LevelPoints Lv, LawDev law, int per,
+                                                            double* mu64, float* mu32) {
+    extern __shared__ double su[];  // [per][3 NF^3]
+    constexpr int nv = 3 * NF * NF * NF;
+    const int n = Lv.n, n3 = n * n * n;
+    const long long ncell = (long long)Lv.nx * Lv.ny * Lv.nz;
+    const int g = threadIdx.x / n3, q = threadIdx.x % n3;
+    for (long long c0 = (long long)blockIdx.x * per; c0 < ncell; c0 += (long long)gridDim.x * per) {
+        __syncthreads();
+        const long long lim = (ncell - c0 < per ? ncell - c0 : per) * nv;
+        for (int i = threadIdx.x; i < lim; i += kSame) su[i] = F.u[c0 * nv + i];
+        __syncthreads();
+        const long long e = c0 + g;
+        if (g < per && e < ncell) {
+            const int ex = (int)(e % Lv.nx), ey = (int)((e / Lv.nx) % Lv.ny), ez = (int)(e / ((long long)Lv.nx * Lv.ny));
+            const double xi[3] = {Lv.g[q % n], Lv.g[(q / n) % n], Lv.g[q / (n * n)]};
+            double G[3][3];
+            velocity_gradient<NF>(F, su + g * nv, ex, ey, ez, xi, G);
+            store_mu(mu64, mu32, e * n3 + q, law, sym_square(G));
+        }
+    }
+}
+
+template <int NF>
+__global__ void __launch_bounds__(kSame) k_picard_face_same(FineVelocity F, LevelPoints Lv, LawDev law,
+                                                            long long nface, int per, double* mu64, float* mu32) {
+    extern __shared__ double su[];  // [per][2][3 NF^3]
+    __shared__ int meta[kSame][6];  // per face: d, pos[3], have lower, have upper
+    constexpr int nv = 3 * NF * NF * NF;
+    const int n = Lv.n, n2 = n * n;
+    const int N[3] = {Lv.nx, Lv.ny, Lv.nz};
+    const int g = threadIdx.x / n2, p = threadIdx.x % n2;
+    for (long long f0 = (long long)blockIdx.x * per; f0 < nface; f0 += (long long)gridDim.x * per) {
+        __syncthreads();
+        if ((int)threadIdx.x < per && f0 + threadIdx.x < nface) {
+            int pos[3];
+            const int d = decode_face(Lv, f0 + threadIdx.x, pos);
+            meta[threadIdx.x][0] = d;
+            meta[threadIdx.x][1] = pos[0]; meta[threadIdx.x][2] = pos[1]; meta[threadIdx.x][3] = pos[2];
+            meta[threadIdx.x][4] = pos[d] > 0;
+            meta[threadIdx.x][5] = pos[d] < N[d];
+        }
+        __syncthreads();
+        const int nf = (int)(nface - f0 < per ? nface - f0 : per);
+        for (int i = threadIdx.x; i < nf * 2 * nv; i += kSame) {
+            const int gg = i / (2 * nv), rem = i % (2 * nv), s = rem / nv, j = rem % nv;
+            if (!meta[gg][4 + s]) continue;
+            const int d = meta[gg][0];
+            int c3[3] = {meta[gg][1], meta[gg][2], meta[gg][3]};
+            c3[d] -= (s == 0);
+            const long long cell = ((long long)c3[2] * Lv.ny + c3[1]) * Lv.nx + c3[0];
+            su[i] = F.u[cell * nv + j];
+        }
+        __syncthreads();
+        if (g < nf) {
+            const int d = meta[g][0];
+            const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+            double acc[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+            int sides = 0;
+            for (int s = 0; s < 2; ++s) {  // s = 0: the lower cell (its face xi_d = 1)
+                if (!meta[g][4 + s]) continue;
+                int c3[3] = {meta[g][1], meta[g][2], meta[g][3]};
+                c3[d] -= (s == 0);
+                double xi[3];
+                xi[t1] = Lv.g[p % n];
+                xi[t2] = Lv.g[p / n];
+                xi[d] = s == 0 ? 1.0 : 0.0;
+                double G[3][3];
+                velocity_gradient<NF>(F, su + (g * 2 + s) * nv, c3[0], c3[1], c3[2], xi, G);
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) acc[i][j] += G[i][j];
+                ++sides;
+            }
+            const double sc = 1.0 / sides;
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) acc[i][j] *= sc;
+            store_mu(mu64, mu32, (f0 + g) * n2 + p, law, sym_square(acc));
+        }
+    }
+}
+
+constexpr int kLdsCap = 56 * 1024;  // dynamic LDS per block of the same-mesh kernels (plus 6 KB of face data)
+
+template <int NF>
+hipError_t launch_nf(const FineVelocity& F, const LevelPoints& Lv, const LawDev& law, long long nface,
+                     double* mu_cell64, float* mu_cell32, double* mu_face64, float* mu_face32, hipStream_t s) {
+    constexpr int nvb = 3 * NF * NF * NF * (int)sizeof(double);
+    const int n = Lv.n;
+    if (Lv.r == 1) {
+        const long long ncell = (long long)Lv.nx * Lv.ny * Lv.nz;
+        int pc = kSame / (n * n * n), pf = kSame / (n * n);
+        pc = pc < kLdsCap / nvb ? pc : kLdsCap / nvb;
+        pf = pf < kLdsCap / (2 * nvb) ? pf : kLdsCap / (2 * nvb);
+        const long long bc = (ncell + pc - 1) / pc, bf = (nface + pf - 1) / pf;
+        hipLaunchKernelGGL(k_picard_cell_same<NF>, dim3((unsigned)(bc < 65535 ? bc : 65535)), dim3(kSame),
+                           (size_t)pc * nvb, s, F, Lv, law, pc, mu_cell64, mu_cell32);
+        hipLaunchKernelGGL(k_picard_face_same<NF>, dim3((unsigned)(bf < 65535 ? bf : 65535)), dim3(kSame),
+                           (size_t)pf * 2 * nvb, s, F, Lv, law, nface, pf, mu_face64, mu_face32);
+        return hipGetLastError();
+    }
+    auto grid = [](long long work) {
+        const long long b = (work + kThreads - 1) / kThreads;
+        return (unsigned)(b < 1 ? 1 : b > 65535 ? 65535 : b);
+    };
+    const long long nc = (long long)Lv.nx * Lv.ny * Lv.nz * n * n * n;
+    hipLaunchKernelGGL(k_picard_cell<NF>, dim3(grid(nc)), dim3(kThreads), 0, s, F, Lv, law, mu_cell64, mu_cell32);
+    hipLaunchKernelGGL(k_picard_face<NF>, dim3(grid(nface * n * n)), dim3(kThreads), 0, s, F, Lv, law, nface,
+                       mu_face64, mu_face32);
+    return hipGetLastError();
 }
 
 // Per-block partial sums of |R|^2, Rp.(R - Rp), |R - Rp|^2 (fixed order).
@@ -227,12 +404,14 @@ inline int grid_for(long long work) {
 hipError_t launch_picard_viscosity(const FineVelocity& F, const LevelPoints& Lv, const LawDev& law, long long nface,
                                    double* mu_cell64, float* mu_cell32, double* mu_face64, float* mu_face32,
                                    hipStream_t s) {
-    const long long nc = (long long)Lv.nx * Lv.ny * Lv.nz * Lv.n * Lv.n * Lv.n;
-    hipLaunchKernelGGL(k_picard_cell, dim3(grid_for(nc)), dim3(kThreads), 0, s, F, Lv, law, mu_cell64, mu_cell32);
-    const long long nf = nface * Lv.n * Lv.n;
-    hipLaunchKernelGGL(k_picard_face, dim3(grid_for(nf)), dim3(kThreads), 0, s, F, Lv, law, nface, mu_face64,
-                       mu_face32);
-    return hipGetLastError();
+    switch (F.n) {
+        case 2: return launch_nf<2>(F, Lv, law, nface, mu_cell64, mu_cell32, mu_face64, mu_face32, s);
+        case 3: return launch_nf<3>(F, Lv, law, nface, mu_cell64, mu_cell32, mu_face64, mu_face32, s);
+        case 4: return launch_nf<4>(F, Lv, law, nface, mu_cell64, mu_cell32, mu_face64, mu_face32, s);
+        case 5: return launch_nf<5>(F, Lv, law, nface, mu_cell64, mu_cell32, mu_face64, mu_face32, s);
+        case 6: return launch_nf<6>(F, Lv, law, nface, mu_cell64, mu_cell32, mu_face64, mu_face32, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_picard_sums(const double* R, const double* Rp, long long n, double* partials, double* out,
