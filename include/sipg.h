@@ -77,10 +77,16 @@ typedef enum { SIPG_BC_DIRICHLET = 0, SIPG_BC_NEUMANN = 1 } sipg_bc;
  *  CARREAU   the generalised Newtonian law of Sec. 2,
  *            mu = mu_inf + (mu0 - mu_inf)[kappa + (lam gdot)^a]^((b-1)/a),
  *            gdot = sqrt(2 eps(w):eps(w)) of the prescribed velocity
- *            w(x) = sum_m v_m cos(2 pi k_m.x + phi_m).
+ *            w(x) = sum_m v_m cos(2 pi k_m.x + phi_m);
+ *  ARRAYS    mu given at every quadrature point (Sec. 4.1 stores it
+ *            pointwise): mu_cell [ncells][n^3] in the node order of a cell,
+ *            mu_face [nfaces][n^2] in the face numbering of
+ *            sipg_viscosity_values, host arrays copied by sipg_plan_create,
+ *            every value finite and >= 0.  No multigrid hierarchy (coarse
+ *            levels have no values of their own).
  * The poisson operator ignores the law (mu = 1). */
 typedef enum {
-    SIPG_LAW_CONST = 0, SIPG_LAW_SINE = 1, SIPG_LAW_LOGFIELD = 2, SIPG_LAW_CARREAU = 3
+    SIPG_LAW_CONST = 0, SIPG_LAW_SINE = 1, SIPG_LAW_LOGFIELD = 2, SIPG_LAW_CARREAU = 3, SIPG_LAW_ARRAYS = 4
 } sipg_law_kind;
 
 #define SIPG_MAX_MODES 16
@@ -106,6 +112,8 @@ typedef struct {
     const double* a;           /* LOGFIELD host [n_modes] amplitudes */
     const double* v;           /* CARREAU host [n_modes][3] velocity amplitudes */
     const double* phi;         /* host [n_modes] phases */
+    const double* mu_cell;     /* ARRAYS: host [ncells][n^3] */
+    const double* mu_face;     /* ARRAYS: host [nfaces][n^2] */
 } sipg_viscosity;
 
 typedef struct {

@@ -13,7 +13,7 @@ F64, F32 = 0, 1
 VISCOUS, POISSON, PENALTY = 0, 1, 2
 OPS = {"viscous": VISCOUS, "poisson": POISSON, "penalty": PENALTY}
 BC = {"D": 0, "N": 1}
-LAW = {"const": 0, "sine": 1, "logfield": 2, "carreau": 3}
+LAW = {"const": 0, "sine": 1, "logfield": 2, "carreau": 3, "arrays": 4}
 MAX_MODES = 16
 
 STATUS = {
@@ -40,7 +40,8 @@ class Viscosity(C.Structure):
                 ("mu0", C.c_double), ("mu_inf", C.c_double), ("lam", C.c_double),
                 ("n_exp", C.c_double), ("kappa", C.c_double), ("a_exp", C.c_double),
                 ("n_modes", C.c_int32), ("k", C.POINTER(C.c_int32)), ("a", C.POINTER(C.c_double)),
-                ("v", C.POINTER(C.c_double)), ("phi", C.POINTER(C.c_double))]
+                ("v", C.POINTER(C.c_double)), ("phi", C.POINTER(C.c_double)),
+                ("mu_cell", C.POINTER(C.c_double)), ("mu_face", C.POINTER(C.c_double))]
 
 
 class Params(C.Structure):

@@ -117,6 +117,8 @@ struct sipg_plan {
     std::vector<double> tau_div, tau_cont;   // its per-cell factors (host)
     double *tau_div_d = nullptr, *tau_cont_d = nullptr;
     LawDev law;
+    std::vector<double> mu_cell_h, mu_face_h;   // ARRAYS law: the caller's values (host)
+    std::vector<float> mu_cell_h32, mu_face_h32;
     long long ncell, ndof, nface, nvert;
     Tables<double> tab64;
     Tables<float> tab32;
@@ -660,6 +662,21 @@ sipg_status sipg_plan_create(const sipg_mesh* mesh, const sipg_viscosity* law, c
                 }
                 break;
             }
+            case SIPG_LAW_ARRAYS: {
+                if (!law->mu_cell || !law->mu_face) {
+                    delete P; return fail(SIPG_ERR_INVALID, "ARRAYS law needs mu_cell and mu_face");
+                }
+                const size_t nc = (size_t)ncell * n * n * n, nf = (size_t)P->nface * n * n;
+                P->mu_cell_h.assign(law->mu_cell, law->mu_cell + nc);
+                P->mu_face_h.assign(law->mu_face, law->mu_face + nf);
+                for (double v : P->mu_cell_h)
+                    if (!(v >= 0.0) || !std::isfinite(v)) { delete P; return fail(SIPG_ERR_INVALID, "ARRAYS values must be finite and >= 0"); }
+                for (double v : P->mu_face_h)
+                    if (!(v >= 0.0) || !std::isfinite(v)) { delete P; return fail(SIPG_ERR_INVALID, "ARRAYS values must be finite and >= 0"); }
+                P->mu_cell_h32.assign(P->mu_cell_h.begin(), P->mu_cell_h.end());
+                P->mu_face_h32.assign(P->mu_face_h.begin(), P->mu_face_h.end());
+                break;
+            }
             default:
                 delete P;
                 return fail(SIPG_ERR_INVALID, "unknown viscosity law");
@@ -749,6 +766,12 @@ sipg_status sipg_plan_bind(sipg_plan* P, void* workspace, size_t bytes, int32_t 
     const OpData<double> od = P->opdata<double>();
     HIP_TRY(launch_setup(P->n, P->C, P->curved, od, P->law, P->penalty, P->hcell, P->tfac64, P->tfac32, P->mu_cell64,
                          P->mu_cell32, P->mu_face64, P->mu_face32, (int)P->nface, P->tau_div_d, P->tau_cont_d, s));
+    if (P->law.kind == SIPG_LAW_ARRAYS && P->C == 3 && !P->pen) {
+        HIP_TRY(hipMemcpyAsync(P->mu_cell64, P->mu_cell_h.data(), P->mu_cell_h.size() * 8, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(P->mu_face64, P->mu_face_h.data(), P->mu_face_h.size() * 8, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(P->mu_cell32, P->mu_cell_h32.data(), P->mu_cell_h32.size() * 4, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(P->mu_face32, P->mu_face_h32.data(), P->mu_face_h32.size() * 4, hipMemcpyHostToDevice, s));
+    }
     const OpData<double> od2 = P->opdata<double>();
     HIP_TRY(launch_diagonal(P->n, P->C, P->curved, od2, P->diag64, P->dinv64, P->dinv32, s));
     if (P->mg_on && P->with_solver) {
@@ -836,6 +859,8 @@ sipg_status sipg_plan_set_multigrid(sipg_plan* P, const sipg_mg_opts* opts) {
     if (opts) o = *opts; else sipg_mg_opts_default(&o);
     if (o.coarse_degree < 1 || o.coarse_degree > 63 || o.min_cells < 1 || o.max_levels < 1)
         return fail(SIPG_ERR_INVALID, "bad multigrid options");
+    if (P->C == 3 && !P->pen && P->law.kind == SIPG_LAW_ARRAYS)
+        return fail(SIPG_ERR_UNSUPPORTED, "tabulated viscosity (ARRAYS law) has no values on coarse levels");
     for (sipg_plan* c : P->mg) sipg_plan_destroy(c);
     P->mg.clear();
     // levels: degree k-1 .. 1 on the plan's mesh, then the mesh halved while possible

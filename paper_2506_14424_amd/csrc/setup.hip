@@ -288,7 +288,7 @@ hipError_t launch_setup(int n, int C, bool curved, const OpData<double>& op, con
     const double pk2 = penalty * (double)n * (double)n;
     hipLaunchKernelGGL(k_face_penalty, dim3((nface + bt - 1) / bt), dim3(bt), 0, s, op, nface, pk2, hcell, tfac64,
                        tfac32);
-    if (C == 3) {
+    if (C == 3 && law.kind != SIPG_LAW_ARRAYS) {  // ARRAYS: the values are copied in by the plan
         const long long nc = (long long)op.ncell * n * n * n;
         hipLaunchKernelGGL(k_visc_cell, dim3((unsigned)((nc + bt - 1) / bt)), dim3(bt), 0, s, op, n, law, mu_cell64,
                            mu_cell32);

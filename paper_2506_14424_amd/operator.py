@@ -56,6 +56,12 @@ def _law_struct(law: dict | None, keep: list) -> F.Viscosity:
         v.mu = law["mu"]
     elif kind == "sine":
         v.mu, v.amp = law["mu"], law["amp"]
+    elif kind == "arrays":
+        mc = np.ascontiguousarray(law["mu_cell"], dtype=np.float64).reshape(-1)
+        mf = np.ascontiguousarray(law["mu_face"], dtype=np.float64).reshape(-1)
+        keep += [mc, mf]
+        v.mu_cell = mc.ctypes.data_as(C.POINTER(C.c_double))
+        v.mu_face = mf.ctypes.data_as(C.POINTER(C.c_double))
     elif kind in ("logfield", "carreau"):
         k = np.ascontiguousarray(law["k"], dtype=np.int32).reshape(-1)
         phi = np.ascontiguousarray(law["phi"], dtype=np.float64)

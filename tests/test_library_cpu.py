@@ -124,3 +124,20 @@ def test_picard_entry_points_on_cpu():
     assert F.lib.sipg_update_viscosity(op._h, None, None) == -1
     sine = Operator.from_config(W.config("c1"))
     assert F.lib.sipg_update_viscosity(sine._h, dummy, None) == -7
+
+
+def test_arrays_law_validation_on_cpu():
+    """The tabulated viscosity is checked and copied at plan creation; it
+    has no multigrid hierarchy."""
+    from paper_2506_14424_amd import Operator, SipgError
+    cfg = W.config("c1", 2)
+    n = cfg["degree"] + 1
+    nface = 3 * 3 * 4
+    good = {"kind": "arrays", "mu_cell": np.ones((8, n ** 3)), "mu_face": np.ones((nface, n * n))}
+    op = Operator(2, 2, 2, cfg["degree"], "viscous", 10.0, 1.0, good)
+    assert op.nface == nface
+    with pytest.raises(SipgError, match="ARRAYS"):
+        Operator(2, 2, 2, cfg["degree"], "viscous", 10.0, 1.0, {"kind": "arrays", "mu_cell": good["mu_cell"],
+                                                               "mu_face": -good["mu_face"]})
+    with pytest.raises(SipgError, match="multigrid|coarse"):
+        op.set_multigrid()
