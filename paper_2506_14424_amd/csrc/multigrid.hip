@@ -5,9 +5,11 @@
 // cell at the fine nodes: for a degree step through P[i][j] = l^c_j(x^f_i) in
 // every direction of the same cell, for a mesh step through
 // H[b][i][j] = l_j((b + x_i) / 2) from the parent cell to its child b in
-// every direction.  Restriction is the transpose.  One thread per output
-// value; the few (n <= 6) tensor-product terms are summed directly, so no
-// output is written by more than one thread and no atomics are needed.
+// every direction.  Restriction is the transpose.  Degree steps run as
+// three 1D sweeps per cell in LDS; mesh steps (small, coarse levels) use one
+// thread per output value summing the few (n <= 6) tensor-product terms
+// directly.  No output is written by more than one thread and no atomics
+// are needed.
 
 #include "device_common.h"
 
@@ -109,6 +111,60 @@ __global__ void k_prolong_add(int C, int nf, int nc, int fx, int fy, int fz, con
     }
 }
 
+// Degree steps (same cell) by sum factorisation: one block per cell, the
+// cell's C n^3 input values in LDS, three 1D sweeps with the n_f x n_c table
+// P (restriction: contraction over the fine index; prolongation: over the
+// coarse index), the result written (restriction) or added (prolongation)
+// with coalesced accesses.  O(n) operations per intermediate value instead
+// of O(n^3) per output.
+constexpr int kSfThreads = 128;
+constexpr int kSfVals = 3 * kMaxN * kMaxN * kMaxN;
+
+template <typename T, bool RESTRICT>
+__global__ void __launch_bounds__(kSfThreads) k_pstep(int C, int nf, int nc, int ncell, const MgTab<T> tab,
+                                                     const T* in, T* out, const int* skip) {
+    if (skip != nullptr && *skip) return;
+    __shared__ T A[kSfVals], B[kSfVals];
+    // input extent (a) and output extent (b) along one direction
+    const int na = RESTRICT ? nf : nc, nb = RESTRICT ? nc : nf;
+    const int nin = C * na * na * na;
+    for (int e = blockIdx.x; e < ncell; e += gridDim.x) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < nin; i += kSfThreads) A[i] = in[(long long)e * nin + i];
+        __syncthreads();
+        // sweep 1 (first index): B[c][a3][a2][b1] = sum_a1 W(a1, b1) A[c][a3][a2][a1]
+        const int n1 = C * na * na * nb;
+        for (int k = threadIdx.x; k < n1; k += kSfThreads) {
+            const int b1 = k % nb, rest = k / nb;  // rest = (c, a3, a2)
+            const T* src = A + rest * na;
+            T acc = 0;
+            for (int a = 0; a < na; ++a) acc += (RESTRICT ? tab.P[a][b1] : tab.P[b1][a]) * src[a];
+            B[k] = acc;
+        }
+        __syncthreads();
+        // sweep 2 (second index): A[c][a3][b2][b1] = sum_a2 W(a2, b2) B[c][a3][a2][b1]
+        const int n2 = C * na * nb * nb;
+        for (int k = threadIdx.x; k < n2; k += kSfThreads) {
+            const int b1 = k % nb, b2 = (k / nb) % nb, rest = k / (nb * nb);  // rest = (c, a3)
+            const T* src = B + rest * na * nb + b1;
+            T acc = 0;
+            for (int a = 0; a < na; ++a) acc += (RESTRICT ? tab.P[a][b2] : tab.P[b2][a]) * src[a * nb];
+            A[k] = acc;
+        }
+        __syncthreads();
+        // sweep 3 (third index): out[c][b3][b2][b1] = sum_a3 W(a3, b3) A[c][a3][b2][b1]
+        const int nbb = nb * nb, n3 = C * nb * nbb;
+        for (int k = threadIdx.x; k < n3; k += kSfThreads) {
+            const int b12 = k % nbb, b3 = (k / nbb) % nb, c = k / (nbb * nb);
+            const T* src = A + c * na * nbb + b12;
+            T acc = 0;
+            for (int a = 0; a < na; ++a) acc += (RESTRICT ? tab.P[a][b3] : tab.P[b3][a]) * src[a * nbb];
+            if (RESTRICT) out[(long long)e * n3 + k] = acc;
+            else out[(long long)e * n3 + k] += acc;
+        }
+    }
+}
+
 template <typename T>
 __global__ void k_cheb_start_t(const T* r, T* z, T* d, const T* dinv, long long n, const SolveState* st,
                                const int* skip) {
@@ -149,8 +205,8 @@ hipError_t launch_restrict(bool mesh_step, int C, int nf, int nc, int fx, int fy
         hipLaunchKernelGGL((k_restrict<T, true>), dim3(grid_for(total)), dim3(kThreads), 0, s, C, nf, nc, fx, fy, fz,
                            tab, tf, rc, total, skip);
     else
-        hipLaunchKernelGGL((k_restrict<T, false>), dim3(grid_for(total)), dim3(kThreads), 0, s, C, nf, nc, fx, fy, fz,
-                           tab, tf, rc, total, skip);
+        hipLaunchKernelGGL((k_pstep<T, true>), dim3((unsigned)(ncell < 65535 ? ncell : 65535)), dim3(kSfThreads), 0, s,
+                           C, nf, nc, (int)ncell, tab, tf, rc, skip);
     return hipGetLastError();
 }
 
@@ -158,12 +214,13 @@ template <typename T>
 hipError_t launch_prolong_add(bool mesh_step, int C, int nf, int nc, int fx, int fy, int fz, const MgTab<T>& tab,
                               const T* zc, T* zf, const int* skip, hipStream_t s) {
     const long long total = (long long)fx * fy * fz * C * nf * nf * nf;
+    const long long ncell = (long long)fx * fy * fz;
     if (mesh_step)
         hipLaunchKernelGGL((k_prolong_add<T, true>), dim3(grid_for(total)), dim3(kThreads), 0, s, C, nf, nc, fx, fy,
                            fz, tab, zc, zf, total, skip);
     else
-        hipLaunchKernelGGL((k_prolong_add<T, false>), dim3(grid_for(total)), dim3(kThreads), 0, s, C, nf, nc, fx, fy,
-                           fz, tab, zc, zf, total, skip);
+        hipLaunchKernelGGL((k_pstep<T, false>), dim3((unsigned)(ncell < 65535 ? ncell : 65535)), dim3(kSfThreads), 0,
+                           s, C, nf, nc, (int)ncell, tab, zc, zf, skip);
     return hipGetLastError();
 }
 
