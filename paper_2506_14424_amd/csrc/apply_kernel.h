@@ -59,7 +59,12 @@ struct Shape {
     // work-space stride: skewed layout +8 (the four cells of a wavefront at
     // offsets 0, 8, 16, 24 mod 32 doubles: line tasks and lane-per-point
     // accesses of the face stages spread over all bank pairs), else +1
-    static constexpr int W = (2 * C * CS > 8 * C * NN ? 2 * C * CS : 8 * C * NN) + (SKEW ? 8 : 1);
+    // n = 4: the face stages' tangential sweeps exchange values across lanes
+    // (DPP) instead of through LDS; their only LDS array left is the
+    // projection's, so the FP64 pad shrinks to 4 and the per-lane derivative
+    // table fits in the same 20 KB
+    static constexpr bool DPP = N == 4;
+    static constexpr int W = (2 * C * CS > 8 * C * NN ? 2 * C * CS : 8 * C * NN) + (SKEW ? (DPP ? 4 : 8) : 1);
 };
 
 // Barrier between LDS stages.  A workgroup of one wavefront only needs the
@@ -143,6 +148,7 @@ __device__ __forceinline__ void inverse_from_columns(const T a[3][3], T Ji[3][3]
 
 struct CellIdx {
     int lc, t, i1, i2, ec, ex, ey, ez;
+    int rb[4];  // n = 4: b index of the lane whose value line_b delivers in slot r
     bool active;
 };
 
@@ -182,7 +188,45 @@ __device__ __forceinline__ void vol_offsets(int la, int lb, int lc, VolOff<N>& o
 template <typename T, int N>
 struct LaneTab {
     T x[N], w[N], S[2][N], G[2][N];
+    T D[N][N];  // D[q][j] = l_j'(g_q), read per lane by the cross-lane face sweeps
 };
+
+// Cross-lane moves within rows of 16 lanes (DPP).  For n = 4 a cell's 16
+// lanes are one row and lane 4 b + a holds face point (a, b), so the lines
+// of a face are a quad (along a) or the lanes 4 apart (along b).
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+
+template <int CTRL, typename T>
+__device__ __forceinline__ T dpp_mov(T v) {
+    if constexpr (sizeof(T) == 8) {
+        const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+        const unsigned lo = (unsigned)dpp_i<CTRL>((int)(unsigned)(b & 0xffffffffull));
+        const unsigned hi = (unsigned)dpp_i<CTRL>((int)(unsigned)(b >> 32));
+        return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+    } else {
+        return __builtin_bit_cast(float, dpp_i<CTRL>(__builtin_bit_cast(int, v)));
+    }
+}
+
+// The four values of a lane's line along a (quad broadcasts, index j = a')
+// and along b (own value, then rows rotated by 4, 8, 12 lanes).
+template <typename T>
+__device__ __forceinline__ void line_a(T v, T out[4]) {
+    out[0] = dpp_mov<0x00>(v);
+    out[1] = dpp_mov<0x55>(v);
+    out[2] = dpp_mov<0xAA>(v);
+    out[3] = dpp_mov<0xFF>(v);
+}
+template <typename T>
+__device__ __forceinline__ void line_b(T v, T out[4]) {
+    out[0] = v;
+    out[1] = dpp_mov<0x124>(v);
+    out[2] = dpp_mov<0x128>(v);
+    out[3] = dpp_mov<0x12C>(v);
+}
 
 // The neighbour's line of nodal values through face point (i1, i2) of face
 // (D, s), and the face viscosity and penalty factor at that point.
@@ -267,8 +311,10 @@ __device__ __forceinline__ void face_pass(const OpData<T>& op, const ApplyIO<T>&
     T* VT = sw + 2 * C * NN;  // [2] transposed sweeps                      C1 -> C2
     T* VV = sw + 6 * C * NN;  // [2] value / normal coefficients (D < 2)    C2
 
+    constexpr bool DPP = Shape<N, C, sizeof(T) == 8>::DPP;
     // ---- A: traces
     T ju[C], uno[C], unn[C];  // jump u_own - u_nbr (mirror state on Dirichlet faces), normal derivatives
+    T tv[C], tw[C];           // trace values of both sides (kept in registers for the cross-lane sweeps)
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         T v0 = 0, v1 = 0, w0 = 0, w1 = 0;
@@ -286,17 +332,23 @@ __device__ __forceinline__ void face_pass(const OpData<T>& op, const ApplyIO<T>&
         ju[c] = has_nb ? v0 - w0 : T(2) * v0;
         uno[c] = v1;
         unn[c] = w1;
-        FT[c * NN + t] = v0;
-        FT[(C + c) * NN + t] = w0;
+        tv[c] = v0;
+        tw[c] = w0;
+        if constexpr (!DPP) {
+            FT[c * NN + t] = v0;
+            FT[(C + c) * NN + t] = w0;
+        }
     }
     if constexpr (CURVED) {
         if (t < 3)
 #pragma unroll
             for (int k = 0; k < 8; ++k) geo[1][k][t] = gnb[k];
     }
-    stage_sync<THREADS>();
+    if constexpr (CURVED || !DPP) stage_sync<THREADS>();
 
     // ---- B1: tangential derivatives; task k = ((side*2 + dir)*C + c)*N + line
+    // (n = 4: computed per lane from cross-lane moves at the start of B2)
+    if constexpr (!DPP)
 #pragma unroll
     for (int k0 = 0; k0 < 4 * C * N; k0 += NN) {
         const int k = k0 + t;
@@ -318,7 +370,7 @@ __device__ __forceinline__ void face_pass(const OpData<T>& op, const ApplyIO<T>&
             }
         }
     }
-    stage_sync<THREADS>();
+    if constexpr (!DPP) stage_sync<THREADS>();
 
     // ---- B2: geometry and flux at the face point
     //
@@ -381,11 +433,39 @@ __device__ __forceinline__ void face_pass(const OpData<T>& op, const ApplyIO<T>&
     // gs = gr + gr' M: reference gradient of both sides in the own frame
     // (Dirichlet mirror: grad u+ = grad u-, so gs = 2 gr)
     T gs[C][3];
+    T da[DPP ? 4 : 1], db[DPP ? 4 : 1];  // n = 4: this lane's rows of D along a and b
+    if constexpr (DPP) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            da[j] = lt.D[i1][j];
+            db[j] = lt.D[i2][ci.rb[j]];
+        }
+    }
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-        const T o1 = TD[(0 * C + c) * NN + t], o2 = TD[(1 * C + c) * NN + t];
+        // tangential derivatives of both traces (own: o1, o2; neighbour: n1, n2)
+        T o1, o2, n1, n2;
+        if constexpr (DPP) {
+            T la[4], lb[4], ma[4], mb[4];
+            line_a(tv[c], la);
+            line_b(tv[c], lb);
+            line_a(tw[c], ma);
+            line_b(tw[c], mb);
+            o1 = o2 = n1 = n2 = T(0);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                o1 += da[j] * la[j];
+                o2 += db[j] * lb[j];
+                n1 += da[j] * ma[j];
+                n2 += db[j] * mb[j];
+            }
+        } else {
+            o1 = TD[(0 * C + c) * NN + t];
+            o2 = TD[(1 * C + c) * NN + t];
+            n1 = TD[(2 * C + c) * NN + t];
+            n2 = TD[(3 * C + c) * NN + t];
+        }
         if (has_nb) {
-            const T n1 = TD[(2 * C + c) * NN + t], n2 = TD[(3 * C + c) * NN + t];
             gs[c][t1] = o1 + n1;
             gs[c][t2] = o2 + n2;
             if constexpr (CURVED) {
@@ -446,6 +526,29 @@ __device__ __forceinline__ void face_pass(const OpData<T>& op, const ApplyIO<T>&
 #pragma unroll
         for (int d = 0; d < 3; ++d) Bh[0][d] = hb * mo[d];
     }
+    T vt[2][C];  // transposed tangential sweeps of the flux at this lane's point
+    if constexpr (DPP) {
+        T dat[4], dbt[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            dat[j] = lt.D[j][i1];
+            dbt[j] = lt.D[ci.rb[j]][i2];
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            T la[4], lb[4];
+            line_a(Bh[c][t1], la);
+            line_b(Bh[c][t2], lb);
+            T a1 = 0, a2 = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                a1 += dat[j] * la[j];
+                a2 += dbt[j] * lb[j];
+            }
+            vt[0][c] = a1;
+            vt[1][c] = a2;
+        }
+    } else {
     stage_sync<THREADS>();  // TD reads done before BT/VT overwrite the space
 #pragma unroll
     for (int c = 0; c < C; ++c) {
@@ -477,12 +580,18 @@ __device__ __forceinline__ void face_pass(const OpData<T>& op, const ApplyIO<T>&
         }
     }
     stage_sync<THREADS>();
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        vt[0][c] = VT[c * NN + t];
+        vt[1][c] = VT[(C + c) * NN + t];
+    }
+    }
 
     // ---- C2: projection onto the nodes
     T vv[C], vn[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-        vv[c] = av[c] + VT[c * NN + t] + VT[(C + c) * NN + t];
+        vv[c] = av[c] + vt[0][c] + vt[1][c];
         vn[c] = Bh[c][D];
     }
     if (D == 2) {
@@ -667,6 +776,16 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
         s_lt.S[1][j] = tb.S[1][j];
         s_lt.G[0][j] = tb.G[0][j];
         s_lt.G[1][j] = tb.G[1][j];
+#pragma unroll
+        for (int q = 0; q < N; ++q) s_lt.D[q][j] = tb.D[q][j];
+    }
+    if constexpr (Sh::DPP) {
+        // which b each rotation of line_b delivers, read off the lane index
+        // itself (no assumption on the rotation's direction)
+        ci.rb[0] = i2;
+        ci.rb[1] = dpp_i<0x124>(t) / N;
+        ci.rb[2] = dpp_i<0x128>(t) / N;
+        ci.rb[3] = dpp_i<0x12C>(t) / N;
     }
 
     // ------------------------------------------------------------ load; xi_3 derivative of the own line
