@@ -194,9 +194,11 @@ struct LaneTab {
 // Cross-lane moves within rows of 16 lanes (DPP).  For n = 4 a cell's 16
 // lanes are one row and lane 4 b + a holds face point (a, b), so the lines
 // of a face are a quad (along a) or the lanes 4 apart (along b).
+// (quad permutations and row rotations read a valid lane everywhere, so
+// no "old" value has to be kept: bound_ctrl lets the move write directly)
 template <int CTRL>
 __device__ __forceinline__ int dpp_i(int v) {
-    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, true);
 }
 
 template <int CTRL, typename T>
