@@ -148,7 +148,7 @@ __device__ __forceinline__ void inverse_from_columns(const T a[3][3], T Ji[3][3]
 
 struct CellIdx {
     int lc, t, i1, i2, ec, ex, ey, ez;
-    int rb[4];  // n = 4: b index of the lane whose value line_b delivers in slot r
+    int ra[4], rb[4];  // n = 4: a / b index of the lane whose value line_a / line_b delivers in slot r
     bool active;
 };
 
@@ -213,14 +213,15 @@ __device__ __forceinline__ T dpp_mov(T v) {
     }
 }
 
-// The four values of a lane's line along a (quad broadcasts, index j = a')
-// and along b (own value, then rows rotated by 4, 8, 12 lanes).
+// The four values of a lane's line along a (own value, then the quad
+// rotated so that slot r holds a' = (a + r) mod 4) and along b (own value,
+// then rows rotated by 4, 8, 12 lanes; slot r holds b' = CellIdx::rb[r]).
 template <typename T>
 __device__ __forceinline__ void line_a(T v, T out[4]) {
-    out[0] = dpp_mov<0x00>(v);
-    out[1] = dpp_mov<0x55>(v);
-    out[2] = dpp_mov<0xAA>(v);
-    out[3] = dpp_mov<0xFF>(v);
+    out[0] = v;
+    out[1] = dpp_mov<0x39>(v);  // quad_perm [1, 2, 3, 0]
+    out[2] = dpp_mov<0x4E>(v);  // quad_perm [2, 3, 0, 1]
+    out[3] = dpp_mov<0x93>(v);  // quad_perm [3, 0, 1, 2]
 }
 template <typename T>
 __device__ __forceinline__ void line_b(T v, T out[4]) {
@@ -439,7 +440,7 @@ __device__ __forceinline__ void face_pass(const OpData<T>& op, const ApplyIO<T>&
     if constexpr (DPP) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            da[j] = lt.D[i1][j];
+            da[j] = lt.D[i1][ci.ra[j]];
             db[j] = lt.D[i2][ci.rb[j]];
         }
     }
@@ -533,7 +534,7 @@ __device__ __forceinline__ void face_pass(const OpData<T>& op, const ApplyIO<T>&
         T dat[4], dbt[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            dat[j] = lt.D[j][i1];
+            dat[j] = lt.D[ci.ra[j]][i1];
             dbt[j] = lt.D[ci.rb[j]][i2];
         }
 #pragma unroll
@@ -788,6 +789,10 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
         ci.rb[1] = dpp_i<0x124>(t) / N;
         ci.rb[2] = dpp_i<0x128>(t) / N;
         ci.rb[3] = dpp_i<0x12C>(t) / N;
+        ci.ra[0] = i1;
+        ci.ra[1] = dpp_i<0x39>(t) % N;
+        ci.ra[2] = dpp_i<0x4E>(t) % N;
+        ci.ra[3] = dpp_i<0x93>(t) % N;
     }
 
     // ------------------------------------------------------------ load; xi_3 derivative of the own line
