@@ -37,8 +37,11 @@ namespace sipg {
 
 template <int N, int C, bool DBL>
 struct Shape {
-    // cells per workgroup: one wavefront for n <= 4, LDS well under 64 KB
-    static constexpr int CPB = N == 2 ? 16 : N == 3 ? 7 : N == 4 ? 4 : N == 5 ? 5 : (DBL && C == 3 ? 3 : 7);
+    // cells per workgroup: one wavefront for n <= 4 and for FP64 n = 5 (two
+    // cells, 50 lanes: wavefront fences instead of workgroup barriers beat
+    // the idle lanes there; FP32 n = 5 keeps five cells in two wavefronts),
+    // LDS well under 64 KB
+    static constexpr int CPB = N == 2 ? 16 : N == 3 ? 7 : N == 4 ? 4 : N == 5 ? (DBL ? 2 : 5) : (DBL && C == 3 ? 3 : 7);
     static constexpr int THREADS = CPB * N * N;
     static constexpr int NNN = N * N * N, NN = N * N;
     // LDS layout of a cell's volume arrays: node (i1, i2, i3) of component c at
