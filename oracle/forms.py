@@ -97,11 +97,28 @@ class Problem:
 # geometry
 # ---------------------------------------------------------------------------
 
-def cell_sizes(pb: Problem) -> np.ndarray:
-    """h_e = (int_e 1 dx)^(1/3); the n-point rule is exact for trilinear cells."""
+def cell_sizes(pb: Problem, cells=None) -> np.ndarray:
+    """h_e = (int_e 1 dx)^(1/3); the n-point rule is exact for trilinear cells.
+    With `cells` given only those entries are computed (the others are NaN)."""
     pts, w = cell_points(pb.n)
-    J = pb.mesh.jacobian(np.arange(pb.mesh.ncells), pts)
-    return (np.linalg.det(J) @ w) ** (1.0 / 3.0)
+    if cells is None:
+        J = pb.mesh.jacobian(np.arange(pb.mesh.ncells), pts)
+        return (np.linalg.det(J) @ w) ** (1.0 / 3.0)
+    cells = np.unique(np.asarray(cells))
+    h = np.full(pb.mesh.ncells, np.nan)
+    h[cells] = (np.linalg.det(pb.mesh.jacobian(cells, pts)) @ w) ** (1.0 / 3.0)
+    return h
+
+
+def _with_neighbours(mesh, cells) -> np.ndarray:
+    """The cells and the (up to six) cells sharing a face with them."""
+    ex, ey, ez = mesh.cell_ijk(np.asarray(cells))
+    out = [np.asarray(cells)]
+    for d, (lim, stride) in enumerate(((mesh.nx, 1), (mesh.ny, mesh.nx), (mesh.nz, mesh.nx * mesh.ny))):
+        pos = (ex, ey, ez)[d]
+        out.append(np.asarray(cells)[pos > 0] - stride)
+        out.append(np.asarray(cells)[pos < lim - 1] + stride)
+    return np.unique(np.concatenate(out))
 
 
 def _cell_geo(pb: Problem, cells):
@@ -367,7 +384,7 @@ def apply(pb: Problem, x: np.ndarray, parts=PARTS_ALL, batch: int = 4096, cells=
     mesh, n, C = pb.mesh, pb.n, pb.C
     X = np.asarray(x, dtype=np.float64).reshape(mesh.ncells, C, n ** 3)
     Y = np.zeros_like(X)
-    h = cell_sizes(pb)
+    h = cell_sizes(pb) if cells is None else cell_sizes(pb, _with_neighbours(mesh, cells))
     sel = np.ones(mesh.ncells, dtype=bool)
     if cells is not None:
         sel[:] = False
