@@ -211,3 +211,40 @@ def test_full_size_properties(name):
         one = torch.ones(op.ndof, dtype=torch.float64, device="cuda")
         A1 = op.apply(one)
         assert float(A1.abs().max()) <= 1e-12 * float(Au.abs().max())
+
+
+def test_max_size_sampled_cells():
+    """Near the library's indexing limit (ndof < 2^31): 192^3 curved cells
+    at k = 3, 1,358,954,496 unknowns (10.9 GB per FP64 vector), 32 sampled
+    cells (corners, the last cell, random) evaluated by the oracle one by
+    one, FP64 and FP32."""
+    n = 192
+    cfg = W.config("c2", n)
+    V = W.box_vertices(n, n, n, cfg["perturb"])
+    ndof = W.ndofs(cfg)
+    assert 2 ** 30 < ndof < 2 ** 31 - 1
+    free, _ = torch.cuda.mem_get_info()
+    if free < 80 * 2 ** 30:
+        pytest.skip(f"needs ~60 GB of device memory, {free / 2 ** 30:.0f} GB free")
+    say(f"[max size] {n}^3 k=3: {ndof} DoFs")
+    op = Operator.from_config(cfg, V).bind(with_solver=False)
+    x = W.uniform_vector(cfg["x_seed"], ndof)
+    xt = torch.from_numpy(x).cuda()
+    y = op.apply(xt).cpu().numpy()
+    y32 = op.apply(xt.float()).cpu().numpy()
+    torch.cuda.synchronize()
+    say("   applied")
+    pb = Problem.from_config(cfg, V)
+    nc = pb.mesh.ncells
+    rng = np.random.default_rng(3)
+    cells = np.unique(np.concatenate([[0, n - 1, nc - n, nc - 1, nc // 2], rng.integers(0, nc, 27)]))
+    nl = pb.nloc
+    ref = oracle_apply(pb, x, cells=cells).reshape(nc, nl)[cells]
+    e = rel_err(y.reshape(nc, nl)[cells], ref)
+    say(f"   fp64 sampled err={e:.3e}")
+    assert e <= TOL64
+    x32 = x.astype(np.float32).astype(np.float64)
+    ref32 = oracle_apply(pb, x32, cells=cells).reshape(nc, nl)[cells]
+    e32 = rel_err(y32.astype(np.float64).reshape(nc, nl)[cells], ref32)
+    say(f"   fp32 sampled err={e32:.3e}")
+    assert e32 <= TOL32
