@@ -429,6 +429,7 @@ sipg_status run_lanczos(sipg_plan* P, hipStream_t s) {
         sk_lz_next(vprev, w, n, P->st, s);   // vprev <- w / beta
         std::swap(v, vprev);                 // (vprev, v) <- (v, w/beta)
     }
+    sk_lz_eig(P->st, s);
     HIP_TRY(hipGetLastError());
     P->lz_valid = true;
     P->lz_steps = P->opts.lanczos_steps;
@@ -527,7 +528,7 @@ sipg_status prepare_precond(sipg_plan* P, hipStream_t s) {
             if (rc != SIPG_OK) return rc;
         }
         const int deg = (mg && l == nl - 1) ? P->mg_opts.coarse_degree : o.cheb_degree;
-        sk_lz_finish(L->st, o.cheb_safety, o.cheb_ratio, deg, s);
+        sk_lz_coef(L->st, o.cheb_safety, o.cheb_ratio, deg, s);
     }
     HIP_TRY(hipGetLastError());
     return SIPG_OK;

@@ -108,40 +108,76 @@ __global__ void k_lz_next(double* vnew, const double* w, long long n, const Solv
 // and the coefficients of the three-term recurrence (Saad, Alg. 12.1):
 // theta = (hi+lo)/2, delta = (hi-lo)/2, sigma = theta/delta, rho_0 = 1/sigma,
 // rho_j = 1/(2 sigma - rho_{j-1}), c1_j = rho_j rho_{j-1}, c2_j = 2 rho_j / delta.
-__global__ void k_lz_finish(SolveState* st, double safety, double ratio, int degree) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// The largest eigenvalue of the Lanczos tridiagonal by Sturm counts, with
+// the bracket [lo, hi] (count(lo) < m <= count(hi), Gershgorin start)
+// narrowed by multisection: the 64 lanes of one wavefront each count at one
+// of 64 interior points, the bracket shrinks 65-fold per round, until its
+// width is below 1e-15 |hi|; lambda = hi.
+constexpr int kEigLanes = 64;
+
+__global__ void __launch_bounds__(kEigLanes) k_lz_eig(SolveState* st) {
+    __shared__ double sa[64], sb2[64];
+    __shared__ int cnt[kEigLanes];
+    __shared__ double br[2];
     const int m = st->lz_m;
-    double lam;
+    const int l = threadIdx.x;
     if (m <= 0) {
-        lam = 1.0;
-    } else {
+        if (l == 0) st->lam_max = 1.0;
+        return;
+    }
+    if (l < m) {
+        sa[l] = st->lz_alpha[l];
+        sb2[l] = l > 0 ? st->lz_beta[l] * st->lz_beta[l] : 0.0;
+    }
+    if (l == 0) {
         double lo = 1e300, hi = -1e300;
         for (int i = 0; i < m; ++i) {
             const double r = (i > 0 ? fabs(st->lz_beta[i]) : 0.0) + (i + 1 < m ? fabs(st->lz_beta[i + 1]) : 0.0);
             lo = fmin(lo, st->lz_alpha[i] - r);
             hi = fmax(hi, st->lz_alpha[i] + r);
         }
-        // count(x) = number of eigenvalues < x
-        auto count = [&](double x) {
-            int cnt = 0;
-            double q = 1.0;
-            for (int i = 0; i < m; ++i) {
-                const double b2 = i > 0 ? st->lz_beta[i] * st->lz_beta[i] : 0.0;
-                q = st->lz_alpha[i] - x - (i > 0 ? b2 / q : 0.0);
-                if (q == 0.0) q = -1e-300;
-                if (q < 0.0) ++cnt;
-            }
-            return cnt;
-        };
-        hi += 1e-12 * fabs(hi) + 1e-300;
-        for (int it = 0; it < 200 && hi - lo > 1e-15 * fabs(hi); ++it) {
-            const double mid = 0.5 * (lo + hi);
-            if (count(mid) >= m) hi = mid;  // all eigenvalues below mid
-            else lo = mid;
-        }
-        lam = hi;
+        br[0] = lo;
+        br[1] = hi + (1e-12 * fabs(hi) + 1e-300);
     }
-    st->lam_max = lam;
+    __syncthreads();
+    for (int round = 0; round < 40; ++round) {
+        const double lo = br[0], hi = br[1];
+        if (!(hi - lo > 1e-15 * fabs(hi))) break;  // uniform: every lane reads the same bracket
+        const double x = lo + (hi - lo) * (double)(l + 1) / (double)(kEigLanes + 1);
+        int c = 0;
+        double q = 1.0;
+        for (int i = 0; i < m; ++i) {
+            q = sa[i] - x - (i > 0 ? sb2[i] / q : 0.0);
+            if (q == 0.0) q = -1e-300;
+            if (q < 0.0) ++c;
+        }
+        cnt[l] = c;
+        __syncthreads();
+        if (l == 0) {
+            // first point with every eigenvalue below it
+            int k = kEigLanes;
+            for (int j = 0; j < kEigLanes; ++j)
+                if (cnt[j] >= m) { k = j; break; }
+            const double w = hi - lo;
+            const double nlo = k == 0 ? lo : lo + w * (double)k / (double)(kEigLanes + 1);
+            const double nhi = k == kEigLanes ? hi : lo + w * (double)(k + 1) / (double)(kEigLanes + 1);
+            br[0] = nlo;
+            br[1] = nhi;
+        }
+        __syncthreads();
+    }
+    if (l == 0) st->lam_max = br[1];
+}
+
+// Chebyshev interval and coefficients from the cached estimate (cheap; once
+// per solve and level): lambda_hi = safety * lambda, lambda_lo =
+// lambda_hi / ratio, and the coefficients of the three-term recurrence
+// (Saad, Alg. 12.1): theta = (hi+lo)/2, delta = (hi-lo)/2, sigma =
+// theta/delta, rho_0 = 1/sigma, rho_j = 1/(2 sigma - rho_{j-1}),
+// c1_j = rho_j rho_{j-1}, c2_j = 2 rho_j / delta.
+__global__ void k_lz_coef(SolveState* st, double safety, double ratio, int degree) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double lam = st->lam_max;
     const double lhi = safety * lam, llo = lhi / ratio;
     const double theta = 0.5 * (lhi + llo), delta = 0.5 * (lhi - llo);
     const double sigma = theta / delta;
@@ -451,8 +487,11 @@ void sk_lz_orth(double* w, const double* v, const double* vprev, long long n, co
 void sk_lz_next(double* vnew, const double* w, long long n, const SolveState* st, hipStream_t s) {
     L(k_lz_next, vnew, w, n, st);
 }
-void sk_lz_finish(SolveState* st, double safety, double ratio, int degree, hipStream_t s) {
-    hipLaunchKernelGGL(k_lz_finish, dim3(1), dim3(1), 0, s, st, safety, ratio, degree);
+void sk_lz_eig(SolveState* st, hipStream_t s) {
+    hipLaunchKernelGGL(k_lz_eig, dim3(1), dim3(kEigLanes), 0, s, st);
+}
+void sk_lz_coef(SolveState* st, double safety, double ratio, int degree, hipStream_t s) {
+    hipLaunchKernelGGL(k_lz_coef, dim3(1), dim3(1), 0, s, st, safety, ratio, degree);
 }
 void sk_scalar(SolveState* st, const double* partials, int nslots, int op, long long n, hipStream_t s,
                int respect_skip) {

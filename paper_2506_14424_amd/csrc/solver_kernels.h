@@ -16,7 +16,8 @@ void sk_lz_post(double* w, const double* v, const double* dinv, long long n, dou
 void sk_lz_orth(double* w, const double* v, const double* vprev, long long n, const SolveState* st,
                 double* partials, hipStream_t s);
 void sk_lz_next(double* vnew, const double* w, long long n, const SolveState* st, hipStream_t s);
-void sk_lz_finish(SolveState* st, double safety, double ratio, int degree, hipStream_t s);
+void sk_lz_eig(SolveState* st, hipStream_t s);   // lambda_max of the Lanczos tridiagonal
+void sk_lz_coef(SolveState* st, double safety, double ratio, int degree, hipStream_t s);  // Chebyshev coefficients
 void sk_scalar(SolveState* st, const double* partials, int nslots, int op, long long n, hipStream_t s,
                int respect_skip = 0);
 void sk_sum(const double* x, long long n, double* partials, const SolveState* st, hipStream_t s);
