@@ -66,7 +66,7 @@ struct Shape {
     // (DPP) instead of through LDS; their only LDS array left is the
     // projection's, so the FP64 pad shrinks to 4 and the per-lane derivative
     // table fits in the same 20 KB
-    static constexpr bool DPP = N == 4;
+    static constexpr bool DPP = N == 4 || N == 2;
     static constexpr int W = (2 * C * CS > 8 * C * NN ? 2 * C * CS : 8 * C * NN) + (SKEW ? (DPP ? 4 : 8) : 1);
 };
 
@@ -216,22 +216,32 @@ __device__ __forceinline__ T dpp_mov(T v) {
     }
 }
 
-// The four values of a lane's line along a (own value, then the quad
-// rotated so that slot r holds a' = (a + r) mod 4) and along b (own value,
-// then rows rotated by 4, 8, 12 lanes; slot r holds b' = CellIdx::rb[r]).
-template <typename T>
-__device__ __forceinline__ void line_a(T v, T out[4]) {
+// The n values of a lane's line along a (own value, then the quad
+// permuted so that slot r holds a' = CellIdx::ra[r]) and along b (own value,
+// then, for n = 4, rows rotated by 4, 8, 12 lanes; for n = 2 the other pair
+// of the quad; slot r holds b' = CellIdx::rb[r]).  n = 4: a cell is a row of
+// 16 lanes; n = 2: a cell is a quad, lane 2 b + a.
+template <int N, typename T>
+__device__ __forceinline__ void line_a(T v, T out[N]) {
     out[0] = v;
-    out[1] = dpp_mov<0x39>(v);  // quad_perm [1, 2, 3, 0]
-    out[2] = dpp_mov<0x4E>(v);  // quad_perm [2, 3, 0, 1]
-    out[3] = dpp_mov<0x93>(v);  // quad_perm [3, 0, 1, 2]
+    if constexpr (N == 4) {
+        out[1] = dpp_mov<0x39>(v);  // quad_perm [1, 2, 3, 0]
+        out[2] = dpp_mov<0x4E>(v);  // quad_perm [2, 3, 0, 1]
+        out[3] = dpp_mov<0x93>(v);  // quad_perm [3, 0, 1, 2]
+    } else {
+        out[1] = dpp_mov<0xB1>(v);  // quad_perm [1, 0, 3, 2]
+    }
 }
-template <typename T>
-__device__ __forceinline__ void line_b(T v, T out[4]) {
+template <int N, typename T>
+__device__ __forceinline__ void line_b(T v, T out[N]) {
     out[0] = v;
-    out[1] = dpp_mov<0x124>(v);
-    out[2] = dpp_mov<0x128>(v);
-    out[3] = dpp_mov<0x12C>(v);
+    if constexpr (N == 4) {
+        out[1] = dpp_mov<0x124>(v);  // row_ror:4
+        out[2] = dpp_mov<0x128>(v);  // row_ror:8
+        out[3] = dpp_mov<0x12C>(v);  // row_ror:12
+    } else {
+        out[1] = dpp_mov<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+    }
 }
 
 // The neighbour's line of nodal values through face point (i1, i2) of face
@@ -439,10 +449,10 @@ __device__ __forceinline__ void face_pass(const OpData<T>& op, const ApplyIO<T>&
     // gs = gr + gr' M: reference gradient of both sides in the own frame
     // (Dirichlet mirror: grad u+ = grad u-, so gs = 2 gr)
     T gs[C][3];
-    T da[DPP ? 4 : 1], db[DPP ? 4 : 1];  // n = 4: this lane's rows of D along a and b
+    T da[DPP ? N : 1], db[DPP ? N : 1];  // this lane's rows of D along a and b (cross-lane sweeps)
     if constexpr (DPP) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < N; ++j) {
             da[j] = lt.D[i1][ci.ra[j]];
             db[j] = lt.D[i2][ci.rb[j]];
         }
@@ -452,14 +462,14 @@ __device__ __forceinline__ void face_pass(const OpData<T>& op, const ApplyIO<T>&
         // tangential derivatives of both traces (own: o1, o2; neighbour: n1, n2)
         T o1, o2, n1, n2;
         if constexpr (DPP) {
-            T la[4], lb[4], ma[4], mb[4];
-            line_a(tv[c], la);
-            line_b(tv[c], lb);
-            line_a(tw[c], ma);
-            line_b(tw[c], mb);
+            T la[N], lb[N], ma[N], mb[N];
+            line_a<N>(tv[c], la);
+            line_b<N>(tv[c], lb);
+            line_a<N>(tw[c], ma);
+            line_b<N>(tw[c], mb);
             o1 = o2 = n1 = n2 = T(0);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
+            for (int j = 0; j < N; ++j) {
                 o1 += da[j] * la[j];
                 o2 += db[j] * lb[j];
                 n1 += da[j] * ma[j];
@@ -534,20 +544,20 @@ __device__ __forceinline__ void face_pass(const OpData<T>& op, const ApplyIO<T>&
     }
     T vt[2][C];  // transposed tangential sweeps of the flux at this lane's point
     if constexpr (DPP) {
-        T dat[4], dbt[4];
+        T dat[N], dbt[N];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < N; ++j) {
             dat[j] = lt.D[ci.ra[j]][i1];
             dbt[j] = lt.D[ci.rb[j]][i2];
         }
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            T la[4], lb[4];
-            line_a(Bh[c][t1], la);
-            line_b(Bh[c][t2], lb);
+            T la[N], lb[N];
+            line_a<N>(Bh[c][t1], la);
+            line_b<N>(Bh[c][t2], lb);
             T a1 = 0, a2 = 0;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
+            for (int j = 0; j < N; ++j) {
                 a1 += dat[j] * la[j];
                 a2 += dbt[j] * lb[j];
             }
@@ -786,16 +796,21 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
         for (int q = 0; q < N; ++q) s_lt.D[q][j] = tb.D[q][j];
     }
     if constexpr (Sh::DPP) {
-        // which b each rotation of line_b delivers, read off the lane index
-        // itself (no assumption on the rotation's direction)
-        ci.rb[0] = i2;
-        ci.rb[1] = dpp_i<0x124>(t) / N;
-        ci.rb[2] = dpp_i<0x128>(t) / N;
-        ci.rb[3] = dpp_i<0x12C>(t) / N;
+        // which a / b each slot of line_a / line_b delivers, read off the lane
+        // index itself (no assumption on the direction of a rotation)
         ci.ra[0] = i1;
-        ci.ra[1] = dpp_i<0x39>(t) % N;
-        ci.ra[2] = dpp_i<0x4E>(t) % N;
-        ci.ra[3] = dpp_i<0x93>(t) % N;
+        ci.rb[0] = i2;
+        if constexpr (N == 4) {
+            ci.rb[1] = dpp_i<0x124>(t) / N;
+            ci.rb[2] = dpp_i<0x128>(t) / N;
+            ci.rb[3] = dpp_i<0x12C>(t) / N;
+            ci.ra[1] = dpp_i<0x39>(t) % N;
+            ci.ra[2] = dpp_i<0x4E>(t) % N;
+            ci.ra[3] = dpp_i<0x93>(t) % N;
+        } else {
+            ci.ra[1] = dpp_i<0xB1>(t) % N;
+            ci.rb[1] = dpp_i<0x4E>(t) / N;
+        }
     }
 
     // ------------------------------------------------------------ load; xi_3 derivative of the own line
