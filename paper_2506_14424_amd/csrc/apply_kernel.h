@@ -741,6 +741,123 @@ __device__ __forceinline__ void face_pass_pen(const OpData<T>& op, const ApplyIO
     stage_sync<THREADS>();
 }
 
+// Cell term for n = 2 by slices xi_3 = const: the xi_1 and xi_2 derivatives
+// of the own node come from cross-lane moves within the cell's quad, the
+// stress is formed pointwise, and its xi_1 / xi_2 test-function sweeps go
+// back across the lanes the same way; the xi_3 direction stays in the
+// lane's registers (g3).  No LDS stores and no fences.  (For n = 4 the
+// moves cost more than the LDS stages they replace.)
+template <int N, int C, typename T, bool CURVED, bool PEN>
+__device__ __forceinline__ void cell_pass_dpp(const OpData<T>& op, const CellIdx& ci, const T* su, T (*geo)[8][3],
+                                              const LaneTab<T, N>& lt, const VolOff<N>& vo, T (&g3)[C][N],
+                                              const T (&muq)[N], T (&y)[C][N]) {
+    constexpr int CS = Shape<N, C, sizeof(T) == 8>::CS;
+    const auto& tb = op.tab;
+    const int i1 = ci.i1, i2 = ci.i2;
+    T da[N], db[N], dat[N], dbt[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        da[j] = lt.D[i1][ci.ra[j]];
+        db[j] = lt.D[i2][ci.rb[j]];
+        dat[j] = lt.D[ci.ra[j]][i1];
+        dbt[j] = lt.D[ci.rb[j]][i2];
+    }
+    // along the own xi_3 line the Jacobian columns of a trilinear cell are
+    // a_0 = A0 + B0 xi_3, a_1 = A1 + B1 xi_3 and a_2 constant
+    T A0[3], B0[3], A1[3], B1[3], a2c[3];
+    if constexpr (CURVED) {
+        const T(*g)[3] = geo[0];
+        const T x1 = lt.x[i1], x2 = lt.x[i2];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            A0[i] = g[1][i] + g[4][i] * x2;
+            B0[i] = g[5][i] + g[7][i] * x2;
+            A1[i] = g[2][i] + g[4][i] * x1;
+            B1[i] = g[6][i] + g[7][i] * x1;
+            a2c[i] = g[3][i] + g[5][i] * x1 + g[6][i] * x2 + g[7][i] * (x1 * x2);
+        }
+    }
+#pragma unroll
+    for (int q3 = 0; q3 < N; ++q3) {
+        T Ji[3][3], JxW;
+        if constexpr (CURVED) {
+            const T x3 = tb.x[q3];
+            T a[3][3], det;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                a[0][i] = A0[i] + B0[i] * x3;
+                a[1][i] = A1[i] + B1[i] * x3;
+                a[2][i] = a2c[i];
+            }
+            inverse_from_columns(a, Ji, det);
+            JxW = det * (lt.w[i1] * lt.w[i2] * tb.w[q3]);
+        } else {
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) Ji[a][b] = a == b ? op.hinv[a] : T(0);
+            JxW = op.h[0] * op.h[1] * op.h[2] * (lt.w[i1] * lt.w[i2] * tb.w[q3]);
+        }
+        T u[C], G[C][3];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            u[c] = su[c * CS + vo.oz[q3]];
+            T la[N], lb[N];
+            line_a<N>(u[c], la);
+            line_b<N>(u[c], lb);
+            T g1 = 0, g2 = 0;
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                g1 += da[j] * la[j];
+                g2 += db[j] * lb[j];
+            }
+            const T gg3 = g3[c][q3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) G[c][i] = g1 * Ji[0][i] + g2 * Ji[1][i] + gg3 * Ji[2][i];
+        }
+        T S[C][3];
+        if constexpr (PEN) {
+            const T dv = muq[q3] * JxW * (G[0][0] + G[1][1] + G[2][2]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int i = 0; i < 3; ++i) S[c][i] = c == i ? dv : T(0);
+        } else if constexpr (C == 3) {
+            const T f = muq[q3] * JxW;
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int i = 0; i < 3; ++i) S[c][i] = f * (G[c][i] + G[i][c]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) S[0][i] = JxW * G[0][i];
+        }
+        const T mass = op.alpha * JxW;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const T b1 = Ji[0][0] * S[c][0] + Ji[0][1] * S[c][1] + Ji[0][2] * S[c][2];
+            const T b2 = Ji[1][0] * S[c][0] + Ji[1][1] * S[c][1] + Ji[1][2] * S[c][2];
+            g3[c][q3] = Ji[2][0] * S[c][0] + Ji[2][1] * S[c][1] + Ji[2][2] * S[c][2];
+            T la[N], lb[N];
+            line_a<N>(b1, la);
+            line_b<N>(b2, lb);
+            T acc = mass * u[c];
+#pragma unroll
+            for (int j = 0; j < N; ++j) acc += dat[j] * la[j] + dbt[j] * lb[j];
+            y[c][q3] = acc;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int i3 = 0; i3 < N; ++i3) {
+            T acc = y[c][i3];
+#pragma unroll
+            for (int q = 0; q < N; ++q) acc += tb.D[q][i3] * g3[c][q];
+            y[c][i3] = acc;
+        }
+}
+
 // ---------------------------------------------------------------- kernel
 
 template <int N, int C, typename T, bool CURVED, int MODE, bool PEN>
@@ -857,7 +974,9 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
         for (int j = 0; j < N; ++j) y[c][j] = T(0);
 
     // ------------------------------------------------------------ cell
-    if (io.parts & SIPG_PART_CELL) {
+    if constexpr (N == 2) {
+        if (io.parts & SIPG_PART_CELL) cell_pass_dpp<N, C, T, CURVED, PEN>(op, ci, su, geo, lt, vo, g3, muq, y);
+    } else if (io.parts & SIPG_PART_CELL) {
         T* W1 = sw;            // [C][NNN] d/dxi_1, then B^_1
         T* W2 = sw + C * CS;  // [C][NNN] d/dxi_2, then B^_2
         // forward sweeps along xi_1 and xi_2
