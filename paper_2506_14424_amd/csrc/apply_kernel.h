@@ -67,7 +67,10 @@ struct Shape {
     // projection's, so the FP64 pad shrinks to 4 and the per-lane derivative
     // table fits in the same 20 KB
     static constexpr bool DPP = N == 4 || N == 2;
-    static constexpr int W = (2 * C * CS > 8 * C * NN ? 2 * C * CS : 8 * C * NN) + (SKEW ? (DPP ? 4 : 8) : 1);
+    // n = 2 (cell and face passes across lanes): only the projection's
+    // coefficient array remains, so the work space shrinks to that
+    static constexpr int W = N == 2 ? 2 * C * NN + 1
+                                    : (2 * C * CS > 8 * C * NN ? 2 * C * CS : 8 * C * NN) + (SKEW ? (DPP ? 4 : 8) : 1);
 };
 
 // Barrier between LDS stages.  A workgroup of one wavefront only needs the
@@ -320,14 +323,14 @@ __device__ __forceinline__ void face_pass(const OpData<T>& op, const ApplyIO<T>&
     if (D == 0) fid = (ci.ez * op.ny + ci.ey) * (op.nx + 1) + ci.ex + s;
     else if (D == 1) fid = op.nfx + (ci.ez * (op.ny + 1) + ci.ey + s) * op.nx + ci.ex;
     else fid = op.nfx + op.nfy + ((ci.ez + s) * op.ny + ci.ey) * op.nx + ci.ex;
+    constexpr bool DPP = Shape<N, C, sizeof(T) == 8>::DPP;
     // LDS regions of the work space, each [.][C][NN]
     T* FT = sw;               // [2] trace values (own, neighbour)          A  -> B1
     T* TD = sw + 2 * C * NN;  // [2][2] tangential derivatives (side, dir)  B1 -> B2
     T* BT = sw;               // [2] flux components along t1, t2           B2 -> C1
     T* VT = sw + 2 * C * NN;  // [2] transposed sweeps                      C1 -> C2
-    T* VV = sw + 6 * C * NN;  // [2] value / normal coefficients (D < 2)    C2
+    T* VV = sw + (DPP ? 0 : 6 * C * NN);  // [2] value / normal coefficients (D < 2)    C2
 
-    constexpr bool DPP = Shape<N, C, sizeof(T) == 8>::DPP;
     // ---- A: traces
     T ju[C], uno[C], unn[C];  // jump u_own - u_nbr (mirror state on Dirichlet faces), normal derivatives
     T tv[C], tw[C];           // trace values of both sides (kept in registers for the cross-lane sweeps)
