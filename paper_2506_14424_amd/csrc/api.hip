@@ -418,16 +418,14 @@ sipg_status run_lanczos(sipg_plan* P, hipStream_t s) {
     sk_lz_start(v, n, 12345ull, P->partials, s);
     sk_scalar(P->st, P->partials, 1, SC_LZ_NORM, n, s);
     sk_lz_normalize(v, vprev, n, P->st, s);
+    sk_lz_pre(t, v, P->dinv64, n, s);
     for (int j = 0; j < P->opts.lanczos_steps; ++j) {
-        sk_lz_pre(t, v, P->dinv64, n, s);
         sipg_status rc = do_apply<double>(P, SIPG_PART_ALL, t, w, s);
         if (rc != SIPG_OK) return rc;
-        sk_lz_post(w, v, P->dinv64, n, P->partials, s);
-        sk_scalar(P->st, P->partials, 1, SC_LZ_ALPHA, n, s);
-        sk_lz_orth(w, v, vprev, n, P->st, P->partials, s);
-        sk_scalar(P->st, P->partials, 1, SC_LZ_BETA, n, s);
-        sk_lz_next(vprev, w, n, P->st, s);   // vprev <- w / beta
-        std::swap(v, vprev);                 // (vprev, v) <- (v, w/beta)
+        sk_lz_post_alpha(w, v, P->dinv64, n, P->st, P->partials, s);
+        sk_lz_orth_beta(w, v, vprev, n, P->st, P->partials, s);
+        sk_lz_next_pre(vprev, t, w, P->dinv64, n, P->st, s);  // vprev <- w / beta, t <- its pre-scaling
+        std::swap(v, vprev);                                  // (vprev, v) <- (v, w/beta)
     }
     sk_lz_eig(P->st, s);
     HIP_TRY(hipGetLastError());

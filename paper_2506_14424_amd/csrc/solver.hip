@@ -349,6 +349,46 @@ __global__ void k_residual(const double* b, const double* q, double* r, long lon
     if (reduce_last<1>(acc, partials, st, tot) && threadIdx.x == 0) scalar_step(st, SC_TRUE, tot[0], 0.0, n);
 }
 
+// Lanczos step with the scalar steps fused (same fixed-order sums as the
+// separate kernels): w = sqrt(dinv) w with alpha_m = w.v, ...
+__global__ void k_lz_post_alpha(double* w, const double* v, const double* dinv, long long n, SolveState* st,
+                                double* partials) {
+    double acc[1] = {0.0}, tot[1];
+    GRID_STRIDE(i, n) {
+        const double x = sqrt(dinv[i]) * w[i];
+        w[i] = x;
+        acc[0] += x * v[i];
+    }
+    if (reduce_last<1>(acc, partials, st, tot) && threadIdx.x == 0) scalar_step(st, SC_LZ_ALPHA, tot[0], 0.0, n);
+}
+
+// ... w -= alpha_m v + beta_m vprev with beta_{m+1} = |w| (m advances), ...
+__global__ void k_lz_orth_beta(double* w, const double* v, const double* vprev, long long n, SolveState* st,
+                               double* partials) {
+    const int m = st->lz_m;
+    const double a = st->lz_alpha[m], b = st->lz_beta[m];
+    double acc[1] = {0.0}, tot[1];
+    GRID_STRIDE(i, n) {
+        const double x = w[i] - a * v[i] - b * vprev[i];
+        w[i] = x;
+        acc[0] += x * x;
+    }
+    if (reduce_last<1>(acc, partials, st, tot) && threadIdx.x == 0) scalar_step(st, SC_LZ_BETA, tot[0], 0.0, n);
+}
+
+// ... and the next vector vnew = w / beta with the next step's input
+// t = sqrt(dinv) vnew.
+__global__ void k_lz_next_pre(double* vnew, double* t, const double* w, const double* dinv, long long n,
+                              const SolveState* st) {
+    const double b = st->lz_beta[st->lz_m];
+    const double inv = b > 0.0 ? 1.0 / b : 0.0;
+    GRID_STRIDE(i, n) {
+        const double x = w[i] * inv;
+        vnew[i] = x;
+        t[i] = sqrt(dinv[i]) * x;
+    }
+}
+
 // alpha = (r.z) / (p.Ap), breakdown when p.Ap is not positive
 __global__ void k_cg_alpha(const double* p, const double* q, long long n, SolveState* st, double* partials) {
     if (skipped(st)) return;
@@ -486,6 +526,18 @@ void sk_lz_orth(double* w, const double* v, const double* vprev, long long n, co
 }
 void sk_lz_next(double* vnew, const double* w, long long n, const SolveState* st, hipStream_t s) {
     L(k_lz_next, vnew, w, n, st);
+}
+void sk_lz_post_alpha(double* w, const double* v, const double* dinv, long long n, SolveState* st, double* partials,
+                      hipStream_t s) {
+    L(k_lz_post_alpha, w, v, dinv, n, st, partials);
+}
+void sk_lz_orth_beta(double* w, const double* v, const double* vprev, long long n, SolveState* st, double* partials,
+                     hipStream_t s) {
+    L(k_lz_orth_beta, w, v, vprev, n, st, partials);
+}
+void sk_lz_next_pre(double* vnew, double* t, const double* w, const double* dinv, long long n, const SolveState* st,
+                    hipStream_t s) {
+    L(k_lz_next_pre, vnew, t, w, dinv, n, st);
 }
 void sk_lz_eig(SolveState* st, hipStream_t s) {
     hipLaunchKernelGGL(k_lz_eig, dim3(1), dim3(kEigLanes), 0, s, st);

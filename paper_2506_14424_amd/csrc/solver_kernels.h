@@ -16,6 +16,13 @@ void sk_lz_post(double* w, const double* v, const double* dinv, long long n, dou
 void sk_lz_orth(double* w, const double* v, const double* vprev, long long n, const SolveState* st,
                 double* partials, hipStream_t s);
 void sk_lz_next(double* vnew, const double* w, long long n, const SolveState* st, hipStream_t s);
+// fused Lanczos step: post-scaling with alpha, orthogonalisation with beta, next vector with its pre-scaling
+void sk_lz_post_alpha(double* w, const double* v, const double* dinv, long long n, SolveState* st, double* partials,
+                      hipStream_t s);
+void sk_lz_orth_beta(double* w, const double* v, const double* vprev, long long n, SolveState* st, double* partials,
+                     hipStream_t s);
+void sk_lz_next_pre(double* vnew, double* t, const double* w, const double* dinv, long long n, const SolveState* st,
+                    hipStream_t s);
 void sk_lz_eig(SolveState* st, hipStream_t s);   // lambda_max of the Lanczos tridiagonal
 void sk_lz_coef(SolveState* st, double safety, double ratio, int degree, hipStream_t s);  // Chebyshev coefficients
 void sk_scalar(SolveState* st, const double* partials, int nslots, int op, long long n, hipStream_t s,
