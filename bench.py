@@ -179,7 +179,9 @@ def solve_compare(tol=1e-8):
 def penalty_step(steps, warmup, tol=1e-8):
     """c6: the penalty-step operator (mass + divergence and normal-continuity
     penalties), FP64 and FP32 applies, and mixed-precision solves with the
-    one-level Chebyshev-Jacobi and the hp-multigrid preconditioners."""
+    one-level Chebyshev-Jacobi and the hp-multigrid preconditioners, each
+    with eager kernel launches and with the iteration chunks replayed from
+    captured HIP graphs (a small, launch-bound problem)."""
     import torch
     import workloads as W
     from paper_2506_14424_amd import Operator, SolveOptions
@@ -200,15 +202,20 @@ def penalty_step(steps, warmup, tol=1e-8):
                          "achieved_GBs": b32["total"] / (ms32 * 1e-3) / 1e9},
            "multigrid_levels": op.multigrid_levels()}
     b = torch.from_numpy(W.uniform_vector(cfg["x_seed"], op.ndof)).cuda()
-    for key, kind, deg in (("chebyshev_f32_precond", "chebyshev", 5), ("mg_f32_precond", "multigrid", 3)):
-        opts = SolveOptions(rel_tol=tol, precond_precision="f32", precond=kind, cheb_degree=deg, check_every=5)
+    for key, kind, deg, graph in (("chebyshev_f32_precond", "chebyshev", 5, False),
+                                  ("chebyshev_f32_precond_graph", "chebyshev", 5, True),
+                                  ("mg_f32_precond", "multigrid", 3, False),
+                                  ("mg_f32_precond_graph", "multigrid", 3, True)):
+        opts = SolveOptions(rel_tol=tol, precond_precision="f32", precond=kind, cheb_degree=deg, check_every=5,
+                            use_graph=graph)
         op.solve(b, opts=opts)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         x, info = op.solve(b, opts=opts)
         torch.cuda.synchronize()
         out[key] = {"seconds": time.perf_counter() - t0, "iterations": info["iterations"],
-                    "rel_residual": info["rel_residual"], "status": info["status"], "degree": deg}
+                    "rel_residual": info["rel_residual"], "status": info["status"], "degree": deg,
+                    "hip_graph": graph}
     return out
 
 

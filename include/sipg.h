@@ -136,6 +136,10 @@ typedef struct {
     int32_t check_every;       /* sipg_solve: iterations between host read-backs */
     int32_t max_restarts;      /* defect-correction restarts */
     int32_t precond_kind;      /* sipg_precond_kind; MULTIGRID needs sipg_plan_set_multigrid */
+    int32_t use_graph;         /* nonzero: the iterations between read-backs are captured once into a HIP
+                                  graph (per plan: chunk length, x, precision, preconditioner; two cached)
+                                  and replayed, for problems small enough to be launch-bound; results are
+                                  the same as without (same kernels, same order) */
 } sipg_solve_opts;
 
 /* Preconditioner of the FP64 CG (Sec. 5.3): Chebyshev-accelerated Jacobi on

@@ -149,6 +149,17 @@ struct sipg_plan {
     int lz_steps = 0;
     sipg_solve_info info;
 
+    // captured CG chunks (sipg_solve_opts::use_graph): key and executable
+    struct GraphEntry {
+        hipGraphExec_t exec = nullptr;
+        int iters = 0, prec = -1, kind = -1, deg = -1, mz = -1;
+        const void* x = nullptr;
+        const void* z = nullptr;
+    };
+    hipStream_t cap_stream = nullptr;
+    GraphEntry graphs[2];
+    int graph_next = 0;
+
     // multigrid hierarchy: this plan is the finest level, mg[i] is level i+1
     bool mg_on = false;
     sipg_mg_opts mg_opts;
@@ -409,6 +420,65 @@ sipg_status cg_iterations(sipg_plan* P, int iters) {
         std::swap(P->z, P->zo);
     }
     HIP_TRY(hipGetLastError());
+    return SIPG_OK;
+}
+
+// `iters` CG iterations, eagerly or (opts.use_graph) by replaying a captured
+// HIP graph of them.  A capture runs the eager enqueue on a private stream
+// (the solve stream may be the null stream, which cannot be captured); its
+// host-side pointer swaps are undone and re-applied on every replay, so the
+// key includes the parity of z at the chunk's start.  Any failure to
+// capture or instantiate falls back to the eager path.
+sipg_status cg_chunk(sipg_plan* P, int iters) {
+    auto eager = [&]() {
+        return P->opts.precond_precision == SIPG_F32 ? cg_iterations<float>(P, iters) : cg_iterations<double>(P, iters);
+    };
+    if (!P->opts.use_graph) return eager();
+    const int prec = P->opts.precond_precision, kind = P->opts.precond_kind, deg = P->opts.cheb_degree;
+    const int mz = P->mean_zero ? 1 : 0;
+    auto swaps = [&]() {
+        for (int i = 0; i < iters; ++i) std::swap(P->z, P->zo);
+    };
+    for (auto& g : P->graphs)
+        if (g.exec && g.iters == iters && g.x == P->x && g.z == P->z && g.prec == prec && g.kind == kind &&
+            g.deg == deg && g.mz == mz) {
+            HIP_TRY(hipGraphLaunch(g.exec, P->sstream));
+            swaps();
+            return SIPG_OK;
+        }
+    if (!P->cap_stream && hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        P->cap_stream = nullptr;
+        return eager();
+    }
+    double *z0 = P->z, *zo0 = P->zo;
+    hipStream_t real = P->sstream;
+    P->sstream = P->cap_stream;
+    hipGraph_t graph = nullptr;
+    bool ok = hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+        const sipg_status rc = eager();
+        ok = hipStreamEndCapture(P->cap_stream, &graph) == hipSuccess && rc == SIPG_OK && graph != nullptr;
+    }
+    P->sstream = real;
+    P->z = z0;
+    P->zo = zo0;
+    hipGraphExec_t exec = nullptr;
+    if (ok) ok = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    if (!ok) {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        return eager();
+    }
+    auto& g = P->graphs[P->graph_next];
+    P->graph_next ^= 1;
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    g.exec = exec;
+    g.iters = iters; g.prec = prec; g.kind = kind; g.deg = deg; g.mz = mz;
+    g.x = P->x;
+    g.z = z0;
+    HIP_TRY(hipGraphLaunch(g.exec, P->sstream));
+    swaps();
     return SIPG_OK;
 }
 
@@ -690,8 +760,17 @@ sipg_status sipg_plan_create(const sipg_mesh* mesh, const sipg_viscosity* law, c
     return SIPG_OK;
 }
 
+void drop_graphs(sipg_plan* P) {
+    for (auto& g : P->graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        g = sipg_plan::GraphEntry();
+    }
+}
+
 void sipg_plan_destroy(sipg_plan* P) {
     if (!P) return;
+    drop_graphs(P);
+    if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
     for (sipg_plan* c : P->mg) sipg_plan_destroy(c);
     if (P->mirror) (void)hipHostFree(P->mirror);
     if (P->ev) (void)hipEventDestroy(P->ev);
@@ -754,6 +833,7 @@ sipg_status sipg_plan_bind(sipg_plan* P, void* workspace, size_t bytes, int32_t 
     }
     P->lz_valid = false;
     P->phase = PH_IDLE;
+    drop_graphs(P);  // captured chunks refer to the old workspace
     if (P->curved) {
         HIP_TRY(hipMemcpyAsync(P->verts64_d, P->verts.data(), P->verts.size() * 8, hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemcpyAsync(P->verts32_d, P->verts32.data(), P->verts32.size() * 4, hipMemcpyHostToDevice, s));
@@ -841,6 +921,7 @@ void sipg_solve_opts_default(sipg_solve_opts* o) {
     o->check_every = 10;
     o->max_restarts = 3;
     o->precond_kind = SIPG_PRECOND_CHEBYSHEV;
+    o->use_graph = 0;
 }
 
 void sipg_mg_opts_default(sipg_mg_opts* o) {
@@ -1053,8 +1134,7 @@ sipg_status sipg_solve_advance(sipg_plan* P, int32_t iters) {
     if (!valid_plan(P)) return fail(SIPG_ERR_INVALID, "null plan");
     if (P->phase == PH_IDLE) return fail(SIPG_ERR_STATE, "no solve in progress");
     if (P->phase != PH_RUNNING || iters <= 0) return SIPG_OK;  // checking, done: nothing to enqueue
-    const sipg_status rc = P->opts.precond_precision == SIPG_F32 ? cg_iterations<float>(P, iters)
-                                                                 : cg_iterations<double>(P, iters);
+    const sipg_status rc = cg_chunk(P, iters);
     if (rc != SIPG_OK) return rc;
     return enqueue_readback(P);
 }

@@ -22,6 +22,7 @@ class SolveOptions:
     check_every: int = 10
     max_restarts: int = 3
     precond: str = "chebyshev"       # or "multigrid" (after Operator.set_multigrid)
+    use_graph: bool = False          # replay captured HIP graphs of the iteration chunks
 
     def to_c(self) -> F.SolveOpts:
         o = F.SolveOpts()
@@ -35,6 +36,7 @@ class SolveOptions:
         o.check_every = self.check_every
         o.max_restarts = self.max_restarts
         o.precond_kind = F.PRECOND[self.precond]
+        o.use_graph = int(self.use_graph)
         return o
 
 
