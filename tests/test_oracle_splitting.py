@@ -1,0 +1,239 @@
+"""Pins of the oracle's dual-splitting step (Sec. 3 "Splitting Scheme",
+Sec. 4.1 weak forms, Sec. 5.1 Alg. 1), each against a closed form that does
+not come from the oracle's own tables: the mass matrix integrates the
+domain's volume; the convective term of a linear field is (u . grad) u at
+every node and the upwind flux of a piecewise-constant field takes the
+inflow side's value (1D Lagrange values from scipy, Gauss weights from
+numpy); the divergence form of a linear field is -div(u) times the integral
+of each pressure basis function; the pressure right-hand side sums to the
+wall flux of (grad u) u, i.e. tr(B^2) for u = B x + d; the projection of a
+linear pressure removes its constant gradient and a piecewise-constant
+pressure acts through half its jump; the penalty factors of a constant
+velocity; and the whole step keeps a fluid at rest under a gradient body
+force with the hydrostatic pressure."""
+import numpy as np
+import pytest
+from scipy.interpolate import lagrange
+
+import workloads as W
+from oracle import splitting as SP
+from oracle.forms import Problem, interpolate, node_points
+from oracle.mesh import Mesh
+
+
+def gauss01(n):
+    x, w = np.polynomial.legendre.leggauss(n)
+    return (x + 1) / 2, w / 2
+
+
+def ends(n):
+    """l_j(0), l_j(1) of the n Gauss points' Lagrange basis (scipy)."""
+    g, _ = gauss01(n)
+    l0, l1 = np.zeros(n), np.zeros(n)
+    for j in range(n):
+        e = np.zeros(n)
+        e[j] = 1.0
+        P = lagrange(g, e)
+        l0[j], l1[j] = P(0.0), P(1.0)
+    return l0, l1
+
+
+def velocity_problem(nx, ny, nz, deg, perturb=0.0, dt=0.1):
+    V = W.box_vertices(nx, ny, nz, perturb) if perturb else None
+    return Problem(Mesh(nx, ny, nz, V), deg, "viscous", 1.0 / dt, 1.0)
+
+
+def aniso_box(nx, ny, nz, sx, sy, sz):
+    x = np.linspace(0, sx, nx + 1)
+    y = np.linspace(0, sy, ny + 1)
+    z = np.linspace(0, sz, nz + 1)
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    return np.stack([X, Y, Z], -1).reshape(-1, 3)
+
+
+A = np.array([[0.3, -1.2, 0.5], [0.7, 0.1, -0.4], [-0.6, 0.9, 0.2]])
+c0 = np.array([0.25, -0.5, 1.0])
+
+
+def linear(M, c):
+    return lambda x: x @ M.T + c
+
+
+@pytest.mark.parametrize("perturb", [0.0, 0.1])
+def test_mass_integrates_the_volume(perturb):
+    pb = velocity_problem(3, 2, 2, 3, perturb)
+    one = np.ones(pb.ndof)
+    m = SP.mass_apply(pb, one).reshape(pb.mesh.ncells, 3, -1)
+    assert np.allclose(m.sum(axis=(0, 2)), 1.0, rtol=0, atol=1e-13)
+    x = W.uniform_vector(1, pb.ndof)
+    assert np.allclose(SP.mass_solve(pb, SP.mass_apply(pb, x)), x, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("perturb,deg", [(0.0, 2), (0.1, 3)])
+def test_convective_term_of_a_linear_field(perturb, deg):
+    """u = A x + c is continuous and in the space (also on trilinear cells):
+    the face terms vanish (no jump; {u} = g_u = 0 on the walls) and M^-1 c_h
+    at each node is (u . grad) u = A (A x + c)."""
+    pb = velocity_problem(3, 2, 2, deg, perturb)
+    u = interpolate(pb, linear(A, c0))
+    got = SP.mass_solve(pb, SP.convective_form(pb, u, u))
+    ref = interpolate(pb, lambda x: (x @ A.T + c0) @ A.T)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+    dt = 0.05
+    b = W.uniform_vector(2, pb.ndof)
+    uhat = SP.convective_step(pb, u, b, dt)
+    assert np.abs(uhat - (u + dt * (b - ref))).max() <= 1e-13
+
+
+@pytest.mark.parametrize("inflow_from_right", [True, False])
+def test_upwind_flux_of_piecewise_constants(inflow_from_right):
+    """Two cells along x (widths hx = 0.5, heights 0.7 x 1.3), u constant per
+    cell: only the shared face acts; on the side where {u}.n < 0 the node
+    value is l_i1(face) / (hx w_i1) ({u}.n) (u_other - u_own), zero on the
+    outflow side."""
+    deg = 3
+    n = deg + 1
+    m = Mesh(2, 1, 1, aniso_box(2, 1, 1, 1.0, 0.7, 1.3))
+    pb = Problem(m, deg, "viscous", 1.0, 1.0)
+    ua = np.array([-3.0, 1.0, 0.25]) if inflow_from_right else np.array([2.0, -1.0, 0.5])
+    ub = np.array([1.0, 0.5, -2.0]) if inflow_from_right else np.array([-0.5, 2.0, 1.5])
+    U = np.zeros((2, 3, n ** 3))
+    U[0] = ua[:, None]
+    U[1] = ub[:, None]
+    got = SP.mass_solve(pb, SP.convective_form(pb, U.reshape(-1), U.reshape(-1))).reshape(2, 3, n, n, n)
+    g, w = gauss01(n)
+    l0, l1 = ends(n)
+    hx = 0.5
+    wn = 0.5 * (ua[0] + ub[0])          # {u}.n with n = +x out of cell 0
+    ref = np.zeros_like(got)
+    if wn < 0:
+        ref[0] = (wn * (ub - ua))[:, None, None, None] * (l1 / (hx * w))[None, None, None, :]
+    else:
+        ref[1] = (-wn * (ua - ub))[:, None, None, None] * (l0 / (hx * w))[None, None, None, :]
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("deg", [2, 4])
+def test_divergence_form_of_a_linear_field(deg):
+    """sum_e (grad q, u)_e - (q, {u}.n)_de = -(q, div u) for a continuous
+    u = A x + c with its own trace on the walls; on an affine box of cell
+    sizes hx, hy, hz, int q_j = hx hy hz w_j1 w_j2 w_j3 (k-point weights)."""
+    nx, ny, nz = 3, 2, 2
+    m = Mesh(nx, ny, nz, aniso_box(nx, ny, nz, 1.2, 0.8, 1.0))
+    pb = Problem(m, deg, "viscous", 1.0, 1.0)
+    pp = SP.pressure_problem(m, deg)
+    u = interpolate(pb, linear(A, c0))
+    U = u.reshape(m.ncells, 3, -1)
+    from oracle.basis import face_points, tensor_tables
+
+    def trace(d, s):
+        V, _ = tensor_tables(pb.n, face_points(pb.n, d, s)[0])
+        return np.einsum("pj,ecj->epc", V, U[m.boundary_cells(d, s)])
+
+    got = SP.divergence_form(pb, pp, u, trace).reshape(m.ncells, deg, deg, deg)
+    _, wq = gauss01(deg)
+    vol = (1.2 / nx) * (0.8 / ny) * (1.0 / nz)
+    ref = -np.trace(A) * vol * wq[None, :, None, None] * wq[None, None, :, None] * wq[None, None, None, :]
+    assert np.abs(got - np.broadcast_to(ref, got.shape)).max() <= 1e-13
+
+
+@pytest.mark.parametrize("perturb", [0.0, 0.1])
+def test_pressure_rhs_sums_to_the_wall_flux(perturb):
+    """Summed over the pressure basis (a partition of unity) the interior
+    face terms cancel and the walls leave int (grad u^n) u^n . n = tr(B^2)
+    on the unit cube for u^n = B x + d, whatever uhat and b are."""
+    pb = velocity_problem(2, 3, 2, 3, perturb)
+    pp = SP.pressure_problem(pb.mesh, pb.degree)
+    B = np.array([[0.5, 0.2, -0.3], [0.1, -0.4, 0.6], [0.8, 0.3, 0.1]])
+    u_old = interpolate(pb, linear(B, np.array([1.0, -2.0, 0.5])))
+    uhat = W.uniform_vector(3, pb.ndof)
+    b = W.uniform_vector(4, pb.ndof)
+    f = SP.ppe_rhs(pb, pp, uhat, u_old, b, 0.05)
+    assert abs(f.sum() - np.trace(B @ B)) <= 1e-11
+
+
+@pytest.mark.parametrize("perturb,deg", [(0.0, 2), (0.0, 4), (0.1, 3)])
+def test_projection_of_a_linear_pressure(perturb, deg):
+    """p = g.x + p0 is continuous ({p} = p, also on the walls): the form
+    is -(v, grad p), so M^-1 of it is -g at every velocity node."""
+    pb = velocity_problem(2, 2, 3, deg, perturb)
+    pp = SP.pressure_problem(pb.mesh, deg)
+    gvec = np.array([0.7, -1.1, 0.4])
+    p = interpolate(pp, lambda x: x @ gvec + 0.3)
+    got = SP.mass_solve(pb, SP.projection_form(pb, pp, p)).reshape(pb.mesh.ncells, 3, -1)
+    assert np.abs(got + gvec[None, :, None]).max() <= 1e-12
+
+
+def test_projection_of_piecewise_constant_pressure():
+    """Two cells along x, p constant per cell: (div v, p_e) - (v, {p} n) =
+    sum over faces (p_e - {p}) v.n, i.e. half the jump on the shared face
+    and nothing on the walls."""
+    deg = 3
+    n = deg + 1
+    m = Mesh(2, 1, 1, aniso_box(2, 1, 1, 1.0, 0.7, 1.3))
+    pb = Problem(m, deg, "viscous", 1.0, 1.0)
+    pp = SP.pressure_problem(m, deg)
+    p0, p1 = 2.0, -0.5
+    p = np.concatenate([np.full(deg ** 3, p0), np.full(deg ** 3, p1)])
+    got = SP.mass_solve(pb, SP.projection_form(pb, pp, p)).reshape(2, 3, n, n, n)
+    _, w = gauss01(n)
+    l0, l1 = ends(n)
+    ref = np.zeros_like(got)
+    ref[0, 0] = (0.5 * (p0 - p1) * l1 / (0.5 * w))[None, None, :]
+    ref[1, 0] = (-0.5 * (p1 - p0) * l0 / (0.5 * w))[None, None, :]
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_penalty_factors_of_a_constant_velocity():
+    nx, ny, nz, deg, dt, zeta = 3, 2, 4, 3, 0.02, 1.5
+    m = Mesh(nx, ny, nz, aniso_box(nx, ny, nz, 1.2, 0.8, 1.0))
+    pb = Problem(m, deg, "viscous", 1.0 / dt, 1.0)
+    c = np.array([0.3, -0.4, 1.2])
+    td, tc = SP.penalty_factors(pb, interpolate(pb, lambda x: np.broadcast_to(c, x.shape)), dt, zeta)
+    h = ((1.2 / nx) * (0.8 / ny) * (1.0 / nz)) ** (1 / 3)
+    speed = np.linalg.norm(c)
+    assert np.allclose(td, zeta * speed * h * dt / (deg + 1), rtol=1e-13, atol=0)
+    assert np.allclose(tc, zeta * speed * dt, rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("perturb,deg", [(0.0, 2), (0.1, 3)])
+def test_rest_under_a_gradient_force(perturb, deg):
+    """u^n = 0 and b = g (= grad(g.x)): uhat = dt g, the pressure solves
+    -lap p = 0 with grad p.n = g.n, so p = g.x up to the level (linear, in
+    the space: SIPG is exact), the projection removes dt grad p, and the
+    fluid stays at rest through the viscous and penalty steps."""
+    dt = 0.05
+    pb = velocity_problem(2, 2, 2, deg, perturb, dt)
+    gvec = np.array([0.4, -1.0, 2.5])
+    b = interpolate(pb, lambda x: np.broadcast_to(gvec, x.shape))
+    law = W.carreau_law(3)
+    out = SP.split_step(pb, law, np.zeros(pb.ndof), b, dt)
+    assert np.abs(out["uhat"] - dt * b).max() <= 1e-14
+    pe = node_points(out["pb_p"]).reshape(-1, 3) @ gvec
+    pe -= pe.mean()
+    assert np.abs(out["p"] - pe).max() <= 1e-10
+    assert np.abs(out["uhh"]).max() <= 1e-10
+    assert np.abs(out["u_new"]).max() <= 1e-10
+    assert np.all(out["tau_div"] == 0.0) and np.all(out["tau_cont"] == 0.0)
+
+
+def test_step_rejects_other_boundaries_and_mass_coefficients():
+    pb = Problem(Mesh(2, 2, 2, None, ("D", "N", "D", "D", "D", "D")), 2, "viscous", 10.0, 1.0)
+    with pytest.raises(ValueError):
+        SP.convective_form(pb, np.zeros(pb.ndof), np.zeros(pb.ndof))
+    pb = velocity_problem(2, 2, 2, 2, 0.0, 0.1)
+    with pytest.raises(ValueError):
+        SP.split_step(pb, W.carreau_law(3), np.zeros(pb.ndof), np.zeros(pb.ndof), 0.2)
+
+
+def test_penalty_factor_speed_is_the_volume_mean():
+    """u = (x^2, 0, 0) (in Q_2): the volume mean of |u| over a cell
+    [a, a + hx] x ... is a^2 + a hx + hx^2/3."""
+    nx, ny, nz, deg, dt = 4, 1, 2, 2, 0.1
+    m = Mesh(nx, ny, nz, aniso_box(nx, ny, nz, 1.6, 0.5, 1.0))
+    pb = Problem(m, deg, "viscous", 1.0 / dt, 1.0)
+    u = interpolate(pb, lambda x: np.stack([x[:, 0] ** 2, 0 * x[:, 0], 0 * x[:, 0]], -1))
+    _, tc = SP.penalty_factors(pb, u, dt, 1.0)
+    hx = 1.6 / nx
+    a = hx * (np.arange(m.ncells) % nx)
+    assert np.allclose(tc, (a ** 2 + a * hx + hx ** 2 / 3) * dt, rtol=1e-13, atol=0)
