@@ -348,6 +348,86 @@ sipg_status sipg_picard_solve(sipg_plan* plan, const double* b, double* x, void*
                               const sipg_solve_opts* lin_opts, const sipg_picard_opts* opts,
                               sipg_picard_info* info, void* stream);
 
+/* ---------------------------------------------------------------------
+ * One time step of the dual splitting scheme (Sec. 3 "Splitting Scheme";
+ * the weak forms of Sec. 4.1: eqs. convective_step_weak,
+ * convective_term_weak, pressure_step_weak, guhat_consistent_BC,
+ * pressure_Neumann_BC, projection_step_weak; the order of Alg. 1), with
+ * BDF1 coefficients (gamma_0 = alpha_0 = beta_0 = 1; m_p = 0, so h_p holds
+ * no extrapolated convective or viscous terms) on a box whose six sides are
+ * no-slip walls (velocity Dirichlet with g_u = 0, pressure Neumann).
+ *
+ * Three plans on the same mesh (same cells and vertices):
+ *   vel   SIPG_VISCOUS, degree k in [2, 5], all sides Dirichlet,
+ *         alpha = gamma_0/dt, law SIPG_LAW_CARREAU (its eta parameters);
+ *   pres  SIPG_POISSON, degree k - 1, all sides Neumann, alpha = 0;
+ *   pen   SIPG_PENALTY, degree k, all sides Dirichlet, alpha = 1, no
+ *         multigrid hierarchy (its factors are recomputed on the device).
+ * Velocities, forces: device FP64 in vel's layout (3 components, k+1
+ * Gauss points per direction); pressures: device FP64 in pres's layout
+ * (k Gauss points per direction).  All integrals of the mixed forms use the
+ * velocity's (k+1)-point Gauss rule.  The operators below are
+ * stream-ordered and allocate nothing; b may be NULL (no body force).
+ */
+
+/* uhat = (alpha_0/gamma_0) u + (dt/gamma_0)(b - beta_0 M^-1 c_h(u; u)) with
+ * c_h(v, u; w) = (v, (w.grad) u)_e - (v, ({w}.n) u)_de + (v, ({w}.n) u_dag)_de,
+ * u_dag = {u} + sign({w}.n)(u- - u+)/2 (upwind), mirror principle on the
+ * walls (where {w} = 0 removes the face term). */
+sipg_status sipg_convective_step(sipg_plan* vel, const double* u, const double* b, double dt, double* uhat,
+                                 void* stream);
+
+/* Right-hand side of the pressure Poisson equation (pres layout):
+ * f_q = (gamma_0/dt)[(grad q, uhat)_e - (q, {uhat}.n)_de] + (q, h_p)_walls,
+ * with {uhat} = g_uhat = (dt/gamma_0)(b - beta_0 (grad u_old) u_old) on the
+ * walls and h_p = n.b, both from interior traces of u_old and b. */
+sipg_status sipg_pressure_rhs(sipg_plan* vel, sipg_plan* pres, const double* uhat, const double* u_old,
+                              const double* b, double dt, double* f, void* stream);
+
+/* uhh = uhat + (dt/gamma_0) M^-1 [(div v, p)_e - (v, {p} n)_de] ({p} = p- on
+ * the walls) and, if rhs_visc is not NULL, the viscous step's right-hand
+ * side (gamma_0/dt) M uhh. */
+sipg_status sipg_projection(sipg_plan* vel, sipg_plan* pres, const double* uhat, const double* p, double dt,
+                            double* uhh, double* rhs_visc, void* stream);
+
+/* Recomputes a penalty-step plan's per-cell factors from the velocity u:
+ * tau_div = zeta |u_e| h_e dt/(k+1), tau_cont = zeta |u_e| dt (|u_e| the
+ * volume mean of |u| over the cell, h_e = |cell|^(1/3)), then its face
+ * factors and diagonal, and drops its cached eigenvalue estimate.  Needs a
+ * bound plan without a multigrid hierarchy and no solve in progress. */
+sipg_status sipg_update_penalty_factors(sipg_plan* pen, const double* u, double dt, double zeta, void* stream);
+
+typedef struct {
+    sipg_solve_opts pressure;  /* pressure Poisson solve (pure Neumann: mean-zero) */
+    sipg_solve_opts viscous;   /* viscous step */
+    sipg_solve_opts penalty;   /* penalty step */
+    double zeta;               /* penalty factor scale (1) */
+} sipg_split_opts;
+
+typedef struct {
+    sipg_solve_info pressure, viscous, penalty;
+} sipg_split_info;
+
+void sipg_split_opts_default(sipg_split_opts* opts);
+
+/* Device bytes of the `work` buffer of sipg_split_step: four velocity
+ * vectors and one pressure vector, each 256-byte aligned. */
+size_t sipg_split_work_bytes(const sipg_plan* vel, const sipg_plan* pres);
+
+/* One BDF1 step of Alg. 1 with linear-implicit viscosity: uhat
+ * (convective step), the pressure p (Poisson solve of sipg_pressure_rhs,
+ * its mean removed, solution of zero nodal mean), uhh and the viscous
+ * right-hand side (projection), the viscosity nu(u_old) on every level of
+ * vel (sipg_update_viscosity), the viscous solve, the penalty factors from
+ * u_old and the penalty solve with right-hand side M u_visc into u_new.
+ * Every solve starts from zero.  u_old, b (may be NULL): inputs; u_new, p:
+ * outputs (u_new must not alias u_old); work: device buffer of
+ * sipg_split_work_bytes, 256-byte aligned.  Blocks until done; returns the
+ * first failing solve's status (info, which may be NULL, holds all three). */
+sipg_status sipg_split_step(sipg_plan* vel, sipg_plan* pres, sipg_plan* pen, const double* u_old, const double* b,
+                            double dt, double* u_new, double* p, void* work, const sipg_split_opts* opts,
+                            sipg_split_info* info, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -12,6 +12,7 @@ from __future__ import annotations
 from ._ffi import (LIB_PATH, SipgError, lib, PART_CELL, PART_INTERIOR, PART_BOUNDARY,
                    PART_ALL)
 from .operator import Operator, SolveOptions
+from .splitting import SplitOptions, SplitStep
 
-__all__ = ["Operator", "SolveOptions", "SipgError", "lib", "LIB_PATH",
+__all__ = ["Operator", "SolveOptions", "SplitStep", "SplitOptions", "SipgError", "lib", "LIB_PATH",
            "PART_CELL", "PART_INTERIOR", "PART_BOUNDARY", "PART_ALL"]

@@ -80,6 +80,14 @@ class SolveInfo(C.Structure):
                 ("lambda_max", C.c_double), ("status", C.c_int32)]
 
 
+class SplitOpts(C.Structure):
+    _fields_ = [("pressure", SolveOpts), ("viscous", SolveOpts), ("penalty", SolveOpts), ("zeta", C.c_double)]
+
+
+class SplitInfo(C.Structure):
+    _fields_ = [("pressure", SolveInfo), ("viscous", SolveInfo), ("penalty", SolveInfo)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2506_14424_amd.build` "
@@ -119,6 +127,13 @@ def _load():
         "sipg_picard_opts_default": (None, [C.POINTER(PicardOpts)]),
         "sipg_picard_work_bytes": (C.c_size_t, [P]),
         "sipg_picard_solve": (st, [P, P, P, P, C.POINTER(SolveOpts), C.POINTER(PicardOpts), C.POINTER(PicardInfo), P]),
+        "sipg_convective_step": (st, [P, P, P, C.c_double, P, P]),
+        "sipg_pressure_rhs": (st, [P, P, P, P, P, C.c_double, P, P]),
+        "sipg_projection": (st, [P, P, P, P, C.c_double, P, P, P]),
+        "sipg_update_penalty_factors": (st, [P, P, C.c_double, C.c_double, P]),
+        "sipg_split_opts_default": (None, [C.POINTER(SplitOpts)]),
+        "sipg_split_work_bytes": (C.c_size_t, [P, P]),
+        "sipg_split_step": (st, [P, P, P, P, P, C.c_double, P, P, P, C.POINTER(SplitOpts), C.POINTER(SplitInfo), P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

@@ -1314,4 +1314,215 @@ sipg_status sipg_picard_solve(sipg_plan* P, const double* b, double* x, void* wo
                                              : "Picard iteration stopped: linear solve failed or residual not finite");
 }
 
+// ------------------------------------------------------------ dual splitting step
+
+}  // extern "C"
+
+namespace {
+
+bool same_mesh(const sipg_plan* A, const sipg_plan* B) {
+    return A->nx == B->nx && A->ny == B->ny && A->nz == B->nz && A->curved == B->curved && A->verts == B->verts;
+}
+
+bool all_bc(const sipg_plan* P, int v) {
+    return std::all_of(P->bc, P->bc + 6, [v](int b) { return b == v; });
+}
+
+bool busy(const sipg_plan* P) { return P->phase == PH_RUNNING || P->phase == PH_CHECKING; }
+
+// velocity plan: viscous or penalty, degree 2..5, no-slip walls, bound
+sipg_status check_velocity(const sipg_plan* V) {
+    if (!valid_plan(V)) return fail(SIPG_ERR_INVALID, "null plan");
+    if (V->C != 3) return fail(SIPG_ERR_INVALID, "the velocity plan needs 3 components");
+    if (V->degree < 2 || V->degree > 5) return fail(SIPG_ERR_INVALID, "the splitting step needs velocity degree 2..5");
+    if (!all_bc(V, SIPG_BC_DIRICHLET)) return fail(SIPG_ERR_INVALID, "the splitting step needs no-slip walls (all Dirichlet)");
+    if (!V->bound) return fail(SIPG_ERR_STATE, "plan not bound");
+    return SIPG_OK;
+}
+
+sipg_status check_pressure(const sipg_plan* V, const sipg_plan* Pp) {
+    if (!valid_plan(Pp)) return fail(SIPG_ERR_INVALID, "null plan");
+    if (Pp->op != SIPG_POISSON || Pp->degree != V->degree - 1 || !all_bc(Pp, SIPG_BC_NEUMANN) || Pp->alpha != 0.0)
+        return fail(SIPG_ERR_INVALID, "the pressure plan must be Poisson of degree k-1, all Neumann, alpha = 0");
+    if (!same_mesh(V, Pp)) return fail(SIPG_ERR_INVALID, "velocity and pressure plans are on different meshes");
+    if (!Pp->bound) return fail(SIPG_ERR_STATE, "plan not bound");
+    return SIPG_OK;
+}
+
+void fill_split_geo(const sipg_plan* V, SplitGeo& S) {
+    std::memset(&S, 0, sizeof(S));
+    S.nx = V->nx; S.ny = V->ny; S.nz = V->nz;
+    S.verts = V->curved ? V->verts64_d : nullptr;
+    S.h[0] = 1.0 / V->nx; S.h[1] = 1.0 / V->ny; S.h[2] = 1.0 / V->nz;
+    S.hinv[0] = V->nx; S.hinv[1] = V->ny; S.hinv[2] = V->nz;
+    S.tab = V->tab64;
+    const int n = V->n, np = n - 1;
+    double xp[kMaxN], wp[kMaxN];
+    gauss_legendre01(np, xp, wp);
+    // Lagrange basis on the np pressure points and its derivative (product rule) at t
+    auto basis = [&](double t, int j, double& val, double& der) {
+        val = 1.0;
+        der = 0.0;
+        for (int m = 0; m < np; ++m) {
+            if (m == j) continue;
+            der = der * (t - xp[m]) / (xp[j] - xp[m]) + val / (xp[j] - xp[m]);
+            val *= (t - xp[m]) / (xp[j] - xp[m]);
+        }
+    };
+    for (int q = 0; q < n; ++q)
+        for (int j = 0; j < np; ++j) basis(V->tab64.x[q], j, S.PV[q][j], S.PD[q][j]);
+    for (int s = 0; s < 2; ++s)
+        for (int j = 0; j < np; ++j) {
+            double d;
+            basis((double)s, j, S.PS[s][j], d);
+        }
+}
+
+size_t split_vec_bytes(long long n) { return align256((size_t)n * sizeof(double)); }
+
+}  // namespace
+
+extern "C" {
+
+sipg_status sipg_convective_step(sipg_plan* V, const double* u, const double* b, double dt, double* uhat,
+                                 void* stream) {
+    sipg_status rc = check_velocity(V);
+    if (rc != SIPG_OK) return rc;
+    if (!u || !uhat) return fail(SIPG_ERR_INVALID, "null argument");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(SIPG_ERR_INVALID, "dt must be finite and > 0");
+    if (static_cast<const void*>(u) == static_cast<void*>(uhat) || static_cast<const void*>(b) == static_cast<void*>(uhat))
+        return fail(SIPG_ERR_INVALID, "uhat must not alias u or b (neighbours' values are read)");
+    SplitGeo S;
+    fill_split_geo(V, S);
+    HIP_TRY(launch_split_convective(V->n, S, u, b, dt, uhat, static_cast<hipStream_t>(stream)));
+    return SIPG_OK;
+}
+
+sipg_status sipg_pressure_rhs(sipg_plan* V, sipg_plan* Pp, const double* uhat, const double* u_old, const double* b,
+                              double dt, double* f, void* stream) {
+    sipg_status rc = check_velocity(V);
+    if (rc == SIPG_OK) rc = check_pressure(V, Pp);
+    if (rc != SIPG_OK) return rc;
+    if (!uhat || !u_old || !f) return fail(SIPG_ERR_INVALID, "null argument");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(SIPG_ERR_INVALID, "dt must be finite and > 0");
+    SplitGeo S;
+    fill_split_geo(V, S);
+    HIP_TRY(launch_split_ppe_rhs(V->n, S, uhat, u_old, b, dt, f, static_cast<hipStream_t>(stream)));
+    return SIPG_OK;
+}
+
+sipg_status sipg_projection(sipg_plan* V, sipg_plan* Pp, const double* uhat, const double* p, double dt, double* uhh,
+                            double* rhs_visc, void* stream) {
+    sipg_status rc = check_velocity(V);
+    if (rc == SIPG_OK) rc = check_pressure(V, Pp);
+    if (rc != SIPG_OK) return rc;
+    if (!uhat || !p || !uhh) return fail(SIPG_ERR_INVALID, "null argument");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(SIPG_ERR_INVALID, "dt must be finite and > 0");
+    if (static_cast<const void*>(p) == static_cast<void*>(uhh) || (rhs_visc && static_cast<const void*>(p) == rhs_visc) ||
+        (rhs_visc && static_cast<const void*>(uhat) == rhs_visc) || rhs_visc == uhh)
+        return fail(SIPG_ERR_INVALID, "outputs must not alias p, each other, or (rhs_visc) uhat");
+    SplitGeo S;
+    fill_split_geo(V, S);
+    HIP_TRY(launch_split_projection(V->n, S, uhat, p, dt, uhh, rhs_visc, static_cast<hipStream_t>(stream)));
+    return SIPG_OK;
+}
+
+sipg_status sipg_update_penalty_factors(sipg_plan* P, const double* u, double dt, double zeta, void* stream) {
+    sipg_status rc = check_velocity(P);
+    if (rc != SIPG_OK) return rc;
+    if (!P->pen) return fail(SIPG_ERR_INVALID, "not a penalty-step plan");
+    if (!u) return fail(SIPG_ERR_INVALID, "null argument");
+    if (P->mg_on) return fail(SIPG_ERR_UNSUPPORTED, "the factors of multigrid levels are fixed at creation");
+    if (busy(P)) return fail(SIPG_ERR_STATE, "a solve is in progress on this plan");
+    if (!(dt > 0.0) || !std::isfinite(dt) || !(zeta >= 0.0) || !std::isfinite(zeta))
+        return fail(SIPG_ERR_INVALID, "dt must be finite and > 0, zeta finite and >= 0");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    SplitGeo S;
+    fill_split_geo(P, S);
+    HIP_TRY(launch_pen_factors(P->n, S, u, dt, zeta, P->hcell, P->tau_div_d, P->tau_cont_d, s));
+    const OpData<double> od = P->opdata<double>();
+    HIP_TRY(launch_setup(P->n, P->C, P->curved, od, P->law, P->penalty, P->hcell, P->tfac64, P->tfac32, P->mu_cell64,
+                         P->mu_cell32, P->mu_face64, P->mu_face32, (int)P->nface, P->tau_div_d, P->tau_cont_d, s));
+    HIP_TRY(launch_diagonal(P->n, P->C, P->curved, P->opdata<double>(), P->diag64, P->dinv64, P->dinv32, s));
+    P->lz_valid = false;
+    return SIPG_OK;
+}
+
+void sipg_split_opts_default(sipg_split_opts* o) {
+    if (!o) return;
+    sipg_solve_opts_default(&o->pressure);
+    sipg_solve_opts_default(&o->viscous);
+    sipg_solve_opts_default(&o->penalty);
+    o->zeta = 1.0;
+}
+
+size_t sipg_split_work_bytes(const sipg_plan* V, const sipg_plan* Pp) {
+    if (!valid_plan(V) || !valid_plan(Pp)) return 0;
+    return 4 * split_vec_bytes(V->ndof) + split_vec_bytes(Pp->ndof);
+}
+
+sipg_status sipg_split_step(sipg_plan* V, sipg_plan* Pp, sipg_plan* Pen, const double* u_old, const double* b,
+                            double dt, double* u_new, double* p, void* work, const sipg_split_opts* opts,
+                            sipg_split_info* info, void* stream) {
+    sipg_status rc = check_velocity(V);
+    if (rc == SIPG_OK) rc = check_pressure(V, Pp);
+    if (rc == SIPG_OK) rc = check_velocity(Pen);
+    if (rc != SIPG_OK) return rc;
+    if (V->op != SIPG_VISCOUS || V->law.kind != SIPG_LAW_CARREAU)
+        return fail(SIPG_ERR_INVALID, "the velocity plan must be viscous with the CARREAU law");
+    if (!Pen->pen || Pen->degree != V->degree || Pen->alpha != 1.0 || !same_mesh(V, Pen))
+        return fail(SIPG_ERR_INVALID, "the penalty plan must be a penalty step of the same degree and mesh, alpha = 1");
+    if (!V->with_solver || !Pp->with_solver || !Pen->with_solver)
+        return fail(SIPG_ERR_STATE, "plans must be bound with solver workspace");
+    if (busy(V) || busy(Pp) || busy(Pen)) return fail(SIPG_ERR_STATE, "a solve is in progress on one of the plans");
+    if (!u_old || !u_new || !p || !work) return fail(SIPG_ERR_INVALID, "null argument");
+    if (reinterpret_cast<uintptr_t>(work) % 256 != 0) return fail(SIPG_ERR_INVALID, "work must be 256-byte aligned");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(SIPG_ERR_INVALID, "dt must be finite and > 0");
+    if (std::fabs(V->alpha * dt - 1.0) > 1e-12)
+        return fail(SIPG_ERR_INVALID, "the velocity plan's alpha must be gamma_0/dt (BDF1: 1/dt)");
+    if (static_cast<const void*>(u_old) == static_cast<void*>(u_new))
+        return fail(SIPG_ERR_INVALID, "u_new must not alias u_old");
+    sipg_split_opts o;
+    if (opts) o = *opts; else sipg_split_opts_default(&o);
+    if (!(o.zeta >= 0.0) || !std::isfinite(o.zeta)) return fail(SIPG_ERR_INVALID, "zeta must be finite and >= 0");
+    const long long nu = V->ndof;
+    char* w = static_cast<char*>(work);
+    const size_t vb = split_vec_bytes(nu);
+    double* uhat = reinterpret_cast<double*>(w);
+    double* uhh = reinterpret_cast<double*>(w + vb);
+    double* rhs = reinterpret_cast<double*>(w + 2 * vb);
+    double* uvisc = reinterpret_cast<double*>(w + 3 * vb);
+    double* f = reinterpret_cast<double*>(w + 4 * vb);
+    const char* we = w + sipg_split_work_bytes(V, Pp);
+    auto overlaps = [&](const void* v, size_t bytes) {
+        const char* a = static_cast<const char*>(v);
+        return v && a + bytes > w && a < we;
+    };
+    if (overlaps(u_old, nu * 8) || overlaps(b, nu * 8) || overlaps(u_new, nu * 8) || overlaps(p, Pp->ndof * 8))
+        return fail(SIPG_ERR_INVALID, "work must not alias the step's vectors");
+
+    sipg_split_info inf;
+    std::memset(&inf, 0, sizeof(inf));
+    auto finish = [&](sipg_status r) {
+        if (info) *info = inf;
+        return r;
+    };
+    rc = sipg_convective_step(V, u_old, b, dt, uhat, stream);
+    if (rc == SIPG_OK) rc = sipg_pressure_rhs(V, Pp, uhat, u_old, b, dt, f, stream);
+    if (rc == SIPG_OK) rc = sipg_solve(Pp, f, p, &o.pressure, &inf.pressure, stream);
+    if (rc == SIPG_OK) rc = sipg_projection(V, Pp, uhat, p, dt, uhh, rhs, stream);
+    if (rc == SIPG_OK) rc = update_viscosity(V, u_old, static_cast<hipStream_t>(stream));
+    if (rc == SIPG_OK) rc = sipg_solve(V, rhs, uvisc, &o.viscous, &inf.viscous, stream);
+    if (rc == SIPG_OK) rc = sipg_update_penalty_factors(Pen, u_old, dt, o.zeta, stream);
+    if (rc == SIPG_OK) {
+        SplitGeo S;
+        fill_split_geo(V, S);
+        const hipError_t e = launch_split_mass(V->n, S, uvisc, 1.0, rhs, static_cast<hipStream_t>(stream));
+        if (e != hipSuccess) rc = fail(SIPG_ERR_HIP, std::string("split mass: ") + hipGetErrorString(e));
+    }
+    if (rc == SIPG_OK) rc = sipg_solve(Pen, rhs, u_new, &o.penalty, &inf.penalty, stream);
+    if (rc == SIPG_OK) g_err.clear();
+    return finish(rc);
+}
+
 }  // extern "C"

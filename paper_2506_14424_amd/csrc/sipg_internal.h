@@ -120,6 +120,18 @@ struct LevelPoints {
 
 constexpr int kPicardBlocks = 512;  // blocks of the residual sums (partials: 3 * kPicardBlocks)
 
+// Dual-splitting step: the velocity mesh and 1D tables, and the pressure
+// basis (n - 1 Gauss points) evaluated at the velocity's n Gauss points.
+struct SplitGeo {
+    int nx, ny, nz;
+    const double* verts;         // curved cells, else nullptr (straight cells of edge h)
+    double h[3], hinv[3];
+    Tables<double> tab;          // velocity: n Gauss points
+    double PV[kMaxN][kMaxN];     // PV[q][j] = l^p_j(g_q)
+    double PD[kMaxN][kMaxN];     // PD[q][j] = l^p_j'(g_q)
+    double PS[2][kMaxN];         // PS[s][j] = l^p_j(s)
+};
+
 // ---------------------------------------------------------------- launchers
 // (defined in the .hip files; return hipError_t of the launch)
 
@@ -146,6 +158,17 @@ hipError_t launch_picard_viscosity(const FineVelocity& F, const LevelPoints& Lv,
 hipError_t launch_picard_sums(const double* R, const double* Rp, long long n, double* partials, double* out,
                               hipStream_t s);
 hipError_t launch_axpy(double* x, const double* d, double omega, long long n, hipStream_t s);
+
+// Dual-splitting step operators (n = 3..6; one workgroup per cell)
+hipError_t launch_split_convective(int n, const SplitGeo& S, const double* u, const double* b, double dt,
+                                   double* uhat, hipStream_t s);
+hipError_t launch_split_ppe_rhs(int n, const SplitGeo& S, const double* uhat, const double* u_old, const double* b,
+                                double dt, double* f, hipStream_t s);
+hipError_t launch_split_projection(int n, const SplitGeo& S, const double* uhat, const double* p, double dt,
+                                   double* uhh, double* rhs, hipStream_t s);
+hipError_t launch_split_mass(int n, const SplitGeo& S, const double* x, double scale, double* y, hipStream_t s);
+hipError_t launch_pen_factors(int n, const SplitGeo& S, const double* u, double dt, double zeta, const double* hcell,
+                              double* tau_div, double* tau_cont, hipStream_t s);
 
 // Multigrid transfers between a fine level (nf nodes per direction, fine
 // mesh fx*fy*fz cells) and the next coarser one (nc; same mesh for a degree

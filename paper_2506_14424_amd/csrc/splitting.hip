@@ -1,0 +1,532 @@
+// Operators of one dual-splitting time step that are not linear solves
+// (Sec. 3 "Splitting Scheme"; weak forms of Sec. 4.1; order of Alg. 1):
+//
+//   convective step   uhat = (alpha_0/gamma_0) u^n + (dt/gamma_0)(b - beta_0 M^-1 c_h(u^n; u^n))
+//                     (eqs. convective_step_weak, convective_term_weak: (w.grad)u
+//                     in the cell, upwind flux on the faces, mirror principle
+//                     with g_u = 0 on the walls, where {w} = 0 removes the term)
+//   pressure rhs      f_q = (gamma_0/dt)[(grad q, uhat) - (q, {uhat}.n)] + (q, h_p)_walls
+//                     (eq. pressure_step_weak; on the walls {uhat} = g_uhat of
+//                     eq. guhat_consistent_BC from the interior traces of u^n, b,
+//                     grad u^n, and h_p of eq. pressure_Neumann_BC)
+//   projection        uhh = uhat + (dt/gamma_0) M^-1 [(div v, p) - (v, {p} n)]
+//                     (eq. projection_step_weak; {p} = p- on the walls) and the
+//                     viscous step's right-hand side (gamma_0/dt) M uhh
+//   mass              y = s M x
+//   penalty factors   tau_div = zeta |u_e| h_e dt/(k+1), tau_cont = zeta |u_e| dt,
+//                     |u_e| the volume mean of |u| over the cell
+//
+// BDF1 coefficients (gamma_0 = alpha_0 = beta_0 = 1; m_p = 0 leaves no
+// extrapolated terms in h_p).  Velocity DG_k nodal at its n = k+1 Gauss
+// points, pressure DG_{k-1} at its n-1; all integrals on the velocity's
+// n-point rule.  One workgroup per cell: thread q < n^3 owns a velocity
+// node (or a quadrature point), thread t < 6 n^2 a face point, thread
+// j < (n-1)^3 a pressure node; the cell's data are staged in LDS.  FP64.
+
+#include "device_common.h"
+
+namespace sipg {
+
+namespace {
+
+constexpr double kGamma0 = 1.0, kAlpha0 = 1.0, kBeta0 = 1.0;
+constexpr int kThreads = 256;
+
+struct CellMap {
+    bool curved;
+    double geo[8][3];
+    double h[3], hinv[3];
+};
+
+__device__ __forceinline__ void cell_map(const SplitGeo& S, int ex, int ey, int ez, CellMap& m) {
+    m.curved = S.verts != nullptr;
+    if (m.curved) {
+        double g[8];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            trilinear_coeffs(S.verts, S.nx, S.ny, ex, ey, ez, i, g);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) m.geo[k][i] = g[k];
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        m.h[d] = S.h[d];
+        m.hinv[d] = S.hinv[d];
+    }
+}
+
+__device__ __forceinline__ void point_geo(const CellMap& m, double x1, double x2, double x3, double Ji[3][3],
+                                          double& det) {
+    if (m.curved) {
+        jacobian_inverse<double>(m.geo, x1, x2, x3, Ji, det);
+        return;
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) Ji[d][i] = d == i ? m.hinv[d] : 0.0;
+    det = m.h[0] * m.h[1] * m.h[2];
+}
+
+// The face xi_d = s of a cell: its tangential axes (t1 < t2), the unit
+// normal out of the cell and ds at the face point (g_a, g_b).
+struct FacePoint {
+    int t1, t2;
+    double n[3], ds;
+    double Ji[3][3];
+};
+
+__device__ __forceinline__ void face_point(const SplitGeo& S, const CellMap& m, int d, int s, int a, int b,
+                                           FacePoint& fp) {
+    fp.t1 = d == 0 ? 1 : 0;
+    fp.t2 = d == 2 ? 1 : 2;
+    double xi[3];
+    xi[d] = s;
+    xi[fp.t1] = S.tab.x[a];
+    xi[fp.t2] = S.tab.x[b];
+    double det;
+    point_geo(m, xi[0], xi[1], xi[2], fp.Ji, det);
+    const double v0 = fp.Ji[d][0], v1 = fp.Ji[d][1], v2 = fp.Ji[d][2];
+    const double nv = sqrt(v0 * v0 + v1 * v1 + v2 * v2);
+    const double sg = s ? 1.0 : -1.0;
+    fp.n[0] = sg * v0 / nv;
+    fp.n[1] = sg * v1 / nv;
+    fp.n[2] = sg * v2 / nv;
+    fp.ds = det * nv * S.tab.w[a] * S.tab.w[b];
+}
+
+__device__ __forceinline__ void cell_ijk(const SplitGeo& S, int e, int ijk[3]) {
+    ijk[0] = e % S.nx;
+    ijk[1] = (e / S.nx) % S.ny;
+    ijk[2] = e / (S.nx * S.ny);
+}
+
+// neighbour across face (d, s), or -1 on the boundary
+__device__ __forceinline__ int neighbour(const SplitGeo& S, int e, const int ijk[3], int d, int s) {
+    const int lim = d == 0 ? S.nx : d == 1 ? S.ny : S.nz;
+    const int stride = d == 0 ? 1 : d == 1 ? S.nx : S.nx * S.ny;
+    if (s == 1) return ijk[d] < lim - 1 ? e + stride : -1;
+    return ijk[d] > 0 ? e - stride : -1;
+}
+
+template <int N>
+__global__ void __launch_bounds__(kThreads) k_split_convective(SplitGeo S, const double* __restrict__ u,
+                                                               const double* __restrict__ b, double dt,
+                                                               double* __restrict__ uhat) {
+    constexpr int N2 = N * N, N3 = N2 * N;
+    __shared__ double U[3 * N3];
+    const int e = blockIdx.x, t = threadIdx.x;
+    const double* ue = u + (long long)e * 3 * N3;
+    for (int i = t; i < 3 * N3; i += blockDim.x) U[i] = ue[i];
+    __syncthreads();
+    if (t >= N3) return;
+    int ijk[3];
+    cell_ijk(S, e, ijk);
+    CellMap m;
+    cell_map(S, ijk[0], ijk[1], ijk[2], m);
+    const int qi[3] = {t % N, (t / N) % N, t / N2};
+    const int str[3] = {1, N, N2};
+    double Ji[3][3], det;
+    point_geo(m, S.tab.x[qi[0]], S.tab.x[qi[1]], S.tab.x[qi[2]], Ji, det);
+    double uq[3], gr[3][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        uq[c] = U[c * N3 + t];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            double acc = 0.0;
+            const int base = c * N3 + t - qi[d] * str[d];
+#pragma unroll
+            for (int k = 0; k < N; ++k) acc += S.tab.D[qi[d]][k] * U[base + k * str[d]];
+            gr[c][d] = acc;
+        }
+    }
+    double a[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        double acc = 0.0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) acc += (gr[c][0] * Ji[0][i] + gr[c][1] * Ji[1][i] + gr[c][2] * Ji[2][i]) * uq[i];
+        a[c] = acc;
+    }
+    const double wq = S.tab.w[qi[0]] * S.tab.w[qi[1]] * S.tab.w[qi[2]];
+    double face[3] = {0.0, 0.0, 0.0};
+#pragma unroll 1
+    for (int f = 0; f < 6; ++f) {
+        const int d = f >> 1, s = f & 1;
+        const int ne = neighbour(S, e, ijk, d, s);
+        if (ne < 0) continue;                    // wall: {w} = g_u = 0
+        FacePoint fp;
+        const int ta = d == 0 ? 1 : 0, tb = d == 2 ? 1 : 2;
+        face_point(S, m, d, s, qi[ta], qi[tb], fp);
+        const double* un = u + (long long)ne * 3 * N3;
+        double um[3], up[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int base = c * N3 + t - qi[d] * str[d];
+            double sm = 0.0, sp = 0.0;
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                sm += S.tab.S[s][k] * U[base + k * str[d]];
+                sp += S.tab.S[1 - s][k] * un[base + k * str[d]];
+            }
+            um[c] = sm;
+            up[c] = sp;
+        }
+        const double wn = 0.5 * ((um[0] + up[0]) * fp.n[0] + (um[1] + up[1]) * fp.n[1] + (um[2] + up[2]) * fp.n[2]);
+        if (wn < 0.0) {                          // inflow: u_dag = u+
+            const double sc = S.tab.S[s][qi[d]] * fp.ds * wn;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) face[c] += sc * (up[c] - um[c]);
+        }
+    }
+    const double inv_m = 1.0 / (wq * det);
+    double* out = uhat + (long long)e * 3 * N3;
+    const double* be = b ? b + (long long)e * 3 * N3 : nullptr;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double bq = be ? be[c * N3 + t] : 0.0;
+        out[c * N3 + t] = kAlpha0 / kGamma0 * uq[c] + dt / kGamma0 * (bq - kBeta0 * (a[c] + face[c] * inv_m));
+    }
+}
+
+template <int N>
+__global__ void __launch_bounds__(kThreads) k_split_ppe_rhs(SplitGeo S, const double* __restrict__ uhat,
+                                                            const double* __restrict__ u_old,
+                                                            const double* __restrict__ b, double dt,
+                                                            double* __restrict__ f) {
+    constexpr int N2 = N * N, N3 = N2 * N, NP = N - 1, NP3 = NP * NP * NP;
+    __shared__ double GQ[3][N3];
+    __shared__ double FF[6][N2];
+    const int e = blockIdx.x, t = threadIdx.x;
+    int ijk[3];
+    cell_ijk(S, e, ijk);
+    CellMap m;
+    cell_map(S, ijk[0], ijk[1], ijk[2], m);
+    const int str[3] = {1, N, N2};
+    const double* uh = uhat + (long long)e * 3 * N3;
+    if (t < N3) {
+        const int q1 = t % N, q2 = (t / N) % N, q3 = t / N2;
+        double Ji[3][3], det;
+        point_geo(m, S.tab.x[q1], S.tab.x[q2], S.tab.x[q3], Ji, det);
+        const double jw = S.tab.w[q1] * S.tab.w[q2] * S.tab.w[q3] * det;
+        const double u0 = uh[t], u1 = uh[N3 + t], u2 = uh[2 * N3 + t];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) GQ[d][t] = jw * (Ji[d][0] * u0 + Ji[d][1] * u1 + Ji[d][2] * u2);
+    }
+    if (t < 6 * N2) {
+        const int fc = t / N2, ab = t % N2, d = fc >> 1, s = fc & 1, a = ab % N, bb = ab / N;
+        FacePoint fp;
+        face_point(S, m, d, s, a, bb, fp);
+        const int line = a * str[fp.t1] + bb * str[fp.t2];     // node (0 along d, a, bb)
+        const int ne = neighbour(S, e, ijk, d, s);
+        double val;
+        if (ne >= 0) {
+            const double* un = uhat + (long long)ne * 3 * N3;
+            double an = 0.0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                double sm = 0.0, sp = 0.0;
+#pragma unroll
+                for (int k = 0; k < N; ++k) {
+                    sm += S.tab.S[s][k] * uh[c * N3 + line + k * str[d]];
+                    sp += S.tab.S[1 - s][k] * un[c * N3 + line + k * str[d]];
+                }
+                an += 0.5 * (sm + sp) * fp.n[c];
+            }
+            val = -kGamma0 / dt * an;
+        } else {
+            // wall: g_uhat = (dt/gamma_0)(b - beta_0 (grad u^n) u^n) (+ alpha_0/gamma_0 g_u = 0),
+            // h_p = n.b (- n.d_t g_u = 0), from the interior traces
+            const double* uo = u_old + (long long)e * 3 * N3;
+            const double* be = b ? b + (long long)e * 3 * N3 : nullptr;
+            double ut[3], bt[3], gref[3][3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const double* uc = uo + c * N3;
+                double tr = 0.0, dn = 0.0, btc = 0.0, d1 = 0.0, d2 = 0.0;
+#pragma unroll
+                for (int k = 0; k < N; ++k) {
+                    tr += S.tab.S[s][k] * uc[line + k * str[d]];
+                    dn += S.tab.G[s][k] * uc[line + k * str[d]];
+                    if (be) btc += S.tab.S[s][k] * be[c * N3 + line + k * str[d]];
+                }
+                // tangential derivatives of the trace
+#pragma unroll 1
+                for (int k2 = 0; k2 < N; ++k2) {
+                    double t1v = 0.0, t2v = 0.0;
+#pragma unroll
+                    for (int k = 0; k < N; ++k) {
+                        t1v += S.tab.S[s][k] * uc[k2 * str[fp.t1] + bb * str[fp.t2] + k * str[d]];
+                        t2v += S.tab.S[s][k] * uc[a * str[fp.t1] + k2 * str[fp.t2] + k * str[d]];
+                    }
+                    d1 += S.tab.D[a][k2] * t1v;
+                    d2 += S.tab.D[bb][k2] * t2v;
+                }
+                ut[c] = tr;
+                bt[c] = btc;
+                gref[c][d] = dn;
+                gref[c][fp.t1] = d1;
+                gref[c][fp.t2] = d2;
+            }
+            double gn = 0.0, hp = 0.0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                double conv = 0.0;
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+                    conv += (gref[c][0] * fp.Ji[0][i] + gref[c][1] * fp.Ji[1][i] + gref[c][2] * fp.Ji[2][i]) * ut[i];
+                const double guhat = dt / kGamma0 * (bt[c] - kBeta0 * conv);
+                gn += guhat * fp.n[c];
+                hp += fp.n[c] * bt[c];
+            }
+            val = -kGamma0 / dt * gn + hp;
+        }
+        FF[fc][ab] = fp.ds * val;
+    }
+    __syncthreads();
+    if (t >= NP3) return;
+    const int j[3] = {t % NP, (t / NP) % NP, t / (NP * NP)};
+    double acc = 0.0;
+#pragma unroll 1
+    for (int q3 = 0; q3 < N; ++q3) {
+        const double v3 = S.PV[q3][j[2]], d3 = S.PD[q3][j[2]];
+#pragma unroll
+        for (int q2 = 0; q2 < N; ++q2) {
+            const double v2 = S.PV[q2][j[1]], d2 = S.PD[q2][j[1]];
+#pragma unroll
+            for (int q1 = 0; q1 < N; ++q1) {
+                const int q = (q3 * N + q2) * N + q1;
+                const double v1 = S.PV[q1][j[0]], d1 = S.PD[q1][j[0]];
+                acc += d1 * v2 * v3 * GQ[0][q] + v1 * d2 * v3 * GQ[1][q] + v1 * v2 * d3 * GQ[2][q];
+            }
+        }
+    }
+    acc *= kGamma0 / dt;
+#pragma unroll 1
+    for (int fc = 0; fc < 6; ++fc) {
+        const int d = fc >> 1, s = fc & 1;
+        const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+        const double cn = S.PS[s][j[d]];
+        double fs = 0.0;
+#pragma unroll
+        for (int bb = 0; bb < N; ++bb) {
+            double row = 0.0;
+#pragma unroll
+            for (int a = 0; a < N; ++a) row += S.PV[a][j[t1]] * FF[fc][bb * N + a];
+            fs += S.PV[bb][j[t2]] * row;
+        }
+        acc += cn * fs;
+    }
+    f[(long long)e * NP3 + t] = acc;
+}
+
+// pressure of a cell (NP^3 nodal values) at the velocity face point (a, b) of face (d, s)
+template <int N>
+__device__ __forceinline__ double pressure_at_face(const SplitGeo& S, const double* P, int d, int s, int a, int b) {
+    constexpr int NP = N - 1;
+    const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+    const int sp[3] = {1, NP, NP * NP};
+    double acc = 0.0;
+#pragma unroll
+    for (int jd = 0; jd < NP; ++jd) {
+        double plane = 0.0;
+#pragma unroll
+        for (int j2 = 0; j2 < NP; ++j2) {
+            double row = 0.0;
+#pragma unroll
+            for (int j1 = 0; j1 < NP; ++j1) row += S.PV[a][j1] * P[jd * sp[d] + j1 * sp[t1] + j2 * sp[t2]];
+            plane += S.PV[b][j2] * row;
+        }
+        acc += S.PS[s][jd] * plane;
+    }
+    return acc;
+}
+
+template <int N>
+__global__ void __launch_bounds__(kThreads) k_split_projection(SplitGeo S, const double* __restrict__ uhat,
+                                                               const double* __restrict__ p, double dt,
+                                                               double* __restrict__ uhh, double* __restrict__ rhs) {
+    constexpr int N2 = N * N, N3 = N2 * N, NP = N - 1, NP3 = NP * NP * NP;
+    __shared__ double H[9][N3];
+    __shared__ double FP[6][N2][3];
+    __shared__ double PL[NP3];
+    const int e = blockIdx.x, t = threadIdx.x;
+    for (int i = t; i < NP3; i += blockDim.x) PL[i] = p[(long long)e * NP3 + i];
+    __syncthreads();
+    int ijk[3];
+    cell_ijk(S, e, ijk);
+    CellMap m;
+    cell_map(S, ijk[0], ijk[1], ijk[2], m);
+    const int str[3] = {1, N, N2};
+    const int qi[3] = {t % N, (t / N) % N, t / N2};
+    double jw = 0.0;
+    if (t < N3) {
+        double Ji[3][3], det;
+        point_geo(m, S.tab.x[qi[0]], S.tab.x[qi[1]], S.tab.x[qi[2]], Ji, det);
+        jw = S.tab.w[qi[0]] * S.tab.w[qi[1]] * S.tab.w[qi[2]] * det;
+        double pq = 0.0;
+#pragma unroll 1
+        for (int j3 = 0; j3 < NP; ++j3) {
+            double plane = 0.0;
+#pragma unroll
+            for (int j2 = 0; j2 < NP; ++j2) {
+                double row = 0.0;
+#pragma unroll
+                for (int j1 = 0; j1 < NP; ++j1) row += S.PV[qi[0]][j1] * PL[(j3 * NP + j2) * NP + j1];
+                plane += S.PV[qi[1]][j2] * row;
+            }
+            pq += S.PV[qi[2]][j3] * plane;
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) H[d * 3 + c][t] = jw * Ji[d][c] * pq;
+    }
+    if (t < 6 * N2) {
+        const int fc = t / N2, ab = t % N2, d = fc >> 1, s = fc & 1, a = ab % N, bb = ab / N;
+        FacePoint fp;
+        face_point(S, m, d, s, a, bb, fp);
+        const int ne = neighbour(S, e, ijk, d, s);
+        double pavg = pressure_at_face<N>(S, PL, d, s, a, bb);
+        if (ne >= 0) pavg = 0.5 * (pavg + pressure_at_face<N>(S, p + (long long)ne * NP3, d, 1 - s, a, bb));
+#pragma unroll
+        for (int c = 0; c < 3; ++c) FP[fc][ab][c] = fp.ds * pavg * fp.n[c];
+    }
+    __syncthreads();
+    if (t >= N3) return;
+    const double* ue = uhat + (long long)e * 3 * N3;
+    double* out = uhh + (long long)e * 3 * N3;
+    double* ro = rhs ? rhs + (long long)e * 3 * N3 : nullptr;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        double acc = 0.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int base = t - qi[d] * str[d];
+#pragma unroll
+            for (int k = 0; k < N; ++k) acc += S.tab.D[k][qi[d]] * H[d * 3 + c][base + k * str[d]];
+        }
+#pragma unroll
+        for (int fc = 0; fc < 6; ++fc) {
+            const int d = fc >> 1, s = fc & 1;
+            const int ta = d == 0 ? 1 : 0, tb = d == 2 ? 1 : 2;
+            acc -= S.tab.S[s][qi[d]] * FP[fc][qi[tb] * N + qi[ta]][c];
+        }
+        const double v = ue[c * N3 + t] + dt / kGamma0 * acc / jw;
+        out[c * N3 + t] = v;
+        if (ro) ro[c * N3 + t] = kGamma0 / dt * jw * v;
+    }
+}
+
+template <int N>
+__global__ void __launch_bounds__(kThreads) k_split_mass(SplitGeo S, const double* __restrict__ x, double scale,
+                                                         double* __restrict__ y) {
+    constexpr int N2 = N * N, N3 = N2 * N;
+    const int e = blockIdx.x, t = threadIdx.x;
+    if (t >= N3) return;
+    int ijk[3];
+    cell_ijk(S, e, ijk);
+    CellMap m;
+    cell_map(S, ijk[0], ijk[1], ijk[2], m);
+    const int q1 = t % N, q2 = (t / N) % N, q3 = t / N2;
+    double Ji[3][3], det;
+    point_geo(m, S.tab.x[q1], S.tab.x[q2], S.tab.x[q3], Ji, det);
+    const double jw = scale * S.tab.w[q1] * S.tab.w[q2] * S.tab.w[q3] * det;
+    const long long o = (long long)e * 3 * N3 + t;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) y[o + c * N3] = jw * x[o + c * N3];
+}
+
+template <int N>
+__global__ void __launch_bounds__(kThreads) k_pen_factors(SplitGeo S, const double* __restrict__ u, double dt,
+                                                          double zeta, const double* __restrict__ hcell,
+                                                          double* __restrict__ tau_div, double* __restrict__ tau_cont) {
+    constexpr int N2 = N * N, N3 = N2 * N;
+    __shared__ double sw[kThreads], su[kThreads];
+    const int e = blockIdx.x, t = threadIdx.x;
+    double jw = 0.0, js = 0.0;
+    if (t < N3) {
+        int ijk[3];
+        cell_ijk(S, e, ijk);
+        CellMap m;
+        cell_map(S, ijk[0], ijk[1], ijk[2], m);
+        const int q1 = t % N, q2 = (t / N) % N, q3 = t / N2;
+        double Ji[3][3], det;
+        point_geo(m, S.tab.x[q1], S.tab.x[q2], S.tab.x[q3], Ji, det);
+        jw = S.tab.w[q1] * S.tab.w[q2] * S.tab.w[q3] * det;
+        const double* ue = u + (long long)e * 3 * N3;
+        const double a = ue[t], b = ue[N3 + t], c = ue[2 * N3 + t];
+        js = jw * sqrt(a * a + b * b + c * c);
+    }
+    sw[t] = jw;
+    su[t] = js;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {   // fixed-order tree: deterministic
+        if (t < w) {
+            sw[t] += sw[t + w];
+            su[t] += su[t + w];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        const double ue = su[0] / sw[0];
+        tau_div[e] = zeta * ue * hcell[e] * dt / N;
+        tau_cont[e] = zeta * ue * dt;
+    }
+}
+
+template <int N>
+hipError_t launch_n(int which, const SplitGeo& S, const double* a0, const double* a1, const double* a2, double s0,
+                    double s1, double* o0, double* o1, hipStream_t s) {
+    const dim3 grid((unsigned)(S.nx * S.ny * S.nz)), block(kThreads);
+    switch (which) {
+        case 0: hipLaunchKernelGGL(k_split_convective<N>, grid, block, 0, s, S, a0, a1, s0, o0); break;
+        case 1: hipLaunchKernelGGL(k_split_ppe_rhs<N>, grid, block, 0, s, S, a0, a1, a2, s0, o0); break;
+        case 2: hipLaunchKernelGGL(k_split_projection<N>, grid, block, 0, s, S, a0, a1, s0, o0, o1); break;
+        case 3: hipLaunchKernelGGL(k_split_mass<N>, grid, block, 0, s, S, a0, s0, o0); break;
+        case 4: hipLaunchKernelGGL(k_pen_factors<N>, grid, block, 0, s, S, a0, s0, s1, a1, o0, o1); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t dispatch(int n, int which, const SplitGeo& S, const double* a0, const double* a1, const double* a2,
+                    double s0, double s1, double* o0, double* o1, hipStream_t s) {
+    switch (n) {
+        case 3: return launch_n<3>(which, S, a0, a1, a2, s0, s1, o0, o1, s);
+        case 4: return launch_n<4>(which, S, a0, a1, a2, s0, s1, o0, o1, s);
+        case 5: return launch_n<5>(which, S, a0, a1, a2, s0, s1, o0, o1, s);
+        case 6: return launch_n<6>(which, S, a0, a1, a2, s0, s1, o0, o1, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_split_convective(int n, const SplitGeo& S, const double* u, const double* b, double dt,
+                                   double* uhat, hipStream_t s) {
+    return dispatch(n, 0, S, u, b, nullptr, dt, 0.0, uhat, nullptr, s);
+}
+
+hipError_t launch_split_ppe_rhs(int n, const SplitGeo& S, const double* uhat, const double* u_old, const double* b,
+                                double dt, double* f, hipStream_t s) {
+    return dispatch(n, 1, S, uhat, u_old, b, dt, 0.0, f, nullptr, s);
+}
+
+hipError_t launch_split_projection(int n, const SplitGeo& S, const double* uhat, const double* p, double dt,
+                                   double* uhh, double* rhs, hipStream_t s) {
+    return dispatch(n, 2, S, uhat, p, nullptr, dt, 0.0, uhh, rhs, s);
+}
+
+hipError_t launch_split_mass(int n, const SplitGeo& S, const double* x, double scale, double* y, hipStream_t s) {
+    return dispatch(n, 3, S, x, nullptr, nullptr, scale, 0.0, y, nullptr, s);
+}
+
+hipError_t launch_pen_factors(int n, const SplitGeo& S, const double* u, double dt, double zeta, const double* hcell,
+                              double* tau_div, double* tau_cont, hipStream_t s) {
+    return dispatch(n, 4, S, u, hcell, nullptr, dt, zeta, tau_div, tau_cont, s);
+}
+
+}  // namespace sipg

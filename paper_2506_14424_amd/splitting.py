@@ -1,0 +1,121 @@
+"""SplitStep: the three plans of one dual-splitting time step (velocity
+viscous step, pressure Poisson, penalty step) and the library's step
+operators; see the dual-splitting section of include/sipg.h."""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import _ffi as F
+from ._ffi import check, lib
+from .operator import Operator, SolveOptions, _stream_handle
+
+
+@dataclass
+class SplitOptions:
+    pressure: SolveOptions = field(default_factory=lambda: SolveOptions(rel_tol=1e-10))
+    viscous: SolveOptions = field(default_factory=lambda: SolveOptions(rel_tol=1e-10))
+    penalty: SolveOptions = field(default_factory=lambda: SolveOptions(rel_tol=1e-10))
+    zeta: float = 1.0
+
+    def to_c(self) -> F.SplitOpts:
+        o = F.SplitOpts()
+        o.pressure, o.viscous, o.penalty = self.pressure.to_c(), self.viscous.to_c(), self.penalty.to_c()
+        o.zeta = self.zeta
+        return o
+
+
+def _ptr(t):
+    return C.c_void_p(0 if t is None else t.data_ptr())
+
+
+class SplitStep:
+    """Velocity DG_k (viscous plan with alpha = 1/dt and the Carreau law
+    `law`), pressure DG_{k-1} (pure-Neumann Poisson) and the penalty step
+    (alpha = 1, factors recomputed from the velocity) on one mesh whose six
+    sides are no-slip walls."""
+
+    def __init__(self, nx: int, ny: int, nz: int, degree: int, dt: float, law: dict, vertices=None,
+                 penalty: float = 1.0):
+        if law.get("kind") != "carreau":
+            raise ValueError("the splitting step takes a Carreau law (viscosity updated from the velocity)")
+        self.dt = float(dt)
+        self.vel = Operator(nx, ny, nz, degree, "viscous", 1.0 / dt, penalty, law, vertices, ("D",) * 6)
+        self.pres = Operator(nx, ny, nz, degree - 1, "poisson", 0.0, penalty, None, vertices, ("N",) * 6)
+        zero = np.zeros(nx * ny * nz)
+        self.pen = Operator(nx, ny, nz, degree, "penalty", 1.0, 1.0, None, vertices, ("D",) * 6, zero, zero)
+        self.ndof_u, self.ndof_p = self.vel.ndof, self.pres.ndof
+        self._work = None
+
+    def set_multigrid(self, **kw) -> "SplitStep":
+        """hp-multigrid for the viscous and pressure solves (the penalty step
+        keeps the one-level preconditioner)."""
+        self.vel.set_multigrid(**kw)
+        self.pres.set_multigrid(**kw)
+        return self
+
+    def bind(self, stream=None) -> "SplitStep":
+        for op in (self.vel, self.pres, self.pen):
+            op.bind(with_solver=True, stream=stream)
+        return self
+
+    def _vec(self, t, n, name):
+        import torch
+        if t is None or not t.is_cuda or not t.is_contiguous() or t.numel() != n or t.dtype != torch.float64:
+            raise ValueError(f"{name}: expected a contiguous FP64 device vector of {n} entries")
+
+    def convective_step(self, u, b=None, uhat=None, stream=None):
+        import torch
+        self._vec(u, self.ndof_u, "u")
+        if b is not None:
+            self._vec(b, self.ndof_u, "b")
+        uhat = torch.empty_like(u) if uhat is None else uhat
+        check(lib.sipg_convective_step(self.vel._h, _ptr(u), _ptr(b), self.dt, _ptr(uhat),
+                                       C.c_void_p(_stream_handle(stream))))
+        return uhat
+
+    def pressure_rhs(self, uhat, u_old, b=None, f=None, stream=None):
+        import torch
+        self._vec(uhat, self.ndof_u, "uhat")
+        self._vec(u_old, self.ndof_u, "u_old")
+        f = torch.empty(self.ndof_p, dtype=torch.float64, device=uhat.device) if f is None else f
+        check(lib.sipg_pressure_rhs(self.vel._h, self.pres._h, _ptr(uhat), _ptr(u_old), _ptr(b), self.dt, _ptr(f),
+                                    C.c_void_p(_stream_handle(stream))))
+        return f
+
+    def projection(self, uhat, p, stream=None):
+        import torch
+        self._vec(uhat, self.ndof_u, "uhat")
+        self._vec(p, self.ndof_p, "p")
+        uhh, rhs = torch.empty_like(uhat), torch.empty_like(uhat)
+        check(lib.sipg_projection(self.vel._h, self.pres._h, _ptr(uhat), _ptr(p), self.dt, _ptr(uhh), _ptr(rhs),
+                                  C.c_void_p(_stream_handle(stream))))
+        return uhh, rhs
+
+    def update_penalty_factors(self, u, zeta: float = 1.0, stream=None):
+        self._vec(u, self.ndof_u, "u")
+        check(lib.sipg_update_penalty_factors(self.pen._h, _ptr(u), self.dt, float(zeta),
+                                              C.c_void_p(_stream_handle(stream))))
+
+    def work_bytes(self) -> int:
+        return int(lib.sipg_split_work_bytes(self.vel._h, self.pres._h))
+
+    def step(self, u_old, b=None, u_new=None, p=None, opts: SplitOptions | None = None, stream=None):
+        """One BDF1 step; returns (u_new, p, info)."""
+        import torch
+        self._vec(u_old, self.ndof_u, "u_old")
+        u_new = torch.empty_like(u_old) if u_new is None else u_new
+        p = torch.empty(self.ndof_p, dtype=torch.float64, device=u_old.device) if p is None else p
+        nbytes = self.work_bytes()
+        if self._work is None or self._work.numel() < nbytes + 256:
+            self._work = torch.empty(nbytes + 256, dtype=torch.uint8, device=u_old.device)
+        ptr = self._work.data_ptr()
+        off = (-ptr) % 256
+        o = (opts or SplitOptions()).to_c()
+        info = F.SplitInfo()
+        check(lib.sipg_split_step(self.vel._h, self.pres._h, self.pen._h, _ptr(u_old), _ptr(b), self.dt,
+                                  _ptr(u_new), _ptr(p), C.c_void_p(ptr + off), C.byref(o), C.byref(info),
+                                  C.c_void_p(_stream_handle(stream))))
+        return u_new, p, {k: Operator._info(getattr(info, k)) for k in ("pressure", "viscous", "penalty")}

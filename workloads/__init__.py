@@ -185,6 +185,9 @@ def config(name: str, n: int | None = None) -> dict:
         with the viscosity taken from the velocity (Picard iteration), zero
         initial velocity, right-hand side ``b_scale`` U(-1, 1) with seed 7,
         b_scale = 100 alpha / (cells (k+1)^3).
+    c8  one dual-splitting time step (BDF1, dt = 1e-3, no-slip walls): c3's
+        mesh, velocity degree 4 (pressure 3) and Carreau parameters, the old
+        velocity and body force of ``split_inputs``.
     """
     if name == "c1":
         return _cfg("c1", n or 4, 2, "viscous", sine_law(1.0, 0.5), 10.0, ALL_DIRICHLET, 0.0,
@@ -210,7 +213,49 @@ def config(name: str, n: int | None = None) -> dict:
         m = n or 24
         return _cfg("c7", m, 4, "viscous", carreau_law(3), 10.0, ALL_DIRICHLET, 0.1, x_seed=7, tol=1e-8,
                     b_scale=100.0 * 10.0 / (m ** 3 * 125), picard=True)
+    if name == "c8":
+        m = n or 24
+        dt = 1e-3
+        return _cfg("c8", m, 4, "viscous", carreau_law(3), 1.0 / dt, ALL_DIRICHLET, 0.1, x_seed=8, tol=1e-8,
+                    dt=dt, split=True)
     raise KeyError(name)
+
+
+def node_positions(nx: int, ny: int, nz: int, degree: int, vertices=None) -> np.ndarray:
+    """Physical positions (cells, (k+1)^3, 3) of the Gauss-point nodes of
+    every cell (first reference direction fastest) under the trilinear map
+    of its 8 vertices."""
+    n = degree + 1
+    g = (np.polynomial.legendre.leggauss(n)[0] + 1.0) / 2.0
+    if vertices is None:
+        Z, Y, X = np.meshgrid(np.linspace(0, 1, nz + 1), np.linspace(0, 1, ny + 1), np.linspace(0, 1, nx + 1),
+                              indexing="ij")
+        vertices = np.stack([X, Y, Z], axis=-1)
+    V = np.asarray(vertices, dtype=np.float64).reshape(nz + 1, ny + 1, nx + 1, 3)
+    L = np.stack([1.0 - g, g])                                  # (2, n): linear shape functions at the points
+    out = np.zeros((nz, ny, nx, n, n, n, 3))
+    for c in (0, 1):
+        for b in (0, 1):
+            for a in (0, 1):
+                Xc = V[c:nz + c, b:ny + b, a:nx + a]             # (nz, ny, nx, 3)
+                w = L[c][:, None, None] * L[b][None, :, None] * L[a][None, None, :]   # (q3, q2, q1)
+                out += Xc[:, :, :, None, None, None, :] * w[None, None, None, :, :, :, None]
+    return out.reshape(nx * ny * nz, n ** 3, 3)
+
+
+def split_inputs(cfg: dict, vertices=None) -> tuple[np.ndarray, np.ndarray]:
+    """Old velocity and body force of the dual-splitting workload, nodal
+    vectors (cells, 3, (k+1)^3): u^n = 6.4 x(1-x) y(1-y) z(1-z) w(x) with w
+    the seeded smooth background velocity of ``carreau_law(x_seed)`` (zero on
+    the walls), b = (sin 2 pi y, sin 2 pi z, sin 2 pi x)."""
+    x = node_positions(cfg["nx"], cfg["ny"], cfg["nz"], cfg["degree"], vertices)
+    law = carreau_law(cfg["x_seed"])
+    arg = 2 * np.pi * x @ law["k"].T.astype(np.float64) + law["phi"]
+    w = np.cos(arg) @ law["v"]
+    bub = 6.4 * np.prod(x * (1.0 - x), axis=-1)
+    u = bub[..., None] * w
+    b = np.sin(2 * np.pi * x[..., [1, 2, 0]])
+    return np.transpose(u, (0, 2, 1)).reshape(-1).copy(), np.transpose(b, (0, 2, 1)).reshape(-1).copy()
 
 
 CONFIGS = ("c1", "c2", "c3", "c4p", "c4v")
