@@ -8,8 +8,8 @@ last-level cache.  Besides the headline DoF/s the line reports the FP32
 (preconditioner precision) apply, the setup including the inverse diagonal,
 FP64- vs FP32-preconditioned solves (one-level Chebyshev-Jacobi and
 hp-multigrid) of the 24^3 k = 4 Carreau workload to 1e-8, the penalty-step
-operator (applies and solves), the Picard-Aitken nonlinear viscous step, the
-continuous-batching request loop (solves/s, p50/p99), the
+operator (applies and solves), the Picard-Aitken nonlinear viscous step, one
+dual-splitting time step, the continuous-batching request loop (solves/s, p50/p99), the
 roofline of the apply kernel and the CPU oracle timed on this host.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
@@ -256,6 +256,92 @@ def picard_step(tol=1e-8):
     return out
 
 
+def split_step(reps=5, tol=1e-8):
+    """c8: one dual-splitting time step (BDF1, no-slip walls): the whole step
+    (convective step, pressure right-hand side, pressure Poisson solve,
+    projection, viscosity update, viscous solve, penalty factors, penalty
+    solve) and each part alone; the three non-solve operators with their
+    algorithmic bytes."""
+    import torch
+    import workloads as W
+    from paper_2506_14424_amd import SolveOptions, SplitOptions, SplitStep
+    cfg = W.config("c8")
+    m, deg, dt = cfg["nx"], cfg["degree"], cfg["dt"]
+    V = W.box_vertices(m, m, m, cfg["perturb"])
+    st = SplitStep(m, m, m, deg, dt, cfg["law"], V).set_multigrid().bind()
+    u0, b0 = W.split_inputs(cfg, V)
+    u, b = torch.from_numpy(u0).cuda(), torch.from_numpy(b0).cuda()
+    mg = SolveOptions(rel_tol=tol, precond="multigrid", cheb_degree=3)
+    opts = SplitOptions(pressure=mg, viscous=mg, penalty=SolveOptions(rel_tol=tol), zeta=1.0)
+    un, p, info = st.step(u, b, opts=opts)                         # warm: eigenvalue estimates, code paths
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        un, p, info = st.step(u, b, u_new=un, p=p, opts=opts)
+    torch.cuda.synchronize()
+    step_s = (time.perf_counter() - t0) / reps
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+    def timed(fn, n=20):
+        fn()
+        ev[0].record()
+        for _ in range(n):
+            fn()
+        ev[1].record()
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]) / n
+
+    uhat = st.convective_step(u, b)
+    f = st.pressure_rhs(uhat, u, b)
+    uhh, rhs = st.projection(uhat, p)
+    ms_conv = timed(lambda: st.convective_step(u, b, uhat=uhat))
+    ms_rhs = timed(lambda: st.pressure_rhs(uhat, u, b, f=f))
+    ms_proj = timed(lambda: st.projection(uhat, p))
+    ms_pen = timed(lambda: st.update_penalty_factors(u))
+    ms_visc = timed(lambda: st.vel.update_viscosity(u), 5)
+
+    def wall(fn):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, r
+
+    t_p, (_, ip) = wall(lambda: st.pres.solve(f, opts=mg))
+    st.vel.update_viscosity(u)
+    t_v, (uv, iv) = wall(lambda: st.vel.solve(rhs, opts=mg))
+    t_vc, _ = wall(lambda: st.vel.solve(rhs, opts=mg))              # eigenvalue estimates cached
+    st.update_penalty_factors(u)
+    t_q, (_, iq) = wall(lambda: st.pen.solve(rhs, opts=opts.penalty))
+    nu, npr = st.ndof_u, st.ndof_p
+    ncell = m ** 3
+    nb = m ** 3 - (m - 2) ** 3                                     # cells on a wall
+    verts = (m + 1) ** 3 * 3 * 8
+    bytes_conv = 3 * 8 * nu + verts                                # u, b in; uhat out
+    bytes_rhs = 8 * nu + 8 * npr + 2 * 8 * nb * 3 * (deg + 1) ** 3 + verts   # uhat; f; u, b of the wall cells
+    bytes_proj = 3 * 8 * nu + 8 * npr + verts                      # uhat, p in; uhh, rhs out
+
+    def kern(ms, nbytes):
+        return {"avg_launch_ms": ms, "algorithmic_bytes": nbytes, "achieved_GBs": nbytes / (ms * 1e-3) / 1e9,
+                "hbm_frac": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+    return {"workload": f"c8: one BDF1 dual-splitting step, 24^3 perturbed cells, velocity k={deg} "
+                        f"({nu} DoFs), pressure k={deg - 1} ({npr} DoFs), Carreau viscosity of u^n, dt={dt:g}, "
+                        f"no-slip walls, solves to {tol:g} (FP32 multigrid for pressure and viscous, "
+                        f"Chebyshev-Jacobi for the penalty step)",
+            "step_seconds": step_s,
+            "iterations": {k: v["iterations"] for k, v in info.items()},
+            "status": {k: v["status"] for k, v in info.items()},
+            "convective_step": kern(ms_conv, bytes_conv),
+            "pressure_rhs": kern(ms_rhs, bytes_rhs),
+            "projection": kern(ms_proj, bytes_proj),
+            "penalty_factors_ms": ms_pen,
+            "viscosity_update_ms": ms_visc,
+            "pressure_solve_s": t_p, "pressure_iterations": ip["iterations"],
+            "viscous_solve_s": t_v, "viscous_solve_cached_eigs_s": t_vc, "viscous_iterations": iv["iterations"],
+            "penalty_solve_s": t_q, "penalty_iterations": iq["iterations"]}
+
+
 def serving(count=256, rate=20.0, budget=8 << 30):
     """c5: the seeded request stream through the continuous-batching loop."""
     import workloads as W
@@ -281,12 +367,17 @@ def main():
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--copy-probe", action="store_true", help="also run a plain copy of known size")
+    ap.add_argument("--split-only", action="store_true", help="only the dual-splitting step section")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the operator path has no "
-                                   "multi-GPU mode (see the sharding note in DESIGN.md)",
+                                   "multi-GPU mode (it would shard by blocks of cells with one face-trace "
+                                   "exchange per apply)",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.split_only:
+        print(json.dumps({"split_step": split_step()}), flush=True)
+        return
 
     import torch
     import workloads as W
@@ -388,6 +479,9 @@ def main():
         log("nonlinear viscous step (c7) ...")
         line["picard"] = picard_step()
         log(json.dumps(line["picard"]))
+        log("dual-splitting step (c8) ...")
+        line["split_step"] = split_step()
+        log(json.dumps(line["split_step"]))
     if not args.no_serve:
         log("serving loop (c5) ...")
         line["serving"] = serving()

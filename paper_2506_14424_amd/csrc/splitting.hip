@@ -152,7 +152,7 @@ __global__ void __launch_bounds__(kThreads) k_split_convective(SplitGeo S, const
     }
     const double wq = S.tab.w[qi[0]] * S.tab.w[qi[1]] * S.tab.w[qi[2]];
     double face[3] = {0.0, 0.0, 0.0};
-#pragma unroll 1
+#pragma unroll
     for (int f = 0; f < 6; ++f) {
         const int d = f >> 1, s = f & 1;
         const int ne = neighbour(S, e, ijk, d, s);
@@ -191,6 +191,83 @@ __global__ void __launch_bounds__(kThreads) k_split_convective(SplitGeo S, const
     }
 }
 
+template <int N, int FC>
+__device__ __forceinline__ double ppe_face(const SplitGeo& S, const CellMap& m, int e, const int ijk[3], int ab,
+                                       const double* __restrict__ uhat, const double* __restrict__ u_old,
+                                       const double* __restrict__ b, double dt) {
+    constexpr int N2 = N * N, N3 = N2 * N, d = FC >> 1, s = FC & 1;
+    const int str[3] = {1, N, N2};
+    const int a = ab % N, bb = ab / N;
+    const double* uh = uhat + (long long)e * 3 * N3;
+    FacePoint fp;
+    face_point(S, m, d, s, a, bb, fp);
+    const int line = a * str[fp.t1] + bb * str[fp.t2];     // node (0 along d, a, bb)
+    const int ne = neighbour(S, e, ijk, d, s);
+    double val;
+    if (ne >= 0) {
+        const double* un = uhat + (long long)ne * 3 * N3;
+        double an = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double sm = 0.0, sp = 0.0;
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                sm += S.tab.S[s][k] * uh[c * N3 + line + k * str[d]];
+                sp += S.tab.S[1 - s][k] * un[c * N3 + line + k * str[d]];
+            }
+            an += 0.5 * (sm + sp) * fp.n[c];
+        }
+        val = -kGamma0 / dt * an;
+    } else {
+        // wall: g_uhat = (dt/gamma_0)(b - beta_0 (grad u^n) u^n) (+ alpha_0/gamma_0 g_u = 0),
+        // h_p = n.b (- n.d_t g_u = 0), from the interior traces
+        const double* uo = u_old + (long long)e * 3 * N3;
+        const double* be = b ? b + (long long)e * 3 * N3 : nullptr;
+        double ut[3], bt[3], gref[3][3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double* uc = uo + c * N3;
+            double tr = 0.0, dn = 0.0, btc = 0.0, d1 = 0.0, d2 = 0.0;
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                tr += S.tab.S[s][k] * uc[line + k * str[d]];
+                dn += S.tab.G[s][k] * uc[line + k * str[d]];
+                if (be) btc += S.tab.S[s][k] * be[c * N3 + line + k * str[d]];
+            }
+            // tangential derivatives of the trace
+#pragma unroll 1
+            for (int k2 = 0; k2 < N; ++k2) {
+                double t1v = 0.0, t2v = 0.0;
+#pragma unroll
+                for (int k = 0; k < N; ++k) {
+                    t1v += S.tab.S[s][k] * uc[k2 * str[fp.t1] + bb * str[fp.t2] + k * str[d]];
+                    t2v += S.tab.S[s][k] * uc[a * str[fp.t1] + k2 * str[fp.t2] + k * str[d]];
+                }
+                d1 += S.tab.D[a][k2] * t1v;
+                d2 += S.tab.D[bb][k2] * t2v;
+            }
+            ut[c] = tr;
+            bt[c] = btc;
+            gref[c][d] = dn;
+            gref[c][fp.t1] = d1;
+            gref[c][fp.t2] = d2;
+        }
+        double gn = 0.0, hp = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double conv = 0.0;
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+                conv += (gref[c][0] * fp.Ji[0][i] + gref[c][1] * fp.Ji[1][i] + gref[c][2] * fp.Ji[2][i]) * ut[i];
+            const double guhat = dt / kGamma0 * (bt[c] - kBeta0 * conv);
+            gn += guhat * fp.n[c];
+            hp += fp.n[c] * bt[c];
+        }
+        val = -kGamma0 / dt * gn + hp;
+    }
+    return fp.ds * val;
+}
+
 template <int N>
 __global__ void __launch_bounds__(kThreads) k_split_ppe_rhs(SplitGeo S, const double* __restrict__ uhat,
                                                             const double* __restrict__ u_old,
@@ -216,74 +293,17 @@ __global__ void __launch_bounds__(kThreads) k_split_ppe_rhs(SplitGeo S, const do
         for (int d = 0; d < 3; ++d) GQ[d][t] = jw * (Ji[d][0] * u0 + Ji[d][1] * u1 + Ji[d][2] * u2);
     }
     if (t < 6 * N2) {
-        const int fc = t / N2, ab = t % N2, d = fc >> 1, s = fc & 1, a = ab % N, bb = ab / N;
-        FacePoint fp;
-        face_point(S, m, d, s, a, bb, fp);
-        const int line = a * str[fp.t1] + bb * str[fp.t2];     // node (0 along d, a, bb)
-        const int ne = neighbour(S, e, ijk, d, s);
-        double val;
-        if (ne >= 0) {
-            const double* un = uhat + (long long)ne * 3 * N3;
-            double an = 0.0;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                double sm = 0.0, sp = 0.0;
-#pragma unroll
-                for (int k = 0; k < N; ++k) {
-                    sm += S.tab.S[s][k] * uh[c * N3 + line + k * str[d]];
-                    sp += S.tab.S[1 - s][k] * un[c * N3 + line + k * str[d]];
-                }
-                an += 0.5 * (sm + sp) * fp.n[c];
-            }
-            val = -kGamma0 / dt * an;
-        } else {
-            // wall: g_uhat = (dt/gamma_0)(b - beta_0 (grad u^n) u^n) (+ alpha_0/gamma_0 g_u = 0),
-            // h_p = n.b (- n.d_t g_u = 0), from the interior traces
-            const double* uo = u_old + (long long)e * 3 * N3;
-            const double* be = b ? b + (long long)e * 3 * N3 : nullptr;
-            double ut[3], bt[3], gref[3][3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const double* uc = uo + c * N3;
-                double tr = 0.0, dn = 0.0, btc = 0.0, d1 = 0.0, d2 = 0.0;
-#pragma unroll
-                for (int k = 0; k < N; ++k) {
-                    tr += S.tab.S[s][k] * uc[line + k * str[d]];
-                    dn += S.tab.G[s][k] * uc[line + k * str[d]];
-                    if (be) btc += S.tab.S[s][k] * be[c * N3 + line + k * str[d]];
-                }
-                // tangential derivatives of the trace
-#pragma unroll 1
-                for (int k2 = 0; k2 < N; ++k2) {
-                    double t1v = 0.0, t2v = 0.0;
-#pragma unroll
-                    for (int k = 0; k < N; ++k) {
-                        t1v += S.tab.S[s][k] * uc[k2 * str[fp.t1] + bb * str[fp.t2] + k * str[d]];
-                        t2v += S.tab.S[s][k] * uc[a * str[fp.t1] + k2 * str[fp.t2] + k * str[d]];
-                    }
-                    d1 += S.tab.D[a][k2] * t1v;
-                    d2 += S.tab.D[bb][k2] * t2v;
-                }
-                ut[c] = tr;
-                bt[c] = btc;
-                gref[c][d] = dn;
-                gref[c][fp.t1] = d1;
-                gref[c][fp.t2] = d2;
-            }
-            double gn = 0.0, hp = 0.0;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                double conv = 0.0;
-#pragma unroll
-                for (int i = 0; i < 3; ++i)
-                    conv += (gref[c][0] * fp.Ji[0][i] + gref[c][1] * fp.Ji[1][i] + gref[c][2] * fp.Ji[2][i]) * ut[i];
-                const double guhat = dt / kGamma0 * (bt[c] - kBeta0 * conv);
-                gn += guhat * fp.n[c];
-                hp += fp.n[c] * bt[c];
-            }
-            val = -kGamma0 / dt * gn + hp;
+        const int fc = t / N2, ab = t % N2;
+        double v = 0.0;
+        switch (fc) {
+            case 0: v = ppe_face<N, 0>(S, m, e, ijk, ab, uhat, u_old, b, dt); break;
+            case 1: v = ppe_face<N, 1>(S, m, e, ijk, ab, uhat, u_old, b, dt); break;
+            case 2: v = ppe_face<N, 2>(S, m, e, ijk, ab, uhat, u_old, b, dt); break;
+            case 3: v = ppe_face<N, 3>(S, m, e, ijk, ab, uhat, u_old, b, dt); break;
+            case 4: v = ppe_face<N, 4>(S, m, e, ijk, ab, uhat, u_old, b, dt); break;
+            default: v = ppe_face<N, 5>(S, m, e, ijk, ab, uhat, u_old, b, dt); break;
         }
-        FF[fc][ab] = fp.ds * val;
+        FF[fc][ab] = v;
     }
     __syncthreads();
     if (t >= NP3) return;
@@ -304,7 +324,7 @@ __global__ void __launch_bounds__(kThreads) k_split_ppe_rhs(SplitGeo S, const do
         }
     }
     acc *= kGamma0 / dt;
-#pragma unroll 1
+#pragma unroll
     for (int fc = 0; fc < 6; ++fc) {
         const int d = fc >> 1, s = fc & 1;
         const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
@@ -342,6 +362,21 @@ __device__ __forceinline__ double pressure_at_face(const SplitGeo& S, const doub
         acc += S.PS[s][jd] * plane;
     }
     return acc;
+}
+
+// ds {p} n at the face point ab of face FC ({p} = p- on a wall)
+template <int N, int FC>
+__device__ __forceinline__ void proj_face(const SplitGeo& S, const CellMap& m, int e, const int ijk[3], int ab,
+                                          const double* PL, const double* __restrict__ p, double* out) {
+    constexpr int NP = N - 1, NP3 = NP * NP * NP, d = FC >> 1, s = FC & 1;
+    const int a = ab % N, bb = ab / N;
+    FacePoint fp;
+    face_point(S, m, d, s, a, bb, fp);
+    const int ne = neighbour(S, e, ijk, d, s);
+    double pavg = pressure_at_face<N>(S, PL, d, s, a, bb);
+    if (ne >= 0) pavg = 0.5 * (pavg + pressure_at_face<N>(S, p + (long long)ne * NP3, d, 1 - s, a, bb));
+#pragma unroll
+    for (int c = 0; c < 3; ++c) out[c] = fp.ds * pavg * fp.n[c];
 }
 
 template <int N>
@@ -385,14 +420,15 @@ __global__ void __launch_bounds__(kThreads) k_split_projection(SplitGeo S, const
             for (int c = 0; c < 3; ++c) H[d * 3 + c][t] = jw * Ji[d][c] * pq;
     }
     if (t < 6 * N2) {
-        const int fc = t / N2, ab = t % N2, d = fc >> 1, s = fc & 1, a = ab % N, bb = ab / N;
-        FacePoint fp;
-        face_point(S, m, d, s, a, bb, fp);
-        const int ne = neighbour(S, e, ijk, d, s);
-        double pavg = pressure_at_face<N>(S, PL, d, s, a, bb);
-        if (ne >= 0) pavg = 0.5 * (pavg + pressure_at_face<N>(S, p + (long long)ne * NP3, d, 1 - s, a, bb));
-#pragma unroll
-        for (int c = 0; c < 3; ++c) FP[fc][ab][c] = fp.ds * pavg * fp.n[c];
+        const int fc = t / N2, ab = t % N2;
+        switch (fc) {
+            case 0: proj_face<N, 0>(S, m, e, ijk, ab, PL, p, FP[0][ab]); break;
+            case 1: proj_face<N, 1>(S, m, e, ijk, ab, PL, p, FP[1][ab]); break;
+            case 2: proj_face<N, 2>(S, m, e, ijk, ab, PL, p, FP[2][ab]); break;
+            case 3: proj_face<N, 3>(S, m, e, ijk, ab, PL, p, FP[3][ab]); break;
+            case 4: proj_face<N, 4>(S, m, e, ijk, ab, PL, p, FP[4][ab]); break;
+            default: proj_face<N, 5>(S, m, e, ijk, ab, PL, p, FP[5][ab]); break;
+        }
     }
     __syncthreads();
     if (t >= N3) return;
