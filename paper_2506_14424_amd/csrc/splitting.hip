@@ -30,7 +30,13 @@ namespace sipg {
 namespace {
 
 constexpr double kGamma0 = 1.0, kAlpha0 = 1.0, kBeta0 = 1.0;
-constexpr int kThreads = 256;
+// Workgroup sizes: a multiple of the 64-wide wavefront covering a cell's
+// n^3 nodes (kCellThreads, a power of two for the tree sums) or also its
+// 6 n^2 face points (kFaceThreads).
+template <int N>
+constexpr int kCellThreads = N * N * N <= 64 ? 64 : N * N * N <= 128 ? 128 : 256;
+template <int N>
+constexpr int kFaceThreads = ((N * N * N > 6 * N * N ? N * N * N : 6 * N * N) + 63) / 64 * 64;
 
 struct CellMap {
     bool curved;
@@ -110,21 +116,68 @@ __device__ __forceinline__ int neighbour(const SplitGeo& S, int e, const int ijk
     return ijk[d] > 0 ? e - stride : -1;
 }
 
+// ds ({w}.n) (u+ - u-) at face point ab of face FC if {w}.n < 0 (inflow:
+// u_dag = u+), else 0; zero on a wall ({w} = g_u = 0).  U: the cell's values.
+template <int N, int FC>
+__device__ __forceinline__ void conv_face(const SplitGeo& S, const CellMap& m, int e, const int ijk[3], int ab,
+                                          const double* U, const double* __restrict__ u, double* out) {
+    constexpr int N2 = N * N, N3 = N2 * N, d = FC >> 1, s = FC & 1;
+    const int str[3] = {1, N, N2};
+    out[0] = out[1] = out[2] = 0.0;
+    const int ne = neighbour(S, e, ijk, d, s);
+    if (ne < 0) return;
+    const int a = ab % N, bb = ab / N;
+    FacePoint fp;
+    face_point(S, m, d, s, a, bb, fp);
+    const int line = a * str[fp.t1] + bb * str[fp.t2];
+    const double* un = u + (long long)ne * 3 * N3;
+    double um[3], up[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        double sm = 0.0, sp = 0.0;
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            sm += S.tab.S[s][k] * U[c * N3 + line + k * str[d]];
+            sp += S.tab.S[1 - s][k] * un[c * N3 + line + k * str[d]];
+        }
+        um[c] = sm;
+        up[c] = sp;
+    }
+    const double wn = 0.5 * ((um[0] + up[0]) * fp.n[0] + (um[1] + up[1]) * fp.n[1] + (um[2] + up[2]) * fp.n[2]);
+    if (wn < 0.0) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) out[c] = fp.ds * wn * (up[c] - um[c]);
+    }
+}
+
 template <int N>
-__global__ void __launch_bounds__(kThreads) k_split_convective(SplitGeo S, const double* __restrict__ u,
-                                                               const double* __restrict__ b, double dt,
-                                                               double* __restrict__ uhat) {
+__global__ void __launch_bounds__(kFaceThreads<N>) k_split_convective(SplitGeo S, const double* __restrict__ u,
+                                                                     const double* __restrict__ b, double dt,
+                                                                     double* __restrict__ uhat) {
     constexpr int N2 = N * N, N3 = N2 * N;
     __shared__ double U[3 * N3];
+    __shared__ double FF[6][N2][3];
     const int e = blockIdx.x, t = threadIdx.x;
     const double* ue = u + (long long)e * 3 * N3;
     for (int i = t; i < 3 * N3; i += blockDim.x) U[i] = ue[i];
     __syncthreads();
-    if (t >= N3) return;
     int ijk[3];
     cell_ijk(S, e, ijk);
     CellMap m;
     cell_map(S, ijk[0], ijk[1], ijk[2], m);
+    if (t < 6 * N2) {
+        const int fc = t / N2, ab = t % N2;
+        switch (fc) {
+            case 0: conv_face<N, 0>(S, m, e, ijk, ab, U, u, FF[0][ab]); break;
+            case 1: conv_face<N, 1>(S, m, e, ijk, ab, U, u, FF[1][ab]); break;
+            case 2: conv_face<N, 2>(S, m, e, ijk, ab, U, u, FF[2][ab]); break;
+            case 3: conv_face<N, 3>(S, m, e, ijk, ab, U, u, FF[3][ab]); break;
+            case 4: conv_face<N, 4>(S, m, e, ijk, ab, U, u, FF[4][ab]); break;
+            default: conv_face<N, 5>(S, m, e, ijk, ab, U, u, FF[5][ab]); break;
+        }
+    }
+    __syncthreads();
+    if (t >= N3) return;
     const int qi[3] = {t % N, (t / N) % N, t / N2};
     const int str[3] = {1, N, N2};
     double Ji[3][3], det;
@@ -150,37 +203,17 @@ __global__ void __launch_bounds__(kThreads) k_split_convective(SplitGeo S, const
         for (int i = 0; i < 3; ++i) acc += (gr[c][0] * Ji[0][i] + gr[c][1] * Ji[1][i] + gr[c][2] * Ji[2][i]) * uq[i];
         a[c] = acc;
     }
-    const double wq = S.tab.w[qi[0]] * S.tab.w[qi[1]] * S.tab.w[qi[2]];
     double face[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-    for (int f = 0; f < 6; ++f) {
-        const int d = f >> 1, s = f & 1;
-        const int ne = neighbour(S, e, ijk, d, s);
-        if (ne < 0) continue;                    // wall: {w} = g_u = 0
-        FacePoint fp;
+    for (int fc = 0; fc < 6; ++fc) {
+        const int d = fc >> 1, s = fc & 1;
         const int ta = d == 0 ? 1 : 0, tb = d == 2 ? 1 : 2;
-        face_point(S, m, d, s, qi[ta], qi[tb], fp);
-        const double* un = u + (long long)ne * 3 * N3;
-        double um[3], up[3];
+        const double sc = S.tab.S[s][qi[d]];
+        const double* F = FF[fc][qi[tb] * N + qi[ta]];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const int base = c * N3 + t - qi[d] * str[d];
-            double sm = 0.0, sp = 0.0;
-#pragma unroll
-            for (int k = 0; k < N; ++k) {
-                sm += S.tab.S[s][k] * U[base + k * str[d]];
-                sp += S.tab.S[1 - s][k] * un[base + k * str[d]];
-            }
-            um[c] = sm;
-            up[c] = sp;
-        }
-        const double wn = 0.5 * ((um[0] + up[0]) * fp.n[0] + (um[1] + up[1]) * fp.n[1] + (um[2] + up[2]) * fp.n[2]);
-        if (wn < 0.0) {                          // inflow: u_dag = u+
-            const double sc = S.tab.S[s][qi[d]] * fp.ds * wn;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) face[c] += sc * (up[c] - um[c]);
-        }
+        for (int c = 0; c < 3; ++c) face[c] += sc * F[c];
     }
+    const double wq = S.tab.w[qi[0]] * S.tab.w[qi[1]] * S.tab.w[qi[2]];
     const double inv_m = 1.0 / (wq * det);
     double* out = uhat + (long long)e * 3 * N3;
     const double* be = b ? b + (long long)e * 3 * N3 : nullptr;
@@ -269,7 +302,7 @@ __device__ __forceinline__ double ppe_face(const SplitGeo& S, const CellMap& m, 
 }
 
 template <int N>
-__global__ void __launch_bounds__(kThreads) k_split_ppe_rhs(SplitGeo S, const double* __restrict__ uhat,
+__global__ void __launch_bounds__(kFaceThreads<N>) k_split_ppe_rhs(SplitGeo S, const double* __restrict__ uhat,
                                                             const double* __restrict__ u_old,
                                                             const double* __restrict__ b, double dt,
                                                             double* __restrict__ f) {
@@ -380,7 +413,7 @@ __device__ __forceinline__ void proj_face(const SplitGeo& S, const CellMap& m, i
 }
 
 template <int N>
-__global__ void __launch_bounds__(kThreads) k_split_projection(SplitGeo S, const double* __restrict__ uhat,
+__global__ void __launch_bounds__(kFaceThreads<N>) k_split_projection(SplitGeo S, const double* __restrict__ uhat,
                                                                const double* __restrict__ p, double dt,
                                                                double* __restrict__ uhh, double* __restrict__ rhs) {
     constexpr int N2 = N * N, N3 = N2 * N, NP = N - 1, NP3 = NP * NP * NP;
@@ -457,7 +490,7 @@ __global__ void __launch_bounds__(kThreads) k_split_projection(SplitGeo S, const
 }
 
 template <int N>
-__global__ void __launch_bounds__(kThreads) k_split_mass(SplitGeo S, const double* __restrict__ x, double scale,
+__global__ void __launch_bounds__(kCellThreads<N>) k_split_mass(SplitGeo S, const double* __restrict__ x, double scale,
                                                          double* __restrict__ y) {
     constexpr int N2 = N * N, N3 = N2 * N;
     const int e = blockIdx.x, t = threadIdx.x;
@@ -476,11 +509,12 @@ __global__ void __launch_bounds__(kThreads) k_split_mass(SplitGeo S, const doubl
 }
 
 template <int N>
-__global__ void __launch_bounds__(kThreads) k_pen_factors(SplitGeo S, const double* __restrict__ u, double dt,
+__global__ void __launch_bounds__(kCellThreads<N>) k_pen_factors(SplitGeo S, const double* __restrict__ u, double dt,
                                                           double zeta, const double* __restrict__ hcell,
                                                           double* __restrict__ tau_div, double* __restrict__ tau_cont) {
     constexpr int N2 = N * N, N3 = N2 * N;
-    __shared__ double sw[kThreads], su[kThreads];
+    constexpr int B = kCellThreads<N>;
+    __shared__ double sw[B], su[B];
     const int e = blockIdx.x, t = threadIdx.x;
     double jw = 0.0, js = 0.0;
     if (t < N3) {
@@ -499,7 +533,7 @@ __global__ void __launch_bounds__(kThreads) k_pen_factors(SplitGeo S, const doub
     sw[t] = jw;
     su[t] = js;
     __syncthreads();
-    for (int w = kThreads / 2; w > 0; w >>= 1) {   // fixed-order tree: deterministic
+    for (int w = B / 2; w > 0; w >>= 1) {          // fixed-order tree: deterministic
         if (t < w) {
             sw[t] += sw[t + w];
             su[t] += su[t + w];
@@ -516,13 +550,15 @@ __global__ void __launch_bounds__(kThreads) k_pen_factors(SplitGeo S, const doub
 template <int N>
 hipError_t launch_n(int which, const SplitGeo& S, const double* a0, const double* a1, const double* a2, double s0,
                     double s1, double* o0, double* o1, hipStream_t s) {
-    const dim3 grid((unsigned)(S.nx * S.ny * S.nz)), block(kThreads);
+    const dim3 grid((unsigned)(S.nx * S.ny * S.nz)), cb(kCellThreads<N>), fb(kFaceThreads<N>);
+    static_assert(kCellThreads<N> >= N * N * N && kFaceThreads<N> >= 6 * N * N && kFaceThreads<N> >= N * N * N,
+                  "a workgroup must cover the cell's nodes and face points");
     switch (which) {
-        case 0: hipLaunchKernelGGL(k_split_convective<N>, grid, block, 0, s, S, a0, a1, s0, o0); break;
-        case 1: hipLaunchKernelGGL(k_split_ppe_rhs<N>, grid, block, 0, s, S, a0, a1, a2, s0, o0); break;
-        case 2: hipLaunchKernelGGL(k_split_projection<N>, grid, block, 0, s, S, a0, a1, s0, o0, o1); break;
-        case 3: hipLaunchKernelGGL(k_split_mass<N>, grid, block, 0, s, S, a0, s0, o0); break;
-        case 4: hipLaunchKernelGGL(k_pen_factors<N>, grid, block, 0, s, S, a0, s0, s1, a1, o0, o1); break;
+        case 0: hipLaunchKernelGGL(k_split_convective<N>, grid, fb, 0, s, S, a0, a1, s0, o0); break;
+        case 1: hipLaunchKernelGGL(k_split_ppe_rhs<N>, grid, fb, 0, s, S, a0, a1, a2, s0, o0); break;
+        case 2: hipLaunchKernelGGL(k_split_projection<N>, grid, fb, 0, s, S, a0, a1, s0, o0, o1); break;
+        case 3: hipLaunchKernelGGL(k_split_mass<N>, grid, cb, 0, s, S, a0, s0, o0); break;
+        case 4: hipLaunchKernelGGL(k_pen_factors<N>, grid, cb, 0, s, S, a0, s0, s1, a1, o0, o1); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
