@@ -140,6 +140,11 @@ typedef struct {
                                   graph (per plan: chunk length, x, precision, preconditioner; two cached)
                                   and replayed, for problems small enough to be launch-bound; results are
                                   the same as without (same kernels, same order) */
+    int32_t reuse_eigs;        /* nonzero: eigenvalue estimates made before a viscosity or penalty-factor
+                                  update (sipg_update_viscosity, sipg_update_penalty_factors) are kept for
+                                  the changed operator instead of being re-estimated (a preconditioner
+                                  refreshed less often than the operator, as in time-stepping codes);
+                                  zero (default): re-estimated on the next solve */
 } sipg_solve_opts;
 
 /* Preconditioner of the FP64 CG (Sec. 5.3): Chebyshev-accelerated Jacobi on
@@ -302,8 +307,9 @@ sipg_status sipg_solve_poll(sipg_plan* plan, int32_t* done, sipg_solve_info* inf
  * multigrid level evaluates the same velocity at its own quadrature points
  * (a coarse point lies in one fine cell through the nesting of the
  * reference cells).  Then recomputes every level's diagonal and inverse
- * diagonal (FP64 and FP32) and drops the cached eigenvalue estimates, so
- * the next solve re-estimates them.  Needs a bound plan; stream-ordered;
+ * diagonal (FP64 and FP32) and marks the cached eigenvalue estimates
+ * stale, so the next solve re-estimates them (unless its opts->reuse_eigs
+ * keeps them).  Needs a bound plan; stream-ordered;
  * no solve may be in progress. */
 sipg_status sipg_update_viscosity(sipg_plan* plan, const double* u, void* stream);
 
@@ -393,8 +399,10 @@ sipg_status sipg_projection(sipg_plan* vel, sipg_plan* pres, const double* uhat,
 /* Recomputes a penalty-step plan's per-cell factors from the velocity u:
  * tau_div = zeta |u_e| h_e dt/(k+1), tau_cont = zeta |u_e| dt (|u_e| the
  * volume mean of |u| over the cell, h_e = |cell|^(1/3)), then its face
- * factors and diagonal, and drops its cached eigenvalue estimate.  Needs a
- * bound plan without a multigrid hierarchy and no solve in progress. */
+ * factors and diagonal, and marks its cached eigenvalue estimate stale (as
+ * sipg_update_viscosity does).  Needs a bound plan without a multigrid
+ * hierarchy and no solve in progress.  A later sipg_plan_bind restores the
+ * factors given at creation. */
 sipg_status sipg_update_penalty_factors(sipg_plan* pen, const double* u, double dt, double zeta, void* stream);
 
 typedef struct {

@@ -54,7 +54,8 @@ class SolveOpts(C.Structure):
     _fields_ = [("rel_tol", C.c_double), ("max_iter", C.c_int32), ("precond_precision", C.c_int32),
                 ("cheb_degree", C.c_int32), ("cheb_ratio", C.c_double), ("cheb_safety", C.c_double),
                 ("lanczos_steps", C.c_int32), ("check_every", C.c_int32), ("max_restarts", C.c_int32),
-                ("precond_kind", C.c_int32), ("use_graph", C.c_int32)]
+                ("precond_kind", C.c_int32), ("use_graph", C.c_int32),
+                ("reuse_eigs", C.c_int32)]
 
 
 class MgOpts(C.Structure):

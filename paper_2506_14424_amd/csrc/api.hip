@@ -145,7 +145,8 @@ struct sipg_plan {
     int phase = PH_IDLE;
     int restarts = 0;
     bool mean_zero = false;
-    bool lz_valid = false;
+    bool lz_valid = false;               // eigenvalue estimates exist (lz_steps Lanczos steps)
+    bool lz_stale = false;               // ... but the operator changed since (viscosity, penalty factors)
     int lz_steps = 0;
     sipg_solve_info info;
 
@@ -500,6 +501,7 @@ sipg_status run_lanczos(sipg_plan* P, hipStream_t s) {
     sk_lz_eig(P->st, s);
     HIP_TRY(hipGetLastError());
     P->lz_valid = true;
+    P->lz_stale = false;
     P->lz_steps = P->opts.lanczos_steps;
     return SIPG_OK;
 }
@@ -576,7 +578,7 @@ sipg_status update_viscosity(sipg_plan* P, const double* u, hipStream_t s) {
         HIP_TRY(launch_picard_viscosity(F, Lv, L->law, L->nface, L->mu_cell64, L->mu_cell32, L->mu_face64,
                                         L->mu_face32, s));
         HIP_TRY(launch_diagonal(L->n, L->C, L->curved, L->opdata<double>(), L->diag64, L->dinv64, L->dinv32, s));
-        L->lz_valid = false;
+        L->lz_stale = true;
     }
     return SIPG_OK;
 }
@@ -591,7 +593,7 @@ sipg_status prepare_precond(sipg_plan* P, hipStream_t s) {
     for (int l = 0; l < nl; ++l) {
         sipg_plan* L = mg_level(P, l);
         if (l > 0) L->opts = o;
-        if (!L->lz_valid || L->lz_steps != o.lanczos_steps) {
+        if (!L->lz_valid || L->lz_steps != o.lanczos_steps || (L->lz_stale && !o.reuse_eigs)) {
             const sipg_status rc = run_lanczos(L, s);
             if (rc != SIPG_OK) return rc;
         }
@@ -922,6 +924,7 @@ void sipg_solve_opts_default(sipg_solve_opts* o) {
     o->max_restarts = 3;
     o->precond_kind = SIPG_PRECOND_CHEBYSHEV;
     o->use_graph = 0;
+    o->reuse_eigs = 0;
 }
 
 void sipg_mg_opts_default(sipg_mg_opts* o) {
@@ -1444,7 +1447,7 @@ sipg_status sipg_update_penalty_factors(sipg_plan* P, const double* u, double dt
     HIP_TRY(launch_setup(P->n, P->C, P->curved, od, P->law, P->penalty, P->hcell, P->tfac64, P->tfac32, P->mu_cell64,
                          P->mu_cell32, P->mu_face64, P->mu_face32, (int)P->nface, P->tau_div_d, P->tau_cont_d, s));
     HIP_TRY(launch_diagonal(P->n, P->C, P->curved, P->opdata<double>(), P->diag64, P->dinv64, P->dinv32, s));
-    P->lz_valid = false;
+    P->lz_stale = true;
     return SIPG_OK;
 }
 

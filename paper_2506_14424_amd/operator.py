@@ -23,6 +23,7 @@ class SolveOptions:
     max_restarts: int = 3
     precond: str = "chebyshev"       # or "multigrid" (after Operator.set_multigrid)
     use_graph: bool = False          # replay captured HIP graphs of the iteration chunks
+    reuse_eigs: bool = False         # keep eigenvalue estimates across viscosity / penalty-factor updates
 
     def to_c(self) -> F.SolveOpts:
         o = F.SolveOpts()
@@ -37,6 +38,7 @@ class SolveOptions:
         o.max_restarts = self.max_restarts
         o.precond_kind = F.PRECOND[self.precond]
         o.use_graph = int(self.use_graph)
+        o.reuse_eigs = int(self.reuse_eigs)
         return o
 
 

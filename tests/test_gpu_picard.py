@@ -168,3 +168,34 @@ def test_full_size_c7_picard():
     ef = rel(mf, PC.generalized_newtonian(law, gf[faces]))
     say(f"   sampled viscosity err: cells {ec:.2e}, faces {ef:.2e}; mu in [{mc.min():.3f}, {mc.max():.3f}]")
     assert ec <= 1e-12 and ef <= 1e-12
+
+
+def test_reuse_eigs_keeps_the_estimates():
+    """A viscosity update marks the eigenvalue estimates stale: a solve with
+    reuse_eigs keeps them, one without re-estimates; the Picard iteration
+    with multigrid and reused estimates reaches the same fixed point."""
+    cfg, V = case(3, 3, 3, 2)
+    op = Operator.from_config(cfg, V).bind(with_solver=True)
+    b = torch.from_numpy(W.uniform_vector(7, op.ndof)).cuda()
+    u = torch.from_numpy(velocity(3, op.ndof, 2.0)).cuda()
+    _, i0 = op.solve(b, opts=SolveOptions(rel_tol=1e-8))
+    op.update_viscosity(u)
+    _, i1 = op.solve(b, opts=SolveOptions(rel_tol=1e-8, reuse_eigs=True))
+    _, i2 = op.solve(b, opts=SolveOptions(rel_tol=1e-8))
+    _, i3 = op.solve(b, opts=SolveOptions(rel_tol=1e-8, reuse_eigs=True))
+    say(f"[reuse eigs] lambda before {i0['lambda_max']:.6f}, kept {i1['lambda_max']:.6f}, "
+        f"re-estimated {i2['lambda_max']:.6f}, {i3['lambda_max']:.6f}")
+    assert all(i["status"] == "SIPG_OK" for i in (i0, i1, i2, i3))
+    assert i1["lambda_max"] == i0["lambda_max"] and i2["lambda_max"] != i0["lambda_max"]
+    assert i3["lambda_max"] == i2["lambda_max"]
+    cfg, V = case(4, 4, 4, 3)
+    rhs = torch.from_numpy(W.uniform_vector(7, W.ndofs(cfg)) * 100.0 * 10.0 / (64 * 64)).cuda()
+    out = {}
+    for reuse in (False, True):
+        mg = Operator.from_config(cfg, V).set_multigrid(min_cells=1).bind(with_solver=True)
+        lin = SolveOptions(rel_tol=1e-3, precond="multigrid", cheb_degree=3, reuse_eigs=reuse)
+        out[reuse] = mg.picard_solve(rhs, opts=lin, rel_tol=1e-8, max_iter=60)
+        say(f"   picard reuse_eigs={reuse}: {out[reuse][1]['iterations']} its, "
+            f"{out[reuse][1]['linear_iterations']} CG")
+        assert out[reuse][1]["status"] == "SIPG_OK"
+    assert rel(out[True][0].cpu().numpy(), out[False][0].cpu().numpy()) <= 1e-6

@@ -23,6 +23,8 @@ if not torch.cuda.is_available():
 from oracle import splitting as SP  # noqa: E402
 from oracle.forms import Problem, apply as oracle_apply, diagonal as oracle_diagonal, interpolate  # noqa: E402
 from oracle.mesh import Mesh  # noqa: E402
+from dataclasses import replace  # noqa: E402
+
 from paper_2506_14424_amd import SolveOptions, SplitOptions, SplitStep  # noqa: E402
 
 
@@ -170,3 +172,22 @@ def test_full_size_properties():
     e4 = rel(got[lo + 1:lo + 3, lo + 1:lo + 3, lo + 1:lo + 3], ref[1:3, 1:3, 1:3])
     say(f"   sampled interior block vs oracle {e4:.2e}")
     assert e4 <= 1e-12
+
+
+def test_second_step_with_reused_estimates():
+    """Two steps: the second with the viscous and penalty solves keeping the
+    first step's eigenvalue estimates (reuse_eigs) equals the second step
+    with fresh estimates to the solves' tolerance."""
+    st, pb, law, V = make((3, 2, 2), 3, 0.1)
+    x = W.node_positions(3, 2, 2, 3, V)
+    u = dev(np.transpose(6.4 * np.prod(x * (1 - x), -1)[..., None] * np.stack(
+        [np.sin(np.pi * x[..., 1]), np.cos(np.pi * x[..., 2]), x[..., 0]], -1), (0, 2, 1)).reshape(-1))
+    b = dev(W.uniform_vector(7, pb.ndof))
+    u1, _, _ = st.step(u, b, opts=TIGHT)
+    r = replace(_T, reuse_eigs=True)
+    u2r, p2r, ir = st.step(u1, b, opts=SplitOptions(pressure=_T, viscous=r, penalty=r))
+    u2, p2, i2 = st.step(u1, b, opts=TIGHT)
+    say(f"[split reuse] iterations fresh {[v['iterations'] for v in i2.values()]}, "
+        f"reused {[v['iterations'] for v in ir.values()]}")
+    assert all(v["status"] == "SIPG_OK" for v in ir.values())
+    assert rel(host(u2r), host(u2)) <= 1e-9 and rel(host(p2r), host(p2)) <= 1e-9

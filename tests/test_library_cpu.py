@@ -34,6 +34,7 @@ def test_abi_version_and_defaults():
     o = F.SolveOpts()
     F.lib.sipg_solve_opts_default(C.byref(o))
     assert o.rel_tol == 1e-8 and o.cheb_degree == 5 and o.precond_precision == F.F32
+    assert o.use_graph == 0 and o.reuse_eigs == 0
 
 
 def test_plan_counts_and_workspace_on_cpu():
