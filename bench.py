@@ -223,7 +223,8 @@ def picard_step(tol=1e-8):
     """c7: the nonlinear viscous step (viscosity from the velocity, Picard
     iterations) with and without Aitken relaxation, linear solves to 1e-3 with
     FP32 hp-multigrid, re-estimating the smoothers' eigenvalues after every
-    viscosity update or (aitken_reuse_eigs) keeping the first ones; plus the
+    viscosity update or (aitken_reuse_eigs) keeping the estimates the plan
+    already holds (here: from the warm-up run); plus the
     viscosity update alone (all levels and their diagonals)."""
     import torch
     import workloads as W
@@ -344,7 +345,9 @@ def split_step(reps=5, tol=1e-8):
             "step_seconds": step_s,
             "step_seconds_reuse_eigs": step_reuse_s,
             "reuse_eigs_note": "viscous and penalty solves keep the eigenvalue estimates of an earlier "
-                               "step (the preconditioner refreshed less often than the operator)",
+                               "step (the preconditioner refreshed less often than the operator); every "
+                               "timed step starts from the same u^n, so here the kept estimates are those "
+                               "of the same operator",
             "reuse_eigs_rel_diff_u": reuse_diff,
             "iterations": {k: v["iterations"] for k, v in info.items()},
             "status": {k: v["status"] for k, v in info.items()},
