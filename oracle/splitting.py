@@ -13,8 +13,10 @@ Scope and readings taken here:
   * BDF1 (m = 1): gamma_0 = alpha_0 = beta_0 = 1, and m_p = min(m - 1, 2) = 0,
     so the extrapolated convective and viscous terms of h_p are empty sums
     (no vorticity is needed for this order);
-  * every boundary is a no-slip wall: velocity Dirichlet with g_u = 0 (so
-    d_t g_u = 0), pressure Neumann with h_p of eq. pressure_Neumann_BC; the
+  * every boundary is a wall with velocity Dirichlet data g_u constant in
+    time (d_t g_u = 0; g_u = 0 for no-slip, a moving lid otherwise), given
+    at the velocity's face quadrature points of the boundary faces (layout of
+    ``wall_rows``), pressure Neumann with h_p of eq. pressure_Neumann_BC; the
     pressure level is fixed by removing the mean of the right-hand side and
     taking the solution of zero nodal mean;
   * the body force b is given as nodal values of DG_k (constant in time);
@@ -24,6 +26,9 @@ Scope and readings taken here:
   * the convective term is (w . grad) u (the paper's notation) with the
     upwind flux u_dag = {u} + sign({w}.n) [u]_oriented / 2 and the mirror
     principle on the walls (u+ = 2 g_u - u-, w+ likewise);
+  * the data enter the viscous step's right-hand side through the mirror
+    principle of the SIPG form (the load of ``forms.load_vector``) and the
+    penalty step's through its oriented jump u - g_u on the walls;
   * [c(u, u)]^# in g_uhat on the walls is evaluated from the interior trace
     of u^n and of its gradient;
   * viscosity linear implicit, nu^# = eta(gdot(grad^S u^#)) with u^# = u^n
@@ -41,7 +46,8 @@ import scipy.sparse.linalg as spla
 
 from . import picard as PC
 from .basis import cell_points, face_points, tensor_tables
-from .forms import Problem, _cell_geo, _face_geo, _phys_grad, _test_project, assemble, cell_sizes
+from .forms import (Problem, _cell_geo, _face_geo, _mu_face, _phys_grad, _sym, _tau, _tau_face, _test_project,
+                    assemble, cell_sizes)
 from .mesh import Mesh
 
 # BDF1 coefficients (m = 1)
@@ -57,6 +63,32 @@ def pressure_problem(mesh: Mesh, degree_u: int) -> Problem:
 def _walls(pb: Problem):
     if any(b != "D" for b in pb.mesh.bc):
         raise ValueError("the splitting step is defined here for no-slip walls on every side")
+
+
+def wall_rows(mesh: Mesh) -> dict:
+    """Rows of the wall-data array per wall (d, side): sides in the order
+    -x, +x, -y, +y, -z, +z, each side's faces in the order of
+    ``mesh.boundary_cells(d, side)``; each row holds the n^2 face points
+    (index b n + a, a along the lower tangential axis) times 3 components."""
+    sizes = (mesh.ny * mesh.nz, mesh.nx * mesh.nz, mesh.nx * mesh.ny)
+    out, off = {}, 0
+    for d in range(3):
+        for side in (0, 1):
+            out[(d, side)] = slice(off, off + sizes[d])
+            off += sizes[d]
+    return out
+
+
+def wall_count(mesh: Mesh) -> int:
+    return 2 * (mesh.ny * mesh.nz + mesh.nx * mesh.nz + mesh.nx * mesh.ny)
+
+
+def _wall_g(pb: Problem, g_wall, d: int, side: int) -> np.ndarray:
+    """g_u at the face points of wall (d, side): (cells, n^2, 3)."""
+    rows = wall_rows(pb.mesh)[(d, side)]
+    if g_wall is None:
+        return np.zeros((rows.stop - rows.start, pb.n ** 2, 3))
+    return np.asarray(g_wall, dtype=np.float64).reshape(wall_count(pb.mesh), pb.n ** 2, 3)[rows]
 
 
 def _values(pb: Problem, X, V):
@@ -102,9 +134,10 @@ def _upwind_face(um, up, wm, wp, nrm):
     return wn[..., None] * (udag - um)
 
 
-def convective_form(pb: Problem, u, w) -> np.ndarray:
+def convective_form(pb: Problem, u, w, g_wall=None) -> np.ndarray:
     """c_h(phi_I, u; w) summed over the cells, for every test function:
-    (v, (w . grad) u)_e - (v, ({w}.n) u)_de + (v, ({w}.n) u_dag)_de."""
+    (v, (w . grad) u)_e - (v, ({w}.n) u)_de + (v, ({w}.n) u_dag)_de; on the
+    walls u+ = 2 g_u - u-, w+ = 2 g_u - w-."""
     _walls(pb)
     mesh, n = pb.mesh, pb.n
     U = np.asarray(u, dtype=np.float64).reshape(mesh.ncells, 3, n ** 3)
@@ -130,20 +163,22 @@ def convective_form(pb: Problem, u, w) -> np.ndarray:
             zero = np.zeros(um.shape + (3,))
             Y[em] += _test_project(Vm, Gm, Jim, _upwind_face(um, up, wm, wp, nrm), zero, ds)
             Y[ep] += _test_project(Vp, Gp, Jip, _upwind_face(up, um, wp, wm, -nrm), zero, ds)
-        for side in (0, 1):                                        # walls: mirror with g_u = 0
+        for side in (0, 1):                                        # walls: mirror principle
             bc = mesh.boundary_cells(d, side)
             Vf, Gf = tensor_tables(n, face_points(n, d, side)[0])
             _, _, Ji, nrm, ds = _face_geo(pb, bc, d, side)
             ui, wi = _values(pb, U[bc], Vf), _values(pb, W[bc], Vf)
-            Y[bc] += _test_project(Vf, Gf, Ji, _upwind_face(ui, -ui, wi, -wi, nrm), np.zeros(ui.shape + (3,)), ds)
+            g = _wall_g(pb, g_wall, d, side)
+            Y[bc] += _test_project(Vf, Gf, Ji, _upwind_face(ui, 2 * g - ui, wi, 2 * g - wi, nrm),
+                                   np.zeros(ui.shape + (3,)), ds)
     return Y.reshape(-1)
 
 
-def convective_step(pb: Problem, u, b, dt: float) -> np.ndarray:
+def convective_step(pb: Problem, u, b, dt: float, g_wall=None) -> np.ndarray:
     """uhat from eq. convective_step_weak:
     (gamma_0/dt)(v, uhat) = (v, b) + (alpha_0/dt)(v, u^n) - beta_0 c_h(v, u^n; u^n)."""
     u = np.asarray(u, dtype=np.float64)
-    rhs = mass_apply(pb, b) + ALPHA0 / dt * mass_apply(pb, u) - BETA0 * convective_form(pb, u, u)
+    rhs = mass_apply(pb, b) + ALPHA0 / dt * mass_apply(pb, u) - BETA0 * convective_form(pb, u, u, g_wall)
     return dt / GAMMA0 * mass_solve(pb, rhs)
 
 
@@ -151,7 +186,7 @@ def convective_step(pb: Problem, u, b, dt: float) -> np.ndarray:
 # pressure step (eqs. pressure_step_weak, guhat_consistent_BC, pressure_Neumann_BC)
 # ---------------------------------------------------------------------------
 
-def wall_data(pb: Problem, u_old, b, dt: float, d: int, side: int):
+def wall_data(pb: Problem, u_old, b, dt: float, d: int, side: int, g_wall=None):
     """On the wall xi_d = side: g_uhat and h_p at the face points of the
     boundary cells, with u^n and b taken from the interior traces.
     g_uhat = (dt/gamma_0) (b - beta_0 (grad u^n) u^n) + (alpha_0/gamma_0) g_u,
@@ -164,8 +199,8 @@ def wall_data(pb: Problem, u_old, b, dt: float, d: int, side: int):
     _, _, Ji, nrm, ds = _face_geo(pb, bc, d, side)
     ui, bi = _values(pb, U[bc], Vf), _values(pb, B[bc], Vf)
     conv = np.einsum("epci,epi->epc", _phys_grad(U[bc], Gf, Ji), ui)
-    g_u = np.zeros_like(ui)
-    dt_g_u = np.zeros_like(ui)
+    g_u = _wall_g(pb, g_wall, d, side)
+    dt_g_u = np.zeros_like(ui)                                   # data constant in time
     g_uhat = dt / GAMMA0 * (bi - BETA0 * conv) + ALPHA0 / GAMMA0 * g_u
     h_p = np.einsum("epc,epc->ep", nrm, bi) - np.einsum("epc,epc->ep", nrm, dt_g_u)
     return bc, g_uhat, h_p
@@ -224,12 +259,12 @@ def wall_neumann_form(pb_u: Problem, pb_p: Problem, h_value) -> np.ndarray:
     return F.reshape(-1)
 
 
-def ppe_rhs(pb_u: Problem, pb_p: Problem, uhat, u_old, b, dt: float) -> np.ndarray:
+def ppe_rhs(pb_u: Problem, pb_p: Problem, uhat, u_old, b, dt: float, g_wall=None) -> np.ndarray:
     """Right-hand side of eq. pressure_step_weak with the wall data moved
     over: (gamma_0/dt) [(grad q, uhat) - (q, {uhat}.n)] + (q, h_p)_walls,
     {uhat} = g_uhat on the walls (mirror principle)."""
     _walls(pb_u)
-    data = {(d, s): wall_data(pb_u, u_old, b, dt, d, s) for d in range(3) for s in (0, 1)}
+    data = {(d, s): wall_data(pb_u, u_old, b, dt, d, s, g_wall) for d in range(3) for s in (0, 1)}
     div = divergence_form(pb_u, pb_p, uhat, lambda d, s: data[(d, s)][1])
     return GAMMA0 / dt * div + wall_neumann_form(pb_u, pb_p, lambda d, s: data[(d, s)][2])
 
@@ -317,7 +352,46 @@ def penalty_factors(pb: Problem, u, dt: float, zeta: float = 1.0):
     return zeta * ue * h * dt / (pb.degree + 1), zeta * ue * dt
 
 
-def split_step(pb_visc: Problem, law: dict, u_old, b, dt: float, zeta: float = 1.0) -> dict:
+def viscous_wall_load(pb: Problem, g_wall) -> np.ndarray:
+    """The viscous step's load of the wall data (mirror principle of the
+    SIPG form): int -2 mu eps(v):(g (x) n) + 2 tau (v.g + (v.n)(g.n)) over the
+    walls, mu the problem's viscosity at the face points."""
+    mesh, n = pb.mesh, pb.n
+    Y = np.zeros((mesh.ncells, 3, n ** 3))
+    h = cell_sizes(pb)
+    for d in range(3):
+        for side in (0, 1):
+            bc = mesh.boundary_cells(d, side)
+            Vf, Gf = tensor_tables(n, face_points(n, d, side)[0])
+            _, xq, Ji, nrm, ds = _face_geo(pb, bc, d, side)
+            mu = _mu_face(pb, d, bc, side, xq)
+            tau = _tau(pb, mu, h[bc])
+            g = _wall_g(pb, g_wall, d, side)
+            gn = np.einsum("epc,epc->ep", g, nrm)
+            a = 2.0 * tau[..., None] * (g + nrm * gn[..., None])
+            B = -2.0 * mu[..., None, None] * _sym(g[..., :, None] * nrm[..., None, :])
+            Y[bc] += _test_project(Vf, Gf, Ji, a, B, ds)
+    return Y.reshape(-1)
+
+
+def penalty_wall_load(pb: Problem, g_wall) -> np.ndarray:
+    """The penalty step's load of the wall data: int tau_e (v.n)(g.n) over
+    the walls (oriented jump u - g with the cell's own continuity factor)."""
+    mesh, n = pb.mesh, pb.n
+    Y = np.zeros((mesh.ncells, 3, n ** 3))
+    for d in range(3):
+        for side in (0, 1):
+            bc = mesh.boundary_cells(d, side)
+            Vf, Gf = tensor_tables(n, face_points(n, d, side)[0])
+            _, _, Ji, nrm, ds = _face_geo(pb, bc, d, side)
+            g = _wall_g(pb, g_wall, d, side)
+            tf = _tau_face(pb, bc)[:, None]
+            a = tf[..., None] * nrm * np.einsum("epc,epc->ep", g, nrm)[..., None]
+            Y[bc] += _test_project(Vf, Gf, Ji, a, np.zeros(a.shape + (3,)), ds)
+    return Y.reshape(-1)
+
+
+def split_step(pb_visc: Problem, law: dict, u_old, b, dt: float, zeta: float = 1.0, g_wall=None) -> dict:
     """One BDF1 step of Alg. 1 with linear-implicit viscosity: convective
     step, pressure step, projection, viscous step, penalty step.  pb_visc is
     the viscous problem with alpha = gamma_0/dt on the velocity mesh (no-slip
@@ -325,14 +399,19 @@ def split_step(pb_visc: Problem, law: dict, u_old, b, dt: float, zeta: float = 1
     if abs(pb_visc.alpha * dt - GAMMA0) > 1e-12 * GAMMA0:
         raise ValueError("the viscous problem's mass coefficient must be gamma_0/dt")
     pb_p = pressure_problem(pb_visc.mesh, pb_visc.degree)
-    uhat = convective_step(pb_visc, u_old, b, dt)
-    f = ppe_rhs(pb_visc, pb_p, uhat, u_old, b, dt)
+    uhat = convective_step(pb_visc, u_old, b, dt, g_wall)
+    f = ppe_rhs(pb_visc, pb_p, uhat, u_old, b, dt, g_wall)
     p = pressure_solve(pb_p, f)
     uhh, rhs_v = projection(pb_visc, pb_p, uhat, p, dt)
     pb_v = PC.with_velocity_viscosity(pb_visc, pb_visc, u_old, law)
+    if g_wall is not None:
+        rhs_v = rhs_v + viscous_wall_load(pb_v, g_wall)
     u_visc = spla.spsolve(assemble(pb_v).tocsc(), rhs_v)
     td, tc = penalty_factors(pb_visc, u_old, dt, zeta)
     pb_pen = Problem(pb_visc.mesh, pb_visc.degree, "penalty", 1.0, 1.0, tau_div=td, tau_cont=tc)
-    u_new = spla.spsolve(assemble(pb_pen).tocsc(), mass_apply(pb_pen, u_visc))
+    rhs_pen = mass_apply(pb_pen, u_visc)
+    if g_wall is not None:
+        rhs_pen = rhs_pen + penalty_wall_load(pb_pen, g_wall)
+    u_new = spla.spsolve(assemble(pb_pen).tocsc(), rhs_pen)
     return {"uhat": uhat, "ppe_rhs": f, "p": p, "uhh": uhh, "rhs_visc": rhs_v, "u_visc": u_visc,
             "tau_div": td, "tau_cont": tc, "u_new": u_new, "pb_p": pb_p}

@@ -9,8 +9,11 @@ of each pressure basis function; the pressure right-hand side sums to the
 wall flux of (grad u) u, i.e. tr(B^2) for u = B x + d; the projection of a
 linear pressure removes its constant gradient and a piecewise-constant
 pressure acts through half its jump; the penalty factors of a constant
-velocity; and the whole step keeps a fluid at rest under a gradient body
-force with the hydrostatic pressure."""
+velocity; the whole step keeps a fluid at rest under a gradient body
+force with the hydrostatic pressure; and with velocity data on the walls:
+the viscous load equals the forms' SIPG load vector, a uniform flow through
+the box stays uniform with zero pressure, the inflow flux of a wall, and the
+penalty step's wall load in closed form."""
 import numpy as np
 import pytest
 from scipy.interpolate import lagrange
@@ -237,3 +240,90 @@ def test_penalty_factor_speed_is_the_volume_mean():
     hx = 1.6 / nx
     a = hx * (np.arange(m.ncells) % nx)
     assert np.allclose(tc, (a ** 2 + a * hx + hx ** 2 / 3) * dt, rtol=1e-13, atol=0)
+
+
+def _g_wall_from(pb, fn):
+    """Wall-data array of the callable fn at the walls' face points."""
+    from oracle.forms import _face_geo
+    rows = SP.wall_rows(pb.mesh)
+    g = np.zeros((SP.wall_count(pb.mesh), pb.n ** 2, 3))
+    for (d, side), sl in rows.items():
+        _, xq, _, _, _ = _face_geo(pb, pb.mesh.boundary_cells(d, side), d, side)
+        g[sl] = fn(xq.reshape(-1, 3)).reshape(xq.shape)
+    return g.reshape(-1)
+
+
+def test_viscous_wall_load_equals_the_forms_load():
+    """The wall-data load of the viscous step equals the SIPG load vector of
+    the forms (pinned there by patch tests with inhomogeneous data)."""
+    from oracle import picard as PC
+    from oracle.forms import load_vector
+    pb = velocity_problem(3, 2, 2, 3, 0.1)
+    pbv = PC.with_velocity_viscosity(pb, pb, W.uniform_vector(3, pb.ndof), W.carreau_law(3))
+    fn = linear(A, c0)
+    ref = load_vector(pbv, lambda x: np.zeros_like(x), fn)
+    got = SP.viscous_wall_load(pbv, _g_wall_from(pbv, fn))
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("perturb,deg", [(0.0, 2), (0.1, 3)])
+def test_uniform_flow_through_the_box_is_steady(perturb, deg):
+    """u^n = c, g_u = c on every wall (inflow and outflow), b = 0: no
+    convection, a zero pressure, and the viscous (SIPG consistency) and
+    penalty steps (no divergence, no jump against g) return c."""
+    dt = 0.05
+    pb = velocity_problem(2, 2, 2, deg, perturb, dt)
+    c = np.array([0.7, -0.4, 0.25])
+    const = lambda x: np.broadcast_to(c, x.shape)
+    u = interpolate(pb, const)
+    out = SP.split_step(pb, W.carreau_law(3), u, np.zeros(pb.ndof), dt, g_wall=_g_wall_from(pb, const))
+    assert np.abs(out["uhat"] - u).max() <= 1e-13
+    assert np.abs(out["p"]).max() <= 1e-10
+    assert np.abs(out["u_new"] - u).max() <= 1e-10
+    assert np.all(out["tau_div"] > 0)
+
+
+@pytest.mark.parametrize("gx", [0.8, -0.8])
+def test_wall_inflow_flux(gx):
+    """Two cells along x, u = c in both; data g only on the -x wall: the
+    inflow case (g.n < 0) gives l_i1(0) / (hx w_i1) (g.n)(2g - 2c) at the
+    nodes of the first cell, the outflow case nothing."""
+    deg = 3
+    n = deg + 1
+    m = Mesh(2, 1, 1, aniso_box(2, 1, 1, 1.0, 0.7, 1.3))
+    pb = Problem(m, deg, "viscous", 1.0, 1.0)
+    c = np.array([0.3, -0.2, 0.5])
+    g = np.array([gx, 0.4, -0.1])
+    U = np.tile(c[None, :, None], (2, 1, n ** 3)).reshape(-1)
+    gw = np.zeros((SP.wall_count(m), n * n, 3))
+    gw[SP.wall_rows(m)[(0, 0)]] = g
+    got = SP.mass_solve(pb, SP.convective_form(pb, U, U, gw.reshape(-1))).reshape(2, 3, n, n, n)
+    _, w = gauss01(n)
+    l0, _ = ends(n)
+    gn = -g[0]
+    ref = np.zeros_like(got)
+    if gn < 0:
+        ref[0] = (gn * (2 * g - 2 * c))[:, None, None, None] * (l0 / (0.5 * w))[None, None, None, :]
+    scale = max(np.abs(ref).max(), 1.0)
+    assert np.abs(got - ref).max() <= 1e-12 * scale
+
+
+def test_penalty_wall_load_closed_form():
+    """One cell, tau_cont = t: the load of g = (gx, 0, 0) on the -x wall is
+    t (g.n)(v.n) integrated: at node i, -l_i1(0) t gx (-1) hy hz w_i2 w_i3 for
+    the x component, zero elsewhere."""
+    deg = 2
+    n = deg + 1
+    m = Mesh(1, 1, 1, aniso_box(1, 1, 1, 0.6, 0.7, 1.3))
+    t = 0.37
+    pb = Problem(m, deg, "penalty", 1.0, 1.0, tau_div=np.array([0.1]), tau_cont=np.array([t]))
+    gx = 1.3
+    gw = np.zeros((SP.wall_count(m), n * n, 3))
+    gw[SP.wall_rows(m)[(0, 0)], :, 0] = gx
+    got = SP.penalty_wall_load(pb, gw.reshape(-1)).reshape(3, n, n, n)
+    _, w = gauss01(n)
+    l0, _ = ends(n)
+    ref = np.zeros_like(got)
+    # (g.n)(v.n) with n = -e_x: (-gx)(-v_x) = gx v_x
+    ref[0] = t * gx * 0.7 * 1.3 * w[None, :, None] * w[:, None, None] * l0[None, None, :]
+    assert np.abs(got - ref).max() <= 1e-13
