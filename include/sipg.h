@@ -361,7 +361,15 @@ sipg_status sipg_picard_solve(sipg_plan* plan, const double* b, double* x, void*
  * pressure_Neumann_BC, projection_step_weak; the order of Alg. 1), with
  * BDF1 coefficients (gamma_0 = alpha_0 = beta_0 = 1; m_p = 0, so h_p holds
  * no extrapolated convective or viscous terms) on a box whose six sides are
- * no-slip walls (velocity Dirichlet with g_u = 0, pressure Neumann).
+ * walls: velocity Dirichlet data g_u constant in time (g_wall; NULL = no-slip,
+ * g_u = 0), pressure Neumann.
+ *
+ * g_wall: device FP64, the data at the velocity's face quadrature points of
+ * every boundary face: rows for the sides -x, +x, -y, +y, -z, +z in turn
+ * (ny*nz, ny*nz, nx*nz, nx*nz, nx*ny, nx*ny rows), within a side the faces
+ * in the order of their two cell indices along the side (slower: the higher
+ * axis); each row holds the (k+1)^2 face points (b*(k+1) + a, a along the
+ * lower tangential axis) times 3 components.
  *
  * Three plans on the same mesh (same cells and vertices):
  *   vel   SIPG_VISCOUS, degree k in [2, 5], all sides Dirichlet,
@@ -379,16 +387,18 @@ sipg_status sipg_picard_solve(sipg_plan* plan, const double* b, double* x, void*
 /* uhat = (alpha_0/gamma_0) u + (dt/gamma_0)(b - beta_0 M^-1 c_h(u; u)) with
  * c_h(v, u; w) = (v, (w.grad) u)_e - (v, ({w}.n) u)_de + (v, ({w}.n) u_dag)_de,
  * u_dag = {u} + sign({w}.n)(u- - u+)/2 (upwind), mirror principle on the
- * walls (where {w} = 0 removes the face term). */
-sipg_status sipg_convective_step(sipg_plan* vel, const double* u, const double* b, double dt, double* uhat,
-                                 void* stream);
+ * walls (u+ = 2 g_u - u-, w+ = 2 g_u - w-; with g_u = 0, {w} = 0 removes the
+ * face term). */
+sipg_status sipg_convective_step(sipg_plan* vel, const double* u, const double* b, const double* g_wall, double dt,
+                                 double* uhat, void* stream);
 
 /* Right-hand side of the pressure Poisson equation (pres layout):
  * f_q = (gamma_0/dt)[(grad q, uhat)_e - (q, {uhat}.n)_de] + (q, h_p)_walls,
- * with {uhat} = g_uhat = (dt/gamma_0)(b - beta_0 (grad u_old) u_old) on the
- * walls and h_p = n.b, both from interior traces of u_old and b. */
+ * with {uhat} = g_uhat = (dt/gamma_0)(b - beta_0 (grad u_old) u_old) +
+ * (alpha_0/gamma_0) g_u on the walls and h_p = n.b (data constant in time),
+ * both from interior traces of u_old and b. */
 sipg_status sipg_pressure_rhs(sipg_plan* vel, sipg_plan* pres, const double* uhat, const double* u_old,
-                              const double* b, double dt, double* f, void* stream);
+                              const double* b, const double* g_wall, double dt, double* f, void* stream);
 
 /* uhh = uhat + (dt/gamma_0) M^-1 [(div v, p)_e - (v, {p} n)_de] ({p} = p- on
  * the walls) and, if rhs_visc is not NULL, the viscous step's right-hand
@@ -404,6 +414,13 @@ sipg_status sipg_projection(sipg_plan* vel, sipg_plan* pres, const double* uhat,
  * hierarchy and no solve in progress.  A later sipg_plan_bind restores the
  * factors given at creation. */
 sipg_status sipg_update_penalty_factors(sipg_plan* pen, const double* u, double dt, double zeta, void* stream);
+
+/* y += the load of the wall data g_wall for a viscous plan (mirror
+ * principle of the SIPG form, with the plan's current viscosity at the face
+ * points: int -2 mu eps(v):(g (x) n) + 2 tau (v.g + (v.n)(g.n))) or a
+ * penalty-step plan (oriented jump u - g: int tau_e (v.n)(g.n)), over all six
+ * sides (plans with Dirichlet sides only).  Stream-ordered. */
+sipg_status sipg_wall_load(sipg_plan* plan, const double* g_wall, double* y, void* stream);
 
 typedef struct {
     sipg_solve_opts pressure;  /* pressure Poisson solve (pure Neumann: mean-zero) */
@@ -427,14 +444,15 @@ size_t sipg_split_work_bytes(const sipg_plan* vel, const sipg_plan* pres);
  * its mean removed, solution of zero nodal mean), uhh and the viscous
  * right-hand side (projection), the viscosity nu(u_old) on every level of
  * vel (sipg_update_viscosity), the viscous solve, the penalty factors from
- * u_old and the penalty solve with right-hand side M u_visc into u_new.
+ * u_old and the penalty solve with right-hand side M u_visc into u_new; with
+ * g_wall, the viscous and penalty right-hand sides take sipg_wall_load.
  * Every solve starts from zero.  u_old, b (may be NULL): inputs; u_new, p:
  * outputs (u_new must not alias u_old); work: device buffer of
  * sipg_split_work_bytes, 256-byte aligned.  Blocks until done; returns the
  * first failing solve's status (info, which may be NULL, holds all three). */
 sipg_status sipg_split_step(sipg_plan* vel, sipg_plan* pres, sipg_plan* pen, const double* u_old, const double* b,
-                            double dt, double* u_new, double* p, void* work, const sipg_split_opts* opts,
-                            sipg_split_info* info, void* stream);
+                            const double* g_wall, double dt, double* u_new, double* p, void* work,
+                            const sipg_split_opts* opts, sipg_split_info* info, void* stream);
 
 #ifdef __cplusplus
 }

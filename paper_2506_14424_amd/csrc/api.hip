@@ -1383,12 +1383,16 @@ void fill_split_geo(const sipg_plan* V, SplitGeo& S) {
 
 size_t split_vec_bytes(long long n) { return align256((size_t)n * sizeof(double)); }
 
+long long wall_faces(const sipg_plan* V) {
+    return 2LL * ((long long)V->ny * V->nz + (long long)V->nx * V->nz + (long long)V->nx * V->ny);
+}
+
 }  // namespace
 
 extern "C" {
 
-sipg_status sipg_convective_step(sipg_plan* V, const double* u, const double* b, double dt, double* uhat,
-                                 void* stream) {
+sipg_status sipg_convective_step(sipg_plan* V, const double* u, const double* b, const double* g_wall, double dt,
+                                 double* uhat, void* stream) {
     sipg_status rc = check_velocity(V);
     if (rc != SIPG_OK) return rc;
     if (!u || !uhat) return fail(SIPG_ERR_INVALID, "null argument");
@@ -1397,12 +1401,13 @@ sipg_status sipg_convective_step(sipg_plan* V, const double* u, const double* b,
         return fail(SIPG_ERR_INVALID, "uhat must not alias u or b (neighbours' values are read)");
     SplitGeo S;
     fill_split_geo(V, S);
+    S.gw = g_wall;
     HIP_TRY(launch_split_convective(V->n, S, u, b, dt, uhat, static_cast<hipStream_t>(stream)));
     return SIPG_OK;
 }
 
 sipg_status sipg_pressure_rhs(sipg_plan* V, sipg_plan* Pp, const double* uhat, const double* u_old, const double* b,
-                              double dt, double* f, void* stream) {
+                              const double* g_wall, double dt, double* f, void* stream) {
     sipg_status rc = check_velocity(V);
     if (rc == SIPG_OK) rc = check_pressure(V, Pp);
     if (rc != SIPG_OK) return rc;
@@ -1410,6 +1415,7 @@ sipg_status sipg_pressure_rhs(sipg_plan* V, sipg_plan* Pp, const double* uhat, c
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(SIPG_ERR_INVALID, "dt must be finite and > 0");
     SplitGeo S;
     fill_split_geo(V, S);
+    S.gw = g_wall;
     HIP_TRY(launch_split_ppe_rhs(V->n, S, uhat, u_old, b, dt, f, static_cast<hipStream_t>(stream)));
     return SIPG_OK;
 }
@@ -1451,6 +1457,18 @@ sipg_status sipg_update_penalty_factors(sipg_plan* P, const double* u, double dt
     return SIPG_OK;
 }
 
+sipg_status sipg_wall_load(sipg_plan* P, const double* g_wall, double* y, void* stream) {
+    sipg_status rc = check_velocity(P);
+    if (rc != SIPG_OK) return rc;
+    if (!g_wall || !y) return fail(SIPG_ERR_INVALID, "null argument");
+    if (P->op != SIPG_VISCOUS && !P->pen) return fail(SIPG_ERR_INVALID, "wall load: viscous or penalty-step plan");
+    SplitGeo S;
+    fill_split_geo(P, S);
+    S.gw = g_wall;
+    HIP_TRY(launch_wall_load(P->n, S, P->mu_face64, P->tfac64, P->pen ? 1 : 0, y, static_cast<hipStream_t>(stream)));
+    return SIPG_OK;
+}
+
 void sipg_split_opts_default(sipg_split_opts* o) {
     if (!o) return;
     sipg_solve_opts_default(&o->pressure);
@@ -1465,8 +1483,8 @@ size_t sipg_split_work_bytes(const sipg_plan* V, const sipg_plan* Pp) {
 }
 
 sipg_status sipg_split_step(sipg_plan* V, sipg_plan* Pp, sipg_plan* Pen, const double* u_old, const double* b,
-                            double dt, double* u_new, double* p, void* work, const sipg_split_opts* opts,
-                            sipg_split_info* info, void* stream) {
+                            const double* g_wall, double dt, double* u_new, double* p, void* work,
+                            const sipg_split_opts* opts, sipg_split_info* info, void* stream) {
     sipg_status rc = check_velocity(V);
     if (rc == SIPG_OK) rc = check_pressure(V, Pp);
     if (rc == SIPG_OK) rc = check_velocity(Pen);
@@ -1501,7 +1519,9 @@ sipg_status sipg_split_step(sipg_plan* V, sipg_plan* Pp, sipg_plan* Pen, const d
         const char* a = static_cast<const char*>(v);
         return v && a + bytes > w && a < we;
     };
-    if (overlaps(u_old, nu * 8) || overlaps(b, nu * 8) || overlaps(u_new, nu * 8) || overlaps(p, Pp->ndof * 8))
+    const size_t gw_bytes = (size_t)wall_faces(V) * V->n * V->n * 3 * 8;
+    if (overlaps(u_old, nu * 8) || overlaps(b, nu * 8) || overlaps(u_new, nu * 8) || overlaps(p, Pp->ndof * 8) ||
+        overlaps(g_wall, gw_bytes))
         return fail(SIPG_ERR_INVALID, "work must not alias the step's vectors");
 
     sipg_split_info inf;
@@ -1510,11 +1530,12 @@ sipg_status sipg_split_step(sipg_plan* V, sipg_plan* Pp, sipg_plan* Pen, const d
         if (info) *info = inf;
         return r;
     };
-    rc = sipg_convective_step(V, u_old, b, dt, uhat, stream);
-    if (rc == SIPG_OK) rc = sipg_pressure_rhs(V, Pp, uhat, u_old, b, dt, f, stream);
+    rc = sipg_convective_step(V, u_old, b, g_wall, dt, uhat, stream);
+    if (rc == SIPG_OK) rc = sipg_pressure_rhs(V, Pp, uhat, u_old, b, g_wall, dt, f, stream);
     if (rc == SIPG_OK) rc = sipg_solve(Pp, f, p, &o.pressure, &inf.pressure, stream);
     if (rc == SIPG_OK) rc = sipg_projection(V, Pp, uhat, p, dt, uhh, rhs, stream);
     if (rc == SIPG_OK) rc = update_viscosity(V, u_old, static_cast<hipStream_t>(stream));
+    if (rc == SIPG_OK && g_wall) rc = sipg_wall_load(V, g_wall, rhs, stream);
     if (rc == SIPG_OK) rc = sipg_solve(V, rhs, uvisc, &o.viscous, &inf.viscous, stream);
     if (rc == SIPG_OK) rc = sipg_update_penalty_factors(Pen, u_old, dt, o.zeta, stream);
     if (rc == SIPG_OK) {
@@ -1523,6 +1544,7 @@ sipg_status sipg_split_step(sipg_plan* V, sipg_plan* Pp, sipg_plan* Pen, const d
         const hipError_t e = launch_split_mass(V->n, S, uvisc, 1.0, rhs, static_cast<hipStream_t>(stream));
         if (e != hipSuccess) rc = fail(SIPG_ERR_HIP, std::string("split mass: ") + hipGetErrorString(e));
     }
+    if (rc == SIPG_OK && g_wall) rc = sipg_wall_load(Pen, g_wall, rhs, stream);
     if (rc == SIPG_OK) rc = sipg_solve(Pen, rhs, u_new, &o.penalty, &inf.penalty, stream);
     if (rc == SIPG_OK) g_err.clear();
     return finish(rc);

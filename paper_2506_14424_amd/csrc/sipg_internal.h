@@ -130,6 +130,7 @@ struct SplitGeo {
     double PV[kMaxN][kMaxN];     // PV[q][j] = l^p_j(g_q)
     double PD[kMaxN][kMaxN];     // PD[q][j] = l^p_j'(g_q)
     double PS[2][kMaxN];         // PS[s][j] = l^p_j(s)
+    const double* gw;            // velocity data on the walls (wall rows x n^2 points x 3), or nullptr (0)
 };
 
 // ---------------------------------------------------------------- launchers
@@ -169,6 +170,10 @@ hipError_t launch_split_projection(int n, const SplitGeo& S, const double* uhat,
 hipError_t launch_split_mass(int n, const SplitGeo& S, const double* x, double scale, double* y, hipStream_t s);
 hipError_t launch_pen_factors(int n, const SplitGeo& S, const double* u, double dt, double zeta, const double* hcell,
                               double* tau_div, double* tau_cont, hipStream_t s);
+// y += load of the wall data S.gw: viscous (pen = 0; mu_face, tfac = P(k+1)^2/h_F
+// per face) or penalty step (pen = 1; tfac = the face's continuity factor)
+hipError_t launch_wall_load(int n, const SplitGeo& S, const double* mu_face, const double* tfac, int pen, double* y,
+                            hipStream_t s);
 
 // Multigrid transfers between a fine level (nf nodes per direction, fine
 // mesh fx*fy*fz cells) and the next coarser one (nc; same mesh for a degree

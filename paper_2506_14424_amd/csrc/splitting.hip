@@ -116,6 +116,26 @@ __device__ __forceinline__ int neighbour(const SplitGeo& S, int e, const int ijk
     return ijk[d] > 0 ? e - stride : -1;
 }
 
+// Row of the wall data for the face (d, s) of a boundary cell: sides -x,
+// +x, -y, +y, -z, +z, each in the order of its cells' tangential indices.
+__device__ __forceinline__ int wall_row(const SplitGeo& S, const int ijk[3], int d, int s) {
+    const int nx = S.nx, ny = S.ny, nz = S.nz;
+    const int sz[3] = {ny * nz, nx * nz, nx * ny};
+    int off = 0;
+    for (int k = 0; k < 2 * d + s; ++k) off += sz[k >> 1];
+    const int in = d == 0 ? ijk[2] * ny + ijk[1] : d == 1 ? ijk[2] * nx + ijk[0] : ijk[1] * nx + ijk[0];
+    return off + in;
+}
+
+// Global number of the face (d, s) of cell ijk: x-faces, then y-, then z-faces.
+__device__ __forceinline__ int face_id(const SplitGeo& S, const int ijk[3], int d, int s) {
+    const int nx = S.nx, ny = S.ny, nz = S.nz;
+    const int nfx = (nx + 1) * ny * nz, nfy = nx * (ny + 1) * nz;
+    if (d == 0) return (ijk[2] * ny + ijk[1]) * (nx + 1) + ijk[0] + s;
+    if (d == 1) return nfx + (ijk[2] * (ny + 1) + ijk[1] + s) * nx + ijk[0];
+    return nfx + nfy + ((ijk[2] + s) * ny + ijk[1]) * nx + ijk[0];
+}
+
 // ds ({w}.n) (u+ - u-) at face point ab of face FC if {w}.n < 0 (inflow:
 // u_dag = u+), else 0; zero on a wall ({w} = g_u = 0).  U: the cell's values.
 template <int N, int FC>
@@ -125,23 +145,35 @@ __device__ __forceinline__ void conv_face(const SplitGeo& S, const CellMap& m, i
     const int str[3] = {1, N, N2};
     out[0] = out[1] = out[2] = 0.0;
     const int ne = neighbour(S, e, ijk, d, s);
-    if (ne < 0) return;
+    if (ne < 0 && S.gw == nullptr) return;       // no-slip wall: {w} = g_u = 0
     const int a = ab % N, bb = ab / N;
     FacePoint fp;
     face_point(S, m, d, s, a, bb, fp);
     const int line = a * str[fp.t1] + bb * str[fp.t2];
-    const double* un = u + (long long)ne * 3 * N3;
     double um[3], up[3];
+    if (ne >= 0) {
+        const double* un = u + (long long)ne * 3 * N3;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        double sm = 0.0, sp = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            double sm = 0.0, sp = 0.0;
 #pragma unroll
-        for (int k = 0; k < N; ++k) {
-            sm += S.tab.S[s][k] * U[c * N3 + line + k * str[d]];
-            sp += S.tab.S[1 - s][k] * un[c * N3 + line + k * str[d]];
+            for (int k = 0; k < N; ++k) {
+                sm += S.tab.S[s][k] * U[c * N3 + line + k * str[d]];
+                sp += S.tab.S[1 - s][k] * un[c * N3 + line + k * str[d]];
+            }
+            um[c] = sm;
+            up[c] = sp;
         }
-        um[c] = sm;
-        up[c] = sp;
+    } else {                                      // wall data: mirror u+ = 2 g_u - u-
+        const double* g = S.gw + ((long long)wall_row(S, ijk, d, s) * N2 + ab) * 3;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double sm = 0.0;
+#pragma unroll
+            for (int k = 0; k < N; ++k) sm += S.tab.S[s][k] * U[c * N3 + line + k * str[d]];
+            um[c] = sm;
+            up[c] = 2.0 * g[c] - sm;
+        }
     }
     const double wn = 0.5 * ((um[0] + up[0]) * fp.n[0] + (um[1] + up[1]) * fp.n[1] + (um[2] + up[2]) * fp.n[2]);
     if (wn < 0.0) {
@@ -252,8 +284,8 @@ __device__ __forceinline__ double ppe_face(const SplitGeo& S, const CellMap& m, 
         }
         val = -kGamma0 / dt * an;
     } else {
-        // wall: g_uhat = (dt/gamma_0)(b - beta_0 (grad u^n) u^n) (+ alpha_0/gamma_0 g_u = 0),
-        // h_p = n.b (- n.d_t g_u = 0), from the interior traces
+        // wall: g_uhat = (dt/gamma_0)(b - beta_0 (grad u^n) u^n) + (alpha_0/gamma_0) g_u,
+        // h_p = n.b (- n.d_t g_u = 0: data constant in time), from the interior traces
         const double* uo = u_old + (long long)e * 3 * N3;
         const double* be = b ? b + (long long)e * 3 * N3 : nullptr;
         double ut[3], bt[3], gref[3][3];
@@ -292,7 +324,8 @@ __device__ __forceinline__ double ppe_face(const SplitGeo& S, const CellMap& m, 
 #pragma unroll
             for (int i = 0; i < 3; ++i)
                 conv += (gref[c][0] * fp.Ji[0][i] + gref[c][1] * fp.Ji[1][i] + gref[c][2] * fp.Ji[2][i]) * ut[i];
-            const double guhat = dt / kGamma0 * (bt[c] - kBeta0 * conv);
+            const double gu = S.gw ? S.gw[((long long)wall_row(S, ijk, d, s) * N2 + ab) * 3 + c] : 0.0;
+            const double guhat = dt / kGamma0 * (bt[c] - kBeta0 * conv) + kAlpha0 / kGamma0 * gu;
             gn += guhat * fp.n[c];
             hp += fp.n[c] * bt[c];
         }
@@ -547,6 +580,99 @@ __global__ void __launch_bounds__(kCellThreads<N>) k_pen_factors(SplitGeo S, con
     }
 }
 
+// One wall face point of the load: ds a (value part) and ds J^-1 B (gradient
+// part, reference frame) of the viscous (a = 2 tau (g + (g.n) n), B = -2 mu
+// sym(g (x) n)) or penalty (a = tau_e (g.n) n, B = 0) wall data; zero off the walls.
+template <int N, int FC>
+__device__ __forceinline__ void load_face(const SplitGeo& S, const CellMap& m, int e, const int ijk[3], int ab,
+                                          const double* __restrict__ mu_face, const double* __restrict__ tfac,
+                                          int pen, double* va, double* vb) {
+    constexpr int N2 = N * N, d = FC >> 1, s = FC & 1;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) va[c] = 0.0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) vb[k] = 0.0;
+    if (neighbour(S, e, ijk, d, s) >= 0) return;
+    const int a = ab % N, bb = ab / N;
+    FacePoint fp;
+    face_point(S, m, d, s, a, bb, fp);
+    const int fid = face_id(S, ijk, d, s);
+    const double* g = S.gw + ((long long)wall_row(S, ijk, d, s) * N2 + ab) * 3;
+    const double gn = g[0] * fp.n[0] + g[1] * fp.n[1] + g[2] * fp.n[2];
+    if (pen) {
+        const double t = tfac[fid] * gn * fp.ds;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) va[c] = t * fp.n[c];
+        return;
+    }
+    const double mu = mu_face[(long long)fid * N2 + ab];
+    const double tau = tfac[fid] * mu;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) va[c] = fp.ds * 2.0 * tau * (g[c] + gn * fp.n[c]);
+    // B = -2 mu sym(g (x) n) = -mu (g_c n_i + g_i n_c); vb[c*3 + r] = ds sum_i Ji[r][i] B[c][i]
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            double acc = 0.0;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) acc += fp.Ji[r][i] * (-mu * (g[c] * fp.n[i] + g[i] * fp.n[c]));
+            vb[c * 3 + r] = fp.ds * acc;
+        }
+}
+
+template <int N>
+__global__ void __launch_bounds__(kFaceThreads<N>) k_wall_load(SplitGeo S, const double* __restrict__ mu_face,
+                                                              const double* __restrict__ tfac, int pen,
+                                                              double* __restrict__ y) {
+    constexpr int N2 = N * N, N3 = N2 * N;
+    __shared__ double VA[6][N2][3];
+    __shared__ double VB[6][N2][9];
+    const int e = blockIdx.x, t = threadIdx.x;
+    int ijk[3];
+    cell_ijk(S, e, ijk);
+    const bool wall = ijk[0] == 0 || ijk[0] == S.nx - 1 || ijk[1] == 0 || ijk[1] == S.ny - 1 || ijk[2] == 0 ||
+                      ijk[2] == S.nz - 1;
+    if (!wall) return;                            // whole workgroup: interior cells carry no load
+    CellMap m;
+    cell_map(S, ijk[0], ijk[1], ijk[2], m);
+    if (t < 6 * N2) {
+        const int fc = t / N2, ab = t % N2;
+        switch (fc) {
+            case 0: load_face<N, 0>(S, m, e, ijk, ab, mu_face, tfac, pen, VA[0][ab], VB[0][ab]); break;
+            case 1: load_face<N, 1>(S, m, e, ijk, ab, mu_face, tfac, pen, VA[1][ab], VB[1][ab]); break;
+            case 2: load_face<N, 2>(S, m, e, ijk, ab, mu_face, tfac, pen, VA[2][ab], VB[2][ab]); break;
+            case 3: load_face<N, 3>(S, m, e, ijk, ab, mu_face, tfac, pen, VA[3][ab], VB[3][ab]); break;
+            case 4: load_face<N, 4>(S, m, e, ijk, ab, mu_face, tfac, pen, VA[4][ab], VB[4][ab]); break;
+            default: load_face<N, 5>(S, m, e, ijk, ab, mu_face, tfac, pen, VA[5][ab], VB[5][ab]); break;
+        }
+    }
+    __syncthreads();
+    if (t >= N3) return;
+    const int qi[3] = {t % N, (t / N) % N, t / N2};
+    double* out = y + (long long)e * 3 * N3;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        double acc = 0.0;
+#pragma unroll
+        for (int fc = 0; fc < 6; ++fc) {
+            const int d = fc >> 1, s = fc & 1;
+            const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+            const int a = qi[t1], b = qi[t2];
+            const double sv = S.tab.S[s][qi[d]];
+            // grad phi_i at the face point (k, b) along t1 and (a, k) along t2; l_j'(g_k) = D[k][j]
+            double f = sv * VA[fc][b * N + a][c] + S.tab.G[s][qi[d]] * VB[fc][b * N + a][c * 3 + d];
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                f += sv * S.tab.D[k][a] * VB[fc][b * N + k][c * 3 + t1];
+                f += sv * S.tab.D[k][b] * VB[fc][k * N + a][c * 3 + t2];
+            }
+            acc += f;
+        }
+        out[c * N3 + t] += acc;
+    }
+}
+
 template <int N>
 hipError_t launch_n(int which, const SplitGeo& S, const double* a0, const double* a1, const double* a2, double s0,
                     double s1, double* o0, double* o1, hipStream_t s) {
@@ -559,6 +685,7 @@ hipError_t launch_n(int which, const SplitGeo& S, const double* a0, const double
         case 2: hipLaunchKernelGGL(k_split_projection<N>, grid, fb, 0, s, S, a0, a1, s0, o0, o1); break;
         case 3: hipLaunchKernelGGL(k_split_mass<N>, grid, cb, 0, s, S, a0, s0, o0); break;
         case 4: hipLaunchKernelGGL(k_pen_factors<N>, grid, cb, 0, s, S, a0, s0, s1, a1, o0, o1); break;
+        case 5: hipLaunchKernelGGL(k_wall_load<N>, grid, fb, 0, s, S, a0, a1, (int)s0, o0); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -599,6 +726,12 @@ hipError_t launch_split_mass(int n, const SplitGeo& S, const double* x, double s
 hipError_t launch_pen_factors(int n, const SplitGeo& S, const double* u, double dt, double zeta, const double* hcell,
                               double* tau_div, double* tau_cont, hipStream_t s) {
     return dispatch(n, 4, S, u, hcell, nullptr, dt, zeta, tau_div, tau_cont, s);
+}
+
+hipError_t launch_wall_load(int n, const SplitGeo& S, const double* mu_face, const double* tfac, int pen, double* y,
+                            hipStream_t s) {
+    if (S.gw == nullptr) return hipSuccess;
+    return dispatch(n, 5, S, mu_face, tfac, nullptr, (double)pen, 0.0, y, nullptr, s);
 }
 
 }  // namespace sipg

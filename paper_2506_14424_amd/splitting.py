@@ -35,7 +35,8 @@ class SplitStep:
     """Velocity DG_k (viscous plan with alpha = 1/dt and the Carreau law
     `law`), pressure DG_{k-1} (pure-Neumann Poisson) and the penalty step
     (alpha = 1, factors recomputed from the velocity) on one mesh whose six
-    sides are no-slip walls."""
+    sides are walls: no-slip, or with the velocity data `g_wall` of the step
+    calls (layout of include/sipg.h)."""
 
     def __init__(self, nx: int, ny: int, nz: int, degree: int, dt: float, law: dict, vertices=None,
                  penalty: float = 1.0):
@@ -66,24 +67,43 @@ class SplitStep:
         if t is None or not t.is_cuda or not t.is_contiguous() or t.numel() != n or t.dtype != torch.float64:
             raise ValueError(f"{name}: expected a contiguous FP64 device vector of {n} entries")
 
-    def convective_step(self, u, b=None, uhat=None, stream=None):
+    def wall_count(self) -> int:
+        """Rows of the wall data: one per boundary face (see include/sipg.h)."""
+        v = self.vel
+        return 2 * (v.ny * v.nz + v.nx * v.nz + v.nx * v.ny)
+
+    def _wall(self, g):
+        if g is not None:
+            self._vec(g, self.wall_count() * self.vel.n ** 2 * 3, "g_wall")
+
+    def convective_step(self, u, b=None, uhat=None, g_wall=None, stream=None):
         import torch
         self._vec(u, self.ndof_u, "u")
         if b is not None:
             self._vec(b, self.ndof_u, "b")
+        self._wall(g_wall)
         uhat = torch.empty_like(u) if uhat is None else uhat
-        check(lib.sipg_convective_step(self.vel._h, _ptr(u), _ptr(b), self.dt, _ptr(uhat),
+        check(lib.sipg_convective_step(self.vel._h, _ptr(u), _ptr(b), _ptr(g_wall), self.dt, _ptr(uhat),
                                        C.c_void_p(_stream_handle(stream))))
         return uhat
 
-    def pressure_rhs(self, uhat, u_old, b=None, f=None, stream=None):
+    def pressure_rhs(self, uhat, u_old, b=None, f=None, g_wall=None, stream=None):
         import torch
         self._vec(uhat, self.ndof_u, "uhat")
         self._vec(u_old, self.ndof_u, "u_old")
+        self._wall(g_wall)
         f = torch.empty(self.ndof_p, dtype=torch.float64, device=uhat.device) if f is None else f
-        check(lib.sipg_pressure_rhs(self.vel._h, self.pres._h, _ptr(uhat), _ptr(u_old), _ptr(b), self.dt, _ptr(f),
-                                    C.c_void_p(_stream_handle(stream))))
+        check(lib.sipg_pressure_rhs(self.vel._h, self.pres._h, _ptr(uhat), _ptr(u_old), _ptr(b), _ptr(g_wall),
+                                    self.dt, _ptr(f), C.c_void_p(_stream_handle(stream))))
         return f
+
+    def wall_load(self, op: Operator, g_wall, y, stream=None):
+        """y += the load of the wall data for the viscous (self.vel) or
+        penalty (self.pen) plan."""
+        self._wall(g_wall)
+        self._vec(y, self.ndof_u, "y")
+        check(lib.sipg_wall_load(op._h, _ptr(g_wall), _ptr(y), C.c_void_p(_stream_handle(stream))))
+        return y
 
     def projection(self, uhat, p, stream=None):
         import torch
@@ -102,10 +122,11 @@ class SplitStep:
     def work_bytes(self) -> int:
         return int(lib.sipg_split_work_bytes(self.vel._h, self.pres._h))
 
-    def step(self, u_old, b=None, u_new=None, p=None, opts: SplitOptions | None = None, stream=None):
+    def step(self, u_old, b=None, u_new=None, p=None, opts: SplitOptions | None = None, g_wall=None, stream=None):
         """One BDF1 step; returns (u_new, p, info)."""
         import torch
         self._vec(u_old, self.ndof_u, "u_old")
+        self._wall(g_wall)
         u_new = torch.empty_like(u_old) if u_new is None else u_new
         p = torch.empty(self.ndof_p, dtype=torch.float64, device=u_old.device) if p is None else p
         nbytes = self.work_bytes()
@@ -115,7 +136,7 @@ class SplitStep:
         off = (-ptr) % 256
         o = (opts or SplitOptions()).to_c()
         info = F.SplitInfo()
-        check(lib.sipg_split_step(self.vel._h, self.pres._h, self.pen._h, _ptr(u_old), _ptr(b), self.dt,
+        check(lib.sipg_split_step(self.vel._h, self.pres._h, self.pen._h, _ptr(u_old), _ptr(b), _ptr(g_wall), self.dt,
                                   _ptr(u_new), _ptr(p), C.c_void_p(ptr + off), C.byref(o), C.byref(info),
                                   C.c_void_p(_stream_handle(stream))))
         return u_new, p, {k: Operator._info(getattr(info, k)) for k in ("pressure", "viscous", "penalty")}

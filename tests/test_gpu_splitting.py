@@ -191,3 +191,76 @@ def test_second_step_with_reused_estimates():
         f"reused {[v['iterations'] for v in ir.values()]}")
     assert all(v["status"] == "SIPG_OK" for v in ir.values())
     assert rel(host(u2r), host(u2)) <= 1e-9 and rel(host(p2r), host(p2)) <= 1e-9
+
+
+def wall_data(pb, fn):
+    """g_u of the callable fn at the walls' face points (oracle geometry)."""
+    from oracle.forms import _face_geo
+    g = np.zeros((SP.wall_count(pb.mesh), pb.n ** 2, 3))
+    for (d, side), sl in SP.wall_rows(pb.mesh).items():
+        _, xq, _, _, _ = _face_geo(pb, pb.mesh.boundary_cells(d, side), d, side)
+        g[sl] = fn(xq.reshape(-1, 3)).reshape(xq.shape)
+    return g.reshape(-1)
+
+
+@pytest.mark.parametrize("label,shape,deg,perturb", CASES[:2] + CASES[3:], ids=[c[0] for c in CASES[:2] + CASES[3:]])
+def test_wall_data_operators_match_oracle(label, shape, deg, perturb):
+    """Velocity data on the walls (random at every wall face point): the
+    convective step, the pressure right-hand side and the viscous and
+    penalty wall loads equal the oracle's."""
+    from oracle import picard as PC
+    dt = 1e-2
+    st, pb, law, _ = make(shape, deg, perturb, dt)
+    pp = SP.pressure_problem(pb.mesh, deg)
+    u = W.uniform_vector(1, pb.ndof)
+    b = W.uniform_vector(2, pb.ndof)
+    uh = W.uniform_vector(3, pb.ndof)
+    gw = W.uniform_vector(8, SP.wall_count(pb.mesh) * pb.n ** 2 * 3)
+    e1 = rel(host(st.convective_step(dev(u), dev(b), g_wall=dev(gw))), SP.convective_step(pb, u, b, dt, gw))
+    e2 = rel(host(st.pressure_rhs(dev(uh), dev(u), dev(b), g_wall=dev(gw))), SP.ppe_rhs(pb, pp, uh, u, b, dt, gw))
+    st.vel.update_viscosity(dev(u))
+    pbv = PC.with_velocity_viscosity(pb, pb, u, law)
+    y0 = W.uniform_vector(4, pb.ndof)
+    e3 = rel(host(st.wall_load(st.vel, dev(gw), dev(y0))), y0 + SP.viscous_wall_load(pbv, gw))
+    st.update_penalty_factors(dev(u))
+    td, tc = SP.penalty_factors(pb, u, dt)
+    pen = Problem(pb.mesh, deg, "penalty", 1.0, 1.0, tau_div=td, tau_cont=tc)
+    e4 = rel(host(st.wall_load(st.pen, dev(gw), torch.zeros(pb.ndof, dtype=torch.float64, device="cuda"))),
+             SP.penalty_wall_load(pen, gw))
+    say(f"[split walls] {label}: convective {e1:.2e}, pressure rhs {e2:.2e}, viscous load {e3:.2e}, "
+        f"penalty load {e4:.2e}")
+    assert max(e1, e2, e3, e4) <= 1e-12
+
+
+def test_lid_driven_step_matches_oracle():
+    """A moving lid (g_u = (1, 0, 0) on the +z wall) plus small random data
+    on the other walls: the whole step equals the oracle's direct solves."""
+    dt = 1e-2
+    st, pb, law, V = make((3, 2, 2), 3, 0.1, dt)
+    rows = SP.wall_rows(pb.mesh)
+    gw = 0.1 * W.uniform_vector(9, SP.wall_count(pb.mesh) * pb.n ** 2 * 3).reshape(-1, pb.n ** 2, 3)
+    gw[rows[(2, 1)]] = np.array([1.0, 0.0, 0.0])
+    gw = gw.reshape(-1)
+    x = W.node_positions(3, 2, 2, 3, V)
+    u = np.transpose(6.4 * np.prod(x * (1 - x), -1)[..., None] * np.stack(
+        [np.sin(np.pi * x[..., 1]), np.cos(np.pi * x[..., 2]), x[..., 0]], -1), (0, 2, 1)).reshape(-1)
+    b = W.uniform_vector(7, pb.ndof)
+    ref = SP.split_step(pb, law, u, b, dt, g_wall=gw)
+    un, p, info = st.step(dev(u), dev(b), opts=TIGHT, g_wall=dev(gw))
+    eu, ep = rel(host(un), ref["u_new"]), rel(host(p), ref["p"])
+    say(f"[split lid] {info}; u_new rel. diff {eu:.2e}, p {ep:.2e}")
+    assert all(v["status"] == "SIPG_OK" for v in info.values())
+    assert eu <= 1e-8 and ep <= 1e-8
+
+
+def test_uniform_flow_through_the_box():
+    """u^n = c and g_u = c on every wall (inflow and outflow), b = 0: the
+    step returns u = c and p = 0."""
+    st, pb, law, V = make((3, 3, 2), 3, 0.1)
+    c = np.array([0.7, -0.4, 0.25])
+    u = np.tile(c[None, :, None], (pb.mesh.ncells, 1, pb.n ** 3)).reshape(-1)
+    gw = np.tile(c, SP.wall_count(pb.mesh) * pb.n ** 2)
+    un, p, info = st.step(dev(u), opts=TIGHT, g_wall=dev(gw))
+    eu, ep = float(np.abs(host(un) - u).max()), float(np.abs(host(p)).max())
+    say(f"[split uniform flow] |u - c| {eu:.2e}, |p| {ep:.2e}")
+    assert eu <= 1e-9 and ep <= 1e-9
