@@ -274,22 +274,23 @@ def split_step(reps=5, tol=1e-8):
     st = SplitStep(m, m, m, deg, dt, cfg["law"], V).set_multigrid().bind()
     u0, b0 = W.split_inputs(cfg, V)
     u, b = torch.from_numpy(u0).cuda(), torch.from_numpy(b0).cuda()
+    gw = torch.from_numpy(W.lid_data(cfg)).cuda()
     mg = SolveOptions(rel_tol=tol, precond="multigrid", cheb_degree=3)
     opts = SplitOptions(pressure=mg, viscous=mg, penalty=SolveOptions(rel_tol=tol), zeta=1.0)
-    un, p, info = st.step(u, b, opts=opts)                         # warm: eigenvalue estimates, code paths
+    un, p, info = st.step(u, b, opts=opts, g_wall=gw)              # warm: eigenvalue estimates, code paths
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
-        un, p, info = st.step(u, b, u_new=un, p=p, opts=opts)
+        un, p, info = st.step(u, b, u_new=un, p=p, opts=opts, g_wall=gw)
     torch.cuda.synchronize()
     step_s = (time.perf_counter() - t0) / reps
     mgr = SolveOptions(rel_tol=tol, precond="multigrid", cheb_degree=3, reuse_eigs=True)
     ropts = SplitOptions(pressure=mg, viscous=mgr, penalty=SolveOptions(rel_tol=tol, reuse_eigs=True), zeta=1.0)
-    un_r, p_r, info_r = st.step(u, b, opts=ropts)
+    un_r, p_r, info_r = st.step(u, b, opts=ropts, g_wall=gw)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
-        un_r, p_r, info_r = st.step(u, b, u_new=un_r, p=p_r, opts=ropts)
+        un_r, p_r, info_r = st.step(u, b, u_new=un_r, p=p_r, opts=ropts, g_wall=gw)
     torch.cuda.synchronize()
     step_reuse_s = (time.perf_counter() - t0) / reps
     reuse_diff = float((un_r - un).norm() / un.norm())
@@ -304,14 +305,15 @@ def split_step(reps=5, tol=1e-8):
         torch.cuda.synchronize()
         return ev[0].elapsed_time(ev[1]) / n
 
-    uhat = st.convective_step(u, b)
-    f = st.pressure_rhs(uhat, u, b)
+    uhat = st.convective_step(u, b, g_wall=gw)
+    f = st.pressure_rhs(uhat, u, b, g_wall=gw)
     uhh, rhs = st.projection(uhat, p)
-    ms_conv = timed(lambda: st.convective_step(u, b, uhat=uhat))
-    ms_rhs = timed(lambda: st.pressure_rhs(uhat, u, b, f=f))
+    ms_conv = timed(lambda: st.convective_step(u, b, uhat=uhat, g_wall=gw))
+    ms_rhs = timed(lambda: st.pressure_rhs(uhat, u, b, f=f, g_wall=gw))
     ms_proj = timed(lambda: st.projection(uhat, p))
     ms_pen = timed(lambda: st.update_penalty_factors(u))
     ms_visc = timed(lambda: st.vel.update_viscosity(u), 5)
+    ms_load = timed(lambda: st.wall_load(st.vel, gw, rhs))
 
     def wall(fn):
         torch.cuda.synchronize()
@@ -338,7 +340,7 @@ def split_step(reps=5, tol=1e-8):
         return {"avg_launch_ms": ms, "algorithmic_bytes": nbytes, "achieved_GBs": nbytes / (ms * 1e-3) / 1e9,
                 "hbm_frac": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
-    return {"workload": f"c8: one BDF1 dual-splitting step, 24^3 perturbed cells, velocity k={deg} "
+    return {"workload": f"c8: one BDF1 dual-splitting step of a lid-driven box, 24^3 perturbed cells, velocity k={deg} "
                         f"({nu} DoFs), pressure k={deg - 1} ({npr} DoFs), Carreau viscosity of u^n, dt={dt:g}, "
                         f"no-slip walls, solves to {tol:g} (FP32 multigrid for pressure and viscous, "
                         f"Chebyshev-Jacobi for the penalty step)",
@@ -355,6 +357,7 @@ def split_step(reps=5, tol=1e-8):
             "pressure_rhs": kern(ms_rhs, bytes_rhs),
             "projection": kern(ms_proj, bytes_proj),
             "penalty_factors_ms": ms_pen,
+            "viscous_wall_load_ms": ms_load,
             "viscosity_update_ms": ms_visc,
             "pressure_solve_s": t_p, "pressure_iterations": ip["iterations"],
             "viscous_solve_s": t_v, "viscous_solve_cached_eigs_s": t_vc, "viscous_iterations": iv["iterations"],
@@ -375,18 +378,19 @@ def split_step_32(reps=3, tol=1e-8):
     st = SplitStep(m, m, m, deg, dt, cfg["law"], V).set_multigrid().bind()
     u0, b0 = W.split_inputs(cfg, V)
     u, b = torch.from_numpy(u0).cuda(), torch.from_numpy(b0).cuda()
-    out = {"workload": f"c8 family at 32^3 cells: velocity k={deg} ({st.ndof_u} DoFs), pressure k={deg - 1} "
+    gw = torch.from_numpy(W.lid_data(cfg)).cuda()
+    out = {"workload": f"c8 family at 32^3 cells (lid-driven box): velocity k={deg} ({st.ndof_u} DoFs), pressure k={deg - 1} "
                        f"({st.ndof_p} DoFs), solves to {tol:g}",
            "unknowns": st.ndof_u + st.ndof_p}
     for key, reuse in (("fresh_eigs", False), ("reuse_eigs", True)):
         mg = SolveOptions(rel_tol=tol, precond="multigrid", cheb_degree=3)
         mgv = SolveOptions(rel_tol=tol, precond="multigrid", cheb_degree=3, reuse_eigs=reuse)
         opts = SplitOptions(pressure=mg, viscous=mgv, penalty=SolveOptions(rel_tol=tol, reuse_eigs=reuse))
-        un, p, info = st.step(u, b, opts=opts)
+        un, p, info = st.step(u, b, opts=opts, g_wall=gw)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(reps):
-            un, p, info = st.step(u, b, u_new=un, p=p, opts=opts)
+            un, p, info = st.step(u, b, u_new=un, p=p, opts=opts, g_wall=gw)
         torch.cuda.synchronize()
         sec = (time.perf_counter() - t0) / reps
         out[key] = {"step_seconds": sec, "unknowns_per_s_per_step": out["unknowns"] / sec,

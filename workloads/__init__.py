@@ -185,9 +185,10 @@ def config(name: str, n: int | None = None) -> dict:
         with the viscosity taken from the velocity (Picard iteration), zero
         initial velocity, right-hand side ``b_scale`` U(-1, 1) with seed 7,
         b_scale = 100 alpha / (cells (k+1)^3).
-    c8  one dual-splitting time step (BDF1, dt = 1e-3, no-slip walls): c3's
-        mesh, velocity degree 4 (pressure 3) and Carreau parameters, the old
-        velocity and body force of ``split_inputs``.
+    c8  one dual-splitting time step (BDF1, dt = 1e-3) of a lid-driven box
+        (``lid_data``: the +z wall moves with (1, 0, 0), the others are
+        no-slip): c3's mesh, velocity degree 4 (pressure 3) and Carreau
+        parameters, the old velocity and body force of ``split_inputs``.
     """
     if name == "c1":
         return _cfg("c1", n or 4, 2, "viscous", sine_law(1.0, 0.5), 10.0, ALL_DIRICHLET, 0.0,
@@ -219,6 +220,18 @@ def config(name: str, n: int | None = None) -> dict:
         return _cfg("c8", m, 4, "viscous", carreau_law(3), 1.0 / dt, ALL_DIRICHLET, 0.1, x_seed=8, tol=1e-8,
                     dt=dt, split=True)
     raise KeyError(name)
+
+
+def lid_data(cfg: dict) -> np.ndarray:
+    """Wall data of a lid-driven box: g_u = (1, 0, 0) on the +z wall, 0 on
+    the others, at every wall face point (the wall layout of the splitting
+    step: sides -x, +x, -y, +y, -z, +z, (k+1)^2 points, 3 components)."""
+    nx, ny, nz, n = cfg["nx"], cfg["ny"], cfg["nz"], cfg["degree"] + 1
+    sizes = [ny * nz, ny * nz, nx * nz, nx * nz, nx * ny, nx * ny]
+    g = np.zeros((sum(sizes), n * n, 3))
+    top = sum(sizes[:5])
+    g[top:top + sizes[5], :, 0] = 1.0
+    return g.reshape(-1)
 
 
 def node_positions(nx: int, ny: int, nz: int, degree: int, vertices=None) -> np.ndarray:
