@@ -10,9 +10,15 @@ Only tests, the package's smoke check and the benchmark's CPU baseline use
 this module.
 
 Scope and readings taken here:
-  * BDF1 (m = 1): gamma_0 = alpha_0 = beta_0 = 1, and m_p = min(m - 1, 2) = 0,
-    so the extrapolated convective and viscous terms of h_p are empty sums
-    (no vorticity is needed for this order);
+  * BDF1 (m = 1: gamma_0 = alpha_0 = beta_0 = 1; m_p = min(m - 1, 2) = 0, so
+    h_p has no extrapolated convective or viscous terms) or, given u^{n-1},
+    BDF2 with a constant step (m = 2: gamma_0 = 3/2, alpha = (2, -1/2),
+    beta = (2, -1); m_p = 1, beta_bar = (1), u^dd = u^n);
+  * the vorticity omega = curl u^dd is the element-local L2 projection onto
+    DG_k (Alg. 1), and nu^dd = eta(gdot(grad^S u^dd)) enters h_p with its
+    value at the wall point (interior trace) and the gradient of its
+    element-local L2 projection onto DG_k (the paper does not say how its
+    gradient is formed);
   * every boundary is a wall with velocity Dirichlet data g_u constant in
     time (d_t g_u = 0; g_u = 0 for no-slip, a moving lid otherwise), given
     at the velocity's face quadrature points of the boundary faces (layout of
@@ -31,8 +37,9 @@ Scope and readings taken here:
     penalty step's through its oriented jump u - g_u on the walls;
   * [c(u, u)]^# in g_uhat on the walls is evaluated from the interior trace
     of u^n and of its gradient;
-  * viscosity linear implicit, nu^# = eta(gdot(grad^S u^#)) with u^# = u^n
-    (Alg. 1 leaves the loop after one pass in this case);
+  * viscosity linear implicit, nu^# = eta(gdot(grad^S u^#)) with the
+    extrapolation u^# = sum_i beta_i u^{n-i} (Alg. 1 leaves the loop after
+    one pass in this case); the penalty factors use u^# as well;
   * penalty step factors (Fehn et al. 2018, restated in the penalty-step
     reading of this package): |u_e| = volume mean of |u^#| over the cell,
     h_e = |cell|^(1/3), tau_div = zeta |u_e| h_e dt / (k + 1),
@@ -46,12 +53,23 @@ import scipy.sparse.linalg as spla
 
 from . import picard as PC
 from .basis import cell_points, face_points, tensor_tables
+from .laws import generalized_newtonian
 from .forms import (Problem, _cell_geo, _face_geo, _mu_face, _phys_grad, _sym, _tau, _tau_face, _test_project,
                     assemble, cell_sizes)
 from .mesh import Mesh
 
 # BDF1 coefficients (m = 1)
 GAMMA0, ALPHA0, BETA0 = 1.0, 1.0, 1.0
+
+
+def bdf(order: int) -> dict:
+    """gamma_0, alpha_i, beta_i (extrapolation of order m) and beta_bar_i
+    (extrapolation of order m_p = min(m - 1, 2)) for a constant step."""
+    if order == 1:
+        return {"gamma0": 1.0, "alpha": (1.0,), "beta": (1.0,), "beta_bar": ()}
+    if order == 2:
+        return {"gamma0": 1.5, "alpha": (2.0, -0.5), "beta": (2.0, -1.0), "beta_bar": (1.0,)}
+    raise ValueError("BDF order 1 or 2")
 
 
 def pressure_problem(mesh: Mesh, degree_u: int) -> Problem:
@@ -174,35 +192,96 @@ def convective_form(pb: Problem, u, w, g_wall=None) -> np.ndarray:
     return Y.reshape(-1)
 
 
-def convective_step(pb: Problem, u, b, dt: float, g_wall=None) -> np.ndarray:
+def convective_step(pb: Problem, u, b, dt: float, g_wall=None, u_prev=None) -> np.ndarray:
     """uhat from eq. convective_step_weak:
-    (gamma_0/dt)(v, uhat) = (v, b) + (alpha_0/dt)(v, u^n) - beta_0 c_h(v, u^n; u^n)."""
-    u = np.asarray(u, dtype=np.float64)
-    rhs = mass_apply(pb, b) + ALPHA0 / dt * mass_apply(pb, u) - BETA0 * convective_form(pb, u, u, g_wall)
-    return dt / GAMMA0 * mass_solve(pb, rhs)
+    (gamma_0/dt)(v, uhat) = (v, b) + sum_i (alpha_i/dt)(v, u^{n-i}) - sum_i beta_i c_h(v, u^{n-i}; u^{n-i})
+    (BDF1, or BDF2 with u_prev = u^{n-1})."""
+    olds = [np.asarray(u, dtype=np.float64)] + ([] if u_prev is None else [np.asarray(u_prev, dtype=np.float64)])
+    c = bdf(len(olds))
+    rhs = mass_apply(pb, b)
+    for a_i, b_i, ui in zip(c["alpha"], c["beta"], olds):
+        rhs = rhs + a_i / dt * mass_apply(pb, ui) - b_i * convective_form(pb, ui, ui, g_wall)
+    return dt / c["gamma0"] * mass_solve(pb, rhs)
+
+
+def _curl(G):
+    """curl from G[..., c, i] = d u_c / d x_i."""
+    return np.stack([G[..., 2, 1] - G[..., 1, 2], G[..., 0, 2] - G[..., 2, 0], G[..., 1, 0] - G[..., 0, 1]], -1)
+
+
+def l2_project(pb: Problem, values) -> np.ndarray:
+    """Element-local L2 projection onto DG_k of values (cells, P, C) at the
+    cell quadrature points: per cell M_e x = (phi_j, values)_e; (cells, C, n^3)."""
+    n = pb.n
+    pts, _ = cell_points(n)
+    V, _ = tensor_tables(n, pts)
+    _, _, JxW = _cell_geo(pb, np.arange(pb.mesh.ncells))
+    rhs = np.einsum("pj,ep,epc->ecj", V, JxW, values)
+    M = np.einsum("pi,ep,pj->eij", V, JxW, V)
+    return np.linalg.solve(M[:, None], rhs[..., None])[..., 0]
+
+
+def vorticity(pb: Problem, u) -> np.ndarray:
+    """omega_h = element-local L2 projection of curl u onto DG_k (Alg. 1)."""
+    n = pb.n
+    U = np.asarray(u, dtype=np.float64).reshape(pb.mesh.ncells, 3, n ** 3)
+    pts, _ = cell_points(n)
+    _, G = tensor_tables(n, pts)
+    _, Jinv, _ = _cell_geo(pb, np.arange(pb.mesh.ncells))
+    return l2_project(pb, _curl(_phys_grad(U, G, Jinv)))
+
+
+def viscosity_projection(pb: Problem, u, law: dict) -> np.ndarray:
+    """eta(gdot(grad^S u)) at the cell points, projected element-locally onto DG_k."""
+    n = pb.n
+    U = np.asarray(u, dtype=np.float64).reshape(pb.mesh.ncells, 3, n ** 3)
+    pts, _ = cell_points(n)
+    _, G = tensor_tables(n, pts)
+    _, Jinv, _ = _cell_geo(pb, np.arange(pb.mesh.ncells))
+    nu = generalized_newtonian(law, PC._shear_rate(_phys_grad(U, G, Jinv)))
+    return l2_project(pb, nu[..., None])
 
 
 # ---------------------------------------------------------------------------
 # pressure step (eqs. pressure_step_weak, guhat_consistent_BC, pressure_Neumann_BC)
 # ---------------------------------------------------------------------------
 
-def wall_data(pb: Problem, u_old, b, dt: float, d: int, side: int, g_wall=None):
+def wall_data(pb: Problem, u_old, b, dt: float, d: int, side: int, g_wall=None, u_prev=None, law=None):
     """On the wall xi_d = side: g_uhat and h_p at the face points of the
-    boundary cells, with u^n and b taken from the interior traces.
-    g_uhat = (dt/gamma_0) (b - beta_0 (grad u^n) u^n) + (alpha_0/gamma_0) g_u,
-    h_p = n.b - n.d_t g_u (BDF1: m_p = 0 drops the extrapolated terms)."""
+    boundary cells, with the velocities and b taken from the interior traces.
+    g_uhat = (dt/gamma_0) (b - sum_i beta_i (grad u^{n-i}) u^{n-i}) + sum_i (alpha_i/gamma_0) g_u,
+    h_p = n.b - n.d_t g_u - sum_{i<m_p} beta_bar_i n.((grad u^{n-i}) u^{n-i})
+          - nu^dd n.curl(omega^dd) + 2 n.(grad^S u^dd . grad nu^dd)   (the last two for m_p >= 1),
+    u^dd = sum_{i<m_p} beta_bar_i u^{n-i}."""
     n = pb.n
-    U = np.asarray(u_old, dtype=np.float64).reshape(pb.mesh.ncells, 3, n ** 3)
+    olds = [u_old] + ([] if u_prev is None else [u_prev])
+    c = bdf(len(olds))
+    Us = [np.asarray(v, dtype=np.float64).reshape(pb.mesh.ncells, 3, n ** 3) for v in olds]
     B = np.asarray(b, dtype=np.float64).reshape(pb.mesh.ncells, 3, n ** 3)
     bc = pb.mesh.boundary_cells(d, side)
     Vf, Gf = tensor_tables(n, face_points(n, d, side)[0])
     _, _, Ji, nrm, ds = _face_geo(pb, bc, d, side)
-    ui, bi = _values(pb, U[bc], Vf), _values(pb, B[bc], Vf)
-    conv = np.einsum("epci,epi->epc", _phys_grad(U[bc], Gf, Ji), ui)
+    bi = _values(pb, B[bc], Vf)
+    convs = [np.einsum("epci,epi->epc", _phys_grad(U[bc], Gf, Ji), _values(pb, U[bc], Vf)) for U in Us]
     g_u = _wall_g(pb, g_wall, d, side)
-    dt_g_u = np.zeros_like(ui)                                   # data constant in time
-    g_uhat = dt / GAMMA0 * (bi - BETA0 * conv) + ALPHA0 / GAMMA0 * g_u
+    dt_g_u = np.zeros_like(bi)                                   # data constant in time
+    g_uhat = dt / c["gamma0"] * (bi - sum(b_i * cv for b_i, cv in zip(c["beta"], convs))) \
+        + sum(c["alpha"]) / c["gamma0"] * g_u
     h_p = np.einsum("epc,epc->ep", nrm, bi) - np.einsum("epc,epc->ep", nrm, dt_g_u)
+    for bb_i, cv in zip(c["beta_bar"], convs):
+        h_p = h_p - bb_i * np.einsum("epc,epc->ep", nrm, cv)
+    if c["beta_bar"]:
+        if law is None:
+            raise ValueError("BDF2 wall data need the viscosity law")
+        udd = sum(bb_i * v for bb_i, v in zip(c["beta_bar"], olds))
+        Udd = np.asarray(udd, dtype=np.float64).reshape(pb.mesh.ncells, 3, n ** 3)
+        gu = _phys_grad(Udd[bc], Gf, Ji)                           # grad u^dd at the wall points
+        nu = generalized_newtonian(law, PC._shear_rate(gu))
+        curl_om = _curl(_phys_grad(vorticity(pb, udd)[bc], Gf, Ji))
+        grad_nu = _phys_grad(viscosity_projection(pb, udd, law)[bc], Gf, Ji)[..., 0, :]
+        S = 0.5 * (gu + np.swapaxes(gu, -1, -2))
+        h_p = h_p - nu * np.einsum("epc,epc->ep", nrm, curl_om) \
+            + 2.0 * np.einsum("epi,epij,epj->ep", nrm, S, grad_nu)
     return bc, g_uhat, h_p
 
 
@@ -259,14 +338,16 @@ def wall_neumann_form(pb_u: Problem, pb_p: Problem, h_value) -> np.ndarray:
     return F.reshape(-1)
 
 
-def ppe_rhs(pb_u: Problem, pb_p: Problem, uhat, u_old, b, dt: float, g_wall=None) -> np.ndarray:
+def ppe_rhs(pb_u: Problem, pb_p: Problem, uhat, u_old, b, dt: float, g_wall=None, u_prev=None,
+            law=None) -> np.ndarray:
     """Right-hand side of eq. pressure_step_weak with the wall data moved
     over: (gamma_0/dt) [(grad q, uhat) - (q, {uhat}.n)] + (q, h_p)_walls,
     {uhat} = g_uhat on the walls (mirror principle)."""
     _walls(pb_u)
-    data = {(d, s): wall_data(pb_u, u_old, b, dt, d, s, g_wall) for d in range(3) for s in (0, 1)}
+    g0 = bdf(1 if u_prev is None else 2)["gamma0"]
+    data = {(d, s): wall_data(pb_u, u_old, b, dt, d, s, g_wall, u_prev, law) for d in range(3) for s in (0, 1)}
     div = divergence_form(pb_u, pb_p, uhat, lambda d, s: data[(d, s)][1])
-    return GAMMA0 / dt * div + wall_neumann_form(pb_u, pb_p, lambda d, s: data[(d, s)][2])
+    return g0 / dt * div + wall_neumann_form(pb_u, pb_p, lambda d, s: data[(d, s)][2])
 
 
 def pressure_solve(pb_p: Problem, f) -> np.ndarray:
@@ -326,12 +407,12 @@ def projection_form(pb_u: Problem, pb_p: Problem, p) -> np.ndarray:
     return Y.reshape(-1)
 
 
-def projection(pb_u: Problem, pb_p: Problem, uhat, p, dt: float):
+def projection(pb_u: Problem, pb_p: Problem, uhat, p, dt: float, gamma0: float = GAMMA0):
     """uhh from (gamma_0/dt)(v, uhh) = (gamma_0/dt)(v, uhat) + (div v, p) - (v, {p} n),
     and the viscous step's right-hand side (gamma_0/dt) M uhh."""
     _walls(pb_u)
-    uhh = np.asarray(uhat, dtype=np.float64) + dt / GAMMA0 * mass_solve(pb_u, projection_form(pb_u, pb_p, p))
-    return uhh, GAMMA0 / dt * mass_apply(pb_u, uhh)
+    uhh = np.asarray(uhat, dtype=np.float64) + dt / gamma0 * mass_solve(pb_u, projection_form(pb_u, pb_p, p))
+    return uhh, gamma0 / dt * mass_apply(pb_u, uhh)
 
 
 # ---------------------------------------------------------------------------
@@ -391,23 +472,28 @@ def penalty_wall_load(pb: Problem, g_wall) -> np.ndarray:
     return Y.reshape(-1)
 
 
-def split_step(pb_visc: Problem, law: dict, u_old, b, dt: float, zeta: float = 1.0, g_wall=None) -> dict:
-    """One BDF1 step of Alg. 1 with linear-implicit viscosity: convective
-    step, pressure step, projection, viscous step, penalty step.  pb_visc is
-    the viscous problem with alpha = gamma_0/dt on the velocity mesh (no-slip
-    walls); every linear system is solved directly."""
-    if abs(pb_visc.alpha * dt - GAMMA0) > 1e-12 * GAMMA0:
+def split_step(pb_visc: Problem, law: dict, u_old, b, dt: float, zeta: float = 1.0, g_wall=None,
+               u_prev=None) -> dict:
+    """One step of Alg. 1 (BDF1, or BDF2 given u_prev = u^{n-1}) with
+    linear-implicit viscosity: convective step, pressure step, projection,
+    viscous step, penalty step.  pb_visc is the viscous problem with
+    alpha = gamma_0/dt on the velocity mesh (walls); every linear system is
+    solved directly."""
+    c = bdf(1 if u_prev is None else 2)
+    if abs(pb_visc.alpha * dt - c["gamma0"]) > 1e-12 * c["gamma0"]:
         raise ValueError("the viscous problem's mass coefficient must be gamma_0/dt")
+    olds = [np.asarray(u_old, dtype=np.float64)] + ([] if u_prev is None else [np.asarray(u_prev, dtype=np.float64)])
+    u_ex = sum(b_i * v for b_i, v in zip(c["beta"], olds))     # u^#
     pb_p = pressure_problem(pb_visc.mesh, pb_visc.degree)
-    uhat = convective_step(pb_visc, u_old, b, dt, g_wall)
-    f = ppe_rhs(pb_visc, pb_p, uhat, u_old, b, dt, g_wall)
+    uhat = convective_step(pb_visc, u_old, b, dt, g_wall, u_prev)
+    f = ppe_rhs(pb_visc, pb_p, uhat, u_old, b, dt, g_wall, u_prev, law)
     p = pressure_solve(pb_p, f)
-    uhh, rhs_v = projection(pb_visc, pb_p, uhat, p, dt)
-    pb_v = PC.with_velocity_viscosity(pb_visc, pb_visc, u_old, law)
+    uhh, rhs_v = projection(pb_visc, pb_p, uhat, p, dt, c["gamma0"])
+    pb_v = PC.with_velocity_viscosity(pb_visc, pb_visc, u_ex, law)
     if g_wall is not None:
         rhs_v = rhs_v + viscous_wall_load(pb_v, g_wall)
     u_visc = spla.spsolve(assemble(pb_v).tocsc(), rhs_v)
-    td, tc = penalty_factors(pb_visc, u_old, dt, zeta)
+    td, tc = penalty_factors(pb_visc, u_ex, dt, zeta)
     pb_pen = Problem(pb_visc.mesh, pb_visc.degree, "penalty", 1.0, 1.0, tau_div=td, tau_cont=tc)
     rhs_pen = mass_apply(pb_pen, u_visc)
     if g_wall is not None:

@@ -13,7 +13,13 @@ velocity; the whole step keeps a fluid at rest under a gradient body
 force with the hydrostatic pressure; and with velocity data on the walls:
 the viscous load equals the forms' SIPG load vector, a uniform flow through
 the box stays uniform with zero pressure, the inflow flux of a wall, and the
-penalty step's wall load in closed form."""
+penalty step's wall load in closed form.  BDF2: the coefficients reproduce
+constants, a quadratic's derivative and a linear extrapolation; the
+vorticity of a polynomial field and the projected viscosity of a law that
+is polynomial in the gradient are exact; the wall data h_p of s(y^2, 0, 0)
+in closed form (curl curl, the viscosity gradient term); equal linear states
+make the right-hand side sum vanish; the convective step of two linear
+fields; rest and uniform flow through whole BDF2 steps."""
 import numpy as np
 import pytest
 from scipy.interpolate import lagrange
@@ -327,3 +333,115 @@ def test_penalty_wall_load_closed_form():
     # (g.n)(v.n) with n = -e_x: (-gx)(-v_x) = gx v_x
     ref[0] = t * gx * 0.7 * 1.3 * w[None, :, None] * w[:, None, None] * l0[None, None, :]
     assert np.abs(got - ref).max() <= 1e-13
+
+
+# ---------------------------------------------------------------- BDF2
+
+def poly_law(mu0=1.0, mu_inf=0.2, lam=0.7):
+    """Carreau parameters with kappa = 0, a = 2, n = 3: eta = mu_inf + (mu0 - mu_inf) (lam gdot)^2,
+    a polynomial in the velocity gradient."""
+    law = dict(W.carreau_law(3))
+    law.update(mu0=mu0, mu_inf=mu_inf, lam=lam, kappa=0.0, a_exp=2.0, n_exp=3.0)
+    return law
+
+
+def test_bdf2_coefficients():
+    for m in (1, 2):
+        c = SP.bdf(m)
+        assert abs(sum(c["alpha"]) - c["gamma0"]) <= 1e-15          # constants are steady
+        assert abs(sum(c["beta"]) - 1.0) <= 1e-15                   # extrapolation of constants
+    c = SP.bdf(2)
+    # BDF2 differentiates t^2 exactly at t = 1 from t = 0, -1: (3/2 - 2*0 + 1/2*1) = 2
+    assert abs(c["gamma0"] * 1.0 - c["alpha"][0] * 0.0 - c["alpha"][1] * 1.0 - 2.0) <= 1e-15
+    # second-order extrapolation: 2 f(0) - f(-1) = f(1) for linear f
+    assert abs(c["beta"][0] * 0.0 + c["beta"][1] * (-1.0) - 1.0) <= 1e-15
+
+
+def test_vorticity_of_a_polynomial_field():
+    deg = 2
+    m = Mesh(3, 2, 2, aniso_box(3, 2, 2, 1.2, 0.8, 1.0))
+    pb = Problem(m, deg, "viscous", 1.0, 1.0)
+    u = interpolate(pb, lambda x: np.stack([x[:, 1] ** 2, x[:, 2] * x[:, 0], x[:, 0] * x[:, 1]], -1))
+    ref = interpolate(pb, lambda x: np.stack([0 * x[:, 0], -x[:, 1], x[:, 2] - 2 * x[:, 1]], -1))
+    got = SP.vorticity(pb, u).reshape(-1)
+    assert np.abs(got - ref).max() <= 1e-12
+
+
+def test_viscosity_projection_of_a_polynomial_law():
+    deg = 3
+    m = Mesh(2, 3, 2, aniso_box(2, 3, 2, 1.0, 0.9, 1.1))
+    pb = Problem(m, deg, "viscous", 1.0, 1.0)
+    law, s = poly_law(), 0.8
+    u = interpolate(pb, lambda x: np.stack([s * x[:, 1] ** 2, 0 * x[:, 0], 0 * x[:, 0]], -1))
+    nu = lambda y: law["mu_inf"] + (law["mu0"] - law["mu_inf"]) * law["lam"] ** 2 * 4 * s ** 2 * y ** 2
+    ref = interpolate(Problem(m, deg, "poisson"), lambda x: nu(x[:, 1]))
+    assert np.abs(SP.viscosity_projection(pb, u, law).reshape(-1) - ref).max() <= 1e-12
+
+
+def test_bdf2_wall_data_closed_form():
+    """u^n = u^{n-1} = s (y^2, 0, 0), b = 0, no wall data, polynomial law:
+    (grad u) u = 0, curl curl u = (-2s, 0, 0), grad^S u . grad nu = (s y nu', 0, 0),
+    so h_p = n_x 2 s (nu + y nu') and g_uhat = 0 on the x walls."""
+    deg, dt = 3, 0.05
+    m = Mesh(2, 2, 3, aniso_box(2, 2, 3, 1.0, 1.0, 1.0))
+    pb = Problem(m, deg, "viscous", 1.5 / dt, 1.0)
+    law, s = poly_law(), 0.6
+    u = interpolate(pb, lambda x: np.stack([s * x[:, 1] ** 2, 0 * x[:, 0], 0 * x[:, 0]], -1))
+    k2 = (law["mu0"] - law["mu_inf"]) * law["lam"] ** 2 * 4 * s ** 2
+    from oracle.forms import _face_geo
+    for side, nx_ in ((0, -1.0), (1, 1.0)):
+        bc, g_uhat, h_p = SP.wall_data(pb, u, np.zeros(pb.ndof), dt, 0, side, None, u, law)
+        _, xq, _, _, _ = _face_geo(pb, bc, 0, side)
+        y = xq[..., 1]
+        nu = law["mu_inf"] + k2 * y ** 2
+        ref = nx_ * 2 * s * (nu + y * 2 * k2 * y)
+        assert np.abs(h_p - ref).max() <= 1e-11 * np.abs(ref).max()
+        assert np.abs(g_uhat).max() <= 1e-13
+
+
+@pytest.mark.parametrize("perturb", [0.0, 0.1])
+def test_bdf2_pressure_rhs_sum_for_equal_linear_states(perturb):
+    """u^n = u^{n-1} = B x + d: the wall terms of sum_i beta_i (2 - 1 = 1) and
+    beta_bar_0 (= 1) cancel, the vorticity and the viscosity are constant:
+    the right-hand side sums to zero (BDF1 gives tr(B^2))."""
+    pb = velocity_problem(2, 3, 2, 3, perturb)
+    pp = SP.pressure_problem(pb.mesh, pb.degree)
+    B = np.array([[0.5, 0.2, -0.3], [0.1, -0.4, 0.6], [0.8, 0.3, 0.1]])
+    u = interpolate(pb, linear(B, np.array([1.0, -2.0, 0.5])))
+    f = SP.ppe_rhs(pb, pp, W.uniform_vector(3, pb.ndof), u, W.uniform_vector(4, pb.ndof), 0.05, None, u,
+                   W.carreau_law(3))
+    assert abs(f.sum()) <= 1e-10
+
+
+def test_bdf2_convective_step_of_linear_fields():
+    pb = velocity_problem(3, 2, 2, 2, 0.1)
+    A2 = np.array([[-0.2, 0.4, 0.1], [0.3, 0.5, -0.6], [0.2, -0.1, 0.3]])
+    c2 = np.array([0.1, 0.4, -0.3])
+    u1, u0 = interpolate(pb, linear(A, c0)), interpolate(pb, linear(A2, c2))
+    b, dt = W.uniform_vector(2, pb.ndof), 0.05
+    conv1 = interpolate(pb, lambda x: (x @ A.T + c0) @ A.T)
+    conv0 = interpolate(pb, lambda x: (x @ A2.T + c2) @ A2.T)
+    ref = (2 * u1 - 0.5 * u0) / 1.5 + dt / 1.5 * (b - 2 * conv1 + conv0)
+    got = SP.convective_step(pb, u1, b, dt, None, u0)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("perturb", [0.0, 0.1])
+def test_bdf2_rest_and_uniform_flow(perturb):
+    """BDF2 steps of a fluid at rest under a gradient force (p = g.x) and of
+    a uniform flow through the box (u = c, p = 0)."""
+    dt = 0.05
+    nx = 2
+    V = W.box_vertices(nx, nx, nx, perturb) if perturb else None
+    pb = Problem(Mesh(nx, nx, nx, V), 3, "viscous", 1.5 / dt, 1.0)
+    law = W.carreau_law(3)
+    g = np.array([0.4, -1.0, 2.5])
+    b = interpolate(pb, lambda x: np.broadcast_to(g, x.shape))
+    out = SP.split_step(pb, law, np.zeros(pb.ndof), b, dt, u_prev=np.zeros(pb.ndof))
+    pe = node_points(out["pb_p"]).reshape(-1, 3) @ g
+    assert np.abs(out["p"] - (pe - pe.mean())).max() <= 1e-10 and np.abs(out["u_new"]).max() <= 1e-10
+    c = np.array([0.7, -0.4, 0.25])
+    const = lambda x: np.broadcast_to(c, x.shape)
+    u = interpolate(pb, const)
+    out = SP.split_step(pb, law, u, np.zeros(pb.ndof), dt, g_wall=_g_wall_from(pb, const), u_prev=u)
+    assert np.abs(out["u_new"] - u).max() <= 1e-10 and np.abs(out["p"]).max() <= 1e-10
