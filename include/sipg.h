@@ -358,9 +358,13 @@ sipg_status sipg_picard_solve(sipg_plan* plan, const double* b, double* x, void*
  * One time step of the dual splitting scheme (Sec. 3 "Splitting Scheme";
  * the weak forms of Sec. 4.1: eqs. convective_step_weak,
  * convective_term_weak, pressure_step_weak, guhat_consistent_BC,
- * pressure_Neumann_BC, projection_step_weak; the order of Alg. 1), with
- * BDF1 coefficients (gamma_0 = alpha_0 = beta_0 = 1; m_p = 0, so h_p holds
- * no extrapolated convective or viscous terms) on a box whose six sides are
+ * pressure_Neumann_BC, projection_step_weak; the order of Alg. 1), BDF1
+ * (gamma_0 = alpha_0 = beta_0 = 1; m_p = 0, so h_p holds no extrapolated
+ * convective or viscous terms) or, given u_prev = u^{n-1}, BDF2 with a
+ * constant step (gamma_0 = 3/2, alpha = (2, -1/2), beta = (2, -1); m_p = 1:
+ * h_p adds -n.((grad u^n) u^n) - nu n.curl(omega) + 2 n.(grad^S u^n . grad nu)
+ * with the vorticity omega = curl u^n and nu = eta(gdot(u^n)) projected onto
+ * DG_k element by element), on a box whose six sides are
  * walls: velocity Dirichlet data g_u constant in time (g_wall; NULL = no-slip,
  * g_u = 0), pressure Neumann.
  *
@@ -373,7 +377,8 @@ sipg_status sipg_picard_solve(sipg_plan* plan, const double* b, double* x, void*
  *
  * Three plans on the same mesh (same cells and vertices):
  *   vel   SIPG_VISCOUS, degree k in [2, 5], all sides Dirichlet,
- *         alpha = gamma_0/dt, law SIPG_LAW_CARREAU (its eta parameters);
+ *         alpha = gamma_0/dt (1/dt for BDF1, 3/(2 dt) for BDF2), law
+ *         SIPG_LAW_CARREAU (its eta parameters);
  *   pres  SIPG_POISSON, degree k - 1, all sides Neumann, alpha = 0;
  *   pen   SIPG_PENALTY, degree k, all sides Dirichlet, alpha = 1, no
  *         multigrid hierarchy (its factors are recomputed on the device).
@@ -384,27 +389,30 @@ sipg_status sipg_picard_solve(sipg_plan* plan, const double* b, double* x, void*
  * stream-ordered and allocate nothing; b may be NULL (no body force).
  */
 
-/* uhat = (alpha_0/gamma_0) u + (dt/gamma_0)(b - beta_0 M^-1 c_h(u; u)) with
+/* uhat = sum_i (alpha_i/gamma_0) u^{n-i} + (dt/gamma_0)(b - sum_i beta_i M^-1 c_h(u^{n-i}; u^{n-i}))
+ * (u^n = u, u^{n-1} = u_prev for BDF2, NULL for BDF1) with
  * c_h(v, u; w) = (v, (w.grad) u)_e - (v, ({w}.n) u)_de + (v, ({w}.n) u_dag)_de,
  * u_dag = {u} + sign({w}.n)(u- - u+)/2 (upwind), mirror principle on the
  * walls (u+ = 2 g_u - u-, w+ = 2 g_u - w-; with g_u = 0, {w} = 0 removes the
  * face term). */
-sipg_status sipg_convective_step(sipg_plan* vel, const double* u, const double* b, const double* g_wall, double dt,
-                                 double* uhat, void* stream);
+sipg_status sipg_convective_step(sipg_plan* vel, const double* u, const double* u_prev, const double* b,
+                                 const double* g_wall, double dt, double* uhat, void* stream);
 
 /* Right-hand side of the pressure Poisson equation (pres layout):
  * f_q = (gamma_0/dt)[(grad q, uhat)_e - (q, {uhat}.n)_de] + (q, h_p)_walls,
- * with {uhat} = g_uhat = (dt/gamma_0)(b - beta_0 (grad u_old) u_old) +
- * (alpha_0/gamma_0) g_u on the walls and h_p = n.b (data constant in time),
- * both from interior traces of u_old and b. */
+ * with {uhat} = g_uhat = (dt/gamma_0)(b - sum_i beta_i (grad u^{n-i}) u^{n-i}) +
+ * sum_i (alpha_i/gamma_0) g_u on the walls and h_p = n.b (data constant in
+ * time; BDF2 adds the terms above), all from interior traces of u_old = u^n,
+ * u_prev = u^{n-1} (NULL: BDF1) and b.  BDF2 takes eta from vel's CARREAU law. */
 sipg_status sipg_pressure_rhs(sipg_plan* vel, sipg_plan* pres, const double* uhat, const double* u_old,
-                              const double* b, const double* g_wall, double dt, double* f, void* stream);
+                              const double* u_prev, const double* b, const double* g_wall, double dt, double* f,
+                              void* stream);
 
-/* uhh = uhat + (dt/gamma_0) M^-1 [(div v, p)_e - (v, {p} n)_de] ({p} = p- on
+/* uhh = uhat + (dt/gamma_0) M^-1 [(div v, p)_e - (v, {p} n)_de] (gamma_0 of the BDF order 1 or 2; {p} = p- on
  * the walls) and, if rhs_visc is not NULL, the viscous step's right-hand
  * side (gamma_0/dt) M uhh. */
-sipg_status sipg_projection(sipg_plan* vel, sipg_plan* pres, const double* uhat, const double* p, double dt,
-                            double* uhh, double* rhs_visc, void* stream);
+sipg_status sipg_projection(sipg_plan* vel, sipg_plan* pres, const double* uhat, const double* p, int32_t order,
+                            double dt, double* uhh, double* rhs_visc, void* stream);
 
 /* Recomputes a penalty-step plan's per-cell factors from the velocity u:
  * tau_div = zeta |u_e| h_e dt/(k+1), tau_cont = zeta |u_e| dt (|u_e| the
@@ -435,24 +443,26 @@ typedef struct {
 
 void sipg_split_opts_default(sipg_split_opts* opts);
 
-/* Device bytes of the `work` buffer of sipg_split_step: four velocity
+/* Device bytes of the `work` buffer of sipg_split_step: five velocity
  * vectors and one pressure vector, each 256-byte aligned. */
 size_t sipg_split_work_bytes(const sipg_plan* vel, const sipg_plan* pres);
 
-/* One BDF1 step of Alg. 1 with linear-implicit viscosity: uhat
+/* One BDF1 step (u_prev NULL) or BDF2 step (u_prev = u^{n-1}; vel's alpha
+ * = 3/(2 dt)) of Alg. 1 with linear-implicit viscosity nu(u^#), u^# =
+ * sum_i beta_i u^{n-i} (the penalty factors also use u^#): uhat
  * (convective step), the pressure p (Poisson solve of sipg_pressure_rhs,
  * its mean removed, solution of zero nodal mean), uhh and the viscous
- * right-hand side (projection), the viscosity nu(u_old) on every level of
+ * right-hand side (projection), the viscosity nu(u^#) on every level of
  * vel (sipg_update_viscosity), the viscous solve, the penalty factors from
- * u_old and the penalty solve with right-hand side M u_visc into u_new; with
+ * u^# and the penalty solve with right-hand side M u_visc into u_new; with
  * g_wall, the viscous and penalty right-hand sides take sipg_wall_load.
- * Every solve starts from zero.  u_old, b (may be NULL): inputs; u_new, p:
- * outputs (u_new must not alias u_old); work: device buffer of
+ * Every solve starts from zero.  u_old, u_prev, b (may be NULL): inputs;
+ * u_new, p: outputs (u_new must not alias u_old or u_prev); work: device buffer of
  * sipg_split_work_bytes, 256-byte aligned.  Blocks until done; returns the
  * first failing solve's status (info, which may be NULL, holds all three). */
-sipg_status sipg_split_step(sipg_plan* vel, sipg_plan* pres, sipg_plan* pen, const double* u_old, const double* b,
-                            const double* g_wall, double dt, double* u_new, double* p, void* work,
-                            const sipg_split_opts* opts, sipg_split_info* info, void* stream);
+sipg_status sipg_split_step(sipg_plan* vel, sipg_plan* pres, sipg_plan* pen, const double* u_old,
+                            const double* u_prev, const double* b, const double* g_wall, double dt, double* u_new,
+                            double* p, void* work, const sipg_split_opts* opts, sipg_split_info* info, void* stream);
 
 #ifdef __cplusplus
 }

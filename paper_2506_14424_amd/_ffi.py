@@ -128,15 +128,15 @@ def _load():
         "sipg_picard_opts_default": (None, [C.POINTER(PicardOpts)]),
         "sipg_picard_work_bytes": (C.c_size_t, [P]),
         "sipg_picard_solve": (st, [P, P, P, P, C.POINTER(SolveOpts), C.POINTER(PicardOpts), C.POINTER(PicardInfo), P]),
-        "sipg_convective_step": (st, [P, P, P, P, C.c_double, P, P]),
-        "sipg_pressure_rhs": (st, [P, P, P, P, P, P, C.c_double, P, P]),
+        "sipg_convective_step": (st, [P, P, P, P, P, C.c_double, P, P]),
+        "sipg_pressure_rhs": (st, [P, P, P, P, P, P, P, C.c_double, P, P]),
         "sipg_wall_load": (st, [P, P, P, P]),
-        "sipg_projection": (st, [P, P, P, P, C.c_double, P, P, P]),
+        "sipg_projection": (st, [P, P, P, P, C.c_int32, C.c_double, P, P, P]),
         "sipg_update_penalty_factors": (st, [P, P, C.c_double, C.c_double, P]),
         "sipg_split_opts_default": (None, [C.POINTER(SplitOpts)]),
         "sipg_split_work_bytes": (C.c_size_t, [P, P]),
-        "sipg_split_step": (st, [P, P, P, P, P, P, C.c_double, P, P, P, C.POINTER(SplitOpts), C.POINTER(SplitInfo),
-                                 P]),
+        "sipg_split_step": (st, [P, P, P, P, P, P, P, C.c_double, P, P, P, C.POINTER(SplitOpts),
+                                 C.POINTER(SplitInfo), P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

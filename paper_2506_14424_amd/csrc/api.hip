@@ -1352,8 +1352,16 @@ sipg_status check_pressure(const sipg_plan* V, const sipg_plan* Pp) {
     return SIPG_OK;
 }
 
-void fill_split_geo(const sipg_plan* V, SplitGeo& S) {
+void fill_split_geo(const sipg_plan* V, SplitGeo& S, int order = 1) {
     std::memset(&S, 0, sizeof(S));
+    S.order = order;
+    if (order == 2) {
+        S.gamma0 = 1.5; S.alpha[0] = 2.0; S.alpha[1] = -0.5; S.beta[0] = 2.0; S.beta[1] = -1.0; S.beta_bar = 1.0;
+    } else {
+        S.gamma0 = 1.0; S.alpha[0] = 1.0; S.beta[0] = 1.0; S.beta_bar = 0.0;
+    }
+    S.eta[0] = V->law.mu0; S.eta[1] = V->law.mu_inf; S.eta[2] = V->law.lam;
+    S.eta[3] = V->law.n_exp; S.eta[4] = V->law.kappa; S.eta[5] = V->law.a_exp;
     S.nx = V->nx; S.ny = V->ny; S.nz = V->nz;
     S.verts = V->curved ? V->verts64_d : nullptr;
     S.h[0] = 1.0 / V->nx; S.h[1] = 1.0 / V->ny; S.h[2] = 1.0 / V->nz;
@@ -1391,37 +1399,41 @@ long long wall_faces(const sipg_plan* V) {
 
 extern "C" {
 
-sipg_status sipg_convective_step(sipg_plan* V, const double* u, const double* b, const double* g_wall, double dt,
-                                 double* uhat, void* stream) {
+sipg_status sipg_convective_step(sipg_plan* V, const double* u, const double* u_prev, const double* b,
+                                 const double* g_wall, double dt, double* uhat, void* stream) {
     sipg_status rc = check_velocity(V);
     if (rc != SIPG_OK) return rc;
     if (!u || !uhat) return fail(SIPG_ERR_INVALID, "null argument");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(SIPG_ERR_INVALID, "dt must be finite and > 0");
-    if (static_cast<const void*>(u) == static_cast<void*>(uhat) || static_cast<const void*>(b) == static_cast<void*>(uhat))
-        return fail(SIPG_ERR_INVALID, "uhat must not alias u or b (neighbours' values are read)");
+    if (static_cast<const void*>(u) == static_cast<void*>(uhat) || static_cast<const void*>(b) == static_cast<void*>(uhat) ||
+        static_cast<const void*>(u_prev) == static_cast<void*>(uhat))
+        return fail(SIPG_ERR_INVALID, "uhat must not alias u, u_prev or b (neighbours' values are read)");
     SplitGeo S;
-    fill_split_geo(V, S);
+    fill_split_geo(V, S, u_prev ? 2 : 1);
     S.gw = g_wall;
-    HIP_TRY(launch_split_convective(V->n, S, u, b, dt, uhat, static_cast<hipStream_t>(stream)));
+    HIP_TRY(launch_split_convective(V->n, S, u, u_prev, b, dt, uhat, static_cast<hipStream_t>(stream)));
     return SIPG_OK;
 }
 
-sipg_status sipg_pressure_rhs(sipg_plan* V, sipg_plan* Pp, const double* uhat, const double* u_old, const double* b,
-                              const double* g_wall, double dt, double* f, void* stream) {
+sipg_status sipg_pressure_rhs(sipg_plan* V, sipg_plan* Pp, const double* uhat, const double* u_old,
+                              const double* u_prev, const double* b, const double* g_wall, double dt, double* f,
+                              void* stream) {
     sipg_status rc = check_velocity(V);
     if (rc == SIPG_OK) rc = check_pressure(V, Pp);
     if (rc != SIPG_OK) return rc;
     if (!uhat || !u_old || !f) return fail(SIPG_ERR_INVALID, "null argument");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(SIPG_ERR_INVALID, "dt must be finite and > 0");
+    if (u_prev && (V->law.kind != SIPG_LAW_CARREAU || V->op != SIPG_VISCOUS))
+        return fail(SIPG_ERR_INVALID, "the BDF2 pressure wall data need the velocity plan's CARREAU law");
     SplitGeo S;
-    fill_split_geo(V, S);
+    fill_split_geo(V, S, u_prev ? 2 : 1);
     S.gw = g_wall;
-    HIP_TRY(launch_split_ppe_rhs(V->n, S, uhat, u_old, b, dt, f, static_cast<hipStream_t>(stream)));
+    HIP_TRY(launch_split_ppe_rhs(V->n, S, uhat, u_old, u_prev, b, dt, f, static_cast<hipStream_t>(stream)));
     return SIPG_OK;
 }
 
-sipg_status sipg_projection(sipg_plan* V, sipg_plan* Pp, const double* uhat, const double* p, double dt, double* uhh,
-                            double* rhs_visc, void* stream) {
+sipg_status sipg_projection(sipg_plan* V, sipg_plan* Pp, const double* uhat, const double* p, int32_t order, double dt,
+                            double* uhh, double* rhs_visc, void* stream) {
     sipg_status rc = check_velocity(V);
     if (rc == SIPG_OK) rc = check_pressure(V, Pp);
     if (rc != SIPG_OK) return rc;
@@ -1430,8 +1442,9 @@ sipg_status sipg_projection(sipg_plan* V, sipg_plan* Pp, const double* uhat, con
     if (static_cast<const void*>(p) == static_cast<void*>(uhh) || (rhs_visc && static_cast<const void*>(p) == rhs_visc) ||
         (rhs_visc && static_cast<const void*>(uhat) == rhs_visc) || rhs_visc == uhh)
         return fail(SIPG_ERR_INVALID, "outputs must not alias p, each other, or (rhs_visc) uhat");
+    if (order != 1 && order != 2) return fail(SIPG_ERR_INVALID, "BDF order 1 or 2");
     SplitGeo S;
-    fill_split_geo(V, S);
+    fill_split_geo(V, S, order);
     HIP_TRY(launch_split_projection(V->n, S, uhat, p, dt, uhh, rhs_visc, static_cast<hipStream_t>(stream)));
     return SIPG_OK;
 }
@@ -1479,11 +1492,11 @@ void sipg_split_opts_default(sipg_split_opts* o) {
 
 size_t sipg_split_work_bytes(const sipg_plan* V, const sipg_plan* Pp) {
     if (!valid_plan(V) || !valid_plan(Pp)) return 0;
-    return 4 * split_vec_bytes(V->ndof) + split_vec_bytes(Pp->ndof);
+    return 5 * split_vec_bytes(V->ndof) + split_vec_bytes(Pp->ndof);
 }
 
-sipg_status sipg_split_step(sipg_plan* V, sipg_plan* Pp, sipg_plan* Pen, const double* u_old, const double* b,
-                            const double* g_wall, double dt, double* u_new, double* p, void* work,
+sipg_status sipg_split_step(sipg_plan* V, sipg_plan* Pp, sipg_plan* Pen, const double* u_old, const double* u_prev,
+                            const double* b, const double* g_wall, double dt, double* u_new, double* p, void* work,
                             const sipg_split_opts* opts, sipg_split_info* info, void* stream) {
     sipg_status rc = check_velocity(V);
     if (rc == SIPG_OK) rc = check_pressure(V, Pp);
@@ -1499,10 +1512,13 @@ sipg_status sipg_split_step(sipg_plan* V, sipg_plan* Pp, sipg_plan* Pen, const d
     if (!u_old || !u_new || !p || !work) return fail(SIPG_ERR_INVALID, "null argument");
     if (reinterpret_cast<uintptr_t>(work) % 256 != 0) return fail(SIPG_ERR_INVALID, "work must be 256-byte aligned");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(SIPG_ERR_INVALID, "dt must be finite and > 0");
-    if (std::fabs(V->alpha * dt - 1.0) > 1e-12)
-        return fail(SIPG_ERR_INVALID, "the velocity plan's alpha must be gamma_0/dt (BDF1: 1/dt)");
-    if (static_cast<const void*>(u_old) == static_cast<void*>(u_new))
-        return fail(SIPG_ERR_INVALID, "u_new must not alias u_old");
+    const int order = u_prev ? 2 : 1;
+    const double gamma0 = order == 2 ? 1.5 : 1.0;
+    if (std::fabs(V->alpha * dt - gamma0) > 1e-12 * gamma0)
+        return fail(SIPG_ERR_INVALID, "the velocity plan's alpha must be gamma_0/dt (BDF1: 1/dt, BDF2: 1.5/dt)");
+    if (static_cast<const void*>(u_old) == static_cast<void*>(u_new) ||
+        static_cast<const void*>(u_prev) == static_cast<void*>(u_new))
+        return fail(SIPG_ERR_INVALID, "u_new must not alias u_old or u_prev");
     sipg_split_opts o;
     if (opts) o = *opts; else sipg_split_opts_default(&o);
     if (!(o.zeta >= 0.0) || !std::isfinite(o.zeta)) return fail(SIPG_ERR_INVALID, "zeta must be finite and >= 0");
@@ -1513,15 +1529,16 @@ sipg_status sipg_split_step(sipg_plan* V, sipg_plan* Pp, sipg_plan* Pen, const d
     double* uhh = reinterpret_cast<double*>(w + vb);
     double* rhs = reinterpret_cast<double*>(w + 2 * vb);
     double* uvisc = reinterpret_cast<double*>(w + 3 * vb);
-    double* f = reinterpret_cast<double*>(w + 4 * vb);
+    double* uex = reinterpret_cast<double*>(w + 4 * vb);
+    double* f = reinterpret_cast<double*>(w + 5 * vb);
     const char* we = w + sipg_split_work_bytes(V, Pp);
     auto overlaps = [&](const void* v, size_t bytes) {
         const char* a = static_cast<const char*>(v);
         return v && a + bytes > w && a < we;
     };
     const size_t gw_bytes = (size_t)wall_faces(V) * V->n * V->n * 3 * 8;
-    if (overlaps(u_old, nu * 8) || overlaps(b, nu * 8) || overlaps(u_new, nu * 8) || overlaps(p, Pp->ndof * 8) ||
-        overlaps(g_wall, gw_bytes))
+    if (overlaps(u_old, nu * 8) || overlaps(u_prev, nu * 8) || overlaps(b, nu * 8) || overlaps(u_new, nu * 8) ||
+        overlaps(p, Pp->ndof * 8) || overlaps(g_wall, gw_bytes))
         return fail(SIPG_ERR_INVALID, "work must not alias the step's vectors");
 
     sipg_split_info inf;
@@ -1530,14 +1547,20 @@ sipg_status sipg_split_step(sipg_plan* V, sipg_plan* Pp, sipg_plan* Pen, const d
         if (info) *info = inf;
         return r;
     };
-    rc = sipg_convective_step(V, u_old, b, g_wall, dt, uhat, stream);
-    if (rc == SIPG_OK) rc = sipg_pressure_rhs(V, Pp, uhat, u_old, b, g_wall, dt, f, stream);
+    // u^# = sum_i beta_i u^{n-i}: the viscosity and the penalty factors of the step
+    const double* ux = u_old;
+    if (order == 2) {
+        HIP_TRY(launch_lincomb(nu, 2.0, u_old, -1.0, u_prev, uex, static_cast<hipStream_t>(stream)));
+        ux = uex;
+    }
+    rc = sipg_convective_step(V, u_old, u_prev, b, g_wall, dt, uhat, stream);
+    if (rc == SIPG_OK) rc = sipg_pressure_rhs(V, Pp, uhat, u_old, u_prev, b, g_wall, dt, f, stream);
     if (rc == SIPG_OK) rc = sipg_solve(Pp, f, p, &o.pressure, &inf.pressure, stream);
-    if (rc == SIPG_OK) rc = sipg_projection(V, Pp, uhat, p, dt, uhh, rhs, stream);
-    if (rc == SIPG_OK) rc = update_viscosity(V, u_old, static_cast<hipStream_t>(stream));
+    if (rc == SIPG_OK) rc = sipg_projection(V, Pp, uhat, p, order, dt, uhh, rhs, stream);
+    if (rc == SIPG_OK) rc = update_viscosity(V, ux, static_cast<hipStream_t>(stream));
     if (rc == SIPG_OK && g_wall) rc = sipg_wall_load(V, g_wall, rhs, stream);
     if (rc == SIPG_OK) rc = sipg_solve(V, rhs, uvisc, &o.viscous, &inf.viscous, stream);
-    if (rc == SIPG_OK) rc = sipg_update_penalty_factors(Pen, u_old, dt, o.zeta, stream);
+    if (rc == SIPG_OK) rc = sipg_update_penalty_factors(Pen, ux, dt, o.zeta, stream);
     if (rc == SIPG_OK) {
         SplitGeo S;
         fill_split_geo(V, S);

@@ -131,6 +131,10 @@ struct SplitGeo {
     double PD[kMaxN][kMaxN];     // PD[q][j] = l^p_j'(g_q)
     double PS[2][kMaxN];         // PS[s][j] = l^p_j(s)
     const double* gw;            // velocity data on the walls (wall rows x n^2 points x 3), or nullptr (0)
+    int order;                   // BDF order m (1, 2) of the step
+    double gamma0, alpha[2], beta[2];   // BDF coefficients and extrapolation weights
+    double beta_bar;             // extrapolation weight of the pressure wall data (m_p = 1), 0 for m = 1
+    double eta[6];               // mu0, mu_inf, lam, n_exp, kappa, a_exp of the Carreau law (m = 2)
 };
 
 // ---------------------------------------------------------------- launchers
@@ -161,10 +165,12 @@ hipError_t launch_picard_sums(const double* R, const double* Rp, long long n, do
 hipError_t launch_axpy(double* x, const double* d, double omega, long long n, hipStream_t s);
 
 // Dual-splitting step operators (n = 3..6; one workgroup per cell)
-hipError_t launch_split_convective(int n, const SplitGeo& S, const double* u, const double* b, double dt,
-                                   double* uhat, hipStream_t s);
-hipError_t launch_split_ppe_rhs(int n, const SplitGeo& S, const double* uhat, const double* u_old, const double* b,
-                                double dt, double* f, hipStream_t s);
+hipError_t launch_split_convective(int n, const SplitGeo& S, const double* u, const double* u_prev, const double* b,
+                                   double dt, double* uhat, hipStream_t s);
+hipError_t launch_split_ppe_rhs(int n, const SplitGeo& S, const double* uhat, const double* u_old,
+                                const double* u_prev, const double* b, double dt, double* f, hipStream_t s);
+// y = a x + c z (n values)
+hipError_t launch_lincomb(long long n, double a, const double* x, double c, const double* z, double* y, hipStream_t s);
 hipError_t launch_split_projection(int n, const SplitGeo& S, const double* uhat, const double* p, double dt,
                                    double* uhh, double* rhs, hipStream_t s);
 hipError_t launch_split_mass(int n, const SplitGeo& S, const double* x, double scale, double* y, hipStream_t s);

@@ -1,7 +1,7 @@
 // Operators of one dual-splitting time step that are not linear solves
 // (Sec. 3 "Splitting Scheme"; weak forms of Sec. 4.1; order of Alg. 1):
 //
-//   convective step   uhat = (alpha_0/gamma_0) u^n + (dt/gamma_0)(b - beta_0 M^-1 c_h(u^n; u^n))
+//   convective step   uhat = sum_i (alpha_i/gamma_0) u^{n-i} + (dt/gamma_0)(b - sum_i beta_i M^-1 c_h(u^{n-i}; u^{n-i}))
 //                     (eqs. convective_step_weak, convective_term_weak: (w.grad)u
 //                     in the cell, upwind flux on the faces, mirror principle
 //                     with g_u = 0 on the walls, where {w} = 0 removes the term)
@@ -16,12 +16,18 @@
 //   penalty factors   tau_div = zeta |u_e| h_e dt/(k+1), tau_cont = zeta |u_e| dt,
 //                     |u_e| the volume mean of |u| over the cell
 //
-// BDF1 coefficients (gamma_0 = alpha_0 = beta_0 = 1; m_p = 0 leaves no
-// extrapolated terms in h_p).  Velocity DG_k nodal at its n = k+1 Gauss
+// BDF1 (gamma_0 = alpha_0 = beta_0 = 1; m_p = 0 leaves no extrapolated
+// terms in h_p) or BDF2 (gamma_0 = 3/2, alpha = (2, -1/2), beta = (2, -1);
+// m_p = 1: h_p takes -n.((grad u^n) u^n) - nu n.curl(omega) +
+// 2 n.(grad^S u^n . grad nu) with omega = curl u^n and nu = eta(gdot(u^n))
+// projected onto DG_k, i.e. their values at the Gauss nodes; the
+// coefficients come in SplitGeo).  Velocity DG_k nodal at its n = k+1 Gauss
 // points, pressure DG_{k-1} at its n-1; all integrals on the velocity's
 // n-point rule.  One workgroup per cell: thread q < n^3 owns a velocity
 // node (or a quadrature point), thread t < 6 n^2 a face point, thread
 // j < (n-1)^3 a pressure node; the cell's data are staged in LDS.  FP64.
+
+#include <algorithm>
 
 #include "device_common.h"
 
@@ -29,7 +35,6 @@ namespace sipg {
 
 namespace {
 
-constexpr double kGamma0 = 1.0, kAlpha0 = 1.0, kBeta0 = 1.0;
 // Workgroup sizes: a multiple of the 64-wide wavefront covering a cell's
 // n^3 nodes (kCellThreads, a power of two for the tree sums) or also its
 // 6 n^2 face points (kFaceThreads).
@@ -184,82 +189,134 @@ __device__ __forceinline__ void conv_face(const SplitGeo& S, const CellMap& m, i
 
 template <int N>
 __global__ void __launch_bounds__(kFaceThreads<N>) k_split_convective(SplitGeo S, const double* __restrict__ u,
+                                                                     const double* __restrict__ u1,
                                                                      const double* __restrict__ b, double dt,
                                                                      double* __restrict__ uhat) {
     constexpr int N2 = N * N, N3 = N2 * N;
     __shared__ double U[3 * N3];
     __shared__ double FF[6][N2][3];
     const int e = blockIdx.x, t = threadIdx.x;
-    const double* ue = u + (long long)e * 3 * N3;
-    for (int i = t; i < 3 * N3; i += blockDim.x) U[i] = ue[i];
-    __syncthreads();
     int ijk[3];
     cell_ijk(S, e, ijk);
     CellMap m;
     cell_map(S, ijk[0], ijk[1], ijk[2], m);
-    if (t < 6 * N2) {
-        const int fc = t / N2, ab = t % N2;
-        switch (fc) {
-            case 0: conv_face<N, 0>(S, m, e, ijk, ab, U, u, FF[0][ab]); break;
-            case 1: conv_face<N, 1>(S, m, e, ijk, ab, U, u, FF[1][ab]); break;
-            case 2: conv_face<N, 2>(S, m, e, ijk, ab, U, u, FF[2][ab]); break;
-            case 3: conv_face<N, 3>(S, m, e, ijk, ab, U, u, FF[3][ab]); break;
-            case 4: conv_face<N, 4>(S, m, e, ijk, ab, U, u, FF[4][ab]); break;
-            default: conv_face<N, 5>(S, m, e, ijk, ab, U, u, FF[5][ab]); break;
-        }
-    }
-    __syncthreads();
-    if (t >= N3) return;
     const int qi[3] = {t % N, (t / N) % N, t / N2};
     const int str[3] = {1, N, N2};
-    double Ji[3][3], det;
-    point_geo(m, S.tab.x[qi[0]], S.tab.x[qi[1]], S.tab.x[qi[2]], Ji, det);
-    double uq[3], gr[3][3];
+    double Ji[3][3], det = 1.0;
+    if (t < N3) point_geo(m, S.tab.x[qi[0]], S.tab.x[qi[1]], S.tab.x[qi[2]], Ji, det);
+    const double wq = S.tab.w[qi[0] % N] * S.tab.w[qi[1] % N] * S.tab.w[qi[2] % N];
+    const double inv_m = 1.0 / (wq * det);
+    double cacc[3] = {0.0, 0.0, 0.0}, uacc[3] = {0.0, 0.0, 0.0};
+    // sum over the old velocities u^{n-i}: alpha_i u^{n-i} and beta_i M^-1 c_h(u^{n-i}; u^{n-i})
+    for (int i = 0; i < S.order; ++i) {
+        const double* ui = i == 0 ? u : u1;
+        __syncthreads();                              // the previous velocity's readers are done
+        const double* ue = ui + (long long)e * 3 * N3;
+        for (int k = t; k < 3 * N3; k += blockDim.x) U[k] = ue[k];
+        __syncthreads();
+        if (t < 6 * N2) {
+            const int fc = t / N2, ab = t % N2;
+            switch (fc) {
+                case 0: conv_face<N, 0>(S, m, e, ijk, ab, U, ui, FF[0][ab]); break;
+                case 1: conv_face<N, 1>(S, m, e, ijk, ab, U, ui, FF[1][ab]); break;
+                case 2: conv_face<N, 2>(S, m, e, ijk, ab, U, ui, FF[2][ab]); break;
+                case 3: conv_face<N, 3>(S, m, e, ijk, ab, U, ui, FF[3][ab]); break;
+                case 4: conv_face<N, 4>(S, m, e, ijk, ab, U, ui, FF[4][ab]); break;
+                default: conv_face<N, 5>(S, m, e, ijk, ab, U, ui, FF[5][ab]); break;
+            }
+        }
+        __syncthreads();
+        if (t < N3) {
+            double uq[3], gr[3][3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        uq[c] = U[c * N3 + t];
+            for (int c = 0; c < 3; ++c) {
+                uq[c] = U[c * N3 + t];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            double acc = 0.0;
-            const int base = c * N3 + t - qi[d] * str[d];
+                for (int d = 0; d < 3; ++d) {
+                    double acc = 0.0;
+                    const int base = c * N3 + t - qi[d] * str[d];
 #pragma unroll
-            for (int k = 0; k < N; ++k) acc += S.tab.D[qi[d]][k] * U[base + k * str[d]];
-            gr[c][d] = acc;
+                    for (int k = 0; k < N; ++k) acc += S.tab.D[qi[d]][k] * U[base + k * str[d]];
+                    gr[c][d] = acc;
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                double a = 0.0;
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+                    a += (gr[c][0] * Ji[0][k] + gr[c][1] * Ji[1][k] + gr[c][2] * Ji[2][k]) * uq[k];
+                double face = 0.0;
+#pragma unroll
+                for (int fc = 0; fc < 6; ++fc) {
+                    const int d = fc >> 1, s = fc & 1;
+                    const int ta = d == 0 ? 1 : 0, tb = d == 2 ? 1 : 2;
+                    face += S.tab.S[s][qi[d]] * FF[fc][qi[tb] * N + qi[ta]][c];
+                }
+                cacc[c] += S.beta[i] * (a + face * inv_m);
+                uacc[c] += S.alpha[i] * uq[c];
+            }
         }
     }
-    double a[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        double acc = 0.0;
-#pragma unroll
-        for (int i = 0; i < 3; ++i) acc += (gr[c][0] * Ji[0][i] + gr[c][1] * Ji[1][i] + gr[c][2] * Ji[2][i]) * uq[i];
-        a[c] = acc;
-    }
-    double face[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-    for (int fc = 0; fc < 6; ++fc) {
-        const int d = fc >> 1, s = fc & 1;
-        const int ta = d == 0 ? 1 : 0, tb = d == 2 ? 1 : 2;
-        const double sc = S.tab.S[s][qi[d]];
-        const double* F = FF[fc][qi[tb] * N + qi[ta]];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) face[c] += sc * F[c];
-    }
-    const double wq = S.tab.w[qi[0]] * S.tab.w[qi[1]] * S.tab.w[qi[2]];
-    const double inv_m = 1.0 / (wq * det);
+    if (t >= N3) return;
     double* out = uhat + (long long)e * 3 * N3;
     const double* be = b ? b + (long long)e * 3 * N3 : nullptr;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const double bq = be ? be[c * N3 + t] : 0.0;
-        out[c * N3 + t] = kAlpha0 / kGamma0 * uq[c] + dt / kGamma0 * (bq - kBeta0 * (a[c] + face[c] * inv_m));
+        out[c * N3 + t] = uacc[c] / S.gamma0 + dt / S.gamma0 * (bq - cacc[c]);
     }
+}
+
+__device__ __forceinline__ double eta_split(const SplitGeo& S, double gdot) {
+    return S.eta[1] + (S.eta[0] - S.eta[1]) * pow(S.eta[4] + pow(S.eta[2] * gdot, S.eta[5]), (S.eta[3] - 1.0) / S.eta[5]);
+}
+
+// Trace and reference gradient (d/dxi_1, d/dxi_2, d/dxi_3) at the face point
+// (a, bb) of face (D, SD) of one component's n^3 nodal values P of a cell.
+template <int N, int D, int SD>
+__device__ __forceinline__ void face_trace_grad(const SplitGeo& S, const double* P, int a, int bb, double& tr,
+                                                double gref[3]) {
+    constexpr int t1 = D == 0 ? 1 : 0, t2 = D == 2 ? 1 : 2;
+    const int str[3] = {1, N, N * N};
+    const int line = a * str[t1] + bb * str[t2];
+    double v = 0.0, dn = 0.0, d1 = 0.0, d2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        v += S.tab.S[SD][k] * P[line + k * str[D]];
+        dn += S.tab.G[SD][k] * P[line + k * str[D]];
+    }
+#pragma unroll 1
+    for (int k2 = 0; k2 < N; ++k2) {
+        double t1v = 0.0, t2v = 0.0;
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            t1v += S.tab.S[SD][k] * P[k2 * str[t1] + bb * str[t2] + k * str[D]];
+            t2v += S.tab.S[SD][k] * P[a * str[t1] + k2 * str[t2] + k * str[D]];
+        }
+        d1 += S.tab.D[a][k2] * t1v;
+        d2 += S.tab.D[bb][k2] * t2v;
+    }
+    tr = v;
+    gref[D] = dn;
+    gref[t1] = d1;
+    gref[t2] = d2;
+}
+
+// physical gradient G[c][i] of a 3-component field at a face point from its
+// trace ut and reference gradients gref[c][d]
+__device__ __forceinline__ void phys_grad3(const double gref[3][3], const double Ji[3][3], double G[3][3]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) G[c][i] = gref[c][0] * Ji[0][i] + gref[c][1] * Ji[1][i] + gref[c][2] * Ji[2][i];
 }
 
 template <int N, int FC>
 __device__ __forceinline__ double ppe_face(const SplitGeo& S, const CellMap& m, int e, const int ijk[3], int ab,
-                                       const double* __restrict__ uhat, const double* __restrict__ u_old,
-                                       const double* __restrict__ b, double dt) {
+                                           const double* __restrict__ uhat, const double* __restrict__ u_old,
+                                           const double* __restrict__ u1, const double* __restrict__ b, double dt,
+                                           const double* OM, const double* NU) {
     constexpr int N2 = N * N, N3 = N2 * N, d = FC >> 1, s = FC & 1;
     const int str[3] = {1, N, N2};
     const int a = ab % N, bb = ab / N;
@@ -282,66 +339,97 @@ __device__ __forceinline__ double ppe_face(const SplitGeo& S, const CellMap& m, 
             }
             an += 0.5 * (sm + sp) * fp.n[c];
         }
-        val = -kGamma0 / dt * an;
+        val = -S.gamma0 / dt * an;
     } else {
-        // wall: g_uhat = (dt/gamma_0)(b - beta_0 (grad u^n) u^n) + (alpha_0/gamma_0) g_u,
-        // h_p = n.b (- n.d_t g_u = 0: data constant in time), from the interior traces
-        const double* uo = u_old + (long long)e * 3 * N3;
+        // wall, from the interior traces:
+        // g_uhat = (dt/gamma_0)(b - sum_i beta_i (grad u^{n-i}) u^{n-i}) + sum_i (alpha_i/gamma_0) g_u,
+        // h_p = n.b - n.d_t g_u (= 0: data constant in time) - beta_bar n.((grad u^n) u^n)
+        //       - nu n.curl(omega) + 2 n.(grad^S u^n . grad nu)      (BDF2: m_p = 1, u^dd = u^n)
         const double* be = b ? b + (long long)e * 3 * N3 : nullptr;
-        double ut[3], bt[3], gref[3][3];
+        double bt[3] = {0.0, 0.0, 0.0};
+        if (be) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const double* uc = uo + c * N3;
-            double tr = 0.0, dn = 0.0, btc = 0.0, d1 = 0.0, d2 = 0.0;
+            for (int c = 0; c < 3; ++c) {
+                double v = 0.0;
 #pragma unroll
-            for (int k = 0; k < N; ++k) {
-                tr += S.tab.S[s][k] * uc[line + k * str[d]];
-                dn += S.tab.G[s][k] * uc[line + k * str[d]];
-                if (be) btc += S.tab.S[s][k] * be[c * N3 + line + k * str[d]];
+                for (int k = 0; k < N; ++k) v += S.tab.S[s][k] * be[c * N3 + line + k * str[d]];
+                bt[c] = v;
             }
-            // tangential derivatives of the trace
-#pragma unroll 1
-            for (int k2 = 0; k2 < N; ++k2) {
-                double t1v = 0.0, t2v = 0.0;
+        }
+        double conv_sum[3] = {0.0, 0.0, 0.0}, conv0[3] = {0.0, 0.0, 0.0}, G0[3][3];
+        for (int i = 0; i < S.order; ++i) {
+            const double* uo = (i == 0 ? u_old : u1) + (long long)e * 3 * N3;
+            double ut[3], gref[3][3], G[3][3];
 #pragma unroll
-                for (int k = 0; k < N; ++k) {
-                    t1v += S.tab.S[s][k] * uc[k2 * str[fp.t1] + bb * str[fp.t2] + k * str[d]];
-                    t2v += S.tab.S[s][k] * uc[a * str[fp.t1] + k2 * str[fp.t2] + k * str[d]];
-                }
-                d1 += S.tab.D[a][k2] * t1v;
-                d2 += S.tab.D[bb][k2] * t2v;
+            for (int c = 0; c < 3; ++c) face_trace_grad<N, d, s>(S, uo + c * N3, a, bb, ut[c], gref[c]);
+            phys_grad3(gref, fp.Ji, G);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const double cv = G[c][0] * ut[0] + G[c][1] * ut[1] + G[c][2] * ut[2];
+                conv_sum[c] += S.beta[i] * cv;
+                if (i == 0) conv0[c] = cv;
             }
-            ut[c] = tr;
-            bt[c] = btc;
-            gref[c][d] = dn;
-            gref[c][fp.t1] = d1;
-            gref[c][fp.t2] = d2;
+            if (i == 0) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) G0[c][k] = G[c][k];
+            }
         }
         double gn = 0.0, hp = 0.0;
+        const double asum = S.alpha[0] + (S.order > 1 ? S.alpha[1] : 0.0);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            double conv = 0.0;
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-                conv += (gref[c][0] * fp.Ji[0][i] + gref[c][1] * fp.Ji[1][i] + gref[c][2] * fp.Ji[2][i]) * ut[i];
             const double gu = S.gw ? S.gw[((long long)wall_row(S, ijk, d, s) * N2 + ab) * 3 + c] : 0.0;
-            const double guhat = dt / kGamma0 * (bt[c] - kBeta0 * conv) + kAlpha0 / kGamma0 * gu;
+            const double guhat = dt / S.gamma0 * (bt[c] - conv_sum[c]) + asum / S.gamma0 * gu;
             gn += guhat * fp.n[c];
-            hp += fp.n[c] * bt[c];
+            hp += fp.n[c] * (bt[c] - S.beta_bar * conv0[c]);
         }
-        val = -kGamma0 / dt * gn + hp;
+        if (S.order > 1) {
+            double ee = 0.0, Sy[3][3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    Sy[c][k] = 0.5 * (G0[c][k] + G0[k][c]);
+                    ee += Sy[c][k] * Sy[c][k];
+                }
+            const double nu = eta_split(S, sqrt(2.0 * ee));
+            double ot[3], gro[3][3], Go[3][3], nt, gn_ref[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) face_trace_grad<N, d, s>(S, OM + c * N3, a, bb, ot[c], gro[c]);
+            phys_grad3(gro, fp.Ji, Go);
+            const double curl[3] = {Go[2][1] - Go[1][2], Go[0][2] - Go[2][0], Go[1][0] - Go[0][1]};
+            face_trace_grad<N, d, s>(S, NU, a, bb, nt, gn_ref);
+            double gnu[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                gnu[k] = gn_ref[0] * fp.Ji[0][k] + gn_ref[1] * fp.Ji[1][k] + gn_ref[2] * fp.Ji[2][k];
+            double ncurl = 0.0, nsg = 0.0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                ncurl += fp.n[c] * curl[c];
+                nsg += fp.n[c] * (Sy[c][0] * gnu[0] + Sy[c][1] * gnu[1] + Sy[c][2] * gnu[2]);
+            }
+            hp += -nu * ncurl + 2.0 * nsg;
+        }
+        val = -S.gamma0 / dt * gn + hp;
     }
     return fp.ds * val;
 }
 
 template <int N>
 __global__ void __launch_bounds__(kFaceThreads<N>) k_split_ppe_rhs(SplitGeo S, const double* __restrict__ uhat,
-                                                            const double* __restrict__ u_old,
-                                                            const double* __restrict__ b, double dt,
-                                                            double* __restrict__ f) {
+                                                                  const double* __restrict__ u_old,
+                                                                  const double* __restrict__ u1,
+                                                                  const double* __restrict__ b, double dt,
+                                                                  double* __restrict__ f) {
     constexpr int N2 = N * N, N3 = N2 * N, NP = N - 1, NP3 = NP * NP * NP;
     __shared__ double GQ[3][N3];
     __shared__ double FF[6][N2];
+    __shared__ double UO[3 * N3];      // BDF2, wall cells: u^n, its vorticity and viscosity at the nodes
+    __shared__ double OM[3 * N3];
+    __shared__ double NU[N3];
     const int e = blockIdx.x, t = threadIdx.x;
     int ijk[3];
     cell_ijk(S, e, ijk);
@@ -349,25 +437,64 @@ __global__ void __launch_bounds__(kFaceThreads<N>) k_split_ppe_rhs(SplitGeo S, c
     cell_map(S, ijk[0], ijk[1], ijk[2], m);
     const int str[3] = {1, N, N2};
     const double* uh = uhat + (long long)e * 3 * N3;
+    const bool wall = ijk[0] == 0 || ijk[0] == S.nx - 1 || ijk[1] == 0 || ijk[1] == S.ny - 1 || ijk[2] == 0 ||
+                      ijk[2] == S.nz - 1;
+    if (S.order > 1 && wall) {         // uniform over the workgroup
+        const double* uo = u_old + (long long)e * 3 * N3;
+        for (int k = t; k < 3 * N3; k += blockDim.x) UO[k] = uo[k];
+        __syncthreads();
+        if (t < N3) {
+            // omega = curl u and nu = eta(gdot(grad^S u)) at the node: with the
+            // nodes at the Gauss points (diagonal mass matrix) these are the
+            // element-local L2 projections onto DG_k
+            const int qi[3] = {t % N, (t / N) % N, t / N2};
+            double Ji[3][3], det, gr[3][3], G[3][3];
+            point_geo(m, S.tab.x[qi[0]], S.tab.x[qi[1]], S.tab.x[qi[2]], Ji, det);
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    double acc = 0.0;
+                    const int base = c * N3 + t - qi[d] * str[d];
+#pragma unroll
+                    for (int k = 0; k < N; ++k) acc += S.tab.D[qi[d]][k] * UO[base + k * str[d]];
+                    gr[c][d] = acc;
+                }
+            phys_grad3(gr, Ji, G);
+            OM[t] = G[2][1] - G[1][2];
+            OM[N3 + t] = G[0][2] - G[2][0];
+            OM[2 * N3 + t] = G[1][0] - G[0][1];
+            double ee = 0.0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const double sy = 0.5 * (G[c][k] + G[k][c]);
+                    ee += sy * sy;
+                }
+            NU[t] = eta_split(S, sqrt(2.0 * ee));
+        }
+        __syncthreads();
+    }
     if (t < N3) {
         const int q1 = t % N, q2 = (t / N) % N, q3 = t / N2;
         double Ji[3][3], det;
         point_geo(m, S.tab.x[q1], S.tab.x[q2], S.tab.x[q3], Ji, det);
         const double jw = S.tab.w[q1] * S.tab.w[q2] * S.tab.w[q3] * det;
-        const double u0 = uh[t], u1 = uh[N3 + t], u2 = uh[2 * N3 + t];
+        const double u0 = uh[t], v1 = uh[N3 + t], v2 = uh[2 * N3 + t];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) GQ[d][t] = jw * (Ji[d][0] * u0 + Ji[d][1] * u1 + Ji[d][2] * u2);
+        for (int d = 0; d < 3; ++d) GQ[d][t] = jw * (Ji[d][0] * u0 + Ji[d][1] * v1 + Ji[d][2] * v2);
     }
     if (t < 6 * N2) {
         const int fc = t / N2, ab = t % N2;
         double v = 0.0;
         switch (fc) {
-            case 0: v = ppe_face<N, 0>(S, m, e, ijk, ab, uhat, u_old, b, dt); break;
-            case 1: v = ppe_face<N, 1>(S, m, e, ijk, ab, uhat, u_old, b, dt); break;
-            case 2: v = ppe_face<N, 2>(S, m, e, ijk, ab, uhat, u_old, b, dt); break;
-            case 3: v = ppe_face<N, 3>(S, m, e, ijk, ab, uhat, u_old, b, dt); break;
-            case 4: v = ppe_face<N, 4>(S, m, e, ijk, ab, uhat, u_old, b, dt); break;
-            default: v = ppe_face<N, 5>(S, m, e, ijk, ab, uhat, u_old, b, dt); break;
+            case 0: v = ppe_face<N, 0>(S, m, e, ijk, ab, uhat, u_old, u1, b, dt, OM, NU); break;
+            case 1: v = ppe_face<N, 1>(S, m, e, ijk, ab, uhat, u_old, u1, b, dt, OM, NU); break;
+            case 2: v = ppe_face<N, 2>(S, m, e, ijk, ab, uhat, u_old, u1, b, dt, OM, NU); break;
+            case 3: v = ppe_face<N, 3>(S, m, e, ijk, ab, uhat, u_old, u1, b, dt, OM, NU); break;
+            case 4: v = ppe_face<N, 4>(S, m, e, ijk, ab, uhat, u_old, u1, b, dt, OM, NU); break;
+            default: v = ppe_face<N, 5>(S, m, e, ijk, ab, uhat, u_old, u1, b, dt, OM, NU); break;
         }
         FF[fc][ab] = v;
     }
@@ -389,7 +516,7 @@ __global__ void __launch_bounds__(kFaceThreads<N>) k_split_ppe_rhs(SplitGeo S, c
             }
         }
     }
-    acc *= kGamma0 / dt;
+    acc *= S.gamma0 / dt;
 #pragma unroll
     for (int fc = 0; fc < 6; ++fc) {
         const int d = fc >> 1, s = fc & 1;
@@ -406,6 +533,12 @@ __global__ void __launch_bounds__(kFaceThreads<N>) k_split_ppe_rhs(SplitGeo S, c
         acc += cn * fs;
     }
     f[(long long)e * NP3 + t] = acc;
+}
+
+__global__ void k_lincomb(long long n, double a, const double* __restrict__ x, double c,
+                          const double* __restrict__ z, double* __restrict__ y) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        y[i] = a * x[i] + c * z[i];
 }
 
 // pressure of a cell (NP^3 nodal values) at the velocity face point (a, b) of face (d, s)
@@ -516,9 +649,9 @@ __global__ void __launch_bounds__(kFaceThreads<N>) k_split_projection(SplitGeo S
             const int ta = d == 0 ? 1 : 0, tb = d == 2 ? 1 : 2;
             acc -= S.tab.S[s][qi[d]] * FP[fc][qi[tb] * N + qi[ta]][c];
         }
-        const double v = ue[c * N3 + t] + dt / kGamma0 * acc / jw;
+        const double v = ue[c * N3 + t] + dt / S.gamma0 * acc / jw;
         out[c * N3 + t] = v;
-        if (ro) ro[c * N3 + t] = kGamma0 / dt * jw * v;
+        if (ro) ro[c * N3 + t] = S.gamma0 / dt * jw * v;
     }
 }
 
@@ -674,14 +807,14 @@ __global__ void __launch_bounds__(kFaceThreads<N>) k_wall_load(SplitGeo S, const
 }
 
 template <int N>
-hipError_t launch_n(int which, const SplitGeo& S, const double* a0, const double* a1, const double* a2, double s0,
-                    double s1, double* o0, double* o1, hipStream_t s) {
+hipError_t launch_n(int which, const SplitGeo& S, const double* a0, const double* a1, const double* a2,
+                    const double* a3, double s0, double s1, double* o0, double* o1, hipStream_t s) {
     const dim3 grid((unsigned)(S.nx * S.ny * S.nz)), cb(kCellThreads<N>), fb(kFaceThreads<N>);
     static_assert(kCellThreads<N> >= N * N * N && kFaceThreads<N> >= 6 * N * N && kFaceThreads<N> >= N * N * N,
                   "a workgroup must cover the cell's nodes and face points");
     switch (which) {
-        case 0: hipLaunchKernelGGL(k_split_convective<N>, grid, fb, 0, s, S, a0, a1, s0, o0); break;
-        case 1: hipLaunchKernelGGL(k_split_ppe_rhs<N>, grid, fb, 0, s, S, a0, a1, a2, s0, o0); break;
+        case 0: hipLaunchKernelGGL(k_split_convective<N>, grid, fb, 0, s, S, a0, a1, a2, s0, o0); break;
+        case 1: hipLaunchKernelGGL(k_split_ppe_rhs<N>, grid, fb, 0, s, S, a0, a1, a2, a3, s0, o0); break;
         case 2: hipLaunchKernelGGL(k_split_projection<N>, grid, fb, 0, s, S, a0, a1, s0, o0, o1); break;
         case 3: hipLaunchKernelGGL(k_split_mass<N>, grid, cb, 0, s, S, a0, s0, o0); break;
         case 4: hipLaunchKernelGGL(k_pen_factors<N>, grid, cb, 0, s, S, a0, s0, s1, a1, o0, o1); break;
@@ -692,26 +825,32 @@ hipError_t launch_n(int which, const SplitGeo& S, const double* a0, const double
 }
 
 hipError_t dispatch(int n, int which, const SplitGeo& S, const double* a0, const double* a1, const double* a2,
-                    double s0, double s1, double* o0, double* o1, hipStream_t s) {
+                    double s0, double s1, double* o0, double* o1, hipStream_t s, const double* a3 = nullptr) {
     switch (n) {
-        case 3: return launch_n<3>(which, S, a0, a1, a2, s0, s1, o0, o1, s);
-        case 4: return launch_n<4>(which, S, a0, a1, a2, s0, s1, o0, o1, s);
-        case 5: return launch_n<5>(which, S, a0, a1, a2, s0, s1, o0, o1, s);
-        case 6: return launch_n<6>(which, S, a0, a1, a2, s0, s1, o0, o1, s);
+        case 3: return launch_n<3>(which, S, a0, a1, a2, a3, s0, s1, o0, o1, s);
+        case 4: return launch_n<4>(which, S, a0, a1, a2, a3, s0, s1, o0, o1, s);
+        case 5: return launch_n<5>(which, S, a0, a1, a2, a3, s0, s1, o0, o1, s);
+        case 6: return launch_n<6>(which, S, a0, a1, a2, a3, s0, s1, o0, o1, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 }  // namespace
 
-hipError_t launch_split_convective(int n, const SplitGeo& S, const double* u, const double* b, double dt,
-                                   double* uhat, hipStream_t s) {
-    return dispatch(n, 0, S, u, b, nullptr, dt, 0.0, uhat, nullptr, s);
+hipError_t launch_split_convective(int n, const SplitGeo& S, const double* u, const double* u_prev, const double* b,
+                                   double dt, double* uhat, hipStream_t s) {
+    return dispatch(n, 0, S, u, u_prev, b, dt, 0.0, uhat, nullptr, s);
 }
 
-hipError_t launch_split_ppe_rhs(int n, const SplitGeo& S, const double* uhat, const double* u_old, const double* b,
-                                double dt, double* f, hipStream_t s) {
-    return dispatch(n, 1, S, uhat, u_old, b, dt, 0.0, f, nullptr, s);
+hipError_t launch_split_ppe_rhs(int n, const SplitGeo& S, const double* uhat, const double* u_old,
+                                const double* u_prev, const double* b, double dt, double* f, hipStream_t s) {
+    return dispatch(n, 1, S, uhat, u_old, u_prev, dt, 0.0, f, nullptr, s, b);
+}
+
+hipError_t launch_lincomb(long long n, double a, const double* x, double c, const double* z, double* y, hipStream_t s) {
+    const long long blocks = std::min<long long>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_lincomb, dim3((unsigned)(blocks > 0 ? blocks : 1)), dim3(256), 0, s, n, a, x, c, z, y);
+    return hipGetLastError();
 }
 
 hipError_t launch_split_projection(int n, const SplitGeo& S, const double* uhat, const double* p, double dt,

@@ -264,3 +264,56 @@ def test_uniform_flow_through_the_box():
     eu, ep = float(np.abs(host(un) - u).max()), float(np.abs(host(p)).max())
     say(f"[split uniform flow] |u - c| {eu:.2e}, |p| {ep:.2e}")
     assert eu <= 1e-9 and ep <= 1e-9
+
+
+@pytest.mark.parametrize("label,shape,deg,perturb", CASES, ids=[c[0] for c in CASES])
+def test_bdf2_operators_match_oracle(label, shape, deg, perturb):
+    """BDF2 (u^{n-1} given): the convective step with two old velocities,
+    the pressure right-hand side with h_p's extrapolated convective term,
+    nu curl(omega) and grad^S u . grad nu, and the projection with
+    gamma_0 = 3/2, with wall data, equal the oracle's."""
+    dt = 1e-2
+    nx, ny, nz = shape
+    V = W.box_vertices(nx, ny, nz, perturb) if perturb else None
+    law = W.carreau_law(3)
+    st = SplitStep(nx, ny, nz, deg, dt, law, V, order=2).bind()
+    pb = Problem(Mesh(nx, ny, nz, V), deg, "viscous", 1.5 / dt, 1.0, law)
+    pp = SP.pressure_problem(pb.mesh, deg)
+    u1, u0 = W.uniform_vector(1, pb.ndof), W.uniform_vector(11, pb.ndof)
+    b, uh = W.uniform_vector(2, pb.ndof), W.uniform_vector(3, pb.ndof)
+    p = W.uniform_vector(4, pp.ndof)
+    gw = W.uniform_vector(8, SP.wall_count(pb.mesh) * pb.n ** 2 * 3)
+    e1 = rel(host(st.convective_step(dev(u1), dev(b), g_wall=dev(gw), u_prev=dev(u0))),
+             SP.convective_step(pb, u1, b, dt, gw, u0))
+    e2 = rel(host(st.pressure_rhs(dev(uh), dev(u1), dev(b), g_wall=dev(gw), u_prev=dev(u0))),
+             SP.ppe_rhs(pb, pp, uh, u1, b, dt, gw, u0, law))
+    uhh, rhs = st.projection(dev(uh), dev(p))
+    ruhh, rrhs = SP.projection(pb, pp, uh, p, dt, 1.5)
+    e3, e4 = rel(host(uhh), ruhh), rel(host(rhs), rrhs)
+    say(f"[split bdf2] {label}: convective {e1:.2e}, pressure rhs {e2:.2e}, projection {e3:.2e}, rhs {e4:.2e}")
+    assert max(e1, e2, e3, e4) <= 1e-12
+
+
+def test_bdf2_lid_step_matches_oracle():
+    dt = 1e-2
+    V = W.box_vertices(3, 2, 2, 0.1)
+    law = W.carreau_law(3)
+    st = SplitStep(3, 2, 2, 3, dt, law, V, order=2).bind()
+    pb = Problem(Mesh(3, 2, 2, V), 3, "viscous", 1.5 / dt, 1.0, law)
+    rows = SP.wall_rows(pb.mesh)
+    gw = np.zeros((SP.wall_count(pb.mesh), pb.n ** 2, 3))
+    gw[rows[(2, 1)]] = np.array([1.0, 0.0, 0.0])
+    gw = gw.reshape(-1)
+    x = W.node_positions(3, 2, 2, 3, V)
+    base = 6.4 * np.prod(x * (1 - x), -1)[..., None]
+    u0 = np.transpose(base * np.stack([np.sin(np.pi * x[..., 1]), np.cos(np.pi * x[..., 2]), x[..., 0]], -1),
+                      (0, 2, 1)).reshape(-1)
+    u1 = np.transpose(base * np.stack([np.sin(np.pi * x[..., 2]), x[..., 1], np.cos(np.pi * x[..., 0])], -1),
+                      (0, 2, 1)).reshape(-1)
+    b = W.uniform_vector(7, pb.ndof)
+    ref = SP.split_step(pb, law, u1, b, dt, g_wall=gw, u_prev=u0)
+    un, p, info = st.step(dev(u1), dev(b), opts=TIGHT, g_wall=dev(gw), u_prev=dev(u0))
+    eu, ep = rel(host(un), ref["u_new"]), rel(host(p), ref["p"])
+    say(f"[split bdf2 lid] {info}; u_new rel. diff {eu:.2e}, p {ep:.2e}")
+    assert all(v["status"] == "SIPG_OK" for v in info.values())
+    assert eu <= 1e-8 and ep <= 1e-8

@@ -155,20 +155,25 @@ def test_split_step_entry_points_on_cpu():
     law = W.carreau_law(3)
     s = SplitStep(3, 2, 2, 3, 0.01, law, W.box_vertices(3, 2, 2, 0.1))
     assert s.ndof_u == 12 * 3 * 64 and s.ndof_p == 12 * 27
-    assert s.work_bytes() >= 4 * 8 * s.ndof_u + 8 * s.ndof_p
+    assert s.work_bytes() >= 5 * 8 * s.ndof_u + 8 * s.ndof_p
+    s2 = SplitStep(3, 2, 2, 3, 0.01, law, None, order=2)
+    with pytest.raises(ValueError):
+        s2._prev(None)                                            # BDF2 needs u_prev
+    with pytest.raises(ValueError):
+        SplitStep(3, 2, 2, 3, 0.01, law, None, order=3)
     d = C.c_void_p(256)
-    assert F.lib.sipg_convective_step(s.vel._h, d, None, None, 0.01, C.c_void_p(512), None) == -7   # not bound
-    assert F.lib.sipg_pressure_rhs(s.vel._h, s.pres._h, d, d, None, None, 0.01, d, None) == -7
+    assert F.lib.sipg_convective_step(s.vel._h, d, None, None, None, 0.01, C.c_void_p(512), None) == -7  # unbound
+    assert F.lib.sipg_pressure_rhs(s.vel._h, s.pres._h, d, d, None, None, None, 0.01, d, None) == -7
     assert F.lib.sipg_wall_load(s.vel._h, d, C.c_void_p(512), None) == -7
     assert F.lib.sipg_update_penalty_factors(s.pen._h, d, 0.01, 1.0, None) == -7
-    rc = F.lib.sipg_split_step(s.vel._h, s.pres._h, s.pen._h, d, None, None, 0.01, d, d, d, None, None, None)
+    rc = F.lib.sipg_split_step(s.vel._h, s.pres._h, s.pen._h, d, None, None, None, 0.01, d, d, d, None, None, None)
     assert rc == -7
     # wrong plans: Neumann sides on the velocity, pressure of the wrong degree
     from paper_2506_14424_amd import Operator
     bad = Operator(3, 2, 2, 3, "viscous", 100.0, 1.0, law, None, ("D", "N", "D", "D", "D", "D"))
-    assert F.lib.sipg_convective_step(bad._h, d, None, None, 0.01, C.c_void_p(512), None) == -1
+    assert F.lib.sipg_convective_step(bad._h, d, None, None, None, 0.01, C.c_void_p(512), None) == -1
     assert "no-slip" in F.lib.sipg_last_error().decode()
-    assert F.lib.sipg_convective_step(None, d, None, None, 0.01, d, None) == -1
+    assert F.lib.sipg_convective_step(None, d, None, None, None, 0.01, d, None) == -1
     assert s.wall_count() == 2 * (2 * 2 + 3 * 2 + 3 * 2)
     with pytest.raises(ValueError):
         SplitStep(3, 2, 2, 3, 0.01, W.sine_law(1.0, 0.5))
