@@ -260,7 +260,8 @@ def picard_step(tol=1e-8):
 
 
 def split_step(reps=5, tol=1e-8):
-    """c8: one dual-splitting time step (BDF1, no-slip walls): the whole step
+    """c8: one dual-splitting time step (BDF1, lid-driven box) and a BDF2
+    step from its result: the whole step
     (convective step, pressure right-hand side, pressure Poisson solve,
     projection, viscosity update, viscous solve, penalty factors, penalty
     solve) and each part alone; the three non-solve operators with their
@@ -294,6 +295,16 @@ def split_step(reps=5, tol=1e-8):
     torch.cuda.synchronize()
     step_reuse_s = (time.perf_counter() - t0) / reps
     reuse_diff = float((un_r - un).norm() / un.norm())
+    # BDF2 steps (u^{n-1} = the BDF1 step's input, u^n = its result): plans with gamma_0 = 3/2
+    st2 = SplitStep(m, m, m, deg, dt, cfg["law"], V, order=2).set_multigrid().bind()
+    un2, p2, info2 = st2.step(un, b, opts=opts, g_wall=gw, u_prev=u)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        un2, p2, info2 = st2.step(un, b, u_new=un2, p=p2, opts=opts, g_wall=gw, u_prev=u)
+    torch.cuda.synchronize()
+    step2_s = (time.perf_counter() - t0) / reps
+    del st2
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
 
     def timed(fn, n=20):
@@ -346,6 +357,8 @@ def split_step(reps=5, tol=1e-8):
                         f"Chebyshev-Jacobi for the penalty step)",
             "step_seconds": step_s,
             "step_seconds_reuse_eigs": step_reuse_s,
+            "bdf2_step_seconds": step2_s,
+            "bdf2_iterations": {k: v["iterations"] for k, v in info2.items()},
             "reuse_eigs_note": "viscous and penalty solves keep the eigenvalue estimates of an earlier "
                                "step (the preconditioner refreshed less often than the operator); every "
                                "timed step starts from the same u^n, so here the kept estimates are those "

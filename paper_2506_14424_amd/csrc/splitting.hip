@@ -312,7 +312,7 @@ __device__ __forceinline__ void phys_grad3(const double gref[3][3], const double
         for (int i = 0; i < 3; ++i) G[c][i] = gref[c][0] * Ji[0][i] + gref[c][1] * Ji[1][i] + gref[c][2] * Ji[2][i];
 }
 
-template <int N, int FC>
+template <int N, int ORDER, int FC>
 __device__ __forceinline__ double ppe_face(const SplitGeo& S, const CellMap& m, int e, const int ijk[3], int ab,
                                            const double* __restrict__ uhat, const double* __restrict__ u_old,
                                            const double* __restrict__ u1, const double* __restrict__ b, double dt,
@@ -341,84 +341,134 @@ __device__ __forceinline__ double ppe_face(const SplitGeo& S, const CellMap& m, 
         }
         val = -S.gamma0 / dt * an;
     } else {
-        // wall, from the interior traces:
-        // g_uhat = (dt/gamma_0)(b - sum_i beta_i (grad u^{n-i}) u^{n-i}) + sum_i (alpha_i/gamma_0) g_u,
-        // h_p = n.b - n.d_t g_u (= 0: data constant in time) - beta_bar n.((grad u^n) u^n)
-        //       - nu n.curl(omega) + 2 n.(grad^S u^n . grad nu)      (BDF2: m_p = 1, u^dd = u^n)
-        const double* be = b ? b + (long long)e * 3 * N3 : nullptr;
-        double bt[3] = {0.0, 0.0, 0.0};
-        if (be) {
-#pragma unroll
+        if constexpr (ORDER == 1) {
+            // BDF1 wall: g_uhat = (dt/gamma_0)(b - beta_0 (grad u^n) u^n) + (alpha_0/gamma_0) g_u,
+            // h_p = n.b (- n.d_t g_u = 0: data constant in time), from the interior traces
+            const double* uo = u_old + (long long)e * 3 * N3;
+            const double* be = b ? b + (long long)e * 3 * N3 : nullptr;
+            double ut[3], bt[3], gref[3][3];
+    #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                double v = 0.0;
-#pragma unroll
-                for (int k = 0; k < N; ++k) v += S.tab.S[s][k] * be[c * N3 + line + k * str[d]];
-                bt[c] = v;
-            }
-        }
-        double conv_sum[3] = {0.0, 0.0, 0.0}, conv0[3] = {0.0, 0.0, 0.0}, G0[3][3];
-        for (int i = 0; i < S.order; ++i) {
-            const double* uo = (i == 0 ? u_old : u1) + (long long)e * 3 * N3;
-            double ut[3], gref[3][3], G[3][3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) face_trace_grad<N, d, s>(S, uo + c * N3, a, bb, ut[c], gref[c]);
-            phys_grad3(gref, fp.Ji, G);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const double cv = G[c][0] * ut[0] + G[c][1] * ut[1] + G[c][2] * ut[2];
-                conv_sum[c] += S.beta[i] * cv;
-                if (i == 0) conv0[c] = cv;
-            }
-            if (i == 0) {
-#pragma unroll
-                for (int c = 0; c < 3; ++c)
-#pragma unroll
-                    for (int k = 0; k < 3; ++k) G0[c][k] = G[c][k];
-            }
-        }
-        double gn = 0.0, hp = 0.0;
-        const double asum = S.alpha[0] + (S.order > 1 ? S.alpha[1] : 0.0);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const double gu = S.gw ? S.gw[((long long)wall_row(S, ijk, d, s) * N2 + ab) * 3 + c] : 0.0;
-            const double guhat = dt / S.gamma0 * (bt[c] - conv_sum[c]) + asum / S.gamma0 * gu;
-            gn += guhat * fp.n[c];
-            hp += fp.n[c] * (bt[c] - S.beta_bar * conv0[c]);
-        }
-        if (S.order > 1) {
-            double ee = 0.0, Sy[3][3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-#pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    Sy[c][k] = 0.5 * (G0[c][k] + G0[k][c]);
-                    ee += Sy[c][k] * Sy[c][k];
+                const double* uc = uo + c * N3;
+                double tr = 0.0, dn = 0.0, btc = 0.0, d1 = 0.0, d2 = 0.0;
+    #pragma unroll
+                for (int k = 0; k < N; ++k) {
+                    tr += S.tab.S[s][k] * uc[line + k * str[d]];
+                    dn += S.tab.G[s][k] * uc[line + k * str[d]];
+                    if (be) btc += S.tab.S[s][k] * be[c * N3 + line + k * str[d]];
                 }
-            const double nu = eta_split(S, sqrt(2.0 * ee));
-            double ot[3], gro[3][3], Go[3][3], nt, gn_ref[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) face_trace_grad<N, d, s>(S, OM + c * N3, a, bb, ot[c], gro[c]);
-            phys_grad3(gro, fp.Ji, Go);
-            const double curl[3] = {Go[2][1] - Go[1][2], Go[0][2] - Go[2][0], Go[1][0] - Go[0][1]};
-            face_trace_grad<N, d, s>(S, NU, a, bb, nt, gn_ref);
-            double gnu[3];
-#pragma unroll
-            for (int k = 0; k < 3; ++k)
-                gnu[k] = gn_ref[0] * fp.Ji[0][k] + gn_ref[1] * fp.Ji[1][k] + gn_ref[2] * fp.Ji[2][k];
-            double ncurl = 0.0, nsg = 0.0;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                ncurl += fp.n[c] * curl[c];
-                nsg += fp.n[c] * (Sy[c][0] * gnu[0] + Sy[c][1] * gnu[1] + Sy[c][2] * gnu[2]);
+                // tangential derivatives of the trace
+    #pragma unroll 1
+                for (int k2 = 0; k2 < N; ++k2) {
+                    double t1v = 0.0, t2v = 0.0;
+    #pragma unroll
+                    for (int k = 0; k < N; ++k) {
+                        t1v += S.tab.S[s][k] * uc[k2 * str[fp.t1] + bb * str[fp.t2] + k * str[d]];
+                        t2v += S.tab.S[s][k] * uc[a * str[fp.t1] + k2 * str[fp.t2] + k * str[d]];
+                    }
+                    d1 += S.tab.D[a][k2] * t1v;
+                    d2 += S.tab.D[bb][k2] * t2v;
+                }
+                ut[c] = tr;
+                bt[c] = btc;
+                gref[c][d] = dn;
+                gref[c][fp.t1] = d1;
+                gref[c][fp.t2] = d2;
             }
-            hp += -nu * ncurl + 2.0 * nsg;
+            double gn = 0.0, hp = 0.0;
+    #pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                double conv = 0.0;
+    #pragma unroll
+                for (int i = 0; i < 3; ++i)
+                    conv += (gref[c][0] * fp.Ji[0][i] + gref[c][1] * fp.Ji[1][i] + gref[c][2] * fp.Ji[2][i]) * ut[i];
+                const double gu = S.gw ? S.gw[((long long)wall_row(S, ijk, d, s) * N2 + ab) * 3 + c] : 0.0;
+                const double guhat = dt / S.gamma0 * (bt[c] - S.beta[0] * conv) + S.alpha[0] / S.gamma0 * gu;
+                gn += guhat * fp.n[c];
+                hp += fp.n[c] * bt[c];
+            }
+            val = -S.gamma0 / dt * gn + hp;
+        } else {
+            // wall, from the interior traces:
+            // g_uhat = (dt/gamma_0)(b - sum_i beta_i (grad u^{n-i}) u^{n-i}) + sum_i (alpha_i/gamma_0) g_u,
+            // h_p = n.b - n.d_t g_u (= 0: data constant in time) - beta_bar n.((grad u^n) u^n)
+            //       - nu n.curl(omega) + 2 n.(grad^S u^n . grad nu)      (BDF2: m_p = 1, u^dd = u^n)
+            const double* be = b ? b + (long long)e * 3 * N3 : nullptr;
+            double bt[3] = {0.0, 0.0, 0.0};
+            if (be) {
+    #pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    double v = 0.0;
+    #pragma unroll
+                    for (int k = 0; k < N; ++k) v += S.tab.S[s][k] * be[c * N3 + line + k * str[d]];
+                    bt[c] = v;
+                }
+            }
+            double conv_sum[3] = {0.0, 0.0, 0.0}, conv0[3] = {0.0, 0.0, 0.0}, G0[3][3];
+    #pragma unroll
+            for (int i = 0; i < ORDER; ++i) {
+                const double* uo = (i == 0 ? u_old : u1) + (long long)e * 3 * N3;
+                double ut[3], gref[3][3], G[3][3];
+    #pragma unroll
+                for (int c = 0; c < 3; ++c) face_trace_grad<N, d, s>(S, uo + c * N3, a, bb, ut[c], gref[c]);
+                phys_grad3(gref, fp.Ji, G);
+    #pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const double cv = G[c][0] * ut[0] + G[c][1] * ut[1] + G[c][2] * ut[2];
+                    conv_sum[c] += S.beta[i] * cv;
+                    if (i == 0) conv0[c] = cv;
+                }
+                if (ORDER > 1 && i == 0) {
+    #pragma unroll
+                    for (int c = 0; c < 3; ++c)
+    #pragma unroll
+                        for (int k = 0; k < 3; ++k) G0[c][k] = G[c][k];
+                }
+            }
+            double gn = 0.0, hp = 0.0;
+            const double asum = S.alpha[0] + (ORDER > 1 ? S.alpha[1] : 0.0);
+    #pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const double gu = S.gw ? S.gw[((long long)wall_row(S, ijk, d, s) * N2 + ab) * 3 + c] : 0.0;
+                const double guhat = dt / S.gamma0 * (bt[c] - conv_sum[c]) + asum / S.gamma0 * gu;
+                gn += guhat * fp.n[c];
+                hp += fp.n[c] * (bt[c] - S.beta_bar * conv0[c]);
+            }
+            if constexpr (ORDER > 1) {
+                double ee = 0.0, Sy[3][3];
+    #pragma unroll
+                for (int c = 0; c < 3; ++c)
+    #pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        Sy[c][k] = 0.5 * (G0[c][k] + G0[k][c]);
+                        ee += Sy[c][k] * Sy[c][k];
+                    }
+                const double nu = eta_split(S, sqrt(2.0 * ee));
+                double ot[3], gro[3][3], Go[3][3], nt, gn_ref[3];
+    #pragma unroll
+                for (int c = 0; c < 3; ++c) face_trace_grad<N, d, s>(S, OM + c * N3, a, bb, ot[c], gro[c]);
+                phys_grad3(gro, fp.Ji, Go);
+                const double curl[3] = {Go[2][1] - Go[1][2], Go[0][2] - Go[2][0], Go[1][0] - Go[0][1]};
+                face_trace_grad<N, d, s>(S, NU, a, bb, nt, gn_ref);
+                double gnu[3];
+    #pragma unroll
+                for (int k = 0; k < 3; ++k)
+                    gnu[k] = gn_ref[0] * fp.Ji[0][k] + gn_ref[1] * fp.Ji[1][k] + gn_ref[2] * fp.Ji[2][k];
+                double ncurl = 0.0, nsg = 0.0;
+    #pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    ncurl += fp.n[c] * curl[c];
+                    nsg += fp.n[c] * (Sy[c][0] * gnu[0] + Sy[c][1] * gnu[1] + Sy[c][2] * gnu[2]);
+                }
+                hp += -nu * ncurl + 2.0 * nsg;
+            }
+            val = -S.gamma0 / dt * gn + hp;
         }
-        val = -S.gamma0 / dt * gn + hp;
     }
     return fp.ds * val;
 }
 
-template <int N>
+template <int N, int ORDER>
 __global__ void __launch_bounds__(kFaceThreads<N>) k_split_ppe_rhs(SplitGeo S, const double* __restrict__ uhat,
                                                                   const double* __restrict__ u_old,
                                                                   const double* __restrict__ u1,
@@ -427,9 +477,10 @@ __global__ void __launch_bounds__(kFaceThreads<N>) k_split_ppe_rhs(SplitGeo S, c
     constexpr int N2 = N * N, N3 = N2 * N, NP = N - 1, NP3 = NP * NP * NP;
     __shared__ double GQ[3][N3];
     __shared__ double FF[6][N2];
-    __shared__ double UO[3 * N3];      // BDF2, wall cells: u^n, its vorticity and viscosity at the nodes
-    __shared__ double OM[3 * N3];
-    __shared__ double NU[N3];
+    // BDF2, wall cells: u^n, its vorticity and viscosity at the nodes
+    __shared__ double UO[ORDER > 1 ? 3 * N3 : 1];
+    __shared__ double OM[ORDER > 1 ? 3 * N3 : 1];
+    __shared__ double NU[ORDER > 1 ? N3 : 1];
     const int e = blockIdx.x, t = threadIdx.x;
     int ijk[3];
     cell_ijk(S, e, ijk);
@@ -439,7 +490,7 @@ __global__ void __launch_bounds__(kFaceThreads<N>) k_split_ppe_rhs(SplitGeo S, c
     const double* uh = uhat + (long long)e * 3 * N3;
     const bool wall = ijk[0] == 0 || ijk[0] == S.nx - 1 || ijk[1] == 0 || ijk[1] == S.ny - 1 || ijk[2] == 0 ||
                       ijk[2] == S.nz - 1;
-    if (S.order > 1 && wall) {         // uniform over the workgroup
+    if (ORDER > 1 && wall) {           // uniform over the workgroup
         const double* uo = u_old + (long long)e * 3 * N3;
         for (int k = t; k < 3 * N3; k += blockDim.x) UO[k] = uo[k];
         __syncthreads();
@@ -489,12 +540,12 @@ __global__ void __launch_bounds__(kFaceThreads<N>) k_split_ppe_rhs(SplitGeo S, c
         const int fc = t / N2, ab = t % N2;
         double v = 0.0;
         switch (fc) {
-            case 0: v = ppe_face<N, 0>(S, m, e, ijk, ab, uhat, u_old, u1, b, dt, OM, NU); break;
-            case 1: v = ppe_face<N, 1>(S, m, e, ijk, ab, uhat, u_old, u1, b, dt, OM, NU); break;
-            case 2: v = ppe_face<N, 2>(S, m, e, ijk, ab, uhat, u_old, u1, b, dt, OM, NU); break;
-            case 3: v = ppe_face<N, 3>(S, m, e, ijk, ab, uhat, u_old, u1, b, dt, OM, NU); break;
-            case 4: v = ppe_face<N, 4>(S, m, e, ijk, ab, uhat, u_old, u1, b, dt, OM, NU); break;
-            default: v = ppe_face<N, 5>(S, m, e, ijk, ab, uhat, u_old, u1, b, dt, OM, NU); break;
+            case 0: v = ppe_face<N, ORDER, 0>(S, m, e, ijk, ab, uhat, u_old, u1, b, dt, OM, NU); break;
+            case 1: v = ppe_face<N, ORDER, 1>(S, m, e, ijk, ab, uhat, u_old, u1, b, dt, OM, NU); break;
+            case 2: v = ppe_face<N, ORDER, 2>(S, m, e, ijk, ab, uhat, u_old, u1, b, dt, OM, NU); break;
+            case 3: v = ppe_face<N, ORDER, 3>(S, m, e, ijk, ab, uhat, u_old, u1, b, dt, OM, NU); break;
+            case 4: v = ppe_face<N, ORDER, 4>(S, m, e, ijk, ab, uhat, u_old, u1, b, dt, OM, NU); break;
+            default: v = ppe_face<N, ORDER, 5>(S, m, e, ijk, ab, uhat, u_old, u1, b, dt, OM, NU); break;
         }
         FF[fc][ab] = v;
     }
@@ -814,7 +865,12 @@ hipError_t launch_n(int which, const SplitGeo& S, const double* a0, const double
                   "a workgroup must cover the cell's nodes and face points");
     switch (which) {
         case 0: hipLaunchKernelGGL(k_split_convective<N>, grid, fb, 0, s, S, a0, a1, a2, s0, o0); break;
-        case 1: hipLaunchKernelGGL(k_split_ppe_rhs<N>, grid, fb, 0, s, S, a0, a1, a2, a3, s0, o0); break;
+        case 1:
+            if (S.order > 1)
+                hipLaunchKernelGGL((k_split_ppe_rhs<N, 2>), grid, fb, 0, s, S, a0, a1, a2, a3, s0, o0);
+            else
+                hipLaunchKernelGGL((k_split_ppe_rhs<N, 1>), grid, fb, 0, s, S, a0, a1, a2, a3, s0, o0);
+            break;
         case 2: hipLaunchKernelGGL(k_split_projection<N>, grid, fb, 0, s, S, a0, a1, s0, o0, o1); break;
         case 3: hipLaunchKernelGGL(k_split_mass<N>, grid, cb, 0, s, S, a0, s0, o0); break;
         case 4: hipLaunchKernelGGL(k_pen_factors<N>, grid, cb, 0, s, S, a0, s0, s1, a1, o0, o1); break;
