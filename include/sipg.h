@@ -380,8 +380,9 @@ sipg_status sipg_picard_solve(sipg_plan* plan, const double* b, double* x, void*
  *         alpha = gamma_0/dt (1/dt for BDF1, 3/(2 dt) for BDF2), law
  *         SIPG_LAW_CARREAU (its eta parameters);
  *   pres  SIPG_POISSON, degree k - 1, all sides Neumann, alpha = 0;
- *   pen   SIPG_PENALTY, degree k, all sides Dirichlet, alpha = 1, no
- *         multigrid hierarchy (its factors are recomputed on the device).
+ *   pen   SIPG_PENALTY, degree k, all sides Dirichlet, alpha = 1 (its
+ *         factors, and its multigrid levels' if any, are recomputed on the
+ *         device).
  * Velocities, forces: device FP64 in vel's layout (3 components, k+1
  * Gauss points per direction); pressures: device FP64 in pres's layout
  * (k Gauss points per direction).  All integrals of the mixed forms use the
@@ -418,9 +419,11 @@ sipg_status sipg_projection(sipg_plan* vel, sipg_plan* pres, const double* uhat,
  * tau_div = zeta |u_e| h_e dt/(k+1), tau_cont = zeta |u_e| dt (|u_e| the
  * volume mean of |u| over the cell, h_e = |cell|^(1/3)), then its face
  * factors and diagonal, and marks its cached eigenvalue estimate stale (as
- * sipg_update_viscosity does).  Needs a bound plan without a multigrid
- * hierarchy and no solve in progress.  A later sipg_plan_bind restores the
- * factors given at creation. */
+ * sipg_update_viscosity does); with a multigrid hierarchy every level's
+ * factors follow (degree steps share them, mesh steps take the mean of a
+ * coarse cell's 8 children), with their face factors and diagonals.  Needs
+ * a bound plan and no solve in progress.  A later sipg_plan_bind restores
+ * the factors given at creation. */
 sipg_status sipg_update_penalty_factors(sipg_plan* pen, const double* u, double dt, double zeta, void* stream);
 
 /* y += the load of the wall data g_wall for a viscous plan (mirror

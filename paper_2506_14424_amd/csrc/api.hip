@@ -1454,7 +1454,6 @@ sipg_status sipg_update_penalty_factors(sipg_plan* P, const double* u, double dt
     if (rc != SIPG_OK) return rc;
     if (!P->pen) return fail(SIPG_ERR_INVALID, "not a penalty-step plan");
     if (!u) return fail(SIPG_ERR_INVALID, "null argument");
-    if (P->mg_on) return fail(SIPG_ERR_UNSUPPORTED, "the factors of multigrid levels are fixed at creation");
     if (busy(P)) return fail(SIPG_ERR_STATE, "a solve is in progress on this plan");
     if (!(dt > 0.0) || !std::isfinite(dt) || !(zeta >= 0.0) || !std::isfinite(zeta))
         return fail(SIPG_ERR_INVALID, "dt must be finite and > 0, zeta finite and >= 0");
@@ -1467,6 +1466,28 @@ sipg_status sipg_update_penalty_factors(sipg_plan* P, const double* u, double dt
                          P->mu_cell32, P->mu_face64, P->mu_face32, (int)P->nface, P->tau_div_d, P->tau_cont_d, s));
     HIP_TRY(launch_diagonal(P->n, P->C, P->curved, P->opdata<double>(), P->diag64, P->dinv64, P->dinv32, s));
     P->lz_stale = true;
+    // multigrid levels: a degree step keeps the finer level's factors, a mesh
+    // step averages each coarse cell's 8 children (as the hierarchy is built)
+    const double* td = P->tau_div_d;
+    const double* tc = P->tau_cont_d;
+    int fx = P->nx, fy = P->ny, fz = P->nz;
+    for (sipg_plan* L : P->mg) {
+        if (!L->bound) break;                  // levels are bound only with solver workspace
+        if (L->mesh_step) {
+            HIP_TRY(launch_pen_coarsen(fx, fy, fz, td, tc, L->tau_div_d, L->tau_cont_d, s));
+        } else {
+            HIP_TRY(hipMemcpyAsync(L->tau_div_d, td, L->ncell * 8, hipMemcpyDeviceToDevice, s));
+            HIP_TRY(hipMemcpyAsync(L->tau_cont_d, tc, L->ncell * 8, hipMemcpyDeviceToDevice, s));
+        }
+        HIP_TRY(launch_setup(L->n, L->C, L->curved, L->opdata<double>(), L->law, L->penalty, L->hcell, L->tfac64,
+                             L->tfac32, L->mu_cell64, L->mu_cell32, L->mu_face64, L->mu_face32, (int)L->nface,
+                             L->tau_div_d, L->tau_cont_d, s));
+        HIP_TRY(launch_diagonal(L->n, L->C, L->curved, L->opdata<double>(), L->diag64, L->dinv64, L->dinv32, s));
+        L->lz_stale = true;
+        td = L->tau_div_d;
+        tc = L->tau_cont_d;
+        fx = L->nx; fy = L->ny; fz = L->nz;
+    }
     return SIPG_OK;
 }
 

@@ -169,6 +169,9 @@ hipError_t launch_split_convective(int n, const SplitGeo& S, const double* u, co
                                    double dt, double* uhat, hipStream_t s);
 hipError_t launch_split_ppe_rhs(int n, const SplitGeo& S, const double* uhat, const double* u_old,
                                 const double* u_prev, const double* b, double dt, double* f, hipStream_t s);
+// penalty factors of a mesh-step level: the mean of each coarse cell's 8 children
+hipError_t launch_pen_coarsen(int fx, int fy, int fz, const double* td, const double* tc, double* ctd, double* ctc,
+                              hipStream_t s);
 // y = a x + c z (n values)
 hipError_t launch_lincomb(long long n, double a, const double* x, double c, const double* z, double* y, hipStream_t s);
 hipError_t launch_split_projection(int n, const SplitGeo& S, const double* uhat, const double* p, double dt,

@@ -586,6 +586,25 @@ __global__ void __launch_bounds__(kFaceThreads<N>) k_split_ppe_rhs(SplitGeo S, c
     f[(long long)e * NP3 + t] = acc;
 }
 
+// Penalty-step factors of a coarse mesh-step level: the mean of each coarse
+// cell's 8 children (fine mesh fx * fy * fz, children in the order of their
+// (z, y, x) offsets), as the multigrid hierarchy is built.
+__global__ void k_pen_coarsen(int fx, int fy, int fz, const double* __restrict__ td, const double* __restrict__ tc,
+                              double* __restrict__ ctd, double* __restrict__ ctc) {
+    const int cx = fx / 2, cy = fy / 2, cz = fz / 2;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= cx * cy * cz) return;
+    const int i = e % cx, j = (e / cx) % cy, k = e / (cx * cy);
+    double a = 0.0, b = 0.0;
+    for (int c = 0; c < 8; ++c) {
+        const long long f = ((long long)(2 * k + (c >> 2)) * fy + 2 * j + ((c >> 1) & 1)) * fx + 2 * i + (c & 1);
+        a += td[f];
+        b += tc[f];
+    }
+    ctd[e] = a / 8.0;
+    ctc[e] = b / 8.0;
+}
+
 __global__ void k_lincomb(long long n, double a, const double* __restrict__ x, double c,
                           const double* __restrict__ z, double* __restrict__ y) {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
@@ -901,6 +920,13 @@ hipError_t launch_split_convective(int n, const SplitGeo& S, const double* u, co
 hipError_t launch_split_ppe_rhs(int n, const SplitGeo& S, const double* uhat, const double* u_old,
                                 const double* u_prev, const double* b, double dt, double* f, hipStream_t s) {
     return dispatch(n, 1, S, uhat, u_old, u_prev, dt, 0.0, f, nullptr, s, b);
+}
+
+hipError_t launch_pen_coarsen(int fx, int fy, int fz, const double* td, const double* tc, double* ctd, double* ctc,
+                              hipStream_t s) {
+    const int nc = (fx / 2) * (fy / 2) * (fz / 2);
+    hipLaunchKernelGGL(k_pen_coarsen, dim3((nc + 255) / 256), dim3(256), 0, s, fx, fy, fz, td, tc, ctd, ctc);
+    return hipGetLastError();
 }
 
 hipError_t launch_lincomb(long long n, double a, const double* x, double c, const double* z, double* y, hipStream_t s) {

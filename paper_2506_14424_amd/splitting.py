@@ -54,11 +54,14 @@ class SplitStep:
         self.ndof_u, self.ndof_p = self.vel.ndof, self.pres.ndof
         self._work = None
 
-    def set_multigrid(self, **kw) -> "SplitStep":
-        """hp-multigrid for the viscous and pressure solves (the penalty step
-        keeps the one-level preconditioner)."""
+    def set_multigrid(self, penalty: bool = False, **kw) -> "SplitStep":
+        """hp-multigrid for the viscous and pressure solves and, with
+        penalty=True, for the penalty step (its levels' factors follow every
+        update)."""
         self.vel.set_multigrid(**kw)
         self.pres.set_multigrid(**kw)
+        if penalty:
+            self.pen.set_multigrid(**kw)
         return self
 
     def bind(self, stream=None) -> "SplitStep":

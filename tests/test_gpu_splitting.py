@@ -317,3 +317,36 @@ def test_bdf2_lid_step_matches_oracle():
     say(f"[split bdf2 lid] {info}; u_new rel. diff {eu:.2e}, p {ep:.2e}")
     assert all(v["status"] == "SIPG_OK" for v in info.values())
     assert eu <= 1e-8 and ep <= 1e-8
+
+
+def test_penalty_multigrid_levels_follow_the_factor_update():
+    """With a hierarchy on the penalty plan, the device update of the
+    factors reaches every level (degree steps share, mesh steps average 8
+    children): one V-cycle equals the oracle's over levels built from the
+    oracle's factors, and the multigrid-preconditioned penalty solve
+    converges."""
+    from oracle import multigrid as MG
+    from oracle.forms import apply as oracle_apply
+    dt = 1e-2
+    V = W.box_vertices(4, 4, 4, 0.1)
+    law = W.carreau_law(3)
+    st = SplitStep(4, 4, 4, 3, dt, law, V).set_multigrid(penalty=True, coarse_degree=12, min_cells=1).bind()
+    pb = Problem(Mesh(4, 4, 4, V), 3, "viscous", 1.0 / dt, 1.0, law)
+    u = W.uniform_vector(1, pb.ndof)
+    st.update_penalty_factors(dev(u), zeta=1.5)
+    td, tc = SP.penalty_factors(pb, u, dt, 1.5)
+    pen = Problem(pb.mesh, 3, "penalty", 1.0, 1.0, tau_div=td, tau_cont=tc)
+    H = MG.Hierarchy(pen, smooth_degree=3, coarse_degree=12, min_cells=1)
+    assert st.pen.multigrid_levels() == [(p.degree, p.mesh.nx, p.mesh.ny, p.mesh.nz) for p in H.levels]
+    r = W.uniform_vector(11, pb.ndof)
+    z = host(st.pen.precondition(dev(r), opts=SolveOptions(precond_precision="f64", cheb_degree=3,
+                                                          precond="multigrid")))
+    ref = H.vcycle(r)
+    err = float(np.linalg.norm(z - ref) / np.linalg.norm(ref))
+    b = W.uniform_vector(5, pb.ndof)
+    x, info = st.pen.solve(dev(b), opts=SolveOptions(rel_tol=1e-10, precond="multigrid", cheb_degree=3))
+    res = float(np.linalg.norm(b - oracle_apply(pen, host(x))) / np.linalg.norm(b))
+    say(f"[split penalty mg] levels {st.pen.multigrid_levels()}: V-cycle rel. diff {err:.2e}; solve {info}, "
+        f"oracle residual {res:.2e}")
+    assert err <= 1e-8
+    assert info["status"] == "SIPG_OK" and res <= 1.0001e-10
