@@ -438,6 +438,9 @@ typedef struct {
     sipg_solve_opts viscous;   /* viscous step */
     sipg_solve_opts penalty;   /* penalty step */
     double zeta;               /* penalty factor scale (1) */
+    int32_t warm_start;        /* nonzero: the viscous solve starts from uhh and the penalty solve from
+                                  u_visc (a correction solve for b - A x0 to the tolerance relative to
+                                  |b|); zero (default): every solve starts from zero */
 } sipg_split_opts;
 
 typedef struct {
@@ -447,7 +450,7 @@ typedef struct {
 void sipg_split_opts_default(sipg_split_opts* opts);
 
 /* Device bytes of the `work` buffer of sipg_split_step: five velocity
- * vectors and one pressure vector, each 256-byte aligned. */
+ * vectors, one pressure vector and reduction partials, each 256-byte aligned. */
 size_t sipg_split_work_bytes(const sipg_plan* vel, const sipg_plan* pres);
 
 /* One BDF1 step (u_prev NULL) or BDF2 step (u_prev = u^{n-1}; vel's alpha
@@ -459,7 +462,7 @@ size_t sipg_split_work_bytes(const sipg_plan* vel, const sipg_plan* pres);
  * vel (sipg_update_viscosity), the viscous solve, the penalty factors from
  * u^# and the penalty solve with right-hand side M u_visc into u_new; with
  * g_wall, the viscous and penalty right-hand sides take sipg_wall_load.
- * Every solve starts from zero.  u_old, u_prev, b (may be NULL): inputs;
+ * Every solve starts from zero unless opts->warm_start.  u_old, u_prev, b (may be NULL): inputs;
  * u_new, p: outputs (u_new must not alias u_old or u_prev); work: device buffer of
  * sipg_split_work_bytes, 256-byte aligned.  Blocks until done; returns the
  * first failing solve's status (info, which may be NULL, holds all three). */

@@ -82,7 +82,8 @@ class SolveInfo(C.Structure):
 
 
 class SplitOpts(C.Structure):
-    _fields_ = [("pressure", SolveOpts), ("viscous", SolveOpts), ("penalty", SolveOpts), ("zeta", C.c_double)]
+    _fields_ = [("pressure", SolveOpts), ("viscous", SolveOpts), ("penalty", SolveOpts), ("zeta", C.c_double),
+                ("warm_start", C.c_int32)]
 
 
 class SplitInfo(C.Structure):

@@ -1503,17 +1503,66 @@ sipg_status sipg_wall_load(sipg_plan* P, const double* g_wall, double* y, void* 
     return SIPG_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Solve A x = b starting from x0: R = b - A x0 (operator kernel, residual
+// mode), then A d = R to the relative tolerance that makes |b - A x| <=
+// rel_tol |b|, and x = x0 + d (x must not alias x0; R: a scratch vector;
+// sums: 3 kPicardBlocks + 8 doubles).  info->rel_residual is relative to |b|.
+sipg_status warm_solve(sipg_plan* P, const double* b, const double* x0, double* x, double* R, double* sums,
+                       const sipg_solve_opts& o, sipg_solve_info* info, hipStream_t s) {
+    const long long n = P->ndof;
+    double* partials = sums;
+    double* out = sums + 3 * kPicardBlocks;
+    ApplyIO<double> io;
+    std::memset(&io, 0, sizeof(io));
+    io.x = x0; io.y = R; io.parts = SIPG_PART_ALL; io.r = b;
+    HIP_TRY(launch_apply<double>(P->n, P->C, P->curved, P->opdata<double>(), io, MODE_RESID, s));
+    double h[2];
+    HIP_TRY(launch_picard_sums(b, nullptr, n, partials, out, s));
+    HIP_TRY(hipMemcpyAsync(&h[0], out, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(launch_picard_sums(R, nullptr, n, partials, out, s));
+    HIP_TRY(hipMemcpyAsync(&h[1], out, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const double bn = std::sqrt(h[0]), rn = std::sqrt(h[1]);
+    sipg_solve_opts od = o;
+    if (rn > 0.0) od.rel_tol = std::min(1.0, o.rel_tol * bn / rn);
+    sipg_solve_info inf;
+    std::memset(&inf, 0, sizeof(inf));
+    sipg_status rc = SIPG_OK;
+    if (!(rn > o.rel_tol * bn)) {             // x0 already solves to the tolerance
+        HIP_TRY(hipMemcpyAsync(x, x0, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        inf.status = SIPG_OK;
+        inf.rel_residual = bn > 0.0 ? rn / bn : 0.0;
+    } else {
+        rc = sipg_solve(P, R, x, &od, &inf, s);
+        HIP_TRY(launch_axpy(x, x0, 1.0, n, s));
+        inf.rel_residual = bn > 0.0 ? inf.rel_residual * rn / bn : 0.0;
+    }
+    if (info) *info = inf;
+    return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
 void sipg_split_opts_default(sipg_split_opts* o) {
     if (!o) return;
     sipg_solve_opts_default(&o->pressure);
     sipg_solve_opts_default(&o->viscous);
     sipg_solve_opts_default(&o->penalty);
     o->zeta = 1.0;
+    o->warm_start = 0;
 }
 
 size_t sipg_split_work_bytes(const sipg_plan* V, const sipg_plan* Pp) {
     if (!valid_plan(V) || !valid_plan(Pp)) return 0;
-    return 5 * split_vec_bytes(V->ndof) + split_vec_bytes(Pp->ndof);
+    return 5 * split_vec_bytes(V->ndof) + split_vec_bytes(Pp->ndof) +
+           align256((3 * kPicardBlocks + 8) * sizeof(double));
 }
 
 sipg_status sipg_split_step(sipg_plan* V, sipg_plan* Pp, sipg_plan* Pen, const double* u_old, const double* u_prev,
@@ -1552,6 +1601,7 @@ sipg_status sipg_split_step(sipg_plan* V, sipg_plan* Pp, sipg_plan* Pen, const d
     double* uvisc = reinterpret_cast<double*>(w + 3 * vb);
     double* uex = reinterpret_cast<double*>(w + 4 * vb);
     double* f = reinterpret_cast<double*>(w + 5 * vb);
+    double* sums = reinterpret_cast<double*>(w + 5 * vb + split_vec_bytes(Pp->ndof));
     const char* we = w + sipg_split_work_bytes(V, Pp);
     auto overlaps = [&](const void* v, size_t bytes) {
         const char* a = static_cast<const char*>(v);
@@ -1580,7 +1630,11 @@ sipg_status sipg_split_step(sipg_plan* V, sipg_plan* Pp, sipg_plan* Pen, const d
     if (rc == SIPG_OK) rc = sipg_projection(V, Pp, uhat, p, order, dt, uhh, rhs, stream);
     if (rc == SIPG_OK) rc = update_viscosity(V, ux, static_cast<hipStream_t>(stream));
     if (rc == SIPG_OK && g_wall) rc = sipg_wall_load(V, g_wall, rhs, stream);
-    if (rc == SIPG_OK) rc = sipg_solve(V, rhs, uvisc, &o.viscous, &inf.viscous, stream);
+    if (rc == SIPG_OK) {
+        rc = o.warm_start ? warm_solve(V, rhs, uhh, uvisc, uhat, sums, o.viscous, &inf.viscous,
+                                       static_cast<hipStream_t>(stream))
+                          : sipg_solve(V, rhs, uvisc, &o.viscous, &inf.viscous, stream);
+    }
     if (rc == SIPG_OK) rc = sipg_update_penalty_factors(Pen, ux, dt, o.zeta, stream);
     if (rc == SIPG_OK) {
         SplitGeo S;
@@ -1589,7 +1643,11 @@ sipg_status sipg_split_step(sipg_plan* V, sipg_plan* Pp, sipg_plan* Pen, const d
         if (e != hipSuccess) rc = fail(SIPG_ERR_HIP, std::string("split mass: ") + hipGetErrorString(e));
     }
     if (rc == SIPG_OK && g_wall) rc = sipg_wall_load(Pen, g_wall, rhs, stream);
-    if (rc == SIPG_OK) rc = sipg_solve(Pen, rhs, u_new, &o.penalty, &inf.penalty, stream);
+    if (rc == SIPG_OK) {
+        rc = o.warm_start ? warm_solve(Pen, rhs, uvisc, u_new, uhat, sums, o.penalty, &inf.penalty,
+                                       static_cast<hipStream_t>(stream))
+                          : sipg_solve(Pen, rhs, u_new, &o.penalty, &inf.penalty, stream);
+    }
     if (rc == SIPG_OK) g_err.clear();
     return finish(rc);
 }

@@ -19,11 +19,13 @@ class SplitOptions:
     viscous: SolveOptions = field(default_factory=lambda: SolveOptions(rel_tol=1e-10))
     penalty: SolveOptions = field(default_factory=lambda: SolveOptions(rel_tol=1e-10))
     zeta: float = 1.0
+    warm_start: bool = False         # viscous solve from uhh, penalty solve from u_visc
 
     def to_c(self) -> F.SplitOpts:
         o = F.SplitOpts()
         o.pressure, o.viscous, o.penalty = self.pressure.to_c(), self.viscous.to_c(), self.penalty.to_c()
         o.zeta = self.zeta
+        o.warm_start = int(self.warm_start)
         return o
 
 

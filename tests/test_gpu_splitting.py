@@ -350,3 +350,29 @@ def test_penalty_multigrid_levels_follow_the_factor_update():
         f"oracle residual {res:.2e}")
     assert err <= 1e-8
     assert info["status"] == "SIPG_OK" and res <= 1.0001e-10
+
+
+def test_warm_started_step():
+    """warm_start: the viscous solve starts from the projected velocity and
+    the penalty solve from the viscous one (correction solves to the
+    tolerance relative to |b|); the step equals the cold one to the
+    tolerance and needs no more iterations."""
+    dt = 1e-2
+    st, pb, law, V = make((3, 2, 2), 3, 0.1, dt)
+    gw = np.zeros((SP.wall_count(pb.mesh), pb.n ** 2, 3))
+    gw[SP.wall_rows(pb.mesh)[(2, 1)]] = np.array([1.0, 0.0, 0.0])
+    x = W.node_positions(3, 2, 2, 3, V)
+    u = dev(np.transpose(6.4 * np.prod(x * (1 - x), -1)[..., None] * np.stack(
+        [np.sin(np.pi * x[..., 1]), np.cos(np.pi * x[..., 2]), x[..., 0]], -1), (0, 2, 1)).reshape(-1))
+    b = dev(W.uniform_vector(7, pb.ndof))
+    g = dev(gw.reshape(-1))
+    o = SolveOptions(rel_tol=1e-10, precond_precision="f64")
+    cold, pc, ic = st.step(u, b, opts=SplitOptions(pressure=o, viscous=o, penalty=o), g_wall=g)
+    warm, pw, iw = st.step(u, b, opts=SplitOptions(pressure=o, viscous=o, penalty=o, warm_start=True), g_wall=g)
+    say(f"[split warm] cold {[v['iterations'] for v in ic.values()]}, warm {[v['iterations'] for v in iw.values()]}; "
+        f"residuals {[v['rel_residual'] for v in iw.values()]}")
+    assert all(v["status"] == "SIPG_OK" for v in iw.values())
+    assert all(v["rel_residual"] <= 1.0001e-10 for v in iw.values())
+    assert iw["viscous"]["iterations"] <= ic["viscous"]["iterations"]
+    assert iw["penalty"]["iterations"] <= ic["penalty"]["iterations"]
+    assert rel(host(warm), host(cold)) <= 1e-8 and torch.equal(pw, pc)
