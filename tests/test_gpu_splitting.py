@@ -133,6 +133,24 @@ def test_edge_cases():
     un, p, info = st.step(u)                                        # nothing moves
     assert float(un.abs().max()) == 0.0 and float(p.abs().max()) == 0.0
     assert info["pressure"]["iterations"] == 0
+    # plans that do not belong together are refused before any work
+    from paper_2506_14424_amd import Operator, SipgError, _ffi as F
+    import ctypes as C
+    d = lambda t: C.c_void_p(t.data_ptr())
+    f = torch.zeros(st.ndof_p, dtype=torch.float64, device="cuda")
+    wrong_p = Operator(2, 2, 2, 2, "poisson", 0.0, 1.0, None, None, ("N",) * 6).bind()        # degree k, not k-1
+    assert F.lib.sipg_pressure_rhs(st.vel._h, wrong_p._h, d(u), d(u), None, None, None, 0.01, d(f), None) == -1
+    other_mesh = Operator(2, 2, 3, 1, "poisson", 0.0, 1.0, None, None, ("N",) * 6).bind()
+    assert F.lib.sipg_pressure_rhs(st.vel._h, other_mesh._h, d(u), d(u), None, None, None, 0.01, d(f), None) == -1
+    with pytest.raises(SipgError, match="gamma_0/dt"):
+        st.dt, dt0 = 0.5, st.dt                                     # the viscous plan's alpha is 1/0.01
+        try:
+            st.step(u)
+        finally:
+            st.dt = dt0
+    bdf2 = SplitStep(2, 2, 2, 2, 1e-2, law, None, order=2).bind()
+    with pytest.raises(ValueError):
+        bdf2.step(u)                                                # BDF2 needs u_prev
 
 
 def test_full_size_properties():
