@@ -190,6 +190,22 @@ def test_full_size_properties():
     e4 = rel(got[lo + 1:lo + 3, lo + 1:lo + 3, lo + 1:lo + 3], ref[1:3, 1:3, 1:3])
     say(f"   sampled interior block vs oracle {e4:.2e}")
     assert e4 <= 1e-12
+    # the pressure right-hand side and the projection of the same block
+    # (interior cells depend only on themselves and their face neighbours)
+    pp = SP.pressure_problem(pbb.mesh, deg)
+    npn = deg ** 3
+    uh = W.uniform_vector(3, st.ndof_u)
+    pr = W.uniform_vector(4, st.ndof_p)
+    f = host(st.pressure_rhs(dev(uh), dev(u), dev(b))).reshape(m, m, m, npn)
+    subp = lambda v: v.reshape(m, m, m, npn)[lo:lo + 4, lo:lo + 4, lo:lo + 4].reshape(-1)
+    fr = SP.ppe_rhs(pbb, pp, sub(uh), sub(u), sub(b), dt).reshape(4, 4, 4, npn)
+    e5 = rel(f[lo + 1:lo + 3, lo + 1:lo + 3, lo + 1:lo + 3], fr[1:3, 1:3, 1:3])
+    uhh, _ = st.projection(dev(uh), dev(pr))
+    uhr, _ = SP.projection(pbb, pp, sub(uh), subp(pr), dt)
+    e6 = rel(host(uhh).reshape(m, m, m, 3, -1)[lo + 1:lo + 3, lo + 1:lo + 3, lo + 1:lo + 3],
+             uhr.reshape(4, 4, 4, 3, -1)[1:3, 1:3, 1:3])
+    say(f"   sampled block: pressure rhs {e5:.2e}, projection {e6:.2e}")
+    assert e5 <= 1e-12 and e6 <= 1e-12
 
 
 def test_second_step_with_reused_estimates():
