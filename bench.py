@@ -224,7 +224,8 @@ def picard_step(tol=1e-8):
     iterations) with and without Aitken relaxation, linear solves to 1e-3 with
     FP32 hp-multigrid, re-estimating the smoothers' eigenvalues after every
     viscosity update or (aitken_reuse_eigs) keeping the estimates the plan
-    already holds (here: from the warm-up run); plus the
+    already holds (here: from the warm-up run), or (aitken_lanczos10)
+    re-estimating them with 10 Lanczos steps instead of 20; plus the
     viscosity update alone (all levels and their diagonals)."""
     import torch
     import workloads as W
@@ -238,7 +239,9 @@ def picard_step(tol=1e-8):
     out = {"workload": f"c7: nonlinear viscous step, k=4, 24^3 perturbed, Carreau law of the velocity, "
                        f"{op.ndof} DoFs, x0 = 0, rel. tol {tol:g} of the nonlinear residual"}
     reuse = SolveOptions(rel_tol=1e-3, precond="multigrid", cheb_degree=4, reuse_eigs=True)
-    for key, aitken, lo in (("aitken", True, lin), ("plain", False, lin), ("aitken_reuse_eigs", True, reuse)):
+    lz10 = SolveOptions(rel_tol=1e-3, precond="multigrid", cheb_degree=4, lanczos_steps=10)
+    for key, aitken, lo in (("aitken", True, lin), ("plain", False, lin), ("aitken_reuse_eigs", True, reuse),
+                            ("aitken_lanczos10", True, lz10)):
         op.picard_solve(b, opts=lo, rel_tol=tol, max_iter=60, aitken=aitken, work=work)   # warm
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -261,7 +264,8 @@ def picard_step(tol=1e-8):
 
 def split_step(reps=5, tol=1e-8):
     """c8: one dual-splitting time step (BDF1, lid-driven box) and a BDF2
-    step from its result: the whole step
+    step from its result (also with kept eigenvalue estimates, with warm
+    starts, and with 10 instead of 20 Lanczos steps): the whole step
     (convective step, pressure right-hand side, pressure Poisson solve,
     projection, viscosity update, viscous solve, penalty factors, penalty
     solve) and each part alone; the three non-solve operators with their
@@ -305,6 +309,16 @@ def split_step(reps=5, tol=1e-8):
     torch.cuda.synchronize()
     step_warm_s = (time.perf_counter() - t0) / reps
     warm_diff = float((un_w - un).norm() / un.norm())
+    mg10 = SolveOptions(rel_tol=tol, precond="multigrid", cheb_degree=4, lanczos_steps=10)
+    lopts = SplitOptions(pressure=mg10, viscous=mg10, penalty=SolveOptions(rel_tol=tol, lanczos_steps=10), zeta=1.0)
+    un_l, p_l, info_l = st.step(u, b, opts=lopts, g_wall=gw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        un_l, p_l, info_l = st.step(u, b, u_new=un_l, p=p_l, opts=lopts, g_wall=gw)
+    torch.cuda.synchronize()
+    step_lz10_s = (time.perf_counter() - t0) / reps
+    lz10_diff = float((un_l - un).norm() / un.norm())
     # BDF2 steps (u^{n-1} = the BDF1 step's input, u^n = its result): plans with gamma_0 = 3/2
     st2 = SplitStep(m, m, m, deg, dt, cfg["law"], V, order=2).set_multigrid().bind()
     un2, p2, info2 = st2.step(un, b, opts=opts, g_wall=gw, u_prev=u)
@@ -371,6 +385,9 @@ def split_step(reps=5, tol=1e-8):
             "step_seconds_reuse_eigs_warm_start": step_warm_s,
             "warm_start_iterations": {k: v["iterations"] for k, v in info_w.items()},
             "warm_start_rel_diff_u": warm_diff,
+            "step_seconds_lanczos10": step_lz10_s,
+            "lanczos10_iterations": {k: v["iterations"] for k, v in info_l.items()},
+            "lanczos10_rel_diff_u": lz10_diff,
             "bdf2_step_seconds": step2_s,
             "bdf2_iterations": {k: v["iterations"] for k, v in info2.items()},
             "reuse_eigs_note": "viscous and penalty solves keep the eigenvalue estimates of an earlier "
