@@ -274,8 +274,11 @@ __device__ __forceinline__ double eta_split(const SplitGeo& S, double gdot) {
 
 // Trace and reference gradient (d/dxi_1, d/dxi_2, d/dxi_3) at the face point
 // (a, bb) of face (D, SD) of one component's n^3 nodal values P of a cell.
+// TB: the 1D tables in LDS, D (n x n), then S (2 x n), then G (2 x n); read
+// from LDS rather than the kernel argument, whose runtime-indexed reads made
+// the compiler copy the whole argument into scratch.
 template <int N, int D, int SD>
-__device__ __forceinline__ void face_trace_grad(const SplitGeo& S, const double* P, int a, int bb, double& tr,
+__device__ __forceinline__ void face_trace_grad(const double* TB, const double* P, int a, int bb, double& tr,
                                                 double gref[3]) {
     constexpr int t1 = D == 0 ? 1 : 0, t2 = D == 2 ? 1 : 2;
     const int str[3] = {1, N, N * N};
@@ -283,19 +286,19 @@ __device__ __forceinline__ void face_trace_grad(const SplitGeo& S, const double*
     double v = 0.0, dn = 0.0, d1 = 0.0, d2 = 0.0;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        v += S.tab.S[SD][k] * P[line + k * str[D]];
-        dn += S.tab.G[SD][k] * P[line + k * str[D]];
+        v += TB[N * N + SD * N + k] * P[line + k * str[D]];
+        dn += TB[N * N + 2 * N + SD * N + k] * P[line + k * str[D]];
     }
 #pragma unroll 1
     for (int k2 = 0; k2 < N; ++k2) {
         double t1v = 0.0, t2v = 0.0;
 #pragma unroll
         for (int k = 0; k < N; ++k) {
-            t1v += S.tab.S[SD][k] * P[k2 * str[t1] + bb * str[t2] + k * str[D]];
-            t2v += S.tab.S[SD][k] * P[a * str[t1] + k2 * str[t2] + k * str[D]];
+            t1v += TB[N * N + SD * N + k] * P[k2 * str[t1] + bb * str[t2] + k * str[D]];
+            t2v += TB[N * N + SD * N + k] * P[a * str[t1] + k2 * str[t2] + k * str[D]];
         }
-        d1 += S.tab.D[a][k2] * t1v;
-        d2 += S.tab.D[bb][k2] * t2v;
+        d1 += TB[a * N + k2] * t1v;
+        d2 += TB[bb * N + k2] * t2v;
     }
     tr = v;
     gref[D] = dn;
@@ -316,7 +319,7 @@ template <int N, int ORDER, int FC>
 __device__ __forceinline__ double ppe_face(const SplitGeo& S, const CellMap& m, int e, const int ijk[3], int ab,
                                            const double* __restrict__ uhat, const double* __restrict__ u_old,
                                            const double* __restrict__ u1, const double* __restrict__ b, double dt,
-                                           const double* OM, const double* NU) {
+                                           const double* OM, const double* NU, const double* TB) {
     constexpr int N2 = N * N, N3 = N2 * N, d = FC >> 1, s = FC & 1;
     const int str[3] = {1, N, N2};
     const int a = ab % N, bb = ab / N;
@@ -410,7 +413,7 @@ __device__ __forceinline__ double ppe_face(const SplitGeo& S, const CellMap& m, 
                 const double* uo = (i == 0 ? u_old : u1) + (long long)e * 3 * N3;
                 double ut[3], gref[3][3], G[3][3];
     #pragma unroll
-                for (int c = 0; c < 3; ++c) face_trace_grad<N, d, s>(S, uo + c * N3, a, bb, ut[c], gref[c]);
+                for (int c = 0; c < 3; ++c) face_trace_grad<N, d, s>(TB, uo + c * N3, a, bb, ut[c], gref[c]);
                 phys_grad3(gref, fp.Ji, G);
     #pragma unroll
                 for (int c = 0; c < 3; ++c) {
@@ -446,10 +449,10 @@ __device__ __forceinline__ double ppe_face(const SplitGeo& S, const CellMap& m, 
                 const double nu = eta_split(S, sqrt(2.0 * ee));
                 double ot[3], gro[3][3], Go[3][3], nt, gn_ref[3];
     #pragma unroll
-                for (int c = 0; c < 3; ++c) face_trace_grad<N, d, s>(S, OM + c * N3, a, bb, ot[c], gro[c]);
+                for (int c = 0; c < 3; ++c) face_trace_grad<N, d, s>(TB, OM + c * N3, a, bb, ot[c], gro[c]);
                 phys_grad3(gro, fp.Ji, Go);
                 const double curl[3] = {Go[2][1] - Go[1][2], Go[0][2] - Go[2][0], Go[1][0] - Go[0][1]};
-                face_trace_grad<N, d, s>(S, NU, a, bb, nt, gn_ref);
+                face_trace_grad<N, d, s>(TB, NU, a, bb, nt, gn_ref);
                 double gnu[3];
     #pragma unroll
                 for (int k = 0; k < 3; ++k)
@@ -481,6 +484,8 @@ __global__ void __launch_bounds__(kFaceThreads<N>) k_split_ppe_rhs(SplitGeo S, c
     __shared__ double UO[ORDER > 1 ? 3 * N3 : 1];
     __shared__ double OM[ORDER > 1 ? 3 * N3 : 1];
     __shared__ double NU[ORDER > 1 ? N3 : 1];
+    __shared__ double TB[ORDER > 1 ? N2 + 4 * N : 1];   // BDF2 wall cells: D, S, G tables
+    static_assert(kFaceThreads<N> >= N2 + 4 * N, "one thread per table entry");
     const int e = blockIdx.x, t = threadIdx.x;
     int ijk[3];
     cell_ijk(S, e, ijk);
@@ -493,6 +498,9 @@ __global__ void __launch_bounds__(kFaceThreads<N>) k_split_ppe_rhs(SplitGeo S, c
     if (ORDER > 1 && wall) {           // uniform over the workgroup
         const double* uo = u_old + (long long)e * 3 * N3;
         for (int k = t; k < 3 * N3; k += blockDim.x) UO[k] = uo[k];
+        if (t < N2) TB[t] = S.tab.D[t / N][t % N];
+        else if (t < N2 + 2 * N) TB[t] = S.tab.S[(t - N2) / N][(t - N2) % N];
+        else if (t < N2 + 4 * N) TB[t] = S.tab.G[(t - N2 - 2 * N) / N][(t - N2 - 2 * N) % N];
         __syncthreads();
         if (t < N3) {
             // omega = curl u and nu = eta(gdot(grad^S u)) at the node: with the
@@ -540,12 +548,12 @@ __global__ void __launch_bounds__(kFaceThreads<N>) k_split_ppe_rhs(SplitGeo S, c
         const int fc = t / N2, ab = t % N2;
         double v = 0.0;
         switch (fc) {
-            case 0: v = ppe_face<N, ORDER, 0>(S, m, e, ijk, ab, uhat, u_old, u1, b, dt, OM, NU); break;
-            case 1: v = ppe_face<N, ORDER, 1>(S, m, e, ijk, ab, uhat, u_old, u1, b, dt, OM, NU); break;
-            case 2: v = ppe_face<N, ORDER, 2>(S, m, e, ijk, ab, uhat, u_old, u1, b, dt, OM, NU); break;
-            case 3: v = ppe_face<N, ORDER, 3>(S, m, e, ijk, ab, uhat, u_old, u1, b, dt, OM, NU); break;
-            case 4: v = ppe_face<N, ORDER, 4>(S, m, e, ijk, ab, uhat, u_old, u1, b, dt, OM, NU); break;
-            default: v = ppe_face<N, ORDER, 5>(S, m, e, ijk, ab, uhat, u_old, u1, b, dt, OM, NU); break;
+            case 0: v = ppe_face<N, ORDER, 0>(S, m, e, ijk, ab, uhat, u_old, u1, b, dt, OM, NU, TB); break;
+            case 1: v = ppe_face<N, ORDER, 1>(S, m, e, ijk, ab, uhat, u_old, u1, b, dt, OM, NU, TB); break;
+            case 2: v = ppe_face<N, ORDER, 2>(S, m, e, ijk, ab, uhat, u_old, u1, b, dt, OM, NU, TB); break;
+            case 3: v = ppe_face<N, ORDER, 3>(S, m, e, ijk, ab, uhat, u_old, u1, b, dt, OM, NU, TB); break;
+            case 4: v = ppe_face<N, ORDER, 4>(S, m, e, ijk, ab, uhat, u_old, u1, b, dt, OM, NU, TB); break;
+            default: v = ppe_face<N, ORDER, 5>(S, m, e, ijk, ab, uhat, u_old, u1, b, dt, OM, NU, TB); break;
         }
         FF[fc][ab] = v;
     }
