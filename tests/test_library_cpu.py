@@ -177,3 +177,49 @@ def test_split_step_entry_points_on_cpu():
     assert s.wall_count() == 2 * (2 * 2 + 3 * 2 + 3 * 2)
     with pytest.raises(ValueError):
         SplitStep(3, 2, 2, 3, 0.01, W.sine_law(1.0, 0.5))
+
+
+def kernel_scratch_bytes(lib_path):
+    """Per-lane scratch (private segment) of every kernel in the library's
+    gfx950 code objects, from the code-object metadata notes."""
+    import shutil
+    import subprocess
+    import tempfile
+    tools = "/opt/rocm/llvm/bin"
+    need = [os.path.join(tools, t) for t in ("llvm-objcopy", "clang-offload-bundler", "llvm-readelf")]
+    if not all(shutil.which(t) for t in need):
+        pytest.skip("ROCm LLVM tools not found")
+    out = {}
+    with tempfile.TemporaryDirectory() as d:
+        fat = os.path.join(d, "fat.bin")
+        subprocess.run([need[0], f"--dump-section=.hip_fatbin={fat}", lib_path, os.path.join(d, "lib.o")],
+                       check=True, capture_output=True)
+        data = open(fat, "rb").read()
+        offs = [m.start() for m in re.finditer(b"__CLANG_OFFLOAD_BUNDLE__", data)] + [len(data)]
+        for i in range(len(offs) - 1):
+            b, co = os.path.join(d, f"b{i}.bin"), os.path.join(d, f"c{i}.o")
+            open(b, "wb").write(data[offs[i]:offs[i + 1]])
+            subprocess.run([need[1], "--unbundle", "--type=o", "--targets=hipv4-amdgcn-amd-amdhsa--gfx950",
+                            f"--input={b}", f"--output={co}"], check=True, capture_output=True)
+            notes = subprocess.run([need[2], "--notes", co], check=True, capture_output=True, text=True).stdout
+            if "amdhsa.kernels:" not in notes:
+                continue
+            body = re.split(r"\namdhsa\.", notes[notes.index("amdhsa.kernels:"):])[0]
+            for k in re.split(r"\n  - ", body)[1:]:
+                name = re.search(r"\.name:\s+(\S+)", k).group(1)
+                out[name] = int(re.search(r"\.private_segment_fixed_size:\s+(\d+)", k).group(1))
+    return out
+
+
+def test_hot_kernels_use_no_scratch():
+    """The splitting-step kernels and the FP64/FP32 apply instances up to
+    n = 5 keep everything in registers and LDS: a kernel argument copied to
+    scratch for runtime indexing (or a spill) shows up here at build time."""
+    from paper_2506_14424_amd import LIB_PATH
+    scratch = kernel_scratch_bytes(LIB_PATH)
+    split = {k: v for k, v in scratch.items() if re.search(r"k_split_|k_pen_factors|k_wall_load", k)}
+    assert len(split) == 28, sorted(split)        # 7 kernels (ppe right-hand side: 2 BDF orders) x n = 3..6
+    assert not {k: v for k, v in split.items() if v}
+    apply = {k: v for k, v in scratch.items() if re.match(r"_ZN4sipg7k_applyILi[2-5]E", k)}
+    assert len(apply) >= 40
+    assert not {k: v for k, v in apply.items() if v}
