@@ -208,6 +208,42 @@ def test_full_size_properties():
     assert e5 <= 1e-12 and e6 <= 1e-12
 
 
+def test_full_size_bdf2_lid_corner_block():
+    """BDF2 at the c8 size (24^3 curved, k = 4, Carreau law, lid on +z): the
+    convective step with two old velocities and the pressure right-hand side
+    with its wall terms (extrapolated convective term, nu curl(omega),
+    2 grad^S u . grad nu, the lid's data) equal the oracle's on a 4^3 block
+    in the corner where the lid meets the -x and -y walls.  The oracle runs
+    on the block alone (same vertices, the lid's data on its +z side), so
+    only the block cells whose faces are all interior or real walls are
+    compared: the block's +x, +y and -z sides are artificial walls."""
+    cfg = W.config("c8")
+    m, deg, dt, law = cfg["nx"], cfg["degree"], cfg["dt"], cfg["law"]
+    V = W.box_vertices(m, m, m, cfg["perturb"])
+    st = SplitStep(m, m, m, deg, dt, law, V, order=2).bind()
+    u, b = W.split_inputs(cfg, V)
+    up = 0.8 * u + 0.1 * W.uniform_vector(12, st.ndof_u)
+    uh = W.uniform_vector(3, st.ndof_u)
+    gw = dev(W.lid_data(cfg))
+    conv = host(st.convective_step(dev(u), dev(b), g_wall=gw, u_prev=dev(up))).reshape(m, m, m, 3, -1)
+    npn = deg ** 3
+    f = host(st.pressure_rhs(dev(uh), dev(u), dev(b), g_wall=gw, u_prev=dev(up))).reshape(m, m, m, npn)
+    z0 = m - 4
+    Vb = V.reshape(m + 1, m + 1, m + 1, 3)[z0:z0 + 5, 0:5, 0:5].reshape(-1, 3)
+    pbb = Problem(Mesh(4, 4, 4, Vb), deg, "viscous", 1.5 / dt, 1.0, law)
+    pp = SP.pressure_problem(pbb.mesh, deg)
+    gsub = np.zeros((SP.wall_count(pbb.mesh), pbb.n ** 2, 3))
+    gsub[SP.wall_rows(pbb.mesh)[(2, 1)]] = np.array([1.0, 0.0, 0.0])
+    gsub = gsub.reshape(-1)
+    sub = lambda v: v.reshape(m, m, m, 3, -1)[z0:z0 + 4, 0:4, 0:4].reshape(-1)
+    cref = SP.convective_step(pbb, sub(u), sub(b), dt, gsub, sub(up)).reshape(4, 4, 4, 3, -1)
+    fref = SP.ppe_rhs(pbb, pp, sub(uh), sub(u), sub(b), dt, gsub, sub(up), law).reshape(4, 4, 4, npn)
+    e1 = rel(conv[z0 + 1:, 0:3, 0:3], cref[1:, 0:3, 0:3])
+    e2 = rel(f[z0 + 1:, 0:3, 0:3], fref[1:, 0:3, 0:3])
+    say(f"[split bdf2 full size] corner block: convective {e1:.2e}, pressure rhs {e2:.2e}")
+    assert e1 <= 1e-12 and e2 <= 1e-12
+
+
 def test_second_step_with_reused_estimates():
     """Two steps: the second with the viscous and penalty solves keeping the
     first step's eigenvalue estimates (reuse_eigs) equals the second step
