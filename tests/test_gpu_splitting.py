@@ -244,6 +244,50 @@ def test_full_size_bdf2_lid_corner_block():
     assert e1 <= 1e-12 and e2 <= 1e-12
 
 
+def test_full_size_wall_loads_corner_block():
+    """The viscous and penalty wall loads at the c8 size with random data on
+    every wall face point, after the viscosity and penalty-factor updates
+    from the c8 velocity, equal the oracle's on the 4^3 corner block at
+    +z, -x, -y: the block gets the full data's rows of its real walls and
+    zeros on its artificial ones, whose cells are not compared."""
+    from oracle import picard as PC
+    cfg = W.config("c8")
+    m, deg, dt, law = cfg["nx"], cfg["degree"], cfg["dt"], cfg["law"]
+    V = W.box_vertices(m, m, m, cfg["perturb"])
+    st = SplitStep(m, m, m, deg, dt, law, V).bind()
+    u, _ = W.split_inputs(cfg, V)
+    full = Mesh(m, m, m, V)
+    n2 = (deg + 1) ** 2
+    gw = W.uniform_vector(8, SP.wall_count(full) * n2 * 3)
+    zero = lambda: torch.zeros(st.ndof_u, dtype=torch.float64, device="cuda")
+    st.vel.update_viscosity(dev(u))
+    yv = host(st.wall_load(st.vel, dev(gw), zero())).reshape(m, m, m, 3, -1)
+    st.update_penalty_factors(dev(u))
+    yp = host(st.wall_load(st.pen, dev(gw), zero())).reshape(m, m, m, 3, -1)
+    z0 = m - 4
+    mb = Mesh(4, 4, 4, V.reshape(m + 1, m + 1, m + 1, 3)[z0:z0 + 5, 0:5, 0:5].reshape(-1, 3))
+    pbb = Problem(mb, deg, "viscous", 1.0 / dt, 1.0, law)
+    G = gw.reshape(-1, n2, 3)
+    gsub = np.zeros((SP.wall_count(mb), n2, 3))
+    rows_f, rows_b = SP.wall_rows(full), SP.wall_rows(mb)
+    for d, side in ((0, 0), (1, 0), (2, 1)):
+        fcells, bcells = full.boundary_cells(d, side), mb.boundary_cells(d, side)
+        fid = ((bcells // 16 + z0) * m + (bcells // 4) % 4) * m + bcells % 4
+        idx = np.searchsorted(fcells, fid)
+        assert (fcells[idx] == fid).all()
+        gsub[rows_b[(d, side)]] = G[rows_f[(d, side)]][idx]
+    gsub = gsub.reshape(-1)
+    ub = u.reshape(m, m, m, 3, -1)[z0:z0 + 4, 0:4, 0:4].reshape(-1)
+    rv = SP.viscous_wall_load(PC.with_velocity_viscosity(pbb, pbb, ub, law), gsub).reshape(4, 4, 4, 3, -1)
+    td, tc = SP.penalty_factors(pbb, ub, dt)
+    pen = Problem(mb, deg, "penalty", 1.0, 1.0, tau_div=td, tau_cont=tc)
+    rp = SP.penalty_wall_load(pen, gsub).reshape(4, 4, 4, 3, -1)
+    ev = rel(yv[z0 + 1:, 0:3, 0:3], rv[1:, 0:3, 0:3])
+    ep = rel(yp[z0 + 1:, 0:3, 0:3], rp[1:, 0:3, 0:3])
+    say(f"[split walls full size] corner block: viscous load {ev:.2e}, penalty load {ep:.2e}")
+    assert ev <= 1e-12 and ep <= 1e-12
+
+
 def test_second_step_with_reused_estimates():
     """Two steps: the second with the viscous and penalty solves keeping the
     first step's eigenvalue estimates (reuse_eigs) equals the second step
