@@ -10,15 +10,19 @@
  *            tau_1 = {{mu grad u}} - tau [[u]], tau_2 = tau_1^T ("Viscous Step");
  *   poisson  the SIPG Laplacian of the pressure step ("Pressure Step"), with
  *            the coercive penalty sign and an optional mass term alpha;
- *   penalty  the operator of the penalty step (Sec. 3, "Consistent
+ *   penalty  the operator of the penalty step (Sec. 4.3, "Consistent
  *            Stabilization", eq. penalty_step): (alpha v, u) +
  *            (div v, tau_div^e div u)_e + (v.n, tau_cont [[u]].n) on faces, with
  *            per-cell factors given by the caller, the face factor the mean of
  *            the two cells' tau_cont, and the oriented jump u - g on Dirichlet
  *            faces (no mirror doubling); alpha = 1 is the paper's form.
  * Boundary conditions are homogeneous and imposed by the mirror principle
- * (Sec. 4).  Penalty: tau = P (k+1)^2 mu(x) / h_F, h_F = min(h^-, h^+),
- * h_e = |cell|^(1/3) (the paper defers the formula to Hillewaert 2013).
+ * (Sec. 4).  Penalty (Sec. 4.1 takes it from Hillewaert 2013 without the
+ * formula): tau = P (k+1)^2 mu(x) sigma_F at every face point, with sigma_e =
+ * (sum over the cell's faces of w_f |f|) / |e| the cell's surface-to-volume
+ * ratio, w_f = 1/2 for faces shared with another cell and 1 on the boundary
+ * (3/h for an interior cube of edge h), sigma_F = max(sigma^-, sigma^+) on an
+ * interior face and the cell's own sigma on a boundary face.
  *
  * Discretisation: structured nx*ny*nz hexahedral mesh of a box, cells
  * trilinear in their vertices (straight unit box when no vertices are given),

@@ -21,7 +21,7 @@ What it computes, and from which passage:
   principle at the boundary;
 * the SIPG Poisson form of the pressure step (Sec. 4.1, paragraph
   "Pressure Step") with a coercive penalty sign;
-* the penalty-step form (Sec. 3, "Consistent Stabilization"): mass plus
+* the penalty-step form (Sec. 4.3, "Consistent Stabilization"): mass plus
   divergence and normal-continuity penalties;
 * the viscosity laws of Sec. 2 (generalised Newtonian law) and smooth
   prescribed fields, evaluated pointwise at quadrature points (Sec. 4.1);

@@ -24,7 +24,7 @@ Poisson operator (Sec. 4.1, paragraph "Pressure Step"), coercive SIPG sign:
             + sum_interior int -{{grad q}}.n [p] - {{grad p}}.n [q] + tau_p [q][p]
             + sum_Dirichlet int -(grad q . n) p - (grad p . n) q + 2 tau_p q p
 
-Penalty step (Sec. 3, "Consistent Stabilization", eq. penalty_step): per cell
+Penalty step (Sec. 4.3, "Consistent Stabilization", eq. penalty_step): per cell
 (v, u) + (div v, tau_div^e div u) + (v.n, tau_cont^e [[u]].n) on the cell
 boundary.  Summed over cells with the face factor taken as the mean of the
 two cells' tau_cont (a reading: it keeps the form symmetric) and the
@@ -36,9 +36,13 @@ oriented jump u - g on Dirichlet faces (no mirror doubling):
 
 with alpha = 1 for the paper's form; the factors come per cell as inputs.
 
-Penalty of the SIPG forms (the paper defers to Hillewaert 2013 and omits the formula):
-tau = P (k+1)^2 mu(x) / h_F with h_F = min(h^-, h^+), h_e = |cell|^(1/3),
-h_F = h^- on the boundary, and mu = 1 for the Poisson operator.
+Penalty of the SIPG forms (Sec. 4.1 takes it from Hillewaert 2013 and omits
+the formula): tau = P (k+1)^2 mu(x) sigma_F, where sigma_e is the cell's
+surface-to-volume ratio with interior faces weighted by one half,
+  sigma_e = (sum_{faces f of e} w_f |f|) / |e|,  w_f = 1/2 inside, 1 on the boundary,
+sigma_F = max(sigma^-, sigma^+) on an interior face and the cell's own value on
+a boundary face, mu the pointwise viscosity at the face point (mu = 1 for the
+Poisson operator).  For a cube of edge h inside the mesh sigma_e = 3/h.
 
 Degrees of freedom: nodal values at the Gauss points; vector index
 ((e*C + c)*n + i3)*n^2 + i2*n + i1.
@@ -61,7 +65,7 @@ class Problem:
     degree: int
     op: str = "viscous"          # "viscous" (3 components), "poisson" (1) or "penalty" (3)
     alpha: float = 0.0           # gamma_0 / dt in front of the mass term (1 for the penalty step)
-    penalty: float = 1.0         # P in tau = P (k+1)^2 mu / h_F
+    penalty: float = 1.0         # P in tau = P (k+1)^2 mu sigma_F
     law: object = field(default_factory=lambda: {"kind": "const", "mu": 1.0})
     tau_div: object = None       # penalty step: tau_div per cell
     tau_cont: object = None      # penalty step: tau_cont per cell
@@ -108,6 +112,30 @@ def cell_sizes(pb: Problem, cells=None) -> np.ndarray:
     h = np.full(pb.mesh.ncells, np.nan)
     h[cells] = (np.linalg.det(pb.mesh.jacobian(cells, pts)) @ w) ** (1.0 / 3.0)
     return h
+
+
+def penalty_geometry(pb: Problem, cells=None) -> np.ndarray:
+    """sigma_e = (sum_f w_f |f|) / |e| per cell: face areas |f| = sum of ds
+    over the face rule, w_f = 1/2 for a face shared with another cell and 1
+    for a face on the boundary of the box, |e| = sum of JxW.  With `cells`
+    given only those entries are computed (the others are NaN)."""
+    mesh = pb.mesh
+    sel = np.arange(mesh.ncells) if cells is None else np.unique(np.asarray(cells))
+    sig = np.full(mesh.ncells, np.nan)
+    if len(sel) == 0:
+        return sig
+    _, _, JxW = _cell_geo(pb, sel)
+    vol = JxW.sum(axis=1)
+    ijk = mesh.cell_ijk(sel)
+    surf = np.zeros(len(sel))
+    for d in range(3):
+        lim = (mesh.nx, mesh.ny, mesh.nz)[d]
+        for side in (0, 1):
+            _, _, _, _, ds = _face_geo(pb, sel, d, side)
+            on_boundary = ijk[d] == (lim - 1 if side == 1 else 0)
+            surf += np.where(on_boundary, 1.0, 0.5) * ds.sum(axis=1)
+    sig[sel] = surf / vol
+    return sig
 
 
 def _with_neighbours(mesh, cells) -> np.ndarray:
@@ -167,8 +195,9 @@ def _mu_face(pb: Problem, d, cells, side, x):
     return _mu(pb, x)
 
 
-def _tau(pb: Problem, mu, hF):
-    return pb.penalty * (pb.degree + 1) ** 2 * mu / hF[:, None]
+def _tau(pb: Problem, mu, sigF):
+    """tau = P (k+1)^2 mu sigma_F at the face points (mu: (F, points))."""
+    return pb.penalty * (pb.degree + 1) ** 2 * mu * sigF[:, None]
 
 
 def _sym(G):
@@ -266,7 +295,7 @@ def assemble(pb: Problem, parts=PARTS_ALL) -> sp.csr_matrix:
     mesh, n, C, nloc = pb.mesh, pb.n, pb.C, pb.nloc
     rows, cols, vals = [], [], []
     loc = np.arange(nloc)
-    h = cell_sizes(pb)
+    sig = penalty_geometry(pb)
 
     def add(block, dofs_r, dofs_c):
         R, Cc = np.meshgrid(dofs_r, dofs_c, indexing="ij")
@@ -303,7 +332,7 @@ def assemble(pb: Problem, parts=PARTS_ALL) -> sp.csr_matrix:
                 _, xq, Jim, nrm, ds = _face_geo(pb, np.array([a]), d, 1)
                 _, _, Jip, _, _ = _face_geo(pb, np.array([b]), d, 0)
                 mu = _mu_face(pb, d, np.array([a]), 1, xq)[0]
-                tau = _tau(pb, mu[None], np.array([min(h[a], h[b])]))[0]
+                tau = _tau(pb, mu[None], np.array([max(sig[a], sig[b])]))[0]
                 vm_, gm_ = _basis_traces(pb, Vm, Gm, Jim[0])
                 vp_, gp_ = _basis_traces(pb, Vp, Gp, Jip[0])
                 # test/trial functions of both cells: first the "-" cell's, then the "+" cell's
@@ -336,7 +365,7 @@ def assemble(pb: Problem, parts=PARTS_ALL) -> sp.csr_matrix:
                 for e in mesh.boundary_cells(d, side):
                     _, xq, Ji, nrm, ds = _face_geo(pb, np.array([e]), d, side)
                     mu = _mu_face(pb, d, np.array([e]), side, xq)[0]
-                    tau = _tau(pb, mu[None], np.array([h[e]]))[0]
+                    tau = _tau(pb, mu[None], np.array([sig[e]]))[0]
                     v, g = _basis_traces(pb, Vf, Gf, Ji[0])
                     K = np.zeros((nloc, nloc))
                     for f in range(len(ds[0])):
@@ -384,7 +413,7 @@ def apply(pb: Problem, x: np.ndarray, parts=PARTS_ALL, batch: int = 4096, cells=
     mesh, n, C = pb.mesh, pb.n, pb.C
     X = np.asarray(x, dtype=np.float64).reshape(mesh.ncells, C, n ** 3)
     Y = np.zeros_like(X)
-    h = cell_sizes(pb) if cells is None else cell_sizes(pb, _with_neighbours(mesh, cells))
+    sig = penalty_geometry(pb) if cells is None else penalty_geometry(pb, _with_neighbours(mesh, cells))
     sel = np.ones(mesh.ncells, dtype=bool)
     if cells is not None:
         sel[:] = False
@@ -424,7 +453,7 @@ def apply(pb: Problem, x: np.ndarray, parts=PARTS_ALL, batch: int = 4096, cells=
                 _, xq, Jim, nrm, ds = _face_geo(pb, em, d, 1)
                 _, _, Jip, _, _ = _face_geo(pb, ep, d, 0)
                 mu = _mu_face(pb, d, em, 1, xq)
-                tau = _tau(pb, mu, np.minimum(h[em], h[ep]))
+                tau = _tau(pb, mu, np.maximum(sig[em], sig[ep]))
                 um = np.einsum("pj,ecj->epc", Vm, X[em]); up = np.einsum("pj,ecj->epc", Vp, X[ep])
                 gm = _phys_grad(X[em], Gm, Jim); gp = _phys_grad(X[ep], Gp, Jip)
                 if pb.op == "penalty":
@@ -459,7 +488,7 @@ def apply(pb: Problem, x: np.ndarray, parts=PARTS_ALL, batch: int = 4096, cells=
                     continue
                 _, xq, Ji, nrm, ds = _face_geo(pb, cells, d, side)
                 mu = _mu_face(pb, d, cells, side, xq)
-                tau = _tau(pb, mu, h[cells])
+                tau = _tau(pb, mu, sig[cells])
                 u = np.einsum("pj,ecj->epc", Vf, X[cells])
                 gu = _phys_grad(X[cells], Gf, Ji)
                 if pb.op == "penalty":
@@ -489,7 +518,7 @@ def diagonal(pb: Problem, batch: int = 1024) -> np.ndarray:
     Jacobi-type smoother)."""
     mesh, n, C, nloc = pb.mesh, pb.n, pb.C, pb.nloc
     D = np.zeros((mesh.ncells, nloc))
-    h = cell_sizes(pb)
+    sig = penalty_geometry(pb)
     pts, _ = cell_points(n)
     V, G = tensor_tables(n, pts)
     for s in range(0, mesh.ncells, batch):
@@ -510,12 +539,12 @@ def diagonal(pb: Problem, batch: int = 1024) -> np.ndarray:
                 dens = pb.alpha * V[None] ** 2 + g2
             D[cells, c * n ** 3:(c + 1) * n ** 3] += np.einsum("ep,epj->ej", JxW, dens)
 
-    def face_self(cells, d, side, hF, dirichlet, tau_p=None):
+    def face_self(cells, d, side, sigF, dirichlet, tau_p=None):
         pts, _ = face_points(n, d, side)
         Vf, Gf = tensor_tables(n, pts)
         _, xq, Ji, nrm, ds = _face_geo(pb, cells, d, side)
         mu = _mu_face(pb, d, cells, side, xq)
-        tau = _tau(pb, mu, hF)
+        tau = _tau(pb, mu, sigF)
         out = np.zeros((len(cells), nloc))
         for ii, e in enumerate(cells):
             v, g = _basis_traces(pb, Vf, Gf, Ji[ii])
@@ -552,14 +581,14 @@ def diagonal(pb: Problem, batch: int = 1024) -> np.ndarray:
     for d in range(3):
         em, ep = mesh.interior_faces(d)
         if len(em):
-            hF = np.minimum(h[em], h[ep])
+            sF = np.maximum(sig[em], sig[ep])
             tp = _tau_face(pb, em, ep) if pen else None
-            D[em] += face_self(em, d, 1, hF, False, tp)
-            D[ep] += face_self(ep, d, 0, hF, False, tp)
+            D[em] += face_self(em, d, 1, sF, False, tp)
+            D[ep] += face_self(ep, d, 0, sF, False, tp)
         for side in (0, 1):
             if mesh.bc[2 * d + side] == "D":
                 cells = mesh.boundary_cells(d, side)
-                D[cells] += face_self(cells, d, side, h[cells], True, _tau_face(pb, cells) if pen else None)
+                D[cells] += face_self(cells, d, side, sig[cells], True, _tau_face(pb, cells) if pen else None)
     return D.reshape(-1)
 
 
@@ -591,7 +620,7 @@ def load_vector(pb: Problem, f, g=None, hN=None) -> np.ndarray:
     receives the outward unit normal at the points."""
     mesh, n, C = pb.mesh, pb.n, pb.C
     Y = np.zeros((mesh.ncells, C, n ** 3))
-    h = cell_sizes(pb)
+    sig = penalty_geometry(pb)
     pts, _ = cell_points(n)
     V, G = tensor_tables(n, pts)
     cells = np.arange(mesh.ncells)
@@ -609,7 +638,7 @@ def load_vector(pb: Problem, f, g=None, hN=None) -> np.ndarray:
             E, P = xq.shape[:2]
             if kind == "D" and g is not None:
                 mu = _mu_face(pb, d, bc_cells, side, xq)
-                tau = _tau(pb, mu, h[bc_cells])
+                tau = _tau(pb, mu, sig[bc_cells])
                 gv = np.asarray(g(xq.reshape(-1, 3))).reshape(E, P, C)
                 if pb.op == "viscous":
                     a = 2.0 * tau[..., None] * (gv + nrm * np.einsum("epc,epc->ep", gv, nrm)[..., None])

@@ -55,7 +55,7 @@ from . import picard as PC
 from .basis import cell_points, face_points, tensor_tables
 from .laws import generalized_newtonian
 from .forms import (Problem, _cell_geo, _face_geo, _mu_face, _phys_grad, _sym, _tau, _tau_face, _test_project,
-                    assemble, cell_sizes)
+                    assemble, cell_sizes, penalty_geometry)
 from .mesh import Mesh
 
 # BDF1 coefficients (m = 1)
@@ -439,14 +439,14 @@ def viscous_wall_load(pb: Problem, g_wall) -> np.ndarray:
     walls, mu the problem's viscosity at the face points."""
     mesh, n = pb.mesh, pb.n
     Y = np.zeros((mesh.ncells, 3, n ** 3))
-    h = cell_sizes(pb)
+    sig = penalty_geometry(pb)
     for d in range(3):
         for side in (0, 1):
             bc = mesh.boundary_cells(d, side)
             Vf, Gf = tensor_tables(n, face_points(n, d, side)[0])
             _, xq, Ji, nrm, ds = _face_geo(pb, bc, d, side)
             mu = _mu_face(pb, d, bc, side, xq)
-            tau = _tau(pb, mu, h[bc])
+            tau = _tau(pb, mu, sig[bc])
             g = _wall_g(pb, g_wall, d, side)
             gn = np.einsum("epc,epc->ep", g, nrm)
             a = 2.0 * tau[..., None] * (g + nrm * gn[..., None])

@@ -224,7 +224,7 @@ Layout layout(const sipg_plan* P) {
     const size_t ntau = P->pen ? (size_t)P->ncell : 0;
     const size_t nd = (size_t)P->ndof;
     L.verts64 = take(nv * 8); L.verts32 = take(nv * 4);
-    L.hcell = take((size_t)P->ncell * 8);
+    L.hcell = take((size_t)P->ncell * 16);   // h_e, then the penalty's sigma_e
     L.tfac64 = take((size_t)P->nface * 8); L.tfac32 = take((size_t)P->nface * 4);
     L.mu_cell64 = take(nqc * 8); L.mu_cell32 = take(nqc * 4);
     L.mu_face64 = take(nqf * 8); L.mu_face32 = take(nqf * 4);

@@ -24,12 +24,17 @@ __device__ inline void cell_geo_full(const OpData<double>& op, int e, double geo
     }
 }
 
-// h_e = |cell|^(1/3); the n-point Gauss rule integrates det J of a trilinear
-// cell exactly.
+// Per cell: h_e = |e|^(1/3) into hcell[e], and the penalty's surface-to-volume
+// ratio sigma_e = (sum_f w_f |f|) / |e| into hcell[ncell + e], w_f = 1/2 for a
+// face shared with another cell and 1 on the boundary of the box.  Volume and
+// face areas by the n-point Gauss rules (exact for the volume of a trilinear
+// cell); the area element of face xi_d = s is |a_t1 x a_t2|, the length of
+// the adjugate row d.
 __global__ void k_cell_size(const OpData<double> op, int n, double* hcell) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= op.ncell) return;
-    double vol = 0.0;
+    const int ex = e % op.nx, ey = (e / op.nx) % op.ny, ez = e / (op.nx * op.ny);
+    double vol = 0.0, area[3][2];
     if (op.verts) {
         double geo[8][3];
         cell_geo_full(op, e, geo);
@@ -40,10 +45,37 @@ __global__ void k_cell_size(const OpData<double> op, int n, double* hcell) {
                     jacobian_inverse<double>(geo, op.tab.x[q1], op.tab.x[q2], op.tab.x[q3], Ji, det);
                     vol += det * op.tab.w[q1] * op.tab.w[q2] * op.tab.w[q3];
                 }
+        for (int d = 0; d < 3; ++d) {
+            const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+            for (int s = 0; s < 2; ++s) {
+                double A = 0.0;
+                for (int qb = 0; qb < n; ++qb)
+                    for (int qa = 0; qa < n; ++qa) {
+                        double xi[3];
+                        xi[t1] = op.tab.x[qa];
+                        xi[t2] = op.tab.x[qb];
+                        xi[d] = (double)s;
+                        double Ji[3][3], det;
+                        jacobian_inverse<double>(geo, xi[0], xi[1], xi[2], Ji, det);
+                        // adjugate row d = det * (row d of J^-1)
+                        const double r = det * sqrt(Ji[d][0] * Ji[d][0] + Ji[d][1] * Ji[d][1] + Ji[d][2] * Ji[d][2]);
+                        A += r * op.tab.w[qa] * op.tab.w[qb];
+                    }
+                area[d][s] = A;
+            }
+        }
     } else {
         vol = op.h[0] * op.h[1] * op.h[2];
+        for (int d = 0; d < 3; ++d) area[d][0] = area[d][1] = vol / op.h[d];
+    }
+    double surf = 0.0;
+    const int pos[3] = {ex, ey, ez}, lim[3] = {op.nx, op.ny, op.nz};
+    for (int d = 0; d < 3; ++d) {
+        surf += (pos[d] == 0 ? 1.0 : 0.5) * area[d][0];
+        surf += (pos[d] == lim[d] - 1 ? 1.0 : 0.5) * area[d][1];
     }
     hcell[e] = cbrt(vol);
+    hcell[op.ncell + e] = surf / vol;
 }
 
 // Decode a face id into its direction, the lower ("-") and upper ("+")
@@ -76,16 +108,19 @@ __device__ inline FaceInfo decode_face(const OpData<double>& op, int fid) {
     return f;
 }
 
-// tau factor P (k+1)^2 / h_F, h_F = min(h-, h+) inside, h of the cell on the boundary
+// Penalty factor of a face, P (k+1)^2 sigma_F (the kernels multiply by the
+// viscosity at the face point): sigma_F = max(sigma^-, sigma^+) inside, the
+// cell's own sigma on the boundary.
 __global__ void k_face_penalty(const OpData<double> op, int nface, double pk2, const double* hcell,
                                double* tfac64, float* tfac32) {
     const int fid = blockIdx.x * blockDim.x + threadIdx.x;
     if (fid >= nface) return;
     const FaceInfo f = decode_face(op, fid);
-    double hF;
-    if (f.em >= 0 && f.ep >= 0) hF = fmin(hcell[f.em], hcell[f.ep]);
-    else hF = hcell[f.em >= 0 ? f.em : f.ep];
-    const double t = pk2 / hF;
+    const double* sig = hcell + op.ncell;
+    double sF;
+    if (f.em >= 0 && f.ep >= 0) sF = fmax(sig[f.em], sig[f.ep]);
+    else sF = sig[f.em >= 0 ? f.em : f.ep];
+    const double t = pk2 * sF;
     tfac64[fid] = t;
     tfac32[fid] = (float)t;
 }

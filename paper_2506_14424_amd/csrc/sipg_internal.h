@@ -35,7 +35,7 @@ struct OpData {
     const T* verts;          // curved cells: vertex coordinates, else nullptr
     const T* mu_cell;        // [ncell][n^3]
     const T* mu_face;        // [nface][n^2]
-    const T* tfac;           // [nface] P (k+1)^2 / h_F
+    const T* tfac;           // [nface] P (k+1)^2 sigma_F (penalty per unit viscosity)
     Tables<T> tab;
 };
 
@@ -179,7 +179,7 @@ hipError_t launch_split_projection(int n, const SplitGeo& S, const double* uhat,
 hipError_t launch_split_mass(int n, const SplitGeo& S, const double* x, double scale, double* y, hipStream_t s);
 hipError_t launch_pen_factors(int n, const SplitGeo& S, const double* u, double dt, double zeta, const double* hcell,
                               double* tau_div, double* tau_cont, hipStream_t s);
-// y += load of the wall data S.gw: viscous (pen = 0; mu_face, tfac = P(k+1)^2/h_F
+// y += load of the wall data S.gw: viscous (pen = 0; mu_face, tfac = P(k+1)^2 sigma_F
 // per face) or penalty step (pen = 1; tfac = the face's continuity factor)
 hipError_t launch_wall_load(int n, const SplitGeo& S, const double* mu_face, const double* tfac, int pen, double* y,
                             hipStream_t s);

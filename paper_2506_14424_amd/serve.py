@@ -184,15 +184,17 @@ def _ndof(cfg):
 
 
 def summarize(completed, t_start, t_end, **extra) -> dict:
-    lat = np.array([r.finished - r.arrival for r in completed])
+    good = [r for r in completed if r.info.get("status") == "SIPG_OK"]
+    lat = np.array([r.finished - r.arrival for r in good])
     wait = np.array([r.admitted - r.arrival for r in completed])
     its = np.array([r.info.get("iterations", 0) for r in completed])
-    ok = sum(r.info.get("status") == "SIPG_OK" for r in completed)
     span = max(t_end - t_start, 1e-9)
     pct = lambda a, q: float(np.percentile(a, q)) if len(a) else None
     out = {
-        "requests": len(completed), "converged": int(ok),
-        "solves_per_s": len(completed) / span,
+        # throughput and latency count converged solves only; the others are listed
+        "requests": len(completed), "converged": len(good),
+        "failed": {str(r.id): r.info.get("status") for r in completed if r not in good},
+        "solves_per_s": len(good) / span,
         "latency_p50_s": pct(lat, 50), "latency_p99_s": pct(lat, 99),
         "queue_wait_p50_s": pct(wait, 50), "queue_wait_p99_s": pct(wait, 99),
         "iterations_mean": float(its.mean()) if len(its) else None,

@@ -1,4 +1,4 @@
-"""GPU parity of the penalty-step operator (Sec. 3, "Consistent
+"""GPU parity of the penalty-step operator (Sec. 4.3, "Consistent
 Stabilization", eq. penalty_step) with the oracle: operator parts and whole,
 diagonal, multigrid transfers of the penalty factors through V-cycles, and
 preconditioned solves; full size on sampled cells and by a property that

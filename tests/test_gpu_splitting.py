@@ -292,8 +292,10 @@ def test_full_size_operators_after_updates():
     """At the c8 size, after the viscosity update from the c8 velocity and
     the penalty-factor update from it, the viscous and penalty operators
     applied to a random vector equal the oracle's operators built from the
-    same velocity on an interior 4^3 block, on the block cells whose
-    neighbours all lie in the block."""
+    same velocity on an interior 6^3 block, on the block's central 2^3
+    cells: their neighbours lie in the block and have no face on the block's
+    artificial walls, so the penalty's surface-to-volume ratios of both
+    sides of every face they touch equal the full mesh's."""
     from oracle import picard as PC
     cfg = W.config("c8")
     m, deg, dt, law = cfg["nx"], cfg["degree"], cfg["dt"], cfg["law"]
@@ -305,16 +307,16 @@ def test_full_size_operators_after_updates():
     st.update_penalty_factors(dev(u))
     yv = host(st.vel.apply(dev(x))).reshape(m, m, m, 3, -1)
     yp = host(st.pen.apply(dev(x))).reshape(m, m, m, 3, -1)
-    lo = 10
-    mb = Mesh(4, 4, 4, V.reshape(m + 1, m + 1, m + 1, 3)[lo:lo + 5, lo:lo + 5, lo:lo + 5].reshape(-1, 3))
+    lo = 9
+    mb = Mesh(6, 6, 6, V.reshape(m + 1, m + 1, m + 1, 3)[lo:lo + 7, lo:lo + 7, lo:lo + 7].reshape(-1, 3))
     pbb = Problem(mb, deg, "viscous", 1.0 / dt, 1.0, law)
-    sub = lambda v: v.reshape(m, m, m, 3, -1)[lo:lo + 4, lo:lo + 4, lo:lo + 4].reshape(-1)
+    sub = lambda v: v.reshape(m, m, m, 3, -1)[lo:lo + 6, lo:lo + 6, lo:lo + 6].reshape(-1)
     ub, xb = sub(u), sub(x)
-    rv = oracle_apply(PC.with_velocity_viscosity(pbb, pbb, ub, law), xb).reshape(4, 4, 4, 3, -1)
+    rv = oracle_apply(PC.with_velocity_viscosity(pbb, pbb, ub, law), xb).reshape(6, 6, 6, 3, -1)
     td, tc = SP.penalty_factors(pbb, ub, dt)
-    rp = oracle_apply(Problem(mb, deg, "penalty", 1.0, 1.0, tau_div=td, tau_cont=tc), xb).reshape(4, 4, 4, 3, -1)
-    inner = (slice(lo + 1, lo + 3),) * 3
-    ev, ep = rel(yv[inner], rv[1:3, 1:3, 1:3]), rel(yp[inner], rp[1:3, 1:3, 1:3])
+    rp = oracle_apply(Problem(mb, deg, "penalty", 1.0, 1.0, tau_div=td, tau_cont=tc), xb).reshape(6, 6, 6, 3, -1)
+    inner = (slice(lo + 2, lo + 4),) * 3
+    ev, ep = rel(yv[inner], rv[2:4, 2:4, 2:4]), rel(yp[inner], rp[2:4, 2:4, 2:4])
     say(f"[split operators full size] interior block: viscous {ev:.2e}, penalty {ep:.2e}")
     assert ev <= 1e-12 and ep <= 1e-12
 

@@ -1,4 +1,4 @@
-"""Pins of the oracle's penalty-step operator (Sec. 3, "Consistent
+"""Pins of the oracle's penalty-step operator (Sec. 4.3, "Consistent
 Stabilization", eq. penalty_step): mass + divergence penalty per cell +
 continuity penalty on the normal jump, with the face factor the mean of the
 two cells' values (reading) and the oriented jump u - g on Dirichlet faces.

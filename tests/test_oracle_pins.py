@@ -134,22 +134,67 @@ def test_zero_viscosity_leaves_diagonal_mass_of_domain_volume():
         assert abs(d[:, c].sum() - 4.0) < 1e-12
 
 
+def _indicator_energy(pb, cell, comp=0):
+    u = np.zeros(pb.ndof)
+    n3 = pb.n ** 3
+    u[(cell * pb.C + comp) * n3:(cell * pb.C + comp + 1) * n3] = 1.0
+    return u @ apply(pb, u)
+
+
 @pytest.mark.parametrize("deg", [2, 3])
 def test_penalty_energy_of_cell_indicator(deg):
-    """Piecewise constant on the corner cell of an affine 3^3 mesh: only the
-    penalty survives.  Poisson: 3 interior faces (tau) + 3 Dirichlet faces (2 tau),
-    tau = (k+1)^2 / h, area h^2.  Viscous component c: tau (1 + n_c^2) inside,
-    2 tau (1 + n_c^2) on the boundary, tau = (k+1)^2 mu / h."""
+    """Piecewise constant on one cell of an affine 3^3 mesh (h = 1/3, all
+    Dirichlet): only the penalty survives, tau = (k+1)^2 mu sigma_F on each of
+    the cell's six faces of area h^2 (interior faces tau [q]^2, Dirichlet faces
+    2 tau q^2; viscous component c: (1 + n_c^2) times that).
+    sigma_e with half-weighted interior faces: corner cell (3 boundary faces)
+    4.5/h, centre cell 3/h, a centre cell's face neighbour (1 boundary face)
+    3.5/h, an edge cell's neighbour along the edge 4/h.
+      corner cell: every face takes max(4.5, 4)/h = 4.5/h;
+        Poisson 3 tau h^2 + 3 * 2 tau h^2 = 40.5 (k+1)^2 h,
+        viscous 4 tau h^2 + 8 tau h^2 = 54 (k+1)^2 mu h;
+      centre cell: every face takes the neighbour's 3.5/h (the max; the min
+        or either side's own value would give 3/h on some faces):
+        Poisson 6 tau h^2 = 21 (k+1)^2 h, viscous 8 tau h^2 = 28 (k+1)^2 mu h."""
     N, h = 3, 1.0 / 3
+    k2 = (deg + 1) ** 2
     pbp = Problem(Mesh(N, N, N), deg, "poisson", 0.0, 1.0)
-    u = np.zeros(pbp.ndof); u[: (deg + 1) ** 3] = 1.0
-    assert abs(u @ apply(pbp, u) - 9 * (deg + 1) ** 2 * h) < 1e-12
+    assert abs(_indicator_energy(pbp, 0) - 40.5 * k2 * h) < 1e-12
+    assert abs(_indicator_energy(pbp, 13) - 21.0 * k2 * h) < 1e-12
     mu = 0.3
     pbv = Problem(Mesh(N, N, N), deg, "viscous", 0.0, 1.0, W.const_law(mu))
-    n3 = (deg + 1) ** 3
     for c in range(3):
-        u = np.zeros(pbv.ndof); u[c * n3:(c + 1) * n3] = 1.0
-        assert abs(u @ apply(pbv, u) - 12 * (deg + 1) ** 2 * mu * h) < 1e-12
+        assert abs(_indicator_energy(pbv, 0, c) - 54.0 * k2 * mu * h) < 1e-12
+        assert abs(_indicator_energy(pbv, 13, c) - 28.0 * k2 * mu * h) < 1e-12
+
+
+@pytest.mark.parametrize("a", [0.7, 0.3])
+def test_penalty_takes_the_larger_surface_to_volume_ratio_of_unequal_cells(a):
+    """Two affine cells [0,a]x[0,1]^2 and [a,1]x[0,1]^2 (all Dirichlet).
+    sigma of a cell of width w: (boundary x-face 1 + half the shared face 1/2
+    + four boundary side faces 4w) / w.  An indicator of either cell sees
+    tau_F = (k+1)^2 max(sigma_0, sigma_1) on the shared face and its own
+    sigma on its five boundary faces (area 1 + 4w, factor 2):
+      E_i = (k+1)^2 (max(sigma_0, sigma_1) + 2 sigma_i (1 + 4 w_i)).
+    Both widths are tried so that the narrower (larger-sigma) cell is once
+    the "-" and once the "+" cell: a one-sided choice, the minimum, or a
+    penalty in terms of h_e = |e|^(1/3) all miss one of the four values."""
+    deg = 2
+    k2 = (deg + 1) ** 2
+    V = Mesh(2, 1, 1).vertices.copy()
+    V[:, :, 1, 0] = a
+    pb = Problem(Mesh(2, 1, 1, V.reshape(-1, 3)), deg, "poisson", 0.0, 1.0)
+    w = np.array([a, 1.0 - a])
+    sig = (1.5 + 4 * w) / w
+    for i in range(2):
+        ref = k2 * (sig.max() + 2 * sig[i] * (1 + 4 * w[i]))
+        assert abs(_indicator_energy(pb, i) - ref) < 1e-11 * ref
+    # the alternatives differ from the pinned values by far more than the tolerance
+    for i in range(2):
+        ref = k2 * (sig.max() + 2 * sig[i] * (1 + 4 * w[i]))
+        for alt in (sig.min(), sig[0], sig[1]):
+            if alt != sig.max():
+                assert abs(k2 * (alt + 2 * sig[i] * (1 + 4 * w[i])) - ref) > 1e-3 * ref
 
 
 def test_constant_viscosity_reduces_to_laplacian():
@@ -276,7 +321,7 @@ def test_poisson_patch_test_on_curved_cells():
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("deg,Ns,curved", [(2, (2, 3, 4), False), (3, (2, 3), False), (2, (3, 4), True)])
+@pytest.mark.parametrize("deg,Ns,curved", [(2, (3, 4), False), (3, (3, 4), False), (2, (3, 4), True)])
 def test_viscous_converges_at_order_k_plus_1(deg, Ns, curved):
     """Sec. 6.1 reports optimal k+1 L2 convergence; here for the viscous
     operator alone with the smooth viscosity 1 + 0.5 sin sin sin."""
@@ -296,18 +341,18 @@ def test_viscous_converges_at_order_k_plus_1(deg, Ns, curved):
         e, r = l2_error(pb, sol, _vec_fn(u))
         errs.append(e / r)
     rates = [np.log(errs[i] / errs[i + 1]) / np.log(Ns[i + 1] / Ns[i]) for i in range(len(Ns) - 1)]
-    assert abs(rates[-1] - (deg + 1)) < 0.6, rates
+    assert abs(rates[-1] - (deg + 1)) < 0.3, rates
 
 
-def test_bruteforce_entries_affine_two_cells():
-    """Recompute entries of the Poisson and viscous matrices on two affine cells
-    with an independent construction: 1D basis from numpy's polynomial fit
-    through the Legendre roots, physical coordinates directly (J = h I), a
+def test_bruteforce_poisson_entries_affine_two_cells():
+    """Recompute entries of the Poisson matrix on two affine cells with an
+    independent construction: 1D basis from numpy's polynomial fit through
+    the Legendre roots, physical coordinates directly (J = h I), a
     (k+3)-point rule (integrands are polynomials, both rules are exact), and
-    faces enumerated by hand."""
+    faces enumerated by hand.  (The viscous form is recomputed on curved
+    cells with variable viscosity by the test below.)"""
     deg, hx = 2, 0.5
     n = deg + 1
-    mu = 1.3
     roots = (np.polynomial.legendre.legroots([0] * n + [1]) + 1) / 2
     polys = [np.polynomial.Polynomial.fit(roots, np.eye(n)[j], n - 1).convert() for j in range(n)]
     dpolys = [p.deriv() for p in polys]
@@ -343,8 +388,9 @@ def test_bruteforce_entries_affine_two_cells():
         Q = P.copy(); Q[:, d] += (-1e-13 if s == 1 else 1e-13)
         return Q
 
-    h_e = (0.5 * 1 * 1) ** (1 / 3)
-    tau_p = (deg + 1) ** 2 / h_e
+    # sigma of each 0.5 x 1 x 1 cell: (x wall 1 + half the shared face 1/2 + four side walls 0.5) / 0.5
+    sigma = (1.0 + 0.5 + 4 * 0.5) / 0.5
+    tau_p = (deg + 1) ** 2 * sigma
     # face list: (plane coordinate, direction, normal sign for the owning cell, owner, neighbour or None)
     faces = [(0.0, 0, -1, 0, None), (0.5, 0, +1, 0, 1), (1.0, 0, +1, 1, None)]
     for cell in (0, 1):
@@ -386,6 +432,181 @@ def test_bruteforce_entries_affine_two_cells():
         ref = poisson_entry(I, J)
         # the 1e-13 nudge that picks a side of a face costs ~1e-12 in the traces
         assert abs(A[idx(*I), idx(*J)] - ref) <= 1e-10 * np.abs(A).max(), (I, J)
+
+
+class _NaiveCells:
+    """A second, deliberately plain construction of the viscous form for a
+    pins test: its own 1D Lagrange basis (numpy polynomial fit through the
+    Legendre roots), its own trilinear map written out vertex by vertex,
+    physical points looped one at a time, face normals and area elements from
+    the cross product of the two tangent vectors, and the "+" side's
+    reference point of a face point found by Newton's method on that cell's
+    map (no assumption that the two cells share face coordinates)."""
+
+    def __init__(self, V, nx, deg, alpha, mu_fn):
+        self.V = V                      # (2, 2, nx + 1, 3): vertices (k, j, i)
+        self.nx, self.n, self.alpha, self.mu = nx, deg + 1, alpha, mu_fn
+        n = self.n
+        roots = (np.polynomial.legendre.legroots([0] * n + [1]) + 1) / 2
+        self.p = [np.polynomial.Polynomial.fit(roots, np.eye(n)[j], n - 1).convert() for j in range(n)]
+        self.dp = [q.deriv() for q in self.p]
+        g, w = np.polynomial.legendre.leggauss(n)
+        self.g, self.w = (g + 1) / 2, w / 2
+        self.k2 = (deg + 1) ** 2
+        self.sigma = [self._sigma(e) for e in range(nx)]
+
+    def map(self, e, xi):
+        x, J = np.zeros(3), np.zeros((3, 3))
+        for a in (0, 1):
+            for b in (0, 1):
+                for c in (0, 1):
+                    X = self.V[c, b, e + a]
+                    L = [1 - xi[0] if a == 0 else xi[0], 1 - xi[1] if b == 0 else xi[1],
+                         1 - xi[2] if c == 0 else xi[2]]
+                    dL = [-1.0 if a == 0 else 1.0, -1.0 if b == 0 else 1.0, -1.0 if c == 0 else 1.0]
+                    x += X * L[0] * L[1] * L[2]
+                    J[:, 0] += X * dL[0] * L[1] * L[2]
+                    J[:, 1] += X * L[0] * dL[1] * L[2]
+                    J[:, 2] += X * L[0] * L[1] * dL[2]
+        return x, J
+
+    def inverse_map(self, e, P):
+        xi = np.full(3, 0.5)
+        for _ in range(50):
+            x, J = self.map(e, xi)
+            step = np.linalg.solve(J, x - P)
+            xi = xi - step
+            if np.abs(step).max() < 1e-16:
+                break
+        return xi
+
+    def face_point(self, e, d, side, qa, qb):
+        """Physical point, outward unit normal and area weight of face point (qa, qb)."""
+        t1, t2 = (d + 1) % 3, (d + 2) % 3
+        xi = np.zeros(3); xi[d] = side; xi[t1] = self.g[qa]; xi[t2] = self.g[qb]
+        x, J = self.map(e, xi)
+        c = np.cross(J[:, t1], J[:, t2])       # along +xi_d for the cyclic tangent order
+        area = np.linalg.norm(c)
+        return x, (1.0 if side == 1 else -1.0) * c / area, area * self.w[qa] * self.w[qb]
+
+    def _sigma(self, e):
+        vol = 0.0
+        for q in np.ndindex(self.n, self.n, self.n):
+            vol += np.linalg.det(self.map(e, self.g[list(q)])[1]) * np.prod(self.w[list(q)])
+        surf = 0.0
+        for d in range(3):
+            for side in (0, 1):
+                inner = d == 0 and ((side == 1 and e < self.nx - 1) or (side == 0 and e > 0))
+                A = sum(self.face_point(e, d, side, qa, qb)[2] for qa in range(self.n) for qb in range(self.n))
+                surf += (0.5 if inner else 1.0) * A
+        return surf / vol
+
+    def basis(self, I, e, xi, J):
+        """Value (3,) and gradient (3, 3) [component, direction] of the vector
+        basis function I = (cell, component, (i1, i2, i3)) inside cell e."""
+        cell, comp, (i1, i2, i3) = I
+        val, grad = np.zeros(3), np.zeros((3, 3))
+        if cell != e:
+            return val, grad
+        v = [self.p[i](t) for i, t in zip((i1, i2, i3), xi)]
+        dv = [self.dp[i](t) for i, t in zip((i1, i2, i3), xi)]
+        ref = np.array([dv[0] * v[1] * v[2], v[0] * dv[1] * v[2], v[0] * v[1] * dv[2]])
+        val[comp] = v[0] * v[1] * v[2]
+        grad[comp] = np.linalg.solve(J.T, ref)
+        return val, grad
+
+    def entry(self, I, Jt):
+        """(cell, interior-face, boundary-face) parts of a(phi_I, phi_J)."""
+        eps = lambda G: 0.5 * (G + G.T)
+        cellp = intp = bndp = 0.0
+        for e in {I[0], Jt[0]}:
+            for q in np.ndindex(self.n, self.n, self.n):
+                xi = self.g[list(q)]
+                x, J = self.map(e, xi)
+                wq = np.linalg.det(J) * np.prod(self.w[list(q)])
+                v, Gv = self.basis(I, e, xi, J)
+                u, Gu = self.basis(Jt, e, xi, J)
+                cellp += wq * (self.alpha * v @ u + 2 * self.mu(x) * np.sum(eps(Gv) * eps(Gu)))
+        for e in range(self.nx):
+            for d in range(3):
+                for side in (0, 1):
+                    nb = e + 1 if (d == 0 and side == 1 and e < self.nx - 1) else None
+                    if d == 0 and side == 0 and e > 0:
+                        continue                   # counted from the "-" cell
+                    if e not in (I[0], Jt[0]) and nb not in (I[0], Jt[0]):
+                        continue
+                    for qa in range(self.n):
+                        for qb in range(self.n):
+                            x, nrm, ds = self.face_point(e, d, side, qa, qb)
+                            mu = self.mu(x)
+                            xm = self.inverse_map(e, x)
+                            Jm = self.map(e, xm)[1]
+                            vm, Gvm = self.basis(I, e, xm, Jm)
+                            um, Gum = self.basis(Jt, e, xm, Jm)
+                            if nb is None:       # Dirichlet wall, mirror principle
+                                tau = self.k2 * mu * self.sigma[e]
+                                bndp += ds * (-2 * mu * np.sum(eps(Gvm) * np.outer(um, nrm))
+                                              - 2 * mu * np.sum(eps(Gum) * np.outer(vm, nrm))
+                                              + 2 * tau * (vm @ um + (vm @ nrm) * (um @ nrm)))
+                                continue
+                            xp = self.inverse_map(nb, x)
+                            Jp = self.map(nb, xp)[1]
+                            vp, Gvp = self.basis(I, nb, xp, Jp)
+                            up, Gup = self.basis(Jt, nb, xp, Jp)
+                            tau = self.k2 * mu * max(self.sigma[e], self.sigma[nb])
+                            jv, ju = vm - vp, um - up
+                            av = 0.5 * mu * (eps(Gvm) + eps(Gvp))
+                            au = 0.5 * mu * (eps(Gum) + eps(Gup))
+                            intp += ds * (-2 * np.sum(av * np.outer(ju, nrm)) - 2 * np.sum(au * np.outer(jv, nrm))
+                                          + tau * (jv @ ju + (jv @ nrm) * (ju @ nrm)))
+        return cellp, intp, bndp
+
+
+@pytest.mark.parametrize("deg", [2, 3])
+def test_bruteforce_viscous_entries_curved_cells_variable_viscosity(deg):
+    """Entries of the viscous matrix (cell terms, the interior face, Dirichlet
+    mirror faces) on two trilinear cells with randomly moved vertices and the
+    viscosity 1 + 0.5 sin 2pi x sin 2pi y sin 2pi z, recomputed by the plain
+    construction above with the same n-point Gauss rules, part by part."""
+    rng = np.random.default_rng(12 + deg)
+    V = Mesh(2, 1, 1).vertices.copy()
+    V += rng.uniform(-0.08, 0.08, V.shape)
+    alpha = 4.0
+    mu_fn = lambda x: 1 + 0.5 * np.sin(2 * np.pi * x[0]) * np.sin(2 * np.pi * x[1]) * np.sin(2 * np.pi * x[2])
+    pb = Problem(Mesh(2, 1, 1, V.reshape(-1, 3)), deg, "viscous", alpha, 1.0, W.sine_law(1.0, 0.5))
+    parts = [assemble(pb, (p,)).toarray() for p in ("cell", "interior", "boundary")]
+    scale = np.abs(sum(parts)).max()
+    bf = _NaiveCells(V, 2, deg, alpha, mu_fn)
+    n = deg + 1
+    idx = lambda I: (I[0] * 3 + I[1]) * n ** 3 + I[2][2] * n * n + I[2][1] * n + I[2][0]
+    draw = lambda: (int(rng.integers(2)), int(rng.integers(3)), tuple(int(v) for v in rng.integers(0, n, 3)))
+    pairs = [(draw(), draw()) for _ in range(14)]
+    # pairs across the interior face, and a node pair on a wall of the same cell
+    pairs += [((0, 0, (n - 1, 1, 0)), (1, 2, (0, 1, n - 1))), ((1, 1, (0, 0, 0)), (0, 1, (n - 1, 0, 0))),
+              ((0, 2, (0, 0, 0)), (0, 0, (0, 1, 0)))]
+    for I, J in pairs:
+        ref = bf.entry(I, J)
+        for got, want in zip((P[idx(I), idx(J)] for P in parts), ref):
+            assert abs(got - want) <= 1e-13 * scale, (I, J, got, want)
+
+
+def test_sampled_cell_apply_equals_rows_of_full_apply():
+    """apply(pb, x, cells=S) returns the rows of the full apply for the cells
+    in S (and zero elsewhere) on a curved 4^3 mesh with mixed boundary
+    conditions, for a corner, an edge, a face and an interior cell, every part
+    and the viscous and Poisson operators."""
+    Vt = W.box_vertices(4, 4, 4, 0.1)
+    bc = ("D", "N", "D", "D", "N", "D")
+    S = np.array([0, 2, 5, 21, 63])         # corner, edge, face, interior, corner
+    for op, law in (("viscous", W.logfield_law(3, 1e2)), ("poisson", W.const_law(1.0))):
+        pb = Problem(Mesh(4, 4, 4, Vt, bc), 2, op, 3.0, 1.0, law)
+        x = np.random.default_rng(5).uniform(-1, 1, pb.ndof)
+        for parts in (("cell", "interior", "boundary"), ("cell",), ("interior",), ("boundary",)):
+            full = apply(pb, x, parts).reshape(64, -1)
+            part = apply(pb, x, parts, cells=S).reshape(64, -1)
+            assert np.abs(part[S] - full[S]).max() <= 1e-14 * np.abs(full).max()
+            others = np.setdiff1d(np.arange(64), S)
+            assert not np.any(part[others])
 
 
 def test_oracle_modes_agree():
@@ -497,18 +718,20 @@ def test_neumann_poisson_solve_is_mean_zero():
 
 
 @pytest.mark.slow
-def test_pointwise_viscosity_can_make_the_operator_indefinite():
-    """Sec. 4.1 notes that the pointwise viscosity update does not by itself
-    guarantee a positive operator.  With the penalty tau = (k+1)^2 mu(x)/h at
-    each face point, a 3^3 mesh with a viscosity contrast of 1e4 across the
-    unit cube has negative eigenvalues, while the same mesh with contrast 10
-    stays positive definite."""
+def test_high_contrast_request_is_positive_definite():
+    """Sec. 4.1 remarks that the pointwise viscosity does not by itself make
+    the operator positive.  A 3^3, k = 3 request of the serving stream with a
+    viscosity contrast of 1e4 across the unit cube is positive definite with
+    the surface-to-volume penalty (3.5-4.5 (k+1)^2 mu / h on this mesh); with
+    a quarter of it (about the plain (k+1)^2 mu / h scaling) the matrix has
+    negative eigenvalues."""
     cfg = W.serving_requests(seed=11, count=12, rate=200.0, nmin=2, nmax=6)[3]["cfg"]
     assert (cfg["nx"], cfg["degree"], cfg["law"]["contrast"]) == (3, 3, 1e4)
 
-    def lam_min(contrast):
-        law = dict(cfg["law"], contrast=contrast)
-        pb = Problem(Mesh(3, 3, 3), 3, "viscous", cfg["alpha"], 1.0, law)
-        return np.linalg.eigvalsh(assemble(pb).toarray())[0]
-    assert lam_min(1e4) < 0.0
-    assert lam_min(10.0) > 0.0
+    def lam_min(P):
+        pb = Problem(Mesh(3, 3, 3), 3, "viscous", cfg["alpha"], P, cfg["law"])
+        A = assemble(pb)
+        d = 1.0 / np.sqrt(A.diagonal())
+        return np.linalg.eigvalsh((A.multiply(np.outer(d, d))).toarray())[0]
+    assert lam_min(1.0) > 0.0
+    assert lam_min(0.25) < 0.0

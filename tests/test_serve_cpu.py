@@ -83,7 +83,8 @@ def test_oversized_request_is_rejected_and_others_proceed():
     out = Server(ex, hbm_budget=1000).run(reqs, clock=clk, sleep=clk.sleep)
     st = {r.id: r.info["status"] for r in reqs}
     assert st == {0: "SIPG_OK", 1: "SIPG_ERR_OOM", 2: "SIPG_OK"}
-    assert out["converged"] == 2
+    assert out["converged"] == 2 and out["failed"] == {"1": "SIPG_ERR_OOM"}
+    assert out["solves_per_s"] == 2 / out["span_s"]     # only converged solves count
 
 
 def test_failing_request_is_isolated():
@@ -94,6 +95,7 @@ def test_failing_request_is_isolated():
     assert reqs[1].info["status"].startswith("failed")
     assert reqs[0].info["status"] == reqs[2].info["status"] == "SIPG_OK"
     assert ex.live_bytes == 0 and out["requests"] == 3
+    assert list(out["failed"]) == ["1"] and out["converged"] == 2
 
 
 def test_latency_accounts_for_arrival_times():
