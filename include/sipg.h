@@ -358,6 +358,23 @@ sipg_status sipg_picard_solve(sipg_plan* plan, const double* b, double* x, void*
                               const sipg_solve_opts* lin_opts, const sipg_picard_opts* opts,
                               sipg_picard_info* info, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * Picard iteration as sipg_picard_solve, with its work area (three vectors
+ * and the reduction partials) in a static device array of the library
+ * instead of a caller buffer.  The array holds SIPG_PICARD_NOALLOC_MAX_DOF
+ * unknowns (48 MiB), one copy per GPU the library runs on, kept until the
+ * process ends; the call allocates no device memory.  Plans with more
+ * unknowns, and lin_opts->use_graph != 0 (graph instantiation allocates),
+ * are refused with SIPG_ERR_INVALID before any work.  Every call on one GPU
+ * uses the same array: calls that overlap in time on one GPU (other host
+ * threads, other streams) race, and the caller must serialise them.
+ * Arguments and results as sipg_picard_solve without `work`. */
+#define SIPG_PICARD_NOALLOC_MAX_DOF 2097152
+sipg_status sipg_picard_solve_noalloc(sipg_plan* plan, const double* b, double* x,
+                                      const sipg_solve_opts* lin_opts, const sipg_picard_opts* opts,
+                                      sipg_picard_info* info, void* stream);
+
 /* ---------------------------------------------------------------------
  * One time step of the dual splitting scheme (Sec. 3 "Splitting Scheme";
  * the weak forms of Sec. 4.1: eqs. convective_step_weak,

@@ -64,6 +64,7 @@ class MgOpts(C.Structure):
 
 
 PICARD_HISTORY = 64
+PICARD_NOALLOC_MAX_DOF = 2097152   # SIPG_PICARD_NOALLOC_MAX_DOF
 
 
 class PicardOpts(C.Structure):
@@ -129,6 +130,7 @@ def _load():
         "sipg_picard_opts_default": (None, [C.POINTER(PicardOpts)]),
         "sipg_picard_work_bytes": (C.c_size_t, [P]),
         "sipg_picard_solve": (st, [P, P, P, P, C.POINTER(SolveOpts), C.POINTER(PicardOpts), C.POINTER(PicardInfo), P]),
+        "sipg_picard_solve_noalloc": (st, [P, P, P, C.POINTER(SolveOpts), C.POINTER(PicardOpts), C.POINTER(PicardInfo), P]),
         "sipg_convective_step": (st, [P, P, P, P, P, C.c_double, P, P]),
         "sipg_pressure_rhs": (st, [P, P, P, P, P, P, P, C.c_double, P, P]),
         "sipg_wall_load": (st, [P, P, P, P]),

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1227,8 +1228,15 @@ sipg_status sipg_update_viscosity(sipg_plan* P, const double* u, void* stream) {
     return update_viscosity(P, u, static_cast<hipStream_t>(stream));
 }
 
-sipg_status sipg_picard_solve(sipg_plan* P, const double* b, double* x, void* work, const sipg_solve_opts* lin_opts,
-                              const sipg_picard_opts* opts, sipg_picard_info* info, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// The Picard iteration on a work area of sipg_picard_work_bytes(P) bytes
+// (three vectors and the reduction partials; nothing in it has to start at
+// zero: every value is written before it is read).
+sipg_status picard_run(sipg_plan* P, const double* b, double* x, void* work, const sipg_solve_opts* lin_opts,
+                       const sipg_picard_opts* opts, sipg_picard_info* info, void* stream) {
     if (!valid_plan(P) || !b || !x || !work) return fail(SIPG_ERR_INVALID, "null argument");
     if (!P->bound || !P->with_solver) return fail(SIPG_ERR_STATE, "plan not bound with solver workspace");
     if (P->op != SIPG_VISCOUS || P->law.kind != SIPG_LAW_CARREAU)
@@ -1315,6 +1323,62 @@ sipg_status sipg_picard_solve(sipg_plan* P, const double* b, double* x, void* wo
     return fail((sipg_status)inf.status, inf.status == SIPG_ERR_NOT_CONVERGED
                                              ? "Picard iteration did not reach the tolerance"
                                              : "Picard iteration stopped: linear solve failed or residual not finite");
+}
+
+}  // namespace
+
+// Work area of sipg_picard_solve_noalloc: a static device array, one copy per
+// GPU, held until the process ends.  Host code must not use its name as an
+// address (that is a host-side stand-in); the device address comes from
+// hipGetSymbolAddress, once per device, and is kept in g_scratch_ptr.
+constexpr size_t kScratchBytes = (3 * (size_t)SIPG_PICARD_NOALLOC_MAX_DOF + 3 * kPicardBlocks + 8) * sizeof(double);
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the first
+// call on that device).
+sipg_status scratch_address(void** out) {
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(SIPG_ERR_UNSUPPORTED, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(SIPG_ERR_HIP, "hipGetSymbolAddress returned a null address");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return SIPG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sipg_status sipg_picard_solve(sipg_plan* P, const double* b, double* x, void* work, const sipg_solve_opts* lin_opts,
+                              const sipg_picard_opts* opts, sipg_picard_info* info, void* stream) {
+    return picard_run(P, b, x, work, lin_opts, opts, info, stream);
+}
+
+sipg_status sipg_picard_solve_noalloc(sipg_plan* P, const double* b, double* x, const sipg_solve_opts* lin_opts,
+                                      const sipg_picard_opts* opts, sipg_picard_info* info, void* stream) {
+    if (!valid_plan(P) || !b || !x) return fail(SIPG_ERR_INVALID, "null argument");
+    if (P->ndof > SIPG_PICARD_NOALLOC_MAX_DOF || sipg_picard_work_bytes(P) > kScratchBytes)
+        return fail(SIPG_ERR_INVALID, "sipg_picard_solve_noalloc: the plan has " + std::to_string(P->ndof) +
+                                          " unknowns, more than the static work area holds (" +
+                                          std::to_string((long long)SIPG_PICARD_NOALLOC_MAX_DOF) + ")");
+    if (lin_opts && lin_opts->use_graph)
+        return fail(SIPG_ERR_INVALID, "sipg_picard_solve_noalloc: use_graph would instantiate graphs (allocation)");
+    void* work = nullptr;
+    const sipg_status rc = scratch_address(&work);
+    if (rc != SIPG_OK) return rc;
+    return picard_run(P, b, x, work, lin_opts, opts, info, stream);
 }
 
 // ------------------------------------------------------------ dual splitting step

@@ -279,8 +279,6 @@ class Operator:
         self._check_vec(b)
         if b.dtype != torch.float64:
             raise TypeError("picard_solve takes FP64 vectors")
-        x = torch.zeros_like(b) if x is None else x
-        self._check_vec(x)
         nbytes = self.picard_work_bytes()
         if work is None:
             work = torch.empty(nbytes + 256, dtype=torch.uint8, device=b.device)
@@ -288,13 +286,37 @@ class Operator:
         off = (-ptr) % 256
         if work.numel() - off < nbytes:
             raise ValueError(f"work needs {nbytes} bytes after 256-byte alignment")
+        return self._picard(b, x, opts, rel_tol, abs_tol, max_iter, aitken, ptr + off, stream, raise_on_error)
+
+    def picard_solve_noalloc(self, b, x=None, opts: SolveOptions | None = None, rel_tol: float = 1e-8,
+                             abs_tol: float = 0.0, max_iter: int = 50, aitken: bool = True, stream=None,
+                             raise_on_error=True):
+        """picard_solve with the work area in the library's static device
+        array (sipg_picard_solve_noalloc: no device allocation by the call;
+        at most PICARD_NOALLOC_MAX_DOF unknowns; calls overlapping on one
+        GPU race)."""
+        import torch
+        self._check_vec(b)
+        if b.dtype != torch.float64:
+            raise TypeError("picard_solve_noalloc takes FP64 vectors")
+        return self._picard(b, x, opts, rel_tol, abs_tol, max_iter, aitken, None, stream, raise_on_error)
+
+    def _picard(self, b, x, opts, rel_tol, abs_tol, max_iter, aitken, work_ptr, stream, raise_on_error):
+        import torch
+        x = torch.zeros_like(b) if x is None else x
+        self._check_vec(x)
         po = F.PicardOpts()
         po.rel_tol, po.abs_tol, po.max_iter, po.aitken = rel_tol, abs_tol, max_iter, int(aitken)
         lo = (opts or SolveOptions(rel_tol=1e-3)).to_c()
         info = F.PicardInfo()
-        rc = lib.sipg_picard_solve(self._h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()),
-                                   C.c_void_p(ptr + off), C.byref(lo), C.byref(po), C.byref(info),
-                                   C.c_void_p(_stream_handle(stream)))
+        if work_ptr is None:
+            rc = lib.sipg_picard_solve_noalloc(self._h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()),
+                                               C.byref(lo), C.byref(po), C.byref(info),
+                                               C.c_void_p(_stream_handle(stream)))
+        else:
+            rc = lib.sipg_picard_solve(self._h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()),
+                                       C.c_void_p(work_ptr), C.byref(lo), C.byref(po), C.byref(info),
+                                       C.c_void_p(_stream_handle(stream)))
         if rc != 0 and raise_on_error:
             check(rc)
         k = info.recorded
