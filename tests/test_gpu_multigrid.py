@@ -77,18 +77,29 @@ def test_vcycle_matches_oracle(case):
     ref = H.vcycle(r)
     err = float(np.linalg.norm(z - ref) / np.linalg.norm(ref))
     print(f"[mg] {case}: V-cycle rel. diff {err:.2e}", flush=True)
-    assert err <= 1e-8
+    assert err <= 1e-12
     # the one-level Chebyshev-Jacobi preconditioner through the same entry point
     zc = op.precondition(torch.from_numpy(r).cuda(),
                          opts=SolveOptions(precond_precision="f64", cheb_degree=5)).cpu().numpy()
     dinv = H.dinv[0]
     lam = lanczos_max(lambda v: oracle_apply(pb, v), dinv)
     refc = chebyshev_jacobi(lambda v: oracle_apply(pb, v), dinv, r, 5, 1.2 * lam, 1.2 * lam / 20)
-    assert float(np.linalg.norm(zc - refc) / np.linalg.norm(refc)) <= 1e-8
+    errc = float(np.linalg.norm(zc - refc) / np.linalg.norm(refc))
+    # the same one-level polynomial with the operator applied in FP32 (the
+    # mixed-precision preconditioner as the solves use it)
+    zc32 = op.precondition(torch.from_numpy(r).cuda(),
+                           opts=SolveOptions(precond_precision="f32", cheb_degree=5)).cpu().numpy()
+    errc32 = float(np.linalg.norm(zc32 - refc) / np.linalg.norm(refc))
+    errc32m = float(np.abs(zc32 - refc).max() / np.abs(refc).max())
     # FP32 V-cycle: the same operator up to single-precision rounding
     z32 = op.precondition(torch.from_numpy(r).cuda(), opts=SolveOptions(
         precond_precision="f32", cheb_degree=3, precond="multigrid")).cpu().numpy()
-    assert float(np.linalg.norm(z32 - ref) / np.linalg.norm(ref)) <= 1e-4
+    err32 = float(np.linalg.norm(z32 - ref) / np.linalg.norm(ref))
+    print(f"[mg] {case}: one-level FP64 {errc:.2e}, one-level FP32 {errc32:.2e} (max {errc32m:.2e}), "
+          f"V-cycle FP32 {err32:.2e}", flush=True)
+    assert errc <= 1e-12
+    assert errc32 <= 1e-5 and errc32m <= 1e-5
+    assert err32 <= 1e-4
 
 
 def test_multigrid_solve_matches_oracle_solver():

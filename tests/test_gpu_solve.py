@@ -50,7 +50,7 @@ def test_c1_solve_matches_oracle_solver(prec):
     assert info["status"] == "SIPG_OK"
     assert rel <= 1.5e-10
     xo, io = solvers.solve(lambda v: A @ v, A.diagonal(), b, tol=1e-10)
-    say(f"   oracle: {io}")
+    say(f"   oracle: {io}; lambda rel. diff {abs(info['lambda_max'] - io['lambda_max']) / io['lambda_max']:.2e}")
     assert abs(info["lambda_max"] - io["lambda_max"]) <= 1e-9 * io["lambda_max"]
     if prec == "f64":
         assert abs(info["iterations"] - io["iterations"]) <= 2
