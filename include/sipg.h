@@ -164,13 +164,25 @@ typedef enum { SIPG_PRECOND_CHEBYSHEV = 0, SIPG_PRECOND_MULTIGRID = 1 } sipg_pre
  * every level evaluates the viscosity law at its own quadrature points and
  * has its own inverse diagonal and eigenvalue estimate.  Smoothing:
  * opts->cheb_degree Chebyshev-Jacobi steps before and after the coarse
- * correction; the coarsest level gets one Chebyshev-Jacobi polynomial of
- * degree coarse_degree (in place of the paper's AMG cycles). */
+ * correction.
+ * continuous = 1 (default; the paper's cph-multigrid): only the finest level
+ * is smoothed in the DG space; below it come continuous levels Q_k, ...,
+ * Q_1 on the plan's mesh and Q_1 on the coarser meshes (nodal at the
+ * Gauss-Lobatto points, embedded in the DG level of the same degree and mesh,
+ * operator G^T A G of that level's cell and boundary terms, Chebyshev-Jacobi
+ * smoothing on each), and the coarsest continuous level is solved by an FP64
+ * dense inverse when it is of degree 1 with at most direct_max unknowns,
+ * else approximated by one Chebyshev-Jacobi polynomial of degree
+ * coarse_degree.  continuous = 0: the levels stay discontinuous and the
+ * coarsest level gets the degree-coarse_degree polynomial (in place of the
+ * paper's AMG cycles). */
 typedef struct {
     int32_t coarse_degree;     /* 1..63 */
     int32_t min_cells;         /* >= 1 */
     int32_t max_levels;        /* >= 1, including the finest */
     int32_t h_coarsen;         /* 0: degree lowering only */
+    int32_t continuous;        /* 1: cph hierarchy (default), 0: all levels DG */
+    int32_t direct_max;        /* 0..2048: largest coarsest level solved directly (default 1024) */
 } sipg_mg_opts;
 
 typedef struct {
@@ -252,7 +264,7 @@ void sipg_solve_opts_default(sipg_solve_opts* opts);
 sipg_status sipg_solve(sipg_plan* plan, const double* b, double* x, const sipg_solve_opts* opts,
                        sipg_solve_info* info, void* stream);
 
-void sipg_mg_opts_default(sipg_mg_opts* opts);   /* 12, 2, 16, 1 */
+void sipg_mg_opts_default(sipg_mg_opts* opts);   /* 12, 2, 16, 1, 1, 1024 */
 
 /* Builds the multigrid hierarchy of a plan (host only).  Must be called
  * before sipg_plan_workspace_bytes / sipg_plan_bind: the coarse levels' data

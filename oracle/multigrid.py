@@ -167,8 +167,9 @@ class Hierarchy:
 #   coarsest is solved directly in FP64 when it has at most `direct_max`
 #   unknowns (for the pure-Neumann Poisson problem with the operator plus
 #   mean(diag) 1 1^T / n, whose inverse is the pseudo-inverse on mean-zero
-#   vectors), else approximated by the Chebyshev-Jacobi polynomial of degree
-#   `coarse_degree`.
+#   vectors) when it is of degree 1 (the hierarchy reaches degree 1 unless
+#   `max_levels` cuts it short) and has at most `direct_max` unknowns, else
+#   approximated by the Chebyshev-Jacobi polynomial of degree `coarse_degree`.
 
 def gll_points(j: int) -> np.ndarray:
     """The j + 1 Gauss-Lobatto-Legendre points of [0, 1]: the end points and
@@ -275,7 +276,7 @@ class CphHierarchy:
         self.lam = [lanczos_max(lambda v, A=A: A @ v, d, lanczos_steps, seed) for A, d in zip(self.A, self.dinv)]
         self.interval = [(safety * l, safety * l / ratio) for l in self.lam]
         Ac = self.A[-1]
-        self.direct = Ac.shape[0] <= direct_max
+        self.direct = self.carriers[-1].degree == 1 and Ac.shape[0] <= direct_max
         if self.direct:
             M = Ac.toarray()
             if _mean_zero(pb):

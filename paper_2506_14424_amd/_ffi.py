@@ -60,7 +60,7 @@ class SolveOpts(C.Structure):
 
 class MgOpts(C.Structure):
     _fields_ = [("coarse_degree", C.c_int32), ("min_cells", C.c_int32), ("max_levels", C.c_int32),
-                ("h_coarsen", C.c_int32)]
+                ("h_coarsen", C.c_int32), ("continuous", C.c_int32), ("direct_max", C.c_int32)]
 
 
 PICARD_HISTORY = 64

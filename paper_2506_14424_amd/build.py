@@ -16,7 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsipg.so")
-SOURCES = ["apply.hip", "apply_penalty.hip", "api.hip", "setup.hip", "solver.hip", "multigrid.hip", "picard.hip", "splitting.hip"]
+SOURCES = ["apply.hip", "apply_penalty.hip", "api.hip", "setup.hip", "solver.hip", "multigrid.hip", "picard.hip",
+           "splitting.hip", "continuous.hip"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 FLAGS = [

@@ -105,6 +105,106 @@ inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 enum Phase { PH_IDLE = 0, PH_RUNNING, PH_CHECKING, PH_DONE };
 
+// Gauss-Lobatto points of degree j on [0, 1] (j + 1 points, ascending): the
+// end points and the roots of P_j', by Newton's method from the
+// Chebyshev-Lobatto points (P_j and P_j' from the three-term recurrence,
+// P_j'' = (2 z P_j' - j (j + 1) P_j) / (1 - z^2)).
+void gll01(int j, double* x) {
+    x[0] = 0.0;
+    x[j] = 1.0;
+    for (int i = 1; i < j; ++i) {
+        double z = -std::cos(M_PI * i / j);
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= j; ++k) {
+                const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            const double d1 = j * (z * p1 - p0) / (z * z - 1.0);           // P_j'
+            const double d2 = (2.0 * z * d1 - j * (j + 1.0) * p1) / (1.0 - z * z);
+            const double dz = d1 / d2;
+            z -= dz;
+            if (std::fabs(dz) < 1e-17) break;
+        }
+        x[i] = 0.5 * (1.0 + z);
+    }
+}
+
+// Lagrange basis through nodes[0..m-1] at t: values and derivatives.
+void lagrange_vd(const double* nodes, int m, double t, double* val, double* der) {
+    for (int a = 0; a < m; ++a) {
+        double v = 1.0, d = 0.0;
+        for (int k = 0; k < m; ++k) {
+            if (k == a) continue;
+            double term = 1.0 / (nodes[a] - nodes[k]);
+            for (int l = 0; l < m; ++l)
+                if (l != a && l != k) term *= (t - nodes[l]) / (nodes[a] - nodes[l]);
+            d += term;
+            v *= (t - nodes[k]) / (nodes[a] - nodes[k]);
+        }
+        val[a] = v;
+        if (der) der[a] = d;
+    }
+}
+
+// A 1D transfer matrix in CSR form (host).
+struct Csr {
+    int rows = 0;
+    std::vector<int> rp, ci;
+    std::vector<double> v;
+};
+
+Csr csr_of(const std::vector<std::vector<double>>& M, int cols) {
+    Csr c;
+    c.rows = (int)M.size();
+    c.rp.push_back(0);
+    for (const auto& row : M) {
+        for (int k = 0; k < cols; ++k)
+            if (row[k] != 0.0) { c.ci.push_back(k); c.v.push_back(row[k]); }
+        c.rp.push_back((int)c.ci.size());
+    }
+    return c;
+}
+
+Csr csr_transpose(const std::vector<std::vector<double>>& M, int cols) {
+    std::vector<std::vector<double>> T(cols, std::vector<double>(M.size(), 0.0));
+    for (size_t i = 0; i < M.size(); ++i)
+        for (int k = 0; k < cols; ++k) T[k][i] = M[i][k];
+    return csr_of(T, (int)M.size());
+}
+
+// One continuous level of the cph hierarchy (see sipg_mg_opts): host tables
+// built with the hierarchy, device pointers set at binding (all in the
+// finest plan's workspace, 8 bytes per vector entry in either precision).
+struct CgLevel {
+    sipg_plan* carrier = nullptr;    // the DG plan of the same degree and mesh
+    CgGeo geo;
+    long long n = 0;                 // unknowns
+    long long dgsize = 0;            // the carrier's unknowns
+    CgL<double> L64;
+    CgL<float> L32;
+    CgDiagTab dtab;
+    // transfer to the next coarser level: prolongation (rows: this level's
+    // nodes along an axis) and its transpose, per axis
+    Csr P[3], R[3];
+    bool direct = false;             // coarsest, degree 1, n <= direct_max: dense FP64 inverse
+    void *r = nullptr, *za = nullptr, *zb = nullptr, *d = nullptr, *t = nullptr, *zk = nullptr;
+    void *ta = nullptr, *tb = nullptr;
+    double *diag64 = nullptr, *dinv64 = nullptr;
+    float* dinv32 = nullptr;
+    void *dgx = nullptr, *dgy = nullptr;
+    SolveState* st = nullptr;
+    double* partials = nullptr;
+    int *prp[3] = {}, *pci[3] = {}, *rrp[3] = {}, *rci[3] = {};
+    double *pv64[3] = {}, *rv64[3] = {};
+    float *pv32[3] = {}, *rv32[3] = {};
+    double* cinv = nullptr;          // coarsest: dense inverse
+    double* probes = nullptr;        // coarsest: the carrier applied to C*8 probe vectors
+    bool lz_valid = false, lz_stale = false;
+    int lz_steps = 0;
+};
+
 }  // namespace
 
 struct sipg_plan {
@@ -170,6 +270,7 @@ struct sipg_plan {
     MgTab<double> tr64;              // (coarse level) 1D tables of that transfer
     MgTab<float> tr32;
     void *mgz = nullptr, *mgt = nullptr;  // (finest level) V-cycle correction and residual
+    std::vector<CgLevel> cg;              // (finest level, continuous hierarchy) the continuous levels
 
     template <typename T>
     OpData<T> opdata() const;
@@ -212,6 +313,11 @@ struct Layout {
     size_t tdiv = 0, tcont = 0;       // penalty step: per-cell factors
     size_t mgz = 0, mgt = 0;          // multigrid: finest-level vectors
     std::vector<size_t> level, level_bytes;   // multigrid: workspaces of the coarser levels
+    struct Cg {
+        size_t vec[8], diag64, dinv64, dinv32, dgx, dgy, st, partials, cinv, probes;
+        size_t prp[3], pci[3], pv64[3], pv32[3], rrp[3], rci[3], rv64[3], rv32[3];
+    };
+    std::vector<Cg> cg;               // continuous levels
     size_t op_end, total;
 };
 
@@ -245,11 +351,112 @@ Layout layout(const sipg_plan* P) {
             L.level_bytes.push_back(b);
         }
     }
+    for (const CgLevel& c : P->cg) {
+        Layout::Cg g;
+        std::memset(&g, 0, sizeof(g));
+        for (int k = 0; k < 8; ++k) g.vec[k] = take((size_t)c.n * 8);
+        g.diag64 = take((size_t)c.n * 8); g.dinv64 = take((size_t)c.n * 8); g.dinv32 = take((size_t)c.n * 4);
+        g.dgx = take((size_t)c.dgsize * 8); g.dgy = take((size_t)c.dgsize * 8);
+        g.st = take(sizeof(SolveState));
+        g.partials = take(kRedSlots * kRedBlocks * 8);
+        for (int a = 0; a < 3; ++a) {
+            g.prp[a] = take(c.P[a].rp.size() * 4); g.pci[a] = take(c.P[a].ci.size() * 4);
+            g.pv64[a] = take(c.P[a].v.size() * 8); g.pv32[a] = take(c.P[a].v.size() * 4);
+            g.rrp[a] = take(c.R[a].rp.size() * 4); g.rci[a] = take(c.R[a].ci.size() * 4);
+            g.rv64[a] = take(c.R[a].v.size() * 8); g.rv32[a] = take(c.R[a].v.size() * 4);
+        }
+        g.cinv = c.direct ? take((size_t)c.n * c.n * 8) : 0;
+        g.probes = c.direct ? take((size_t)c.geo.C * 8 * c.dgsize * 8) : 0;
+        L.cg.push_back(g);
+    }
     L.total = off;
     return L;
 }
 
 bool valid_plan(const sipg_plan* P) { return P != nullptr; }
+
+int mg_levels(const sipg_plan* P) { return P->mg_on ? 1 + (int)P->mg.size() : 1; }
+sipg_plan* mg_level(sipg_plan* P, int l) { return l == 0 ? P : P->mg[l - 1]; }
+
+// The continuous levels of the cph hierarchy: one per DG level of the
+// hierarchy (same degree and mesh; the finest DG level itself is the first
+// carrier), with the tables of G (Lobatto -> Gauss per cell), the diagonal's
+// Lobatto basis tables, and the 1D prolongations to each level from the next
+// coarser one (degree step: the coarse Lobatto interpolant at the fine
+// Lobatto nodes of a cell; mesh step at degree 1: fine vertex 2i <- i,
+// 2i + 1 <- the mean of i and i + 1).
+void build_continuous_levels(sipg_plan* P) {
+    P->cg.clear();
+    const int nl = mg_levels(P);
+    for (int l = 0; l < nl; ++l) {
+        sipg_plan* Cr = mg_level(P, l);
+        CgLevel c;
+        c.carrier = Cr;
+        const int j = Cr->degree, n = Cr->n;
+        c.geo.j = j; c.geo.C = Cr->C; c.geo.nx = Cr->nx; c.geo.ny = Cr->ny; c.geo.nz = Cr->nz;
+        c.geo.Mx = j * Cr->nx + 1; c.geo.My = j * Cr->ny + 1; c.geo.Mz = j * Cr->nz + 1;
+        c.n = (long long)Cr->C * c.geo.Mx * c.geo.My * c.geo.Mz;
+        c.dgsize = Cr->ndof;
+        double lob[kMaxN], gx[kMaxN], gw[kMaxN];
+        gll01(j, lob);
+        gauss_legendre01(n, gx, gw);
+        std::memset(&c.L64, 0, sizeof(c.L64));
+        std::memset(&c.L32, 0, sizeof(c.L32));
+        std::memset(&c.dtab, 0, sizeof(c.dtab));
+        for (int q = 0; q < n; ++q) {
+            double v[kMaxN], d[kMaxN];
+            lagrange_vd(lob, n, gx[q], v, d);
+            for (int a = 0; a < n; ++a) {
+                c.L64.L[q][a] = v[a];
+                c.L32.L[q][a] = (float)v[a];
+                c.dtab.LV[q][a] = v[a];
+                c.dtab.LD[q][a] = d[a];
+            }
+        }
+        for (int side = 0; side < 2; ++side) {
+            double v[kMaxN], d[kMaxN];
+            lagrange_vd(lob, n, (double)side, v, d);
+            for (int a = 0; a < n; ++a) c.dtab.LGs[side][a] = d[a];
+        }
+        P->cg.push_back(c);
+    }
+    for (int l = 0; l + 1 < nl; ++l) {
+        CgLevel& f = P->cg[l];
+        const CgLevel& c = P->cg[l + 1];
+        const bool mesh_step = c.geo.nx != f.geo.nx || c.geo.ny != f.geo.ny || c.geo.nz != f.geo.nz;
+        const int cells_c[3] = {c.geo.nx, c.geo.ny, c.geo.nz};
+        for (int a = 0; a < 3; ++a) {
+            const int nc = cells_c[a];
+            std::vector<std::vector<double>> M;
+            int cols;
+            if (mesh_step) {                       // degree 1 on both levels
+                cols = nc + 1;
+                M.assign(2 * nc + 1, std::vector<double>(cols, 0.0));
+                for (int i = 0; i <= 2 * nc; ++i) {
+                    if (i % 2 == 0) M[i][i / 2] = 1.0;
+                    else M[i][i / 2] = M[i][i / 2 + 1] = 0.5;
+                }
+            } else {
+                const int jf = f.geo.j, jc = c.geo.j;
+                double lf[kMaxN], lc[kMaxN];
+                gll01(jf, lf);
+                gll01(jc, lc);
+                cols = jc * nc + 1;
+                M.assign(jf * nc + 1, std::vector<double>(cols, 0.0));
+                for (int i = 0; i <= jf * nc; ++i) {
+                    const int e = std::min(i / jf, nc - 1), loc = i - e * jf;
+                    double v[kMaxN];
+                    lagrange_vd(lc, jc + 1, lf[loc], v, nullptr);
+                    for (int b = 0; b <= jc; ++b) M[i][e * jc + b] = v[b];
+                }
+            }
+            f.P[a] = csr_of(M, cols);
+            f.R[a] = csr_transpose(M, cols);
+        }
+    }
+    CgLevel& last = P->cg.back();
+    last.direct = last.geo.j == 1 && last.n <= P->mg_opts.direct_max;
+}
 
 double cell_corner_det_min(const sipg_plan* P) {
     // det J of a trilinear cell at its 8 corners; positive everywhere iff the cell is valid enough
@@ -320,8 +527,171 @@ sipg_status cheb_steps(sipg_plan* L, int degree, const T* rhs, const int* skip, 
     return SIPG_OK;
 }
 
-int mg_levels(const sipg_plan* P) { return P->mg_on ? 1 + (int)P->mg.size() : 1; }
-sipg_plan* mg_level(sipg_plan* P, int l) { return l == 0 ? P : P->mg[l - 1]; }
+// ------------------------------------------------------------ continuous levels
+
+bool pure_neumann_poisson(const sipg_plan* P) {
+    if (P->C != 1 || P->alpha != 0.0) return false;
+    for (int i = 0; i < 6; ++i)
+        if (P->bc[i] != SIPG_BC_NEUMANN) return false;
+    return true;
+}
+
+// Diagonals of the continuous levels and the coarsest level's dense inverse,
+// from the carriers' current data (after binding and after every viscosity
+// or penalty-factor update); the eigenvalue estimates become stale.
+sipg_status refresh_continuous(sipg_plan* P, hipStream_t s) {
+    for (CgLevel& c : P->cg) {
+        const sipg_plan* Cr = c.carrier;
+        HIP_TRY(launch_cg_diagonal(c.geo, Cr->opdata<double>(), c.dtab, static_cast<double*>(c.dgx), c.diag64,
+                                   c.dinv64, c.dinv32, s));
+        c.lz_stale = true;
+        if (c.direct) {
+            const int ncol = c.geo.C * 8;
+            for (int col = 0; col < ncol; ++col) {
+                HIP_TRY(launch_cg_probe(static_cast<double*>(c.dgx), c.geo.C, Cr->ncell, col, s));
+                ApplyIO<double> io;
+                std::memset(&io, 0, sizeof(io));
+                io.x = static_cast<const double*>(c.dgx);
+                io.y = c.probes + (size_t)col * c.dgsize;
+                io.parts = SIPG_PART_CELL | SIPG_PART_BOUNDARY;
+                HIP_TRY(launch_apply<double>(Cr->n, Cr->C, Cr->curved, Cr->opdata<double>(), io, MODE_APPLY, s));
+            }
+            HIP_TRY(launch_cg_coarse_inverse(c.geo, c.probes, c.dgsize, c.L64, c.cinv,
+                                             pure_neumann_poisson(P) ? 1 : 0, s));
+        }
+    }
+    return SIPG_OK;
+}
+
+template <typename T>
+const CgL<T>& cg_tab(const CgLevel& c) {
+    if constexpr (sizeof(T) == 8) return c.L64; else return c.L32;
+}
+template <typename T>
+const T* cg_dinv(const CgLevel& c) {
+    if constexpr (sizeof(T) == 8) return c.dinv64; else return c.dinv32;
+}
+template <typename T>
+AxisMat<T> cg_axis(const CgLevel& c, int a, bool restrict_) {
+    AxisMat<T> M;
+    M.rows = restrict_ ? c.R[a].rows : c.P[a].rows;
+    M.rp = restrict_ ? c.rrp[a] : c.prp[a];
+    M.ci = restrict_ ? c.rci[a] : c.pci[a];
+    if constexpr (sizeof(T) == 8) M.v = restrict_ ? c.rv64[a] : c.pv64[a];
+    else M.v = restrict_ ? c.rv32[a] : c.pv32[a];
+    return M;
+}
+
+// y = G^T A_(cell+boundary) G x on a continuous level, in precision T; with
+// mode 1 y = r - (that), with mode 2 the Chebyshev step of cg_cheb fused in
+// (d, z, dinv, coef as there)
+template <typename T>
+sipg_status cg_apply(CgLevel& c, const T* x, T* y, const int* skip, hipStream_t s, int mode = 0,
+                     const T* r = nullptr, const T* z = nullptr, T* d = nullptr, const T* dinv = nullptr,
+                     const double* coef = nullptr) {
+    const sipg_plan* Cr = c.carrier;
+    T* dx = static_cast<T*>(c.dgx);
+    T* dy = static_cast<T*>(c.dgy);
+    HIP_TRY(launch_cg_gather<T>(c.geo, cg_tab<T>(c), x, dx, false, skip, s));
+    ApplyIO<T> io;
+    std::memset(&io, 0, sizeof(io));
+    io.x = dx; io.y = dy; io.parts = SIPG_PART_CELL | SIPG_PART_BOUNDARY; io.skip = skip;
+    HIP_TRY(launch_apply<T>(Cr->n, Cr->C, Cr->curved, Cr->opdata<T>(), io, MODE_APPLY, s));
+    HIP_TRY(launch_cg_scatter<T>(c.geo, cg_tab<T>(c), dy, y, skip, s, mode, r, z, d, dinv, coef));
+    return SIPG_OK;
+}
+
+// Lanczos estimate of lambda_max(D^-1 A) of a continuous level (FP64, the
+// same start vector and steps as the DG levels).
+sipg_status run_lanczos_cg(CgLevel& c, int steps, hipStream_t s) {
+    const long long n = c.n;
+    double *v = static_cast<double*>(c.za), *vprev = static_cast<double*>(c.zb);
+    double *w = static_cast<double*>(c.t), *tt = static_cast<double*>(c.d);
+    sk_lz_start(v, n, 12345ull, c.partials, s);
+    sk_scalar(c.st, c.partials, 1, SC_LZ_NORM, n, s);
+    sk_lz_normalize(v, vprev, n, c.st, s);
+    sk_lz_pre(tt, v, c.dinv64, n, s);
+    for (int k = 0; k < steps; ++k) {
+        const sipg_status rc = cg_apply<double>(c, tt, w, nullptr, s);
+        if (rc != SIPG_OK) return rc;
+        sk_lz_post_alpha(w, v, c.dinv64, n, c.st, c.partials, s);
+        sk_lz_orth_beta(w, v, vprev, n, c.st, c.partials, s);
+        sk_lz_next_pre(vprev, tt, w, c.dinv64, n, c.st, s);
+        std::swap(v, vprev);
+    }
+    sk_lz_eig(c.st, s);
+    HIP_TRY(hipGetLastError());
+    c.lz_valid = true;
+    c.lz_stale = false;
+    c.lz_steps = steps;
+    return SIPG_OK;
+}
+
+// Chebyshev-Jacobi polynomial of `degree` of a continuous level applied to
+// rhs from zero (za, zb, d; ta receives A z); *out: the buffer of the result.
+template <typename T>
+sipg_status cg_cheb(CgLevel& c, int degree, const T* rhs, const int* skip, const T** out, hipStream_t s) {
+    T* za = static_cast<T*>(c.za);
+    T* zb = static_cast<T*>(c.zb);
+    T* d = static_cast<T*>(c.d);
+    HIP_TRY(launch_cheb_start_t<T>(rhs, za, d, cg_dinv<T>(c), c.n, c.st, skip, s));
+    for (int k = 1; k < degree; ++k) {
+        // zb = za + d with d <- c1 d + c2 dinv (rhs - A za), fused into the node sums
+        const sipg_status rc = cg_apply<T>(c, za, zb, skip, s, 2, rhs, za, d, cg_dinv<T>(c), &c.st->cheb[k][0]);
+        if (rc != SIPG_OK) return rc;
+        std::swap(za, zb);
+    }
+    *out = za;
+    return SIPG_OK;
+}
+
+// One V-cycle from zero on continuous level i of the finest plan P (right-hand
+// side in the level's r), result in *out.
+template <typename T>
+sipg_status cg_vcycle(sipg_plan* P, int i, const T** out, hipStream_t s) {
+    CgLevel& c = P->cg[i];
+    const int* skip = &P->st->skip;
+    const T* R = static_cast<const T*>(c.r);
+    const bool last = i + 1 == (int)P->cg.size();
+    if (last) {
+        if (c.direct) {
+            HIP_TRY(launch_dense_mv<T>(c.cinv, R, static_cast<T*>(c.za), (int)c.n, skip, s));
+            *out = static_cast<const T*>(c.za);
+            return SIPG_OK;
+        }
+        return cg_cheb<T>(c, P->mg_opts.coarse_degree, R, skip, out, s);
+    }
+    const int deg = P->opts.cheb_degree;
+    T* Z = static_cast<T*>(c.zk);
+    T* Tt = static_cast<T*>(c.t);
+    T* ta = static_cast<T*>(c.ta);
+    T* tb = static_cast<T*>(c.tb);
+    const T* zs = nullptr;
+    sipg_status rc = cg_cheb<T>(c, deg, R, skip, &zs, s);                           // pre-smoothing
+    if (rc != SIPG_OK) return rc;
+    HIP_TRY(launch_copy_t<T>(Z, zs, c.n, skip, s));
+    auto residual = [&]() -> sipg_status {                                          // Tt = R - A Z
+        return cg_apply<T>(c, Z, Tt, skip, s, 1, R);
+    };
+    if ((rc = residual()) != SIPG_OK) return rc;
+    CgLevel& cc = P->cg[i + 1];
+    const int C = c.geo.C;
+    // restriction: along x, y, z with the transposed 1D prolongations
+    HIP_TRY(launch_axis<T>(cg_axis<T>(c, 0, true), 0, C, c.geo.Mx, c.geo.My, c.geo.Mz, Tt, ta, false, skip, s));
+    HIP_TRY(launch_axis<T>(cg_axis<T>(c, 1, true), 1, C, cc.geo.Mx, c.geo.My, c.geo.Mz, ta, tb, false, skip, s));
+    HIP_TRY(launch_axis<T>(cg_axis<T>(c, 2, true), 2, C, cc.geo.Mx, cc.geo.My, c.geo.Mz, tb, static_cast<T*>(cc.r),
+                           false, skip, s));
+    const T* zc = nullptr;
+    if ((rc = cg_vcycle<T>(P, i + 1, &zc, s)) != SIPG_OK) return rc;             // coarse correction
+    HIP_TRY(launch_axis<T>(cg_axis<T>(c, 0, false), 0, C, cc.geo.Mx, cc.geo.My, cc.geo.Mz, zc, ta, false, skip, s));
+    HIP_TRY(launch_axis<T>(cg_axis<T>(c, 1, false), 1, C, c.geo.Mx, cc.geo.My, cc.geo.Mz, ta, tb, false, skip, s));
+    HIP_TRY(launch_axis<T>(cg_axis<T>(c, 2, false), 2, C, c.geo.Mx, c.geo.My, cc.geo.Mz, tb, Z, true, skip, s));
+    if ((rc = residual()) != SIPG_OK) return rc;
+    if ((rc = cg_cheb<T>(c, deg, Tt, skip, &zs, s)) != SIPG_OK) return rc;        // post-smoothing
+    HIP_TRY(launch_add_t<T>(Z, zs, c.n, skip, s));
+    *out = Z;
+    return SIPG_OK;
+}
 
 // One V-cycle from zero on level l of the finest plan `top` (Sec. 5.3):
 // right-hand side in the level's cr (precision T), result in *out.  Level 0's
@@ -333,7 +703,7 @@ sipg_status vcycle(sipg_plan* top, int l, const T** out, hipStream_t s) {
     const int* skip = &top->st->skip;
     const long long n = L->ndof;
     const T* R = static_cast<const T*>(L->cr);
-    const bool last = l == mg_levels(top) - 1;
+    const bool last = top->cg.empty() && l == mg_levels(top) - 1;   // cph: the DG level is never the last
     const int deg = last ? top->mg_opts.coarse_degree : top->opts.cheb_degree;
     if (l > 0) HIP_TRY(launch_cheb_start_t<T>(R, static_cast<T*>(L->cz0), static_cast<T*>(L->cd), dinv_of<T>(L), n,
                                               L->st, skip, s));
@@ -355,13 +725,24 @@ sipg_status vcycle(sipg_plan* top, int l, const T** out, hipStream_t s) {
     };
     HIP_TRY(launch_copy_t<T>(Z, zs, n, skip, s));
     if ((rc = residual()) != SIPG_OK) return rc;
-    sipg_plan* Cc = top->mg[l];
-    HIP_TRY(launch_restrict<T>(Cc->mesh_step, L->C, L->n, Cc->n, L->nx, L->ny, L->nz, tab_of<T>(Cc), Tm,
-                               static_cast<T*>(Cc->cr), skip, s));
-    const T* zc = nullptr;
-    if ((rc = vcycle<T>(top, l + 1, &zc, s)) != SIPG_OK) return rc;               // coarse correction
-    HIP_TRY(launch_prolong_add<T>(Cc->mesh_step, L->C, L->n, Cc->n, L->nx, L->ny, L->nz, tab_of<T>(Cc), zc, Z,
-                                  skip, s));
+    if (l == 0 && !top->cg.empty()) {
+        // cph: the continuous levels below the DG level (restriction G^T,
+        // which overwrites Tm with the cells' local contributions, and
+        // prolongation Z += G zc)
+        CgLevel& c0 = top->cg[0];
+        HIP_TRY(launch_cg_scatter<T>(c0.geo, cg_tab<T>(c0), Tm, static_cast<T*>(c0.r), skip, s));
+        const T* zc = nullptr;
+        if ((rc = cg_vcycle<T>(top, 0, &zc, s)) != SIPG_OK) return rc;
+        HIP_TRY(launch_cg_gather<T>(c0.geo, cg_tab<T>(c0), zc, Z, true, skip, s));
+    } else {
+        sipg_plan* Cc = top->mg[l];
+        HIP_TRY(launch_restrict<T>(Cc->mesh_step, L->C, L->n, Cc->n, L->nx, L->ny, L->nz, tab_of<T>(Cc), Tm,
+                                   static_cast<T*>(Cc->cr), skip, s));
+        const T* zc = nullptr;
+        if ((rc = vcycle<T>(top, l + 1, &zc, s)) != SIPG_OK) return rc;           // coarse correction
+        HIP_TRY(launch_prolong_add<T>(Cc->mesh_step, L->C, L->n, Cc->n, L->nx, L->ny, L->nz, tab_of<T>(Cc), zc, Z,
+                                      skip, s));
+    }
     if ((rc = residual()) != SIPG_OK) return rc;
     HIP_TRY(launch_cheb_start_t<T>(Tm, static_cast<T*>(L->cz0), static_cast<T*>(L->cd), dinv_of<T>(L), n, L->st,
                                    skip, s));
@@ -569,6 +950,7 @@ sipg_status update_viscosity(sipg_plan* P, const double* u, hipStream_t s) {
     const int nl = mg_levels(P);
     for (int l = 0; l < nl; ++l) {
         sipg_plan* L = mg_level(P, l);
+        if (!L->bound) break;                  // coarse levels are bound only with solver workspace
         LevelPoints Lv;
         std::memset(&Lv, 0, sizeof(Lv));
         Lv.nx = L->nx; Lv.ny = L->ny; Lv.nz = L->nz; Lv.n = L->n;
@@ -581,6 +963,7 @@ sipg_status update_viscosity(sipg_plan* P, const double* u, hipStream_t s) {
         HIP_TRY(launch_diagonal(L->n, L->C, L->curved, L->opdata<double>(), L->diag64, L->dinv64, L->dinv32, s));
         L->lz_stale = true;
     }
+    if (!P->cg.empty() && P->with_solver) return refresh_continuous(P, s);
     return SIPG_OK;
 }
 
@@ -590,7 +973,21 @@ sipg_status update_viscosity(sipg_plan* P, const double* u, hipStream_t s) {
 sipg_status prepare_precond(sipg_plan* P, hipStream_t s) {
     const sipg_solve_opts& o = P->opts;
     const bool mg = o.precond_kind == SIPG_PRECOND_MULTIGRID;
-    const int nl = mg ? mg_levels(P) : 1;
+    const bool cph = mg && !P->cg.empty();
+    // cph: the DG level and the continuous levels (the coarser DG plans only
+    // carry the continuous levels' operators)
+    const int nl = mg ? (cph ? 1 : mg_levels(P)) : 1;
+    if (cph) {
+        for (size_t i = 0; i < P->cg.size(); ++i) {
+            CgLevel& c = P->cg[i];
+            if (!c.lz_valid || c.lz_steps != o.lanczos_steps || (c.lz_stale && !o.reuse_eigs)) {
+                const sipg_status rc = run_lanczos_cg(c, o.lanczos_steps, s);
+                if (rc != SIPG_OK) return rc;
+            }
+            const bool coarse_poly = i + 1 == P->cg.size() && !c.direct;
+            sk_lz_coef(c.st, o.cheb_safety, o.cheb_ratio, coarse_poly ? P->mg_opts.coarse_degree : o.cheb_degree, s);
+        }
+    }
     for (int l = 0; l < nl; ++l) {
         sipg_plan* L = mg_level(P, l);
         if (l > 0) L->opts = o;
@@ -598,7 +995,7 @@ sipg_status prepare_precond(sipg_plan* P, hipStream_t s) {
             const sipg_status rc = run_lanczos(L, s);
             if (rc != SIPG_OK) return rc;
         }
-        const int deg = (mg && l == nl - 1) ? P->mg_opts.coarse_degree : o.cheb_degree;
+        const int deg = (mg && !cph && l == nl - 1) ? P->mg_opts.coarse_degree : o.cheb_degree;
         sk_lz_coef(L->st, o.cheb_safety, o.cheb_ratio, deg, s);
     }
     HIP_TRY(hipGetLastError());
@@ -637,7 +1034,7 @@ void fill_transfer(sipg_plan* Cc, int nf, int nc) {
 
 extern "C" {
 
-int32_t sipg_abi_version(void) { return 1; }
+int32_t sipg_abi_version(void) { return 2; }
 
 const char* sipg_last_error(void) { return g_err.c_str(); }
 
@@ -863,6 +1260,46 @@ sipg_status sipg_plan_bind(sipg_plan* P, void* workspace, size_t bytes, int32_t 
             const sipg_status rc = sipg_plan_bind(P->mg[i], w + L.level[i], L.level_bytes[i], 1, stream);
             if (rc != SIPG_OK) return rc;
         }
+        for (size_t i = 0; i < P->cg.size(); ++i) {
+            CgLevel& c = P->cg[i];
+            const Layout::Cg& g = L.cg[i];
+            void** vecs[8] = {&c.r, &c.za, &c.zb, &c.d, &c.t, &c.zk, &c.ta, &c.tb};
+            for (int k = 0; k < 8; ++k) *vecs[k] = w + g.vec[k];
+            c.diag64 = reinterpret_cast<double*>(w + g.diag64);
+            c.dinv64 = reinterpret_cast<double*>(w + g.dinv64);
+            c.dinv32 = reinterpret_cast<float*>(w + g.dinv32);
+            c.dgx = w + g.dgx;
+            c.dgy = w + g.dgy;
+            c.st = reinterpret_cast<SolveState*>(w + g.st);
+            c.partials = reinterpret_cast<double*>(w + g.partials);
+            HIP_TRY(hipMemsetAsync(c.st, 0, sizeof(SolveState), s));
+            for (int a = 0; a < 3; ++a) {
+                c.prp[a] = reinterpret_cast<int*>(w + g.prp[a]);
+                c.pci[a] = reinterpret_cast<int*>(w + g.pci[a]);
+                c.pv64[a] = reinterpret_cast<double*>(w + g.pv64[a]);
+                c.pv32[a] = reinterpret_cast<float*>(w + g.pv32[a]);
+                c.rrp[a] = reinterpret_cast<int*>(w + g.rrp[a]);
+                c.rci[a] = reinterpret_cast<int*>(w + g.rci[a]);
+                c.rv64[a] = reinterpret_cast<double*>(w + g.rv64[a]);
+                c.rv32[a] = reinterpret_cast<float*>(w + g.rv32[a]);
+                auto up = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+                    return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s) : hipSuccess;
+                };
+                HIP_TRY(up(c.prp[a], c.P[a].rp.data(), c.P[a].rp.size() * 4));
+                HIP_TRY(up(c.pci[a], c.P[a].ci.data(), c.P[a].ci.size() * 4));
+                HIP_TRY(up(c.pv64[a], c.P[a].v.data(), c.P[a].v.size() * 8));
+                HIP_TRY(up(c.rrp[a], c.R[a].rp.data(), c.R[a].rp.size() * 4));
+                HIP_TRY(up(c.rci[a], c.R[a].ci.data(), c.R[a].ci.size() * 4));
+                HIP_TRY(up(c.rv64[a], c.R[a].v.data(), c.R[a].v.size() * 8));
+                if (!c.P[a].v.empty()) sk_cast(c.pv32[a], c.pv64[a], (long long)c.P[a].v.size(), s);
+                if (!c.R[a].v.empty()) sk_cast(c.rv32[a], c.rv64[a], (long long)c.R[a].v.size(), s);
+            }
+            c.cinv = c.direct ? reinterpret_cast<double*>(w + g.cinv) : nullptr;
+            c.probes = c.direct ? reinterpret_cast<double*>(w + g.probes) : nullptr;
+            c.lz_valid = false;
+        }
+        const sipg_status rc = refresh_continuous(P, s);
+        if (rc != SIPG_OK) return rc;
     }
     P->bound = true;
     g_err.clear();
@@ -934,6 +1371,8 @@ void sipg_mg_opts_default(sipg_mg_opts* o) {
     o->min_cells = 2;
     o->max_levels = 16;
     o->h_coarsen = 1;
+    o->continuous = 1;
+    o->direct_max = 1024;
 }
 
 sipg_status sipg_plan_set_multigrid(sipg_plan* P, const sipg_mg_opts* opts) {
@@ -941,8 +1380,10 @@ sipg_status sipg_plan_set_multigrid(sipg_plan* P, const sipg_mg_opts* opts) {
     if (P->bound) return fail(SIPG_ERR_STATE, "set the multigrid hierarchy before binding the plan");
     sipg_mg_opts o;
     if (opts) o = *opts; else sipg_mg_opts_default(&o);
-    if (o.coarse_degree < 1 || o.coarse_degree > 63 || o.min_cells < 1 || o.max_levels < 1)
+    if (o.coarse_degree < 1 || o.coarse_degree > 63 || o.min_cells < 1 || o.max_levels < 1 ||
+        (o.continuous != 0 && o.continuous != 1) || o.direct_max < 0 || o.direct_max > 2048)
         return fail(SIPG_ERR_INVALID, "bad multigrid options");
+    P->cg.clear();
     if (P->C == 3 && !P->pen && P->law.kind == SIPG_LAW_ARRAYS)
         return fail(SIPG_ERR_UNSUPPORTED, "tabulated viscosity (ARRAYS law) has no values on coarse levels");
     for (sipg_plan* c : P->mg) sipg_plan_destroy(c);
@@ -1025,6 +1466,7 @@ sipg_status sipg_plan_set_multigrid(sipg_plan* P, const sipg_mg_opts* opts) {
     }
     P->mg_opts = o;
     P->mg_on = true;
+    if (o.continuous) build_continuous_levels(P);
     g_err.clear();
     return SIPG_OK;
 }
@@ -1552,6 +1994,7 @@ sipg_status sipg_update_penalty_factors(sipg_plan* P, const double* u, double dt
         tc = L->tau_cont_d;
         fx = L->nx; fy = L->ny; fz = L->nz;
     }
+    if (!P->cg.empty() && P->with_solver) return refresh_continuous(P, s);
     return SIPG_OK;
 }
 

@@ -1116,9 +1116,24 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
 
     // ------------------------------------------------------------ faces
     if (io.parts & (SIPG_PART_INTERIOR | SIPG_PART_BOUNDARY)) {
+        // boundary terms only (the continuous levels of the multigrid
+        // preconditioner): a face pass that no cell of the workgroup needs
+        // is skipped as a whole (the vote is uniform over the workgroup)
+        const bool only_boundary = (io.parts & SIPG_PART_INTERIOR) == 0;
 #pragma unroll 1
         for (int f = 0; f < 6; ++f) {
             const int s = f & 1;
+            if (only_boundary) {
+                const int D = f >> 1;
+                const int pos = D == 0 ? ci.ex : D == 1 ? ci.ey : ci.ez;
+                const int lim = D == 0 ? op.nx : D == 1 ? op.ny : op.nz;
+                const bool wall = s == 1 ? pos + 1 >= lim : pos == 0;
+                const bool need = ci.active && wall && op.bc[2 * D + s] == 0;
+                bool any;
+                if constexpr (THREADS <= 64) any = __ballot(need) != 0;
+                else any = __syncthreads_or(need) != 0;
+                if (!any) continue;
+            }
             if constexpr (PEN) {
                 if (f < 2) face_pass_pen<N, T, CURVED, 0, THREADS>(op, io, ci, s, y, su, sw, geo, lt, vo);
                 else if (f < 4) face_pass_pen<N, T, CURVED, 1, THREADS>(op, io, ci, s, y, su, sw, geo, lt, vo);

@@ -65,6 +65,24 @@ __device__ __forceinline__ void map_point(const T (*geo)[3], T x1, T x2, T x3, T
                geo[5][i] * (x1 * x3) + geo[6][i] * (x2 * x3) + geo[7][i] * (x1 * x2 * x3);
 }
 
+// Monomial coefficients geo[k][i] of cell e: from the vertices, or for the
+// straight unit box x_i = (pos_i + xi_i) h_i.
+__device__ inline void cell_geo_full(const OpData<double>& op, int e, double geo[8][3]) {
+    const int ex = e % op.nx, ey = (e / op.nx) % op.ny, ez = e / (op.nx * op.ny);
+    for (int i = 0; i < 3; ++i) {
+        double g[8];
+        if (op.verts) {
+            trilinear_coeffs(op.verts, op.nx, op.ny, ex, ey, ez, i, g);
+        } else {
+            for (int k = 0; k < 8; ++k) g[k] = 0.0;
+            const int pos = i == 0 ? ex : i == 1 ? ey : ez;
+            g[0] = pos * op.h[i];
+            g[1 + i] = op.h[i];
+        }
+        for (int k = 0; k < 8; ++k) geo[k][i] = g[k];
+    }
+}
+
 // Viscosity laws (Sec. 2 and smooth prescribed fields), FP64.
 __device__ inline double law_value(const LawDev& L, const double X[3]) {
     const double twopi = 6.283185307179586476925286766559;

@@ -8,22 +8,6 @@ namespace sipg {
 
 // ---------------------------------------------------------------- geometry
 
-__device__ inline void cell_geo_full(const OpData<double>& op, int e, double geo[8][3]) {
-    const int ex = e % op.nx, ey = (e / op.nx) % op.ny, ez = e / (op.nx * op.ny);
-    for (int i = 0; i < 3; ++i) {
-        double g[8];
-        if (op.verts) {
-            trilinear_coeffs(op.verts, op.nx, op.ny, ex, ey, ez, i, g);
-        } else {  // straight unit box: x_i = (pos_i + xi_i) h_i
-            for (int k = 0; k < 8; ++k) g[k] = 0.0;
-            const int pos = i == 0 ? ex : i == 1 ? ey : ez;
-            g[0] = pos * op.h[i];
-            g[1 + i] = op.h[i];
-        }
-        for (int k = 0; k < 8; ++k) geo[k][i] = g[k];
-    }
-}
-
 // Per cell: h_e = |e|^(1/3) into hcell[e], and the penalty's surface-to-volume
 // ratio sigma_e = (sum_f w_f |f|) / |e| into hcell[ncell + e], w_f = 1/2 for a
 // face shared with another cell and 1 on the boundary of the box.  Volume and

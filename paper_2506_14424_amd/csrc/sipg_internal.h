@@ -102,6 +102,31 @@ struct MgTab {
     T H[2][kMaxN][kMaxN];
 };
 
+// Continuous level of the cph-multigrid hierarchy: degree j on nx*ny*nz
+// cells, (Mx, My, Mz) = (j nx + 1, j ny + 1, j nz + 1) Lobatto nodes per
+// direction, C components (component-major).
+struct CgGeo {
+    int j, C, nx, ny, nz, Mx, My, Mz;
+};
+// L[b][a] = l^Lobatto_a(x^Gauss_b): a cell's Lobatto interpolant at its Gauss nodes.
+template <typename T>
+struct CgL {
+    T L[kMaxN][kMaxN];
+};
+// Diagonal of a continuous level: Lobatto basis values and derivatives at
+// the Gauss points, LV[q][a], LD[q][a], and derivatives at the end points LGs[s][a].
+struct CgDiagTab {
+    double LV[kMaxN][kMaxN], LD[kMaxN][kMaxN], LGs[2][kMaxN];
+};
+// 1D sparse transfer matrix (CSR) along one axis.
+template <typename T>
+struct AxisMat {
+    int rows;
+    const int* rp;
+    const int* ci;
+    const T* v;
+};
+
 // Picard viscosity update: the finest level's velocity (3 components) and
 // the points of the level whose viscosity is evaluated.
 struct FineVelocity {
@@ -206,5 +231,36 @@ template <typename T>
 hipError_t launch_add_t(T* y, const T* x, long long n, const int* skip, hipStream_t s);
 template <typename T>
 hipError_t launch_to_f64(double* y, const T* x, long long n, hipStream_t s);
+
+// Continuous levels (cph-multigrid): dg = G cg (add: +=); cg = G^T dg
+// (dg is overwritten by the cells' local contributions); out = M in along
+// one axis of a (C, n2, n1, n0) array; Chebyshev step d <- c1 d + c2 dinv
+// (r - t), zn = z + d; y = r - t; diagonal of G^T A G (local: a DG-sized
+// work array) with its inverses; probe vectors and the coarsest level's
+// dense inverse (in A); z = Ainv r.  Kernels used in a solve are skip-aware.
+template <typename T>
+hipError_t launch_cg_gather(const CgGeo& g, const CgL<T>& tab, const T* cg, T* dg, bool add, const int* skip,
+                            hipStream_t s);
+// scatter modes: 0 cg = G^T dg; 1 cg = r - G^T dg; 2 Chebyshev step with
+// t = G^T dg: d <- c1 d + c2 dinv (r - t), cg = z + d (coef = {c1, c2})
+template <typename T>
+hipError_t launch_cg_scatter(const CgGeo& g, const CgL<T>& tab, T* dg, T* cg, const int* skip, hipStream_t s,
+                             int mode = 0, const T* r = nullptr, const T* z = nullptr, T* d = nullptr,
+                             const T* dinv = nullptr, const double* coef = nullptr);
+template <typename T>
+hipError_t launch_axis(const AxisMat<T>& M, int axis, int C, int n0, int n1, int n2, const T* in, T* out, bool add,
+                       const int* skip, hipStream_t s);
+template <typename T>
+hipError_t launch_cg_cheb(const T* z, T* zn, T* d, const T* r, const T* t, const T* dinv, const double* coef,
+                          long long n, const int* skip, hipStream_t s);
+template <typename T>
+hipError_t launch_cg_sub(T* y, const T* r, const T* t, long long n, const int* skip, hipStream_t s);
+hipError_t launch_cg_diagonal(const CgGeo& g, const OpData<double>& op, const CgDiagTab& tab, double* local,
+                              double* diag, double* dinv64, float* dinv32, hipStream_t s);
+hipError_t launch_cg_probe(double* v, int C, long long ncell, int col, hipStream_t s);
+hipError_t launch_cg_coarse_inverse(const CgGeo& g, const double* probes, long long dgsize, const CgL<double>& tab,
+                                    double* A, int mean_zero, hipStream_t s);
+template <typename T>
+hipError_t launch_dense_mv(const double* Ainv, const T* r, T* z, int n, const int* skip, hipStream_t s);
 
 }  // namespace sipg

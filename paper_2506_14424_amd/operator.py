@@ -148,10 +148,13 @@ class Operator:
 
     # ------------------------------------------------------------- setup
     def set_multigrid(self, coarse_degree: int = 12, min_cells: int = 2, max_levels: int = 16,
-                      h_coarsen: bool = True):
-        """Build the hp-multigrid hierarchy (before bind); see sipg_plan_set_multigrid."""
+                      h_coarsen: bool = True, continuous: bool = True, direct_max: int = 1024):
+        """Build the hp-multigrid hierarchy (before bind); see sipg_plan_set_multigrid.
+        continuous: the cph hierarchy (DG level, then continuous levels, direct
+        coarse solve up to direct_max unknowns); False: all levels DG."""
         o = F.MgOpts()
         o.coarse_degree, o.min_cells, o.max_levels, o.h_coarsen = coarse_degree, min_cells, max_levels, int(h_coarsen)
+        o.continuous, o.direct_max = int(continuous), direct_max
         check(lib.sipg_plan_set_multigrid(self._h, C.byref(o)))
         return self
 

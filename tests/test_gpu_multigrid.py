@@ -70,7 +70,7 @@ def test_vcycle_matches_oracle(case):
         cfg, V = small_curved(4, 4, 4, 3)
     pb = Problem.from_config(cfg, V)
     H = MG.Hierarchy(pb, smooth_degree=3, coarse_degree=12)
-    op = Operator.from_config(cfg, V).set_multigrid(coarse_degree=12).bind(with_solver=True)
+    op = Operator.from_config(cfg, V).set_multigrid(coarse_degree=12, continuous=False).bind(with_solver=True)
     r = W.uniform_vector(11, pb.ndof)
     opts = SolveOptions(precond_precision="f64", cheb_degree=3, precond="multigrid")
     z = op.precondition(torch.from_numpy(r).cuda(), opts=opts).cpu().numpy()
@@ -110,7 +110,7 @@ def test_multigrid_solve_matches_oracle_solver():
     A = lambda v: oracle_apply(pb, v)
     _, ref = oracle_solve(A, 1.0 / H.dinv[0], b, tol=1e-10, precond=H.vcycle)
     _, cheb = oracle_solve(A, 1.0 / H.dinv[0], b, tol=1e-10)
-    op = Operator.from_config(cfg, V).set_multigrid(coarse_degree=12).bind(with_solver=True)
+    op = Operator.from_config(cfg, V).set_multigrid(coarse_degree=12, continuous=False).bind(with_solver=True)
     for prec in ("f64", "f32"):
         x, info = op.solve(torch.from_numpy(b).cuda(), opts=SolveOptions(
             rel_tol=1e-10, precond_precision=prec, cheb_degree=3, precond="multigrid"))

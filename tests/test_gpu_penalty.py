@@ -120,7 +120,7 @@ def test_penalty_vcycle_and_solve_match_oracle():
     cfg, V = pen_case(4, 4, 4, 3)
     pb = Problem.from_config(cfg, V)
     H = MG.Hierarchy(pb, smooth_degree=3, coarse_degree=12, min_cells=1)
-    op = Operator.from_config(cfg, V).set_multigrid(coarse_degree=12, min_cells=1).bind(with_solver=True)
+    op = Operator.from_config(cfg, V).set_multigrid(coarse_degree=12, min_cells=1, continuous=False).bind(with_solver=True)
     ref_levels = [(p.degree, p.mesh.nx, p.mesh.ny, p.mesh.nz) for p in H.levels]
     say(f"[penalty mg] levels {op.multigrid_levels()}")
     assert op.multigrid_levels() == ref_levels

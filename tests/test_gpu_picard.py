@@ -76,7 +76,7 @@ def test_every_level_takes_the_velocity_viscosity():
     whose viscosity comes from the same fine velocity."""
     cfg, V = case(4, 4, 4, 3)
     pb = Problem.from_config(cfg, V)
-    op = Operator.from_config(cfg, V).set_multigrid(coarse_degree=12, min_cells=1).bind(with_solver=True)
+    op = Operator.from_config(cfg, V).set_multigrid(coarse_degree=12, min_cells=1, continuous=False).bind(with_solver=True)
     u = velocity(4, pb.ndof, 3.0)
     levels = [PC.with_velocity_viscosity(L, pb, u, cfg["law"]) for L in MG.level_problems(pb, min_cells=1)]
     H = MG.Hierarchy(pb, smooth_degree=3, coarse_degree=12, levels=levels)

@@ -477,7 +477,7 @@ def test_penalty_multigrid_levels_follow_the_factor_update():
     dt = 1e-2
     V = W.box_vertices(4, 4, 4, 0.1)
     law = W.carreau_law(3)
-    st = SplitStep(4, 4, 4, 3, dt, law, V).set_multigrid(penalty=True, coarse_degree=12, min_cells=1).bind()
+    st = SplitStep(4, 4, 4, 3, dt, law, V).set_multigrid(penalty=True, coarse_degree=12, min_cells=1, continuous=False).bind()
     pb = Problem(Mesh(4, 4, 4, V), 3, "viscous", 1.0 / dt, 1.0, law)
     u = W.uniform_vector(1, pb.ndof)
     st.update_penalty_factors(dev(u), zeta=1.5)

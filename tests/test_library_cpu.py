@@ -30,7 +30,7 @@ def test_library_exports_every_declared_function():
 
 def test_abi_version_and_defaults():
     from paper_2506_14424_amd import _ffi as F
-    assert F.lib.sipg_abi_version() == 1
+    assert F.lib.sipg_abi_version() == 2
     o = F.SolveOpts()
     F.lib.sipg_solve_opts_default(C.byref(o))
     assert o.rel_tol == 1e-8 and o.cheb_degree == 5 and o.precond_precision == F.F32
