@@ -589,15 +589,21 @@ template <typename T>
 sipg_status cg_apply(CgLevel& c, const T* x, T* y, const int* skip, hipStream_t s, int mode = 0,
                      const T* r = nullptr, const T* z = nullptr, T* d = nullptr, const T* dinv = nullptr,
                      const double* coef = nullptr) {
+    // the carrier's kernel in its continuous mode: Lobatto -> Gauss per cell,
+    // cell and boundary terms, local G_e^T; then the node sums
     const sipg_plan* Cr = c.carrier;
-    T* dx = static_cast<T*>(c.dgx);
     T* dy = static_cast<T*>(c.dgy);
-    HIP_TRY(launch_cg_gather<T>(c.geo, cg_tab<T>(c), x, dx, false, skip, s));
     ApplyIO<T> io;
     std::memset(&io, 0, sizeof(io));
-    io.x = dx; io.y = dy; io.parts = SIPG_PART_CELL | SIPG_PART_BOUNDARY; io.skip = skip;
-    HIP_TRY(launch_apply<T>(Cr->n, Cr->C, Cr->curved, Cr->opdata<T>(), io, MODE_APPLY, s));
-    HIP_TRY(launch_cg_scatter<T>(c.geo, cg_tab<T>(c), dy, y, skip, s, mode, r, z, d, dinv, coef));
+    io.x = x; io.y = dy; io.parts = SIPG_PART_CELL | SIPG_PART_BOUNDARY; io.skip = skip;
+    io.xnb = static_cast<const T*>(c.dgx);
+    io.cj = c.geo.j; io.cMx = c.geo.Mx; io.cMy = c.geo.My;
+    io.cnv = (long long)c.geo.Mx * c.geo.My * c.geo.Mz;
+    const CgL<T>& L = cg_tab<T>(c);
+    for (int q = 0; q < kMaxN; ++q)
+        for (int a = 0; a < kMaxN; ++a) io.cL[q][a] = L.L[q][a];
+    HIP_TRY(launch_apply<T>(Cr->n, Cr->C, Cr->curved, Cr->opdata<T>(), io, MODE_CONT, s));
+    HIP_TRY(launch_cg_assemble<T>(c.geo, dy, y, skip, s, mode, r, z, d, dinv, coef));
     return SIPG_OK;
 }
 

@@ -14,6 +14,9 @@ static hipError_t launch_nc(const OpData<T>& op, const ApplyIO<T>& io, int mode,
     else if (mode == MODE_RESID)
         hipLaunchKernelGGL((k_apply<N, C, T, CURVED, MODE_RESID, false>), dim3(blocks), dim3(Sh::THREADS), 0, s, op,
                            io);
+    else if (mode == MODE_CONT)
+        hipLaunchKernelGGL((k_apply<N, C, T, CURVED, MODE_CONT, false>), dim3(blocks), dim3(Sh::THREADS), 0, s, op,
+                           io);
     else
         hipLaunchKernelGGL((k_apply<N, C, T, CURVED, MODE_CHEB, false>), dim3(blocks), dim3(Sh::THREADS), 0, s, op,
                            io);

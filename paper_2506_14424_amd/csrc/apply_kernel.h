@@ -271,7 +271,7 @@ __device__ __forceinline__ void face_prefetch(const OpData<T>& op, const ApplyIO
         trilinear_coeffs(op.verts, op.nx, op.ny, ci.ex + (D == 0 ? dn : 0), ci.ey + (D == 1 ? dn : 0),
                          ci.ez + (D == 2 ? dn : 0), ci.t % 3, gn);
     }
-    const T* xn = io.x + (size_t)en * (C * NNN);
+    const T* xn = (io.xnb ? io.xnb : io.x) + (size_t)en * (C * NNN);
     const bool ld = live && has_nb;
 #pragma unroll
     for (int c = 0; c < C; ++c)
@@ -667,7 +667,7 @@ __device__ __forceinline__ void face_pass_pen(const OpData<T>& op, const ApplyIO
     else if (D == 1) fid = op.nfx + (ci.ez * (op.ny + 1) + ci.ey + s) * op.nx + ci.ex;
     else fid = op.nfx + op.nfy + ((ci.ez + s) * op.ny + ci.ey) * op.nx + ci.ex;
     // neighbour line and face factor: every index is valid on every lane
-    const T* xn = io.x + (size_t)en * (C * NNN);
+    const T* xn = (io.xnb ? io.xnb : io.x) + (size_t)en * (C * NNN);
     T nbl[C][N];
 #pragma unroll
     for (int c = 0; c < C; ++c)
@@ -941,7 +941,59 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
 #pragma unroll
         for (int q3 = 0; q3 < N; ++q3) muq[q3] = op.mu_cell[(size_t)ci.ec * NNN + q3 * NN + t];
     T g3[C][N];
-    {
+    if constexpr (MODE == MODE_CONT) {
+        // the cell's Lobatto values (own xi_3 column (i1, i2, .) per thread),
+        // then Lobatto -> Gauss along xi_1 and xi_2 (lines, in place in LDS)
+        // and xi_3 (own column, in registers)
+        const int jd = io.cj;
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                const T v = io.x[c * io.cnv + ((long long)(ci.ez * jd + j) * io.cMy + ci.ey * jd + i2) * io.cMx +
+                                 ci.ex * jd + i1];  // ec = 0 on inactive lanes: in bounds
+                su[c * CS + vo.oz[j]] = ci.active ? v : T(0);
+            }
+        stage_sync<THREADS>();
+#pragma unroll
+        for (int pass = 0; pass < 2; ++pass) {
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                T v[N];
+#pragma unroll
+                for (int a = 0; a < N; ++a) v[a] = su[c * CS + (pass == 0 ? vo.ox[a] : vo.oy[a])];
+#pragma unroll
+                for (int q = 0; q < N; ++q) {
+                    T acc = 0;
+#pragma unroll
+                    for (int a = 0; a < N; ++a) acc += io.cL[q][a] * v[a];
+                    su[c * CS + (pass == 0 ? vo.ox[q] : vo.oy[q])] = acc;
+                }
+            }
+            stage_sync<THREADS>();
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            T v[N], col[N];
+#pragma unroll
+            for (int a = 0; a < N; ++a) v[a] = su[c * CS + vo.oz[a]];
+#pragma unroll
+            for (int q = 0; q < N; ++q) {
+                T acc = 0;
+#pragma unroll
+                for (int a = 0; a < N; ++a) acc += io.cL[q][a] * v[a];
+                col[q] = acc;
+            }
+#pragma unroll
+            for (int q = 0; q < N; ++q) {
+                su[c * CS + vo.oz[q]] = col[q];
+                T a = 0;
+#pragma unroll
+                for (int j = 0; j < N; ++j) a += tb.D[q][j] * col[j];
+                g3[c][q] = a;
+            }
+        }
+    } else {
         const T* xe = io.x + (size_t)ci.ec * (C * NNN);
 #pragma unroll
         for (int c = 0; c < C; ++c) {
@@ -1147,6 +1199,46 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
     }
 
     // ------------------------------------------------------------ store
+    if constexpr (MODE == MODE_CONT) {
+        // local contributions G_e^T y: Gauss -> Lobatto transposed along xi_3
+        // (own column), then xi_2 and xi_1 (lines in LDS; every lane takes
+        // part, inactive cells write nothing)
+        stage_sync<THREADS>();   // the face passes' last reads of su
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+                T acc = 0;
+#pragma unroll
+                for (int q = 0; q < N; ++q) acc += io.cL[q][a] * y[c][q];
+                su[c * CS + vo.oz[a]] = acc;
+            }
+        stage_sync<THREADS>();
+#pragma unroll
+        for (int pass = 0; pass < 2; ++pass) {
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                T v[N];
+#pragma unroll
+                for (int q = 0; q < N; ++q) v[q] = su[c * CS + (pass == 0 ? vo.oy[q] : vo.ox[q])];
+#pragma unroll
+                for (int a = 0; a < N; ++a) {
+                    T acc = 0;
+#pragma unroll
+                    for (int q = 0; q < N; ++q) acc += io.cL[q][a] * v[q];
+                    su[c * CS + (pass == 0 ? vo.oy[a] : vo.ox[a])] = acc;
+                }
+            }
+            stage_sync<THREADS>();
+        }
+        if (!ci.active) return;
+        const size_t base = (size_t)ci.ec * (C * NNN);
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int j = 0; j < N; ++j) io.y[base + (c * N + j) * NN + t] = su[c * CS + vo.oz[j]];
+        return;
+    }
     if (!ci.active) return;
     const size_t base = (size_t)ci.ec * (C * NNN);
     if constexpr (MODE == MODE_APPLY) {

@@ -15,6 +15,9 @@ static hipError_t launch_pen_n(const OpData<T>& op, const ApplyIO<T>& io, int mo
     else if (mode == MODE_RESID)
         hipLaunchKernelGGL((k_apply<N, 3, T, CURVED, MODE_RESID, true>), dim3(blocks), dim3(Sh::THREADS), 0, s, op,
                            io);
+    else if (mode == MODE_CONT)
+        hipLaunchKernelGGL((k_apply<N, 3, T, CURVED, MODE_CONT, true>), dim3(blocks), dim3(Sh::THREADS), 0, s, op,
+                           io);
     else
         hipLaunchKernelGGL((k_apply<N, 3, T, CURVED, MODE_CHEB, true>), dim3(blocks), dim3(Sh::THREADS), 0, s, op,
                            io);

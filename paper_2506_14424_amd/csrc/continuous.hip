@@ -470,6 +470,19 @@ hipError_t launch_cg_scatter(const CgGeo& g, const CgL<T>& tab, T* dg, T* cg, co
 }
 
 template <typename T>
+hipError_t launch_cg_assemble(const CgGeo& g, const T* local, T* cg, const int* skip, hipStream_t s, int mode,
+                              const T* r, const T* z, T* d, const T* dinv, const double* coef) {
+    const long long total = (long long)g.Mx * g.My * g.Mz * g.C;
+    AsmIO<T> io;
+    io.r = r; io.z = z; io.d = d; io.dinv = dinv; io.coef = coef;
+    const dim3 ag(grid_for(total));
+    if (mode == 1) hipLaunchKernelGGL((k_cg_assemble<T, ASM_RESID>), ag, dim3(kThreads), 0, s, g, local, cg, io, skip);
+    else if (mode == 2) hipLaunchKernelGGL((k_cg_assemble<T, ASM_CHEB>), ag, dim3(kThreads), 0, s, g, local, cg, io, skip);
+    else hipLaunchKernelGGL((k_cg_assemble<T, ASM_SUM>), ag, dim3(kThreads), 0, s, g, local, cg, io, skip);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_axis(const AxisMat<T>& M, int axis, int C, int n0, int n1, int n2, const T* in, T* out, bool add,
                        const int* skip, hipStream_t s) {
     long long total = (long long)C * (axis == 0 ? M.rows : n0) * (axis == 1 ? M.rows : n1) * (axis == 2 ? M.rows : n2);
@@ -533,6 +546,8 @@ hipError_t launch_dense_mv(const double* Ainv, const T* r, T* z, int n, const in
     template hipError_t launch_cg_gather<T>(const CgGeo&, const CgL<T>&, const T*, T*, bool, const int*, hipStream_t); \
     template hipError_t launch_cg_scatter<T>(const CgGeo&, const CgL<T>&, T*, T*, const int*, hipStream_t, int,    \
                                              const T*, const T*, T*, const T*, const double*);                    \
+    template hipError_t launch_cg_assemble<T>(const CgGeo&, const T*, T*, const int*, hipStream_t, int, const T*,   \
+                                              const T*, T*, const T*, const double*);                              \
     template hipError_t launch_axis<T>(const AxisMat<T>&, int, int, int, int, int, const T*, T*, bool, const int*,  \
                                        hipStream_t);                                                                \
     template hipError_t launch_cg_cheb<T>(const T*, T*, T*, const T*, const T*, const T*, const double*, long long, \

@@ -51,8 +51,9 @@ struct LawDev {
     double phi[SIPG_MAX_MODES];
 };
 
-// MODE_APPLY: y = A x;  MODE_CHEB: Chebyshev step (below);  MODE_RESID: y = r - A x
-enum ApplyMode { MODE_APPLY = 0, MODE_CHEB = 1, MODE_RESID = 2 };
+// MODE_APPLY: y = A x;  MODE_CHEB: Chebyshev step (below);  MODE_RESID: y = r - A x;
+// MODE_CONT: a continuous level of the multigrid hierarchy (below)
+enum ApplyMode { MODE_APPLY = 0, MODE_CHEB = 1, MODE_RESID = 2, MODE_CONT = 3 };
 
 // Vector arguments of one operator application.
 template <typename T>
@@ -66,6 +67,17 @@ struct ApplyIO {
     T* d;
     const double* coef;  // device {c1, c2}
     const int* skip;     // device flag: nonzero => kernel returns at once (may be null)
+    // MODE_CONT: x holds the values of a continuous level at its Gauss-Lobatto
+    // nodes (degree cj, cMx * cMy * (cj nz + 1) nodes per component,
+    // component-major); the kernel interpolates every cell's values to its
+    // Gauss nodes (cL[q][a] = l^Lobatto_a(x^Gauss_q)), applies the operator
+    // and writes the cell's local contributions G_e^T (A G x) to y (DG
+    // layout).  xnb: a DG-sized array the face passes may read their
+    // (unused) neighbour values from; null: x.
+    const T* xnb;
+    int cj, cMx, cMy;
+    long long cnv;
+    T cL[kMaxN][kMaxN];
 };
 
 // Device-side state of one CG solve (lives in the workspace).
@@ -247,6 +259,10 @@ template <typename T>
 hipError_t launch_cg_scatter(const CgGeo& g, const CgL<T>& tab, T* dg, T* cg, const int* skip, hipStream_t s,
                              int mode = 0, const T* r = nullptr, const T* z = nullptr, T* d = nullptr,
                              const T* dinv = nullptr, const double* coef = nullptr);
+// the node sums alone (modes as launch_cg_scatter), from the cells' local contributions
+template <typename T>
+hipError_t launch_cg_assemble(const CgGeo& g, const T* local, T* cg, const int* skip, hipStream_t s, int mode,
+                              const T* r, const T* z, T* d, const T* dinv, const double* coef);
 template <typename T>
 hipError_t launch_axis(const AxisMat<T>& M, int axis, int C, int n0, int n1, int n2, const T* in, T* out, bool add,
                        const int* skip, hipStream_t s);
