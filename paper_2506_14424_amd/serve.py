@@ -103,13 +103,18 @@ class GpuExecutor:
             req.x = handle[2].detach().clone()
 
 
+class ServingStall(RuntimeError):
+    """No active request finished for `stall_timeout` seconds."""
+
+
 class Server:
     def __init__(self, executor, hbm_budget: int = 8 << 30, max_active: int = 32,
-                 iters_per_round: int = 4):
+                 iters_per_round: int = 4, stall_timeout: float = 120.0):
         self.ex = executor
         self.budget = int(hbm_budget)
         self.max_active = max_active
         self.iters = iters_per_round
+        self.stall_timeout = stall_timeout
         self.used = 0
         self.peak_used = 0
         self.peak_active = 0
@@ -121,8 +126,16 @@ class Server:
         completed: list[Request] = []
         t0 = clock()
         i = 0
+        last_progress = 0.0           # time of the last completion (or of the run's start)
         while i < len(pending) or waiting or active:
             now = clock() - t0
+            if active and now - last_progress > self.stall_timeout:
+                # the loop only enqueues and polls; with requests on the
+                # device and none finishing, the device queues have stopped
+                # retiring work: report what is in flight instead of spinning
+                raise ServingStall(
+                    f"no request finished for {now - last_progress:.1f} s; in flight: "
+                    + ", ".join(f"{r.id} (admitted {r.admitted:.2f} s)" for r, _ in active))
             while i < len(pending) and pending[i].arrival <= now:
                 req = pending[i]
                 op, req.footprint = self.ex.prepare(req)
@@ -166,6 +179,7 @@ class Server:
                     done, info = True, {"status": f"failed: {exc}", "iterations": -1}
                 if done:
                     req.finished = clock() - t0
+                    last_progress = req.finished
                     req.info = info
                     self.ex.release(req, h)
                     self.used -= req.footprint

@@ -106,3 +106,53 @@ def test_latency_accounts_for_arrival_times():
     for r in reqs:
         assert r.admitted >= r.arrival and r.finished > r.admitted
         assert r.finished - r.arrival < 0.5
+
+
+class OutOfOrderExecutor(FakeExecutor):
+    """Each solve needs a seeded random number of polls before its status
+    read-back shows it done (device work of different streams finishing in
+    any order, polls that find nothing new)."""
+
+    def __init__(self, seed):
+        super().__init__()
+        self.rng = np.random.default_rng(seed)
+
+    def start(self, req, op):
+        h = super().start(req, op)
+        h["polls"] = int(self.rng.integers(1, 40))
+        return h
+
+    def poll(self, h):
+        h["polls"] -= 1
+        if h["left"] == 0 and h["polls"] <= 0:
+            return True, {"status": "SIPG_OK", "iterations": h["done"]}
+        return False, None
+
+
+def test_out_of_order_completion_drains_every_request():
+    for seed in range(5):
+        ex = OutOfOrderExecutor(seed)
+        reqs = [make(i, 0.002 * i, 100 + 37 * (i % 5), 3 + i % 7) for i in range(40)]
+        clk = FakeClock()
+        out = Server(ex, hbm_budget=600, max_active=6, iters_per_round=2).run(reqs, clock=clk, sleep=clk.sleep)
+        assert out["requests"] == 40 and out["converged"] == 40 and not out["failed"]
+        assert ex.live_bytes == 0 and out["peak_reserved"] <= 600
+
+
+class StuckExecutor(FakeExecutor):
+    """Request 1 never finishes (its device queue stops retiring work)."""
+
+    def poll(self, h):
+        if h["req"].id == 1:
+            return False, None
+        return super().poll(h)
+
+
+def test_stalled_device_work_is_reported_not_spun_on():
+    import pytest
+    from paper_2506_14424_amd.serve import ServingStall
+    ex = StuckExecutor()
+    reqs = [make(i, 0.0, 10, 4) for i in range(4)]
+    clk = FakeClock(dt=0.01)
+    with pytest.raises(ServingStall, match="in flight: 1"):
+        Server(ex, hbm_budget=100, stall_timeout=5.0).run(reqs, clock=clk, sleep=clk.sleep)
