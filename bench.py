@@ -662,7 +662,10 @@ def main():
         print(json.dumps({"split_step": split_step(), "split_step_32": split_step_32()}), flush=True)
         return
     if args.apply_only:
-        print(json.dumps(apply_only(args.apply_only, args.steps, args.warmup)), flush=True)
+        out = apply_only(args.apply_only, args.steps, args.warmup)
+        if args.copy_probe:
+            out["copy_probe"] = copy_probe()
+        print(json.dumps(out), flush=True)
         return
 
     import torch
