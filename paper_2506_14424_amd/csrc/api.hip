@@ -200,6 +200,7 @@ struct CgLevel {
     double *pv64[3] = {}, *rv64[3] = {};
     float *pv32[3] = {}, *rv32[3] = {};
     double* cinv = nullptr;          // coarsest: dense inverse
+    double* cwork = nullptr;         // coarsest: the inversion's second buffer
     double* probes = nullptr;        // coarsest: the carrier applied to C*8 probe vectors
     bool lz_valid = false, lz_stale = false;
     int lz_steps = 0;
@@ -314,7 +315,7 @@ struct Layout {
     size_t mgz = 0, mgt = 0;          // multigrid: finest-level vectors
     std::vector<size_t> level, level_bytes;   // multigrid: workspaces of the coarser levels
     struct Cg {
-        size_t vec[8], diag64, dinv64, dinv32, dgx, dgy, st, partials, cinv, probes;
+        size_t vec[8], diag64, dinv64, dinv32, dgx, dgy, st, partials, cinv, cwork, probes;
         size_t prp[3], pci[3], pv64[3], pv32[3], rrp[3], rci[3], rv64[3], rv32[3];
     };
     std::vector<Cg> cg;               // continuous levels
@@ -366,6 +367,7 @@ Layout layout(const sipg_plan* P) {
             g.rv64[a] = take(c.R[a].v.size() * 8); g.rv32[a] = take(c.R[a].v.size() * 4);
         }
         g.cinv = c.direct ? take((size_t)c.n * c.n * 8) : 0;
+        g.cwork = c.direct ? take(((size_t)c.n * c.n + 1) * 8) : 0;
         g.probes = c.direct ? take((size_t)c.geo.C * 8 * c.dgsize * 8) : 0;
         L.cg.push_back(g);
     }
@@ -556,7 +558,7 @@ sipg_status refresh_continuous(sipg_plan* P, hipStream_t s) {
                 io.parts = SIPG_PART_CELL | SIPG_PART_BOUNDARY;
                 HIP_TRY(launch_apply<double>(Cr->n, Cr->C, Cr->curved, Cr->opdata<double>(), io, MODE_APPLY, s));
             }
-            HIP_TRY(launch_cg_coarse_inverse(c.geo, c.probes, c.dgsize, c.L64, c.cinv,
+            HIP_TRY(launch_cg_coarse_inverse(c.geo, c.probes, c.dgsize, c.L64, c.cinv, c.cwork,
                                              pure_neumann_poisson(P) ? 1 : 0, s));
         }
     }
@@ -1301,6 +1303,7 @@ sipg_status sipg_plan_bind(sipg_plan* P, void* workspace, size_t bytes, int32_t 
                 if (!c.R[a].v.empty()) sk_cast(c.rv32[a], c.rv64[a], (long long)c.R[a].v.size(), s);
             }
             c.cinv = c.direct ? reinterpret_cast<double*>(w + g.cinv) : nullptr;
+            c.cwork = c.direct ? reinterpret_cast<double*>(w + g.cwork) : nullptr;
             c.probes = c.direct ? reinterpret_cast<double*>(w + g.probes) : nullptr;
             c.lz_valid = false;
         }

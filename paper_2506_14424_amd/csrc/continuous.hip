@@ -351,7 +351,7 @@ __global__ void k_cg_probe(double* v, int C, long long ncell, int col) {
 // vi), J = (c', vertex vj), sums over the cells holding both vertices
 // G_e[q][vi] K_e[(c, q), (c', q')] G_e[q'][vj], G_e the trilinear vertex
 // basis at the Gauss nodes.  Pure-Neumann Poisson (mean_zero): plus
-// mean(diag) / n on every entry (added by k_gauss_jordan).
+// mean(diag) / n on every entry (added before the inversion).
 __global__ void k_cg_coarse_matrix(CgGeo g, const double* probes, long long dgsize, const CgL<double> tab,
                                    double* A) {
     const long long nv = (long long)g.Mx * g.My * g.Mz, nc = nv * g.C;
@@ -383,48 +383,42 @@ __global__ void k_cg_coarse_matrix(CgGeo g, const double* probes, long long dgsi
     }
 }
 
-// In-place inverse of the symmetric positive definite n x n matrix A by
-// Gauss-Jordan elimination without pivoting, in one block: for every pivot
-// k the pivot row (scaled) and column are staged in LDS, then all n^2
-// entries are updated with coalesced accesses (row-major, threads along the
-// columns).  mean_zero: A + mean(diag A) / n first (the pure-Neumann Poisson
-// problem's constants).
-constexpr int kGjThreads = 1024;
-constexpr int kGjMax = 2048;
-__global__ void __launch_bounds__(kGjThreads) k_gauss_jordan(double* A, int n, int mean_zero) {
-    __shared__ double row[kGjMax], col[kGjMax];
-    __shared__ double red[kGjThreads / 64];
-    if (mean_zero) {
-        double s = 0.0;
-        for (int i = threadIdx.x; i < n; i += kGjThreads) s += A[(long long)i * n + i];
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double t = 0.0;
-            for (int w = 0; w < kGjThreads / 64; ++w) t += red[w];
-            red[0] = t / n / n;
-        }
-        __syncthreads();
-        const double shift = red[0];
-        for (long long i = threadIdx.x; i < (long long)n * n; i += kGjThreads) A[i] += shift;
-        __syncthreads();
-    }
+// Inverse of the symmetric positive definite n x n matrix of the coarsest
+// level by Gauss-Jordan elimination without pivoting, one kernel per pivot
+// over the whole device: step k reads only the previous matrix Ain (its
+// pivot row and column) and writes the next one Aout, so the n steps
+// alternate between two buffers and no step races with itself.
+//   Aout[k][j] = Ain[k][j] / p (j != k),  Aout[k][k] = 1 / p,
+//   Aout[i][j] = Ain[i][j] - Ain[i][k] Ain[k][j] / p,  Aout[i][k] = -Ain[i][k] / p  (i != k).
+__global__ void k_gj_step(const double* Ain, double* Aout, int n, int k) {
+    const double pinv = 1.0 / Ain[(long long)k * n + k];
     const long long nn = (long long)n * n;
-    for (int k = 0; k < n; ++k) {
-        const double pinv = 1.0 / A[(long long)k * n + k];
-        for (int t = threadIdx.x; t < n; t += kGjThreads) {
-            row[t] = (t == k ? 1.0 : A[(long long)k * n + t]) * pinv;   // new row k
-            col[t] = t == k ? 0.0 : A[(long long)t * n + k];              // multipliers of the other rows
-        }
-        __syncthreads();
-        for (long long idx = threadIdx.x; idx < nn; idx += kGjThreads) {
-            const int i = (int)(idx / n), jj = (int)(idx - (long long)i * n);
-            if (i == k) A[idx] = row[jj];
-            else A[idx] = (jj == k ? 0.0 : A[idx]) - col[i] * row[jj];
-        }
+    GRID_STRIDE(idx, nn) {
+        const int i = (int)(idx / n), jj = (int)(idx - (long long)i * n);
+        const double rk = jj == k ? pinv : Ain[(long long)k * n + jj] * pinv;   // new row k
+        if (i == k) Aout[idx] = rk;
+        else Aout[idx] = (jj == k ? 0.0 : Ain[idx]) - Ain[(long long)i * n + k] * rk;
+    }
+}
+
+// Pure-Neumann Poisson: A + mean(diag A) / n on every entry (one block
+// sums the diagonal in a fixed order, then every entry is shifted).
+__global__ void k_mean_diag_shift(double* A, int n, double* shift) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) s += A[(long long)i * n + i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
+    if (threadIdx.x == 0) *shift = red[0] / n / n;
+}
+
+__global__ void k_add_shift(double* A, long long nn, const double* shift) {
+    const double v = *shift;
+    GRID_STRIDE(i, nn) A[i] += v;
 }
 
 // z = Ainv r (FP64 products and sums): one wavefront per row.
@@ -529,10 +523,17 @@ hipError_t launch_cg_probe(double* v, int C, long long ncell, int col, hipStream
 }
 
 hipError_t launch_cg_coarse_inverse(const CgGeo& g, const double* probes, long long dgsize, const CgL<double>& tab,
-                                    double* A, int mean_zero, hipStream_t s) {
-    const long long nc = (long long)g.Mx * g.My * g.Mz * g.C;
-    hipLaunchKernelGGL(k_cg_coarse_matrix, dim3(grid_for(nc * nc)), dim3(kThreads), 0, s, g, probes, dgsize, tab, A);
-    hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(kGjThreads), 0, s, A, (int)nc, mean_zero);
+                                    double* A, double* work, int mean_zero, hipStream_t s) {
+    const long long nc = (long long)g.Mx * g.My * g.Mz * g.C, nn = nc * nc;
+    // the steps alternate between A and work; start where the last step writes A
+    double* buf[2] = {(nc % 2 == 0) ? A : work, (nc % 2 == 0) ? work : A};
+    hipLaunchKernelGGL(k_cg_coarse_matrix, dim3(grid_for(nn)), dim3(kThreads), 0, s, g, probes, dgsize, tab, buf[0]);
+    if (mean_zero) {
+        hipLaunchKernelGGL(k_mean_diag_shift, dim3(1), dim3(256), 0, s, buf[0], (int)nc, work + nn);
+        hipLaunchKernelGGL(k_add_shift, dim3(grid_for(nn)), dim3(kThreads), 0, s, buf[0], nn, work + nn);
+    }
+    for (int k = 0; k < (int)nc; ++k)
+        hipLaunchKernelGGL(k_gj_step, dim3(grid_for(nn)), dim3(kThreads), 0, s, buf[k & 1], buf[(k + 1) & 1], (int)nc, k);
     return hipGetLastError();
 }
 

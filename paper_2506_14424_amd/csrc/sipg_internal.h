@@ -274,8 +274,9 @@ hipError_t launch_cg_sub(T* y, const T* r, const T* t, long long n, const int* s
 hipError_t launch_cg_diagonal(const CgGeo& g, const OpData<double>& op, const CgDiagTab& tab, double* local,
                               double* diag, double* dinv64, float* dinv32, hipStream_t s);
 hipError_t launch_cg_probe(double* v, int C, long long ncell, int col, hipStream_t s);
+// A (n x n) = the inverse of the coarsest level's matrix; work: n * n + 1 doubles
 hipError_t launch_cg_coarse_inverse(const CgGeo& g, const double* probes, long long dgsize, const CgL<double>& tab,
-                                    double* A, int mean_zero, hipStream_t s);
+                                    double* A, double* work, int mean_zero, hipStream_t s);
 template <typename T>
 hipError_t launch_dense_mv(const double* Ainv, const T* r, T* z, int n, const int* skip, hipStream_t s);
 
