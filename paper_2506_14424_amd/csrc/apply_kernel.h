@@ -16,7 +16,11 @@
 // n*n lines of each direction), so all sweep coefficients are the same for
 // the whole wavefront and stay in scalar registers; lines are exchanged
 // through LDS between sweeps.  The thread (i1, i2) owns the xi_3 line
-// (i1, i2, 0..n-1) of quadrature points and outputs.
+// (i1, i2, 0..n-1) of quadrature points and outputs.  FP64 n = 4 runs the
+// sweeps across lanes (xi_1, xi_2 in the cell term, the tangential
+// directions of a face) as FP64 matrix-core products of 4 x 4 tiles, one
+// tile per cell of the wavefront (mf_r, mf_c); its lanes are ordered for
+// that (lane 16 i1 + 4 cell + i2).
 //
 // Forms (Sec. 4.1), per quadrature point, for the test functions of the cell
 // that owns the thread (outward unit normal n, [u] = u_own - u_nbr):
@@ -66,12 +70,35 @@ struct Shape {
     // (DPP) instead of through LDS; their only LDS array left is the
     // projection's, so the FP64 pad shrinks to 4 and the per-lane derivative
     // table fits in the same 20 KB
-    static constexpr bool DPP = N == 4 || N == 2;
+    // FP64 n = 4: the 1D sweeps across lanes run on the matrix cores instead
+    // (v_mfma_f64_4x4x4: four 16-lane blocks, each a 4 x 4 product that
+    // contracts over lane bits 5:4).  Lane 16 i1 + 4 cell + i2 owns the xi_3
+    // column (i1, i2) of its cell, so a 4 x 4 tile of points (i1, i2) of the
+    // four cells is one operand: sweeps along i1 are one product, sweeps
+    // along i2 a product with the identity (which moves i2 to bits 5:4)
+    // and then one more.  No DPP moves, and the cell pass needs no LDS.
+    static constexpr bool MF = DBL && N == 4;
+    static constexpr bool DPP = (N == 4 && !MF) || N == 2;
     // n = 2 (cell and face passes across lanes): only the projection's
     // coefficient array remains, so the work space shrinks to that
     static constexpr int W = N == 2 ? 2 * C * NN + 1
+                           : MF     ? 2 * C * NN + 4
                                     : (2 * C * CS > 8 * C * NN ? 2 * C * CS : 8 * C * NN) + (SKEW ? (DPP ? 4 : 8) : 1);
 };
+
+// Matrix-core sweeps of a 4 x 4 tile per cell (FP64 n = 4 layout, lane
+// 16 r + 4 cell + c holds U[r][c] of its cell).  m is the lane's entry
+// M[c][r] of the 1D matrix M; id is (r == c).
+//   mf_r: V[i][c] = sum_k M[i][k] U[k][c]   (one product, in place)
+//   mf_c: V[r][j] = sum_k M[j][k] U[r][k]   (the identity product gives the
+//         transpose of U, whose rows then contract with M^T)
+__device__ __forceinline__ double mf_r(double u, double m) {
+    return __builtin_amdgcn_mfma_f64_4x4x4f64(m, u, 0.0, 0, 0, 0);
+}
+__device__ __forceinline__ double mf_c(double u, double m, double id) {
+    const double ut = __builtin_amdgcn_mfma_f64_4x4x4f64(u, id, 0.0, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f64_4x4x4f64(ut, m, 0.0, 0, 0, 0);
+}
 
 // Barrier between LDS stages.  A workgroup of one wavefront only needs the
 // wavefront's own (in-order) LDS accesses fenced against compiler reordering.
@@ -155,6 +182,7 @@ __device__ __forceinline__ void inverse_from_columns(const T a[3][3], T Ji[3][3]
 struct CellIdx {
     int lc, t, i1, i2, ec, ex, ey, ez;
     int ra[4], rb[4];  // n = 4: a / b index of the lane whose value line_a / line_b delivers in slot r
+    double md, mt, mi; // matrix-core layout: D[i2][i1], D[i1][i2], (i1 == i2)
     bool active;
 };
 
@@ -324,12 +352,13 @@ __device__ __forceinline__ void face_pass(const OpData<T>& op, const ApplyIO<T>&
     else if (D == 1) fid = op.nfx + (ci.ez * (op.ny + 1) + ci.ey + s) * op.nx + ci.ex;
     else fid = op.nfx + op.nfy + ((ci.ez + s) * op.ny + ci.ey) * op.nx + ci.ex;
     constexpr bool DPP = Shape<N, C, sizeof(T) == 8>::DPP;
+    constexpr bool MF = Shape<N, C, sizeof(T) == 8>::MF;
     // LDS regions of the work space, each [.][C][NN]
     T* FT = sw;               // [2] trace values (own, neighbour)          A  -> B1
     T* TD = sw + 2 * C * NN;  // [2][2] tangential derivatives (side, dir)  B1 -> B2
     T* BT = sw;               // [2] flux components along t1, t2           B2 -> C1
     T* VT = sw + 2 * C * NN;  // [2] transposed sweeps                      C1 -> C2
-    T* VV = sw + (DPP ? 0 : 6 * C * NN);  // [2] value / normal coefficients (D < 2)    C2
+    T* VV = sw + (DPP || MF ? 0 : 6 * C * NN);  // [2] value / normal coefficients (D < 2)    C2
 
     // ---- A: traces
     T ju[C], uno[C], unn[C];  // jump u_own - u_nbr (mirror state on Dirichlet faces), normal derivatives
@@ -353,7 +382,7 @@ __device__ __forceinline__ void face_pass(const OpData<T>& op, const ApplyIO<T>&
         unn[c] = w1;
         tv[c] = v0;
         tw[c] = w0;
-        if constexpr (!DPP) {
+        if constexpr (!DPP && !MF) {
             FT[c * NN + t] = v0;
             FT[(C + c) * NN + t] = w0;
         }
@@ -363,11 +392,11 @@ __device__ __forceinline__ void face_pass(const OpData<T>& op, const ApplyIO<T>&
 #pragma unroll
             for (int k = 0; k < 8; ++k) geo[1][k][t] = gnb[k];
     }
-    if constexpr (CURVED || !DPP) stage_sync<THREADS>();
+    if constexpr (CURVED || !(DPP || MF)) stage_sync<THREADS>();
 
     // ---- B1: tangential derivatives; task k = ((side*2 + dir)*C + c)*N + line
-    // (n = 4: computed per lane from cross-lane moves at the start of B2)
-    if constexpr (!DPP)
+    // (n = 4: computed per lane from cross-lane moves or matrix-core products in B2)
+    if constexpr (!DPP && !MF)
 #pragma unroll
     for (int k0 = 0; k0 < 4 * C * N; k0 += NN) {
         const int k = k0 + t;
@@ -389,7 +418,7 @@ __device__ __forceinline__ void face_pass(const OpData<T>& op, const ApplyIO<T>&
             }
         }
     }
-    if constexpr (!DPP) stage_sync<THREADS>();
+    if constexpr (!DPP && !MF) stage_sync<THREADS>();
 
     // ---- B2: geometry and flux at the face point
     //
@@ -478,13 +507,30 @@ __device__ __forceinline__ void face_pass(const OpData<T>& op, const ApplyIO<T>&
                 n1 += da[j] * ma[j];
                 n2 += db[j] * mb[j];
             }
+        } else if constexpr (MF) {
+            // whole-wavefront products: outside any lane-dependent branch
+            o1 = mf_r(tv[c], ci.md);
+            n1 = mf_r(tw[c], ci.md);
+            o2 = mf_c(tv[c], ci.md, ci.mi);
+            n2 = mf_c(tw[c], ci.md, ci.mi);
         } else {
             o1 = TD[(0 * C + c) * NN + t];
             o2 = TD[(1 * C + c) * NN + t];
             n1 = TD[(2 * C + c) * NN + t];
             n2 = TD[(3 * C + c) * NN + t];
         }
-        if (has_nb) {
+        if constexpr (MF) {
+            // selects, not branches, so that the products stay unconditional
+            T gD = unn[c];
+            if constexpr (CURVED) {
+                T nr[3];
+                nr[t1] = n1; nr[t2] = n2; nr[D] = unn[c];
+                gD = nr[0] * v[0] + nr[1] * v[1] + nr[2] * v[2];
+            }
+            gs[c][t1] = o1 + (has_nb ? n1 : o1);
+            gs[c][t2] = o2 + (has_nb ? n2 : o2);
+            gs[c][D] = uno[c] + (has_nb ? gD : uno[c]);
+        } else if (has_nb) {
             gs[c][t1] = o1 + n1;
             gs[c][t2] = o2 + n2;
             if constexpr (CURVED) {
@@ -566,6 +612,12 @@ __device__ __forceinline__ void face_pass(const OpData<T>& op, const ApplyIO<T>&
             }
             vt[0][c] = a1;
             vt[1][c] = a2;
+        }
+    } else if constexpr (MF) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            vt[0][c] = mf_r(Bh[c][t1], ci.mt);
+            vt[1][c] = mf_c(Bh[c][t2], ci.mt, ci.mi);
         }
     } else {
     stage_sync<THREADS>();  // TD reads done before BT/VT overwrite the space
@@ -861,6 +913,105 @@ __device__ __forceinline__ void cell_pass_dpp(const OpData<T>& op, const CellIdx
         }
 }
 
+// Cell term on the matrix cores (FP64 n = 4): the xi_1 and xi_2 derivatives
+// of each xi_3 slice are tile products (mf_r, mf_c), the xi_3 derivative is
+// the lane's own column (g3); the stress is formed pointwise and its xi_1 /
+// xi_2 test-function sweeps are the transposed products.
+template <int N, int C, typename T, bool CURVED, bool PEN>
+__device__ __forceinline__ void cell_pass_mf(const OpData<T>& op, const CellIdx& ci, const T* su, T (*geo)[8][3],
+                                             const LaneTab<T, N>& lt, const VolOff<N>& vo, T (&g3)[C][N],
+                                             const T (&muq)[N], T (&y)[C][N]) {
+    constexpr int CS = Shape<N, C, sizeof(T) == 8>::CS;
+    const auto& tb = op.tab;
+    const int i1 = ci.i1, i2 = ci.i2;
+    T b1[C][N], b2[C][N];  // reference derivatives on the own column, then B^_1, B^_2
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            const T u = su[c * CS + vo.oz[q]];
+            b1[c][q] = mf_r(u, ci.md);
+            b2[c][q] = mf_c(u, ci.md, ci.mi);
+        }
+    // pointwise, on the own xi_3 line: a_0 = A0 + B0 xi_3, a_1 = A1 + B1 xi_3, a_2 constant
+    T A0[3], B0[3], A1[3], B1[3], a2c[3];
+    if constexpr (CURVED) {
+        const T(*g)[3] = geo[0];
+        const T x1 = lt.x[i1], x2 = lt.x[i2];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            A0[i] = g[1][i] + g[4][i] * x2;
+            B0[i] = g[5][i] + g[7][i] * x2;
+            A1[i] = g[2][i] + g[4][i] * x1;
+            B1[i] = g[6][i] + g[7][i] * x1;
+            a2c[i] = g[3][i] + g[5][i] * x1 + g[6][i] * x2 + g[7][i] * (x1 * x2);
+        }
+    }
+#pragma unroll
+    for (int q3 = 0; q3 < N; ++q3) {
+        T Ji[3][3], JxW;
+        if constexpr (CURVED) {
+            const T x3 = tb.x[q3];
+            T a[3][3], det;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                a[0][i] = A0[i] + B0[i] * x3;
+                a[1][i] = A1[i] + B1[i] * x3;
+                a[2][i] = a2c[i];
+            }
+            inverse_from_columns(a, Ji, det);
+            JxW = det * (lt.w[i1] * lt.w[i2] * tb.w[q3]);
+        } else {
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) Ji[a][b] = a == b ? op.hinv[a] : T(0);
+            JxW = op.h[0] * op.h[1] * op.h[2] * (lt.w[i1] * lt.w[i2] * tb.w[q3]);
+        }
+        T G[C][3];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const T g1 = b1[c][q3], g2 = b2[c][q3], gg3 = g3[c][q3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) G[c][i] = g1 * Ji[0][i] + g2 * Ji[1][i] + gg3 * Ji[2][i];
+        }
+        T S[C][3];
+        if constexpr (PEN) {
+            const T dv = muq[q3] * JxW * (G[0][0] + G[1][1] + G[2][2]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int i = 0; i < 3; ++i) S[c][i] = c == i ? dv : T(0);
+        } else if constexpr (C == 3) {
+            const T f = muq[q3] * JxW;
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int i = 0; i < 3; ++i) S[c][i] = f * (G[c][i] + G[i][c]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) S[0][i] = JxW * G[0][i];
+        }
+        const T mass = op.alpha * JxW;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            b1[c][q3] = Ji[0][0] * S[c][0] + Ji[0][1] * S[c][1] + Ji[0][2] * S[c][2];
+            b2[c][q3] = Ji[1][0] * S[c][0] + Ji[1][1] * S[c][1] + Ji[1][2] * S[c][2];
+            g3[c][q3] = Ji[2][0] * S[c][0] + Ji[2][1] * S[c][1] + Ji[2][2] * S[c][2];
+            y[c][q3] = mass * su[c * CS + vo.oz[q3]];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int i3 = 0; i3 < N; ++i3) {
+            T acc = y[c][i3] + mf_r(b1[c][i3], ci.mt) + mf_c(b2[c][i3], ci.mt, ci.mi);
+#pragma unroll
+            for (int q = 0; q < N; ++q) acc += tb.D[q][i3] * g3[c][q];
+            y[c][i3] = acc;
+        }
+}
+
 // ---------------------------------------------------------------- kernel
 
 template <int N, int C, typename T, bool CURVED, int MODE, bool PEN>
@@ -884,10 +1035,18 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
     __shared__ LaneTab<T, N> s_lt;
 
     CellIdx ci;
-    ci.lc = threadIdx.x / NN;
-    ci.t = threadIdx.x - ci.lc * NN;
-    ci.i1 = ci.t % N;
-    ci.i2 = ci.t / N;
+    if constexpr (Sh::MF) {
+        // lane 16 i1 + 4 cell + i2 (the matrix-core tile layout)
+        ci.lc = (threadIdx.x >> 2) & 3;
+        ci.i1 = threadIdx.x >> 4;
+        ci.i2 = threadIdx.x & 3;
+        ci.t = ci.i2 * N + ci.i1;
+    } else {
+        ci.lc = threadIdx.x / NN;
+        ci.t = threadIdx.x - ci.lc * NN;
+        ci.i1 = ci.t % N;
+        ci.i2 = ci.t / N;
+    }
     const int e = xcd_block(blockIdx.x, gridDim.x) * CPB + ci.lc;
     ci.active = e < op.ncell;
     ci.ec = ci.active ? e : 0;
@@ -1021,6 +1180,11 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
     }
     __syncthreads();
     const LaneTab<T, N>& lt = s_lt;
+    if constexpr (Sh::MF) {
+        ci.md = lt.D[i2][i1];
+        ci.mt = lt.D[i1][i2];
+        ci.mi = i1 == i2 ? 1.0 : 0.0;
+    }
 
     T y[C][N];
 #pragma unroll
@@ -1031,6 +1195,8 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
     // ------------------------------------------------------------ cell
     if constexpr (N == 2) {
         if (io.parts & SIPG_PART_CELL) cell_pass_dpp<N, C, T, CURVED, PEN>(op, ci, su, geo, lt, vo, g3, muq, y);
+    } else if constexpr (Sh::MF) {
+        if (io.parts & SIPG_PART_CELL) cell_pass_mf<N, C, T, CURVED, PEN>(op, ci, su, geo, lt, vo, g3, muq, y);
     } else if (io.parts & SIPG_PART_CELL) {
         T* W1 = sw;            // [C][NNN] d/dxi_1, then B^_1
         T* W2 = sw + C * CS;  // [C][NNN] d/dxi_2, then B^_2
