@@ -466,6 +466,8 @@ sipg_status sipg_update_penalty_factors(sipg_plan* pen, const double* u, double 
  * sides (plans with Dirichlet sides only).  Stream-ordered. */
 sipg_status sipg_wall_load(sipg_plan* plan, const double* g_wall, double* y, void* stream);
 
+/* Defaults (sipg_split_opts_default): the solve defaults with 10-step
+ * Lanczos estimates for all three solves. */
 typedef struct {
     sipg_solve_opts pressure;  /* pressure Poisson solve (pure Neumann: mean-zero) */
     sipg_solve_opts viscous;   /* viscous step */

@@ -15,9 +15,10 @@ from .operator import Operator, SolveOptions, _stream_handle
 
 @dataclass
 class SplitOptions:
-    pressure: SolveOptions = field(default_factory=lambda: SolveOptions(rel_tol=1e-10))
-    viscous: SolveOptions = field(default_factory=lambda: SolveOptions(rel_tol=1e-10))
-    penalty: SolveOptions = field(default_factory=lambda: SolveOptions(rel_tol=1e-10))
+    # 10-step Lanczos estimates, as sipg_split_opts_default
+    pressure: SolveOptions = field(default_factory=lambda: SolveOptions(rel_tol=1e-10, lanczos_steps=10))
+    viscous: SolveOptions = field(default_factory=lambda: SolveOptions(rel_tol=1e-10, lanczos_steps=10))
+    penalty: SolveOptions = field(default_factory=lambda: SolveOptions(rel_tol=1e-10, lanczos_steps=10))
     zeta: float = 1.0
     warm_start: bool = False         # viscous solve from uhh, penalty solve from u_visc
 

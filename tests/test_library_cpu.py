@@ -148,10 +148,12 @@ def test_split_step_entry_points_on_cpu():
     """Defaults, the work size, and the host-side refusals of the
     dual-splitting entry points (plans checked before any GPU call)."""
     import torch  # noqa: F401
-    from paper_2506_14424_amd import SplitStep, _ffi as F
+    from paper_2506_14424_amd import SplitOptions, SplitStep, _ffi as F
     o = F.SplitOpts()
     F.lib.sipg_split_opts_default(C.byref(o))
     assert o.zeta == 1.0 and o.pressure.rel_tol == 1e-8 and o.penalty.cheb_degree == 5
+    assert o.pressure.lanczos_steps == o.viscous.lanczos_steps == o.penalty.lanczos_steps == 10
+    assert SplitOptions().viscous.lanczos_steps == 10
     law = W.carreau_law(3)
     s = SplitStep(3, 2, 2, 3, 0.01, law, W.box_vertices(3, 2, 2, 0.1))
     assert s.ndof_u == 12 * 3 * 64 and s.ndof_p == 12 * 27
