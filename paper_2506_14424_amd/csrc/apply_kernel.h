@@ -50,11 +50,11 @@ struct Shape {
     static constexpr int NNN = N * N * N, NN = N * N;
     // LDS layout of a cell's volume arrays: node (i1, i2, i3) of component c at
     //   plain:  c*CS + i3*S3 + i2*N + i1,
-    //   skewed: c*CS + (i3 ^ x)*S3 + ((i2 + i3) % N)*N + (i1 + i3) % N, x = cell % 4.
-    // The skew (FP64, n = 4) makes the xi_1-line, xi_2-line and xi_3-column
-    // patterns of a cell's 16 lanes hit 16 different bank pairs, and the
-    // plane swap x moves the four cells of a wavefront onto different
-    // quarters of the banks without padding.  In FP32 the padded xi_3
+    //   skewed: c*CS + ((i3 + x) % N)*S3 + ((i2 + i3) % N)*N + (i1 + x) % N, x = cell % 4.
+    // The skew (FP64, n = 4, lanes 16 i1 + 4 cell + i2) makes the xi_1-line,
+    // xi_2-line and xi_3-column patterns of the wavefront's 64 lanes hit
+    // every bank pair equally often without padding (no conflicts with
+    // either 32 or 64 banks of 4 bytes).  In FP32 the padded xi_3
     // stride S3 spreads the three patterns instead (n = 3, 4); there the
     // padding costs no occupancy.
     static constexpr bool SKEW = DBL && N == 4;
@@ -200,10 +200,11 @@ __device__ __forceinline__ int vol_pos(int i1, int i2, int i3, int px) {
     if constexpr (!SKEW) {
         return i3 * S3 + i2 * N + i1;
     } else {
-        int a = i2 + i3, b = i1 + i3;
+        int a = i2 + i3, b = i1 + px, c = i3 + px;
         a = a >= N ? a - N : a;
         b = b >= N ? b - N : b;
-        return (i3 ^ px) * S3 + a * N + b;
+        c = c >= N ? c - N : c;
+        return c * S3 + a * N + b;
     }
 }
 
