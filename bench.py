@@ -740,14 +740,17 @@ def main():
                          "source": os.path.relpath(TRAFFIC_FILE, ROOT)},
                      "fp64_alu": None if counters is None else {
                          "flops_per_launch": counters["fp64_flops_per_launch"],
+                         "vector_flops_per_launch": counters.get("fp64_vector_flops_per_launch"),
+                         "matrix_flops_per_launch": counters.get("fp64_matrix_flops_per_launch"),
                          "flops_per_dof": counters["fp64_flops_per_launch"] / op.ndof,
                          "achieved_tflops": counters["fp64_flops_per_launch"] / (ms64 * 1e-3) / 1e12,
                          "peak_tflops": FP64_PEAK_TFLOPS,
                          "frac": counters["fp64_flops_per_launch"] / (ms64 * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
-                         "note": "executed FP64 operations (FMA counted twice) from SQ counters, "
-                                 "divided by the event-timed launch; the kernel reaches neither this "
-                                 "roof nor the HBM roof (its limits are instruction issue and latency "
-                                 "at 2 wavefronts per SIMD)"}},
+                         "note": "executed FP64 operations from SQ counters (vector FMA counted twice, plus "
+                                 "the 4x4x4 matrix-core products of the 1D sweeps), divided by the "
+                                 "event-timed launch; the kernel reaches neither this roof nor the HBM "
+                                 "roof: its VALU issue floor is 42 % of the launch, the rest is latency "
+                                 "at 2 wavefronts per SIMD"}},
         "fp32_apply": {"dof_per_s": op.ndof * k / (r32["event_ms"] * 1e-3),
                        "avg_launch_ms": r32["event_ms"] / k,
                        "achieved_GBs": b32["total"] / (r32["event_ms"] / k * 1e-3) / 1e9,
