@@ -214,56 +214,65 @@ __global__ void k_cg_sub(T* y, const T* r, const T* t, long long n, const int* s
 //   poisson  ds (-2 psi g.n + 2 tau psi^2)
 //   penalty  ds tau_e psi^2 n_c^2
 // written at the node's local position (DG layout); k_cg_assemble sums the
-// cells.  One block per cell: the geometry of every quadrature point (J^-1,
-// JxW, the coefficient) is computed once into LDS, then thread a sums over
-// the points for its node; likewise per Dirichlet face.
+// cells.  A block holds CPB = 256 / n^3 cells (one thread per node): the
+// geometry of every quadrature point (J^-1, JxW, the coefficient) is computed
+// once into LDS, then the thread sums over the points for its node; likewise
+// per Dirichlet face (each cell of the block checks its own faces).
 constexpr int kDiagThreads = 256;
-template <int C>
-__global__ void __launch_bounds__(kDiagThreads) k_cg_diag_local(const OpData<double> op, int n, const CgDiagTab tab,
+template <int C, int N>
+__global__ void __launch_bounds__(kDiagThreads) k_cg_diag_local(const OpData<double> op, const CgDiagTab tab,
                                                                 double* local) {
-    __shared__ double sJ[kMaxN * kMaxN * kMaxN][9];
-    __shared__ double sW[kMaxN * kMaxN * kMaxN], sM[kMaxN * kMaxN * kMaxN];
-    __shared__ double sF[kMaxN * kMaxN][14];   // face point: J^-1 (9), normal (3), ds, penalty coefficient
-    __shared__ double sFm[kMaxN * kMaxN];      // face point viscosity
-    const int nn = n * n, nnn = nn * n, j = n - 1;
+    constexpr int NN = N * N, NNN = NN * N, CPB = kDiagThreads / NNN, J = N - 1;
+    __shared__ double sJ[CPB * NNN][9];
+    __shared__ double sW[CPB * NNN], sM[CPB * NNN];
+    __shared__ double sF[CPB][NN][14];  // face point: J^-1 (9), normal (3), ds, penalty coefficient
+    __shared__ double sFm[CPB][NN];     // face point viscosity
+    __shared__ double sLV[N][N], sLD[N][N], sLG[2][N];
     const auto& tb = op.tab;
-    for (int e = blockIdx.x; e < op.ncell; e += gridDim.x) {
+    for (int i = threadIdx.x; i < NN; i += blockDim.x) {
+        sLV[i / N][i % N] = tab.LV[i / N][i % N];
+        sLD[i / N][i % N] = tab.LD[i / N][i % N];
+    }
+    if ((int)threadIdx.x < 2 * N) sLG[threadIdx.x / N][threadIdx.x % N] = tab.LGs[threadIdx.x / N][threadIdx.x % N];
+    const int lc = threadIdx.x / NNN, node = threadIdx.x % NNN;  // blockDim = CPB * NNN
+    const int a[3] = {node % N, (node / N) % N, node / NN};
+    for (long long e0 = (long long)blockIdx.x * CPB; e0 < op.ncell; e0 += (long long)gridDim.x * CPB) {
+        const bool act = e0 + lc < op.ncell;
+        const int e = act ? (int)(e0 + lc) : 0;  // inactive threads take cell 0: every access in bounds
         const int ex = e % op.nx, ey = (e / op.nx) % op.ny, ez = e / (op.nx * op.ny);
         double geo[8][3];
         cell_geo_full(op, e, geo);
-        __syncthreads();
-        for (int q = threadIdx.x; q < nnn; q += kDiagThreads) {
-            const int q1 = q % n, q2 = (q / n) % n, q3 = q / nn;
+        __syncthreads();  // the previous cells' readers are done
+        {
+            const int q1 = a[0], q2 = a[1], q3 = a[2];
             double Ji[3][3], det;
             jacobian_inverse<double>(geo, tb.x[q1], tb.x[q2], tb.x[q3], Ji, det);
-            for (int a = 0; a < 3; ++a)
-                for (int b = 0; b < 3; ++b) sJ[q][a * 3 + b] = Ji[a][b];
-            sW[q] = det * tb.w[q1] * tb.w[q2] * tb.w[q3];
-            sM[q] = C == 3 ? op.mu_cell[(size_t)e * nnn + q] : 1.0;
+            for (int u = 0; u < 3; ++u)
+                for (int v = 0; v < 3; ++v) sJ[threadIdx.x][u * 3 + v] = Ji[u][v];
+            sW[threadIdx.x] = det * tb.w[q1] * tb.w[q2] * tb.w[q3];
+            sM[threadIdx.x] = C == 3 ? op.mu_cell[(size_t)e * NNN + node] : 1.0;
         }
         __syncthreads();
-        const int node = threadIdx.x;
-        int a[3] = {0, 0, 0};
+        const double(*cJ)[9] = sJ + lc * NNN;
+        const double* cW = sW + lc * NNN;
+        const double* cM = sM + lc * NNN;
         double acc[C];
         for (int c = 0; c < C; ++c) acc[c] = 0.0;
-        if (node < nnn) {
-            a[0] = node % n; a[1] = (node / n) % n; a[2] = node / nn;
-            for (int q = 0; q < nnn; ++q) {
-                const int q1 = q % n, q2 = (q / n) % n, q3 = q / nn;
-                const double v1 = tab.LV[q1][a[0]], v2 = tab.LV[q2][a[1]], v3 = tab.LV[q3][a[2]];
-                const double psi = v1 * v2 * v3;
-                const double gr[3] = {tab.LD[q1][a[0]] * v2 * v3, v1 * tab.LD[q2][a[1]] * v3,
-                                      v1 * v2 * tab.LD[q3][a[2]]};
-                double g[3];
-                for (int k = 0; k < 3; ++k) g[k] = gr[0] * sJ[q][k] + gr[1] * sJ[q][3 + k] + gr[2] * sJ[q][6 + k];
-                const double g2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
-                for (int c = 0; c < C; ++c) {
-                    double v = op.alpha * psi * psi;
-                    if (C == 3 && op.pen) v += sM[q] * g[c] * g[c];
-                    else if (C == 3) v += sM[q] * (g2 + g[c] * g[c]);
-                    else v += g2;
-                    acc[c] += sW[q] * v;
-                }
+#pragma unroll 1
+        for (int q = 0; q < NNN; ++q) {
+            const int q1 = q % N, q2 = (q / N) % N, q3 = q / NN;
+            const double v1 = sLV[q1][a[0]], v2 = sLV[q2][a[1]], v3 = sLV[q3][a[2]];
+            const double psi = v1 * v2 * v3;
+            const double gr[3] = {sLD[q1][a[0]] * v2 * v3, v1 * sLD[q2][a[1]] * v3, v1 * v2 * sLD[q3][a[2]]};
+            double g[3];
+            for (int k = 0; k < 3; ++k) g[k] = gr[0] * cJ[q][k] + gr[1] * cJ[q][3 + k] + gr[2] * cJ[q][6 + k];
+            const double g2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+            for (int c = 0; c < C; ++c) {
+                double v = op.alpha * psi * psi;
+                if (C == 3 && op.pen) v += cM[q] * g[c] * g[c];
+                else if (C == 3) v += cM[q] * (g2 + g[c] * g[c]);
+                else v += g2;
+                acc[c] += cW[q] * v;
             }
         }
         for (int d = 0; d < 3; ++d)
@@ -271,15 +280,15 @@ __global__ void __launch_bounds__(kDiagThreads) k_cg_diag_local(const OpData<dou
                 const int pos = d == 0 ? ex : d == 1 ? ey : ez;
                 const int lim = d == 0 ? op.nx : d == 1 ? op.ny : op.nz;
                 const bool boundary = s == 1 ? pos + 1 == lim : pos == 0;
-                if (!boundary || op.bc[2 * d + s] != 0) continue;   // uniform over the block (one cell)
+                const bool dface = act && boundary && op.bc[2 * d + s] == 0;  // per cell of the block
                 const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
                 int fid;
                 if (d == 0) fid = (ez * op.ny + ey) * (op.nx + 1) + ex + s;
                 else if (d == 1) fid = op.nfx + (ez * (op.ny + 1) + ey + s) * op.nx + ex;
                 else fid = op.nfx + op.nfy + ((ez + s) * op.ny + ey) * op.nx + ex;
-                __syncthreads();
-                for (int fp = threadIdx.x; fp < nn; fp += kDiagThreads) {
-                    const int qa = fp % n, qb = fp / n;
+                __syncthreads();  // the previous face's readers are done
+                if (dface && node < NN) {
+                    const int fp = node, qa = fp % N, qb = fp / N;
                     double xi[3];
                     xi[t1] = tb.x[qa];
                     xi[t2] = tb.x[qb];
@@ -290,24 +299,25 @@ __global__ void __launch_bounds__(kDiagThreads) k_cg_diag_local(const OpData<dou
                     const double nv = sqrt(w0 * w0 + w1 * w1 + w2 * w2);
                     const double sg = s == 1 ? 1.0 : -1.0;
                     for (int a2 = 0; a2 < 3; ++a2)
-                        for (int b = 0; b < 3; ++b) sF[fp][a2 * 3 + b] = Ji[a2][b];
-                    sF[fp][9] = sg * w0 / nv; sF[fp][10] = sg * w1 / nv; sF[fp][11] = sg * w2 / nv;
-                    sF[fp][12] = det * nv * tb.w[qa] * tb.w[qb];
-                    const double mu = (C == 3 && !op.pen) ? op.mu_face[(size_t)fid * nn + fp] : 1.0;
-                    sFm[fp] = mu;
-                    sF[fp][13] = (C == 3 && !op.pen) ? op.tfac[fid] * mu : op.tfac[fid];
+                        for (int b = 0; b < 3; ++b) sF[lc][fp][a2 * 3 + b] = Ji[a2][b];
+                    sF[lc][fp][9] = sg * w0 / nv; sF[lc][fp][10] = sg * w1 / nv; sF[lc][fp][11] = sg * w2 / nv;
+                    sF[lc][fp][12] = det * nv * tb.w[qa] * tb.w[qb];
+                    const double mu = (C == 3 && !op.pen) ? op.mu_face[(size_t)fid * NN + fp] : 1.0;
+                    sFm[lc][fp] = mu;
+                    sF[lc][fp][13] = (C == 3 && !op.pen) ? op.tfac[fid] * mu : op.tfac[fid];
                 }
                 __syncthreads();
-                if (node >= nnn || a[d] != (s == 1 ? j : 0)) continue;   // no trace on this face
-                for (int fp = 0; fp < nn; ++fp) {
-                    const int qa = fp % n, qb = fp / n;
-                    const double va = tab.LV[qa][a[t1]], vb = tab.LV[qb][a[t2]];
+                if (!dface || a[d] != (s == 1 ? J : 0)) continue;   // no trace on this face
+#pragma unroll 1
+                for (int fp = 0; fp < NN; ++fp) {
+                    const int qa = fp % N, qb = fp / N;
+                    const double va = sLV[qa][a[t1]], vb = sLV[qb][a[t2]];
                     const double psi = va * vb;
                     double gr[3];
-                    gr[t1] = tab.LD[qa][a[t1]] * vb;
-                    gr[t2] = va * tab.LD[qb][a[t2]];
-                    gr[d] = tab.LGs[s][a[d]] * psi;
-                    const double* F = sF[fp];
+                    gr[t1] = sLD[qa][a[t1]] * vb;
+                    gr[t2] = va * sLD[qb][a[t2]];
+                    gr[d] = sLG[s][a[d]] * psi;
+                    const double* F = sF[lc][fp];
                     double g[3];
                     for (int k = 0; k < 3; ++k) g[k] = gr[0] * F[k] + gr[1] * F[3 + k] + gr[2] * F[6 + k];
                     const double nrm[3] = {F[9], F[10], F[11]};
@@ -316,7 +326,7 @@ __global__ void __launch_bounds__(kDiagThreads) k_cg_diag_local(const OpData<dou
                     if (C == 3 && op.pen) {
                         for (int c = 0; c < 3; ++c) acc[c] += ds * tau * psi * psi * nrm[c] * nrm[c];
                     } else if (C == 3) {
-                        const double mu = sFm[fp];
+                        const double mu = sFm[lc][fp];
                         for (int c = 0; c < 3; ++c)
                             acc[c] += 2.0 * ds *
                                       (-mu * psi * (gn + nrm[c] * g[c]) + tau * psi * psi * (1.0 + nrm[c] * nrm[c]));
@@ -325,8 +335,8 @@ __global__ void __launch_bounds__(kDiagThreads) k_cg_diag_local(const OpData<dou
                     }
                 }
             }
-        if (node < nnn)
-            for (int c = 0; c < C; ++c) local[((size_t)e * C + c) * nnn + node] = acc[c];
+        if (act)
+            for (int c = 0; c < C; ++c) local[((size_t)e * C + c) * NNN + node] = acc[c];
     }
 }
 
@@ -502,12 +512,25 @@ hipError_t launch_cg_sub(T* y, const T* r, const T* t, long long n, const int* s
     return hipGetLastError();
 }
 
+template <int N>
+void launch_cg_diag_n(int C, const OpData<double>& op, const CgDiagTab& tab, double* local, hipStream_t s) {
+    constexpr int CPB = kDiagThreads / (N * N * N);
+    const long long blocks = (op.ncell + CPB - 1) / CPB;
+    const dim3 grid((unsigned)(blocks < 65535 ? blocks : 65535)), block(CPB * N * N * N);
+    if (C == 3) hipLaunchKernelGGL((k_cg_diag_local<3, N>), grid, block, 0, s, op, tab, local);
+    else hipLaunchKernelGGL((k_cg_diag_local<1, N>), grid, block, 0, s, op, tab, local);
+}
+
 hipError_t launch_cg_diagonal(const CgGeo& g, const OpData<double>& op, const CgDiagTab& tab, double* local,
                               double* diag, double* dinv64, float* dinv32, hipStream_t s) {
-    const int n = g.j + 1;
-    const dim3 grid((unsigned)(op.ncell < 65535 ? op.ncell : 65535));
-    if (g.C == 3) hipLaunchKernelGGL(k_cg_diag_local<3>, grid, dim3(kDiagThreads), 0, s, op, n, tab, local);
-    else hipLaunchKernelGGL(k_cg_diag_local<1>, grid, dim3(kDiagThreads), 0, s, op, n, tab, local);
+    switch (g.j + 1) {
+        case 2: launch_cg_diag_n<2>(g.C, op, tab, local, s); break;
+        case 3: launch_cg_diag_n<3>(g.C, op, tab, local, s); break;
+        case 4: launch_cg_diag_n<4>(g.C, op, tab, local, s); break;
+        case 5: launch_cg_diag_n<5>(g.C, op, tab, local, s); break;
+        case 6: launch_cg_diag_n<6>(g.C, op, tab, local, s); break;
+        default: return hipErrorInvalidValue;
+    }
     const long long total = (long long)g.Mx * g.My * g.Mz * g.C;
     AsmIO<double> io;
     std::memset(&io, 0, sizeof(io));

@@ -57,6 +57,33 @@ __device__ __forceinline__ void lagrange_one(const FineVelocity& F, double x, in
     dv = der;
 }
 
+// G = gref J^-1 for fine cell (fx, fy, fz) at fine reference point xi
+// (gref[c][d] = d u_c / d xi_d).
+__device__ __forceinline__ void physical_gradient(const FineVelocity& F, int fx, int fy, int fz, const double xi[3],
+                                  const double gref[3][3], double G[3][3]) {
+    double Ji[3][3];
+    if (F.verts != nullptr) {
+        double geo[8][3], gi[8];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            trilinear_coeffs(F.verts, F.nx, F.ny, fx, fy, fz, i, gi);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) geo[k][i] = gi[k];
+        }
+        double det;
+        jacobian_inverse<double>(geo, xi[0], xi[1], xi[2], Ji, det);
+    } else {
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) Ji[d][i] = d == i ? double(d == 0 ? F.nx : d == 1 ? F.ny : F.nz) : 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) G[c][i] = gref[c][0] * Ji[0][i] + gref[c][1] * Ji[1][i] + gref[c][2] * Ji[2][i];
+}
+
 // Physical velocity gradient G[c][i] = d u_c / d x_i of fine cell (fx, fy, fz)
 // at fine reference point xi; U: that cell's 3 NF^3 values (global memory or
 // a copy in LDS).  The xi_1 and xi_2 contractions are unrolled with their
@@ -97,27 +124,7 @@ __device__ void velocity_gradient(const FineVelocity& F, const double* U, int fx
         }
         gref[c][0] = g0; gref[c][1] = g1; gref[c][2] = g2;
     }
-    double Ji[3][3];
-    if (F.verts != nullptr) {
-        double geo[8][3], gi[8];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            trilinear_coeffs(F.verts, F.nx, F.ny, fx, fy, fz, i, gi);
-#pragma unroll
-            for (int k = 0; k < 8; ++k) geo[k][i] = gi[k];
-        }
-        double det;
-        jacobian_inverse<double>(geo, xi[0], xi[1], xi[2], Ji, det);
-    } else {
-#pragma unroll
-        for (int d = 0; d < 3; ++d)
-#pragma unroll
-            for (int i = 0; i < 3; ++i) Ji[d][i] = d == i ? double(d == 0 ? F.nx : d == 1 ? F.ny : F.nz) : 0.0;
-    }
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int i = 0; i < 3; ++i) G[c][i] = gref[c][0] * Ji[0][i] + gref[c][1] * Ji[1][i] + gref[c][2] * Ji[2][i];
+    physical_gradient(F, fx, fy, fz, xi, gref, G);
 }
 
 // eps:eps of the symmetric part of G
@@ -266,15 +273,25 @@ __global__ void __launch_bounds__(kSame) k_picard_cell_same(FineVelocity F, Leve
     }
 }
 
+// Faces of a level on the fine mesh: a face point lies on the fine face, so
+// each side's gradient there factors into the trace and the normal
+// derivative on the face's NF x NF grid of fine tangential nodes (one
+// contraction along the normal per grid node, done once per face and side
+// into LDS) and a 2D interpolation of those to the point (values and
+// tangential derivatives of the fine 1D basis): O(NF^2) per point instead
+// of O(NF^3).
 template <int NF>
 __global__ void __launch_bounds__(kSame) k_picard_face_same(FineVelocity F, LevelPoints Lv, LawDev law,
                                                             long long nface, int per, double* mu64, float* mu32) {
-    extern __shared__ double su[];  // [per][2][3 NF^3]
+    constexpr int nv = 3 * NF * NF * NF, NF2 = NF * NF, tw = 2 * 3 * NF2;  // per face side: trace, d/dxi_d
+    extern __shared__ double st[];  // [per][2 sides][tw]
     __shared__ int meta[kSame][6];  // per face: d, pos[3], have lower, have upper
-    constexpr int nv = 3 * NF * NF * NF;
     const int n = Lv.n, n2 = n * n;
-    const int N[3] = {Lv.nx, Lv.ny, Lv.nz};
     const int g = threadIdx.x / n2, p = threadIdx.x % n2;
+    // the fine 1D basis and its derivative at the lower cell's face (xi_d = 1, side 0) and the upper's (0)
+    double fv[2][NF], fd[2][NF];
+    lagrange_1d<NF>(F, 1.0, fv[0], fd[0]);
+    lagrange_1d<NF>(F, 0.0, fv[1], fd[1]);
     for (long long f0 = (long long)blockIdx.x * per; f0 < nface; f0 += (long long)gridDim.x * per) {
         __syncthreads();
         if ((int)threadIdx.x < per && f0 + threadIdx.x < nface) {
@@ -282,47 +299,88 @@ __global__ void __launch_bounds__(kSame) k_picard_face_same(FineVelocity F, Leve
             const int d = decode_face(Lv, f0 + threadIdx.x, pos);
             meta[threadIdx.x][0] = d;
             meta[threadIdx.x][1] = pos[0]; meta[threadIdx.x][2] = pos[1]; meta[threadIdx.x][3] = pos[2];
-            meta[threadIdx.x][4] = pos[d] > 0;
-            meta[threadIdx.x][5] = pos[d] < N[d];
+            const int pd = d == 0 ? pos[0] : d == 1 ? pos[1] : pos[2];
+            meta[threadIdx.x][4] = pd > 0;
+            meta[threadIdx.x][5] = pd < (d == 0 ? Lv.nx : d == 1 ? Lv.ny : Lv.nz);
         }
         __syncthreads();
         const int nf = (int)(nface - f0 < per ? nface - f0 : per);
-        for (int i = threadIdx.x; i < nf * 2 * nv; i += kSame) {
-            const int gg = i / (2 * nv), rem = i % (2 * nv), s = rem / nv, j = rem % nv;
+        for (int i = threadIdx.x; i < nf * 2 * 3 * NF2; i += kSame) {
+            const int gg = i / (2 * 3 * NF2), rem = i % (2 * 3 * NF2), s = rem / (3 * NF2), c = (rem / NF2) % 3,
+                      jab = rem % NF2;
             if (!meta[gg][4 + s]) continue;
             const int d = meta[gg][0];
-            int c3[3] = {meta[gg][1], meta[gg][2], meta[gg][3]};
-            c3[d] -= (s == 0);
-            const long long cell = ((long long)c3[2] * Lv.ny + c3[1]) * Lv.nx + c3[0];
-            su[i] = F.u[cell * nv + j];
+            const int lo = s == 0 ? 1 : 0;  // the lower cell lies one step down along d
+            const int cx = meta[gg][1] - (d == 0 ? lo : 0), cy = meta[gg][2] - (d == 1 ? lo : 0),
+                      cz = meta[gg][3] - (d == 2 ? lo : 0);
+            const long long cell = ((long long)cz * Lv.ny + cy) * Lv.nx + cx;
+            const double* U = F.u + cell * nv + c * NF * NF2;
+            // node strides along the normal and the two tangential directions (t1 < t2)
+            const int sd = d == 0 ? 1 : d == 1 ? NF : NF2, s1 = d == 0 ? NF : 1, s2 = d == 2 ? NF : NF2;
+            const int base = (jab % NF) * s1 + (jab / NF) * s2;
+            double tv = 0.0, nd = 0.0;
+#pragma unroll
+            for (int jd = 0; jd < NF; ++jd) {
+                const double u = U[base + jd * sd];
+                tv += (s == 0 ? fv[0][jd] : fv[1][jd]) * u;
+                nd += (s == 0 ? fd[0][jd] : fd[1][jd]) * u;
+            }
+            double* T = st + (gg * 2 + s) * tw;
+            T[c * NF2 + jab] = tv;
+            T[3 * NF2 + c * NF2 + jab] = nd;
         }
         __syncthreads();
         if (g < nf) {
             const int d = meta[g][0];
-            const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+            double la[NF], da[NF], lb[NF], db[NF];  // fine basis at the point's tangential coordinates
+            lagrange_1d<NF>(F, Lv.g[p % n], la, da);
+            lagrange_1d<NF>(F, Lv.g[p / n], lb, db);
             double acc[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
             int sides = 0;
             for (int s = 0; s < 2; ++s) {  // s = 0: the lower cell (its face xi_d = 1)
                 if (!meta[g][4 + s]) continue;
-                int c3[3] = {meta[g][1], meta[g][2], meta[g][3]};
-                c3[d] -= (s == 0);
-                double xi[3];
-                xi[t1] = Lv.g[p % n];
-                xi[t2] = Lv.g[p / n];
-                xi[d] = s == 0 ? 1.0 : 0.0;
+                const int lo = s == 0 ? 1 : 0;
+                const int cx = meta[g][1] - (d == 0 ? lo : 0), cy = meta[g][2] - (d == 1 ? lo : 0),
+                          cz = meta[g][3] - (d == 2 ? lo : 0);
+                // (t1, t2) = the tangential directions in increasing order
+                const double xa = Lv.g[p % n], xb = Lv.g[p / n], xn = s == 0 ? 1.0 : 0.0;
+                const double xi[3] = {d == 0 ? xn : xa, d == 0 ? xa : (d == 1 ? xn : xb), d == 2 ? xn : xb};
+                const double* T = st + (g * 2 + s) * tw;
+                double gref[3][3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    double g1 = 0.0, g2 = 0.0, g3 = 0.0;
+#pragma unroll 1
+                    for (int jb = 0; jb < NF; ++jb) {
+                        double sd = 0.0, sv = 0.0, sn = 0.0;
+#pragma unroll
+                        for (int ja = 0; ja < NF; ++ja) {
+                            const double tv = T[c * NF2 + jb * NF + ja], nd = T[3 * NF2 + c * NF2 + jb * NF + ja];
+                            sd += da[ja] * tv;
+                            sv += la[ja] * tv;
+                            sn += la[ja] * nd;
+                        }
+                        g1 += lb[jb] * sd;
+                        g2 += db[jb] * sv;
+                        g3 += lb[jb] * sn;
+                    }
+                    gref[c][0] = d == 0 ? g3 : g1;
+                    gref[c][1] = d == 0 ? g1 : (d == 1 ? g3 : g2);
+                    gref[c][2] = d == 2 ? g3 : g2;
+                }
                 double G[3][3];
-                velocity_gradient<NF>(F, su + (g * 2 + s) * nv, c3[0], c3[1], c3[2], xi, G);
+                physical_gradient(F, cx, cy, cz, xi, gref, G);
 #pragma unroll
                 for (int i = 0; i < 3; ++i)
 #pragma unroll
-                    for (int j = 0; j < 3; ++j) acc[i][j] += G[i][j];
+                    for (int jj = 0; jj < 3; ++jj) acc[i][jj] += G[i][jj];
                 ++sides;
             }
             const double sc = 1.0 / sides;
 #pragma unroll
             for (int i = 0; i < 3; ++i)
 #pragma unroll
-                for (int j = 0; j < 3; ++j) acc[i][j] *= sc;
+                for (int jj = 0; jj < 3; ++jj) acc[i][jj] *= sc;
             store_mu(mu64, mu32, (f0 + g) * n2 + p, law, sym_square(acc));
         }
     }
@@ -337,14 +395,15 @@ hipError_t launch_nf(const FineVelocity& F, const LevelPoints& Lv, const LawDev&
     const int n = Lv.n;
     if (Lv.r == 1) {
         const long long ncell = (long long)Lv.nx * Lv.ny * Lv.nz;
+        constexpr int ftb = 2 * 2 * 3 * NF * NF * (int)sizeof(double);  // per face: both sides' traces
         int pc = kSame / (n * n * n), pf = kSame / (n * n);
         pc = pc < kLdsCap / nvb ? pc : kLdsCap / nvb;
-        pf = pf < kLdsCap / (2 * nvb) ? pf : kLdsCap / (2 * nvb);
+        pf = pf < kLdsCap / ftb ? pf : kLdsCap / ftb;
         const long long bc = (ncell + pc - 1) / pc, bf = (nface + pf - 1) / pf;
         hipLaunchKernelGGL(k_picard_cell_same<NF>, dim3((unsigned)(bc < 65535 ? bc : 65535)), dim3(kSame),
                            (size_t)pc * nvb, s, F, Lv, law, pc, mu_cell64, mu_cell32);
         hipLaunchKernelGGL(k_picard_face_same<NF>, dim3((unsigned)(bf < 65535 ? bf : 65535)), dim3(kSame),
-                           (size_t)pf * 2 * nvb, s, F, Lv, law, nface, pf, mu_face64, mu_face32);
+                           (size_t)pf * ftb, s, F, Lv, law, nface, pf, mu_face64, mu_face32);
         return hipGetLastError();
     }
     auto grid = [](long long work) {
