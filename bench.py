@@ -182,10 +182,13 @@ def solve_compare(tol=1e-8):
                        f"{op.ndof} DoFs, rel. tol {tol:g}",
            "multigrid_levels": op.multigrid_levels()}
     sols = {}
-    for key, prec, kind, deg in (("f64_precond", "f64", "chebyshev", 5), ("f32_precond", "f32", "chebyshev", 5),
-                                 ("mg_f64_precond", "f64", "multigrid", 4), ("mg_f32_precond", "f32", "multigrid", 4)):
+    for key, prec, kind, deg, graph in (("f64_precond", "f64", "chebyshev", 5, False),
+                                        ("f32_precond", "f32", "chebyshev", 5, False),
+                                        ("mg_f64_precond", "f64", "multigrid", 4, False),
+                                        ("mg_f32_precond", "f32", "multigrid", 4, False),
+                                        ("mg_f32_precond_graph", "f32", "multigrid", 4, True)):
         opts = SolveOptions(rel_tol=tol, precond_precision=prec, precond=kind, cheb_degree=deg,
-                            check_every=25 if kind == "chebyshev" else 5)
+                            check_every=25 if kind == "chebyshev" else 5, use_graph=graph)
         op.solve(b, opts=opts)                       # warm (eigenvalue estimates cached after the first)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -194,7 +197,7 @@ def solve_compare(tol=1e-8):
         dt = time.perf_counter() - t0
         sols[key] = x
         out[key] = {"seconds": dt, "iterations": info["iterations"], "rel_residual": info["rel_residual"],
-                    "status": info["status"], "preconditioner": kind, "degree": deg}
+                    "status": info["status"], "preconditioner": kind, "degree": deg, "hip_graph": graph}
     # the same solve with the all-DG hierarchy (no continuous levels), for comparison
     opdg = Operator.from_config(cfg, V).set_multigrid(continuous=False).bind(with_solver=True)
     opts = SolveOptions(rel_tol=tol, precond_precision="f32", precond="multigrid", cheb_degree=4, check_every=5)
