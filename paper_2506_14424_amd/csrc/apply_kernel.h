@@ -63,13 +63,9 @@ struct Shape {
     // per-cell LDS: nodal values and a work space for the cell sweeps and the
     // face stages; +1 staggers consecutive cells over the LDS banks (plain layout)
     static constexpr int U = C * CS + (SKEW ? 0 : 1);
-    // work-space stride: skewed layout +8 (the four cells of a wavefront at
-    // offsets 0, 8, 16, 24 mod 32 doubles: line tasks and lane-per-point
-    // accesses of the face stages spread over all bank pairs), else +1
-    // n = 4: the face stages' tangential sweeps exchange values across lanes
-    // (DPP) instead of through LDS; their only LDS array left is the
-    // projection's, so the FP64 pad shrinks to 4 and the per-lane derivative
-    // table fits in the same 20 KB
+    // work-space stride +1 (staggers consecutive cells over the banks).
+    // FP32 n = 4: the face stages' tangential sweeps exchange values across
+    // lanes (DPP) instead of through LDS.
     // FP64 n = 4: the 1D sweeps across lanes run on the matrix cores instead
     // (v_mfma_f64_4x4x4: four 16-lane blocks, each a 4 x 4 product that
     // contracts over lane bits 5:4).  Lane 16 i1 + 4 cell + i2 owns the xi_3
@@ -81,9 +77,10 @@ struct Shape {
     static constexpr bool DPP = (N == 4 && !MF) || N == 2;
     // n = 2 (cell and face passes across lanes): only the projection's
     // coefficient array remains, so the work space shrinks to that
+    // (FP64 n = 4: the projection's array only, stride 2 C n^2 + 4)
     static constexpr int W = N == 2 ? 2 * C * NN + 1
                            : MF     ? 2 * C * NN + 4
-                                    : (2 * C * CS > 8 * C * NN ? 2 * C * CS : 8 * C * NN) + (SKEW ? (DPP ? 4 : 8) : 1);
+                                    : (2 * C * CS > 8 * C * NN ? 2 * C * CS : 8 * C * NN) + 1;
 };
 
 // Matrix-core sweeps of a 4 x 4 tile per cell (FP64 n = 4 layout, lane
