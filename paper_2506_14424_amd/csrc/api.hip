@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <mutex>
 #include <new>
 #include <string>
@@ -262,6 +263,13 @@ struct sipg_plan {
     hipStream_t cap_stream = nullptr;
     GraphEntry graphs[2];
     int graph_next = 0;
+    // the levels' Lanczos runs side by side (created at the first multi-level
+    // estimate; default priority): fork and join events
+    static constexpr int kLzStreams = 3;
+    hipStream_t lz_streams[kLzStreams] = {};
+    hipEvent_t lz_fork = nullptr, lz_join[kLzStreams] = {};
+    bool lz_aux_failed = false;
+    bool no_alloc = false;           // inside the no-allocation entry point: everything on the caller's stream
 
     // multigrid hierarchy: this plan is the finest level, mg[i] is level i+1
     bool mg_on = false;
@@ -978,6 +986,64 @@ sipg_status update_viscosity(sipg_plan* P, const double* u, hipStream_t s) {
 // Eigenvalue estimates (cached per level) and Chebyshev coefficients of the
 // preconditioner in P->opts: the finest level's polynomial, and with
 // multigrid every coarser level's (coarse_degree on the coarsest).
+// Streams and events for side-by-side Lanczos runs, created once per plan;
+// false (and nothing kept) if the runtime refuses any of them.
+bool lz_aux_ready(sipg_plan* P) {
+    if (P->lz_fork) return true;
+    if (P->lz_aux_failed) return false;
+    bool ok = hipEventCreateWithFlags(&P->lz_fork, hipEventDisableTiming) == hipSuccess;
+    for (int k = 0; ok && k < sipg_plan::kLzStreams; ++k)
+        ok = hipStreamCreateWithFlags(&P->lz_streams[k], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&P->lz_join[k], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        for (int k = 0; k < sipg_plan::kLzStreams; ++k) {
+            if (P->lz_streams[k]) (void)hipStreamDestroy(P->lz_streams[k]);
+            if (P->lz_join[k]) (void)hipEventDestroy(P->lz_join[k]);
+            P->lz_streams[k] = nullptr;
+            P->lz_join[k] = nullptr;
+        }
+        if (P->lz_fork) (void)hipEventDestroy(P->lz_fork);
+        P->lz_fork = nullptr;
+        P->lz_aux_failed = true;
+        (void)hipGetLastError();
+    }
+    return ok;
+}
+
+// Runs the estimate jobs: in order on s, or, when there are several and the
+// plan may use its own streams (not while s is being captured, not in the
+// no-allocation entry point), side by side on the plan's Lanczos streams
+// between a fork and a join on s.  Every job works on its own level's
+// vectors, state and partial sums, so the results do not depend on the
+// schedule.
+sipg_status run_jobs(sipg_plan* P, std::vector<std::function<sipg_status(hipStream_t)>>& jobs, hipStream_t s) {
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    const bool side = jobs.size() > 1 && !P->no_alloc && hipStreamIsCapturing(s, &cap) == hipSuccess &&
+                      cap == hipStreamCaptureStatusNone && lz_aux_ready(P);
+    if (!side) {
+        for (auto& j : jobs) {
+            const sipg_status rc = j(s);
+            if (rc != SIPG_OK) return rc;
+        }
+        return SIPG_OK;
+    }
+    const int K = sipg_plan::kLzStreams;
+    HIP_TRY(hipEventRecord(P->lz_fork, s));
+    for (int k = 0; k < K; ++k) HIP_TRY(hipStreamWaitEvent(P->lz_streams[k], P->lz_fork, 0));
+    sipg_status first = SIPG_OK;
+    for (size_t i = 0; i < jobs.size(); ++i) {
+        const sipg_status rc = jobs[i](P->lz_streams[i % K]);
+        if (rc != SIPG_OK && first == SIPG_OK) first = rc;
+        if (rc != SIPG_OK) break;
+    }
+    // join every stream, also after a failure, so that s orders after all of them
+    for (int k = 0; k < K; ++k) {
+        HIP_TRY(hipEventRecord(P->lz_join[k], P->lz_streams[k]));
+        HIP_TRY(hipStreamWaitEvent(s, P->lz_join[k], 0));
+    }
+    return first;
+}
+
 sipg_status prepare_precond(sipg_plan* P, hipStream_t s) {
     const sipg_solve_opts& o = P->opts;
     const bool mg = o.precond_kind == SIPG_PRECOND_MULTIGRID;
@@ -985,24 +1051,34 @@ sipg_status prepare_precond(sipg_plan* P, hipStream_t s) {
     // cph: the DG level and the continuous levels (the coarser DG plans only
     // carry the continuous levels' operators)
     const int nl = mg ? (cph ? 1 : mg_levels(P)) : 1;
+    // the levels whose estimates are missing or stale, largest first
+    std::vector<std::function<sipg_status(hipStream_t)>> jobs;
+    for (int l = 0; l < nl; ++l) {
+        sipg_plan* L = mg_level(P, l);
+        if (l > 0) L->opts = o;
+        if (!L->lz_valid || L->lz_steps != o.lanczos_steps || (L->lz_stale && !o.reuse_eigs))
+            jobs.push_back([L](hipStream_t t) { return run_lanczos(L, t); });
+    }
     if (cph) {
         for (size_t i = 0; i < P->cg.size(); ++i) {
             CgLevel& c = P->cg[i];
             if (!c.lz_valid || c.lz_steps != o.lanczos_steps || (c.lz_stale && !o.reuse_eigs)) {
-                const sipg_status rc = run_lanczos_cg(c, o.lanczos_steps, s);
-                if (rc != SIPG_OK) return rc;
+                const int steps = o.lanczos_steps;
+                jobs.push_back([&c, steps](hipStream_t t) { return run_lanczos_cg(c, steps, t); });
             }
+        }
+    }
+    const sipg_status rc = run_jobs(P, jobs, s);
+    if (rc != SIPG_OK) return rc;
+    if (cph) {
+        for (size_t i = 0; i < P->cg.size(); ++i) {
+            CgLevel& c = P->cg[i];
             const bool coarse_poly = i + 1 == P->cg.size() && !c.direct;
             sk_lz_coef(c.st, o.cheb_safety, o.cheb_ratio, coarse_poly ? P->mg_opts.coarse_degree : o.cheb_degree, s);
         }
     }
     for (int l = 0; l < nl; ++l) {
         sipg_plan* L = mg_level(P, l);
-        if (l > 0) L->opts = o;
-        if (!L->lz_valid || L->lz_steps != o.lanczos_steps || (L->lz_stale && !o.reuse_eigs)) {
-            const sipg_status rc = run_lanczos(L, s);
-            if (rc != SIPG_OK) return rc;
-        }
         const int deg = (mg && !cph && l == nl - 1) ? P->mg_opts.coarse_degree : o.cheb_degree;
         sk_lz_coef(L->st, o.cheb_safety, o.cheb_ratio, deg, s);
     }
@@ -1179,6 +1255,11 @@ void sipg_plan_destroy(sipg_plan* P) {
     if (!P) return;
     drop_graphs(P);
     if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
+    for (int k = 0; k < sipg_plan::kLzStreams; ++k) {
+        if (P->lz_streams[k]) (void)hipStreamDestroy(P->lz_streams[k]);
+        if (P->lz_join[k]) (void)hipEventDestroy(P->lz_join[k]);
+    }
+    if (P->lz_fork) (void)hipEventDestroy(P->lz_fork);
     for (sipg_plan* c : P->mg) sipg_plan_destroy(c);
     if (P->mirror) (void)hipHostFree(P->mirror);
     if (P->ev) (void)hipEventDestroy(P->ev);
@@ -1829,7 +1910,10 @@ sipg_status sipg_picard_solve_noalloc(sipg_plan* P, const double* b, double* x, 
     void* work = nullptr;
     const sipg_status rc = scratch_address(&work);
     if (rc != SIPG_OK) return rc;
-    return picard_run(P, b, x, work, lin_opts, opts, info, stream);
+    P->no_alloc = true;   // no stream or event creation on this path
+    const sipg_status r = picard_run(P, b, x, work, lin_opts, opts, info, stream);
+    P->no_alloc = false;
+    return r;
 }
 
 // ------------------------------------------------------------ dual splitting step
