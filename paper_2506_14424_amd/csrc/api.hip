@@ -263,12 +263,12 @@ struct sipg_plan {
     hipStream_t cap_stream = nullptr;
     GraphEntry graphs[2];
     int graph_next = 0;
-    // the levels' Lanczos runs side by side (created at the first multi-level
-    // estimate; default priority): fork and join events
-    static constexpr int kLzStreams = 3;
-    hipStream_t lz_streams[kLzStreams] = {};
-    hipEvent_t lz_fork = nullptr, lz_join[kLzStreams] = {};
-    bool lz_aux_failed = false;
+    // per-level work side by side (Lanczos estimates, viscosity updates;
+    // created at first use, default priority): fork and join events
+    static constexpr int kAuxStreams = 3;
+    hipStream_t aux_streams[kAuxStreams] = {};
+    hipEvent_t aux_fork = nullptr, aux_join[kAuxStreams] = {};
+    bool aux_failed = false;
     bool no_alloc = false;           // inside the no-allocation entry point: everything on the caller's stream
 
     // multigrid hierarchy: this plan is the finest level, mg[i] is level i+1
@@ -549,8 +549,8 @@ bool pure_neumann_poisson(const sipg_plan* P) {
 // Diagonals of the continuous levels and the coarsest level's dense inverse,
 // from the carriers' current data (after binding and after every viscosity
 // or penalty-factor update); the eigenvalue estimates become stale.
-sipg_status refresh_continuous(sipg_plan* P, hipStream_t s) {
-    for (CgLevel& c : P->cg) {
+sipg_status refresh_cg_level(sipg_plan* P, CgLevel& c, hipStream_t s) {
+    {
         const sipg_plan* Cr = c.carrier;
         HIP_TRY(launch_cg_diagonal(c.geo, Cr->opdata<double>(), c.dtab, static_cast<double*>(c.dgx), c.diag64,
                                    c.dinv64, c.dinv32, s));
@@ -572,6 +572,15 @@ sipg_status refresh_continuous(sipg_plan* P, hipStream_t s) {
     }
     return SIPG_OK;
 }
+
+sipg_status refresh_continuous(sipg_plan* P, hipStream_t s) {
+    for (CgLevel& c : P->cg) {
+        const sipg_status rc = refresh_cg_level(P, c, s);
+        if (rc != SIPG_OK) return rc;
+    }
+    return SIPG_OK;
+}
+
 
 template <typename T>
 const CgL<T>& cg_tab(const CgLevel& c) {
@@ -979,47 +988,46 @@ sipg_status update_viscosity(sipg_plan* P, const double* u, hipStream_t s) {
         HIP_TRY(launch_diagonal(L->n, L->C, L->curved, L->opdata<double>(), L->diag64, L->dinv64, L->dinv32, s));
         L->lz_stale = true;
     }
+    // (in order: the levels' kernels each fill the device, so side-by-side
+    // streams gained nothing here, unlike the latency-bound Lanczos chains)
     if (!P->cg.empty() && P->with_solver) return refresh_continuous(P, s);
     return SIPG_OK;
 }
 
-// Eigenvalue estimates (cached per level) and Chebyshev coefficients of the
-// preconditioner in P->opts: the finest level's polynomial, and with
-// multigrid every coarser level's (coarse_degree on the coarsest).
-// Streams and events for side-by-side Lanczos runs, created once per plan;
+// Streams and events for side-by-side per-level work, created once per plan;
 // false (and nothing kept) if the runtime refuses any of them.
-bool lz_aux_ready(sipg_plan* P) {
-    if (P->lz_fork) return true;
-    if (P->lz_aux_failed) return false;
-    bool ok = hipEventCreateWithFlags(&P->lz_fork, hipEventDisableTiming) == hipSuccess;
-    for (int k = 0; ok && k < sipg_plan::kLzStreams; ++k)
-        ok = hipStreamCreateWithFlags(&P->lz_streams[k], hipStreamNonBlocking) == hipSuccess &&
-             hipEventCreateWithFlags(&P->lz_join[k], hipEventDisableTiming) == hipSuccess;
+bool aux_ready(sipg_plan* P) {
+    if (P->aux_fork) return true;
+    if (P->aux_failed) return false;
+    bool ok = hipEventCreateWithFlags(&P->aux_fork, hipEventDisableTiming) == hipSuccess;
+    for (int k = 0; ok && k < sipg_plan::kAuxStreams; ++k)
+        ok = hipStreamCreateWithFlags(&P->aux_streams[k], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&P->aux_join[k], hipEventDisableTiming) == hipSuccess;
     if (!ok) {
-        for (int k = 0; k < sipg_plan::kLzStreams; ++k) {
-            if (P->lz_streams[k]) (void)hipStreamDestroy(P->lz_streams[k]);
-            if (P->lz_join[k]) (void)hipEventDestroy(P->lz_join[k]);
-            P->lz_streams[k] = nullptr;
-            P->lz_join[k] = nullptr;
+        for (int k = 0; k < sipg_plan::kAuxStreams; ++k) {
+            if (P->aux_streams[k]) (void)hipStreamDestroy(P->aux_streams[k]);
+            if (P->aux_join[k]) (void)hipEventDestroy(P->aux_join[k]);
+            P->aux_streams[k] = nullptr;
+            P->aux_join[k] = nullptr;
         }
-        if (P->lz_fork) (void)hipEventDestroy(P->lz_fork);
-        P->lz_fork = nullptr;
-        P->lz_aux_failed = true;
+        if (P->aux_fork) (void)hipEventDestroy(P->aux_fork);
+        P->aux_fork = nullptr;
+        P->aux_failed = true;
         (void)hipGetLastError();
     }
     return ok;
 }
 
-// Runs the estimate jobs: in order on s, or, when there are several and the
+// Runs per-level jobs: in order on s, or, when there are several and the
 // plan may use its own streams (not while s is being captured, not in the
-// no-allocation entry point), side by side on the plan's Lanczos streams
+// no-allocation entry point), side by side on the plan's auxiliary streams
 // between a fork and a join on s.  Every job works on its own level's
-// vectors, state and partial sums, so the results do not depend on the
+// buffers, state and partial sums, so the results do not depend on the
 // schedule.
 sipg_status run_jobs(sipg_plan* P, std::vector<std::function<sipg_status(hipStream_t)>>& jobs, hipStream_t s) {
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     const bool side = jobs.size() > 1 && !P->no_alloc && hipStreamIsCapturing(s, &cap) == hipSuccess &&
-                      cap == hipStreamCaptureStatusNone && lz_aux_ready(P);
+                      cap == hipStreamCaptureStatusNone && aux_ready(P);
     if (!side) {
         for (auto& j : jobs) {
             const sipg_status rc = j(s);
@@ -1027,23 +1035,26 @@ sipg_status run_jobs(sipg_plan* P, std::vector<std::function<sipg_status(hipStre
         }
         return SIPG_OK;
     }
-    const int K = sipg_plan::kLzStreams;
-    HIP_TRY(hipEventRecord(P->lz_fork, s));
-    for (int k = 0; k < K; ++k) HIP_TRY(hipStreamWaitEvent(P->lz_streams[k], P->lz_fork, 0));
+    const int K = sipg_plan::kAuxStreams;
+    HIP_TRY(hipEventRecord(P->aux_fork, s));
+    for (int k = 0; k < K; ++k) HIP_TRY(hipStreamWaitEvent(P->aux_streams[k], P->aux_fork, 0));
     sipg_status first = SIPG_OK;
     for (size_t i = 0; i < jobs.size(); ++i) {
-        const sipg_status rc = jobs[i](P->lz_streams[i % K]);
+        const sipg_status rc = jobs[i](P->aux_streams[i % K]);
         if (rc != SIPG_OK && first == SIPG_OK) first = rc;
         if (rc != SIPG_OK) break;
     }
     // join every stream, also after a failure, so that s orders after all of them
     for (int k = 0; k < K; ++k) {
-        HIP_TRY(hipEventRecord(P->lz_join[k], P->lz_streams[k]));
-        HIP_TRY(hipStreamWaitEvent(s, P->lz_join[k], 0));
+        HIP_TRY(hipEventRecord(P->aux_join[k], P->aux_streams[k]));
+        HIP_TRY(hipStreamWaitEvent(s, P->aux_join[k], 0));
     }
     return first;
 }
 
+// Eigenvalue estimates (cached per level) and Chebyshev coefficients of the
+// preconditioner in P->opts: the finest level's polynomial, and with
+// multigrid every coarser level's (coarse_degree on the coarsest).
 sipg_status prepare_precond(sipg_plan* P, hipStream_t s) {
     const sipg_solve_opts& o = P->opts;
     const bool mg = o.precond_kind == SIPG_PRECOND_MULTIGRID;
@@ -1255,11 +1266,11 @@ void sipg_plan_destroy(sipg_plan* P) {
     if (!P) return;
     drop_graphs(P);
     if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
-    for (int k = 0; k < sipg_plan::kLzStreams; ++k) {
-        if (P->lz_streams[k]) (void)hipStreamDestroy(P->lz_streams[k]);
-        if (P->lz_join[k]) (void)hipEventDestroy(P->lz_join[k]);
+    for (int k = 0; k < sipg_plan::kAuxStreams; ++k) {
+        if (P->aux_streams[k]) (void)hipStreamDestroy(P->aux_streams[k]);
+        if (P->aux_join[k]) (void)hipEventDestroy(P->aux_join[k]);
     }
-    if (P->lz_fork) (void)hipEventDestroy(P->lz_fork);
+    if (P->aux_fork) (void)hipEventDestroy(P->aux_fork);
     for (sipg_plan* c : P->mg) sipg_plan_destroy(c);
     if (P->mirror) (void)hipHostFree(P->mirror);
     if (P->ev) (void)hipEventDestroy(P->ev);
