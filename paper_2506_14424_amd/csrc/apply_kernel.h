@@ -326,12 +326,14 @@ __device__ __forceinline__ void face_prefetch(const OpData<T>& op, const ApplyIO
 //   B2 geometry and flux at the face point;
 //   C1 transposed tangential sweeps of the flux, one line per task;
 //   C2 projection onto the cell's nodes (accumulated in y).
-template <int N, int C, typename T, bool CURVED, int D, int THREADS>
+template <int N, int C, typename T, bool CURVED, int D, int THREADS, bool G7>
 __device__ __forceinline__ void face_pass(const OpData<T>& op, const ApplyIO<T>& io, const CellIdx& ci, int s,
                                           T (&y)[C][N], const T* su, T* sw, T (*geo)[8][3],
                                           const LaneTab<T, N>& lt, const VolOff<N>& vo) {
+    // G7: the six neighbours' trilinear coefficients were staged in LDS at
+    // the start (geo[1 + face]); else the neighbour's are loaded here into geo[1]
     T nbl[C][N], mu_pre, tf_pre, gnb[8];
-    face_prefetch<N, C, T, CURVED, D>(op, io, ci, s, nbl, mu_pre, tf_pre, gnb);
+    face_prefetch<N, C, T, CURVED && !G7, D>(op, io, ci, s, nbl, mu_pre, tf_pre, gnb);
     constexpr int NN = N * N, NNN = N * N * N;
     constexpr int CS = Shape<N, C, sizeof(T) == 8>::CS;
     constexpr int t1 = D == 0 ? 1 : 0, t2 = D == 2 ? 1 : 2;
@@ -385,12 +387,12 @@ __device__ __forceinline__ void face_pass(const OpData<T>& op, const ApplyIO<T>&
             FT[(C + c) * NN + t] = w0;
         }
     }
-    if constexpr (CURVED) {
+    if constexpr (CURVED && !G7) {
         if (t < 3)
 #pragma unroll
             for (int k = 0; k < 8; ++k) geo[1][k][t] = gnb[k];
     }
-    if constexpr (CURVED || !(DPP || MF)) stage_sync<THREADS>();
+    if constexpr ((CURVED && !G7) || !(DPP || MF)) stage_sync<THREADS>();
 
     // ---- B1: tangential derivatives; task k = ((side*2 + dir)*C + c)*N + line
     // (n = 4: computed per lane from cross-lane moves or matrix-core products in B2)
@@ -453,7 +455,7 @@ __device__ __forceinline__ void face_pass(const OpData<T>& op, const ApplyIO<T>&
             // the neighbour's xi_D column at the same face point
             T xin[3] = {xi[0], xi[1], xi[2]};
             xin[D] = T(1 - s);
-            const T(*g)[3] = geo[1];
+            const T(*g)[3] = geo[G7 ? 1 + 2 * D + s : 1];
             T an[3];
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
@@ -1028,7 +1030,11 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
     // own / neighbour trilinear coefficients, [2][8][3] per cell; the odd cell
     // stride puts the four cells of a wavefront on different banks (their
     // reads are per-cell broadcasts)
-    constexpr int GS = 2 * 8 * 3 + 1;
+    // G7 (FP64 n = 4, curved, viscous/Poisson): the cell's and its six face
+    // neighbours' coefficients, [7][8][3] per cell plus 8 slots for the
+    // lanes without a second task, loaded with the nodal values
+    constexpr bool G7 = Sh::MF && CURVED && !PEN;
+    constexpr int GS = G7 ? 7 * 8 * 3 + 9 : 2 * 8 * 3 + 1;
     __shared__ T s_geo_all[CPB * GS];
     __shared__ LaneTab<T, N> s_lt;
 
@@ -1091,8 +1097,32 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
     }
 
     // ------------------------------------------------------------ load; xi_3 derivative of the own line
-    T gown[8];
-    if constexpr (CURVED) trilinear_coeffs(op.verts, op.nx, op.ny, ci.ex, ci.ey, ci.ez, t % 3, gown);
+    T gown[8], gsec[8];
+    int slotA = 0, slotB = 0, crdB = 0;
+    if constexpr (G7) {
+        // 21 tasks (7 cells x 3 coordinates) on the cell's 16 lanes: task t and task t + 16 (t < 5);
+        // slot 0 = the cell, slot 1 + f = the neighbour across face f = 2 D + s (the cell itself on the boundary)
+        auto cell_of = [&](int slot, int& cx, int& cy, int& cz) {
+            cx = ci.ex; cy = ci.ey; cz = ci.ez;
+            if (slot > 0) {
+                const int f = slot - 1, D = f >> 1, sd = f & 1;
+                if (D == 0) cx += sd ? (cx + 1 < op.nx ? 1 : 0) : (cx > 0 ? -1 : 0);
+                else if (D == 1) cy += sd ? (cy + 1 < op.ny ? 1 : 0) : (cy > 0 ? -1 : 0);
+                else cz += sd ? (cz + 1 < op.nz ? 1 : 0) : (cz > 0 ? -1 : 0);
+            }
+        };
+        int cx, cy, cz;
+        slotA = t / 3;
+        cell_of(slotA, cx, cy, cz);
+        trilinear_coeffs(op.verts, op.nx, op.ny, cx, cy, cz, t % 3, gown);
+        const int tb2 = t < 5 ? t + 16 : 0;   // lanes t >= 5: a duplicate of task 0, stored into the spare slots
+        slotB = tb2 / 3;
+        crdB = tb2 % 3;
+        cell_of(slotB, cx, cy, cz);
+        trilinear_coeffs(op.verts, op.nx, op.ny, cx, cy, cz, crdB, gsec);
+    } else if constexpr (CURVED) {
+        trilinear_coeffs(op.verts, op.nx, op.ny, ci.ex, ci.ey, ci.ez, t % 3, gown);
+    }
     T muq[N];  // viscosity on the own xi_3 line of quadrature points, loaded with the nodal values
     if constexpr (C == 3)
 #pragma unroll
@@ -1170,7 +1200,14 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
             }
         }
     }
-    if constexpr (CURVED) {
+    if constexpr (G7) {
+        T* gl = s_geo_all + lc * GS;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            gl[(slotA * 8 + k) * 3 + t % 3] = gown[k];
+            gl[t < 5 ? (slotB * 8 + k) * 3 + crdB : 7 * 24 + k] = gsec[k];
+        }
+    } else if constexpr (CURVED) {
         // unconditional stores keep the loads at the top (lanes t >= 3 write into the
         // neighbour slot, which every face stage rewrites before reading it)
 #pragma unroll
@@ -1355,9 +1392,9 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
                 else if (f < 4) face_pass_pen<N, T, CURVED, 1, THREADS>(op, io, ci, s, y, su, sw, geo, lt, vo);
                 else face_pass_pen<N, T, CURVED, 2, THREADS>(op, io, ci, s, y, su, sw, geo, lt, vo);
             } else {
-                if (f < 2) face_pass<N, C, T, CURVED, 0, THREADS>(op, io, ci, s, y, su, sw, geo, lt, vo);
-                else if (f < 4) face_pass<N, C, T, CURVED, 1, THREADS>(op, io, ci, s, y, su, sw, geo, lt, vo);
-                else face_pass<N, C, T, CURVED, 2, THREADS>(op, io, ci, s, y, su, sw, geo, lt, vo);
+                if (f < 2) face_pass<N, C, T, CURVED, 0, THREADS, G7>(op, io, ci, s, y, su, sw, geo, lt, vo);
+                else if (f < 4) face_pass<N, C, T, CURVED, 1, THREADS, G7>(op, io, ci, s, y, su, sw, geo, lt, vo);
+                else face_pass<N, C, T, CURVED, 2, THREADS, G7>(op, io, ci, s, y, su, sw, geo, lt, vo);
             }
         }
     }
