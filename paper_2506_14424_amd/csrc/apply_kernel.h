@@ -316,6 +316,55 @@ __device__ __forceinline__ void face_prefetch(const OpData<T>& op, const ApplyIO
     tf = live ? tff : T(0);
 }
 
+// The neighbour's line of nodal values through this lane's face point of
+// face f = 2 D + s (D known only at run time), with the face viscosity and
+// the penalty factor, masked like face_prefetch: the next face's data,
+// loaded while the current face is computed.
+template <int N, int C, typename T>
+struct FacePre {
+    T nb[C][N];
+    T mu, tf;
+};
+
+template <int N, int C, typename T>
+__device__ __forceinline__ void face_load_rt(const OpData<T>& op, const ApplyIO<T>& io, const CellIdx& ci, int f,
+                                             FacePre<N, C, T>& p) {
+    constexpr int NN = N * N, NNN = N * N * N;
+    const int D = f >> 1, s = f & 1;
+    // arithmetic selects: a select of struct fields by a run-time D becomes
+    // a run-time address and sends the whole struct to scratch
+    const int d0 = D == 0, d1 = D == 1, d2 = D == 2;
+    const int pos = d0 * ci.ex + d1 * ci.ey + d2 * ci.ez;
+    const int lim = d0 * op.nx + d1 * op.ny + d2 * op.nz;
+    const bool has_nb = s == 1 ? pos + 1 < lim : pos > 0;
+    const int stride = d0 + d1 * op.nx + d2 * op.nx * op.ny;
+    const int en = has_nb ? ci.ec + (s == 1 ? stride : -stride) : ci.ec;
+    const int bcf = f == 0 ? op.bc[0] : f == 1 ? op.bc[1] : f == 2 ? op.bc[2] : f == 3 ? op.bc[3] : f == 4 ? op.bc[4]
+                                                                                                     : op.bc[5];
+    const bool dir = !has_nb && bcf == 0;
+    const bool live = ci.active && (has_nb ? (io.parts & SIPG_PART_INTERIOR) != 0
+                                           : (dir && (io.parts & SIPG_PART_BOUNDARY) != 0));
+    const int fid = d0 * ((ci.ez * op.ny + ci.ey) * (op.nx + 1) + ci.ex + s) +
+                    d1 * (op.nfx + (ci.ez * (op.ny + 1) + ci.ey + s) * op.nx + ci.ex) +
+                    d2 * (op.nfx + op.nfy + ((ci.ez + s) * op.ny + ci.ey) * op.nx + ci.ex);
+    // node j along D of the line through face point (i1, i2): base + j * step
+    const int base = d2 * (ci.i2 * N + ci.i1) + d0 * (ci.i2 * NN + ci.i1 * N) + d1 * (ci.i2 * NN + ci.i1);
+    const int step = d2 * NN + d0 + d1 * N;
+    const T* xn = (io.xnb ? io.xnb : io.x) + (size_t)en * (C * NNN) + base;
+    const bool ld = live && has_nb;
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            const T v = xn[c * NNN + j * step];  // en and fid are valid for every lane: load unconditionally
+            p.nb[c][j] = ld ? v : T(0);
+        }
+    const T muf = C == 3 ? op.mu_face[(size_t)fid * NN + ci.t] : T(1);
+    const T tff = op.tfac[fid];
+    p.mu = live ? muf : T(1);
+    p.tf = live ? tff : T(0);
+}
+
 // ---------------------------------------------------------------- faces
 //
 // One face of the cell (direction D, side s), in stages separated by LDS
@@ -329,11 +378,23 @@ __device__ __forceinline__ void face_prefetch(const OpData<T>& op, const ApplyIO
 template <int N, int C, typename T, bool CURVED, int D, int THREADS, bool G7>
 __device__ __forceinline__ void face_pass(const OpData<T>& op, const ApplyIO<T>& io, const CellIdx& ci, int s,
                                           T (&y)[C][N], const T* su, T* sw, T (*geo)[8][3],
-                                          const LaneTab<T, N>& lt, const VolOff<N>& vo) {
+                                          const LaneTab<T, N>& lt, const VolOff<N>& vo, FacePre<N, C, T>& pre,
+                                          int fnext) {
     // G7: the six neighbours' trilinear coefficients were staged in LDS at
-    // the start (geo[1 + face]); else the neighbour's are loaded here into geo[1]
+    // the start (geo[1 + face]) and this face's neighbour line, viscosity and
+    // penalty factor were loaded during the previous face (pre); else all
+    // of it is loaded here (the neighbour's coefficients into geo[1])
     T nbl[C][N], mu_pre, tf_pre, gnb[8];
-    face_prefetch<N, C, T, CURVED && !G7, D>(op, io, ci, s, nbl, mu_pre, tf_pre, gnb);
+    if constexpr (G7) {
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int j = 0; j < N; ++j) nbl[c][j] = pre.nb[c][j];
+        mu_pre = pre.mu;
+        tf_pre = pre.tf;
+    } else {
+        face_prefetch<N, C, T, CURVED, D>(op, io, ci, s, nbl, mu_pre, tf_pre, gnb);
+    }
     constexpr int NN = N * N, NNN = N * N * N;
     constexpr int CS = Shape<N, C, sizeof(T) == 8>::CS;
     constexpr int t1 = D == 0 ? 1 : 0, t2 = D == 2 ? 1 : 2;
@@ -391,6 +452,9 @@ __device__ __forceinline__ void face_pass(const OpData<T>& op, const ApplyIO<T>&
         if (t < 3)
 #pragma unroll
             for (int k = 0; k < 8; ++k) geo[1][k][t] = gnb[k];
+    }
+    if constexpr (G7) {
+        if (fnext < 6) face_load_rt<N, C, T>(op, io, ci, fnext, pre);  // the traces are formed
     }
     if constexpr ((CURVED && !G7) || !(DPP || MF)) stage_sync<THREADS>();
 
@@ -1373,6 +1437,8 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
         // preconditioner): a face pass that no cell of the workgroup needs
         // is skipped as a whole (the vote is uniform over the workgroup)
         const bool only_boundary = (io.parts & SIPG_PART_INTERIOR) == 0;
+        FacePre<N, C, T> pre;
+        if constexpr (G7) face_load_rt<N, C, T>(op, io, ci, 0, pre);
 #pragma unroll 1
         for (int f = 0; f < 6; ++f) {
             const int s = f & 1;
@@ -1385,16 +1451,21 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
                 bool any;
                 if constexpr (THREADS <= 64) any = __ballot(need) != 0;
                 else any = __syncthreads_or(need) != 0;
-                if (!any) continue;
+                if (!any) {
+                    if constexpr (G7) {
+                        if (f + 1 < 6) face_load_rt<N, C, T>(op, io, ci, f + 1, pre);
+                    }
+                    continue;
+                }
             }
             if constexpr (PEN) {
                 if (f < 2) face_pass_pen<N, T, CURVED, 0, THREADS>(op, io, ci, s, y, su, sw, geo, lt, vo);
                 else if (f < 4) face_pass_pen<N, T, CURVED, 1, THREADS>(op, io, ci, s, y, su, sw, geo, lt, vo);
                 else face_pass_pen<N, T, CURVED, 2, THREADS>(op, io, ci, s, y, su, sw, geo, lt, vo);
             } else {
-                if (f < 2) face_pass<N, C, T, CURVED, 0, THREADS, G7>(op, io, ci, s, y, su, sw, geo, lt, vo);
-                else if (f < 4) face_pass<N, C, T, CURVED, 1, THREADS, G7>(op, io, ci, s, y, su, sw, geo, lt, vo);
-                else face_pass<N, C, T, CURVED, 2, THREADS, G7>(op, io, ci, s, y, su, sw, geo, lt, vo);
+                if (f < 2) face_pass<N, C, T, CURVED, 0, THREADS, G7>(op, io, ci, s, y, su, sw, geo, lt, vo, pre, f + 1);
+                else if (f < 4) face_pass<N, C, T, CURVED, 1, THREADS, G7>(op, io, ci, s, y, su, sw, geo, lt, vo, pre, f + 1);
+                else face_pass<N, C, T, CURVED, 2, THREADS, G7>(op, io, ci, s, y, su, sw, geo, lt, vo, pre, f + 1);
             }
         }
     }
