@@ -375,17 +375,17 @@ __device__ __forceinline__ void face_load_rt(const OpData<T>& op, const ApplyIO<
 //   B2 geometry and flux at the face point;
 //   C1 transposed tangential sweeps of the flux, one line per task;
 //   C2 projection onto the cell's nodes (accumulated in y).
-template <int N, int C, typename T, bool CURVED, int D, int THREADS, bool G7>
+template <int N, int C, typename T, bool CURVED, int D, int THREADS, bool G7, bool LA>
 __device__ __forceinline__ void face_pass(const OpData<T>& op, const ApplyIO<T>& io, const CellIdx& ci, int s,
                                           T (&y)[C][N], const T* su, T* sw, T (*geo)[8][3],
                                           const LaneTab<T, N>& lt, const VolOff<N>& vo, FacePre<N, C, T>& pre,
                                           int fnext) {
     // G7: the six neighbours' trilinear coefficients were staged in LDS at
-    // the start (geo[1 + face]) and this face's neighbour line, viscosity and
-    // penalty factor were loaded during the previous face (pre); else all
-    // of it is loaded here (the neighbour's coefficients into geo[1])
+    // the start (geo[1 + face]); LA: this face's neighbour line, viscosity
+    // and penalty factor were loaded during the previous face (pre); else
+    // they are loaded here (and the neighbour's coefficients into geo[1])
     T nbl[C][N], mu_pre, tf_pre, gnb[8];
-    if constexpr (G7) {
+    if constexpr (LA) {
 #pragma unroll
         for (int c = 0; c < C; ++c)
 #pragma unroll
@@ -393,7 +393,7 @@ __device__ __forceinline__ void face_pass(const OpData<T>& op, const ApplyIO<T>&
         mu_pre = pre.mu;
         tf_pre = pre.tf;
     } else {
-        face_prefetch<N, C, T, CURVED, D>(op, io, ci, s, nbl, mu_pre, tf_pre, gnb);
+        face_prefetch<N, C, T, CURVED && !G7, D>(op, io, ci, s, nbl, mu_pre, tf_pre, gnb);
     }
     constexpr int NN = N * N, NNN = N * N * N;
     constexpr int CS = Shape<N, C, sizeof(T) == 8>::CS;
@@ -453,7 +453,7 @@ __device__ __forceinline__ void face_pass(const OpData<T>& op, const ApplyIO<T>&
 #pragma unroll
             for (int k = 0; k < 8; ++k) geo[1][k][t] = gnb[k];
     }
-    if constexpr (G7) {
+    if constexpr (LA) {
         if (fnext < 6) face_load_rt<N, C, T>(op, io, ci, fnext, pre);  // the traces are formed
     }
     if constexpr ((CURVED && !G7) || !(DPP || MF)) stage_sync<THREADS>();
@@ -1094,10 +1094,16 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
     // own / neighbour trilinear coefficients, [2][8][3] per cell; the odd cell
     // stride puts the four cells of a wavefront on different banks (their
     // reads are per-cell broadcasts)
-    // G7 (FP64 n = 4, curved, viscous/Poisson): the cell's and its six face
-    // neighbours' coefficients, [7][8][3] per cell plus 8 slots for the
-    // lanes without a second task, loaded with the nodal values
-    constexpr bool G7 = Sh::MF && CURVED && !PEN;
+    // G7 (curved cells, all six faces computed; FP64 n = 4 and FP32 n >= 5):
+    // the cell's and its six face neighbours' trilinear coefficients,
+    // [7][8][3] per cell plus 8 spare slots for lanes without a task, loaded
+    // with the nodal values.  Measured per instance: c2 FP64 116 -> 111 us,
+    // c3 FP32 82 -> 70 us; slower for FP64 n = 5 (133 -> 142 us, its
+    // registers are full) and FP32 n = 4 (71 -> 73 us); for n <= 3 a cell has
+    // too few lanes for the 21 tasks.  LA (where the registers fit): each
+    // face's neighbour data loaded during the previous face
+    constexpr bool G7 = CURVED && !PEN && MODE != MODE_CONT && (Sh::MF || (sizeof(T) == 4 && N >= 5));
+    constexpr bool LA = G7 && Sh::MF;
     constexpr int GS = G7 ? 7 * 8 * 3 + 9 : 2 * 8 * 3 + 1;
     __shared__ T s_geo_all[CPB * GS];
     __shared__ LaneTab<T, N> s_lt;
@@ -1161,10 +1167,11 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
     }
 
     // ------------------------------------------------------------ load; xi_3 derivative of the own line
-    T gown[8], gsec[8];
-    int slotA = 0, slotB = 0, crdB = 0;
+    constexpr int GR = G7 ? (21 + NN - 1) / NN : 1;   // rounds of the 21 staging tasks over a cell's n^2 lanes
+    T gt[GR][8];
+    int gslot[GR], gcrd[GR];
     if constexpr (G7) {
-        // 21 tasks (7 cells x 3 coordinates) on the cell's 16 lanes: task t and task t + 16 (t < 5);
+        // 21 tasks (7 cells x 3 coordinates): lane t takes tasks t, t + n^2, ...;
         // slot 0 = the cell, slot 1 + f = the neighbour across face f = 2 D + s (the cell itself on the boundary)
         auto cell_of = [&](int slot, int& cx, int& cy, int& cz) {
             cx = ci.ex; cy = ci.ey; cz = ci.ez;
@@ -1175,17 +1182,18 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
                 else cz += sd ? (cz + 1 < op.nz ? 1 : 0) : (cz > 0 ? -1 : 0);
             }
         };
-        int cx, cy, cz;
-        slotA = t / 3;
-        cell_of(slotA, cx, cy, cz);
-        trilinear_coeffs(op.verts, op.nx, op.ny, cx, cy, cz, t % 3, gown);
-        const int tb2 = t < 5 ? t + 16 : 0;   // lanes t >= 5: a duplicate of task 0, stored into the spare slots
-        slotB = tb2 / 3;
-        crdB = tb2 % 3;
-        cell_of(slotB, cx, cy, cz);
-        trilinear_coeffs(op.verts, op.nx, op.ny, cx, cy, cz, crdB, gsec);
+#pragma unroll
+        for (int r = 0; r < GR; ++r) {
+            const int task = t + r * NN;
+            const int tk = task < 21 ? task : 0;   // past the last task: a duplicate of task 0, stored into the spare slots
+            int cx, cy, cz;
+            cell_of(tk / 3, cx, cy, cz);
+            trilinear_coeffs(op.verts, op.nx, op.ny, cx, cy, cz, tk % 3, gt[r]);
+            gslot[r] = task < 21 ? tk / 3 : 7;
+            gcrd[r] = tk % 3;
+        }
     } else if constexpr (CURVED) {
-        trilinear_coeffs(op.verts, op.nx, op.ny, ci.ex, ci.ey, ci.ez, t % 3, gown);
+        trilinear_coeffs(op.verts, op.nx, op.ny, ci.ex, ci.ey, ci.ez, t % 3, gt[0]);
     }
     T muq[N];  // viscosity on the own xi_3 line of quadrature points, loaded with the nodal values
     if constexpr (C == 3)
@@ -1267,15 +1275,14 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
     if constexpr (G7) {
         T* gl = s_geo_all + lc * GS;
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            gl[(slotA * 8 + k) * 3 + t % 3] = gown[k];
-            gl[t < 5 ? (slotB * 8 + k) * 3 + crdB : 7 * 24 + k] = gsec[k];
-        }
+        for (int r = 0; r < GR; ++r)
+#pragma unroll
+            for (int k = 0; k < 8; ++k) gl[gslot[r] < 7 ? (gslot[r] * 8 + k) * 3 + gcrd[r] : 7 * 24 + k] = gt[r][k];
     } else if constexpr (CURVED) {
         // unconditional stores keep the loads at the top (lanes t >= 3 write into the
         // neighbour slot, which every face stage rewrites before reading it)
 #pragma unroll
-        for (int k = 0; k < 8; ++k) *(t < 3 ? &geo[0][k][t] : &geo[1][k][0]) = gown[k];
+        for (int k = 0; k < 8; ++k) *(t < 3 ? &geo[0][k][t] : &geo[1][k][0]) = gt[0][k];
     }
     __syncthreads();
     const LaneTab<T, N>& lt = s_lt;
@@ -1438,7 +1445,7 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
         // is skipped as a whole (the vote is uniform over the workgroup)
         const bool only_boundary = (io.parts & SIPG_PART_INTERIOR) == 0;
         FacePre<N, C, T> pre;
-        if constexpr (G7) face_load_rt<N, C, T>(op, io, ci, 0, pre);
+        if constexpr (LA) face_load_rt<N, C, T>(op, io, ci, 0, pre);
 #pragma unroll 1
         for (int f = 0; f < 6; ++f) {
             const int s = f & 1;
@@ -1452,7 +1459,7 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
                 if constexpr (THREADS <= 64) any = __ballot(need) != 0;
                 else any = __syncthreads_or(need) != 0;
                 if (!any) {
-                    if constexpr (G7) {
+                    if constexpr (LA) {
                         if (f + 1 < 6) face_load_rt<N, C, T>(op, io, ci, f + 1, pre);
                     }
                     continue;
@@ -1463,9 +1470,9 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
                 else if (f < 4) face_pass_pen<N, T, CURVED, 1, THREADS>(op, io, ci, s, y, su, sw, geo, lt, vo);
                 else face_pass_pen<N, T, CURVED, 2, THREADS>(op, io, ci, s, y, su, sw, geo, lt, vo);
             } else {
-                if (f < 2) face_pass<N, C, T, CURVED, 0, THREADS, G7>(op, io, ci, s, y, su, sw, geo, lt, vo, pre, f + 1);
-                else if (f < 4) face_pass<N, C, T, CURVED, 1, THREADS, G7>(op, io, ci, s, y, su, sw, geo, lt, vo, pre, f + 1);
-                else face_pass<N, C, T, CURVED, 2, THREADS, G7>(op, io, ci, s, y, su, sw, geo, lt, vo, pre, f + 1);
+                if (f < 2) face_pass<N, C, T, CURVED, 0, THREADS, G7, LA>(op, io, ci, s, y, su, sw, geo, lt, vo, pre, f + 1);
+                else if (f < 4) face_pass<N, C, T, CURVED, 1, THREADS, G7, LA>(op, io, ci, s, y, su, sw, geo, lt, vo, pre, f + 1);
+                else face_pass<N, C, T, CURVED, 2, THREADS, G7, LA>(op, io, ci, s, y, su, sw, geo, lt, vo, pre, f + 1);
             }
         }
     }
