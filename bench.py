@@ -752,7 +752,7 @@ def main():
                          "note": "executed FP64 operations from SQ counters (vector FMA counted twice, plus "
                                  "the 4x4x4 matrix-core products of the 1D sweeps), divided by the "
                                  "event-timed launch; the kernel reaches neither this roof nor the HBM "
-                                 "roof: its VALU issue floor is 42 % of the launch, the rest is latency "
+                                 "roof: its VALU issue floor is 42-47 % of the launch, the rest is latency "
                                  "at 2 wavefronts per SIMD"}},
         "fp32_apply": {"dof_per_s": op.ndof * k / (r32["event_ms"] * 1e-3),
                        "avg_launch_ms": r32["event_ms"] / k,
