@@ -366,9 +366,10 @@ __device__ __forceinline__ void face_pass(const OpData<T>& op, const ApplyIO<T>&
                                           const LaneTab<T, N>& lt, const VolOff<N>& vo, FacePre<N, C, T>& pre,
                                           int fnext) {
     // G7: the six neighbours' trilinear coefficients were staged in LDS at
-    // the start (geo[1 + face]); LA: this face's neighbour line, viscosity
-    // and penalty factor were loaded during the previous face (pre); else
-    // they are loaded here (and the neighbour's coefficients into geo[1])
+    // the start (geo[1 + face]); LA: this face's neighbour line was loaded
+    // during the previous face (pre, masked below) and the face viscosity
+    // and penalty factor are loaded below; else all of them are loaded here
+    // (and the neighbour's coefficients into geo[1])
     T nbl[C][N], mu_pre, tf_pre, gnb[8];
     if constexpr (!LA) face_prefetch<N, C, T, CURVED && !G7, D>(op, io, ci, s, nbl, mu_pre, tf_pre, gnb);
     constexpr int NN = N * N, NNN = N * N * N;

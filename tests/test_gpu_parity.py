@@ -63,6 +63,18 @@ def small_cases():
     p1.update(nx=4, ny=3, nz=2, degree=4, alpha=2.5, bc=("D", "N", "D", "D", "N", "D"), perturb=0.1,
               name="poisson-curved")
     out.append(("poisson-curved", p1))
+    # degenerate and ragged meshes for the octant cell order (a dimension of
+    # one cell, odd counts, a partial last workgroup) on the matrix-core
+    # instance (k = 3) and on k = 4
+    t1 = W.config("c2", 3)
+    t1.update(nx=1, ny=5, nz=3, bc=("D", "N", "D", "D", "N", "D"), name="thin-k3")
+    out.append(("thin-k3", t1))
+    t2 = W.config("c2", 3)
+    t2.update(nx=7, ny=1, nz=2, name="ragged-k3")
+    out.append(("ragged-k3", t2))
+    t3 = W.config("c3", 3)
+    t3.update(nx=1, ny=1, nz=1, name="single-k4")
+    out.append(("single-k4", t3))
     return out
 
 
