@@ -1097,10 +1097,12 @@ __global__ void __launch_bounds__((Shape<N, C, sizeof(T) == 8>::THREADS)) __attr
     // with the nodal values.  Measured per instance: c2 FP64 116 -> 111 us,
     // c3 FP32 82 -> 70 us; slower for FP64 n = 5 (133 -> 142 us, its
     // registers are full) and FP32 n = 4 (71 -> 73 us); for n <= 3 a cell has
-    // too few lanes for the 21 tasks.  LA (where the registers fit): each
-    // face's neighbour data loaded during the previous face
+    // too few lanes for the 21 tasks.  LA (where the registers fit: every
+    // G7 instance, FP64 n = 4 and FP32 n = 5, 6): each face's neighbour line
+    // loaded during the previous face (FP32 n = 5: 151 -> 165 VGPRs, still
+    // 3 wavefronts per SIMD; c3 FP32 apply 69.4 -> 66.9 us)
     constexpr bool G7 = CURVED && !PEN && MODE != MODE_CONT && (Sh::MF || (sizeof(T) == 4 && N >= 5));
-    constexpr bool LA = G7 && Sh::MF;
+    constexpr bool LA = G7;
     constexpr int GS = G7 ? 7 * 8 * 3 + 9 : 2 * 8 * 3 + 1;
     __shared__ T s_geo_all[CPB * GS];
     __shared__ LaneTab<T, N> s_lt;
