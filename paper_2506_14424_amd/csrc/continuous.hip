@@ -23,6 +23,7 @@
 // Every kernel used inside a solve returns at once while *skip != 0.
 
 #include <cstring>
+#include <type_traits>
 
 #include "device_common.h"
 
@@ -155,6 +156,70 @@ __global__ void k_cg_assemble(CgGeo g, const T* local, T* out, const AsmIO<T> io
             io.d[idx] = dn;
             out[idx] = io.z[idx] + dn;
         }
+    }
+}
+
+// The same sum for a level of degree J known at compile time, one thread per
+// node of a (gz, component) plane: grid (ceil(Mx My / 256), Mz C).  Along
+// each axis a node has a lower candidate cell (g / J - 1, local index J; it
+// exists when g is a positive multiple of J) and an upper one (g / J, local
+// index g % J; it exists when g / J < cells).  All eight candidate loads are
+// issued together, a missing candidate reading the existing one along its
+// axis (in bounds, the same cache line), and the sum takes the existing ones
+// in the generic kernel's order (lower before upper, z, then y, then x), so
+// the two kernels agree bit for bit.  The generic kernel's run-time trip
+// counts issued the up to eight loads one after another, and its 64-bit
+// index divisions cost more than the sums.
+template <typename T, int MODE, int J>
+__global__ void __launch_bounds__(kThreads) k_cg_assemble_j(CgGeo g, const T* local, T* out, const AsmIO<T> io,
+                                                            const int* skip) {
+    if (skip != nullptr && *skip) return;
+    constexpr int n = J + 1, n3 = n * n * n;
+    const int plane = g.Mx * g.My;
+    const int xy = blockIdx.x * kThreads + threadIdx.x;
+    if (xy >= plane) return;
+    const int c = blockIdx.y / g.Mz, gz = blockIdx.y - c * g.Mz;  // uniform over the block
+    const int gy = xy / g.Mx, gx = xy - gy * g.Mx;
+    int ex[2], ax[2], ey[2], ay[2], ez[2], az[2];
+    bool vx[2], vy[2], vz[2];
+    auto cand = [](int gg, int cells, int e[2], int a[2], bool v[2]) {
+        const int q = gg / J, r = gg - q * J;
+        v[0] = r == 0 && gg > 0;
+        v[1] = q < cells;
+        e[1] = v[1] ? q : q - 1;   // the node at the far end has only the lower cell
+        a[1] = v[1] ? r : J;
+        e[0] = v[0] ? q - 1 : e[1];
+        a[0] = v[0] ? J : a[1];
+    };
+    cand(gx, g.nx, ex, ax, vx);
+    cand(gy, g.ny, ey, ay, vy);
+    cand(gz, g.nz, ez, az, vz);
+    T val[2][2][2];
+#pragma unroll
+    for (int kz = 0; kz < 2; ++kz)
+#pragma unroll
+        for (int ky = 0; ky < 2; ++ky)
+#pragma unroll
+            for (int kx = 0; kx < 2; ++kx) {
+                const long long e = ((long long)ez[kz] * g.ny + ey[ky]) * g.nx + ex[kx];
+                val[kz][ky][kx] = local[(e * g.C + c) * n3 + (az[kz] * n + ay[ky]) * n + ax[kx]];
+            }
+    T acc = 0;
+#pragma unroll
+    for (int kz = 0; kz < 2; ++kz)
+#pragma unroll
+        for (int ky = 0; ky < 2; ++ky)
+#pragma unroll
+            for (int kx = 0; kx < 2; ++kx) acc = (vz[kz] && vy[ky] && vx[kx]) ? acc + val[kz][ky][kx] : acc;
+    const long long idx = (long long)c * plane * g.Mz + (long long)gz * plane + xy;
+    if constexpr (MODE == ASM_SUM) {
+        out[idx] = acc;
+    } else if constexpr (MODE == ASM_RESID) {
+        out[idx] = io.r[idx] - acc;
+    } else {
+        const T dn = T(io.coef[0]) * io.d[idx] + T(io.coef[1]) * io.dinv[idx] * (io.r[idx] - acc);
+        io.d[idx] = dn;
+        out[idx] = io.z[idx] + dn;
     }
 }
 
@@ -479,6 +544,27 @@ hipError_t launch_cg_assemble(const CgGeo& g, const T* local, T* cg, const int* 
     const long long total = (long long)g.Mx * g.My * g.Mz * g.C;
     AsmIO<T> io;
     io.r = r; io.z = z; io.d = d; io.dinv = dinv; io.coef = coef;
+    const long long planes = (long long)g.Mz * g.C;
+    if (g.j >= 1 && g.j <= 5 && planes <= 65535) {
+        const dim3 grid((unsigned)(((long long)g.Mx * g.My + kThreads - 1) / kThreads), (unsigned)planes);
+        auto go = [&](auto jc) {
+            constexpr int J = decltype(jc)::value;
+            if (mode == 1)
+                hipLaunchKernelGGL((k_cg_assemble_j<T, ASM_RESID, J>), grid, dim3(kThreads), 0, s, g, local, cg, io, skip);
+            else if (mode == 2)
+                hipLaunchKernelGGL((k_cg_assemble_j<T, ASM_CHEB, J>), grid, dim3(kThreads), 0, s, g, local, cg, io, skip);
+            else
+                hipLaunchKernelGGL((k_cg_assemble_j<T, ASM_SUM, J>), grid, dim3(kThreads), 0, s, g, local, cg, io, skip);
+        };
+        switch (g.j) {
+            case 1: go(std::integral_constant<int, 1>{}); break;
+            case 2: go(std::integral_constant<int, 2>{}); break;
+            case 3: go(std::integral_constant<int, 3>{}); break;
+            case 4: go(std::integral_constant<int, 4>{}); break;
+            default: go(std::integral_constant<int, 5>{}); break;
+        }
+        return hipGetLastError();
+    }
     const dim3 ag(grid_for(total));
     if (mode == 1) hipLaunchKernelGGL((k_cg_assemble<T, ASM_RESID>), ag, dim3(kThreads), 0, s, g, local, cg, io, skip);
     else if (mode == 2) hipLaunchKernelGGL((k_cg_assemble<T, ASM_CHEB>), ag, dim3(kThreads), 0, s, g, local, cg, io, skip);
