@@ -247,6 +247,30 @@ __global__ void k_axis(AxisMat<T> M, int axis, int C, int n0, int n1, int n2, co
     }
 }
 
+// The same with 32-bit indices on a 2D grid: x over the (i0, i1) plane of
+// the output, y over (i2, c) (the generic kernel's 64-bit index divisions
+// cost more than the few products of a row).
+template <typename T, bool ADD>
+__global__ void __launch_bounds__(kThreads) k_axis2(AxisMat<T> M, int axis, int n0, int n1, int n2, int o0, int o1,
+                                                     int o2, const T* in, T* out, const int* skip) {
+    if (skip != nullptr && *skip) return;
+    const int plane = o0 * o1;
+    const int xy = blockIdx.x * kThreads + threadIdx.x;
+    if (xy >= plane) return;
+    const int c = blockIdx.y / o2, i2 = blockIdx.y - c * o2;  // uniform over the block
+    const int i1 = xy / o0, i0 = xy - i1 * o0;
+    const int row = axis == 0 ? i0 : axis == 1 ? i1 : i2;
+    T acc = 0;
+    for (int k = M.rp[row]; k < M.rp[row + 1]; ++k) {
+        const int col = M.ci[k];
+        const int j0 = axis == 0 ? col : i0, j1 = axis == 1 ? col : i1, j2 = axis == 2 ? col : i2;
+        acc += M.v[k] * in[(((long long)c * n2 + j2) * n1 + j1) * n0 + j0];
+    }
+    const long long idx = ((long long)c * o2 + i2) * plane + xy;
+    if (ADD) out[idx] += acc;
+    else out[idx] = acc;
+}
+
 // Chebyshev step of a continuous level: d <- c1 d + c2 dinv (r - t),
 // zn = z + d (t = A z computed before).
 template <typename T>
@@ -576,6 +600,18 @@ template <typename T>
 hipError_t launch_axis(const AxisMat<T>& M, int axis, int C, int n0, int n1, int n2, const T* in, T* out, bool add,
                        const int* skip, hipStream_t s) {
     long long total = (long long)C * (axis == 0 ? M.rows : n0) * (axis == 1 ? M.rows : n1) * (axis == 2 ? M.rows : n2);
+    const int o0 = axis == 0 ? M.rows : n0, o1 = axis == 1 ? M.rows : n1, o2 = axis == 2 ? M.rows : n2;
+    const long long plane = (long long)o0 * o1, planes = (long long)o2 * C;
+    if (plane < (1ll << 31) && planes <= 65535) {
+        const dim3 grid((unsigned)((plane + kThreads - 1) / kThreads), (unsigned)planes);
+        if (add)
+            hipLaunchKernelGGL((k_axis2<T, true>), grid, dim3(kThreads), 0, s, M, axis, n0, n1, n2, o0, o1, o2, in, out,
+                               skip);
+        else
+            hipLaunchKernelGGL((k_axis2<T, false>), grid, dim3(kThreads), 0, s, M, axis, n0, n1, n2, o0, o1, o2, in, out,
+                               skip);
+        return hipGetLastError();
+    }
     if (add)
         hipLaunchKernelGGL((k_axis<T, true>), dim3(grid_for(total)), dim3(kThreads), 0, s, M, axis, C, n0, n1, n2, in,
                            out, skip);
