@@ -547,19 +547,18 @@ hipError_t launch_cg_gather(const CgGeo& g, const CgL<T>& tab, const T* cg, T* d
 }
 
 template <typename T>
+hipError_t launch_cg_assemble(const CgGeo& g, const T* local, T* cg, const int* skip, hipStream_t s, int mode,
+                              const T* r, const T* z, T* d, const T* dinv, const double* coef);
+
+template <typename T>
 hipError_t launch_cg_scatter(const CgGeo& g, const CgL<T>& tab, T* dg, T* cg, const int* skip, hipStream_t s,
                              int mode, const T* r, const T* z, T* d, const T* dinv, const double* coef) {
     const int ncell = g.nx * g.ny * g.nz;
     const dim3 grid((unsigned)(ncell < 65535 ? ncell : 65535));
     hipLaunchKernelGGL((k_cg_cell<T, false, false>), grid, dim3(kCellThreads), 0, s, g, tab, dg, dg, skip);
-    const long long total = (long long)g.Mx * g.My * g.Mz * g.C;
-    AsmIO<T> io;
-    io.r = r; io.z = z; io.d = d; io.dinv = dinv; io.coef = coef;
-    const dim3 ag(grid_for(total));
-    if (mode == 1) hipLaunchKernelGGL((k_cg_assemble<T, ASM_RESID>), ag, dim3(kThreads), 0, s, g, dg, cg, io, skip);
-    else if (mode == 2) hipLaunchKernelGGL((k_cg_assemble<T, ASM_CHEB>), ag, dim3(kThreads), 0, s, g, dg, cg, io, skip);
-    else hipLaunchKernelGGL((k_cg_assemble<T, ASM_SUM>), ag, dim3(kThreads), 0, s, g, dg, cg, io, skip);
-    return hipGetLastError();
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_cg_assemble<T>(g, dg, cg, skip, s, mode, r, z, d, dinv, coef);
 }
 
 template <typename T>
