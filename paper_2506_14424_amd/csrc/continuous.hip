@@ -102,6 +102,79 @@ __global__ void __launch_bounds__(kCellThreads) k_cg_cell(CgGeo g, const CgL<T> 
     }
 }
 
+// The same for a degree known at compile time (n = N per direction): the
+// 1D table in LDS, the index arithmetic by constants and the short loops
+// unrolled; the sums are the generic kernel's, in the same order.
+template <typename T, bool GATHER, bool ADD, int N>
+__global__ void __launch_bounds__(kCellThreads) k_cg_cell_n(CgGeo g, const CgL<T> tab, const T* in, T* out,
+                                                           const int* skip) {
+    if (skip != nullptr && *skip) return;
+    constexpr int n = N, j = N - 1, nn = N * N, n3 = N * N * N;
+    __shared__ T A[kCellVals], B[kCellVals];
+    __shared__ T Wt[N][N];  // Wt[b][a] = W(b, a)
+    const int C = g.C, nin = C * n3;
+    const long long nv = (long long)g.Mx * g.My * g.Mz;
+    const int ncell = g.nx * g.ny * g.nz;
+    if ((int)threadIdx.x < nn) {
+        const int b = threadIdx.x / n, a = threadIdx.x - b * n;
+        Wt[b][a] = GATHER ? tab.L[b][a] : tab.L[a][b];
+    }
+    for (int e = blockIdx.x; e < ncell; e += gridDim.x) {
+        __syncthreads();
+        const int ex = e % g.nx, ey = (e / g.nx) % g.ny, ez = e / (g.nx * g.ny);
+        for (int i = threadIdx.x; i < nin; i += kCellThreads) {
+            if constexpr (GATHER) {
+                const int c = i / n3, a = i - c * n3;
+                const int a1 = a % n, a2 = (a / n) % n, a3 = a / nn;
+                A[i] = in[c * nv + ((long long)(ez * j + a3) * g.My + ey * j + a2) * g.Mx + ex * j + a1];
+            } else {
+                A[i] = in[(long long)e * nin + i];
+            }
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < nin; k += kCellThreads) {
+            const int b1 = k % n, rest = k / n;
+            const T* src = A + rest * n;
+            T acc = 0;
+#pragma unroll
+            for (int a = 0; a < n; ++a) acc += Wt[b1][a] * src[a];
+            B[k] = acc;
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < nin; k += kCellThreads) {
+            const int b1 = k % n, b2 = (k / n) % n, rest = k / nn;
+            const T* src = B + rest * nn + b1;
+            T acc = 0;
+#pragma unroll
+            for (int a = 0; a < n; ++a) acc += Wt[b2][a] * src[a * n];
+            A[k] = acc;
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < nin; k += kCellThreads) {
+            const int b12 = k % nn, b3 = (k / nn) % n, c = k / n3;
+            const T* src = A + c * n3 + b12;
+            T acc = 0;
+#pragma unroll
+            for (int a = 0; a < n; ++a) acc += Wt[b3][a] * src[a * nn];
+            if (ADD) out[(long long)e * nin + k] += acc;
+            else out[(long long)e * nin + k] = acc;
+        }
+    }
+}
+
+template <typename T, bool GATHER, bool ADD>
+void launch_cell_n(const CgGeo& g, const CgL<T>& tab, const T* in, T* out, const int* skip, dim3 grid,
+                   hipStream_t s) {
+    switch (g.j + 1) {
+        case 2: hipLaunchKernelGGL((k_cg_cell_n<T, GATHER, ADD, 2>), grid, dim3(kCellThreads), 0, s, g, tab, in, out, skip); break;
+        case 3: hipLaunchKernelGGL((k_cg_cell_n<T, GATHER, ADD, 3>), grid, dim3(kCellThreads), 0, s, g, tab, in, out, skip); break;
+        case 4: hipLaunchKernelGGL((k_cg_cell_n<T, GATHER, ADD, 4>), grid, dim3(kCellThreads), 0, s, g, tab, in, out, skip); break;
+        case 5: hipLaunchKernelGGL((k_cg_cell_n<T, GATHER, ADD, 5>), grid, dim3(kCellThreads), 0, s, g, tab, in, out, skip); break;
+        case 6: hipLaunchKernelGGL((k_cg_cell_n<T, GATHER, ADD, 6>), grid, dim3(kCellThreads), 0, s, g, tab, in, out, skip); break;
+        default: hipLaunchKernelGGL((k_cg_cell<T, GATHER, ADD>), grid, dim3(kCellThreads), 0, s, g, tab, in, out, skip); break;
+    }
+}
+
 // The cells of a continuous node along one direction: node g of a line with
 // `cells` cells of degree j lies in cell g / j (local index g % j) and, when
 // g % j == 0 and 0 < g < j * cells, also in cell g / j - 1 (local index j).
@@ -541,8 +614,8 @@ hipError_t launch_cg_gather(const CgGeo& g, const CgL<T>& tab, const T* cg, T* d
                             hipStream_t s) {
     const int ncell = g.nx * g.ny * g.nz;
     const dim3 grid((unsigned)(ncell < 65535 ? ncell : 65535));
-    if (add) hipLaunchKernelGGL((k_cg_cell<T, true, true>), grid, dim3(kCellThreads), 0, s, g, tab, cg, dg, skip);
-    else hipLaunchKernelGGL((k_cg_cell<T, true, false>), grid, dim3(kCellThreads), 0, s, g, tab, cg, dg, skip);
+    if (add) launch_cell_n<T, true, true>(g, tab, cg, dg, skip, grid, s);
+    else launch_cell_n<T, true, false>(g, tab, cg, dg, skip, grid, s);
     return hipGetLastError();
 }
 
@@ -555,7 +628,7 @@ hipError_t launch_cg_scatter(const CgGeo& g, const CgL<T>& tab, T* dg, T* cg, co
                              int mode, const T* r, const T* z, T* d, const T* dinv, const double* coef) {
     const int ncell = g.nx * g.ny * g.nz;
     const dim3 grid((unsigned)(ncell < 65535 ? ncell : 65535));
-    hipLaunchKernelGGL((k_cg_cell<T, false, false>), grid, dim3(kCellThreads), 0, s, g, tab, dg, dg, skip);
+    launch_cell_n<T, false, false>(g, tab, dg, dg, skip, grid, s);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_cg_assemble<T>(g, dg, cg, skip, s, mode, r, z, d, dinv, coef);
