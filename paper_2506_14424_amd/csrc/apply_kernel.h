@@ -319,8 +319,8 @@ __device__ __forceinline__ void face_prefetch(const OpData<T>& op, const ApplyIO
 // The neighbour's line of nodal values through this lane's face point of
 // face f = 2 D + s (D known only at run time): the next face's data, loaded
 // while the current face is computed.  Unmasked: the face that uses them
-// zeroes them where there is no live neighbour, so that no instruction of the
-// issuing face waits for the loads.
+// zeroes the traces formed from them where there is no live neighbour, so
+// that no instruction of the issuing face waits for the loads.
 template <int N, int C, typename T>
 struct FacePre {
     T nb[C][N];
@@ -367,9 +367,9 @@ __device__ __forceinline__ void face_pass(const OpData<T>& op, const ApplyIO<T>&
                                           int fnext) {
     // G7: the six neighbours' trilinear coefficients were staged in LDS at
     // the start (geo[1 + face]); LA: this face's neighbour line was loaded
-    // during the previous face (pre, masked below) and the face viscosity
-    // and penalty factor are loaded below; else all of them are loaded here
-    // (and the neighbour's coefficients into geo[1])
+    // during the previous face (pre; its traces are masked below) and the
+    // face viscosity and penalty factor are loaded below; else all of them
+    // are loaded here (and the neighbour's coefficients into geo[1])
     T nbl[C][N], mu_pre, tf_pre, gnb[8];
     if constexpr (!LA) face_prefetch<N, C, T, CURVED && !G7, D>(op, io, ci, s, nbl, mu_pre, tf_pre, gnb);
     constexpr int NN = N * N, NNN = N * N * N;
@@ -390,9 +390,9 @@ __device__ __forceinline__ void face_pass(const OpData<T>& op, const ApplyIO<T>&
     else if (D == 1) fid = op.nfx + (ci.ez * (op.ny + 1) + ci.ey + s) * op.nx + ci.ex;
     else fid = op.nfx + op.nfy + ((ci.ez + s) * op.ny + ci.ey) * op.nx + ci.ex;
     if constexpr (LA) {
-        // the look-ahead loads are masked here, at their first use; the face
-        // viscosity and penalty factor are loaded now, used at the flux
-        // (masked by live there)
+        // the look-ahead line is used as loaded (its traces are masked in
+        // stage A); the face viscosity and penalty factor are loaded now,
+        // used at the flux (masked by live there)
 #pragma unroll
         for (int c = 0; c < C; ++c)
 #pragma unroll
