@@ -654,16 +654,26 @@ sipg_status run_lanczos_cg(CgLevel& c, int steps, hipStream_t s) {
 
 // Chebyshev-Jacobi polynomial of `degree` of a continuous level applied to
 // rhs from zero (za, zb, d; ta receives A z); *out: the buffer of the result.
+// With dst (and degree >= 2) the last step writes its result into dst, or
+// with acc adds it to dst, and *out = dst; the caller copies or adds
+// otherwise (*out != dst).
 template <typename T>
-sipg_status cg_cheb(CgLevel& c, int degree, const T* rhs, const int* skip, const T** out, hipStream_t s) {
+sipg_status cg_cheb(CgLevel& c, int degree, const T* rhs, const int* skip, const T** out, hipStream_t s,
+                    T* dst = nullptr, bool acc = false) {
     T* za = static_cast<T*>(c.za);
     T* zb = static_cast<T*>(c.zb);
     T* d = static_cast<T*>(c.d);
     HIP_TRY(launch_cheb_start_t<T>(rhs, za, d, cg_dinv<T>(c), c.n, c.st, skip, s));
     for (int k = 1; k < degree; ++k) {
         // zb = za + d with d <- c1 d + c2 dinv (rhs - A za), fused into the node sums
-        const sipg_status rc = cg_apply<T>(c, za, zb, skip, s, 2, rhs, za, d, cg_dinv<T>(c), &c.st->cheb[k][0]);
+        const bool into = dst != nullptr && k + 1 == degree;
+        const sipg_status rc = cg_apply<T>(c, za, into ? dst : zb, skip, s, into && acc ? 3 : 2, rhs, za, d,
+                                           cg_dinv<T>(c), &c.st->cheb[k][0]);
         if (rc != SIPG_OK) return rc;
+        if (into) {
+            *out = dst;
+            return SIPG_OK;
+        }
         std::swap(za, zb);
     }
     *out = za;
@@ -692,9 +702,9 @@ sipg_status cg_vcycle(sipg_plan* P, int i, const T** out, hipStream_t s) {
     T* ta = static_cast<T*>(c.ta);
     T* tb = static_cast<T*>(c.tb);
     const T* zs = nullptr;
-    sipg_status rc = cg_cheb<T>(c, deg, R, skip, &zs, s);                           // pre-smoothing
+    sipg_status rc = cg_cheb<T>(c, deg, R, skip, &zs, s, Z);                        // pre-smoothing, into Z
     if (rc != SIPG_OK) return rc;
-    HIP_TRY(launch_copy_t<T>(Z, zs, c.n, skip, s));
+    if (zs != Z) HIP_TRY(launch_copy_t<T>(Z, zs, c.n, skip, s));
     auto residual = [&]() -> sipg_status {                                          // Tt = R - A Z
         return cg_apply<T>(c, Z, Tt, skip, s, 1, R);
     };
@@ -712,8 +722,8 @@ sipg_status cg_vcycle(sipg_plan* P, int i, const T** out, hipStream_t s) {
     HIP_TRY(launch_axis<T>(cg_axis<T>(c, 1, false), 1, C, c.geo.Mx, cc.geo.My, cc.geo.Mz, ta, tb, false, skip, s));
     HIP_TRY(launch_axis<T>(cg_axis<T>(c, 2, false), 2, C, c.geo.Mx, c.geo.My, cc.geo.Mz, tb, Z, true, skip, s));
     if ((rc = residual()) != SIPG_OK) return rc;
-    if ((rc = cg_cheb<T>(c, deg, Tt, skip, &zs, s)) != SIPG_OK) return rc;        // post-smoothing
-    HIP_TRY(launch_add_t<T>(Z, zs, c.n, skip, s));
+    if ((rc = cg_cheb<T>(c, deg, Tt, skip, &zs, s, Z, true)) != SIPG_OK) return rc;  // post-smoothing, added to Z
+    if (zs != Z) HIP_TRY(launch_add_t<T>(Z, zs, c.n, skip, s));
     *out = Z;
     return SIPG_OK;
 }

@@ -188,8 +188,9 @@ __device__ inline int node_cells(int g, int j, int cells, int e[2], int a[2]) {
 // out[node] = sum over the node's cells (in increasing cell order) of their
 // local contributions (DG layout), for every component; with the sum t = (A
 // z) at the node, mode RESID writes out = r - t and mode CHEB the Chebyshev
-// step d <- c1 d + c2 dinv (r - t), out = z + d.
-enum AssembleMode { ASM_SUM = 0, ASM_RESID = 1, ASM_CHEB = 2 };
+// step d <- c1 d + c2 dinv (r - t), out = z + d; mode CHEB_ACC the same step
+// added to out (out += z + d: a V-cycle's last post-smoothing step).
+enum AssembleMode { ASM_SUM = 0, ASM_RESID = 1, ASM_CHEB = 2, ASM_CHEB_ACC = 3 };
 
 template <typename T>
 struct AsmIO {
@@ -227,7 +228,8 @@ __global__ void k_cg_assemble(CgGeo g, const T* local, T* out, const AsmIO<T> io
         } else {
             const T dn = T(io.coef[0]) * io.d[idx] + T(io.coef[1]) * io.dinv[idx] * (io.r[idx] - acc);
             io.d[idx] = dn;
-            out[idx] = io.z[idx] + dn;
+            if constexpr (MODE == ASM_CHEB_ACC) out[idx] = out[idx] + (io.z[idx] + dn);
+            else out[idx] = io.z[idx] + dn;
         }
     }
 }
@@ -292,7 +294,8 @@ __global__ void __launch_bounds__(kThreads) k_cg_assemble_j(CgGeo g, const T* lo
     } else {
         const T dn = T(io.coef[0]) * io.d[idx] + T(io.coef[1]) * io.dinv[idx] * (io.r[idx] - acc);
         io.d[idx] = dn;
-        out[idx] = io.z[idx] + dn;
+        if constexpr (MODE == ASM_CHEB_ACC) out[idx] = out[idx] + (io.z[idx] + dn);
+        else out[idx] = io.z[idx] + dn;
     }
 }
 
@@ -649,6 +652,9 @@ hipError_t launch_cg_assemble(const CgGeo& g, const T* local, T* cg, const int* 
                 hipLaunchKernelGGL((k_cg_assemble_j<T, ASM_RESID, J>), grid, dim3(kThreads), 0, s, g, local, cg, io, skip);
             else if (mode == 2)
                 hipLaunchKernelGGL((k_cg_assemble_j<T, ASM_CHEB, J>), grid, dim3(kThreads), 0, s, g, local, cg, io, skip);
+            else if (mode == 3)
+                hipLaunchKernelGGL((k_cg_assemble_j<T, ASM_CHEB_ACC, J>), grid, dim3(kThreads), 0, s, g, local, cg, io,
+                                   skip);
             else
                 hipLaunchKernelGGL((k_cg_assemble_j<T, ASM_SUM, J>), grid, dim3(kThreads), 0, s, g, local, cg, io, skip);
         };
@@ -664,6 +670,8 @@ hipError_t launch_cg_assemble(const CgGeo& g, const T* local, T* cg, const int* 
     const dim3 ag(grid_for(total));
     if (mode == 1) hipLaunchKernelGGL((k_cg_assemble<T, ASM_RESID>), ag, dim3(kThreads), 0, s, g, local, cg, io, skip);
     else if (mode == 2) hipLaunchKernelGGL((k_cg_assemble<T, ASM_CHEB>), ag, dim3(kThreads), 0, s, g, local, cg, io, skip);
+    else if (mode == 3)
+        hipLaunchKernelGGL((k_cg_assemble<T, ASM_CHEB_ACC>), ag, dim3(kThreads), 0, s, g, local, cg, io, skip);
     else hipLaunchKernelGGL((k_cg_assemble<T, ASM_SUM>), ag, dim3(kThreads), 0, s, g, local, cg, io, skip);
     return hipGetLastError();
 }
