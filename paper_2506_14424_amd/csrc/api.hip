@@ -516,21 +516,28 @@ const MgTab<T>& tab_of(const sipg_plan* P) {
 
 // Chebyshev-Jacobi steps 1..degree-1 (Sec. 5.3) of level L in precision T for
 // the right-hand side rhs, from the start z_1 = theta^-1 D^-1 rhs already in
-// L's cz0 (d = z_1 in cd); *zlast receives the buffer holding the last iterate.
+// L's cz0 (d = z_1 in cd); *zlast receives the buffer holding the last iterate
+// (dst, when given and degree >= 2: the last step writes there).
 template <typename T>
-sipg_status cheb_steps(sipg_plan* L, int degree, const T* rhs, const int* skip, const T** zlast, hipStream_t s) {
+sipg_status cheb_steps(sipg_plan* L, int degree, const T* rhs, const int* skip, const T** zlast, hipStream_t s,
+                       T* dst = nullptr) {
     T* d = static_cast<T*>(L->cd);
     T* za = static_cast<T*>(L->cz0);
     T* zb = static_cast<T*>(L->cz1);
     const OpData<T> od = L->opdata<T>();
     for (int j = 1; j < degree; ++j) {
+        const bool into = dst != nullptr && j + 1 == degree;
         ApplyIO<T> io;
         std::memset(&io, 0, sizeof(io));
-        io.x = za; io.y = zb; io.parts = SIPG_PART_ALL;
+        io.x = za; io.y = into ? dst : zb; io.parts = SIPG_PART_ALL;
         io.r = rhs; io.dinv = dinv_of<T>(L); io.d = d;
         io.coef = &L->st->cheb[j][0];
         io.skip = skip;
         HIP_TRY(launch_apply<T>(L->n, L->C, L->curved, od, io, MODE_CHEB, s));
+        if (into) {
+            *zlast = dst;
+            return SIPG_OK;
+        }
         std::swap(za, zb);
     }
     *zlast = za;
@@ -743,12 +750,12 @@ sipg_status vcycle(sipg_plan* top, int l, const T** out, hipStream_t s) {
     if (l > 0) HIP_TRY(launch_cheb_start_t<T>(R, static_cast<T*>(L->cz0), static_cast<T*>(L->cd), dinv_of<T>(L), n,
                                               L->st, skip, s));
     const T* zs = nullptr;
-    sipg_status rc = cheb_steps<T>(L, deg, R, skip, &zs, s);                     // pre-smoothing
+    T* Z = static_cast<T*>(l == 0 ? top->mgz : static_cast<void*>(L->p));
+    sipg_status rc = cheb_steps<T>(L, deg, R, skip, &zs, s, last ? nullptr : Z);  // pre-smoothing (into Z)
     if (rc != SIPG_OK || last) {
         *out = zs;
         return rc;
     }
-    T* Z = static_cast<T*>(l == 0 ? top->mgz : static_cast<void*>(L->p));
     T* Tm = static_cast<T*>(l == 0 ? top->mgt : static_cast<void*>(L->q));
     const OpData<T> od = L->opdata<T>();
     auto residual = [&]() -> sipg_status {                                       // Tm = R - A Z
@@ -758,7 +765,7 @@ sipg_status vcycle(sipg_plan* top, int l, const T** out, hipStream_t s) {
         HIP_TRY(launch_apply<T>(L->n, L->C, L->curved, od, io, MODE_RESID, s));
         return SIPG_OK;
     };
-    HIP_TRY(launch_copy_t<T>(Z, zs, n, skip, s));
+    if (zs != Z) HIP_TRY(launch_copy_t<T>(Z, zs, n, skip, s));
     if ((rc = residual()) != SIPG_OK) return rc;
     if (l == 0 && !top->cg.empty()) {
         // cph: the continuous levels below the DG level (restriction G^T,
